@@ -1,0 +1,244 @@
+"""FP64 CPU oracle of the hybrid Yee-FFT particle-in-cell step (arXiv:1502.01376).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It wraps the
+plain C library ``libhpic_oracle.so`` (built from ``hpic_oracle.c`` by
+``oracle/_build.py``) with numpy arrays; it shares no code with the GPU library.
+
+Array conventions follow ``hpic_oracle.h``: field components are ``[3][n2][n1]``
+float64 arrays on the Yee-staggered nodes, particle positions are in cell units.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.environ.get("HPIC_ORACLE_LIB", os.path.join(_HERE, "libhpic_oracle.so"))
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_F = ctypes.POINTER(ctypes.c_float)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+
+
+class Grid2(ctypes.Structure):
+    """Mirror of ``or_grid2`` (2D grid and solver options)."""
+
+    _fields_ = [
+        ("n1", ctypes.c_int32), ("n2", ctypes.c_int32),
+        ("dx1", ctypes.c_double), ("dx2", ctypes.c_double), ("dt", ctypes.c_double),
+        ("alpha", ctypes.c_double),
+        ("deriv1", ctypes.c_int32), ("correct", ctypes.c_int32),
+        ("jbg", ctypes.c_double * 3),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIBPATH):
+            from oracle import _build
+            _build.build()
+        L = ctypes.CDLL(_LIBPATH)
+        G = ctypes.POINTER(Grid2)
+        sig = {
+            "or_fft": (ctypes.c_int, [ctypes.c_int32, _D, _D, ctypes.c_int32]),
+            "or_rfft_rows": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _D, _D, _D]),
+            "or_irfft_rows": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _D, _D, _D]),
+            "or_gather2": (None, [G, _D, _D, ctypes.c_int64, _D, _D, _D, _D]),
+            "or_boris": (None, [ctypes.c_int64, ctypes.c_double, ctypes.c_double, _D, _D, _D, _D, _D]),
+            "or_deposit2": (ctypes.c_int, [G, ctypes.c_int64, _D, _D, _D, _D, _D, _D, _D]),
+            "or_rho2": (None, [G, ctypes.c_int64, _D, _D, _D, _D]),
+            "or_field_update2": (ctypes.c_int, [G, _D, _D, _D]),
+            "or_yee_update2": (None, [G, _D, _D, _D]),
+            "or_step2": (ctypes.c_int, [G, ctypes.c_double, ctypes.c_int64, _D, _D, _D, _D, _D,
+                                        _D, _D, _D, _D]),
+            "or_gauss2": (ctypes.c_int, [G, _D, _D, _D, _D]),
+            "or_deposit2_fixed": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                 ctypes.c_float, ctypes.c_float, ctypes.c_int64,
+                                                 _I32, _I32, _F, _F, _I32, _I32, _F, _F, _F, _F,
+                                                 _I64]),
+            "or_rho2_fixed": (None, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                     ctypes.c_int64, _I32, _I32, _F, _F, _F, _I64]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a, kind=_D):
+    return a.ctypes.data_as(kind)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def grid2(n1, n2, dx1, dx2, dt, alpha=1.0, deriv1=0, correct=1, jbg=(0.0, 0.0, 0.0)):
+    g = Grid2()
+    g.n1, g.n2 = int(n1), int(n2)
+    g.dx1, g.dx2, g.dt = float(dx1), float(dx2), float(dt)
+    g.alpha = float(alpha)
+    g.deriv1, g.correct = int(deriv1), int(correct)
+    for c in range(3):
+        g.jbg[c] = float(jbg[c])
+    return g
+
+
+# ---------------------------------------------------------------- transforms
+def fft(x, sign=-1):
+    """Complex FFT of a power-of-two length vector (no 1/n for sign=+1)."""
+    x = np.asarray(x, dtype=np.complex128)
+    re, im = np.ascontiguousarray(x.real), np.ascontiguousarray(x.imag)
+    if lib().or_fft(len(x), _p(re), _p(im), int(sign)) != 0:
+        raise ValueError("length is not a power of two")
+    return re + 1j * im
+
+
+def rfft_rows(f):
+    """Forward transform of each row (last axis) of a real array: kappa = 0..n1/2."""
+    f = _f64(f)
+    n1 = f.shape[-1]
+    rows = f.size // n1
+    nk = n1 // 2 + 1
+    re = np.zeros(rows * nk)
+    im = np.zeros(rows * nk)
+    if lib().or_rfft_rows(n1, rows, _p(f), _p(re), _p(im)) != 0:
+        raise ValueError("bad row length")
+    return (re + 1j * im).reshape(f.shape[:-1] + (nk,))
+
+
+def irfft_rows(F, n1):
+    F = np.asarray(F, dtype=np.complex128)
+    nk = F.shape[-1]
+    rows = F.size // nk
+    re, im = _f64(F.real).ravel(), _f64(F.imag).ravel()
+    f = np.zeros(rows * n1)
+    if lib().or_irfft_rows(int(n1), rows, _p(re), _p(im), _p(f)) != 0:
+        raise ValueError("bad row length")
+    return f.reshape(F.shape[:-1] + (n1,))
+
+
+# ----------------------------------------------------------------- particles
+def gather2(g, E, B, xi1, xi2):
+    E, B, xi1, xi2 = _f64(E), _f64(B), _f64(xi1), _f64(xi2)
+    n = len(xi1)
+    Ep = np.zeros((3, n))
+    Bp = np.zeros((3, n))
+    lib().or_gather2(ctypes.byref(g), _p(E), _p(B), n, _p(xi1), _p(xi2), _p(Ep), _p(Bp))
+    return Ep, Bp
+
+
+def boris(qm, dt, Ep, Bp, u):
+    """Returns the pushed momenta ([3][np]); the input is not modified."""
+    u = _f64(u).copy()
+    Ep, Bp = _f64(Ep), _f64(Bp)
+    n = u.shape[1]
+    u1, u2, u3 = (np.ascontiguousarray(u[c]) for c in range(3))
+    lib().or_boris(n, float(qm), float(dt), _p(Ep), _p(Bp), _p(u1), _p(u2), _p(u3))
+    return np.stack([u1, u2, u3])
+
+
+def deposit2(g, xa1, xa2, xb1, xb2, v3, qw):
+    xa1, xa2, xb1, xb2, v3, qw = map(_f64, (xa1, xa2, xb1, xb2, v3, qw))
+    J = np.zeros((3, g.n2, g.n1))
+    st = lib().or_deposit2(ctypes.byref(g), len(xa1), _p(xa1), _p(xa2), _p(xb1), _p(xb2),
+                           _p(v3), _p(qw), _p(J))
+    if st != 0:
+        raise ValueError("a particle moved a cell or more in one step")
+    return J
+
+
+def rho2(g, xi1, xi2, qw):
+    xi1, xi2, qw = map(_f64, (xi1, xi2, qw))
+    rho = np.zeros((g.n2, g.n1))
+    lib().or_rho2(ctypes.byref(g), len(xi1), _p(xi1), _p(xi2), _p(qw), _p(rho))
+    return rho
+
+
+# ---------------------------------------------------------------- field solve
+def field_update2(g, E, B, J):
+    """Returns (E, B) after one hybrid (or FD-mode) update; inputs not modified."""
+    E, B, J = _f64(E).copy(), _f64(B).copy(), _f64(J)
+    if lib().or_field_update2(ctypes.byref(g), _p(E), _p(B), _p(J)) != 0:
+        raise ValueError("bad grid")
+    return E, B
+
+
+def yee_update2(g, E, B, J):
+    E, B, J = _f64(E).copy(), _f64(B).copy(), _f64(J)
+    lib().or_yee_update2(ctypes.byref(g), _p(E), _p(B), _p(J))
+    return E, B
+
+
+def gauss2(g, E, rho):
+    E, rho = _f64(E), _f64(rho)
+    nk = g.n1 // 2 + 1
+    re = np.zeros(g.n2 * nk)
+    im = np.zeros(g.n2 * nk)
+    lib().or_gauss2(ctypes.byref(g), _p(E), _p(rho), _p(re), _p(im))
+    return (re + 1j * im).reshape(g.n2, nk)
+
+
+class State2:
+    """Particles and fields of one 2D run, advanced by ``step``."""
+
+    def __init__(self, g, qm, xi1, xi2, u, qw, E=None, B=None):
+        self.g, self.qm = g, float(qm)
+        self.xi1, self.xi2 = _f64(xi1).copy(), _f64(xi2).copy()
+        self.u = _f64(u).copy()
+        self.qw = _f64(qw).copy()
+        shape = (3, g.n2, g.n1)
+        self.E = np.zeros(shape) if E is None else _f64(E).copy()
+        self.B = np.zeros(shape) if B is None else _f64(B).copy()
+        self.J = np.zeros(shape)
+
+    def step(self, n=1):
+        g = self.g
+        u1, u2, u3 = (np.ascontiguousarray(self.u[c]) for c in range(3))
+        for _ in range(n):
+            st = lib().or_step2(ctypes.byref(g), self.qm, len(self.xi1), _p(self.xi1), _p(self.xi2),
+                                _p(u1), _p(u2), _p(u3), _p(self.qw), _p(self.E), _p(self.B),
+                                _p(self.J))
+            if st != 0:
+                raise ValueError("oracle step failed (move of a cell or more)")
+        self.u = np.stack([u1, u2, u3])
+        return self
+
+
+# ------------------------------------------- fixed-point deposit (kernel precision)
+def deposit2_fixed(n1, n2, P, inv_wunit, c3, ca1, ca2, fa1, fa2, cb1, cb2, fb1, fb2, v3, qw):
+    i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    ca1, ca2, cb1, cb2 = map(i32, (ca1, ca2, cb1, cb2))
+    fa1, fa2, fb1, fb2, v3, qw = map(f32, (fa1, fa2, fb1, fb2, v3, qw))
+    J = np.zeros((3, n2, n1), dtype=np.int64)
+    st = lib().or_deposit2_fixed(int(n1), int(n2), int(P), float(inv_wunit), float(c3), len(ca1),
+                                 _p(ca1, _I32), _p(ca2, _I32), _p(fa1, _F), _p(fa2, _F),
+                                 _p(cb1, _I32), _p(cb2, _I32), _p(fb1, _F), _p(fb2, _F),
+                                 _p(v3, _F), _p(qw, _F), _p(J, _I64))
+    if st != 0:
+        raise ValueError("a particle moved a cell or more in one step")
+    return J
+
+
+def rho2_fixed(n1, n2, P, inv_wunit, c1, c2, f1, f2, qw):
+    c1 = np.ascontiguousarray(c1, dtype=np.int32)
+    c2 = np.ascontiguousarray(c2, dtype=np.int32)
+    f1 = np.ascontiguousarray(f1, dtype=np.float32)
+    f2 = np.ascontiguousarray(f2, dtype=np.float32)
+    qw = np.ascontiguousarray(qw, dtype=np.float32)
+    rho = np.zeros((n2, n1), dtype=np.int64)
+    lib().or_rho2_fixed(int(n1), int(n2), int(P), float(inv_wunit), len(c1), _p(c1, _I32),
+                        _p(c2, _I32), _p(f1, _F), _p(f2, _F), _p(qw, _F), _p(rho, _I64))
+    return rho
+
+
+def courant_limit2(dx1, dx2):
+    """Largest stable time step of the hybrid solver, Eq. (22)."""
+    return 2.0 / np.sqrt(np.pi ** 2 / dx1 ** 2 + 4.0 / dx2 ** 2)

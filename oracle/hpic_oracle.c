@@ -1,0 +1,588 @@
+/*
+ * hpic_oracle.c -- plain FP64 CPU oracle for the hybrid Yee-FFT
+ * particle-in-cell step of Yu et al., "Mitigation of numerical Cerenkov
+ * radiation and instability using a hybrid finite difference-FFT Maxwell
+ * solver and a local charge conserving current deposit", arXiv:1502.01376.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the reference the GPU library is checked
+ * against.  Only the test-suite, the smoke check and the CPU-baseline leg of
+ * the benchmark load it; the product path never does.  It shares no code,
+ * header, table or constant with the GPU library.
+ *
+ * Everything here is written to be checked by eye against the paper, not to
+ * be fast: straight loops in FP64, explicit periodic wrapping, twiddles from
+ * libm at every butterfly, and the field solver in the literal form of
+ * Sec. 2.1 (E, B and j are transformed along x1 at every step, advanced in
+ * (k1, x2) space and transformed back).
+ *
+ * Readings of the paper taken here (each is listed with its reason in the
+ * design notes of the repository):
+ *  - Fourier convention f_kappa = sum_i f_i exp(-i k1 x_i) over the storage
+ *    index, k1 = 2 pi kappa / (n1 dx1).  With it the forward difference of an
+ *    integer-node quantity is i [k]1 xi+ and the backward difference of a
+ *    half-node quantity is i [k]1 xi-, xi+- = exp(+-i k1 dx1/2) (Eq. (18)).
+ *    The hybrid solver replaces [k]1 by k1 (Eq. (20)); replacing it back by
+ *    [k]1 gives the Yee scheme exactly, as stated at the end of Sec. 2.1.
+ *    The signs of Eqs. (1)-(6) are used for the curl terms.
+ *  - The Nyquist bin kappa1 = n1/2 is kept (its symbols are real).
+ *  - B^n in Eqs. (15) and (17) is read as B^{n+1/2}, as in Eqs. (4)-(6).
+ *  - B is advanced in two half steps around the E update so that B exists at
+ *    integer time for the particle push; this is algebraically the leapfrog
+ *    of Eqs. (12)-(17).
+ *  - The low-pass filter of Sec. 4 is a sharp mask f(k1) = 1 for
+ *    |k1| <= alpha pi/dx1 and 0 above, applied to all current components
+ *    after the correction of Eq. (11).
+ *  - Pusher: relativistic Boris.  Shape: quadratic B-spline (Table 2, Sec. 4),
+ *    momentum-conserving interpolation (Appendix A, first variant).
+ *  - Charge-conserving deposit: Esirkepov's scheme for the quadratic shape
+ *    (the deposit the paper cites satisfies the continuity equation (23)).
+ */
+#include "hpic_oracle.h"
+
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static const double PI = 3.14159265358979323846;
+
+static int wrapi(int64_t i, int64_t n) {
+  int64_t r = i % n;
+  return (int)(r < 0 ? r + n : r);
+}
+
+static int is_pow2(int32_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+/* ------------------------------------------------------------------------ */
+/* FFT: textbook iterative radix-2 Cooley-Tukey with bit-reversed input.     */
+/* ------------------------------------------------------------------------ */
+
+int or_fft(int32_t n, double *re, double *im, int32_t sign) {
+  if (!is_pow2(n)) return -1;
+  /* bit-reversal permutation */
+  for (int32_t i = 1, j = 0; i < n; ++i) {
+    int32_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) {
+      double t = re[i]; re[i] = re[j]; re[j] = t;
+      t = im[i]; im[i] = im[j]; im[j] = t;
+    }
+  }
+  /* butterflies of growing length */
+  for (int32_t len = 2; len <= n; len <<= 1) {
+    for (int32_t start = 0; start < n; start += len) {
+      for (int32_t k = 0; k < len / 2; ++k) {
+        double ang = sign * 2.0 * PI * (double)k / (double)len;
+        double wr = cos(ang), wi = sin(ang);
+        int32_t a = start + k, b = start + k + len / 2;
+        double xr = re[b] * wr - im[b] * wi;
+        double xi = re[b] * wi + im[b] * wr;
+        re[b] = re[a] - xr;
+        im[b] = im[a] - xi;
+        re[a] = re[a] + xr;
+        im[a] = im[a] + xi;
+      }
+    }
+  }
+  return 0;
+}
+
+int or_rfft_rows(int32_t n1, int32_t nrows, const double *f, double *Fre, double *Fim) {
+  if (!is_pow2(n1) || n1 < 2) return -1;
+  int32_t nk = n1 / 2 + 1;
+  double *re = malloc(sizeof(double) * n1), *im = malloc(sizeof(double) * n1);
+  for (int32_t r = 0; r < nrows; ++r) {
+    for (int32_t i = 0; i < n1; ++i) { re[i] = f[(int64_t)r * n1 + i]; im[i] = 0.0; }
+    or_fft(n1, re, im, -1);
+    for (int32_t k = 0; k < nk; ++k) {
+      Fre[(int64_t)r * nk + k] = re[k];
+      Fim[(int64_t)r * nk + k] = im[k];
+    }
+  }
+  free(re); free(im);
+  return 0;
+}
+
+int or_irfft_rows(int32_t n1, int32_t nrows, const double *Fre, const double *Fim, double *f) {
+  if (!is_pow2(n1) || n1 < 2) return -1;
+  int32_t nk = n1 / 2 + 1;
+  double *re = malloc(sizeof(double) * n1), *im = malloc(sizeof(double) * n1);
+  for (int32_t r = 0; r < nrows; ++r) {
+    for (int32_t k = 0; k < nk; ++k) {
+      re[k] = Fre[(int64_t)r * nk + k];
+      im[k] = Fim[(int64_t)r * nk + k];
+    }
+    /* the self-conjugate bins of a real row have no imaginary part */
+    im[0] = 0.0;
+    im[n1 / 2] = 0.0;
+    for (int32_t k = nk; k < n1; ++k) { re[k] = re[n1 - k]; im[k] = -im[n1 - k]; }
+    or_fft(n1, re, im, +1);
+    for (int32_t i = 0; i < n1; ++i) f[(int64_t)r * n1 + i] = re[i] / (double)n1;
+  }
+  free(re); free(im);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Particle shape and field gather                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Quadratic B-spline: weight of a node at signed distance delta (cells). */
+static double spline2(double delta) {
+  double a = fabs(delta);
+  if (a < 0.5) return 0.75 - a * a;
+  if (a < 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
+  return 0.0;
+}
+
+/* Staggering offsets (in cells) of E1..E3 and B1..B3 along x1 and x2, from the
+ * index subscripts of Eqs. (1)-(6). */
+static const double STAG_E[3][2] = {{0.5, 0.0}, {0.0, 0.5}, {0.0, 0.0}};
+static const double STAG_B[3][2] = {{0.0, 0.5}, {0.5, 0.0}, {0.5, 0.5}};
+
+/* Quadratic interpolation of one staggered component F at xi. */
+static double interp2(const or_grid2 *g, const double *F, double s1, double s2, double xi1,
+                      double xi2) {
+  double e1 = xi1 - s1, e2 = xi2 - s2;
+  int64_t m1 = (int64_t)floor(e1 + 0.5), m2 = (int64_t)floor(e2 + 0.5);
+  double acc = 0.0;
+  for (int64_t b = m2 - 1; b <= m2 + 1; ++b) {
+    double w2 = spline2(e2 - (double)b);
+    for (int64_t a = m1 - 1; a <= m1 + 1; ++a) {
+      double w1 = spline2(e1 - (double)a);
+      acc += w1 * w2 * F[(int64_t)wrapi(b, g->n2) * g->n1 + wrapi(a, g->n1)];
+    }
+  }
+  return acc;
+}
+
+void or_gather2(const or_grid2 *g, const double *E, const double *B, int64_t np,
+                const double *xi1, const double *xi2, double *Ep, double *Bp) {
+  int64_t cells = (int64_t)g->n1 * g->n2;
+  for (int64_t p = 0; p < np; ++p) {
+    for (int c = 0; c < 3; ++c) {
+      Ep[c * np + p] = interp2(g, E + c * cells, STAG_E[c][0], STAG_E[c][1], xi1[p], xi2[p]);
+      Bp[c * np + p] = interp2(g, B + c * cells, STAG_B[c][0], STAG_B[c][1], xi1[p], xi2[p]);
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Relativistic Boris push (half electric kick, magnetic rotation, half kick)*/
+/* ------------------------------------------------------------------------ */
+
+void or_boris(int64_t np, double qm, double dt, const double *Ep, const double *Bp,
+              double *u1, double *u2, double *u3) {
+  double h = 0.5 * qm * dt;
+  for (int64_t p = 0; p < np; ++p) {
+    double e[3] = {h * Ep[p], h * Ep[np + p], h * Ep[2 * np + p]};
+    double um[3] = {u1[p] + e[0], u2[p] + e[1], u3[p] + e[2]};
+    double gm = sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+    double t[3] = {h * Bp[p] / gm, h * Bp[np + p] / gm, h * Bp[2 * np + p] / gm};
+    double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    double s[3] = {2.0 * t[0] / (1.0 + tt), 2.0 * t[1] / (1.0 + tt), 2.0 * t[2] / (1.0 + tt)};
+    double up[3] = {um[0] + (um[1] * t[2] - um[2] * t[1]),
+                    um[1] + (um[2] * t[0] - um[0] * t[2]),
+                    um[2] + (um[0] * t[1] - um[1] * t[0])};
+    double uq[3] = {um[0] + (up[1] * s[2] - up[2] * s[1]),
+                    um[1] + (up[2] * s[0] - up[0] * s[2]),
+                    um[2] + (up[0] * s[1] - up[1] * s[0])};
+    u1[p] = uq[0] + e[0];
+    u2[p] = uq[1] + e[1];
+    u3[p] = uq[2] + e[2];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Esirkepov deposit, FP64                                                   */
+/* ------------------------------------------------------------------------ */
+
+int or_deposit2(const or_grid2 *g, int64_t np, const double *xa1, const double *xa2,
+                const double *xb1, const double *xb2, const double *v3, const double *qw,
+                double *J) {
+  int64_t cells = (int64_t)g->n1 * g->n2;
+  double *J1 = J, *J2 = J + cells, *J3 = J + 2 * cells;
+  int status = 0;
+  for (int64_t p = 0; p < np; ++p) {
+    if (fabs(xb1[p] - xa1[p]) >= 1.0 || fabs(xb2[p] - xa2[p]) >= 1.0) { status = -1; continue; }
+    /* a common 4-node window per coordinate holds the old and new stencils */
+    int64_t b1 = (int64_t)fmin(floor(xa1[p] + 0.5), floor(xb1[p] + 0.5)) - 1;
+    int64_t b2 = (int64_t)fmin(floor(xa2[p] + 0.5), floor(xb2[p] + 0.5)) - 1;
+    double S0x[4], S1x[4], S0y[4], S1y[4];
+    for (int a = 0; a < 4; ++a) {
+      S0x[a] = spline2(xa1[p] - (double)(b1 + a));
+      S1x[a] = spline2(xb1[p] - (double)(b1 + a));
+      S0y[a] = spline2(xa2[p] - (double)(b2 + a));
+      S1y[a] = spline2(xb2[p] - (double)(b2 + a));
+    }
+    double f1 = -qw[p] * g->dx1 / g->dt, f2 = -qw[p] * g->dx2 / g->dt;
+    /* j1: running sum along x1 of the W1 weights (continuity, Eq. (23)) */
+    for (int b = 0; b < 4; ++b) {
+      double acc = 0.0;
+      for (int a = 0; a < 4; ++a) {
+        double W1 = (S1x[a] - S0x[a]) * 0.5 * (S0y[b] + S1y[b]);
+        acc += f1 * W1;
+        J1[(int64_t)wrapi(b2 + b, g->n2) * g->n1 + wrapi(b1 + a, g->n1)] += acc;
+      }
+    }
+    /* j2: running sum along x2 of the W2 weights */
+    for (int a = 0; a < 4; ++a) {
+      double acc = 0.0;
+      for (int b = 0; b < 4; ++b) {
+        double W2 = (S1y[b] - S0y[b]) * 0.5 * (S0x[a] + S1x[a]);
+        acc += f2 * W2;
+        J2[(int64_t)wrapi(b2 + b, g->n2) * g->n1 + wrapi(b1 + a, g->n1)] += acc;
+      }
+    }
+    /* j3: out-of-plane current with the time-averaged shape W3 */
+    for (int b = 0; b < 4; ++b) {
+      for (int a = 0; a < 4; ++a) {
+        double W3 = S0x[a] * S0y[b] / 3.0 + S1x[a] * S0y[b] / 6.0 + S0x[a] * S1y[b] / 6.0 +
+                    S1x[a] * S1y[b] / 3.0;
+        J3[(int64_t)wrapi(b2 + b, g->n2) * g->n1 + wrapi(b1 + a, g->n1)] += qw[p] * v3[p] * W3;
+      }
+    }
+  }
+  return status;
+}
+
+void or_rho2(const or_grid2 *g, int64_t np, const double *xi1, const double *xi2,
+             const double *qw, double *rho) {
+  for (int64_t p = 0; p < np; ++p) {
+    int64_t m1 = (int64_t)floor(xi1[p] + 0.5), m2 = (int64_t)floor(xi2[p] + 0.5);
+    for (int64_t b = m2 - 1; b <= m2 + 1; ++b)
+      for (int64_t a = m1 - 1; a <= m1 + 1; ++a)
+        rho[(int64_t)wrapi(b, g->n2) * g->n1 + wrapi(a, g->n1)] +=
+            qw[p] * spline2(xi1[p] - (double)a) * spline2(xi2[p] - (double)b);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Field solvers                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* x1 symbols for mode kappa: the derivative k1 or [k]1, the current
+ * correction of Eq. (11), and the filter mask of Sec. 4. */
+typedef struct {
+  double complex dp, dm; /* forward (integer->half) and backward (half->integer) */
+  double corr, filt;
+} xsym;
+
+static xsym x1_symbols(const or_grid2 *g, int32_t kappa) {
+  xsym s;
+  double k1 = 2.0 * PI * (double)kappa / ((double)g->n1 * g->dx1);
+  double h = 0.5 * k1 * g->dx1;
+  double kk = g->deriv1 ? sin(h) / (0.5 * g->dx1) : k1;
+  s.dp = I * kk * cexp(I * h);  /* i k1 xi+ */
+  s.dm = I * kk * cexp(-I * h); /* i k1 xi- */
+  s.corr = (g->deriv1 || !g->correct || kappa == 0) ? 1.0 : sin(h) / h;
+  s.filt = ((double)kappa <= g->alpha * 0.5 * (double)g->n1) ? 1.0 : 0.0;
+  return s;
+}
+
+static void to_k(int32_t n1, int32_t n2, const double *f, double complex *F) {
+  int32_t nk = n1 / 2 + 1;
+  double *re = malloc(sizeof(double) * n2 * nk), *im = malloc(sizeof(double) * n2 * nk);
+  or_rfft_rows(n1, n2, f, re, im);
+  for (int64_t i = 0; i < (int64_t)n2 * nk; ++i) F[i] = re[i] + I * im[i];
+  free(re); free(im);
+}
+
+static void from_k(int32_t n1, int32_t n2, const double complex *F, double *f) {
+  int32_t nk = n1 / 2 + 1;
+  double *re = malloc(sizeof(double) * n2 * nk), *im = malloc(sizeof(double) * n2 * nk);
+  for (int64_t i = 0; i < (int64_t)n2 * nk; ++i) { re[i] = creal(F[i]); im[i] = cimag(F[i]); }
+  or_irfft_rows(n1, n2, re, im, f);
+  free(re); free(im);
+}
+
+/* Faraday half step B -= (dt/2) curl E in (kappa1, x2) space, Eqs. (12)-(14). */
+static void faraday_half2(const or_grid2 *g, const double complex *Ek, double complex *Bk) {
+  int32_t n2 = g->n2, nk = g->n1 / 2 + 1;
+  int64_t plane = (int64_t)n2 * nk;
+  const double complex *E1 = Ek, *E2 = Ek + plane, *E3 = Ek + 2 * plane;
+  double complex *B1 = Bk, *B2 = Bk + plane, *B3 = Bk + 2 * plane;
+  double hdt = 0.5 * g->dt;
+  for (int32_t k = 0; k < nk; ++k) {
+    xsym s = x1_symbols(g, k);
+    for (int32_t i2 = 0; i2 < n2; ++i2) {
+      int64_t c = (int64_t)i2 * nk + k, up = (int64_t)wrapi(i2 + 1, n2) * nk + k;
+      double complex cE1 = (E3[up] - E3[c]) / g->dx2;
+      double complex cE2 = -s.dp * E3[c];
+      double complex cE3 = s.dp * E2[c] - (E1[up] - E1[c]) / g->dx2;
+      B1[c] -= hdt * cE1;
+      B2[c] -= hdt * cE2;
+      B3[c] -= hdt * cE3;
+    }
+  }
+}
+
+int or_field_update2(const or_grid2 *g, double *E, double *B, const double *J) {
+  int32_t n1 = g->n1, n2 = g->n2, nk = n1 / 2 + 1;
+  if (!is_pow2(n1) || n1 < 2 || n2 < 1) return -1;
+  int64_t cells = (int64_t)n1 * n2, plane = (int64_t)n2 * nk;
+  double complex *Ek = malloc(sizeof(double complex) * 3 * plane);
+  double complex *Bk = malloc(sizeof(double complex) * 3 * plane);
+  double complex *Jk = malloc(sizeof(double complex) * 3 * plane);
+  double *tmp = malloc(sizeof(double) * cells);
+  for (int c = 0; c < 3; ++c) {
+    to_k(n1, n2, E + c * cells, Ek + c * plane);
+    to_k(n1, n2, B + c * cells, Bk + c * plane);
+    for (int64_t i = 0; i < cells; ++i) tmp[i] = J[c * cells + i] + g->jbg[c];
+    to_k(n1, n2, tmp, Jk + c * plane);
+  }
+  /* Eq. (11) on j1, then the low-pass mask on every component */
+  for (int32_t k = 0; k < nk; ++k) {
+    xsym s = x1_symbols(g, k);
+    for (int32_t i2 = 0; i2 < n2; ++i2) {
+      int64_t c = (int64_t)i2 * nk + k;
+      Jk[c] *= s.corr * s.filt;
+      Jk[plane + c] *= s.filt;
+      Jk[2 * plane + c] *= s.filt;
+    }
+  }
+  /* B^{n+1/2} = B^n - (dt/2) curl E^n */
+  faraday_half2(g, Ek, Bk);
+  /* E^{n+1} = E^n + dt (curl B^{n+1/2} - j), Eqs. (15)-(17) */
+  {
+    double complex *E1 = Ek, *E2 = Ek + plane, *E3 = Ek + 2 * plane;
+    const double complex *B1 = Bk, *B2 = Bk + plane, *B3 = Bk + 2 * plane;
+    for (int32_t k = 0; k < nk; ++k) {
+      xsym s = x1_symbols(g, k);
+      for (int32_t i2 = 0; i2 < n2; ++i2) {
+        int64_t c = (int64_t)i2 * nk + k, dn = (int64_t)wrapi(i2 - 1, n2) * nk + k;
+        double complex cB1 = (B3[c] - B3[dn]) / g->dx2;
+        double complex cB2 = -s.dm * B3[c];
+        double complex cB3 = s.dm * B2[c] - (B1[c] - B1[dn]) / g->dx2;
+        E1[c] += g->dt * (cB1 - Jk[c]);
+        E2[c] += g->dt * (cB2 - Jk[plane + c]);
+        E3[c] += g->dt * (cB3 - Jk[2 * plane + c]);
+      }
+    }
+  }
+  /* B^{n+1} = B^{n+1/2} - (dt/2) curl E^{n+1} */
+  faraday_half2(g, Ek, Bk);
+  for (int c = 0; c < 3; ++c) {
+    from_k(n1, n2, Ek + c * plane, E + c * cells);
+    from_k(n1, n2, Bk + c * plane, B + c * cells);
+  }
+  free(Ek); free(Bk); free(Jk); free(tmp);
+  return 0;
+}
+
+/* Real-space Yee half step for B, Eqs. (1)-(3) with dt/2. */
+static void yee_faraday_half2(const or_grid2 *g, const double *E, double *B) {
+  int32_t n1 = g->n1, n2 = g->n2;
+  int64_t cells = (int64_t)n1 * n2;
+  const double *E1 = E, *E2 = E + cells, *E3 = E + 2 * cells;
+  double *B1 = B, *B2 = B + cells, *B3 = B + 2 * cells;
+  double h = 0.5 * g->dt;
+  for (int32_t i2 = 0; i2 < n2; ++i2) {
+    for (int32_t i1 = 0; i1 < n1; ++i1) {
+      int64_t c = (int64_t)i2 * n1 + i1;
+      int64_t e1 = (int64_t)i2 * n1 + wrapi(i1 + 1, n1); /* (i1+1, i2) */
+      int64_t e2 = (int64_t)wrapi(i2 + 1, n2) * n1 + i1; /* (i1, i2+1) */
+      B1[c] -= h * (E3[e2] - E3[c]) / g->dx2;
+      B2[c] += h * (E3[e1] - E3[c]) / g->dx1;
+      B3[c] += -h * (E2[e1] - E2[c]) / g->dx1 + h * (E1[e2] - E1[c]) / g->dx2;
+    }
+  }
+}
+
+void or_yee_update2(const or_grid2 *g, double *E, double *B, const double *J) {
+  int32_t n1 = g->n1, n2 = g->n2;
+  int64_t cells = (int64_t)n1 * n2;
+  yee_faraday_half2(g, E, B);
+  double *E1 = E, *E2 = E + cells, *E3 = E + 2 * cells;
+  const double *B1 = B, *B2 = B + cells, *B3 = B + 2 * cells;
+  for (int32_t i2 = 0; i2 < n2; ++i2) {
+    for (int32_t i1 = 0; i1 < n1; ++i1) {
+      int64_t c = (int64_t)i2 * n1 + i1;
+      int64_t w1 = (int64_t)i2 * n1 + wrapi(i1 - 1, n1); /* (i1-1, i2) */
+      int64_t w2 = (int64_t)wrapi(i2 - 1, n2) * n1 + i1; /* (i1, i2-1) */
+      E1[c] += -g->dt * (J[c] + g->jbg[0]) + g->dt * (B3[c] - B3[w2]) / g->dx2;
+      E2[c] += -g->dt * (J[cells + c] + g->jbg[1]) - g->dt * (B3[c] - B3[w1]) / g->dx1;
+      E3[c] += -g->dt * (J[2 * cells + c] + g->jbg[2]) + g->dt * (B2[c] - B2[w1]) / g->dx1 -
+               g->dt * (B1[c] - B1[w2]) / g->dx2;
+    }
+  }
+  yee_faraday_half2(g, E, B);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole step                                                                */
+/* ------------------------------------------------------------------------ */
+
+int or_step2(const or_grid2 *g, double qm, int64_t np, double *xi1, double *xi2,
+             double *u1, double *u2, double *u3, const double *qw, double *E, double *B,
+             double *J) {
+  int64_t cells = (int64_t)g->n1 * g->n2;
+  double *Ep = malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
+  double *Bp = malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
+  double *xn1 = malloc(sizeof(double) * (np > 0 ? np : 1));
+  double *xn2 = malloc(sizeof(double) * (np > 0 ? np : 1));
+  double *v3 = malloc(sizeof(double) * (np > 0 ? np : 1));
+  or_gather2(g, E, B, np, xi1, xi2, Ep, Bp);
+  or_boris(np, qm, g->dt, Ep, Bp, u1, u2, u3);
+  for (int64_t p = 0; p < np; ++p) {
+    double gam = sqrt(1.0 + u1[p] * u1[p] + u2[p] * u2[p] + u3[p] * u3[p]);
+    xn1[p] = xi1[p] + g->dt * (u1[p] / gam) / g->dx1;
+    xn2[p] = xi2[p] + g->dt * (u2[p] / gam) / g->dx2;
+    v3[p] = u3[p] / gam;
+  }
+  memset(J, 0, sizeof(double) * 3 * cells);
+  int status = or_deposit2(g, np, xi1, xi2, xn1, xn2, v3, qw, J);
+  if (or_field_update2(g, E, B, J) != 0) status = -1;
+  for (int64_t p = 0; p < np; ++p) {
+    xi1[p] = fmod(xn1[p], (double)g->n1);
+    if (xi1[p] < 0.0) xi1[p] += (double)g->n1;
+    xi2[p] = fmod(xn2[p], (double)g->n2);
+    if (xi2[p] < 0.0) xi2[p] += (double)g->n2;
+  }
+  free(Ep); free(Bp); free(xn1); free(xn2); free(v3);
+  return status;
+}
+
+int or_gauss2(const or_grid2 *g, const double *E, const double *rho, double *Rre, double *Rim) {
+  int32_t n1 = g->n1, n2 = g->n2, nk = n1 / 2 + 1;
+  if (!is_pow2(n1) || n1 < 2) return -1;
+  int64_t cells = (int64_t)n1 * n2, plane = (int64_t)n2 * nk;
+  double complex *E1 = malloc(sizeof(double complex) * plane);
+  double complex *E2 = malloc(sizeof(double complex) * plane);
+  double complex *R = malloc(sizeof(double complex) * plane);
+  to_k(n1, n2, E, E1);
+  to_k(n1, n2, E + cells, E2);
+  to_k(n1, n2, rho, R);
+  for (int32_t k = 0; k < nk; ++k) {
+    xsym s = x1_symbols(g, k);
+    for (int32_t i2 = 0; i2 < n2; ++i2) {
+      int64_t c = (int64_t)i2 * nk + k, dn = (int64_t)wrapi(i2 - 1, n2) * nk + k;
+      double complex div = s.dm * E1[c] + (E2[c] - E2[dn]) / g->dx2;
+      R[c] = div - s.filt * R[c];
+    }
+  }
+  for (int64_t i = 0; i < plane; ++i) { Rre[i] = creal(R[i]); Rim[i] = cimag(R[i]); }
+  free(E1); free(E2); free(R);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fixed-point deposit in the kernel's precision                             */
+/* ------------------------------------------------------------------------ */
+/*
+ * The GPU accumulates the current in 64-bit integers.  To keep the discrete
+ * continuity equation (23) exact in those integers, the shape factors of each
+ * coordinate are themselves integers that sum to exactly 2^P:
+ *   d = offset from the nearest node in [-1/2, 1/2)   (FP32, exact)
+ *   D = rint(d 2^P)                                    (FP32 rint)
+ *   s(-1) = round((2^(P-1) - D)^2 / 2^(P+1)),  s(+1) = round((2^(P-1) + D)^2 / 2^(P+1))
+ *   s(0)  = 2^P - s(-1) - s(+1)
+ * which are the quadratic B-spline weights 1/2 (1/2 -+ d)^2 and 3/4 - d^2 times
+ * 2^P, rounded (halves up).  With the integer charge Q = rint(qw * inv_wunit)
+ * the Esirkepov weights become exact integer products:
+ *   J1[a][b] = Q C1[a] (S0y[b] + S1y[b]),   C1[a] = sum_{a'<=a} (S1x[a'] - S0x[a'])
+ *   J2[a][b] = Q C2[b] (S0x[a] + S1x[a]),   C2[b] = sum_{b'<=b} (S1y[b'] - S0y[b'])
+ * and 2 (rho_new - rho_old) = div J holds node by node in integers, where
+ * rho = Q s1 s2.  Physical units: j1 = -(dx1/dt) J1 / (inv_wunit 2^(2P+1)) and
+ * likewise j2 with dx2.  The out-of-plane j3 does not enter the continuity
+ * equation in 2D; it is FP32 with the same operation order as the kernel:
+ *   T = S0x (2 S0y + S1y) + S1x (S0y + 2 S1y),   h = ((qw inv_wunit) v3) c3,
+ *   J3 += rint(T h)      so that j3 = J3 / (inv_wunit c3 6 2^(2P)).
+ * This file is compiled with floating-point contraction off so that each FP32
+ * operation rounds once, as in the kernel.
+ */
+
+static int32_t fixed_shape(int32_t cell, float f, int32_t P, int64_t s[3]) {
+  int32_t up = (f >= 0.5f);
+  float d = up ? (f - 1.0f) : f;
+  float scaled = d * (float)(1 << P);
+  int64_t D = (int64_t)rintf(scaled);
+  int64_t h = (int64_t)1 << (P - 1);
+  int64_t bias = (int64_t)1 << P;
+  s[0] = ((h - D) * (h - D) + bias) >> (P + 1);
+  s[2] = ((h + D) * (h + D) + bias) >> (P + 1);
+  s[1] = ((int64_t)1 << P) - s[0] - s[2];
+  return cell + up;
+}
+
+static int32_t wrap_delta(int32_t db, int32_t n) {
+  int32_t d = wrapi(db, n);
+  return d > n / 2 ? d - n : d;
+}
+
+int or_deposit2_fixed(int32_t n1, int32_t n2, int32_t P, float inv_wunit, float c3,
+                      int64_t np, const int32_t *ca1, const int32_t *ca2, const float *fa1,
+                      const float *fa2, const int32_t *cb1, const int32_t *cb2,
+                      const float *fb1, const float *fb2, const float *v3, const float *qw,
+                      int64_t *J) {
+  int64_t cells = (int64_t)n1 * n2;
+  int64_t *J1 = J, *J2 = J + cells, *J3 = J + 2 * cells;
+  int status = 0;
+  for (int64_t p = 0; p < np; ++p) {
+    int32_t d1 = wrap_delta(cb1[p] - ca1[p], n1), d2 = wrap_delta(cb2[p] - ca2[p], n2);
+    if (d1 < -1 || d1 > 1 || d2 < -1 || d2 > 1) { status = -1; continue; }
+    int64_t sa1[3], sa2[3], sb1[3], sb2[3];
+    int32_t na1 = fixed_shape(ca1[p], fa1[p], P, sa1);
+    int32_t nb1 = fixed_shape(ca1[p] + d1, fb1[p], P, sb1);
+    int32_t na2 = fixed_shape(ca2[p], fa2[p], P, sa2);
+    int32_t nb2 = fixed_shape(ca2[p] + d2, fb2[p], P, sb2);
+    if (na1 - nb1 > 1 || nb1 - na1 > 1 || na2 - nb2 > 1 || nb2 - na2 > 1) { status = -1; continue; }
+    int32_t base1 = (na1 < nb1 ? na1 : nb1) - 1, base2 = (na2 < nb2 ? na2 : nb2) - 1;
+    int64_t S0x[4] = {0, 0, 0, 0}, S1x[4] = {0, 0, 0, 0}, S0y[4] = {0, 0, 0, 0},
+            S1y[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 3; ++k) {
+      S0x[na1 - 1 - base1 + k] = sa1[k];
+      S1x[nb1 - 1 - base1 + k] = sb1[k];
+      S0y[na2 - 1 - base2 + k] = sa2[k];
+      S1y[nb2 - 1 - base2 + k] = sb2[k];
+    }
+    float qs = qw[p] * inv_wunit;
+    int64_t Q = (int64_t)rintf(qs);
+    int64_t C1[4], C2[4], acc1 = 0, acc2 = 0;
+    for (int a = 0; a < 4; ++a) {
+      acc1 += S1x[a] - S0x[a];
+      acc2 += S1y[a] - S0y[a];
+      C1[a] = acc1;
+      C2[a] = acc2;
+    }
+    for (int b = 0; b < 4; ++b) {
+      for (int a = 0; a < 4; ++a) {
+        int64_t idx = (int64_t)wrapi(base2 + b, n2) * n1 + wrapi(base1 + a, n1);
+        J1[idx] += Q * C1[a] * (S0y[b] + S1y[b]);
+        J2[idx] += Q * C2[b] * (S0x[a] + S1x[a]);
+      }
+    }
+    float hv = qs * v3[p];
+    float h = hv * c3;
+    for (int b = 0; b < 4; ++b) {
+      for (int a = 0; a < 4; ++a) {
+        float A0 = (float)S0x[a], A1 = (float)S1x[a];
+        float B0 = (float)S0y[b], B1 = (float)S1y[b];
+        float t0 = 2.0f * B0 + B1;
+        float t1 = B0 + 2.0f * B1;
+        float p0 = A0 * t0;
+        float p1 = A1 * t1;
+        float T = p0 + p1;
+        float v = T * h;
+        int64_t idx = (int64_t)wrapi(base2 + b, n2) * n1 + wrapi(base1 + a, n1);
+        J3[idx] += (int64_t)rintf(v);
+      }
+    }
+  }
+  return status;
+}
+
+void or_rho2_fixed(int32_t n1, int32_t n2, int32_t P, float inv_wunit, int64_t np,
+                   const int32_t *c1, const int32_t *c2, const float *f1, const float *f2,
+                   const float *qw, int64_t *rho) {
+  for (int64_t p = 0; p < np; ++p) {
+    int64_t s1[3], s2[3];
+    int32_t m1 = fixed_shape(c1[p], f1[p], P, s1);
+    int32_t m2 = fixed_shape(c2[p], f2[p], P, s2);
+    int64_t Q = (int64_t)rintf(qw[p] * inv_wunit);
+    for (int b = 0; b < 3; ++b)
+      for (int a = 0; a < 3; ++a)
+        rho[(int64_t)wrapi(m2 - 1 + b, n2) * n1 + wrapi(m1 - 1 + a, n1)] += Q * s1[a] * s2[b];
+  }
+}

@@ -1,0 +1,121 @@
+/*
+ * hpic_oracle.h -- declarations of the plain FP64 CPU oracle for the hybrid
+ * Yee-FFT particle-in-cell step of Yu et al., arXiv:1502.01376.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The oracle is what the GPU library is checked
+ * against.  Only the test-suite, the smoke check and the CPU-baseline leg of
+ * the benchmark may load it; the product path never does.  It shares no code,
+ * header, table or constant with the GPU library.
+ *
+ * Conventions (all routines):
+ *  - 2D grid of n1 x n2 cells, periodic in x1 and x2 (Table 1: periodic).
+ *  - Arrays of a field component are row-major [i2][i1], x1 fastest.
+ *  - Yee staggering (Eqs. (1)-(6)): E1 at (i1+1/2, i2), E2 at (i1, i2+1/2),
+ *    E3 at (i1, i2); B1 at (i1, i2+1/2), B2 at (i1+1/2, i2), B3 at
+ *    (i1+1/2, i2+1/2); j is staggered like E and rho sits on (i1, i2).
+ *    A half-integer position i+1/2 is stored at index i.
+ *  - Particle positions are given in cell units (xi = x / dx), so a node i
+ *    sits at xi = i.
+ *  - Units: c = 1, t in 1/w_p, x in c/w_p, E and B in m c w_p / e, charge
+ *    density in e n_p and current in e n_p c.  The 4*pi and c of the paper's
+ *    Gaussian equations are 1 in these units.
+ */
+#ifndef HPIC_ORACLE_H
+#define HPIC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* 2D grid and solver options.  alpha is the low-pass cutoff as a fraction of
+ * the x1 Nyquist wavenumber (Sec. 4; alpha >= 1 disables the filter).
+ * deriv1 = 0 uses the spectral derivative k1 along x1 (Eq. (20)); deriv1 = 1
+ * uses the finite-difference symbol [k]1 of Eq. (28), which turns the hybrid
+ * update back into the Yee scheme (end of Sec. 2.1).  correct = 1 applies the
+ * current correction of Eq. (11); 0 is an ablation used by tests.  jbg is a
+ * uniform background current added to the deposited current. */
+typedef struct or_grid2 {
+  int32_t n1, n2;
+  double dx1, dx2, dt;
+  double alpha;
+  int32_t deriv1;
+  int32_t correct;
+  double jbg[3];
+} or_grid2;
+
+/* Complex FFT of length n (power of two), in place.  sign = -1 computes
+ * X_k = sum_j x_j exp(-2 pi i j k / n); sign = +1 the same sum with +i and no
+ * 1/n factor.  Returns 0, or -1 if n is not a power of two. */
+int or_fft(int32_t n, double *re, double *im, int32_t sign);
+
+/* Forward transform of nrows real rows of length n1 along x1: F[row][kappa]
+ * for kappa = 0..n1/2 (the Nyquist bin is kept).  Inverse: rebuilds the full
+ * spectrum by Hermitian symmetry and returns the real rows including 1/n1. */
+int or_rfft_rows(int32_t n1, int32_t nrows, const double *f, double *Fre, double *Fim);
+int or_irfft_rows(int32_t n1, int32_t nrows, const double *Fre, const double *Fim, double *f);
+
+/* Momentum-conserving quadratic gather of E and B (each [3][n2][n1]) at np
+ * particles (xi1, xi2 in cell units).  Ep, Bp are [3][np]. */
+void or_gather2(const or_grid2 *g, const double *E, const double *B, int64_t np,
+                const double *xi1, const double *xi2, double *Ep, double *Bp);
+
+/* Relativistic Boris rotation of the momenta u = gamma v, in place. */
+void or_boris(int64_t np, double qm, double dt, const double *Ep, const double *Bp,
+              double *u1, double *u2, double *u3);
+
+/* Esirkepov charge-conserving deposit (quadratic shape) of particles moving
+ * from (xa1, xa2) to (xb1, xb2) (cell units, xb not wrapped) over one step,
+ * added into J [3][n2][n1].  v3 is the out-of-plane velocity and qw the
+ * charge times weight of each particle.  Returns 0, or -1 if a particle moved
+ * one cell or more along a coordinate. */
+int or_deposit2(const or_grid2 *g, int64_t np, const double *xa1, const double *xa2,
+                const double *xb1, const double *xb2, const double *v3, const double *qw,
+                double *J);
+
+/* Charge density on the integer nodes, quadratic shape, added into rho. */
+void or_rho2(const or_grid2 *g, int64_t np, const double *xi1, const double *xi2,
+             const double *qw, double *rho);
+
+/* One field update E^n, B^n -> E^{n+1}, B^{n+1} with the current j^{n+1/2}
+ * (J [3][n2][n1], the background g->jbg is added here).  Hybrid solver:
+ * FFT along x1, current correction and filter, Eqs. (12)-(17) with B split
+ * into two half steps, inverse FFT. */
+int or_field_update2(const or_grid2 *g, double *E, double *B, const double *J);
+
+/* The same update done directly in real space with the Yee differences of
+ * Eqs. (1)-(6) (no FFT, no filter, no correction; jbg is added). */
+void or_yee_update2(const or_grid2 *g, double *E, double *B, const double *J);
+
+/* One whole step: gather, Boris push, move, deposit, field update.  Positions
+ * are wrapped back into [0, n) at the end.  J receives the deposited current
+ * (without background).  Returns 0, or -1 on a move of a cell or more. */
+int or_step2(const or_grid2 *g, double qm, int64_t np, double *xi1, double *xi2,
+             double *u1, double *u2, double *u3, const double *qw, double *E, double *B,
+             double *J);
+
+/* Gauss-law residual of Eq. (27) in (kappa1, i2) space: R = D.E - f rho, with
+ * the same x1 derivative as the update and f the current filter.  rho is the
+ * total charge density on the nodes.  R is [n2][n1/2+1]. */
+int or_gauss2(const or_grid2 *g, const double *E, const double *rho, double *Rre, double *Rim);
+
+/* ---- Fixed-point deposit, in the precision of the GPU kernel ----
+ * Where floating point decides an integer, the oracle takes that decision in
+ * the kernel's precision (FP32), so that both sides land on the same integers.
+ * Positions are a cell index plus an FP32 offset in [0,1).  Shape factors are
+ * quantised to integers with exact sum 2^P; the integer Esirkepov weights then
+ * satisfy the discrete continuity equation exactly (see the .c file). */
+int or_deposit2_fixed(int32_t n1, int32_t n2, int32_t P, float inv_wunit, float c3,
+                      int64_t np, const int32_t *ca1, const int32_t *ca2, const float *fa1,
+                      const float *fa2, const int32_t *cb1, const int32_t *cb2,
+                      const float *fb1, const float *fb2, const float *v3, const float *qw,
+                      int64_t *J);
+void or_rho2_fixed(int32_t n1, int32_t n2, int32_t P, float inv_wunit, int64_t np,
+                   const int32_t *c1, const int32_t *c2, const float *f1, const float *f2,
+                   const float *qw, int64_t *rho);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

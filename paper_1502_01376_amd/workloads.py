@@ -1,0 +1,165 @@
+"""Seeded synthetic inputs for the hybrid Yee-FFT PIC step.
+
+This module holds only input generation: particle loading, momenta, weights
+and analytic initial fields.  It contains none of the method's arithmetic (no
+gather, push, deposit, transform or field update), so both the oracle-side
+tests and the GPU path can take their inputs from it.
+
+Every generator draws from ``numpy.random.Generator(PCG64(seed))``.  Positions
+are returned in cell units ``xi = x / dx`` in ``[0, n)``; momenta are
+``u = gamma v`` (c = 1); ``w`` is the density weight of each macro-particle
+(charge density = q * sum_p w_p * shape), so a uniform density n with ppc
+particles per cell has ``w = n / ppc``.
+
+The named workloads are the drifting-plasma set-ups of the benchmark suite:
+
+* ``drift2d_small``  -- 64 x 32 cells, dx = 0.2, dt = 0.05, quiet 2x2 lattice,
+  gamma = 50, thermal spread 1e-4, filter at half the x1 Nyquist wavenumber.
+* ``drift2d_laser``  -- 2048 x 512 cells, dx = (0.1, 0.2), dt = 0.045,
+  4x2 sub-lattice with uniform jitter (8 per cell), gamma = 20 cold, plus a
+  linearly polarised Gaussian laser (a0 = 2, waist 8, length 4).
+
+The NCI test set-up of Table 1 (dx = 0.2, dt = 0.4 dx1, periodic,
+51.2 x 51.2, gamma = 50, n = 100) is ``nci_table1``.
+"""
+import math
+
+import numpy as np
+
+SEED0 = 1502013760
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def lattice_2d(n1, n2, sub1, sub2, jitter, gen):
+    """Positions of a sub1 x sub2 sub-lattice in every cell (cell units).
+
+    With ``jitter`` false each particle sits at the centre of its sub-cell
+    (offsets 1/4, 3/4 for two per direction); with ``jitter`` true it is placed
+    uniformly at random inside its sub-cell.
+    """
+    i1 = np.arange(n1, dtype=np.float64)
+    i2 = np.arange(n2, dtype=np.float64)
+    a = (np.arange(sub1, dtype=np.float64) + 0.5) / sub1
+    b = (np.arange(sub2, dtype=np.float64) + 0.5) / sub2
+    # particle order: cell-major (i2, i1), then sub-cell (b, a)
+    x1 = (i1[None, :, None, None] + a[None, None, None, :]) + 0.0 * b[None, None, :, None]
+    x2 = (i2[:, None, None, None] + b[None, None, :, None]) + 0.0 * a[None, None, None, :]
+    x1 = np.broadcast_to(x1, (n2, n1, sub2, sub1)).reshape(-1).copy()
+    x2 = np.broadcast_to(x2, (n2, n1, sub2, sub1)).reshape(-1).copy()
+    if jitter:
+        x1 += (gen.random(x1.size) - 0.5) / sub1
+        x2 += (gen.random(x2.size) - 0.5) / sub2
+    x1 = np.mod(x1, n1)
+    x2 = np.mod(x2, n2)
+    return x1, x2
+
+
+def drift_momenta(npart, gamma, sigma_u, gen):
+    """u = (sqrt(gamma^2 - 1), 0, 0) plus a Gaussian spread sigma_u per component."""
+    u = np.zeros((3, npart))
+    u[0] = math.sqrt(gamma * gamma - 1.0)
+    if sigma_u > 0:
+        u += sigma_u * gen.standard_normal((3, npart))
+    return u
+
+
+def mean_current(u, w, q, ncells):
+    """Uniform current density of the loaded particles: sum_p q w_p v_p / ncells.
+
+    This is the background current of infinitely heavy co-drifting ions that
+    cancels the net electron current (j_bg = -mean_current)."""
+    gam = np.sqrt(1.0 + (u * u).sum(axis=0))
+    return (q * w[None, :] * u / gam[None, :]).sum(axis=1) / ncells
+
+
+def laser_2d(n1, n2, dx1, dx2, a0, waist, length, k0, x1c, x2c):
+    """Gaussian laser polarised along x3, moving in -x1, from the vector potential
+
+        A3 = a0 exp(-((x1-x1c)/L)^2) exp(-((x2-x2c)/W)^2) cos(k0 (x1-x1c))
+
+    E3 = -dA3/dt = -dA3/dx1 (a wave moving in -x1) and B = curl(A3 e3) =
+    (dA3/dx2, -dA3/dx1, 0), each evaluated analytically at its Yee node.
+    Returns E, B as [3][n2][n1] arrays."""
+
+    def parts(x1, x2):
+        s1 = x1 - x1c
+        s2 = x2 - x2c
+        g1 = np.exp(-(s1 / length) ** 2)
+        g2 = np.exp(-(s2 / waist) ** 2)
+        c = np.cos(k0 * s1)
+        s = np.sin(k0 * s1)
+        d1 = a0 * g2 * (-2.0 * s1 / length ** 2 * g1 * c - g1 * k0 * s)  # dA3/dx1
+        d2 = a0 * g1 * c * (-2.0 * s2 / waist ** 2 * g2)                 # dA3/dx2
+        return d1, d2
+
+    i1 = np.arange(n1, dtype=np.float64)
+    i2 = np.arange(n2, dtype=np.float64)
+    E = np.zeros((3, n2, n1))
+    B = np.zeros((3, n2, n1))
+    # E3 at (i1, i2)
+    X1, X2 = np.meshgrid(i1 * dx1, i2 * dx2)
+    d1, _ = parts(X1, X2)
+    E[2] = -d1
+    # B1 at (i1, i2 + 1/2)
+    X1, X2 = np.meshgrid(i1 * dx1, (i2 + 0.5) * dx2)
+    _, d2 = parts(X1, X2)
+    B[0] = d2
+    # B2 at (i1 + 1/2, i2)
+    X1, X2 = np.meshgrid((i1 + 0.5) * dx1, i2 * dx2)
+    d1, _ = parts(X1, X2)
+    B[1] = -d1
+    return E, B
+
+
+def drift2d(n1, n2, dx1, dx2, dt, sub=(2, 2), gamma=50.0, sigma_u=1e-4, density=1.0,
+            jitter=False, alpha=0.5, seed=SEED0, laser=None, name="drift2d"):
+    """A 2D electron plasma drifting along x1 over a neutralising background.
+
+    Returns a dict with the grid, particle arrays and initial fields."""
+    gen = rng(seed)
+    x1, x2 = lattice_2d(n1, n2, sub[0], sub[1], jitter, gen)
+    npart = x1.size
+    ppc = sub[0] * sub[1]
+    u = drift_momenta(npart, gamma, sigma_u, gen)
+    w = np.full(npart, density / ppc)
+    q, qm = -1.0, -1.0
+    E = np.zeros((3, n2, n1))
+    B = np.zeros((3, n2, n1))
+    if laser is not None:
+        E, B = laser_2d(n1, n2, dx1, dx2, **laser)
+    jbg = -mean_current(u, w, q, n1 * n2)
+    return dict(name=name, geom=2, n=(n1, n2, 1), dx=(dx1, dx2, 1.0), dt=dt, alpha=alpha,
+                xi=np.stack([x1, x2]), u=u, w=w, q=q, qm=qm, E=E, B=B, jbg=jbg, seed=seed)
+
+
+def drift2d_small(seed=SEED0 + 0):
+    """64 x 32 cells, dx = 0.2, dt = 0.05, 2x2 quiet lattice (8192 particles),
+    uniform density, gamma = 50 with thermal spread 1e-4, filter 0.5, 100 steps."""
+    d = drift2d(64, 32, 0.2, 0.2, 0.05, sub=(2, 2), gamma=50.0, sigma_u=1e-4, seed=seed,
+                name="drift2d_64x32_g50")
+    d["steps"] = 100
+    return d
+
+
+def drift2d_laser(seed=SEED0 + 1, n1=2048, n2=512):
+    """2048 x 512 cells, dx = (0.1, 0.2), dt = 0.045, 8 per cell as a jittered
+    4x2 sub-lattice (8 388 608 particles), gamma = 20 cold, Gaussian laser
+    a0 = 2, waist 8, length 4, k0 = 10, moving against the drift."""
+    dx1, dx2 = 0.1, 0.2
+    L1, L2 = n1 * dx1, n2 * dx2
+    laser = dict(a0=2.0, waist=8.0, length=4.0, k0=10.0, x1c=0.75 * L1, x2c=0.5 * L2)
+    d = drift2d(n1, n2, dx1, dx2, 0.045, sub=(4, 2), gamma=20.0, sigma_u=0.0, jitter=True,
+                seed=seed, laser=laser, name="drift2d_%dx%d_g20_laser" % (n1, n2))
+    d["steps"] = 1000
+    return d
+
+
+def nci_table1(seed=SEED0 + 10, ppc=(2, 2), n=(256, 256)):
+    """Table 1: dx = (0.2, 0.2), dt = 0.4 dx1, periodic, 51.2 x 51.2 (256 x 256
+    cells), gamma = 50, n/n_p = 100."""
+    d = drift2d(n[0], n[1], 0.2, 0.2, 0.08, sub=ppc, gamma=50.0, sigma_u=1e-4, density=100.0,
+                seed=seed, name="nci_table1")
+    return d
