@@ -1,0 +1,161 @@
+"""Benchmark of the hybrid Yee-FFT PIC step on one MI355X.
+
+Workload: the 2D drifting-plasma laser case, 2048 x 512 cells, dx = (0.1, 0.2),
+dt = 0.045, 8 particles per cell (8 388 608), gamma = 20, Gaussian laser
+a0 = 2 (synthetic, seeded).  One step is the whole hot path: gather + Boris +
+charge-conserving deposit, FFT of j along x1 with the current correction and
+the low-pass filter, hybrid Maxwell update, inverse FFT of E and B.
+
+Prints one JSON line: particle-steps/s of the FP32 form (64-bit fixed-point
+deposit) with the FP64 form measured beside it and the FP32-vs-FP64 field error,
+the roofline of the push+deposit kernel from HIP-event timing, and the FP64 CPU
+oracle timed on the host on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# Algorithmic HBM bytes of one push+deposit launch: each particle's state is
+# read once (cell 4 + offsets 8 + momenta 12 + charge 4 = 28 B) and written
+# once (24 B); each cell's six FP32 field values are read once (24 B) and its
+# three 64-bit current accumulators read and written once (48 B).
+BYTES_PER_PARTICLE = 52
+BYTES_PER_CELL = 72
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--fp64-steps", type=int, default=50,
+                    help="steps of the FP64 form timed beside the FP32 form (0: skip)")
+    ap.add_argument("--err-steps", type=int, default=100,
+                    help="steps over which the FP32 form is compared with the FP64 form")
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--n1", type=int, default=2048)
+    ap.add_argument("--n2", type=int, default=512)
+    return ap.parse_args()
+
+
+def run_form(hpic, torch, d, precision, warmup, steps, profile=False):
+    sim = hpic.from_workload(d, precision, stream=torch.cuda.current_stream())
+    sim.step(warmup)
+    sim.synchronize()
+    if profile:
+        sim.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.synchronize()
+    kt = sim.kernel_times() if profile else None
+    return sim, (t1 - t0), kt
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cpu_baseline(d):
+    """FP64 oracle on the host: one full step of the same workload."""
+    import oracle
+    g = oracle.grid2(d["n"][0], d["n"][1], d["dx"][0], d["dx"][1], d["dt"], alpha=d["alpha"],
+                     jbg=d["jbg"])
+    st = oracle.State2(g, d["qm"], d["xi"][0], d["xi"][1], d["u"], d["q"] * d["w"],
+                       E=d["E"], B=d["B"])
+    npart = d["w"].size
+    t0 = time.perf_counter()
+    st.step(1)
+    dt = time.perf_counter() - t0
+    return {"value": npart / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "1 full step of the same workload (%d particles, %dx%d grid), "
+                      "single-threaded FP64 C, %.1f s" % (npart, d["n"][0], d["n"][1], dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1502_01376_amd import hpic
+    from paper_1502_01376_amd import workloads as W
+
+    d = W.drift2d_laser(n1=args.n1, n2=args.n2)
+    npart = d["w"].size
+    ncell = d["n"][0] * d["n"][1]
+
+    sim32, t32, kt = run_form(hpic, torch, d, "fp32", args.warmup, args.steps, profile=True)
+    value = npart * args.steps / t32
+    ms_step = 1e3 * t32 / args.steps
+    pd_ms, pd_n = kt["push_deposit"]
+    pd_avg_s = pd_ms / max(pd_n, 1) * 1e-3
+    alg_bytes = BYTES_PER_PARTICLE * npart + BYTES_PER_CELL * ncell
+    achieved = alg_bytes / pd_avg_s / 1e9
+    kernels = {k: {"avg_us": 1e3 * ms / max(n, 1), "launches": n} for k, (ms, n) in kt.items()}
+    sim32.close()
+
+    out = {
+        "metric": "particle-steps/sec (push+deposit+hybrid solve), FP32-batched vs FP64 at stated err",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": d["name"], "n1": d["n"][0], "n2": d["n"][1],
+                   "dx": list(d["dx"][:2]), "dt": d["dt"], "particles": npart,
+                   "particles_per_cell": 8, "gamma": 20.0, "laser_a0": 2.0,
+                   "filter_frac": d["alpha"], "deposit_accumulator": "int64 fixed point",
+                   "parallelism": "single GPU"},
+        "kernels": kernels,
+        "roofline": {"bound": "hbm", "kernel": "push_deposit", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "alg_bytes_per_launch": alg_bytes},
+    }
+
+    if args.fp64_steps > 0:
+        sim64, t64, _ = run_form(hpic, torch, d, "fp64", min(args.warmup, 5), args.fp64_steps)
+        sim64.close()
+        out["fp64_form"] = {"value": npart * args.fp64_steps / t64,
+                            "ms_per_step": 1e3 * t64 / args.fp64_steps,
+                            "steps": args.fp64_steps,
+                            "fp32_speedup": value / (npart * args.fp64_steps / t64)}
+    if args.err_steps > 0:
+        a = hpic.from_workload(d, "fp32")
+        b = hpic.from_workload(d, "fp64")
+        a.step(args.err_steps)
+        b.step(args.err_steps)
+        Ea, Ba = a.fields(0)
+        Eb, Bb = b.fields(0)
+        ja = np.stack([a.current(0, c) for c in range(3)])
+        jb = np.stack([b.current(0, c) for c in range(3)])
+        da = a.diagnostics(0)
+        out["err_vs_fp64"] = {"steps": args.err_steps, "E_rel_l2": rel_l2(Ea, Eb),
+                              "B_rel_l2": rel_l2(Ba, Bb), "J_rel_l2": rel_l2(ja, jb),
+                              "gauss_rel_l2_fp32": da["gauss_l2"] / max(da["gauss_ref_l2"], 1e-300)}
+        a.close()
+        b.close()
+    if args.cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(d)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * hpic.h -- C ABI of the MI355X hybrid Yee-FFT particle-in-cell library.
+ *
+ * The library advances relativistic electromagnetic PIC runs with the hybrid
+ * Maxwell solver of Yu et al., arXiv:1502.01376: the field equations are
+ * solved in (k1, x2) space after an FFT along the drift direction x1, with the
+ * x1 derivative spectral (Eq. (20)) and the x2 derivative a Yee finite
+ * difference (Eqs. (12)-(17)); the current comes from a local charge-conserving
+ * deposit, is corrected by Eq. (11) so that Gauss's law (27) is kept, and is
+ * low-pass filtered along k1 (Sec. 4).  Every step of the path runs in HIP
+ * kernels on one gfx950 GPU.
+ *
+ * One step (Sec. 2.1 order): relativistic Boris push with a quadratic field
+ * gather, charge-conserving (Esirkepov) deposit of j^{n+1/2}, FFT of j along
+ * x1, current correction and filter, hybrid Maxwell update of E and B, inverse
+ * FFT of E and B for the next push.
+ *
+ * Grid conventions: n1 x n2 cells, periodic; field arrays are [i2][i1] with x1
+ * fastest; Yee staggering of Eqs. (1)-(6): E1 (i1+1/2, i2), E2 (i1, i2+1/2),
+ * E3 (i1, i2), B1 (i1, i2+1/2), B2 (i1+1/2, i2), B3 (i1+1/2, i2+1/2), j like E,
+ * rho on (i1, i2); a half-integer position i+1/2 is stored at index i.
+ * Units: c = 1, t in 1/w_p, x in c/w_p, E and B in m c w_p / e, density in
+ * n_p, current in e n_p c (the 4 pi of the paper's Gaussian form is 1).
+ *
+ * Errors: every call returns 0 (HP_OK) or a negative HP_E* code; the message
+ * of the last failing call on the calling thread is hp_last_error().  A handle
+ * must not be used from two threads at once.  No exception crosses the ABI.
+ */
+#ifndef HPIC_H
+#define HPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HP_OK 0
+#define HP_EINVAL (-1)   /* bad argument, size or enum */
+#define HP_ECOURANT (-2) /* dt above the stability limit of Eq. (22) */
+#define HP_ENOMEM (-3)   /* device allocation failed */
+#define HP_EDEVICE (-4)  /* HIP runtime error or no device */
+#define HP_ERANGE (-5)   /* particle moved a cell or more, or fixed-point headroom exceeded */
+#define HP_ENUMERIC (-6) /* non-finite particle momentum or position */
+#define HP_ESTATE (-7)   /* call out of order (e.g. step before particles) */
+
+#define HP_GEOM_2D 2
+
+#define HP_PREC_FP32_FIXED 0 /* FP32 push/FFT/update, 64-bit fixed-point deposit */
+#define HP_PREC_FP64 1       /* FP64 everywhere, FP64 atomics in the deposit */
+
+/* Kernel indices of hp_get_kernel_times. */
+#define HP_K_PUSH_DEPOSIT 0
+#define HP_K_FFT_J 1
+#define HP_K_KUPDATE 2
+#define HP_K_IFFT_EB 3
+#define HP_K_SORT 4
+#define HP_NK 5
+
+/* Per-run configuration.  n[0] (x1, the FFT direction) must be a power of two
+ * in [8, 4096]; n[1] >= 4.  dt must satisfy the hybrid Courant condition
+ * dt <= 2 / sqrt(pi^2/dx1^2 + 4/dx2^2) of Eq. (22) (for deriv1 = 1 the Yee
+ * limit 1/sqrt(1/dx1^2 + 1/dx2^2)), otherwise HP_ECOURANT. */
+typedef struct hp_config {
+  int32_t geom;              /* HP_GEOM_2D */
+  int32_t n[3];              /* cells per direction (n[2] unused in 2D) */
+  double dx[3];              /* cell sizes */
+  double dt;                 /* time step */
+  int32_t shape_order;       /* particle shape order, 2 (quadratic) */
+  int32_t interp;            /* 0: momentum-conserving gather (Appendix A) */
+  double filter_frac;        /* low-pass cutoff alpha: keep |k1| <= alpha pi/dx1
+                                (Sec. 4); >= 1 disables */
+  int32_t deriv1;            /* 0: spectral k1 (Eq. (20)); 1: FD [k]1 (Eq. (28)) */
+  int32_t correct;           /* 1: current correction of Eq. (11); 0 only for tests */
+  int32_t n_modes;           /* azimuthal modes (quasi-3D; unused in 2D) */
+  int32_t precision;         /* HP_PREC_FP32_FIXED or HP_PREC_FP64; same for all runs */
+  int32_t fixed_shape_bits;  /* P: shape factors quantised to 2^-P; 0 = 20 */
+  int32_t fixed_weight_bits; /* Q: charges quantised to 2^-Q of the largest;
+                                0 = automatic (exact for equal weights, else the
+                                largest Q <= 15 the headroom allows) */
+  int32_t sort_interval;     /* particle tile sort every K steps; 0 = automatic */
+  int32_t reserved[8];
+} hp_config;
+
+/* FP64 diagnostics of one run (Sec. 2.3 and energies), see hp_diagnostics. */
+typedef struct hp_diag {
+  double W_E[3];        /* field energy 1/2 sum E_c^2 dV per component */
+  double W_B[3];        /* 1/2 sum B_c^2 dV */
+  double kinetic;       /* sum_p m w_p (gamma_p - 1) dV */
+  double gauss_l2;      /* || D.E - f (rho + rho_bg) ||_2 over (kappa1, i2), Eq. (27) */
+  double gauss_linf;    /* max-norm of the same residual */
+  double gauss_ref_l2;  /* || f (rho + rho_bg) ||_2 (scale for the residual) */
+  double cont_linf;     /* max-norm of the continuity residual (23) of the last step, or -1 */
+  int64_t cont_int;     /* FP32_FIXED: max |2 (rho_new - rho_old) - div J| in integers, or -1 */
+  double charge_total;  /* sum of rho dV */
+  int64_t step;         /* steps taken */
+} hp_diag;
+
+typedef struct hp_sim hp_sim;
+
+/* Creates a handle with nruns independent runs (one batched launch per stage
+ * advances all of them).  cfgs[nruns] is read before return.  The library owns
+ * *out and all device memory; release with hp_destroy.  Errors: HP_EINVAL,
+ * HP_ECOURANT, HP_ENOMEM, HP_EDEVICE. */
+int hp_create(const hp_config *cfgs, int32_t nruns, hp_sim **out);
+void hp_destroy(hp_sim *sim);
+const char *hp_last_error(void);
+
+/* All later device work of the handle is enqueued on this HIP stream (NULL:
+ * the null stream).  The stream stays owned by the caller. */
+int hp_set_stream(hp_sim *sim, void *hip_stream);
+
+/* Loads n particles of one species into a run (replacing any previous ones).
+ * x is [2][n] in physical units (wrapped into the box), u = gamma v is [3][n],
+ * w[n] the density weight (charge density = q sum w S).  Host buffers are
+ * caller-owned and copied before return.  Sets the fixed-point charge unit of
+ * the run.  Errors: HP_EINVAL (species != 0, n out of range, non-finite
+ * input), HP_ERANGE (fixed-point headroom). */
+int hp_set_particles(hp_sim *sim, int32_t run, int32_t species, int64_t n, const double *x,
+                     const double *u, const double *w, double q_over_m, double q);
+
+/* Sets E^0 and B^0 of a run from host arrays E[3][n2][n1], B[3][n2][n1] at
+ * their Yee nodes (mode must be 0 in 2D). */
+int hp_set_fields(hp_sim *sim, int32_t run, int32_t mode, const double *E, const double *B);
+
+/* Background of a run: with rho_from_particles = 1 the fixed charge density
+ * rho_bg = -rho_e(now) is recorded (used only by the Gauss diagnostic); j_bg[3]
+ * is a uniform current added to the deposited one every step (NULL: zero). */
+int hp_set_background(hp_sim *sim, int32_t run, int32_t rho_from_particles,
+                      const double *j_bg);
+
+/* Advances every run nsteps steps, asynchronously on the handle's stream.
+ * Kernel-detected errors (HP_ERANGE, HP_ENUMERIC) are reported by the next
+ * synchronous call. */
+int hp_step(hp_sim *sim, int32_t nsteps);
+
+/* Waits for the handle's stream and reports kernel-detected errors. */
+int hp_synchronize(hp_sim *sim);
+
+/* Copies field component comp (0..2 = E1..E3, 3..5 = B1..B3) of a run into
+ * out[count], count = n1 n2 (else HP_EINVAL).  Synchronous. */
+int hp_get_field(hp_sim *sim, int32_t run, int32_t comp, int32_t mode, double *out,
+                 size_t count);
+
+/* Current j^{n-1/2} of the last step, component comp (0..2), in physical
+ * units on the j nodes: corrected = 0 as deposited (plus background);
+ * corrected = 1 after Eq. (11) and the filter (transformed back to x1). */
+int hp_get_current(hp_sim *sim, int32_t run, int32_t comp, int32_t corrected, double *out,
+                   size_t count);
+
+/* FP32_FIXED only: the raw 64-bit accumulator of the last step's deposit. */
+int hp_get_current_fixed(hp_sim *sim, int32_t run, int32_t comp, int64_t *out, size_t count);
+
+/* Number of particles of a run. */
+int hp_get_particle_count(hp_sim *sim, int32_t run, int64_t *n);
+
+/* Particles of a run in the library's current order: x[2][n] physical
+ * positions, u[3][n], w[n], id[n] (index given at hp_set_particles).  Any
+ * pointer may be NULL.  n must equal the particle count. */
+int hp_get_particles(hp_sim *sim, int32_t run, int64_t n, double *x, double *u, double *w,
+                     int64_t *id);
+
+/* FP32_FIXED only: raw state, cell[2][n] (i1, i2), off[2][n] in [0,1),
+ * u[3][n], qw[n] (charge times weight), id[n].  Any pointer may be NULL. */
+int hp_get_particles_raw(hp_sim *sim, int32_t run, int64_t n, int32_t *cell, float *off,
+                         float *u, float *qw, int32_t *id);
+
+/* FP64 diagnostics of a run (energies, Gauss residual, continuity residual of
+ * the last step when the previous hp_diagnostics call was one step earlier). */
+int hp_diagnostics(hp_sim *sim, int32_t run, hp_diag *out);
+
+/* Checkpoint: with blob == NULL writes the needed size to *size; otherwise
+ * fills blob (size bytes).  hp_set_state restores a handle created with the
+ * same configs; resuming is bit-exact. */
+int hp_get_state(hp_sim *sim, void *blob, size_t *size);
+int hp_set_state(hp_sim *sim, const void *blob, size_t size);
+
+/* FP32_FIXED only: the deposit kernel alone on host-given particles of a run's
+ * grid (n moves from cell0/off0 to cell1/off1, cells as [2][n]), returning the
+ * 64-bit accumulators j_out[3][n2][n1].  For bit-exact tests. */
+int hp_debug_deposit(hp_sim *sim, int32_t run, int64_t n, const int32_t *cell0,
+                     const float *off0, const int32_t *cell1, const float *off1,
+                     const float *v3, const float *qw, int64_t *j_out);
+
+/* FP32_FIXED only: out[0] = P, out[1] = inv_wunit, out[2] = c3, out[3] = Q of a
+ * run (the fixed-point parameters of the deposit). */
+int hp_get_fixed_params(hp_sim *sim, int32_t run, double *out);
+
+/* Per-kernel timing with HIP events on the handle's stream: enable = 1 starts
+ * recording (and clears the totals), 0 stops.  hp_get_kernel_times returns the
+ * summed milliseconds ms[HP_NK] and launch counts n[HP_NK] (synchronous). */
+int hp_profile(hp_sim *sim, int32_t enable);
+int hp_get_kernel_times(hp_sim *sim, double *ms, int64_t *n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

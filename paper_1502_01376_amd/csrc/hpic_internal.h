@@ -1,0 +1,232 @@
+// hpic_internal.h -- device-side data layout and helpers of the MI355X hybrid
+// Yee-FFT PIC library.  Shared by the kernels (kernels.hip) and the host
+// runtime (runtime.cpp); not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hp {
+
+// ---------------------------------------------------------------- types
+template <class R> struct Cplx;
+template <> struct Cplx<float> { using T = float2; };
+template <> struct Cplx<double> { using T = double2; };
+
+// Deposit accumulator: 64-bit fixed point for the FP32 form, FP64 otherwise.
+template <class R> struct AccOf;
+template <> struct AccOf<float> { using T = long long; };
+template <> struct AccOf<double> { using T = double; };
+
+// One work item of a batched launch: run index and two item-specific ints.
+struct Item {
+  int run;
+  int a;
+  int b;
+};
+
+// Device-side description of one 2D run.  Arrays are owned by the host runtime.
+//   particles: cell[np] (linear i2*n1 + i1), f1/f2[np] offsets in [0,1),
+//              u1..u3[np] momenta, qw[np] charge times weight, id[np]
+//   F:   real-space fields [6][n2][n1] (E1 E2 E3 B1 B2 B3) for the gather
+//   Fk:  k-space master copy [6][n2][nk] (ping-pong, index = step parity)
+//   J:   deposit accumulators [3][n2][n1] (ping-pong, index = step parity)
+//   Jk:  corrected, filtered current [3][n2][nk]
+template <class R>
+struct Run {
+  using C = typename Cplx<R>::T;
+  using Acc = typename AccOf<R>::T;
+  int n1, n2, log2n1, nk;
+  int np;
+  int P;             // fixed point: shape factors in units of 2^-P
+  float inv_wunit;   // fixed point: integer charge = rint(qw * inv_wunit)
+  float c3;          // fixed point: scale of the out-of-plane current
+  R dt, hdt, idx2;   // dt, dt/2, 1/dx2
+  R dtdx1, dtdx2;    // dt/dx1, dt/dx2 (position advance in cells per unit velocity)
+  R qmhdt;           // (q/m) dt/2
+  R jfx1, jfx2;      // FP64 form: -dx1/dt, -dx2/dt (current of a unit-charge move)
+  R inv_m;           // 1/M, M = n1/2 (inverse real FFT normalisation)
+  R jbg0[3];         // n1 * j_bg: added to the kappa = 0 bin of every row
+  int *cell, *id;
+  R *f1, *f2, *u1, *u2, *u3, *qw;
+  R *F;
+  C *Fk[2];
+  Acc *J[2];
+  C *Jk;
+  const C *tw;       // [n1]: exp(-2 pi i m / n1)
+  const R *sym;      // [nk][4]: i k1 xi+ (re, im), i k1 xi- (re, im)
+  const R *jfac;     // [nk][3]: factor on the transformed accumulator per component
+};
+
+// ---------------------------------------------------------------- complex
+__device__ __forceinline__ float2 cmk(float x, float y) { return make_float2(x, y); }
+__device__ __forceinline__ double2 cmk(double x, double y) { return make_double2(x, y); }
+template <class C> __device__ __forceinline__ C cadd(C a, C b) { return cmk(a.x + b.x, a.y + b.y); }
+template <class C> __device__ __forceinline__ C csub(C a, C b) { return cmk(a.x - b.x, a.y - b.y); }
+template <class C> __device__ __forceinline__ C cmul(C a, C b) {
+  return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <class C> __device__ __forceinline__ C cconj(C a) { return cmk(a.x, -a.y); }
+template <class C, class R> __device__ __forceinline__ C cscale(C a, R s) { return cmk(a.x * s, a.y * s); }
+// multiply by +i (inv = true) or -i
+template <class C> __device__ __forceinline__ C cmuli(C a, bool plus) {
+  return plus ? cmk(-a.y, a.x) : cmk(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------- LDS FFT
+// NF independent complex transforms of length M = 2^log2M stored back to back
+// in LDS (buf[f*M + j]), computed by the whole workgroup with Stockham
+// auto-sort radix-4 passes and, for odd log2M, a final radix-2 pass.
+// tw[m * tws] = exp(-2 pi i m / M); inverse = true uses the conjugate twiddles
+// (no 1/M).  MAXB bounds the radix-4 butterflies per thread per pass.
+template <class C, int MAXB>
+__device__ void lds_fft(C *buf, int M, int log2M, int NF, const C *__restrict__ tw, int tws,
+                        bool inverse) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int Q = M >> 2;
+  const int log2Q = log2M - 2;
+  int s = 0;  // log2 of the span Ns already transformed
+  for (; s + 2 <= log2M; s += 2) {
+    const int Ns = 1 << s;
+    C v[MAXB][4];
+    int ob[MAXB];
+    int cnt = 0;
+    const int total = NF * Q;
+#pragma unroll
+    for (int it = 0; it < MAXB; ++it) {
+      const int g = tid + it * nthr;
+      if (g < total) {
+        const int f = g >> log2Q;
+        const int j = g & (Q - 1);
+        C *x = buf + f * M;
+        const int k = j & (Ns - 1);
+        C a0 = x[j], a1 = x[j + Q], a2 = x[j + 2 * Q], a3 = x[j + 3 * Q];
+        if (s > 0) {
+          // twiddle w^(r k), w = exp(-+2 pi i / (4 Ns)) -> table index r k M / (4 Ns)
+          const int e = k << (log2Q - s);
+          C t1 = tw[(e)*tws], t2 = tw[(2 * e) * tws], t3 = tw[(3 * e) * tws];
+          if (inverse) { t1 = cconj(t1); t2 = cconj(t2); t3 = cconj(t3); }
+          a1 = cmul(a1, t1);
+          a2 = cmul(a2, t2);
+          a3 = cmul(a3, t3);
+        }
+        const C b0 = cadd(a0, a2), b1 = csub(a0, a2), b2 = cadd(a1, a3);
+        const C b3 = cmuli(csub(a1, a3), inverse);
+        v[it][0] = cadd(b0, b2);
+        v[it][1] = cadd(b1, b3);
+        v[it][2] = csub(b0, b2);
+        v[it][3] = csub(b1, b3);
+        ob[it] = f * M + ((j >> s) << (s + 2)) + k;
+        cnt = it + 1;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < MAXB; ++it) {
+      if (it < cnt) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) buf[ob[it] + q * Ns] = v[it][q];
+      }
+    }
+    __syncthreads();
+  }
+  if (s < log2M) {
+    // final radix-2 pass: Ns = M/2, in place (each thread owns its pair)
+    const int H = M >> 1;
+    const int total = NF * H;
+    for (int g = tid; g < total; g += nthr) {
+      const int f = g >> (log2M - 1);
+      const int j = g & (H - 1);
+      C *x = buf + f * M;
+      C t = tw[j * tws];
+      if (inverse) t = cconj(t);
+      const C a0 = x[j], a1 = cmul(x[j + H], t);
+      x[j] = cadd(a0, a1);
+      x[j + H] = csub(a0, a1);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- shapes
+// Quadratic B-spline weights of the nodes m-1, m, m+1 for a particle at signed
+// distance d in [-1/2, 1/2) from its nearest node m.
+template <class R> __device__ __forceinline__ void spline3(R d, R w[3]) {
+  const R a = R(0.5) - d, b = R(0.5) + d;
+  w[0] = R(0.5) * a * a;
+  w[1] = R(0.75) - d * d;
+  w[2] = R(0.5) * b * b;
+}
+
+// Quantised quadratic shape of one coordinate (cell + FP32 offset): integers
+// s[0..2] of the nodes m-1, m, m+1 with exact sum 2^P; returns m.  The same
+// definition as the FP32-precision reference deposit.
+__device__ __forceinline__ int fixed_shape(int cell, float f, int P, int s[3]) {
+  const int up = (f >= 0.5f) ? 1 : 0;
+  const float d = up ? (f - 1.0f) : f;             // exact
+  const float scaled = d * (float)(1 << P);         // exact
+  const long long D = (long long)rintf(scaled);
+  const long long h = 1ll << (P - 1);
+  const long long bias = 1ll << P;
+  const long long lo = h - D, hi = h + D;
+  s[0] = (int)((lo * lo + bias) >> (P + 1));
+  s[2] = (int)((hi * hi + bias) >> (P + 1));
+  s[1] = (1 << P) - s[0] - s[2];
+  return cell + up;
+}
+
+__device__ __forceinline__ int wrap_pow2(int i, int n) { return i & (n - 1); }
+__device__ __forceinline__ int wrap_small(int i, int n) {
+  i += (i < 0) ? n : 0;
+  i -= (i >= n) ? n : 0;
+  return i;
+}
+
+// Error bits of the device error word.
+enum : unsigned { ERR_RANGE = 1u, ERR_NUMERIC = 2u };
+
+// ---------------------------------------------------------------- launches
+// Host-side launch wrappers (kernels.hip), one instantiation per precision.
+template <class R>
+struct Launch {
+  static void push_deposit(const Run<R> *runs, const Item *items, int nitems, int parity,
+                           unsigned *err, hipStream_t s);
+  static void fft_j(const Run<R> *runs, const Item *items, int nitems, int parity, int maxM,
+                    hipStream_t s);
+  static void kupdate(const Run<R> *runs, const Item *items, int nitems, int parity,
+                      hipStream_t s);
+  static void ifft_eb(const Run<R> *runs, const Item *items, int nitems, int parity, int maxM,
+                      hipStream_t s);
+  static void fields_to_k(const Run<R> *runs, const Item *items, int nitems, int parity,
+                          int maxM, hipStream_t s);
+};
+
+// Diagnostics and helpers (FP64 unless noted).
+void launch_rho_fixed(const Run<float> *run_dev, int np, int n1, int n2, long long *rho,
+                      hipStream_t s);
+void launch_rho_fp64(const Run<double> *run_dev, int np, int n1, int n2, double *rho,
+                     hipStream_t s);
+template <class R>
+void launch_energy(const R *F, long long cells, double *partial, int nblocks, hipStream_t s);
+template <class R>
+void launch_kinetic(const Run<R> *run_dev, int np, double *partial, int nblocks, hipStream_t s);
+// Gauss residual per row: rho (physical, FP64, [n2][n1]) and the k-space E1,E2
+// of a run; writes per-row [3]: sum |R|^2, max |R|, sum |f rho|^2.
+template <class R>
+void launch_gauss(const Run<R> *run_dev, int n2, int n1, int parity, const double *rho,
+                  const double2 *tw64, const double *sym64, const double *filt, double idx2,
+                  double *rows_out, hipStream_t s);
+void launch_cont_fixed(const long long *rho_new, const long long *rho_old, const long long *J,
+                       int n1, int n2, long long *partial_max, int nblocks, hipStream_t s);
+void launch_cont_fp64(const double *rho_new, const double *rho_old, const double *J, int n1,
+                      int n2, double dt, double idx1, double idx2, double *partial_max,
+                      int nblocks, hipStream_t s);
+void launch_debug_deposit(int n1, int n2, int P, float inv_wunit, float c3, int np,
+                          const int *cell0, const float *off0, const int *cell1,
+                          const float *off1, const float *v3, const float *qw, long long *J,
+                          unsigned *err, hipStream_t s);
+template <class R>
+void launch_inverse_rows(const typename Cplx<R>::T *Xk, int nk, int n1, int nrows,
+                         const typename Cplx<R>::T *tw, R scale, R *out, hipStream_t s);
+
+}  // namespace hp

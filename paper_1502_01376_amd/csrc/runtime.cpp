@@ -1,0 +1,1136 @@
+// runtime.cpp -- host runtime of the MI355X hybrid Yee-FFT PIC library: the C
+// ABI of include/hpic.h.  Validation (Eq. (22) Courant limit, FFT sizes,
+// fixed-point headroom), device allocation, FP64-computed symbol tables,
+// batched work lists, step sequencing on the caller's stream, diagnostics and
+// checkpointing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "hpic.h"
+#include "hpic_internal.h"
+
+using namespace hp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) return fail(HP_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+const double PI = 3.14159265358979323846;
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+// Stability limit of the time step: Eq. (22) for the hybrid solver, the Yee
+// limit when the finite-difference x1 symbol is used.
+double courant_limit(const hp_config &c) {
+  const double a = c.dx[0], b = c.dx[1];
+  if (c.deriv1) return 1.0 / std::sqrt(1.0 / (a * a) + 1.0 / (b * b));
+  return 2.0 / std::sqrt(PI * PI / (a * a) + 4.0 / (b * b));
+}
+
+const int PUSH_CHUNK = 1024;  // particles per push workgroup
+const int UPD_BLOCK = 256;    // (i2, kappa) elements per update workgroup
+
+struct Event2 {
+  int kind;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct SimBase {
+  virtual ~SimBase() {}
+  virtual int set_stream(hipStream_t s) = 0;
+  virtual int set_particles(int run, int64_t n, const double *x, const double *u,
+                            const double *w, double qm, double q) = 0;
+  virtual int set_fields(int run, const double *E, const double *B) = 0;
+  virtual int set_background(int run, int rho_from_particles, const double *jbg) = 0;
+  virtual int step(int nsteps) = 0;
+  virtual int sync() = 0;
+  virtual int get_field(int run, int comp, double *out, size_t count) = 0;
+  virtual int get_current(int run, int comp, int corrected, double *out, size_t count) = 0;
+  virtual int get_current_fixed(int run, int comp, int64_t *out, size_t count) = 0;
+  virtual int get_count(int run, int64_t *n) = 0;
+  virtual int nruns() const = 0;
+  virtual int get_particles(int run, int64_t n, double *x, double *u, double *w, int64_t *id) = 0;
+  virtual int get_particles_raw(int run, int64_t n, int32_t *cell, float *off, float *u,
+                                float *qw, int32_t *id) = 0;
+  virtual int diagnostics(int run, hp_diag *out) = 0;
+  virtual int get_state(void *blob, size_t *size) = 0;
+  virtual int set_state(const void *blob, size_t size) = 0;
+  virtual int debug_deposit(int run, int64_t n, const int32_t *c0, const float *o0,
+                            const int32_t *c1, const float *o1, const float *v3, const float *qw,
+                            int64_t *J) = 0;
+  virtual int fixed_params(int run, double *out) = 0;
+  virtual int profile(int enable) = 0;
+  virtual int kernel_times(double *ms, int64_t *n) = 0;
+};
+
+struct hp_sim {
+  SimBase *impl;
+};
+
+namespace {
+
+template <class R>
+class Sim : public SimBase {
+  using C = typename Cplx<R>::T;
+  using Acc = typename AccOf<R>::T;
+  static constexpr bool FIXED = std::is_same<R, float>::value;
+
+  struct RunHost {
+    hp_config cfg;
+    Run<R> d;              // descriptor uploaded to d_runs
+    int64_t np = 0;
+    double qm = -1.0, q = -1.0;
+    int Qbits = 0;
+    double jbg[3] = {0, 0, 0};
+    // FP64 tables for diagnostics
+    double2 *tw64 = nullptr;
+    double *sym64 = nullptr, *filt64 = nullptr;
+    // diagnostics state
+    Acc *rho0 = nullptr;   // rho_e at hp_set_background (nullptr: none)
+    Acc *rho_prev = nullptr;
+    int64_t rho_prev_step = -2;
+    int row0 = 0, grp0 = 0;  // first items of the run in the row/group lists
+    // per-run particle count cells for headroom
+  };
+
+ public:
+  ~Sim() override {
+    for (auto &e : events_) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    for (void *p : allocs_) (void)hipFree(p);
+  }
+
+  int init(const hp_config *cfgs, int nruns) {
+    HIPCHK(hipGetDevice(&device_));
+    HIPCHK(hipMalloc(&d_err_, sizeof(unsigned)));
+    allocs_.push_back(d_err_);
+    HIPCHK(hipMemset(d_err_, 0, sizeof(unsigned)));
+    runs_.resize(nruns);
+    std::vector<Item> rows, grps, upd;
+    for (int i = 0; i < nruns; ++i) {
+      RunHost &h = runs_[i];
+      h.cfg = cfgs[i];
+      const hp_config &c = cfgs[i];
+      Run<R> &d = h.d;
+      std::memset(&d, 0, sizeof d);
+      d.n1 = c.n[0];
+      d.n2 = c.n[1];
+      d.log2n1 = ilog2(d.n1);
+      d.nk = d.n1 / 2 + 1;
+      d.dt = (R)c.dt;
+      d.hdt = (R)(0.5 * c.dt);
+      d.idx2 = (R)(1.0 / c.dx[1]);
+      d.dtdx1 = (R)(c.dt / c.dx[0]);
+      d.dtdx2 = (R)(c.dt / c.dx[1]);
+      d.jfx1 = (R)(-c.dx[0] / c.dt);
+      d.jfx2 = (R)(-c.dx[1] / c.dt);
+      d.inv_m = (R)(2.0 / d.n1);
+      d.P = c.fixed_shape_bits > 0 ? c.fixed_shape_bits : 20;
+      d.inv_wunit = 1.0f;
+      d.c3 = (float)(std::ldexp(1.0, 30 - 2 * d.P) / 6.0);
+      maxM_ = std::max(maxM_, d.n1 / 2);
+      const size_t cells = (size_t)d.n1 * d.n2, kpl = (size_t)d.n2 * d.nk;
+      int rc;
+      if ((rc = alloc(&d.F, 6 * cells))) return rc;
+      if ((rc = alloc(&d.Fk[0], 6 * kpl))) return rc;
+      if ((rc = alloc(&d.Fk[1], 6 * kpl))) return rc;
+      if ((rc = alloc(&d.J[0], 3 * cells))) return rc;
+      if ((rc = alloc(&d.J[1], 3 * cells))) return rc;
+      if ((rc = alloc(&d.Jk, 3 * kpl))) return rc;
+      // x1 tables, computed in FP64 and rounded once
+      std::vector<C> tw(d.n1);
+      std::vector<double2> tw64(d.n1);
+      for (int m = 0; m < d.n1; ++m) {
+        const double a = -2.0 * PI * m / d.n1;
+        tw[m].x = (R)std::cos(a);
+        tw[m].y = (R)std::sin(a);
+        tw64[m] = make_double2(std::cos(a), std::sin(a));
+      }
+      std::vector<R> sym(4 * d.nk);
+      std::vector<double> sym64(4 * d.nk), filt64(d.nk);
+      for (int k = 0; k < d.nk; ++k) {
+        const double k1 = 2.0 * PI * k / (d.n1 * c.dx[0]);
+        const double hh = 0.5 * k1 * c.dx[0];
+        const double kk = c.deriv1 ? std::sin(hh) / (0.5 * c.dx[0]) : k1;
+        const double v[4] = {-kk * std::sin(hh), kk * std::cos(hh), kk * std::sin(hh),
+                             kk * std::cos(hh)};  // i kk exp(+ih), i kk exp(-ih)
+        for (int j = 0; j < 4; ++j) {
+          sym[4 * k + j] = (R)v[j];
+          sym64[4 * k + j] = v[j];
+        }
+        filt64[k] = (k <= c.filter_frac * 0.5 * d.n1) ? 1.0 : 0.0;
+      }
+      C *dtw;
+      R *dsym, *djfac;
+      if ((rc = alloc(&dtw, d.n1)) || (rc = alloc(&dsym, 4 * d.nk)) ||
+          (rc = alloc(&djfac, 3 * d.nk)) || (rc = alloc(&h.tw64, d.n1)) ||
+          (rc = alloc(&h.sym64, 4 * d.nk)) || (rc = alloc(&h.filt64, d.nk)))
+        return rc;
+      HIPCHK(hipMemcpy(dtw, tw.data(), sizeof(C) * d.n1, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(dsym, sym.data(), sizeof(R) * 4 * d.nk, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(h.tw64, tw64.data(), sizeof(double2) * d.n1, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(h.sym64, sym64.data(), sizeof(double) * 4 * d.nk, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(h.filt64, filt64.data(), sizeof(double) * d.nk, hipMemcpyHostToDevice));
+      d.tw = dtw;
+      d.sym = dsym;
+      d.jfac = djfac;
+      if ((rc = upload_jfac(i))) return rc;
+      h.row0 = (int)rows.size();
+      for (int r = 0; r < d.n2; ++r) rows.push_back(Item{i, r, 0});
+      h.grp0 = (int)grps.size();
+      for (int r = 0; r < d.n2; ++r) {
+        grps.push_back(Item{i, r, 0});
+        grps.push_back(Item{i, r, 1});
+      }
+      const int nel = d.n2 * d.nk;
+      for (int e = 0; e < nel; e += UPD_BLOCK) upd.push_back(Item{i, e, 0});
+    }
+    int rc;
+    if ((rc = alloc(&d_runs_, nruns))) return rc;
+    if ((rc = upload_items(rows, &d_rows_, &n_rows_))) return rc;
+    if ((rc = upload_items(grps, &d_grps_, &n_grps_))) return rc;
+    if ((rc = upload_items(upd, &d_upd_, &n_upd_))) return rc;
+    return upload_runs();
+  }
+
+  int set_stream(hipStream_t s) override {
+    stream_ = s;
+    return HP_OK;
+  }
+
+  int set_particles(int run, int64_t n, const double *x, const double *u, const double *w,
+                    double qm, double q) override {
+    RunHost &h = runs_[run];
+    Run<R> &d = h.d;
+    if (n < 0 || n > (int64_t)0x7fffffff - PUSH_CHUNK) return fail(HP_EINVAL, "particle count %lld out of range", (long long)n);
+    if (n > 0 && (!x || !u || !w)) return fail(HP_EINVAL, "null particle array");
+    if (!std::isfinite(qm) || !std::isfinite(q) || qm == 0.0) return fail(HP_EINVAL, "bad q/m or q");
+    const double L1 = h.cfg.dx[0] * d.n1, L2 = h.cfg.dx[1] * d.n2;
+    std::vector<int> cell(n), id(n);
+    std::vector<R> f1(n), f2(n), u1(n), u2(n), u3(n), qw(n);
+    std::vector<int> count((size_t)d.n1 * d.n2, 0);
+    double qmax = 0.0, qmin = INFINITY;
+    for (int64_t p = 0; p < n; ++p) {
+      const double x1 = x[p], x2 = x[n + p];
+      if (!std::isfinite(x1) || !std::isfinite(x2) || !std::isfinite(u[p]) ||
+          !std::isfinite(u[n + p]) || !std::isfinite(u[2 * n + p]) || !std::isfinite(w[p]))
+        return fail(HP_EINVAL, "non-finite particle input at %lld", (long long)p);
+      int c1, c2;
+      R g1, g2;
+      split(x1, L1, h.cfg.dx[0], d.n1, c1, g1);
+      split(x2, L2, h.cfg.dx[1], d.n2, c2, g2);
+      cell[p] = (c2 << d.log2n1) | c1;
+      f1[p] = g1;
+      f2[p] = g2;
+      u1[p] = (R)u[p];
+      u2[p] = (R)u[n + p];
+      u3[p] = (R)u[2 * n + p];
+      const double qwd = q * w[p];
+      qw[p] = (R)qwd;
+      qmax = std::max(qmax, std::fabs((double)qw[p]));
+      qmin = std::min(qmin, std::fabs((double)qw[p]));
+      id[p] = (int)p;
+      count[(size_t)c2 * d.n1 + c1]++;
+    }
+    if (FIXED && n > 0) {
+      if (!(qmax > 0.0)) return fail(HP_EINVAL, "all particle charges are zero");
+      const int cmax = *std::max_element(count.begin(), count.end());
+      const int P = d.P;
+      // per node |J| <= 24 * (particles per cell) * 2^(2P+Q): keep below 2^62
+      const double room = std::ldexp(1.0, 62 - 2 * P) / (24.0 * std::max(cmax, 1));
+      int Q;
+      if (h.cfg.fixed_weight_bits > 0) {
+        Q = h.cfg.fixed_weight_bits;
+      } else {
+        Q = (qmin == qmax) ? 0 : std::min(15, (int)std::floor(std::log2(room)));
+      }
+      if (Q < 0 || std::ldexp(1.0, Q) > room)
+        return fail(HP_ERANGE,
+                    "fixed-point headroom: %d particles in one cell with %d charge bits and "
+                    "%d shape bits would overflow the 64-bit accumulators",
+                    cmax, Q, P);
+      h.Qbits = Q;
+      d.inv_wunit = (float)(std::ldexp(1.0, Q) / qmax);
+      d.c3 = (float)(std::ldexp(1.0, 30 - Q - 2 * P) / 6.0);
+    }
+    h.qm = qm;
+    h.q = q;
+    d.qmhdt = (R)(0.5 * qm * h.cfg.dt);
+    d.np = (int)n;
+    h.np = n;
+    void *old[8] = {d.cell, d.id, d.f1, d.f2, d.u1, d.u2, d.u3, d.qw};
+    for (void *o : old)
+      if (o) release(o);
+    int rc;
+    if ((rc = alloc(&d.cell, n)) || (rc = alloc(&d.id, n)) || (rc = alloc(&d.f1, n)) ||
+        (rc = alloc(&d.f2, n)) || (rc = alloc(&d.u1, n)) || (rc = alloc(&d.u2, n)) ||
+        (rc = alloc(&d.u3, n)) || (rc = alloc(&d.qw, n)))
+      return rc;
+    if ((rc = h2d(d.cell, cell.data(), n)) || (rc = h2d(d.id, id.data(), n)) ||
+        (rc = h2d(d.f1, f1.data(), n)) || (rc = h2d(d.f2, f2.data(), n)) ||
+        (rc = h2d(d.u1, u1.data(), n)) || (rc = h2d(d.u2, u2.data(), n)) ||
+        (rc = h2d(d.u3, u3.data(), n)) || (rc = h2d(d.qw, qw.data(), n)))
+      return rc;
+    if ((rc = upload_jfac(run))) return rc;
+    if ((rc = rebuild_push_items())) return rc;
+    return upload_runs();
+  }
+
+  int set_fields(int run, const double *E, const double *B) override {
+    RunHost &h = runs_[run];
+    Run<R> &d = h.d;
+    const size_t cells = (size_t)d.n1 * d.n2;
+    std::vector<R> F(6 * cells);
+    for (size_t i = 0; i < 3 * cells; ++i) {
+      if (!std::isfinite(E[i]) || !std::isfinite(B[i])) return fail(HP_EINVAL, "non-finite field");
+      F[i] = (R)E[i];
+      F[3 * cells + i] = (R)B[i];
+    }
+    int rc;
+    if ((rc = h2d(d.F, F.data(), 6 * cells))) return rc;
+    Launch<R>::fields_to_k(d_runs_, d_grps_ + h.grp0, 2 * d.n2, parity_, maxM_, stream_);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream_));
+    return HP_OK;
+  }
+
+  int set_background(int run, int rho_from_particles, const double *jbg) override {
+    RunHost &h = runs_[run];
+    Run<R> &d = h.d;
+    for (int c = 0; c < 3; ++c) {
+      h.jbg[c] = jbg ? jbg[c] : 0.0;
+      d.jbg0[c] = (R)(d.n1 * h.jbg[c]);
+    }
+    if (rho_from_particles) {
+      int rc;
+      if (!h.rho0 && (rc = alloc(&h.rho0, (size_t)d.n1 * d.n2))) return rc;
+      if ((rc = deposit_rho(run, h.rho0))) return rc;
+    }
+    return upload_runs();
+  }
+
+  int step(int nsteps) override {
+    if (nsteps < 0) return fail(HP_EINVAL, "negative step count");
+    for (int s = 0; s < nsteps; ++s) {
+      const int p = parity_;
+      mark(HP_K_PUSH_DEPOSIT, true);
+      Launch<R>::push_deposit(d_runs_, d_push_, n_push_, p, d_err_, stream_);
+      mark(HP_K_PUSH_DEPOSIT, false);
+      mark(HP_K_FFT_J, true);
+      Launch<R>::fft_j(d_runs_, d_rows_, n_rows_, p, maxM_, stream_);
+      mark(HP_K_FFT_J, false);
+      mark(HP_K_KUPDATE, true);
+      Launch<R>::kupdate(d_runs_, d_upd_, n_upd_, p, stream_);
+      mark(HP_K_KUPDATE, false);
+      mark(HP_K_IFFT_EB, true);
+      Launch<R>::ifft_eb(d_runs_, d_grps_, n_grps_, p ^ 1, maxM_, stream_);
+      mark(HP_K_IFFT_EB, false);
+      parity_ ^= 1;
+      ++step_;
+    }
+    HIPCHK(hipGetLastError());
+    return HP_OK;
+  }
+
+  int sync() override {
+    HIPCHK(hipStreamSynchronize(stream_));
+    unsigned e = 0;
+    HIPCHK(hipMemcpy(&e, d_err_, sizeof e, hipMemcpyDeviceToHost));
+    if (e) {
+      HIPCHK(hipMemset(d_err_, 0, sizeof(unsigned)));
+      if (e & ERR_NUMERIC) return fail(HP_ENUMERIC, "non-finite particle momentum or position");
+      return fail(HP_ERANGE, "a particle moved a cell or more in one step");
+    }
+    return HP_OK;
+  }
+
+  int get_field(int run, int comp, double *out, size_t count) override {
+    const Run<R> &d = runs_[run].d;
+    const size_t cells = (size_t)d.n1 * d.n2;
+    if (comp < 0 || comp > 5 || count != cells || !out) return fail(HP_EINVAL, "bad field request");
+    int rc;
+    if ((rc = sync())) return rc;
+    std::vector<R> tmp(cells);
+    if ((rc = d2h(tmp.data(), d.F + comp * cells, cells))) return rc;
+    for (size_t i = 0; i < cells; ++i) out[i] = (double)tmp[i];
+    return HP_OK;
+  }
+
+  int get_current(int run, int comp, int corrected, double *out, size_t count) override {
+    const RunHost &h = runs_[run];
+    const Run<R> &d = h.d;
+    const size_t cells = (size_t)d.n1 * d.n2;
+    if (comp < 0 || comp > 2 || count != cells || !out) return fail(HP_EINVAL, "bad current request");
+    int rc;
+    if ((rc = sync())) return rc;
+    if (corrected) {
+      R *tmp;
+      if ((rc = alloc(&tmp, cells))) return rc;
+      launch_inverse_rows<R>(d.Jk + (size_t)comp * d.n2 * d.nk, d.nk, d.n1, d.n2, d.tw, d.inv_m,
+                             tmp, stream_);
+      std::vector<R> host(cells);
+      rc = d2h(host.data(), tmp, cells);
+      release(tmp);
+      if (rc) return rc;
+      for (size_t i = 0; i < cells; ++i) out[i] = (double)host[i];
+      return HP_OK;
+    }
+    std::vector<Acc> raw(cells);
+    if ((rc = d2h(raw.data(), d.J[parity_ ^ 1] + comp * cells, cells))) return rc;
+    const double f = acc_factor(h, comp);
+    for (size_t i = 0; i < cells; ++i) out[i] = (double)raw[i] * f + h.jbg[comp];
+    return HP_OK;
+  }
+
+  int get_current_fixed(int run, int comp, int64_t *out, size_t count) override {
+    if (!FIXED) return fail(HP_EINVAL, "fixed-point current exists only in the FP32 form");
+    const Run<R> &d = runs_[run].d;
+    const size_t cells = (size_t)d.n1 * d.n2;
+    if (comp < 0 || comp > 2 || count != cells || !out) return fail(HP_EINVAL, "bad current request");
+    int rc;
+    if ((rc = sync())) return rc;
+    return d2h((Acc *)out, d.J[parity_ ^ 1] + comp * cells, cells);
+  }
+
+  int get_count(int run, int64_t *n) override {
+    *n = runs_[run].np;
+    return HP_OK;
+  }
+  int nruns() const override { return (int)runs_.size(); }
+
+  int get_particles(int run, int64_t n, double *x, double *u, double *w, int64_t *id) override {
+    const RunHost &h = runs_[run];
+    const Run<R> &d = h.d;
+    if (n != h.np) return fail(HP_EINVAL, "particle count mismatch");
+    int rc;
+    if ((rc = sync())) return rc;
+    std::vector<int> cell(n), pid(n);
+    std::vector<R> f1(n), f2(n), a(n), b(n), c(n), qw(n);
+    if ((rc = d2h(cell.data(), d.cell, n)) || (rc = d2h(pid.data(), d.id, n)) ||
+        (rc = d2h(f1.data(), d.f1, n)) || (rc = d2h(f2.data(), d.f2, n)) ||
+        (rc = d2h(a.data(), d.u1, n)) || (rc = d2h(b.data(), d.u2, n)) ||
+        (rc = d2h(c.data(), d.u3, n)) || (rc = d2h(qw.data(), d.qw, n)))
+      return rc;
+    for (int64_t p = 0; p < n; ++p) {
+      const int i1 = cell[p] & (d.n1 - 1), i2 = cell[p] >> d.log2n1;
+      if (x) {
+        x[p] = ((double)i1 + (double)f1[p]) * h.cfg.dx[0];
+        x[n + p] = ((double)i2 + (double)f2[p]) * h.cfg.dx[1];
+      }
+      if (u) {
+        u[p] = a[p];
+        u[n + p] = b[p];
+        u[2 * n + p] = c[p];
+      }
+      if (w) w[p] = (double)qw[p] / h.q;
+      if (id) id[p] = pid[p];
+    }
+    return HP_OK;
+  }
+
+  int get_particles_raw(int run, int64_t n, int32_t *cellout, float *off, float *u, float *qwo,
+                        int32_t *id) override {
+    if (!FIXED) return fail(HP_EINVAL, "raw particle state exists only in the FP32 form");
+    const RunHost &h = runs_[run];
+    const Run<R> &d = h.d;
+    if (n != h.np) return fail(HP_EINVAL, "particle count mismatch");
+    int rc;
+    if ((rc = sync())) return rc;
+    std::vector<int> cell(n);
+    if ((rc = d2h(cell.data(), d.cell, n))) return rc;
+    if (cellout)
+      for (int64_t p = 0; p < n; ++p) {
+        cellout[p] = cell[p] & (d.n1 - 1);
+        cellout[n + p] = cell[p] >> d.log2n1;
+      }
+    if (off && ((rc = d2h((R *)off, d.f1, n)) || (rc = d2h((R *)off + n, d.f2, n)))) return rc;
+    if (u && ((rc = d2h((R *)u, d.u1, n)) || (rc = d2h((R *)u + n, d.u2, n)) ||
+              (rc = d2h((R *)u + 2 * n, d.u3, n))))
+      return rc;
+    if (qwo && (rc = d2h((R *)qwo, d.qw, n))) return rc;
+    if (id && (rc = d2h(id, d.id, n))) return rc;
+    return HP_OK;
+  }
+
+  int diagnostics(int run, hp_diag *out) override {
+    RunHost &h = runs_[run];
+    Run<R> &d = h.d;
+    const size_t cells = (size_t)d.n1 * d.n2;
+    const double dV = h.cfg.dx[0] * h.cfg.dx[1];
+    int rc;
+    if ((rc = sync())) return rc;
+    std::memset(out, 0, sizeof *out);
+    out->step = step_;
+    // field energies
+    const int nb = 256;
+    double *part;
+    if ((rc = alloc(&part, 6 * nb))) return rc;
+    launch_energy<R>(d.F, (long long)cells, part, nb, stream_);
+    std::vector<double> hp(6 * nb);
+    rc = d2h(hp.data(), part, 6 * nb);
+    if (rc) { release(part); return rc; }
+    for (int b = 0; b < nb; ++b)
+      for (int c = 0; c < 3; ++c) {
+        out->W_E[c] += 0.5 * dV * hp[6 * b + c];
+        out->W_B[c] += 0.5 * dV * hp[6 * b + 3 + c];
+      }
+    if (h.np > 0) {
+      launch_kinetic<R>(d_runs_ + run, (int)h.np, part, nb, stream_);
+      rc = d2h(hp.data(), part, nb);
+      if (rc) { release(part); return rc; }
+      double s = 0;
+      for (int b = 0; b < nb; ++b) s += hp[b];
+      out->kinetic = s * dV / h.qm;
+    }
+    release(part);
+    // charge density now, and Gauss residual
+    Acc *rho;
+    if ((rc = alloc(&rho, cells))) return rc;
+    if ((rc = deposit_rho(run, rho))) { release(rho); return rc; }
+    std::vector<Acc> rn(cells), r0;
+    if ((rc = d2h(rn.data(), rho, cells))) { release(rho); return rc; }
+    if (h.rho0) {
+      r0.resize(cells);
+      if ((rc = d2h(r0.data(), h.rho0, cells))) { release(rho); return rc; }
+    }
+    const double rf = rho_factor(h);
+    std::vector<double> tot(cells);
+    double qsum = 0;
+    for (size_t i = 0; i < cells; ++i) {
+      const Acc v = h.rho0 ? (Acc)(rn[i] - r0[i]) : rn[i];
+      tot[i] = (double)v * rf;
+      qsum += (double)rn[i] * rf;
+    }
+    out->charge_total = qsum * dV;
+    double *dtot, *rows;
+    if ((rc = alloc(&dtot, cells)) || (rc = alloc(&rows, 3 * (size_t)d.n2))) { release(rho); return rc; }
+    if ((rc = h2d(dtot, tot.data(), cells))) { release(rho); release(dtot); release(rows); return rc; }
+    launch_gauss<R>(d_runs_ + run, d.n2, d.n1, parity_, dtot, h.tw64, h.sym64, h.filt64,
+                    1.0 / h.cfg.dx[1], rows, stream_);
+    std::vector<double> hr(3 * d.n2);
+    rc = d2h(hr.data(), rows, 3 * d.n2);
+    release(dtot);
+    release(rows);
+    if (rc) { release(rho); return rc; }
+    double s2 = 0, smax = 0, sref = 0;
+    for (int r = 0; r < d.n2; ++r) {
+      s2 += hr[3 * r];
+      smax = std::max(smax, hr[3 * r + 1]);
+      sref += hr[3 * r + 2];
+    }
+    out->gauss_l2 = std::sqrt(s2);
+    out->gauss_linf = smax;
+    out->gauss_ref_l2 = std::sqrt(sref);
+    // continuity residual of the last step
+    out->cont_linf = -1.0;
+    out->cont_int = -1;
+    if (h.rho_prev && h.rho_prev_step == step_ - 1 && step_ > 0) {
+      const int nbc = 256;
+      if (FIXED) {
+        long long *pm;
+        if ((rc = alloc(&pm, nbc))) { release(rho); return rc; }
+        launch_cont_fixed((const long long *)rho, (const long long *)h.rho_prev,
+                          (const long long *)d.J[parity_ ^ 1], d.n1, d.n2, pm, nbc, stream_);
+        std::vector<long long> hm(nbc);
+        rc = d2h(hm.data(), pm, nbc);
+        release(pm);
+        if (rc) { release(rho); return rc; }
+        out->cont_int = *std::max_element(hm.begin(), hm.end());
+        // in physical units: integers of rho times rho_factor / dt
+        out->cont_linf = 0.5 * (double)out->cont_int * rf / h.cfg.dt;
+      } else {
+        double *pm;
+        if ((rc = alloc(&pm, nbc))) { release(rho); return rc; }
+        launch_cont_fp64((const double *)rho, (const double *)h.rho_prev,
+                         (const double *)d.J[parity_ ^ 1], d.n1, d.n2, h.cfg.dt,
+                         1.0 / h.cfg.dx[0], 1.0 / h.cfg.dx[1], pm, nbc, stream_);
+        std::vector<double> hm(nbc);
+        rc = d2h(hm.data(), pm, nbc);
+        release(pm);
+        if (rc) { release(rho); return rc; }
+        out->cont_linf = *std::max_element(hm.begin(), hm.end());
+      }
+    }
+    if (h.rho_prev) release(h.rho_prev);
+    h.rho_prev = rho;
+    h.rho_prev_step = step_;
+    return HP_OK;
+  }
+
+  // ---- checkpoint: header + per run raw arrays (bit-exact resume)
+  int get_state(void *blob, size_t *size) override {
+    int rc;
+    if ((rc = sync())) return rc;
+    size_t need = state_size();
+    if (!blob) {
+      *size = need;
+      return HP_OK;
+    }
+    if (*size < need) return fail(HP_EINVAL, "state buffer too small (%zu < %zu)", *size, need);
+    char *o = (char *)blob;
+    auto put = [&](const void *src, size_t bytes) {
+      std::memcpy(o, src, bytes);
+      o += bytes;
+    };
+    const int64_t hdr[6] = {0x48504943, 1, (int64_t)runs_.size(), FIXED ? 0 : 1, step_, parity_};
+    put(hdr, sizeof hdr);
+    for (RunHost &h : runs_) {
+      Run<R> &d = h.d;
+      const size_t cells = (size_t)d.n1 * d.n2, kpl = (size_t)d.n2 * d.nk;
+      const double meta[12] = {(double)h.np, h.qm, h.q, (double)h.Qbits, (double)d.inv_wunit,
+                               (double)d.c3, h.jbg[0], h.jbg[1], h.jbg[2], h.rho0 ? 1.0 : 0.0,
+                               0, 0};
+      put(meta, sizeof meta);
+      const int64_t n = h.np;
+      if ((rc = d2h((int *)o, d.cell, n))) return rc; o += sizeof(int) * n;
+      if ((rc = d2h((int *)o, d.id, n))) return rc; o += sizeof(int) * n;
+      R *arrs[6] = {d.f1, d.f2, d.u1, d.u2, d.u3, d.qw};
+      for (R *a : arrs) { if ((rc = d2h((R *)o, a, n))) return rc; o += sizeof(R) * n; }
+      if ((rc = d2h((R *)o, d.F, 6 * cells))) return rc; o += sizeof(R) * 6 * cells;
+      if ((rc = d2h((C *)o, d.Fk[parity_], 6 * kpl))) return rc; o += sizeof(C) * 6 * kpl;
+      if ((rc = d2h((Acc *)o, d.J[parity_ ^ 1], 3 * cells))) return rc; o += sizeof(Acc) * 3 * cells;
+      if ((rc = d2h((C *)o, d.Jk, 3 * kpl))) return rc; o += sizeof(C) * 3 * kpl;
+      if (h.rho0) { if ((rc = d2h((Acc *)o, h.rho0, cells))) return rc; o += sizeof(Acc) * cells; }
+    }
+    *size = need;
+    return HP_OK;
+  }
+
+  int set_state(const void *blob, size_t size) override {
+    const char *o = (const char *)blob;
+    const char *end = o + size;
+    auto take = [&](void *dst, size_t bytes) {
+      if (o + bytes > end) return false;
+      std::memcpy(dst, o, bytes);
+      o += bytes;
+      return true;
+    };
+    int64_t hdr[6];
+    if (!take(hdr, sizeof hdr) || hdr[0] != 0x48504943 || hdr[1] != 1 ||
+        hdr[2] != (int64_t)runs_.size() || hdr[3] != (FIXED ? 0 : 1))
+      return fail(HP_EINVAL, "state blob does not match this handle");
+    int rc;
+    if ((rc = sync())) return rc;
+    step_ = hdr[4];
+    parity_ = (int)hdr[5];
+    for (int i = 0; i < (int)runs_.size(); ++i) {
+      RunHost &h = runs_[i];
+      Run<R> &d = h.d;
+      const size_t cells = (size_t)d.n1 * d.n2, kpl = (size_t)d.n2 * d.nk;
+      double meta[12];
+      if (!take(meta, sizeof meta)) return fail(HP_EINVAL, "truncated state");
+      const int64_t n = (int64_t)meta[0];
+      const size_t pbytes = n * (2 * sizeof(int) + 6 * sizeof(R));
+      const size_t fbytes = sizeof(R) * 6 * cells + sizeof(C) * 9 * kpl + sizeof(Acc) * 3 * cells +
+                            (meta[9] != 0 ? sizeof(Acc) * cells : 0);
+      if (o + pbytes + fbytes > end) return fail(HP_EINVAL, "truncated state");
+      h.qm = meta[1];
+      h.q = meta[2];
+      h.Qbits = (int)meta[3];
+      d.inv_wunit = (float)meta[4];
+      d.c3 = (float)meta[5];
+      for (int c = 0; c < 3; ++c) {
+        h.jbg[c] = meta[6 + c];
+        d.jbg0[c] = (R)(d.n1 * h.jbg[c]);
+      }
+      d.qmhdt = (R)(0.5 * h.qm * h.cfg.dt);
+      h.np = n;
+      d.np = (int)n;
+      if ((rc = alloc(&d.cell, n)) || (rc = alloc(&d.id, n)) || (rc = alloc(&d.f1, n)) ||
+          (rc = alloc(&d.f2, n)) || (rc = alloc(&d.u1, n)) || (rc = alloc(&d.u2, n)) ||
+          (rc = alloc(&d.u3, n)) || (rc = alloc(&d.qw, n)))
+        return rc;
+      if ((rc = h2d(d.cell, (const int *)o, n))) return rc; o += sizeof(int) * n;
+      if ((rc = h2d(d.id, (const int *)o, n))) return rc; o += sizeof(int) * n;
+      R *arrs[6] = {d.f1, d.f2, d.u1, d.u2, d.u3, d.qw};
+      for (R *a : arrs) { if ((rc = h2d(a, (const R *)o, n))) return rc; o += sizeof(R) * n; }
+      if ((rc = h2d(d.F, (const R *)o, 6 * cells))) return rc; o += sizeof(R) * 6 * cells;
+      if ((rc = h2d(d.Fk[parity_], (const C *)o, 6 * kpl))) return rc; o += sizeof(C) * 6 * kpl;
+      if ((rc = h2d(d.J[parity_ ^ 1], (const Acc *)o, 3 * cells))) return rc; o += sizeof(Acc) * 3 * cells;
+      HIPCHK(hipMemsetAsync(d.J[parity_], 0, sizeof(Acc) * 3 * cells, stream_));
+      if ((rc = h2d(d.Jk, (const C *)o, 3 * kpl))) return rc; o += sizeof(C) * 3 * kpl;
+      if (meta[9] != 0) {
+        if (!h.rho0 && (rc = alloc(&h.rho0, cells))) return rc;
+        if ((rc = h2d(h.rho0, (const Acc *)o, cells))) return rc;
+        o += sizeof(Acc) * cells;
+      }
+      h.rho_prev_step = -2;
+      if ((rc = upload_jfac(i))) return rc;
+    }
+    if ((rc = rebuild_push_items())) return rc;
+    return upload_runs();
+  }
+
+  int debug_deposit(int run, int64_t n, const int32_t *c0, const float *o0, const int32_t *c1,
+                    const float *o1, const float *v3, const float *qw, int64_t *J) override {
+    if (!FIXED) return fail(HP_EINVAL, "the fixed-point deposit exists only in the FP32 form");
+    const Run<R> &d = runs_[run].d;
+    const size_t cells = (size_t)d.n1 * d.n2;
+    if (n < 0 || n > 0x7fffffff) return fail(HP_EINVAL, "bad count");
+    for (int64_t p = 0; p < n; ++p) {
+      if (!(o0[p] >= 0.0f && o0[p] < 1.0f && o0[n + p] >= 0.0f && o0[n + p] < 1.0f &&
+            o1[p] >= 0.0f && o1[p] < 1.0f && o1[n + p] >= 0.0f && o1[n + p] < 1.0f))
+        return fail(HP_EINVAL, "offset out of [0,1) at %lld", (long long)p);
+      if (c0[p] < 0 || c0[p] >= d.n1 || c0[n + p] < 0 || c0[n + p] >= d.n2 || c1[p] < 0 ||
+          c1[p] >= d.n1 || c1[n + p] < 0 || c1[n + p] >= d.n2)
+        return fail(HP_EINVAL, "cell out of range at %lld", (long long)p);
+      if (!std::isfinite(v3[p]) || !std::isfinite(qw[p])) return fail(HP_EINVAL, "non-finite input");
+    }
+    int *dc0, *dc1;
+    float *do0, *do1, *dv3, *dqw;
+    long long *dJ;
+    int rc;
+    const size_t m = n > 0 ? n : 1;
+    if ((rc = alloc(&dc0, 2 * m)) || (rc = alloc(&dc1, 2 * m)) || (rc = alloc(&do0, 2 * m)) ||
+        (rc = alloc(&do1, 2 * m)) || (rc = alloc(&dv3, m)) || (rc = alloc(&dqw, m)) ||
+        (rc = alloc(&dJ, 3 * cells)))
+      return rc;
+    if (n > 0 && ((rc = h2d(dc0, c0, 2 * n)) || (rc = h2d(dc1, c1, 2 * n)) ||
+                  (rc = h2d(do0, o0, 2 * n)) || (rc = h2d(do1, o1, 2 * n)) ||
+                  (rc = h2d(dv3, v3, n)) || (rc = h2d(dqw, qw, n))))
+      return rc;
+    HIPCHK(hipMemsetAsync(dJ, 0, sizeof(long long) * 3 * cells, stream_));
+    launch_debug_deposit(d.n1, d.n2, d.P, d.inv_wunit, d.c3, (int)n, dc0, do0, dc1, do1, dv3, dqw,
+                         dJ, d_err_, stream_);
+    rc = d2h((long long *)J, dJ, 3 * cells);
+    release(dc0); release(dc1); release(do0); release(do1); release(dv3); release(dqw); release(dJ);
+    if (rc) return rc;
+    return sync();
+  }
+
+  int fixed_params(int run, double *out) override {
+    if (!FIXED) return fail(HP_EINVAL, "fixed-point parameters exist only in the FP32 form");
+    const RunHost &h = runs_[run];
+    out[0] = h.d.P;
+    out[1] = h.d.inv_wunit;
+    out[2] = h.d.c3;
+    out[3] = h.Qbits;
+    return HP_OK;
+  }
+
+  int profile(int enable) override {
+    int rc;
+    if ((rc = sync())) return rc;
+    for (auto &e : events_) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    events_.clear();
+    for (int k = 0; k < HP_NK; ++k) {
+      kms_[k] = 0;
+      kn_[k] = 0;
+    }
+    profiling_ = enable != 0;
+    return HP_OK;
+  }
+
+  int kernel_times(double *ms, int64_t *n) override {
+    int rc;
+    if ((rc = sync())) return rc;
+    for (auto &e : events_) {
+      float t = 0;
+      HIPCHK(hipEventElapsedTime(&t, e.a, e.b));
+      kms_[e.kind] += t;
+      kn_[e.kind] += 1;
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    events_.clear();
+    for (int k = 0; k < HP_NK; ++k) {
+      if (ms) ms[k] = kms_[k];
+      if (n) n[k] = kn_[k];
+    }
+    return HP_OK;
+  }
+
+ private:
+  template <class T>
+  int alloc(T **p, size_t count) {
+    void *q = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(HP_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    if (hipMemsetAsync(q, 0, bytes, stream_) != hipSuccess ||
+        hipStreamSynchronize(stream_) != hipSuccess) {
+      (void)hipFree(q);
+      return fail(HP_EDEVICE, "clearing a new allocation failed");
+    }
+    allocs_.push_back(q);
+    *p = (T *)q;
+    return HP_OK;
+  }
+  void release(void *p) {
+    auto it = std::find(allocs_.begin(), allocs_.end(), p);
+    if (it != allocs_.end()) {
+      (void)hipFree(p);
+      allocs_.erase(it);
+    }
+  }
+  template <class T>
+  int h2d(T *dst, const T *src, size_t count) {
+    if (count == 0) return HP_OK;
+    HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, stream_));
+    HIPCHK(hipStreamSynchronize(stream_));
+    return HP_OK;
+  }
+  template <class T>
+  int d2h(T *dst, const T *src, size_t count) {
+    if (count == 0) return HP_OK;
+    HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipStreamSynchronize(stream_));
+    return HP_OK;
+  }
+  int upload_items(const std::vector<Item> &v, Item **d, int *n) {
+    int rc;
+    if ((rc = alloc(d, v.size()))) return rc;
+    *n = (int)v.size();
+    return h2d(*d, v.data(), v.size());
+  }
+  int upload_runs() {
+    std::vector<Run<R>> v(runs_.size());
+    for (size_t i = 0; i < runs_.size(); ++i) v[i] = runs_[i].d;
+    return h2d(d_runs_, v.data(), v.size());
+  }
+  int rebuild_push_items() {
+    std::vector<Item> items;
+    for (int i = 0; i < (int)runs_.size(); ++i)
+      for (int64_t p = 0; p < runs_[i].np; p += PUSH_CHUNK)
+        items.push_back(Item{i, (int)p, (int)std::min<int64_t>(PUSH_CHUNK, runs_[i].np - p)});
+    if (d_push_) release(d_push_);
+    d_push_ = nullptr;
+    n_push_ = 0;
+    if (items.empty()) return HP_OK;
+    return upload_items(items, &d_push_, &n_push_);
+  }
+  // Factor from the deposit accumulator to physical current (before filtering).
+  double acc_factor(const RunHost &h, int comp) const {
+    if (!FIXED) return 1.0;
+    const int P = h.d.P;
+    const double iw = (double)h.d.inv_wunit;
+    if (comp == 0) return -(h.cfg.dx[0] / h.cfg.dt) / (iw * std::ldexp(1.0, 2 * P + 1));
+    if (comp == 1) return -(h.cfg.dx[1] / h.cfg.dt) / (iw * std::ldexp(1.0, 2 * P + 1));
+    return 1.0 / (iw * (double)h.d.c3 * 6.0 * std::ldexp(1.0, 2 * P));
+  }
+  double rho_factor(const RunHost &h) const {
+    if (!FIXED) return 1.0;
+    return 1.0 / ((double)h.d.inv_wunit * std::ldexp(1.0, 2 * h.d.P));
+  }
+  int upload_jfac(int run) {
+    RunHost &h = runs_[run];
+    const Run<R> &d = h.d;
+    std::vector<R> jf(3 * d.nk);
+    for (int k = 0; k < d.nk; ++k) {
+      const double hh = PI * k / d.n1;  // k1 dx1 / 2
+      const bool corr = !h.cfg.deriv1 && h.cfg.correct && k > 0;
+      const double sinc = corr ? std::sin(hh) / hh : 1.0;
+      const double filt = (k <= h.cfg.filter_frac * 0.5 * d.n1) ? 1.0 : 0.0;
+      jf[3 * k + 0] = (R)(acc_factor(h, 0) * sinc * filt);
+      jf[3 * k + 1] = (R)(acc_factor(h, 1) * filt);
+      jf[3 * k + 2] = (R)(acc_factor(h, 2) * filt);
+    }
+    return h2d((R *)d.jfac, jf.data(), 3 * d.nk);
+  }
+  int deposit_rho(int run, Acc *rho) {
+    RunHost &h = runs_[run];
+    const Run<R> &d = h.d;
+    const size_t cells = (size_t)d.n1 * d.n2;
+    HIPCHK(hipMemsetAsync(rho, 0, sizeof(Acc) * cells, stream_));
+    if constexpr (FIXED)
+      launch_rho_fixed(d_runs_ + run, (int)h.np, d.n1, d.n2, rho, stream_);
+    else
+      launch_rho_fp64(d_runs_ + run, (int)h.np, d.n1, d.n2, rho, stream_);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream_));
+    return HP_OK;
+  }
+  size_t state_size() const {
+    size_t s = 6 * sizeof(int64_t);
+    for (const RunHost &h : runs_) {
+      const size_t cells = (size_t)h.d.n1 * h.d.n2, kpl = (size_t)h.d.n2 * h.d.nk;
+      s += 12 * sizeof(double) + h.np * (2 * sizeof(int) + 6 * sizeof(R)) + sizeof(R) * 6 * cells +
+           sizeof(C) * 9 * kpl + sizeof(Acc) * 3 * cells + (h.rho0 ? sizeof(Acc) * cells : 0);
+    }
+    return s;
+  }
+  // Cell index and offset in [0,1) of a physical position, wrapped periodically.
+  static void split(double x, double L, double dx, int n, int &c, R &f) {
+    double xw = std::fmod(x, L);
+    if (xw < 0) xw += L;
+    double xi = xw / dx;
+    double cf = std::floor(xi);
+    c = (int)cf;
+    R g = (R)(xi - cf);
+    if (g >= R(1)) {
+      g = R(0);
+      c += 1;
+    }
+    if (c >= n) c -= n;
+    if (c < 0) c += n;
+    f = g;
+  }
+  void mark(int kind, bool start) {
+    if (!profiling_) return;
+    if (start) {
+      Event2 e;
+      e.kind = kind;
+      (void)hipEventCreate(&e.a);
+      (void)hipEventCreate(&e.b);
+      (void)hipEventRecord(e.a, stream_);
+      events_.push_back(e);
+    } else {
+      (void)hipEventRecord(events_.back().b, stream_);
+    }
+  }
+
+  int device_ = 0;
+  hipStream_t stream_ = nullptr;
+  std::vector<RunHost> runs_;
+  std::vector<void *> allocs_;
+  Run<R> *d_runs_ = nullptr;
+  Item *d_push_ = nullptr, *d_rows_ = nullptr, *d_grps_ = nullptr, *d_upd_ = nullptr;
+  int n_push_ = 0, n_rows_ = 0, n_grps_ = 0, n_upd_ = 0;
+  int maxM_ = 0;
+  int parity_ = 0;
+  int64_t step_ = 0;
+  unsigned *d_err_ = nullptr;
+  bool profiling_ = false;
+  std::vector<Event2> events_;
+  double kms_[HP_NK] = {0};
+  int64_t kn_[HP_NK] = {0};
+};
+
+int check_sim(hp_sim *s) {
+  if (!s || !s->impl) return fail(HP_EINVAL, "null handle");
+  return HP_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+extern "C" {
+
+const char *hp_last_error(void) { return g_err.c_str(); }
+
+int hp_create(const hp_config *cfgs, int32_t nruns, hp_sim **out) {
+  if (!cfgs || !out || nruns < 1 || nruns > 4096) return fail(HP_EINVAL, "bad arguments");
+  *out = nullptr;
+  const int prec = cfgs[0].precision;
+  for (int i = 0; i < nruns; ++i) {
+    const hp_config &c = cfgs[i];
+    if (c.geom != HP_GEOM_2D) return fail(HP_EINVAL, "run %d: only 2D Cartesian geometry is built", i);
+    if (c.precision != prec || (prec != HP_PREC_FP32_FIXED && prec != HP_PREC_FP64))
+      return fail(HP_EINVAL, "run %d: precision must be one of the two forms and equal for all runs", i);
+    if (!is_pow2(c.n[0]) || c.n[0] < 8 || c.n[0] > 4096)
+      return fail(HP_EINVAL, "run %d: n1 = %d must be a power of two in [8, 4096]", i, c.n[0]);
+    if (c.n[1] < 4 || (int64_t)c.n[0] * c.n[1] > (int64_t)1 << 30)
+      return fail(HP_EINVAL, "run %d: n2 = %d out of range", i, c.n[1]);
+    if (!(c.dx[0] > 0) || !(c.dx[1] > 0) || !(c.dt > 0) || !std::isfinite(c.dt))
+      return fail(HP_EINVAL, "run %d: non-positive cell size or time step", i);
+    if (c.shape_order != 2 || c.interp != 0)
+      return fail(HP_EINVAL, "run %d: quadratic shape with momentum-conserving gather only", i);
+    if (!(c.filter_frac > 0)) return fail(HP_EINVAL, "run %d: filter_frac must be > 0", i);
+    if (c.deriv1 != 0 && c.deriv1 != 1) return fail(HP_EINVAL, "run %d: bad deriv1", i);
+    if (c.fixed_shape_bits != 0 && (c.fixed_shape_bits < 8 || c.fixed_shape_bits > 24))
+      return fail(HP_EINVAL, "run %d: fixed_shape_bits in [8, 24]", i);
+    if (c.fixed_weight_bits < 0 || c.fixed_weight_bits > 24)
+      return fail(HP_EINVAL, "run %d: fixed_weight_bits in [0, 24]", i);
+    const double lim = courant_limit(c);
+    if (c.dt > lim * (1 + 1e-12))
+      return fail(HP_ECOURANT, "run %d: dt = %g exceeds the stability limit %g", i, c.dt, lim);
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(HP_EDEVICE, "no HIP device");
+  }
+  hp_sim *s = new hp_sim;
+  int rc;
+  if (prec == HP_PREC_FP32_FIXED) {
+    auto *impl = new Sim<float>();
+    s->impl = impl;
+    rc = impl->init(cfgs, nruns);
+  } else {
+    auto *impl = new Sim<double>();
+    s->impl = impl;
+    rc = impl->init(cfgs, nruns);
+  }
+  if (rc != HP_OK) {
+    std::string msg = g_err;
+    delete s->impl;
+    delete s;
+    g_err = msg;
+    return rc;
+  }
+  *out = s;
+  return HP_OK;
+}
+
+void hp_destroy(hp_sim *sim) {
+  if (!sim) return;
+  delete sim->impl;
+  delete sim;
+}
+
+int hp_set_stream(hp_sim *sim, void *stream) {
+  int rc = check_sim(sim);
+  return rc ? rc : sim->impl->set_stream((hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+// Validates the handle and the run index, then runs f.
+template <class F>
+int with_run(hp_sim *sim, int run, F f) {
+  int rc = check_sim(sim);
+  if (rc) return rc;
+  if (run < 0 || run >= sim->impl->nruns()) return fail(HP_EINVAL, "bad run index %d", run);
+  return f();
+}
+}  // namespace
+
+extern "C" {
+
+int hp_set_particles(hp_sim *sim, int32_t run, int32_t species, int64_t n, const double *x,
+                     const double *u, const double *w, double q_over_m, double q) {
+  return with_run(sim, run, [&] {
+    if (species != 0) return fail(HP_EINVAL, "only species 0 is supported");
+    return sim->impl->set_particles(run, n, x, u, w, q_over_m, q);
+  });
+}
+
+int hp_set_fields(hp_sim *sim, int32_t run, int32_t mode, const double *E, const double *B) {
+  return with_run(sim, run, [&] {
+    if (mode != 0 || !E || !B) return fail(HP_EINVAL, "mode must be 0 and arrays non-null");
+    return sim->impl->set_fields(run, E, B);
+  });
+}
+
+int hp_set_background(hp_sim *sim, int32_t run, int32_t rho_from_particles, const double *j_bg) {
+  return with_run(sim, run, [&] { return sim->impl->set_background(run, rho_from_particles, j_bg); });
+}
+
+int hp_step(hp_sim *sim, int32_t nsteps) {
+  int rc = check_sim(sim);
+  return rc ? rc : sim->impl->step(nsteps);
+}
+
+int hp_synchronize(hp_sim *sim) {
+  int rc = check_sim(sim);
+  return rc ? rc : sim->impl->sync();
+}
+
+int hp_get_field(hp_sim *sim, int32_t run, int32_t comp, int32_t mode, double *out, size_t count) {
+  return with_run(sim, run, [&] {
+    if (mode != 0) return fail(HP_EINVAL, "mode must be 0 in 2D");
+    return sim->impl->get_field(run, comp, out, count);
+  });
+}
+
+int hp_get_current(hp_sim *sim, int32_t run, int32_t comp, int32_t corrected, double *out,
+                   size_t count) {
+  return with_run(sim, run, [&] { return sim->impl->get_current(run, comp, corrected, out, count); });
+}
+
+int hp_get_current_fixed(hp_sim *sim, int32_t run, int32_t comp, int64_t *out, size_t count) {
+  return with_run(sim, run, [&] { return sim->impl->get_current_fixed(run, comp, out, count); });
+}
+
+int hp_get_particle_count(hp_sim *sim, int32_t run, int64_t *n) {
+  return with_run(sim, run, [&] { return sim->impl->get_count(run, n); });
+}
+
+int hp_get_particles(hp_sim *sim, int32_t run, int64_t n, double *x, double *u, double *w,
+                     int64_t *id) {
+  return with_run(sim, run, [&] { return sim->impl->get_particles(run, n, x, u, w, id); });
+}
+
+int hp_get_particles_raw(hp_sim *sim, int32_t run, int64_t n, int32_t *cell, float *off, float *u,
+                         float *qw, int32_t *id) {
+  return with_run(sim, run, [&] { return sim->impl->get_particles_raw(run, n, cell, off, u, qw, id); });
+}
+
+int hp_diagnostics(hp_sim *sim, int32_t run, hp_diag *out) {
+  return with_run(sim, run, [&] {
+    if (!out) return fail(HP_EINVAL, "null output");
+    return sim->impl->diagnostics(run, out);
+  });
+}
+
+int hp_get_state(hp_sim *sim, void *blob, size_t *size) {
+  int rc = check_sim(sim);
+  if (rc) return rc;
+  if (!size) return fail(HP_EINVAL, "null size");
+  return sim->impl->get_state(blob, size);
+}
+
+int hp_set_state(hp_sim *sim, const void *blob, size_t size) {
+  int rc = check_sim(sim);
+  if (rc) return rc;
+  if (!blob) return fail(HP_EINVAL, "null blob");
+  return sim->impl->set_state(blob, size);
+}
+
+int hp_debug_deposit(hp_sim *sim, int32_t run, int64_t n, const int32_t *cell0, const float *off0,
+                     const int32_t *cell1, const float *off1, const float *v3, const float *qw,
+                     int64_t *j_out) {
+  return with_run(sim, run, [&] {
+    if (n > 0 && (!cell0 || !off0 || !cell1 || !off1 || !v3 || !qw)) return fail(HP_EINVAL, "null input");
+    if (!j_out) return fail(HP_EINVAL, "null output");
+    return sim->impl->debug_deposit(run, n, cell0, off0, cell1, off1, v3, qw, j_out);
+  });
+}
+
+int hp_get_fixed_params(hp_sim *sim, int32_t run, double *out) {
+  return with_run(sim, run, [&] {
+    if (!out) return fail(HP_EINVAL, "null output");
+    return sim->impl->fixed_params(run, out);
+  });
+}
+
+int hp_profile(hp_sim *sim, int32_t enable) {
+  int rc = check_sim(sim);
+  return rc ? rc : sim->impl->profile(enable);
+}
+
+int hp_get_kernel_times(hp_sim *sim, double *ms, int64_t *n) {
+  int rc = check_sim(sim);
+  return rc ? rc : sim->impl->kernel_times(ms, n);
+}
+
+}  // extern "C"

@@ -1,0 +1,297 @@
+"""ctypes binding of libhpic.so (include/hpic.h): argument marshalling only.
+
+Every step of the PIC path runs in the library's HIP kernels.  If the library
+is missing this module raises; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "_lib", "libhpic.so")
+
+HP_OK, HP_EINVAL, HP_ECOURANT, HP_ENOMEM, HP_EDEVICE, HP_ERANGE, HP_ENUMERIC, HP_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+HP_GEOM_2D = 2
+HP_PREC_FP32_FIXED, HP_PREC_FP64 = 0, 1
+KERNELS = ("push_deposit", "fft_j", "kupdate", "ifft_eb", "sort")
+HP_NK = len(KERNELS)
+
+# every function of the C ABI (checked against the header by the tests)
+ABI = (
+    "hp_create", "hp_destroy", "hp_last_error", "hp_set_stream", "hp_set_particles",
+    "hp_set_fields", "hp_set_background", "hp_step", "hp_synchronize", "hp_get_field",
+    "hp_get_current", "hp_get_current_fixed", "hp_get_particle_count", "hp_get_particles",
+    "hp_get_particles_raw", "hp_diagnostics", "hp_get_state", "hp_set_state",
+    "hp_debug_deposit", "hp_get_fixed_params", "hp_profile", "hp_get_kernel_times",
+)
+
+
+class HpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("hpic error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("geom", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("dx", ctypes.c_double * 3),
+        ("dt", ctypes.c_double), ("shape_order", ctypes.c_int32), ("interp", ctypes.c_int32),
+        ("filter_frac", ctypes.c_double), ("deriv1", ctypes.c_int32), ("correct", ctypes.c_int32),
+        ("n_modes", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("fixed_shape_bits", ctypes.c_int32), ("fixed_weight_bits", ctypes.c_int32),
+        ("sort_interval", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8),
+    ]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [
+        ("W_E", ctypes.c_double * 3), ("W_B", ctypes.c_double * 3), ("kinetic", ctypes.c_double),
+        ("gauss_l2", ctypes.c_double), ("gauss_linf", ctypes.c_double),
+        ("gauss_ref_l2", ctypes.c_double), ("cont_linf", ctypes.c_double),
+        ("cont_int", ctypes.c_int64), ("charge_total", ctypes.c_double), ("step", ctypes.c_int64),
+    ]
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError("libhpic.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIBPATH)
+        i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        sigs = {
+            "hp_create": [ctypes.POINTER(Config), i32, ctypes.POINTER(_P)],
+            "hp_destroy": [_P],
+            "hp_last_error": [],
+            "hp_set_stream": [_P, _P],
+            "hp_set_particles": [_P, i32, i32, i64, _P, _P, _P, ctypes.c_double, ctypes.c_double],
+            "hp_set_fields": [_P, i32, i32, _P, _P],
+            "hp_set_background": [_P, i32, i32, _P],
+            "hp_step": [_P, i32],
+            "hp_synchronize": [_P],
+            "hp_get_field": [_P, i32, i32, i32, _P, sz],
+            "hp_get_current": [_P, i32, i32, i32, _P, sz],
+            "hp_get_current_fixed": [_P, i32, i32, _P, sz],
+            "hp_get_particle_count": [_P, i32, ctypes.POINTER(i64)],
+            "hp_get_particles": [_P, i32, i64, _P, _P, _P, _P],
+            "hp_get_particles_raw": [_P, i32, i64, _P, _P, _P, _P, _P],
+            "hp_diagnostics": [_P, i32, ctypes.POINTER(Diag)],
+            "hp_get_state": [_P, _P, ctypes.POINTER(sz)],
+            "hp_set_state": [_P, _P, sz],
+            "hp_debug_deposit": [_P, i32, i64, _P, _P, _P, _P, _P, _P, _P],
+            "hp_get_fixed_params": [_P, i32, _P],
+            "hp_profile": [_P, i32],
+            "hp_get_kernel_times": [_P, _P, _P],
+        }
+        for name, args in sigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = None if name == "hp_destroy" else (
+                ctypes.c_char_p if name == "hp_last_error" else ctypes.c_int)
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != HP_OK:
+        raise HpError(code, lib().hp_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_P)
+
+
+def config(n1, n2, dx1, dx2, dt, alpha=0.5, deriv1=0, correct=1, precision="fp32",
+           shape_bits=0, weight_bits=0, sort_interval=0):
+    c = Config()
+    c.geom = HP_GEOM_2D
+    c.n[0], c.n[1], c.n[2] = int(n1), int(n2), 1
+    c.dx[0], c.dx[1], c.dx[2] = float(dx1), float(dx2), 1.0
+    c.dt = float(dt)
+    c.shape_order, c.interp = 2, 0
+    c.filter_frac = float(alpha)
+    c.deriv1, c.correct = int(deriv1), int(correct)
+    c.precision = HP_PREC_FP32_FIXED if precision == "fp32" else HP_PREC_FP64
+    c.fixed_shape_bits, c.fixed_weight_bits = int(shape_bits), int(weight_bits)
+    c.sort_interval = int(sort_interval)
+    return c
+
+
+class Sim:
+    """One handle of the library: nruns independent 2D runs advanced together."""
+
+    def __init__(self, configs, stream=None):
+        if isinstance(configs, Config):
+            configs = [configs]
+        self.cfgs = list(configs)
+        arr = (Config * len(self.cfgs))(*self.cfgs)
+        h = _P()
+        _check(lib().hp_create(arr, len(self.cfgs), ctypes.byref(h)))
+        self.h = h
+        if stream is not None:
+            self.set_stream(stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shape(self, run):
+        c = self.cfgs[run]
+        return c.n[1], c.n[0]
+
+    def set_stream(self, stream):
+        s = getattr(stream, "cuda_stream", stream)
+        _check(lib().hp_set_stream(self.h, _P(int(s)) if s else None))
+
+    def set_particles(self, run, x, u, w, q_over_m=-1.0, q=-1.0):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        n = w.size
+        assert x.shape == (2, n) and u.shape == (3, n)
+        _check(lib().hp_set_particles(self.h, run, 0, n, _ptr(x), _ptr(u), _ptr(w),
+                                      float(q_over_m), float(q)))
+
+    def set_fields(self, run, E, B):
+        n2, n1 = self.shape(run)
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        assert E.shape == (3, n2, n1) and B.shape == (3, n2, n1)
+        _check(lib().hp_set_fields(self.h, run, 0, _ptr(E), _ptr(B)))
+
+    def set_background(self, run, rho_from_particles=True, jbg=(0.0, 0.0, 0.0)):
+        j = np.ascontiguousarray(jbg, dtype=np.float64)
+        _check(lib().hp_set_background(self.h, run, int(bool(rho_from_particles)), _ptr(j)))
+
+    def step(self, n=1):
+        _check(lib().hp_step(self.h, int(n)))
+
+    def synchronize(self):
+        _check(lib().hp_synchronize(self.h))
+
+    def field(self, run, comp):
+        n2, n1 = self.shape(run)
+        out = np.empty((n2, n1))
+        _check(lib().hp_get_field(self.h, run, comp, 0, _ptr(out), out.size))
+        return out
+
+    def fields(self, run):
+        F = np.stack([self.field(run, c) for c in range(6)])
+        return F[:3], F[3:]
+
+    def current(self, run, comp, corrected=False):
+        n2, n1 = self.shape(run)
+        out = np.empty((n2, n1))
+        _check(lib().hp_get_current(self.h, run, comp, int(corrected), _ptr(out), out.size))
+        return out
+
+    def current_fixed(self, run):
+        n2, n1 = self.shape(run)
+        out = np.empty((3, n2, n1), dtype=np.int64)
+        for c in range(3):
+            _check(lib().hp_get_current_fixed(self.h, run, c, _ptr(out[c]), n1 * n2))
+        return out
+
+    def count(self, run):
+        n = ctypes.c_int64()
+        _check(lib().hp_get_particle_count(self.h, run, ctypes.byref(n)))
+        return n.value
+
+    def particles(self, run):
+        n = self.count(run)
+        x = np.empty((2, n))
+        u = np.empty((3, n))
+        w = np.empty(n)
+        pid = np.empty(n, dtype=np.int64)
+        _check(lib().hp_get_particles(self.h, run, n, _ptr(x), _ptr(u), _ptr(w), _ptr(pid)))
+        return dict(x=x, u=u, w=w, id=pid)
+
+    def particles_raw(self, run):
+        n = self.count(run)
+        cell = np.empty((2, n), dtype=np.int32)
+        off = np.empty((2, n), dtype=np.float32)
+        u = np.empty((3, n), dtype=np.float32)
+        qw = np.empty(n, dtype=np.float32)
+        pid = np.empty(n, dtype=np.int32)
+        _check(lib().hp_get_particles_raw(self.h, run, n, _ptr(cell), _ptr(off), _ptr(u),
+                                          _ptr(qw), _ptr(pid)))
+        return dict(cell=cell, off=off, u=u, qw=qw, id=pid)
+
+    def diagnostics(self, run):
+        d = Diag()
+        _check(lib().hp_diagnostics(self.h, run, ctypes.byref(d)))
+        return dict(W_E=list(d.W_E), W_B=list(d.W_B), kinetic=d.kinetic, gauss_l2=d.gauss_l2,
+                    gauss_linf=d.gauss_linf, gauss_ref_l2=d.gauss_ref_l2, cont_linf=d.cont_linf,
+                    cont_int=d.cont_int, charge_total=d.charge_total, step=d.step)
+
+    def get_state(self):
+        size = ctypes.c_size_t(0)
+        _check(lib().hp_get_state(self.h, None, ctypes.byref(size)))
+        buf = np.empty(size.value, dtype=np.uint8)
+        _check(lib().hp_get_state(self.h, _ptr(buf), ctypes.byref(size)))
+        return buf[:size.value].tobytes()
+
+    def set_state(self, blob):
+        buf = np.frombuffer(blob, dtype=np.uint8).copy()
+        _check(lib().hp_set_state(self.h, _ptr(buf), buf.size))
+
+    def debug_deposit(self, run, cell0, off0, cell1, off1, v3, qw):
+        n2, n1 = self.shape(run)
+        c0 = np.ascontiguousarray(cell0, dtype=np.int32)
+        c1 = np.ascontiguousarray(cell1, dtype=np.int32)
+        o0 = np.ascontiguousarray(off0, dtype=np.float32)
+        o1 = np.ascontiguousarray(off1, dtype=np.float32)
+        v3 = np.ascontiguousarray(v3, dtype=np.float32)
+        qw = np.ascontiguousarray(qw, dtype=np.float32)
+        n = qw.size
+        assert c0.shape == (2, n) and o0.shape == (2, n) and c1.shape == (2, n) and o1.shape == (2, n)
+        J = np.empty((3, n2, n1), dtype=np.int64)
+        _check(lib().hp_debug_deposit(self.h, run, n, _ptr(c0), _ptr(o0), _ptr(c1), _ptr(o1),
+                                      _ptr(v3), _ptr(qw), _ptr(J)))
+        return J
+
+    def fixed_params(self, run):
+        out = np.empty(4)
+        _check(lib().hp_get_fixed_params(self.h, run, _ptr(out)))
+        return dict(P=int(out[0]), inv_wunit=np.float32(out[1]), c3=np.float32(out[2]),
+                    Q=int(out[3]))
+
+    def profile(self, enable=True):
+        _check(lib().hp_profile(self.h, int(bool(enable))))
+
+    def kernel_times(self):
+        ms = np.zeros(HP_NK)
+        n = np.zeros(HP_NK, dtype=np.int64)
+        _check(lib().hp_get_kernel_times(self.h, _ptr(ms), _ptr(n)))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
+
+
+def from_workload(d, precision="fp32", alpha=None, deriv1=0, correct=1, background=True,
+                  stream=None, **cfg_kw):
+    """Handle with one run loaded from a ``workloads`` dict (particles, fields,
+    background current and charge)."""
+    n1, n2, _ = d["n"]
+    dx1, dx2, _ = d["dx"]
+    c = config(n1, n2, dx1, dx2, d["dt"], alpha=d["alpha"] if alpha is None else alpha,
+               deriv1=deriv1, correct=correct, precision=precision, **cfg_kw)
+    sim = Sim([c], stream=stream)
+    x = np.stack([d["xi"][0] * dx1, d["xi"][1] * dx2])
+    sim.set_particles(0, x, d["u"], d["w"], d["qm"], d["q"])
+    if np.any(d["E"]) or np.any(d["B"]):
+        sim.set_fields(0, d["E"], d["B"])
+    if background:
+        sim.set_background(0, True, d["jbg"])
+    return sim
