@@ -36,8 +36,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--fp64-steps", type=int, default=50,
-                    help="steps of the FP64 form timed beside the FP32 form (0: skip)")
+    ap.add_argument("--fp64-steps", type=int, default=-1,
+                    help="steps of the FP64 form timed beside the FP32 form (-1: as --steps, 0: skip)")
     ap.add_argument("--err-steps", type=int, default=100,
                     help="steps over which the FP32 form is compared with the FP64 form")
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -59,6 +59,8 @@ def run_form(hpic, torch, d, precision, warmup, steps, profile=False):
     t1 = time.perf_counter()
     sim.synchronize()
     kt = sim.kernel_times() if profile else None
+    if profile:
+        kt["push_stats"] = sim.push_stats()
     return sim, (t1 - t0), kt
 
 
@@ -103,7 +105,10 @@ def main():
     pd_avg_s = pd_ms / max(pd_n, 1) * 1e-3
     alg_bytes = BYTES_PER_PARTICLE * npart + BYTES_PER_CELL * ncell
     achieved = alg_bytes / pd_avg_s / 1e9
+    push_stats = kt.pop("push_stats")
     kernels = {k: {"avg_us": 1e3 * ms / max(n, 1), "launches": n} for k, (ms, n) in kt.items()}
+    kernels["push_deposit"]["lds_fallback_tiles"] = push_stats["fallback_tiles"]
+    kernels["push_deposit"]["tiles"] = push_stats["tiles"]
     sim32.close()
 
     out = {
@@ -130,8 +135,10 @@ def main():
                      "traffic": None, "alg_bytes_per_launch": alg_bytes},
     }
 
+    if args.fp64_steps < 0:
+        args.fp64_steps = args.steps
     if args.fp64_steps > 0:
-        sim64, t64, _ = run_form(hpic, torch, d, "fp64", min(args.warmup, 5), args.fp64_steps)
+        sim64, t64, _ = run_form(hpic, torch, d, "fp64", args.warmup, args.fp64_steps)
         sim64.close()
         out["fp64_form"] = {"value": npart * args.fp64_steps / t64,
                             "ms_per_step": 1e3 * t64 / args.fp64_steps,

@@ -193,6 +193,12 @@ int hp_get_fixed_params(hp_sim *sim, int32_t run, double *out);
 int hp_profile(hp_sim *sim, int32_t enable);
 int hp_get_kernel_times(hp_sim *sim, double *ms, int64_t *n);
 
+/* Push+deposit statistics since the last hp_profile call: out[0] = particle
+ * tiles whose bounding box did not fit the workgroup's LDS (gathered and
+ * deposited through global memory instead), out[1] = tiles processed.
+ * Synchronous. */
+int hp_get_push_stats(hp_sim *sim, int64_t *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -487,8 +487,11 @@ int or_gauss2(const or_grid2 *g, const double *E, const double *rho, double *Rre
  * rho = Q s1 s2.  Physical units: j1 = -(dx1/dt) J1 / (inv_wunit 2^(2P+1)) and
  * likewise j2 with dx2.  The out-of-plane j3 does not enter the continuity
  * equation in 2D; it is FP32 with the same operation order as the kernel:
- *   T = S0x (2 S0y + S1y) + S1x (S0y + 2 S1y),   h = ((qw inv_wunit) v3) c3,
- *   J3 += rint(T h)      so that j3 = J3 / (inv_wunit c3 6 2^(2P)).
+ *   h = ((qw inv_wunit) v3) c3,  x0[a] = S0x[a] h,  x1[a] = S1x[a] h,
+ *   t0[b] = 2 S0y[b] + S1y[b],   t1[b] = S0y[b] + 2 S1y[b],
+ *   J3 += rint(fma(x0[a], t0[b], x1[a] t1[b]))
+ * (the product x1 t1 rounded once, then one fused multiply-add), which is
+ * h times 6 W3 of the Esirkepov scheme, so that j3 = J3 / (inv_wunit c3 6 2^(2P)).
  * This file is compiled with floating-point contraction off so that each FP32
  * operation rounds once, as in the kernel.
  */
@@ -557,14 +560,13 @@ int or_deposit2_fixed(int32_t n1, int32_t n2, int32_t P, float inv_wunit, float 
     float h = hv * c3;
     for (int b = 0; b < 4; ++b) {
       for (int a = 0; a < 4; ++a) {
-        float A0 = (float)S0x[a], A1 = (float)S1x[a];
+        float x0 = (float)S0x[a] * h;
+        float x1 = (float)S1x[a] * h;
         float B0 = (float)S0y[b], B1 = (float)S1y[b];
         float t0 = 2.0f * B0 + B1;
         float t1 = B0 + 2.0f * B1;
-        float p0 = A0 * t0;
-        float p1 = A1 * t1;
-        float T = p0 + p1;
-        float v = T * h;
+        float p1 = x1 * t1;
+        float v = fmaf(x0, t0, p1);
         int64_t idx = (int64_t)wrapi(base2 + b, n2) * n1 + wrapi(base1 + a, n1);
         J3[idx] += (int64_t)rintf(v);
       }

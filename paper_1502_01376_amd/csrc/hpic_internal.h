@@ -25,9 +25,22 @@ struct Item {
   int b;
 };
 
+// Particle state (structure of arrays): cell[np] (linear i2*n1 + i1),
+// f1/f2[np] offsets in [0,1), u1..u3[np] momenta u = gamma v, qw[np] charge
+// times weight, id[np] load index.
+template <class R>
+struct Parts {
+  int *cell, *id;
+  R *f1, *f2, *u1, *u2, *u3, *qw;
+};
+
 // Device-side description of one 2D run.  Arrays are owned by the host runtime.
-//   particles: cell[np] (linear i2*n1 + i1), f1/f2[np] offsets in [0,1),
-//              u1..u3[np] momenta, qw[np] charge times weight, id[np]
+//   pt:  particle buffers, ping-pong for the tile sort (index = particle parity)
+//   tiles: T1 x T2 cells each, nt1 x nt2 of them; tile_start[ntiles + 1] is the
+//        first particle of each tile after the last sort, tile_cnt[ntiles] the
+//        histogram / scatter cursor of the sort; tile_box the bounding box of
+//        the cells of each tile's particles (they drift out of the tile
+//        between sorts)
 //   F:   real-space fields [6][n2][n1] (E1 E2 E3 B1 B2 B3) for the gather
 //   Fk:  k-space master copy [6][n2][nk] (ping-pong, index = step parity)
 //   J:   deposit accumulators [3][n2][n1] (ping-pong, index = step parity)
@@ -41,14 +54,18 @@ struct Run {
   int P;             // fixed point: shape factors in units of 2^-P
   float inv_wunit;   // fixed point: integer charge = rint(qw * inv_wunit)
   float c3;          // fixed point: scale of the out-of-plane current
+  int unit_charge;   // fixed point: |charge| * 2^P < 2^31, so Q*C products fit 32 bits
   R dt, hdt, idx2;   // dt, dt/2, 1/dx2
   R dtdx1, dtdx2;    // dt/dx1, dt/dx2 (position advance in cells per unit velocity)
   R qmhdt;           // (q/m) dt/2
   R jfx1, jfx2;      // FP64 form: -dx1/dt, -dx2/dt (current of a unit-charge move)
   R inv_m;           // 1/M, M = n1/2 (inverse real FFT normalisation)
   R jbg0[3];         // n1 * j_bg: added to the kappa = 0 bin of every row
-  int *cell, *id;
-  R *f1, *f2, *u1, *u2, *u3, *qw;
+  Parts<R> pt[2];
+  int T1, T2, nt1, nt2, ntiles;
+  int *tile_start, *tile_cnt;
+  int *tile_box;     // [ntiles][4]: lo1, hi1, lo2, hi2 of the tile's particle cells
+                     // relative to the tile origin (updated by every push)
   R *F;
   C *Fk[2];
   Acc *J[2];
@@ -165,15 +182,20 @@ __device__ __forceinline__ int fixed_shape(int cell, float f, int P, int s[3]) {
   const int up = (f >= 0.5f) ? 1 : 0;
   const float d = up ? (f - 1.0f) : f;             // exact
   const float scaled = d * (float)(1 << P);         // exact
-  const long long D = (long long)rintf(scaled);
-  const long long h = 1ll << (P - 1);
+  const int D = (int)rintf(scaled);                 // |D| <= 2^(P-1)
+  const int h = 1 << (P - 1);
   const long long bias = 1ll << P;
-  const long long lo = h - D, hi = h + D;
-  s[0] = (int)((lo * lo + bias) >> (P + 1));
-  s[2] = (int)((hi * hi + bias) >> (P + 1));
+  const int lo = h - D, hi = h + D;                 // in [0, 2^P]
+  s[0] = (int)(((long long)lo * lo + bias) >> (P + 1));
+  s[2] = (int)(((long long)hi * hi + bias) >> (P + 1));
   s[1] = (1 << P) - s[0] - s[2];
   return cell + up;
 }
+
+// Global-memory view of a pointer held in a descriptor: lets the compiler use
+// global (not flat) loads, stores and atomics.
+template <class T> using gptr = T __attribute__((address_space(1))) *;
+template <class T> __device__ __forceinline__ gptr<T> G(T *p) { return (gptr<T>)p; }
 
 __device__ __forceinline__ int wrap_pow2(int i, int n) { return i & (n - 1); }
 __device__ __forceinline__ int wrap_small(int i, int n) {
@@ -185,12 +207,26 @@ __device__ __forceinline__ int wrap_small(int i, int n) {
 // Error bits of the device error word.
 enum : unsigned { ERR_RANGE = 1u, ERR_NUMERIC = 2u };
 
+// Statistics words of the push kernel: [0] tiles that fell back to global
+// memory (bounding box too large for LDS), [1] tiles processed.
+enum { STAT_FALLBACK = 0, STAT_TILES = 1, NSTAT = 2 };
+
+// LDS budget of one push+deposit workgroup: staged fields (24 B per node in
+// FP32, 48 B in FP64) and current accumulators (3 x 8 B per node).
+constexpr int PUSH_THREADS = 256;
+constexpr int PUSH_BATCH = 4;  // particles loaded per thread before pushing
+constexpr int PUSH_LDS_BYTES = 32768;
+
 // ---------------------------------------------------------------- launches
 // Host-side launch wrappers (kernels.hip), one instantiation per precision.
 template <class R>
 struct Launch {
   static void push_deposit(const Run<R> *runs, const Item *items, int nitems, int parity,
-                           unsigned *err, hipStream_t s);
+                           int pp, unsigned *err, unsigned *stats, hipStream_t s);
+  // tile sort of the particles of all runs: items are (run, first particle,
+  // count) chunks; tiles lists (run, 0, 0) once per run
+  static void sort(const Run<R> *runs, const Item *chunks, int nchunks, const Item *per_run,
+                   int nruns, int pp, hipStream_t s);
   static void fft_j(const Run<R> *runs, const Item *items, int nitems, int parity, int maxM,
                     hipStream_t s);
   static void kupdate(const Run<R> *runs, const Item *items, int nitems, int parity,
@@ -202,14 +238,12 @@ struct Launch {
 };
 
 // Diagnostics and helpers (FP64 unless noted).
-void launch_rho_fixed(const Run<float> *run_dev, int np, int n1, int n2, long long *rho,
-                      hipStream_t s);
-void launch_rho_fp64(const Run<double> *run_dev, int np, int n1, int n2, double *rho,
-                     hipStream_t s);
+void launch_rho_fixed(const Run<float> *run_dev, int pp, int np, long long *rho, hipStream_t s);
+void launch_rho_fp64(const Run<double> *run_dev, int pp, int np, double *rho, hipStream_t s);
 template <class R>
 void launch_energy(const R *F, long long cells, double *partial, int nblocks, hipStream_t s);
 template <class R>
-void launch_kinetic(const Run<R> *run_dev, int np, double *partial, int nblocks, hipStream_t s);
+void launch_kinetic(const Run<R> *run_dev, int pp, double *partial, int nblocks, hipStream_t s);
 // Gauss residual per row: rho (physical, FP64, [n2][n1]) and the k-space E1,E2
 // of a run; writes per-row [3]: sum |R|^2, max |R|, sum |f rho|^2.
 template <class R>

@@ -56,8 +56,10 @@ double courant_limit(const hp_config &c) {
   return 2.0 / std::sqrt(PI * PI / (a * a) + 4.0 / (b * b));
 }
 
-const int PUSH_CHUNK = 1024;  // particles per push workgroup
+const int SORT_CHUNK = 256;   // particles per sort workgroup
 const int UPD_BLOCK = 256;    // (i2, kappa) elements per update workgroup
+const int TILE1 = 32, TILE2 = 8;  // particle tile (cells along x1, x2)
+const int DEFAULT_SORT_INTERVAL = 16;
 
 struct Event2 {
   int kind;
@@ -92,6 +94,7 @@ struct SimBase {
   virtual int fixed_params(int run, double *out) = 0;
   virtual int profile(int enable) = 0;
   virtual int kernel_times(double *ms, int64_t *n) = 0;
+  virtual int push_stats(int64_t *out) = 0;
 };
 
 struct hp_sim {
@@ -139,7 +142,7 @@ class Sim : public SimBase {
     allocs_.push_back(d_err_);
     HIPCHK(hipMemset(d_err_, 0, sizeof(unsigned)));
     runs_.resize(nruns);
-    std::vector<Item> rows, grps, upd;
+    std::vector<Item> rows, grps, upd, tiles, perrun;
     for (int i = 0; i < nruns; ++i) {
       RunHost &h = runs_[i];
       h.cfg = cfgs[i];
@@ -217,8 +220,23 @@ class Sim : public SimBase {
       }
       const int nel = d.n2 * d.nk;
       for (int e = 0; e < nel; e += UPD_BLOCK) upd.push_back(Item{i, e, 0});
+      d.T1 = std::min(TILE1, d.n1);
+      d.T2 = std::min(TILE2, d.n2);
+      d.nt1 = (d.n1 + d.T1 - 1) / d.T1;
+      d.nt2 = (d.n2 + d.T2 - 1) / d.T2;
+      d.ntiles = d.nt1 * d.nt2;
+      if ((rc = alloc(&d.tile_start, d.ntiles + 1)) || (rc = alloc(&d.tile_cnt, d.ntiles)) ||
+          (rc = alloc(&d.tile_box, 4 * d.ntiles)))
+        return rc;
+      for (int t = 0; t < d.ntiles; ++t) tiles.push_back(Item{i, t, 0});
+      perrun.push_back(Item{i, 0, 0});
     }
+    for (int i = 0; i < nruns; ++i)
+      if (cfgs[i].sort_interval > 0) sort_interval_ = cfgs[i].sort_interval;
     int rc;
+    if ((rc = alloc(&d_stats_, NSTAT))) return rc;
+    if ((rc = upload_items(tiles, &d_tiles_, &n_tiles_))) return rc;
+    if ((rc = upload_items(perrun, &d_perrun_, &n_perrun_))) return rc;
     if ((rc = alloc(&d_runs_, nruns))) return rc;
     if ((rc = upload_items(rows, &d_rows_, &n_rows_))) return rc;
     if ((rc = upload_items(grps, &d_grps_, &n_grps_))) return rc;
@@ -235,7 +253,7 @@ class Sim : public SimBase {
                     double qm, double q) override {
     RunHost &h = runs_[run];
     Run<R> &d = h.d;
-    if (n < 0 || n > (int64_t)0x7fffffff - PUSH_CHUNK) return fail(HP_EINVAL, "particle count %lld out of range", (long long)n);
+    if (n < 0 || n > 1000000000) return fail(HP_EINVAL, "particle count %lld out of range", (long long)n);
     if (n > 0 && (!x || !u || !w)) return fail(HP_EINVAL, "null particle array");
     if (!std::isfinite(qm) || !std::isfinite(q) || qm == 0.0) return fail(HP_EINVAL, "bad q/m or q");
     const double L1 = h.cfg.dx[0] * d.n1, L2 = h.cfg.dx[1] * d.n2;
@@ -283,6 +301,7 @@ class Sim : public SimBase {
                     "%d shape bits would overflow the 64-bit accumulators",
                     cmax, Q, P);
       h.Qbits = Q;
+      d.unit_charge = (Q + P <= 22) ? 1 : 0;  // |Q C| fits 24 signed bits
       d.inv_wunit = (float)(std::ldexp(1.0, Q) / qmax);
       d.c3 = (float)(std::ldexp(1.0, 30 - Q - 2 * P) / 6.0);
     }
@@ -291,22 +310,18 @@ class Sim : public SimBase {
     d.qmhdt = (R)(0.5 * qm * h.cfg.dt);
     d.np = (int)n;
     h.np = n;
-    void *old[8] = {d.cell, d.id, d.f1, d.f2, d.u1, d.u2, d.u3, d.qw};
-    for (void *o : old)
-      if (o) release(o);
     int rc;
-    if ((rc = alloc(&d.cell, n)) || (rc = alloc(&d.id, n)) || (rc = alloc(&d.f1, n)) ||
-        (rc = alloc(&d.f2, n)) || (rc = alloc(&d.u1, n)) || (rc = alloc(&d.u2, n)) ||
-        (rc = alloc(&d.u3, n)) || (rc = alloc(&d.qw, n)))
-      return rc;
-    if ((rc = h2d(d.cell, cell.data(), n)) || (rc = h2d(d.id, id.data(), n)) ||
-        (rc = h2d(d.f1, f1.data(), n)) || (rc = h2d(d.f2, f2.data(), n)) ||
-        (rc = h2d(d.u1, u1.data(), n)) || (rc = h2d(d.u2, u2.data(), n)) ||
-        (rc = h2d(d.u3, u3.data(), n)) || (rc = h2d(d.qw, qw.data(), n)))
+    if ((rc = alloc_particles(run, n))) return rc;
+    Parts<R> &A = d.pt[pp_];
+    if ((rc = h2d(A.cell, cell.data(), n)) || (rc = h2d(A.id, id.data(), n)) ||
+        (rc = h2d(A.f1, f1.data(), n)) || (rc = h2d(A.f2, f2.data(), n)) ||
+        (rc = h2d(A.u1, u1.data(), n)) || (rc = h2d(A.u2, u2.data(), n)) ||
+        (rc = h2d(A.u3, u3.data(), n)) || (rc = h2d(A.qw, qw.data(), n)))
       return rc;
     if ((rc = upload_jfac(run))) return rc;
-    if ((rc = rebuild_push_items())) return rc;
-    return upload_runs();
+    if ((rc = rebuild_sort_items())) return rc;
+    if ((rc = upload_runs())) return rc;
+    return sort_now();
   }
 
   int set_fields(int run, const double *E, const double *B) override {
@@ -346,9 +361,17 @@ class Sim : public SimBase {
     if (nsteps < 0) return fail(HP_EINVAL, "negative step count");
     for (int s = 0; s < nsteps; ++s) {
       const int p = parity_;
+      if (sort_interval_ > 0 && since_sort_ >= sort_interval_) {
+        mark(HP_K_SORT, true);
+        Launch<R>::sort(d_runs_, d_chunks_, n_chunks_, d_perrun_, (int)runs_.size(), pp_, stream_);
+        mark(HP_K_SORT, false);
+        pp_ ^= 1;
+        since_sort_ = 0;
+      }
       mark(HP_K_PUSH_DEPOSIT, true);
-      Launch<R>::push_deposit(d_runs_, d_push_, n_push_, p, d_err_, stream_);
+      Launch<R>::push_deposit(d_runs_, d_tiles_, n_tiles_, p, pp_, d_err_, d_stats_, stream_);
       mark(HP_K_PUSH_DEPOSIT, false);
+      ++since_sort_;
       mark(HP_K_FFT_J, true);
       Launch<R>::fft_j(d_runs_, d_rows_, n_rows_, p, maxM_, stream_);
       mark(HP_K_FFT_J, false);
@@ -439,10 +462,11 @@ class Sim : public SimBase {
     if ((rc = sync())) return rc;
     std::vector<int> cell(n), pid(n);
     std::vector<R> f1(n), f2(n), a(n), b(n), c(n), qw(n);
-    if ((rc = d2h(cell.data(), d.cell, n)) || (rc = d2h(pid.data(), d.id, n)) ||
-        (rc = d2h(f1.data(), d.f1, n)) || (rc = d2h(f2.data(), d.f2, n)) ||
-        (rc = d2h(a.data(), d.u1, n)) || (rc = d2h(b.data(), d.u2, n)) ||
-        (rc = d2h(c.data(), d.u3, n)) || (rc = d2h(qw.data(), d.qw, n)))
+    const Parts<R> &A = d.pt[pp_];
+    if ((rc = d2h(cell.data(), A.cell, n)) || (rc = d2h(pid.data(), A.id, n)) ||
+        (rc = d2h(f1.data(), A.f1, n)) || (rc = d2h(f2.data(), A.f2, n)) ||
+        (rc = d2h(a.data(), A.u1, n)) || (rc = d2h(b.data(), A.u2, n)) ||
+        (rc = d2h(c.data(), A.u3, n)) || (rc = d2h(qw.data(), A.qw, n)))
       return rc;
     for (int64_t p = 0; p < n; ++p) {
       const int i1 = cell[p] & (d.n1 - 1), i2 = cell[p] >> d.log2n1;
@@ -469,19 +493,20 @@ class Sim : public SimBase {
     if (n != h.np) return fail(HP_EINVAL, "particle count mismatch");
     int rc;
     if ((rc = sync())) return rc;
+    const Parts<R> &A = d.pt[pp_];
     std::vector<int> cell(n);
-    if ((rc = d2h(cell.data(), d.cell, n))) return rc;
+    if ((rc = d2h(cell.data(), A.cell, n))) return rc;
     if (cellout)
       for (int64_t p = 0; p < n; ++p) {
         cellout[p] = cell[p] & (d.n1 - 1);
         cellout[n + p] = cell[p] >> d.log2n1;
       }
-    if (off && ((rc = d2h((R *)off, d.f1, n)) || (rc = d2h((R *)off + n, d.f2, n)))) return rc;
-    if (u && ((rc = d2h((R *)u, d.u1, n)) || (rc = d2h((R *)u + n, d.u2, n)) ||
-              (rc = d2h((R *)u + 2 * n, d.u3, n))))
+    if (off && ((rc = d2h((R *)off, A.f1, n)) || (rc = d2h((R *)off + n, A.f2, n)))) return rc;
+    if (u && ((rc = d2h((R *)u, A.u1, n)) || (rc = d2h((R *)u + n, A.u2, n)) ||
+              (rc = d2h((R *)u + 2 * n, A.u3, n))))
       return rc;
-    if (qwo && (rc = d2h((R *)qwo, d.qw, n))) return rc;
-    if (id && (rc = d2h(id, d.id, n))) return rc;
+    if (qwo && (rc = d2h((R *)qwo, A.qw, n))) return rc;
+    if (id && (rc = d2h(id, A.id, n))) return rc;
     return HP_OK;
   }
 
@@ -508,7 +533,7 @@ class Sim : public SimBase {
         out->W_B[c] += 0.5 * dV * hp[6 * b + 3 + c];
       }
     if (h.np > 0) {
-      launch_kinetic<R>(d_runs_ + run, (int)h.np, part, nb, stream_);
+      launch_kinetic<R>(d_runs_ + run, pp_, part, nb, stream_);
       rc = d2h(hp.data(), part, nb);
       if (rc) { release(part); return rc; }
       double s = 0;
@@ -615,9 +640,10 @@ class Sim : public SimBase {
                                0, 0};
       put(meta, sizeof meta);
       const int64_t n = h.np;
-      if ((rc = d2h((int *)o, d.cell, n))) return rc; o += sizeof(int) * n;
-      if ((rc = d2h((int *)o, d.id, n))) return rc; o += sizeof(int) * n;
-      R *arrs[6] = {d.f1, d.f2, d.u1, d.u2, d.u3, d.qw};
+      const Parts<R> &A = d.pt[pp_];
+      if ((rc = d2h((int *)o, A.cell, n))) return rc; o += sizeof(int) * n;
+      if ((rc = d2h((int *)o, A.id, n))) return rc; o += sizeof(int) * n;
+      R *arrs[6] = {A.f1, A.f2, A.u1, A.u2, A.u3, A.qw};
       for (R *a : arrs) { if ((rc = d2h((R *)o, a, n))) return rc; o += sizeof(R) * n; }
       if ((rc = d2h((R *)o, d.F, 6 * cells))) return rc; o += sizeof(R) * 6 * cells;
       if ((rc = d2h((C *)o, d.Fk[parity_], 6 * kpl))) return rc; o += sizeof(C) * 6 * kpl;
@@ -669,13 +695,11 @@ class Sim : public SimBase {
       d.qmhdt = (R)(0.5 * h.qm * h.cfg.dt);
       h.np = n;
       d.np = (int)n;
-      if ((rc = alloc(&d.cell, n)) || (rc = alloc(&d.id, n)) || (rc = alloc(&d.f1, n)) ||
-          (rc = alloc(&d.f2, n)) || (rc = alloc(&d.u1, n)) || (rc = alloc(&d.u2, n)) ||
-          (rc = alloc(&d.u3, n)) || (rc = alloc(&d.qw, n)))
-        return rc;
-      if ((rc = h2d(d.cell, (const int *)o, n))) return rc; o += sizeof(int) * n;
-      if ((rc = h2d(d.id, (const int *)o, n))) return rc; o += sizeof(int) * n;
-      R *arrs[6] = {d.f1, d.f2, d.u1, d.u2, d.u3, d.qw};
+      if ((rc = alloc_particles(i, n))) return rc;
+      const Parts<R> &A = d.pt[pp_];
+      if ((rc = h2d(A.cell, (const int *)o, n))) return rc; o += sizeof(int) * n;
+      if ((rc = h2d(A.id, (const int *)o, n))) return rc; o += sizeof(int) * n;
+      R *arrs[6] = {A.f1, A.f2, A.u1, A.u2, A.u3, A.qw};
       for (R *a : arrs) { if ((rc = h2d(a, (const R *)o, n))) return rc; o += sizeof(R) * n; }
       if ((rc = h2d(d.F, (const R *)o, 6 * cells))) return rc; o += sizeof(R) * 6 * cells;
       if ((rc = h2d(d.Fk[parity_], (const C *)o, 6 * kpl))) return rc; o += sizeof(C) * 6 * kpl;
@@ -690,8 +714,9 @@ class Sim : public SimBase {
       h.rho_prev_step = -2;
       if ((rc = upload_jfac(i))) return rc;
     }
-    if ((rc = rebuild_push_items())) return rc;
-    return upload_runs();
+    if ((rc = rebuild_sort_items())) return rc;
+    if ((rc = upload_runs())) return rc;
+    return sort_now();
   }
 
   int debug_deposit(int run, int64_t n, const int32_t *c0, const float *o0, const int32_t *c1,
@@ -741,9 +766,20 @@ class Sim : public SimBase {
     return HP_OK;
   }
 
+  int push_stats(int64_t *out) override {
+    int rc;
+    if ((rc = sync())) return rc;
+    unsigned h[NSTAT];
+    if ((rc = d2h(h, d_stats_, NSTAT))) return rc;
+    out[0] = h[STAT_FALLBACK];
+    out[1] = h[STAT_TILES];
+    return HP_OK;
+  }
+
   int profile(int enable) override {
     int rc;
     if ((rc = sync())) return rc;
+    HIPCHK(hipMemsetAsync(d_stats_, 0, sizeof(unsigned) * NSTAT, stream_));
     for (auto &e : events_) {
       (void)hipEventDestroy(e.a);
       (void)hipEventDestroy(e.b);
@@ -826,16 +862,42 @@ class Sim : public SimBase {
     for (size_t i = 0; i < runs_.size(); ++i) v[i] = runs_[i].d;
     return h2d(d_runs_, v.data(), v.size());
   }
-  int rebuild_push_items() {
+  // Sort chunks: (run, first particle, count <= SORT_CHUNK) over all particles.
+  int rebuild_sort_items() {
     std::vector<Item> items;
     for (int i = 0; i < (int)runs_.size(); ++i)
-      for (int64_t p = 0; p < runs_[i].np; p += PUSH_CHUNK)
-        items.push_back(Item{i, (int)p, (int)std::min<int64_t>(PUSH_CHUNK, runs_[i].np - p)});
-    if (d_push_) release(d_push_);
-    d_push_ = nullptr;
-    n_push_ = 0;
+      for (int64_t p = 0; p < runs_[i].np; p += SORT_CHUNK)
+        items.push_back(Item{i, (int)p, (int)std::min<int64_t>(SORT_CHUNK, runs_[i].np - p)});
+    if (d_chunks_) release(d_chunks_);
+    d_chunks_ = nullptr;
+    n_chunks_ = 0;
     if (items.empty()) return HP_OK;
-    return upload_items(items, &d_push_, &n_push_);
+    return upload_items(items, &d_chunks_, &n_chunks_);
+  }
+  // Particle buffers of a run: both sort buffers, released and re-made.
+  int alloc_particles(int run, int64_t n) {
+    Run<R> &d = runs_[run].d;
+    for (int b = 0; b < 2; ++b) {
+      Parts<R> &A = d.pt[b];
+      void *old[8] = {A.cell, A.id, A.f1, A.f2, A.u1, A.u2, A.u3, A.qw};
+      for (void *o : old)
+        if (o) release(o);
+      int rc;
+      if ((rc = alloc(&A.cell, n)) || (rc = alloc(&A.id, n)) || (rc = alloc(&A.f1, n)) ||
+          (rc = alloc(&A.f2, n)) || (rc = alloc(&A.u1, n)) || (rc = alloc(&A.u2, n)) ||
+          (rc = alloc(&A.u3, n)) || (rc = alloc(&A.qw, n)))
+        return rc;
+    }
+    return HP_OK;
+  }
+  // Sort the particles of every run by tile now (into the other buffer).
+  int sort_now() {
+    Launch<R>::sort(d_runs_, d_chunks_, n_chunks_, d_perrun_, (int)runs_.size(), pp_, stream_);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream_));
+    if (n_chunks_ > 0) pp_ ^= 1;
+    since_sort_ = 0;
+    return HP_OK;
   }
   // Factor from the deposit accumulator to physical current (before filtering).
   double acc_factor(const RunHost &h, int comp) const {
@@ -871,9 +933,9 @@ class Sim : public SimBase {
     const size_t cells = (size_t)d.n1 * d.n2;
     HIPCHK(hipMemsetAsync(rho, 0, sizeof(Acc) * cells, stream_));
     if constexpr (FIXED)
-      launch_rho_fixed(d_runs_ + run, (int)h.np, d.n1, d.n2, rho, stream_);
+      launch_rho_fixed(d_runs_ + run, pp_, (int)h.np, rho, stream_);
     else
-      launch_rho_fp64(d_runs_ + run, (int)h.np, d.n1, d.n2, rho, stream_);
+      launch_rho_fp64(d_runs_ + run, pp_, (int)h.np, rho, stream_);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream_));
     return HP_OK;
@@ -922,8 +984,13 @@ class Sim : public SimBase {
   std::vector<RunHost> runs_;
   std::vector<void *> allocs_;
   Run<R> *d_runs_ = nullptr;
-  Item *d_push_ = nullptr, *d_rows_ = nullptr, *d_grps_ = nullptr, *d_upd_ = nullptr;
-  int n_push_ = 0, n_rows_ = 0, n_grps_ = 0, n_upd_ = 0;
+  Item *d_chunks_ = nullptr, *d_tiles_ = nullptr, *d_perrun_ = nullptr;
+  Item *d_rows_ = nullptr, *d_grps_ = nullptr, *d_upd_ = nullptr;
+  int n_chunks_ = 0, n_tiles_ = 0, n_rows_ = 0, n_grps_ = 0, n_upd_ = 0;
+  int pp_ = 0;             // particle buffer parity
+  int n_perrun_ = 0;
+  int sort_interval_ = DEFAULT_SORT_INTERVAL, since_sort_ = 0;
+  unsigned *d_stats_ = nullptr;
   int maxM_ = 0;
   int parity_ = 0;
   int64_t step_ = 0;
@@ -1131,6 +1198,13 @@ int hp_profile(hp_sim *sim, int32_t enable) {
 int hp_get_kernel_times(hp_sim *sim, double *ms, int64_t *n) {
   int rc = check_sim(sim);
   return rc ? rc : sim->impl->kernel_times(ms, n);
+}
+
+int hp_get_push_stats(hp_sim *sim, int64_t *out) {
+  int rc = check_sim(sim);
+  if (rc) return rc;
+  if (!out) return fail(HP_EINVAL, "null output");
+  return sim->impl->push_stats(out);
 }
 
 }  // extern "C"

@@ -25,6 +25,7 @@ ABI = (
     "hp_get_current", "hp_get_current_fixed", "hp_get_particle_count", "hp_get_particles",
     "hp_get_particles_raw", "hp_diagnostics", "hp_get_state", "hp_set_state",
     "hp_debug_deposit", "hp_get_fixed_params", "hp_profile", "hp_get_kernel_times",
+    "hp_get_push_stats",
 )
 
 
@@ -88,6 +89,7 @@ def lib():
             "hp_get_fixed_params": [_P, i32, _P],
             "hp_profile": [_P, i32],
             "hp_get_kernel_times": [_P, _P, _P],
+            "hp_get_push_stats": [_P, _P],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -271,6 +273,11 @@ class Sim:
 
     def profile(self, enable=True):
         _check(lib().hp_profile(self.h, int(bool(enable))))
+
+    def push_stats(self):
+        out = np.zeros(2, dtype=np.int64)
+        _check(lib().hp_get_push_stats(self.h, _ptr(out)))
+        return dict(fallback_tiles=int(out[0]), tiles=int(out[1]))
 
     def kernel_times(self):
         ms = np.zeros(HP_NK)
