@@ -34,13 +34,15 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--fp64-steps", type=int, default=-1,
                     help="steps of the FP64 form timed beside the FP32 form (-1: as --steps, 0: skip)")
-    ap.add_argument("--err-steps", type=int, default=100,
+    ap.add_argument("--err-steps", type=int, default=1000,
                     help="steps over which the FP32 form is compared with the FP64 form")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--n1", type=int, default=2048)
     ap.add_argument("--n2", type=int, default=512)
     return ap.parse_args()
@@ -64,24 +66,58 @@ def run_form(hpic, torch, d, precision, warmup, steps, profile=False):
     return sim, (t1 - t0), kt
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_deposit_drift2d_2048x512_hbm_traffic.txt")
+PUSH_SOURCES = [os.path.join(ROOT, "paper_1502_01376_amd", "csrc", f)
+                for f in ("push.hip", "hpic_internal.h")]
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PUSH_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per push+deposit launch from the committed rocprofv3 counter
+    summary, or None if the kernel source changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 2 and not line.startswith("#"):
+                vals[parts[0]] = parts[1]
+    if vals.get("source_hash") != source_hash() or "hbm_bytes_per_launch" not in vals:
+        return None
+    return float(vals["hbm_bytes_per_launch"])
+
+
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def cpu_baseline(d):
-    """FP64 oracle on the host: one full step of the same workload."""
+def cpu_baseline(d, min_seconds=10.0, max_steps=10):
+    """FP64 oracle on the host: whole steps of the same workload until about
+    min_seconds of CPU work (at most max_steps)."""
     import oracle
     g = oracle.grid2(d["n"][0], d["n"][1], d["dx"][0], d["dx"][1], d["dt"], alpha=d["alpha"],
                      jbg=d["jbg"])
     st = oracle.State2(g, d["qm"], d["xi"][0], d["xi"][1], d["u"], d["q"] * d["w"],
                        E=d["E"], B=d["B"])
     npart = d["w"].size
+    steps = 0
     t0 = time.perf_counter()
-    st.step(1)
+    while steps < max_steps and (time.perf_counter() - t0) < min_seconds:
+        st.step(1)
+        steps += 1
     dt = time.perf_counter() - t0
-    return {"value": npart / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "1 full step of the same workload (%d particles, %dx%d grid), "
-                      "single-threaded FP64 C, %.1f s" % (npart, d["n"][0], d["n"][1], dt)}
+    return {"value": npart * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d full steps of the same workload (%d particles, %dx%d grid), "
+                      "single-threaded FP64 C, %.1f s" % (steps, npart, d["n"][0], d["n"][1], dt)}
 
 
 def main():
@@ -132,7 +168,8 @@ def main():
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": "push_deposit", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "alg_bytes_per_launch": alg_bytes},
+                     "traffic": measured_traffic(), "alg_bytes_per_launch": alg_bytes,
+                     "source_hash": source_hash()},
     }
 
     if args.fp64_steps < 0:
@@ -159,6 +196,14 @@ def main():
                               "gauss_rel_l2_fp32": da["gauss_l2"] / max(da["gauss_ref_l2"], 1e-300)}
         a.close()
         b.close()
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 2 * n * 4
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d)
     print(json.dumps(out), flush=True)
