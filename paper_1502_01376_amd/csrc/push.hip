@@ -660,12 +660,17 @@ __global__ void __launch_bounds__(1024) k_sort_scan(const Run<R> *runs, const It
     r.tile_start[t] = run;
     r.tile_cnt[t] = run;
     run += c;
-    // right after the sort every particle of tile t lies in the tile
+    // right after the sort every particle of tile t lies in the tile; the box
+    // is expressed in the frame the push uses (cell minus tile origin, wrapped
+    // into [-n/2, n - n/2)), so a tile wider than half the grid covers the
+    // whole wrapped range
     const int t2 = t / r.nt1, t1 = t - t2 * r.nt1;
-    r.tile_box[4 * t + 0] = 0;
-    r.tile_box[4 * t + 1] = min(r.T1, r.n1 - t1 * r.T1) - 1;
-    r.tile_box[4 * t + 2] = 0;
-    r.tile_box[4 * t + 3] = min(r.T2, r.n2 - t2 * r.T2) - 1;
+    const int w1 = min(r.T1, r.n1 - t1 * r.T1), w2 = min(r.T2, r.n2 - t2 * r.T2);
+    const bool full1 = w1 > r.n1 - (r.n1 >> 1), full2 = w2 > r.n2 - (r.n2 >> 1);
+    r.tile_box[4 * t + 0] = full1 ? -(r.n1 >> 1) : 0;
+    r.tile_box[4 * t + 1] = full1 ? r.n1 - (r.n1 >> 1) - 1 : w1 - 1;
+    r.tile_box[4 * t + 2] = full2 ? -(r.n2 >> 1) : 0;
+    r.tile_box[4 * t + 3] = full2 ? r.n2 - (r.n2 >> 1) - 1 : w2 - 1;
   }
   if (threadIdx.x == 1023) r.tile_start[nt] = part[1023];
 }
