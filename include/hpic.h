@@ -135,6 +135,12 @@ int hp_set_background(hp_sim *sim, int32_t run, int32_t rho_from_particles,
  * synchronous call. */
 int hp_step(hp_sim *sim, int32_t nsteps);
 
+/* With enable = 1 (the default) hp_step replays each block of one particle
+ * sort and sort_interval steps as a captured HIP graph (when sort_interval is
+ * even and no profiling is active); 0 launches every kernel separately.
+ * Results are identical either way. */
+int hp_use_graphs(hp_sim *sim, int32_t enable);
+
 /* Waits for the handle's stream and reports kernel-detected errors. */
 int hp_synchronize(hp_sim *sim);
 

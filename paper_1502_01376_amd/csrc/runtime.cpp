@@ -95,6 +95,7 @@ struct SimBase {
   virtual int profile(int enable) = 0;
   virtual int kernel_times(double *ms, int64_t *n) = 0;
   virtual int push_stats(int64_t *out) = 0;
+  virtual int use_graphs(int enable) = 0;
 };
 
 struct hp_sim {
@@ -129,6 +130,8 @@ class Sim : public SimBase {
 
  public:
   ~Sim() override {
+    drop_graphs();
+    if (capture_stream_) (void)hipStreamDestroy(capture_stream_);
     for (auto &e : events_) {
       (void)hipEventDestroy(e.a);
       (void)hipEventDestroy(e.b);
@@ -357,34 +360,103 @@ class Sim : public SimBase {
     return upload_runs();
   }
 
+  // One eager step (with per-kernel events when profiling).
+  void launch_step() {
+    const int p = parity_;
+    if (sort_interval_ > 0 && since_sort_ >= sort_interval_) {
+      mark(HP_K_SORT, true);
+      Launch<R>::sort(d_runs_, d_chunks_, n_chunks_, d_perrun_, (int)runs_.size(), pp_, stream_);
+      mark(HP_K_SORT, false);
+      if (n_chunks_ > 0) pp_ ^= 1;
+      since_sort_ = 0;
+    }
+    mark(HP_K_PUSH_DEPOSIT, true);
+    Launch<R>::push_deposit(d_runs_, d_tiles_, n_tiles_, p, pp_, d_err_, d_stats_, stream_);
+    mark(HP_K_PUSH_DEPOSIT, false);
+    ++since_sort_;
+    mark(HP_K_FFT_J, true);
+    Launch<R>::fft_j(d_runs_, d_rows_, n_rows_, p, maxM_, stream_);
+    mark(HP_K_FFT_J, false);
+    mark(HP_K_KUPDATE, true);
+    Launch<R>::kupdate(d_runs_, d_upd_, n_upd_, p, stream_);
+    mark(HP_K_KUPDATE, false);
+    mark(HP_K_IFFT_EB, true);
+    Launch<R>::ifft_eb(d_runs_, d_grps_, n_grps_, p ^ 1, maxM_, stream_);
+    mark(HP_K_IFFT_EB, false);
+    parity_ ^= 1;
+    ++step_;
+  }
+
+  // A block of one sort followed by K steps (K = sort interval, even), as a
+  // HIP graph per (particle parity, step parity): the block starts with a due
+  // sort and leaves the step parity unchanged.
+  int block_graph(hipGraphExec_t *out) {
+    hipGraphExec_t &g = graph_[pp_][parity_];
+    if (!g) {
+      if (!capture_stream_) HIPCHK(hipStreamCreateWithFlags(&capture_stream_, hipStreamNonBlocking));
+      const hipStream_t keep = stream_;
+      const int keep_pp = pp_, keep_par = parity_, keep_since = since_sort_;
+      const int64_t keep_step = step_;
+      const bool keep_prof = profiling_;
+      profiling_ = false;
+      stream_ = capture_stream_;
+      HIPCHK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < sort_interval_; ++k) launch_step();
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(stream_, &graph);
+      stream_ = keep;
+      pp_ = keep_pp;
+      parity_ = keep_par;
+      since_sort_ = keep_since;
+      step_ = keep_step;
+      profiling_ = keep_prof;
+      if (e != hipSuccess) return fail(HP_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+      const hipError_t ei = hipGraphInstantiateWithFlags(&g, graph, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        g = nullptr;
+        return fail(HP_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+      }
+    }
+    *out = g;
+    return HP_OK;
+  }
+
+  void drop_graphs() {
+    for (auto &row : graph_)
+      for (auto &g : row)
+        if (g) {
+          (void)hipGraphExecDestroy(g);
+          g = nullptr;
+        }
+  }
+
   int step(int nsteps) override {
     if (nsteps < 0) return fail(HP_EINVAL, "negative step count");
-    for (int s = 0; s < nsteps; ++s) {
-      const int p = parity_;
-      if (sort_interval_ > 0 && since_sort_ >= sort_interval_) {
-        mark(HP_K_SORT, true);
-        Launch<R>::sort(d_runs_, d_chunks_, n_chunks_, d_perrun_, (int)runs_.size(), pp_, stream_);
-        mark(HP_K_SORT, false);
+    int left = nsteps;
+    while (left > 0) {
+      const int K = sort_interval_;
+      if (use_graphs_ && !profiling_ && K > 0 && (K & 1) == 0 && since_sort_ >= K && left >= K &&
+          n_chunks_ > 0) {
+        hipGraphExec_t g;
+        int rc;
+        if ((rc = block_graph(&g))) return rc;
+        HIPCHK(hipGraphLaunch(g, stream_));
         pp_ ^= 1;
-        since_sort_ = 0;
+        since_sort_ = K;
+        step_ += K;
+        left -= K;
+      } else {
+        launch_step();
+        --left;
       }
-      mark(HP_K_PUSH_DEPOSIT, true);
-      Launch<R>::push_deposit(d_runs_, d_tiles_, n_tiles_, p, pp_, d_err_, d_stats_, stream_);
-      mark(HP_K_PUSH_DEPOSIT, false);
-      ++since_sort_;
-      mark(HP_K_FFT_J, true);
-      Launch<R>::fft_j(d_runs_, d_rows_, n_rows_, p, maxM_, stream_);
-      mark(HP_K_FFT_J, false);
-      mark(HP_K_KUPDATE, true);
-      Launch<R>::kupdate(d_runs_, d_upd_, n_upd_, p, stream_);
-      mark(HP_K_KUPDATE, false);
-      mark(HP_K_IFFT_EB, true);
-      Launch<R>::ifft_eb(d_runs_, d_grps_, n_grps_, p ^ 1, maxM_, stream_);
-      mark(HP_K_IFFT_EB, false);
-      parity_ ^= 1;
-      ++step_;
     }
     HIPCHK(hipGetLastError());
+    return HP_OK;
+  }
+
+  int use_graphs(int enable) override {
+    use_graphs_ = enable != 0;
     return HP_OK;
   }
 
@@ -864,6 +936,7 @@ class Sim : public SimBase {
   }
   // Sort chunks: (run, first particle, count <= SORT_CHUNK) over all particles.
   int rebuild_sort_items() {
+    drop_graphs();  // captured launches hold the old item lists and counts
     std::vector<Item> items;
     for (int i = 0; i < (int)runs_.size(); ++i)
       for (int64_t p = 0; p < runs_[i].np; p += SORT_CHUNK)
@@ -991,6 +1064,9 @@ class Sim : public SimBase {
   int n_perrun_ = 0;
   int sort_interval_ = DEFAULT_SORT_INTERVAL, since_sort_ = 0;
   unsigned *d_stats_ = nullptr;
+  bool use_graphs_ = true;
+  hipGraphExec_t graph_[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipStream_t capture_stream_ = nullptr;
   int maxM_ = 0;
   int parity_ = 0;
   int64_t step_ = 0;
@@ -1198,6 +1274,11 @@ int hp_profile(hp_sim *sim, int32_t enable) {
 int hp_get_kernel_times(hp_sim *sim, double *ms, int64_t *n) {
   int rc = check_sim(sim);
   return rc ? rc : sim->impl->kernel_times(ms, n);
+}
+
+int hp_use_graphs(hp_sim *sim, int32_t enable) {
+  int rc = check_sim(sim);
+  return rc ? rc : sim->impl->use_graphs(enable);
 }
 
 int hp_get_push_stats(hp_sim *sim, int64_t *out) {

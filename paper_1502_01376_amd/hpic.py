@@ -25,7 +25,7 @@ ABI = (
     "hp_get_current", "hp_get_current_fixed", "hp_get_particle_count", "hp_get_particles",
     "hp_get_particles_raw", "hp_diagnostics", "hp_get_state", "hp_set_state",
     "hp_debug_deposit", "hp_get_fixed_params", "hp_profile", "hp_get_kernel_times",
-    "hp_get_push_stats",
+    "hp_get_push_stats", "hp_use_graphs",
 )
 
 
@@ -90,6 +90,7 @@ def lib():
             "hp_profile": [_P, i32],
             "hp_get_kernel_times": [_P, _P, _P],
             "hp_get_push_stats": [_P, _P],
+            "hp_use_graphs": [_P, i32],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -180,6 +181,9 @@ class Sim:
 
     def step(self, n=1):
         _check(lib().hp_step(self.h, int(n)))
+
+    def use_graphs(self, enable=True):
+        _check(lib().hp_use_graphs(self.h, int(bool(enable))))
 
     def synchronize(self):
         _check(lib().hp_synchronize(self.h))
@@ -286,19 +290,29 @@ class Sim:
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
 
 
+def from_workloads(ds, precision="fp32", alpha=None, deriv1=0, correct=1, background=True,
+                   stream=None, **cfg_kw):
+    """Handle with one run per ``workloads`` dict of ``ds`` (particles, fields,
+    background current and charge), all advanced together."""
+    cfgs = []
+    for d in ds:
+        n1, n2, _ = d["n"]
+        dx1, dx2, _ = d["dx"]
+        cfgs.append(config(n1, n2, dx1, dx2, d["dt"], alpha=d["alpha"] if alpha is None else alpha,
+                           deriv1=deriv1, correct=correct, precision=precision, **cfg_kw))
+    sim = Sim(cfgs, stream=stream)
+    for r, d in enumerate(ds):
+        dx1, dx2, _ = d["dx"]
+        x = np.stack([d["xi"][0] * dx1, d["xi"][1] * dx2])
+        sim.set_particles(r, x, d["u"], d["w"], d["qm"], d["q"])
+        if np.any(d["E"]) or np.any(d["B"]):
+            sim.set_fields(r, d["E"], d["B"])
+        if background:
+            sim.set_background(r, True, d["jbg"])
+    return sim
+
+
 def from_workload(d, precision="fp32", alpha=None, deriv1=0, correct=1, background=True,
                   stream=None, **cfg_kw):
-    """Handle with one run loaded from a ``workloads`` dict (particles, fields,
-    background current and charge)."""
-    n1, n2, _ = d["n"]
-    dx1, dx2, _ = d["dx"]
-    c = config(n1, n2, dx1, dx2, d["dt"], alpha=d["alpha"] if alpha is None else alpha,
-               deriv1=deriv1, correct=correct, precision=precision, **cfg_kw)
-    sim = Sim([c], stream=stream)
-    x = np.stack([d["xi"][0] * dx1, d["xi"][1] * dx2])
-    sim.set_particles(0, x, d["u"], d["w"], d["qm"], d["q"])
-    if np.any(d["E"]) or np.any(d["B"]):
-        sim.set_fields(0, d["E"], d["B"])
-    if background:
-        sim.set_background(0, True, d["jbg"])
-    return sim
+    """Handle with one run loaded from a ``workloads`` dict."""
+    return from_workloads([d], precision, alpha, deriv1, correct, background, stream, **cfg_kw)

@@ -18,6 +18,11 @@ The named workloads are the drifting-plasma set-ups of the benchmark suite:
 * ``drift2d_laser``  -- 2048 x 512 cells, dx = (0.1, 0.2), dt = 0.045,
   4x2 sub-lattice with uniform jitter (8 per cell), gamma = 20 cold, plus a
   linearly polarised Gaussian laser (a0 = 2, waist 8, length 4).
+* ``scan2d``  -- a batched parameter scan of independent drifting-plasma runs
+  of uneven sizes: per run N1 from {256, 512, 1024, 2048}, N2 from
+  {64, 128, 256, 512}, gamma ~ U[5, 100], density ~ U[0.5, 2], 4..16
+  particles per cell at uniformly random positions in each cell, dx = 0.2,
+  dt = 0.05, thermal spread 1e-4, filter 0.5, 200 steps.
 
 The NCI test set-up of Table 1 (dx = 0.2, dt = 0.4 dx1, periodic,
 51.2 x 51.2, gamma = 50, n = 100) is ``nci_table1``.
@@ -55,6 +60,17 @@ def lattice_2d(n1, n2, sub1, sub2, jitter, gen):
     x1 = np.mod(x1, n1)
     x2 = np.mod(x2, n2)
     return x1, x2
+
+
+def random_in_cells(n1, n2, ppc, gen):
+    """ppc particles per cell at uniformly random positions inside the cell
+    (cell units), cell-major order."""
+    base1 = np.tile(np.arange(n1, dtype=np.float64), n2)
+    base2 = np.repeat(np.arange(n2, dtype=np.float64), n1)
+    x1 = np.repeat(base1, ppc) + gen.random(n1 * n2 * ppc)
+    x2 = np.repeat(base2, ppc) + gen.random(n1 * n2 * ppc)
+    # a draw of exactly 1 - 2^-53 plus the cell index may round up to the next cell
+    return np.mod(x1, n1), np.mod(x2, n2)
 
 
 def drift_momenta(npart, gamma, sigma_u, gen):
@@ -155,6 +171,48 @@ def drift2d_laser(seed=SEED0 + 1, n1=2048, n2=512):
                 seed=seed, laser=laser, name="drift2d_%dx%d_g20_laser" % (n1, n2))
     d["steps"] = 1000
     return d
+
+
+SCAN_N1 = (256, 512, 1024, 2048)
+SCAN_N2 = (64, 128, 256, 512)
+
+
+def scan2d_params(nruns=64, seed=SEED0 + 4, shrink=1):
+    """Per-run parameters of the parameter scan: run r draws, from its own
+    generator seeded seed + 1000 r, N1, N2, gamma, density and particles per
+    cell.  ``shrink`` divides both grid sizes (small versions for tests)."""
+    out = []
+    for r in range(nruns):
+        gen = rng(seed + 1000 * r)
+        n1 = int(gen.choice(SCAN_N1)) // shrink
+        n2 = int(gen.choice(SCAN_N2)) // shrink
+        gamma = float(gen.uniform(5.0, 100.0))
+        density = float(gen.uniform(0.5, 2.0))
+        ppc = int(gen.integers(4, 17))
+        out.append(dict(run=r, n1=n1, n2=n2, gamma=gamma, density=density, ppc=ppc,
+                        seed=seed + 1000 * r))
+    return out
+
+
+def scan2d_run(p, dx=0.2, dt=0.05, sigma_u=1e-4, alpha=0.5):
+    """One run of the parameter scan from its parameters (see scan2d_params)."""
+    gen = rng(p["seed"] + 1)
+    n1, n2, ppc = p["n1"], p["n2"], p["ppc"]
+    x1, x2 = random_in_cells(n1, n2, ppc, gen)
+    npart = x1.size
+    u = drift_momenta(npart, p["gamma"], sigma_u, gen)
+    w = np.full(npart, p["density"] / ppc)
+    q, qm = -1.0, -1.0
+    E = np.zeros((3, n2, n1))
+    jbg = -mean_current(u, w, q, n1 * n2)
+    return dict(name="scan2d_run%d_%dx%d" % (p["run"], n1, n2), geom=2, n=(n1, n2, 1),
+                dx=(dx, dx, 1.0), dt=dt, alpha=alpha, xi=np.stack([x1, x2]), u=u, w=w, q=q,
+                qm=qm, E=E, B=E.copy(), jbg=jbg, seed=p["seed"], steps=200)
+
+
+def scan2d(nruns=64, seed=SEED0 + 4, shrink=1):
+    """All runs of the parameter scan (see scan2d_params, scan2d_run)."""
+    return [scan2d_run(p) for p in scan2d_params(nruns, seed, shrink)]
 
 
 def nci_table1(seed=SEED0 + 10, ppc=(2, 2), n=(256, 256)):
