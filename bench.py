@@ -43,27 +43,48 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--tune-steps", type=int, default=1200,
+                    help="steps advanced by the autotuner before the warm-up (0: default tiling)")
+    ap.add_argument("--scan-steps", type=int, default=200,
+                    help="steps of the 64-run parameter scan (0: skip)")
     ap.add_argument("--n1", type=int, default=2048)
     ap.add_argument("--n2", type=int, default=512)
     return ap.parse_args()
 
 
-def run_form(hpic, torch, d, precision, warmup, steps, profile=False):
-    sim = hpic.from_workload(d, precision, stream=torch.cuda.current_stream())
+def timed_steps(torch, sim, warmup, steps):
+    """Wall time of `steps` steps after `warmup` untimed ones, synchronised on
+    both sides."""
     sim.step(warmup)
     sim.synchronize()
-    if profile:
-        sim.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sim.synchronize()
-    kt = sim.kernel_times() if profile else None
+    return t1 - t0
+
+
+def run_form(hpic, torch, ds, precision, warmup, steps, profile=False, tune_steps=0):
+    """Untimed: the autotuner (tune_steps steps, picking tile shape and sort
+    interval on the live runs) and `warmup` steps.  Timed region: `steps`
+    steps with the captured-graph step (the library's default).  With
+    `profile`, a second pass of the same length launches every kernel with HIP
+    events around it on the library's stream for per-kernel durations."""
+    sim = hpic.from_workloads(ds, precision, stream=torch.cuda.current_stream())
+    if tune_steps > 0:
+        sim.autotune(tune_steps)
+    t = timed_steps(torch, sim, warmup, steps)
+    kt = None
     if profile:
+        sim.profile(True)
+        tp = timed_steps(torch, sim, 0, steps)
+        kt = sim.kernel_times()
         kt["push_stats"] = sim.push_stats()
-    return sim, (t1 - t0), kt
+        kt["profiled_wall_s"] = tp
+        sim.profile(False)
+    return sim, t, kt
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_deposit_drift2d_2048x512_hbm_traffic.txt")
@@ -120,6 +141,44 @@ def cpu_baseline(d, min_seconds=10.0, max_steps=10):
                       "single-threaded FP64 C, %.1f s" % (steps, npart, d["n"][0], d["n"][1], dt)}
 
 
+def scan_leg(hpic, torch, W, steps, tune_steps):
+    """The 64-run parameter scan in one handle: aggregate particle-steps/s of
+    the FP32 form (graph-replayed) and of the FP64 form, and each run's
+    FP32-vs-FP64 relative L2 error of E, B and J after `steps` steps."""
+    t0 = time.perf_counter()
+    ds = W.scan2d()
+    gen_s = time.perf_counter() - t0
+    npart = sum(x["w"].size for x in ds)
+    warm = 16
+    a, t32, _ = run_form(hpic, torch, ds, "fp32", warm, steps, tune_steps=tune_steps)
+    b, t64, _ = run_form(hpic, torch, ds, "fp64", warm, steps, tune_steps=tune_steps)
+    tiling = a.tiling()
+    errs = {"E": [], "B": [], "J": [], "gauss": []}
+    for r in range(len(ds)):
+        Ea, Ba = a.fields(r)
+        Eb, Bb = b.fields(r)
+        ja = np.stack([a.current(r, c) for c in range(3)])
+        jb = np.stack([b.current(r, c) for c in range(3)])
+        errs["E"].append(rel_l2(Ea, Eb))
+        errs["B"].append(rel_l2(Ba, Bb))
+        errs["J"].append(rel_l2(ja, jb))
+        dg = a.diagnostics(r)
+        errs["gauss"].append(dg["gauss_l2"] / max(dg["gauss_ref_l2"], 1e-300))
+    a.close()
+    b.close()
+    v32 = npart * steps / t32
+    v64 = npart * steps / t64
+    summ = {k: {"max": float(np.max(v)), "median": float(np.median(v))} for k, v in errs.items()}
+    return {"workload": "scan2d_64runs", "runs": len(ds), "particles": npart,
+            "cells": int(sum(x["n"][0] * x["n"][1] for x in ds)), "steps": steps,
+            "value": v32, "unit": "particle-steps/s", "ms_per_step": 1e3 * t32 / steps,
+            "fp64_form": {"value": v64, "ms_per_step": 1e3 * t64 / steps,
+                          "fp32_speedup": v32 / v64},
+            "err_vs_fp64_per_run": summ, "generate_s": gen_s, "tiling": tiling,
+            "note": "autotuner (%d steps) and warm-up (%d steps) before the timed region; "
+                    "errors after all %d steps" % (tune_steps, warm, tune_steps + warm + steps)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -134,7 +193,10 @@ def main():
     npart = d["w"].size
     ncell = d["n"][0] * d["n"][1]
 
-    sim32, t32, kt = run_form(hpic, torch, d, "fp32", args.warmup, args.steps, profile=True)
+    sim32, t32, kt = run_form(hpic, torch, [d], "fp32", args.warmup, args.steps, profile=True,
+                              tune_steps=args.tune_steps)
+    tiling = sim32.tiling()
+    profiled_wall = kt.pop("profiled_wall_s")
     value = npart * args.steps / t32
     ms_step = 1e3 * t32 / args.steps
     pd_ms, pd_n = kt["push_deposit"]
@@ -166,16 +228,21 @@ def main():
                    "filter_frac": d["alpha"], "deposit_accumulator": "int64 fixed point",
                    "parallelism": "single GPU"},
         "kernels": kernels,
+        "tiling": tiling,
         "roofline": {"bound": "hbm", "kernel": "push_deposit", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(), "alg_bytes_per_launch": alg_bytes,
-                     "source_hash": source_hash()},
+                     "source_hash": source_hash(),
+                     "timing": "HIP events around each launch in a profiled pass of %d steps "
+                               "(%.4f ms/step with the events)" % (args.steps,
+                                                                     1e3 * profiled_wall / args.steps)},
     }
 
     if args.fp64_steps < 0:
         args.fp64_steps = args.steps
     if args.fp64_steps > 0:
-        sim64, t64, _ = run_form(hpic, torch, d, "fp64", args.warmup, args.fp64_steps)
+        sim64, t64, _ = run_form(hpic, torch, [d], "fp64", args.warmup, args.fp64_steps,
+                                 tune_steps=args.tune_steps)
         sim64.close()
         out["fp64_form"] = {"value": npart * args.fp64_steps / t64,
                             "ms_per_step": 1e3 * t64 / args.fp64_steps,
@@ -196,6 +263,8 @@ def main():
                               "gauss_rel_l2_fp32": da["gauss_l2"] / max(da["gauss_ref_l2"], 1e-300)}
         a.close()
         b.close()
+    if args.scan_steps > 0:
+        out["scan2d"] = scan_leg(hpic, torch, W, args.scan_steps, args.tune_steps)
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
         x = torch.ones(n, dtype=torch.float32, device="cuda")

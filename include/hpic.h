@@ -75,7 +75,8 @@ typedef struct hp_config {
   int32_t correct;           /* 1: current correction of Eq. (11); 0 only for tests */
   int32_t n_modes;           /* azimuthal modes (quasi-3D; unused in 2D) */
   int32_t precision;         /* HP_PREC_FP32_FIXED or HP_PREC_FP64; same for all runs */
-  int32_t fixed_shape_bits;  /* P: shape factors quantised to 2^-P; 0 = 20 */
+  int32_t fixed_shape_bits;  /* P: shape factors quantised to 2^-P; 0 = automatic:
+                                22 if all particle charges are equal, else 20 */
   int32_t fixed_weight_bits; /* Q: charges quantised to 2^-Q of the largest;
                                 0 = automatic (exact for equal weights, else the
                                 largest Q <= 15 the headroom allows) */
@@ -134,6 +135,31 @@ int hp_set_background(hp_sim *sim, int32_t run, int32_t rho_from_particles,
  * Kernel-detected errors (HP_ERANGE, HP_ENUMERIC) are reported by the next
  * synchronous call. */
 int hp_step(hp_sim *sim, int32_t nsteps);
+
+/* Particle tiling of a handle (all runs): the tile shape of the sort and of
+ * the push+deposit workgroups, the sort interval, and the LDS budget of one
+ * push workgroup derived from the tile shape. */
+typedef struct hp_tune {
+  int32_t tile[2];        /* cells per tile along x1, x2 (clipped to each grid) */
+  int32_t sort_interval;  /* steps between particle sorts */
+  int32_t lds_bytes;      /* LDS of one push+deposit workgroup */
+  double ms_per_step;     /* hp_autotune: measured time per step of the choice */
+  int32_t candidates;     /* hp_autotune: settings timed */
+  int32_t steps;          /* hp_autotune: steps advanced */
+} hp_tune;
+
+/* Sets the tile shape (1..4096 cells per direction) and sort interval
+ * (1..1024 steps) and re-sorts the particles.  Results of the FP32_FIXED form
+ * are bit-identical for every setting.  HP_EINVAL out of range. */
+int hp_set_tiling(hp_sim *sim, int32_t tile1, int32_t tile2, int32_t sort_interval);
+int hp_get_tiling(hp_sim *sim, hp_tune *out);
+
+/* Autotuner: advances every run by exactly nsteps steps (as hp_step) while
+ * timing candidate tile shapes and then sort intervals on the live runs, each
+ * over two sort blocks, and keeps the fastest (also for later hp_step calls).
+ * With too few steps the remaining candidates are skipped.  Synchronous.
+ * out may be NULL. */
+int hp_autotune(hp_sim *sim, int32_t nsteps, hp_tune *out);
 
 /* With enable = 1 (the default) hp_step replays each block of one particle
  * sort and sort_interval steps as a captured HIP graph (when sort_interval is

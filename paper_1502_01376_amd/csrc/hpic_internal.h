@@ -42,7 +42,10 @@ struct Parts {
 //        the cells of each tile's particles (they drift out of the tile
 //        between sorts)
 //   F:   real-space fields [6][n2][n1] (E1 E2 E3 B1 B2 B3) for the gather
-//   Fk:  k-space master copy [6][n2][nk] (ping-pong, index = step parity)
+//   Fk:  k-space master copy [6][n2][nk] in FP64 for both forms (ping-pong,
+//        index = step parity): the state that carries the field from step to
+//        step, so its rounding does not accumulate into a phase drift
+//        (FP32 storage of a mode rotated 1000 times drifts by ~1e-5)
 //   J:   deposit accumulators [3][n2][n1] (ping-pong, index = step parity)
 //   Jk:  corrected, filtered current [3][n2][nk]
 template <class R>
@@ -67,11 +70,12 @@ struct Run {
   int *tile_box;     // [ntiles][4]: lo1, hi1, lo2, hi2 of the tile's particle cells
                      // relative to the tile origin (updated by every push)
   R *F;
-  C *Fk[2];
+  double2 *Fk[2];
   Acc *J[2];
   C *Jk;
   const C *tw;       // [n1]: exp(-2 pi i m / n1)
-  const R *sym;      // [nk][4]: i k1 xi+ (re, im), i k1 xi- (re, im)
+  const double *sym; // [nk][4]: i k1 xi+ (re, im), i k1 xi- (re, im)
+  double mdt, mhdt, midx2;  // dt, dt/2, 1/dx2 of the FP64 field update
   const R *jfac;     // [nk][3]: factor on the transformed accumulator per component
 };
 
@@ -85,6 +89,13 @@ template <class C> __device__ __forceinline__ C cmul(C a, C b) {
 }
 template <class C> __device__ __forceinline__ C cconj(C a) { return cmk(a.x, -a.y); }
 template <class C, class R> __device__ __forceinline__ C cscale(C a, R s) { return cmk(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 to_d2(float2 a) { return make_double2(a.x, a.y); }
+__device__ __forceinline__ double2 to_d2(double2 a) { return a; }
+template <class C> __device__ __forceinline__ C from_d2(double2 a);
+template <> __device__ __forceinline__ float2 from_d2<float2>(double2 a) {
+  return make_float2((float)a.x, (float)a.y);
+}
+template <> __device__ __forceinline__ double2 from_d2<double2>(double2 a) { return a; }
 // multiply by +i (inv = true) or -i
 template <class C> __device__ __forceinline__ C cmuli(C a, bool plus) {
   return plus ? cmk(-a.y, a.x) : cmk(a.y, -a.x);
@@ -211,22 +222,28 @@ enum : unsigned { ERR_RANGE = 1u, ERR_NUMERIC = 2u };
 // memory (bounding box too large for LDS), [1] tiles processed.
 enum { STAT_FALLBACK = 0, STAT_TILES = 1, NSTAT = 2 };
 
-// LDS budget of one push+deposit workgroup: staged fields (24 B per node in
-// FP32, 48 B in FP64) and current accumulators (3 x 8 B per node).
+// LDS of one push+deposit workgroup: staged fields (24 B per node in FP32,
+// 48 B in FP64) and current accumulators (3 x 8 B per node).  The budget is
+// set per handle from the tile shape (push_lds_bytes), between the minimum
+// and maximum here.
 constexpr int PUSH_THREADS = 256;
 constexpr int PUSH_BATCH = 4;  // particles loaded per thread before pushing
-constexpr int PUSH_LDS_BYTES = 32768;
+constexpr int PUSH_LDS_MIN = 16384;
+constexpr int PUSH_LDS_MAX = 64512;  // with the static LDS, under 64 KiB
 
 // ---------------------------------------------------------------- launches
 // Host-side launch wrappers (kernels.hip), one instantiation per precision.
 template <class R>
 struct Launch {
   static void push_deposit(const Run<R> *runs, const Item *items, int nitems, int parity,
-                           int pp, unsigned *err, unsigned *stats, hipStream_t s);
+                           int pp, int lds_bytes, unsigned *err, unsigned *stats,
+                           hipStream_t s);
   // tile sort of the particles of all runs: items are (run, first particle,
-  // count) chunks; tiles lists (run, 0, 0) once per run
+  // count) chunks; per_run lists (run, 0, 0) once per run.  scramble = true
+  // spreads the particles of one cell over a tile's slots (for input in cell
+  // order); false keeps the arrival order, so the scatter writes are coalesced
   static void sort(const Run<R> *runs, const Item *chunks, int nchunks, const Item *per_run,
-                   int nruns, int pp, hipStream_t s);
+                   int nruns, int pp, bool scramble, hipStream_t s);
   static void fft_j(const Run<R> *runs, const Item *items, int nitems, int parity, int maxM,
                     hipStream_t s);
   static void kupdate(const Run<R> *runs, const Item *items, int nitems, int parity,

@@ -469,7 +469,7 @@ __device__ __forceinline__ int wave_max(int v) {
 template <class R>
 __global__ void __launch_bounds__(PUSH_THREADS)
 k_push_deposit(const Run<R> *__restrict__ runs, const Item *__restrict__ items, int parity, int pp,
-               unsigned *err, unsigned *stats) {
+               int lds_bytes, unsigned *err, unsigned *stats) {
   using T2 = typename V2<R>::T;
   using SK = Sinks<R>;
   extern __shared__ unsigned char smem_raw[];
@@ -502,7 +502,7 @@ k_push_deposit(const Run<R> *__restrict__ runs, const Item *__restrict__ items, 
     blo1 = min(blo1, d1); bhi1 = max(bhi1, d1);
     blo2 = min(blo2, d2); bhi2 = max(bhi2, d2);
   };
-  if (need > (size_t)PUSH_LDS_BYTES) {
+  if (need > (size_t)lds_bytes) {
     // fallback: gather and deposit in global memory
     if (threadIdx.x == 0) atomicAdd(&stats[STAT_FALLBACK], 1u);
     const GlobalFields<R> S{G((const R *)r.F), n1, n2, cells};
@@ -675,13 +675,16 @@ __global__ void __launch_bounds__(1024) k_sort_scan(const Run<R> *runs, const It
   if (threadIdx.x == 1023) r.tile_start[nt] = part[1023];
 }
 
-// Scatter: a particle's rank within its tile (arrival order) is scrambled by
-// multiplication with a prime larger than any tile count, modulo the count (a
+// Scatter.  With `scramble`, a particle's rank within its tile (arrival order)
+// is multiplied by a prime larger than any tile count, modulo the count (a
 // bijection), so that consecutive slots of a tile hold particles from scattered
 // cells: the lanes of a push wave then rarely hit the same LDS accumulator.
+// That is needed once, for input in cell order; later sorts keep the arrival
+// order (already mixed), so lanes of one wave with the same tile write
+// consecutive slots.
 constexpr long long SCRAMBLE = 1048573;  // prime, > any particle count per tile
 template <class R>
-__global__ void k_sort_scatter(const Run<R> *runs, const Item *chunks, int pp) {
+__global__ void k_sort_scatter(const Run<R> *runs, const Item *chunks, int pp, int scramble) {
   const Item it = chunks[blockIdx.x];
   const Run<R> &r = runs[it.run];
   const bool active = threadIdx.x < (unsigned)it.b;
@@ -694,7 +697,8 @@ __global__ void k_sort_scatter(const Run<R> *runs, const Item *chunks, int pp) {
   if (!active) return;
   const int t0 = r.tile_start[t], cnt = r.tile_start[t + 1] - t0;
   const int rank = q - t0;
-  const int slot = t0 + ((cnt % SCRAMBLE) ? (int)(((long long)rank * SCRAMBLE) % cnt) : rank);
+  const int slot =
+      t0 + ((scramble && (cnt % SCRAMBLE)) ? (int)(((long long)rank * SCRAMBLE) % cnt) : rank);
   B.cell[slot] = c;
   B.id[slot] = A.id[p];
   B.f1[slot] = A.f1[p];
@@ -794,20 +798,21 @@ __global__ void k_kinetic(const Run<R> *run, int pp, double *partial) {
 // ---------------------------------------------------------------- launches
 template <class R>
 void Launch<R>::push_deposit(const Run<R> *runs, const Item *items, int nitems, int parity, int pp,
-                             unsigned *err, unsigned *stats, hipStream_t s) {
+                             int lds_bytes, unsigned *err, unsigned *stats, hipStream_t s) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_push_deposit<R>, dim3(nitems), dim3(PUSH_THREADS), PUSH_LDS_BYTES, s, runs,
-                     items, parity, pp, err, stats);
+  hipLaunchKernelGGL(k_push_deposit<R>, dim3(nitems), dim3(PUSH_THREADS), lds_bytes, s, runs,
+                     items, parity, pp, lds_bytes, err, stats);
 }
 
 template <class R>
 void Launch<R>::sort(const Run<R> *runs, const Item *chunks, int nchunks, const Item *per_run,
-                     int nruns, int pp, hipStream_t s) {
+                     int nruns, int pp, bool scramble, hipStream_t s) {
   if (nchunks <= 0) return;
   hipLaunchKernelGGL(k_sort_clear<R>, dim3(nruns), dim3(256), 0, s, runs, per_run);
   hipLaunchKernelGGL(k_sort_count<R>, dim3(nchunks), dim3(256), 0, s, runs, chunks, pp);
   hipLaunchKernelGGL(k_sort_scan<R>, dim3(nruns), dim3(1024), 0, s, runs, per_run);
-  hipLaunchKernelGGL(k_sort_scatter<R>, dim3(nchunks), dim3(256), 0, s, runs, chunks, pp);
+  hipLaunchKernelGGL(k_sort_scatter<R>, dim3(nchunks), dim3(256), 0, s, runs, chunks, pp,
+                     scramble ? 1 : 0);
 }
 
 template struct Launch<float>;

@@ -58,7 +58,8 @@ double courant_limit(const hp_config &c) {
 
 const int SORT_CHUNK = 256;   // particles per sort workgroup
 const int UPD_BLOCK = 256;    // (i2, kappa) elements per update workgroup
-const int TILE1 = 32, TILE2 = 8;  // particle tile (cells along x1, x2)
+const int TILE1 = 32, TILE2 = 8;  // default particle tile (cells along x1, x2)
+const int SLACK1 = 2, SLACK2 = 1;  // drift beyond the tile the LDS budget allows for
 const int DEFAULT_SORT_INTERVAL = 16;
 
 struct Event2 {
@@ -96,6 +97,9 @@ struct SimBase {
   virtual int kernel_times(double *ms, int64_t *n) = 0;
   virtual int push_stats(int64_t *out) = 0;
   virtual int use_graphs(int enable) = 0;
+  virtual int set_tiling(int t1, int t2, int K) = 0;
+  virtual int get_tiling(hp_tune *out) = 0;
+  virtual int autotune(int nsteps, hp_tune *out) = 0;
 };
 
 struct hp_sim {
@@ -145,7 +149,7 @@ class Sim : public SimBase {
     allocs_.push_back(d_err_);
     HIPCHK(hipMemset(d_err_, 0, sizeof(unsigned)));
     runs_.resize(nruns);
-    std::vector<Item> rows, grps, upd, tiles, perrun;
+    std::vector<Item> rows, grps, upd, perrun;
     for (int i = 0; i < nruns; ++i) {
       RunHost &h = runs_[i];
       h.cfg = cfgs[i];
@@ -171,7 +175,7 @@ class Sim : public SimBase {
       const size_t cells = (size_t)d.n1 * d.n2, kpl = (size_t)d.n2 * d.nk;
       int rc;
       if ((rc = alloc(&d.F, 6 * cells))) return rc;
-      if ((rc = alloc(&d.Fk[0], 6 * kpl))) return rc;
+      if ((rc = alloc(&d.Fk[0], 6 * kpl))) return rc;  // FP64 master (both forms)
       if ((rc = alloc(&d.Fk[1], 6 * kpl))) return rc;
       if ((rc = alloc(&d.J[0], 3 * cells))) return rc;
       if ((rc = alloc(&d.J[1], 3 * cells))) return rc;
@@ -185,7 +189,6 @@ class Sim : public SimBase {
         tw[m].y = (R)std::sin(a);
         tw64[m] = make_double2(std::cos(a), std::sin(a));
       }
-      std::vector<R> sym(4 * d.nk);
       std::vector<double> sym64(4 * d.nk), filt64(d.nk);
       for (int k = 0; k < d.nk; ++k) {
         const double k1 = 2.0 * PI * k / (d.n1 * c.dx[0]);
@@ -193,25 +196,23 @@ class Sim : public SimBase {
         const double kk = c.deriv1 ? std::sin(hh) / (0.5 * c.dx[0]) : k1;
         const double v[4] = {-kk * std::sin(hh), kk * std::cos(hh), kk * std::sin(hh),
                              kk * std::cos(hh)};  // i kk exp(+ih), i kk exp(-ih)
-        for (int j = 0; j < 4; ++j) {
-          sym[4 * k + j] = (R)v[j];
-          sym64[4 * k + j] = v[j];
-        }
+        for (int j = 0; j < 4; ++j) sym64[4 * k + j] = v[j];
         filt64[k] = (k <= c.filter_frac * 0.5 * d.n1) ? 1.0 : 0.0;
       }
       C *dtw;
-      R *dsym, *djfac;
-      if ((rc = alloc(&dtw, d.n1)) || (rc = alloc(&dsym, 4 * d.nk)) ||
-          (rc = alloc(&djfac, 3 * d.nk)) || (rc = alloc(&h.tw64, d.n1)) ||
+      R *djfac;
+      if ((rc = alloc(&dtw, d.n1)) || (rc = alloc(&djfac, 3 * d.nk)) || (rc = alloc(&h.tw64, d.n1)) ||
           (rc = alloc(&h.sym64, 4 * d.nk)) || (rc = alloc(&h.filt64, d.nk)))
         return rc;
       HIPCHK(hipMemcpy(dtw, tw.data(), sizeof(C) * d.n1, hipMemcpyHostToDevice));
-      HIPCHK(hipMemcpy(dsym, sym.data(), sizeof(R) * 4 * d.nk, hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(h.tw64, tw64.data(), sizeof(double2) * d.n1, hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(h.sym64, sym64.data(), sizeof(double) * 4 * d.nk, hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(h.filt64, filt64.data(), sizeof(double) * d.nk, hipMemcpyHostToDevice));
       d.tw = dtw;
-      d.sym = dsym;
+      d.sym = h.sym64;
+      d.mdt = c.dt;
+      d.mhdt = 0.5 * c.dt;
+      d.midx2 = 1.0 / c.dx[1];
       d.jfac = djfac;
       if ((rc = upload_jfac(i))) return rc;
       h.row0 = (int)rows.size();
@@ -223,22 +224,13 @@ class Sim : public SimBase {
       }
       const int nel = d.n2 * d.nk;
       for (int e = 0; e < nel; e += UPD_BLOCK) upd.push_back(Item{i, e, 0});
-      d.T1 = std::min(TILE1, d.n1);
-      d.T2 = std::min(TILE2, d.n2);
-      d.nt1 = (d.n1 + d.T1 - 1) / d.T1;
-      d.nt2 = (d.n2 + d.T2 - 1) / d.T2;
-      d.ntiles = d.nt1 * d.nt2;
-      if ((rc = alloc(&d.tile_start, d.ntiles + 1)) || (rc = alloc(&d.tile_cnt, d.ntiles)) ||
-          (rc = alloc(&d.tile_box, 4 * d.ntiles)))
-        return rc;
-      for (int t = 0; t < d.ntiles; ++t) tiles.push_back(Item{i, t, 0});
       perrun.push_back(Item{i, 0, 0});
     }
     for (int i = 0; i < nruns; ++i)
       if (cfgs[i].sort_interval > 0) sort_interval_ = cfgs[i].sort_interval;
     int rc;
     if ((rc = alloc(&d_stats_, NSTAT))) return rc;
-    if ((rc = upload_items(tiles, &d_tiles_, &n_tiles_))) return rc;
+    if ((rc = make_tiles(TILE1, TILE2))) return rc;
     if ((rc = upload_items(perrun, &d_perrun_, &n_perrun_))) return rc;
     if ((rc = alloc(&d_runs_, nruns))) return rc;
     if ((rc = upload_items(rows, &d_rows_, &n_rows_))) return rc;
@@ -289,9 +281,16 @@ class Sim : public SimBase {
     if (FIXED && n > 0) {
       if (!(qmax > 0.0)) return fail(HP_EINVAL, "all particle charges are zero");
       const int cmax = *std::max_element(count.begin(), count.end());
-      const int P = d.P;
       // per node |J| <= 24 * (particles per cell) * 2^(2P+Q): keep below 2^62
-      const double room = std::ldexp(1.0, 62 - 2 * P) / (24.0 * std::max(cmax, 1));
+      auto room_for = [&](int P) {
+        return std::ldexp(1.0, 62 - 2 * P) / (24.0 * std::max(cmax, 1));
+      };
+      // automatic shape bits: 22 when all charges are equal (no charge bits
+      // needed, products still fit 24 bits), else 20
+      if (h.cfg.fixed_shape_bits <= 0)
+        d.P = (qmin == qmax && h.cfg.fixed_weight_bits <= 0 && room_for(22) >= 1.0) ? 22 : 20;
+      const int P = d.P;
+      const double room = room_for(P);
       int Q;
       if (h.cfg.fixed_weight_bits > 0) {
         Q = h.cfg.fixed_weight_bits;
@@ -365,13 +364,15 @@ class Sim : public SimBase {
     const int p = parity_;
     if (sort_interval_ > 0 && since_sort_ >= sort_interval_) {
       mark(HP_K_SORT, true);
-      Launch<R>::sort(d_runs_, d_chunks_, n_chunks_, d_perrun_, (int)runs_.size(), pp_, stream_);
+      Launch<R>::sort(d_runs_, d_chunks_, n_chunks_, d_perrun_, (int)runs_.size(), pp_, false,
+                      stream_);
       mark(HP_K_SORT, false);
       if (n_chunks_ > 0) pp_ ^= 1;
       since_sort_ = 0;
     }
     mark(HP_K_PUSH_DEPOSIT, true);
-    Launch<R>::push_deposit(d_runs_, d_tiles_, n_tiles_, p, pp_, d_err_, d_stats_, stream_);
+    Launch<R>::push_deposit(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, d_err_, d_stats_,
+                            stream_);
     mark(HP_K_PUSH_DEPOSIT, false);
     ++since_sort_;
     mark(HP_K_FFT_J, true);
@@ -452,6 +453,94 @@ class Sim : public SimBase {
       }
     }
     HIPCHK(hipGetLastError());
+    return HP_OK;
+  }
+
+  int set_tiling(int t1, int t2, int K) override {
+    if (t1 < 1 || t1 > 4096 || t2 < 1 || t2 > 4096 || K < 1 || K > 1024)
+      return fail(HP_EINVAL, "tiling %d x %d, sort interval %d out of range", t1, t2, K);
+    int rc;
+    if ((rc = sync())) return rc;
+    if ((rc = make_tiles(t1, t2)) || (rc = upload_runs())) return rc;
+    sort_interval_ = K;
+    return sort_now();
+  }
+
+  int get_tiling(hp_tune *out) override {
+    out->tile[0] = tile1_;
+    out->tile[1] = tile2_;
+    out->sort_interval = sort_interval_;
+    out->lds_bytes = push_lds_;
+    out->ms_per_step = tuned_ms_;
+    out->candidates = 0;
+    out->steps = 0;
+    return HP_OK;
+  }
+
+  // Advances every run by nsteps while timing tile shapes, then sort
+  // intervals, on the live simulation; keeps the fastest.  The FP32 form's
+  // results do not depend on either (integer deposit), so no step is wasted.
+  int autotune(int nsteps, hp_tune *out) override {
+    if (nsteps < 0) return fail(HP_EINVAL, "negative step count");
+    int rc;
+    if ((rc = sync())) return rc;
+    hipEvent_t ea, eb;
+    HIPCHK(hipEventCreate(&ea));
+    HIPCHK(hipEventCreate(&eb));
+    int left = nsteps, tried = 0;
+    auto trial = [&](int t1, int t2, int K, double *ms) -> int {
+      int rc2;
+      if ((rc2 = set_tiling(t1, t2, K))) return rc2;
+      since_sort_ = K;  // the timed block starts with a sort, as in steady state
+      const int len = 2 * K;
+      HIPCHK(hipEventRecord(ea, stream_));
+      if ((rc2 = step(len))) return rc2;
+      HIPCHK(hipEventRecord(eb, stream_));
+      HIPCHK(hipEventSynchronize(eb));
+      float t = 0;
+      HIPCHK(hipEventElapsedTime(&t, ea, eb));
+      if ((rc2 = sync())) return rc2;
+      *ms = t / len;
+      left -= len;
+      ++tried;
+      return HP_OK;
+    };
+    int best1 = tile1_, best2 = tile2_, bestK = sort_interval_ > 0 ? sort_interval_ : 16;
+    double best = INFINITY;
+    const int shapes[][2] = {{32, 8}, {64, 4}, {16, 16}, {64, 8}, {32, 16}, {128, 4}, {16, 8}, {128, 2}};
+    std::vector<std::vector<int>> seen;
+    const int K0 = bestK;
+    for (const auto &sh : shapes) {
+      std::vector<int> key;
+      for (const RunHost &h : runs_) {
+        key.push_back(std::min(sh[0], h.d.n1));
+        key.push_back(std::min(sh[1], h.d.n2));
+      }
+      if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+      seen.push_back(key);
+      if (left < 2 * K0) break;
+      double ms;
+      if ((rc = trial(sh[0], sh[1], K0, &ms))) break;
+      if (ms < best) { best = ms; best1 = sh[0]; best2 = sh[1]; }
+    }
+    for (int K : {8, 16, 32, 64, 128}) {
+      if (rc || K == K0) continue;
+      if (left < 2 * K) break;
+      double ms;
+      if ((rc = trial(best1, best2, K, &ms))) break;
+      if (ms < best) { best = ms; bestK = K; }
+    }
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    if (rc) return rc;
+    if ((rc = set_tiling(best1, best2, bestK))) return rc;
+    tuned_ms_ = std::isfinite(best) ? best : 0.0;
+    if (left > 0 && (rc = step(left))) return rc;
+    if (out) {
+      get_tiling(out);
+      out->candidates = tried;
+      out->steps = nsteps;
+    }
     return HP_OK;
   }
 
@@ -702,7 +791,7 @@ class Sim : public SimBase {
       std::memcpy(o, src, bytes);
       o += bytes;
     };
-    const int64_t hdr[6] = {0x48504943, 1, (int64_t)runs_.size(), FIXED ? 0 : 1, step_, parity_};
+    const int64_t hdr[6] = {0x48504943, 2, (int64_t)runs_.size(), FIXED ? 0 : 1, step_, parity_};
     put(hdr, sizeof hdr);
     for (RunHost &h : runs_) {
       Run<R> &d = h.d;
@@ -718,7 +807,7 @@ class Sim : public SimBase {
       R *arrs[6] = {A.f1, A.f2, A.u1, A.u2, A.u3, A.qw};
       for (R *a : arrs) { if ((rc = d2h((R *)o, a, n))) return rc; o += sizeof(R) * n; }
       if ((rc = d2h((R *)o, d.F, 6 * cells))) return rc; o += sizeof(R) * 6 * cells;
-      if ((rc = d2h((C *)o, d.Fk[parity_], 6 * kpl))) return rc; o += sizeof(C) * 6 * kpl;
+      if ((rc = d2h((double2 *)o, d.Fk[parity_], 6 * kpl))) return rc; o += sizeof(double2) * 6 * kpl;
       if ((rc = d2h((Acc *)o, d.J[parity_ ^ 1], 3 * cells))) return rc; o += sizeof(Acc) * 3 * cells;
       if ((rc = d2h((C *)o, d.Jk, 3 * kpl))) return rc; o += sizeof(C) * 3 * kpl;
       if (h.rho0) { if ((rc = d2h((Acc *)o, h.rho0, cells))) return rc; o += sizeof(Acc) * cells; }
@@ -737,7 +826,7 @@ class Sim : public SimBase {
       return true;
     };
     int64_t hdr[6];
-    if (!take(hdr, sizeof hdr) || hdr[0] != 0x48504943 || hdr[1] != 1 ||
+    if (!take(hdr, sizeof hdr) || hdr[0] != 0x48504943 || hdr[1] != 2 ||
         hdr[2] != (int64_t)runs_.size() || hdr[3] != (FIXED ? 0 : 1))
       return fail(HP_EINVAL, "state blob does not match this handle");
     int rc;
@@ -752,7 +841,8 @@ class Sim : public SimBase {
       if (!take(meta, sizeof meta)) return fail(HP_EINVAL, "truncated state");
       const int64_t n = (int64_t)meta[0];
       const size_t pbytes = n * (2 * sizeof(int) + 6 * sizeof(R));
-      const size_t fbytes = sizeof(R) * 6 * cells + sizeof(C) * 9 * kpl + sizeof(Acc) * 3 * cells +
+      const size_t fbytes = sizeof(R) * 6 * cells + sizeof(double2) * 6 * kpl +
+                            sizeof(C) * 3 * kpl + sizeof(Acc) * 3 * cells +
                             (meta[9] != 0 ? sizeof(Acc) * cells : 0);
       if (o + pbytes + fbytes > end) return fail(HP_EINVAL, "truncated state");
       h.qm = meta[1];
@@ -774,7 +864,7 @@ class Sim : public SimBase {
       R *arrs[6] = {A.f1, A.f2, A.u1, A.u2, A.u3, A.qw};
       for (R *a : arrs) { if ((rc = h2d(a, (const R *)o, n))) return rc; o += sizeof(R) * n; }
       if ((rc = h2d(d.F, (const R *)o, 6 * cells))) return rc; o += sizeof(R) * 6 * cells;
-      if ((rc = h2d(d.Fk[parity_], (const C *)o, 6 * kpl))) return rc; o += sizeof(C) * 6 * kpl;
+      if ((rc = h2d(d.Fk[parity_], (const double2 *)o, 6 * kpl))) return rc; o += sizeof(double2) * 6 * kpl;
       if ((rc = h2d(d.J[parity_ ^ 1], (const Acc *)o, 3 * cells))) return rc; o += sizeof(Acc) * 3 * cells;
       HIPCHK(hipMemsetAsync(d.J[parity_], 0, sizeof(Acc) * 3 * cells, stream_));
       if ((rc = h2d(d.Jk, (const C *)o, 3 * kpl))) return rc; o += sizeof(C) * 3 * kpl;
@@ -935,6 +1025,46 @@ class Sim : public SimBase {
     return h2d(d_runs_, v.data(), v.size());
   }
   // Sort chunks: (run, first particle, count <= SORT_CHUNK) over all particles.
+  // Particle tiles of every run (t1 x t2 cells, clipped to the grid), the
+  // push work list and the push LDS budget; the caller uploads the runs and
+  // re-sorts.
+  int make_tiles(int t1, int t2) {
+    drop_graphs();
+    std::vector<Item> tiles;
+    int maxbox = 0;
+    for (int i = 0; i < (int)runs_.size(); ++i) {
+      Run<R> &d = runs_[i].d;
+      int **arrs[3] = {&d.tile_start, &d.tile_cnt, &d.tile_box};
+      for (int **a : arrs)
+        if (*a) {
+          release(*a);
+          *a = nullptr;
+        }
+      d.T1 = std::min(t1, d.n1);
+      d.T2 = std::min(t2, d.n2);
+      d.nt1 = (d.n1 + d.T1 - 1) / d.T1;
+      d.nt2 = (d.n2 + d.T2 - 1) / d.T2;
+      d.ntiles = d.nt1 * d.nt2;
+      int rc;
+      if ((rc = alloc(&d.tile_start, d.ntiles + 1)) || (rc = alloc(&d.tile_cnt, d.ntiles)) ||
+          (rc = alloc(&d.tile_box, 4 * d.ntiles)))
+        return rc;
+      for (int t = 0; t < d.ntiles; ++t) tiles.push_back(Item{i, t, 0});
+      // staged box of a tile whose particles spread SLACK cells beyond it
+      const int b1 = std::min(d.T1 + 2 * SLACK1, d.n1) + 6;
+      const int b2 = std::min(d.T2 + 2 * SLACK2, d.n2) + 6;
+      maxbox = std::max(maxbox, b1 * b2);
+    }
+    tile1_ = t1;
+    tile2_ = t2;
+    const int node_bytes = FIXED ? 48 : 72;
+    push_lds_ = std::min(PUSH_LDS_MAX, std::max(PUSH_LDS_MIN, ((maxbox * node_bytes + 1023) / 1024) * 1024));
+    if (d_tiles_) release(d_tiles_);
+    d_tiles_ = nullptr;
+    n_tiles_ = 0;
+    return tiles.empty() ? HP_OK : upload_items(tiles, &d_tiles_, &n_tiles_);
+  }
+
   int rebuild_sort_items() {
     drop_graphs();  // captured launches hold the old item lists and counts
     std::vector<Item> items;
@@ -965,7 +1095,8 @@ class Sim : public SimBase {
   }
   // Sort the particles of every run by tile now (into the other buffer).
   int sort_now() {
-    Launch<R>::sort(d_runs_, d_chunks_, n_chunks_, d_perrun_, (int)runs_.size(), pp_, stream_);
+    Launch<R>::sort(d_runs_, d_chunks_, n_chunks_, d_perrun_, (int)runs_.size(), pp_, true,
+                    stream_);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream_));
     if (n_chunks_ > 0) pp_ ^= 1;
@@ -1018,7 +1149,8 @@ class Sim : public SimBase {
     for (const RunHost &h : runs_) {
       const size_t cells = (size_t)h.d.n1 * h.d.n2, kpl = (size_t)h.d.n2 * h.d.nk;
       s += 12 * sizeof(double) + h.np * (2 * sizeof(int) + 6 * sizeof(R)) + sizeof(R) * 6 * cells +
-           sizeof(C) * 9 * kpl + sizeof(Acc) * 3 * cells + (h.rho0 ? sizeof(Acc) * cells : 0);
+           sizeof(double2) * 6 * kpl + sizeof(C) * 3 * kpl + sizeof(Acc) * 3 * cells +
+           (h.rho0 ? sizeof(Acc) * cells : 0);
     }
     return s;
   }
@@ -1064,6 +1196,8 @@ class Sim : public SimBase {
   int n_perrun_ = 0;
   int sort_interval_ = DEFAULT_SORT_INTERVAL, since_sort_ = 0;
   unsigned *d_stats_ = nullptr;
+  int tile1_ = TILE1, tile2_ = TILE2, push_lds_ = PUSH_LDS_MIN;
+  double tuned_ms_ = 0.0;
   bool use_graphs_ = true;
   hipGraphExec_t graph_[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   hipStream_t capture_stream_ = nullptr;
@@ -1274,6 +1408,23 @@ int hp_profile(hp_sim *sim, int32_t enable) {
 int hp_get_kernel_times(hp_sim *sim, double *ms, int64_t *n) {
   int rc = check_sim(sim);
   return rc ? rc : sim->impl->kernel_times(ms, n);
+}
+
+int hp_set_tiling(hp_sim *sim, int32_t tile1, int32_t tile2, int32_t sort_interval) {
+  int rc = check_sim(sim);
+  return rc ? rc : sim->impl->set_tiling(tile1, tile2, sort_interval);
+}
+
+int hp_get_tiling(hp_sim *sim, hp_tune *out) {
+  int rc = check_sim(sim);
+  if (rc) return rc;
+  if (!out) return fail(HP_EINVAL, "null output");
+  return sim->impl->get_tiling(out);
+}
+
+int hp_autotune(hp_sim *sim, int32_t nsteps, hp_tune *out) {
+  int rc = check_sim(sim);
+  return rc ? rc : sim->impl->autotune(nsteps, out);
 }
 
 int hp_use_graphs(hp_sim *sim, int32_t enable) {

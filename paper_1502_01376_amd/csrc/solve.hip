@@ -109,9 +109,9 @@ __global__ void __launch_bounds__(256) k_fields_to_k(const Run<R> *__restrict__ 
     for (int c = 0; c < 3; ++c) {
       const C Zk = lds[c * M + k];
       const C Zmk = lds[c * M + (mk & (M - 1))];
-      C *out = r.Fk[parity] + (long long)(3 * grp + c) * r.n2 * nk + (long long)row * nk;
-      out[k] = r2c_post(Zk, Zmk, r.tw[k]);
-      if (mk != k) out[mk] = r2c_post(Zmk, Zk, r.tw[mk]);
+      double2 *out = r.Fk[parity] + (long long)(3 * grp + c) * r.n2 * nk + (long long)row * nk;
+      out[k] = to_d2(r2c_post(Zk, Zmk, r.tw[k]));
+      if (mk != k) out[mk] = to_d2(r2c_post(Zmk, Zk, r.tw[mk]));
     }
   }
 }
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) k_fields_to_k(const Run<R> *__restrict__ 
 template <class R>
 __global__ void __launch_bounds__(256) k_kupdate(const Run<R> *__restrict__ runs,
                                                  const Item *__restrict__ items, int parity) {
-  using C = typename Cplx<R>::T;
+  using C = double2;
   const Item it = items[blockIdx.x];
   const Run<R> &r = runs[it.run];
   const int nk = r.nk, n2 = r.n2;
@@ -151,13 +151,14 @@ __global__ void __launch_bounds__(256) k_kupdate(const Run<R> *__restrict__ runs
   const C B1m = at(3, rm), B1 = at(3, i2), B1p = at(3, rp);
   const C B2 = at(4, i2), B2p = at(4, rp);
   const C B3m = at(5, rm), B3 = at(5, i2), B3p = at(5, rp);
-  const C *Jk = r.Jk;
-  const C j1 = Jk[(long long)i2 * nk + k], j1p = Jk[(long long)rp * nk + k];
-  const C j2 = Jk[plane + (long long)i2 * nk + k];
-  const C j3 = Jk[2 * plane + (long long)i2 * nk + k], j3p = Jk[2 * plane + (long long)rp * nk + k];
+  const auto *Jk = r.Jk;
+  const C j1 = to_d2(Jk[(long long)i2 * nk + k]), j1p = to_d2(Jk[(long long)rp * nk + k]);
+  const C j2 = to_d2(Jk[plane + (long long)i2 * nk + k]);
+  const C j3 = to_d2(Jk[2 * plane + (long long)i2 * nk + k]);
+  const C j3p = to_d2(Jk[2 * plane + (long long)rp * nk + k]);
   const C dp = cmk(r.sym[4 * k + 0], r.sym[4 * k + 1]);
   const C dm = cmk(r.sym[4 * k + 2], r.sym[4 * k + 3]);
-  const R hdt = r.hdt, dt = r.dt, i2x = r.idx2;
+  const double hdt = r.mhdt, dt = r.mdt, i2x = r.midx2;
   // B^{n+1/2} on rows rm, i2, rp
   auto b1h = [&](C B, C Ea, C Eb) { return csub(B, cscale(csub(Eb, Ea), hdt * i2x)); };
   auto b2h = [&](C B, C E) { return cadd(B, cscale(cmul(dp, E), hdt)); };
@@ -173,7 +174,7 @@ __global__ void __launch_bounds__(256) k_kupdate(const Run<R> *__restrict__ runs
     return cadd(E, cscale(csub(csub(cmul(dm, B2x), cscale(csub(B1b, B1a), i2x)), j), dt));
   };
   const C E1n = e1n(E1, B3h_m, B3h, j1), E1n_p = e1n(E1p, B3h, B3h_p, j1p);
-  const C E2n = cadd(E2, cscale(csub(cscale(cmul(dm, B3h), R(-1)), j2), dt));
+  const C E2n = cadd(E2, cscale(csub(cscale(cmul(dm, B3h), -1.0), j2), dt));
   const C E3n = e3n(E3, B2h, B1h_m, B1h, j3), E3n_p = e3n(E3p, B2h_p, B1h, B1h_p, j3p);
   // B^{n+1} on row i2
   const C B1n = b1h(B1h, E3n, E3n_p);
@@ -206,8 +207,8 @@ __global__ void __launch_bounds__(256) k_ifft_eb(const Run<R> *__restrict__ runs
   for (int k = threadIdx.x; k <= (M >> 1); k += blockDim.x) {
     const int mk = M - k;
     for (int c = 0; c < 3; ++c) {
-      const C *X = r.Fk[parity] + (long long)(3 * grp + c) * r.n2 * nk + (long long)row * nk;
-      const C Xk = X[k], Xmk = X[mk];
+      const double2 *X = r.Fk[parity] + (long long)(3 * grp + c) * r.n2 * nk + (long long)row * nk;
+      const C Xk = from_d2<C>(X[k]), Xmk = from_d2<C>(X[mk]);
       lds[c * M + k] = c2r_pre(Xk, Xmk, r.tw[k]);
       if (k != 0 && mk != k) lds[c * M + mk] = c2r_pre(Xmk, Xk, r.tw[mk]);
     }
@@ -283,7 +284,6 @@ template <class R>
 __global__ void __launch_bounds__(256) k_gauss(const Run<R> *run, int parity, const double *rho,
                                                const double2 *tw64, const double *sym64,
                                                const double *filt, double idx2, double *rows_out) {
-  using C = typename Cplx<R>::T;
   extern __shared__ unsigned char smem_raw[];
   double2 *lds = (double2 *)smem_raw;
   __shared__ double red[256][3];
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(256) k_gauss(const Run<R> *run, int parity, co
   __syncthreads();
   lds_fft<double2, 6>(lds, M, log2M, 1, tw64, 2, false);
   const long long plane = (long long)n2 * nk;
-  const C *Fk = r.Fk[parity];
+  const double2 *Fk = r.Fk[parity];
   const int rm = wrap_small(row - 1, n2);
   double s2 = 0, smax = 0, sref = 0;
   for (int k = threadIdx.x; k <= (M >> 1); k += blockDim.x) {
@@ -305,9 +305,9 @@ __global__ void __launch_bounds__(256) k_gauss(const Run<R> *run, int parity, co
       if (side && mk == k) break;
       const double2 Zk = lds[kk & (M - 1)], Zmk = lds[(M - kk) & (M - 1)];
       const double2 rh = r2c_post(Zk, Zmk, tw64[kk]);
-      const C e1 = Fk[(long long)row * nk + kk];
-      const C e2 = Fk[plane + (long long)row * nk + kk];
-      const C e2m = Fk[plane + (long long)rm * nk + kk];
+      const double2 e1 = Fk[(long long)row * nk + kk];
+      const double2 e2 = Fk[plane + (long long)row * nk + kk];
+      const double2 e2m = Fk[plane + (long long)rm * nk + kk];
       const double2 dm = make_double2(sym64[4 * kk + 2], sym64[4 * kk + 3]);
       const double2 E1 = make_double2(e1.x, e1.y);
       double2 div = cmul(dm, E1);

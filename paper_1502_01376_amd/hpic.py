@@ -25,7 +25,7 @@ ABI = (
     "hp_get_current", "hp_get_current_fixed", "hp_get_particle_count", "hp_get_particles",
     "hp_get_particles_raw", "hp_diagnostics", "hp_get_state", "hp_set_state",
     "hp_debug_deposit", "hp_get_fixed_params", "hp_profile", "hp_get_kernel_times",
-    "hp_get_push_stats", "hp_use_graphs",
+    "hp_get_push_stats", "hp_use_graphs", "hp_set_tiling", "hp_get_tiling", "hp_autotune",
 )
 
 
@@ -44,6 +44,19 @@ class Config(ctypes.Structure):
         ("fixed_shape_bits", ctypes.c_int32), ("fixed_weight_bits", ctypes.c_int32),
         ("sort_interval", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8),
     ]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [
+        ("tile", ctypes.c_int32 * 2), ("sort_interval", ctypes.c_int32),
+        ("lds_bytes", ctypes.c_int32), ("ms_per_step", ctypes.c_double),
+        ("candidates", ctypes.c_int32), ("steps", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return dict(tile=(self.tile[0], self.tile[1]), sort_interval=self.sort_interval,
+                    lds_bytes=self.lds_bytes, ms_per_step=self.ms_per_step,
+                    candidates=self.candidates, steps=self.steps)
 
 
 class Diag(ctypes.Structure):
@@ -91,6 +104,9 @@ def lib():
             "hp_get_kernel_times": [_P, _P, _P],
             "hp_get_push_stats": [_P, _P],
             "hp_use_graphs": [_P, i32],
+            "hp_set_tiling": [_P, i32, i32, i32],
+            "hp_get_tiling": [_P, _P],
+            "hp_autotune": [_P, i32, _P],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -181,6 +197,19 @@ class Sim:
 
     def step(self, n=1):
         _check(lib().hp_step(self.h, int(n)))
+
+    def set_tiling(self, tile1, tile2, sort_interval):
+        _check(lib().hp_set_tiling(self.h, int(tile1), int(tile2), int(sort_interval)))
+
+    def tiling(self):
+        t = Tune()
+        _check(lib().hp_get_tiling(self.h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def autotune(self, nsteps):
+        t = Tune()
+        _check(lib().hp_autotune(self.h, int(nsteps), ctypes.byref(t)))
+        return t.as_dict()
 
     def use_graphs(self, enable=True):
         _check(lib().hp_use_graphs(self.h, int(bool(enable))))

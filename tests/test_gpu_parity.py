@@ -207,6 +207,48 @@ def test_vacuum_dispersion_gpu(hpic, prec, tol, deriv1):
     sim.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("fp64", 1e-10)])
+def test_vacuum_eigenmode_1000_steps(hpic, prec, tol):
+    """One discrete eigenmode carried 1000 steps: the phase follows the closed
+    form (Eqs. (10), (19)) to FP32 rounding of the real-space output, i.e. the
+    FP32 form does not accumulate a phase drift."""
+    n1, n2, dx1, dx2, dt = 256, 16, 0.1, 0.2, 0.045
+    sim = hpic.Sim([hpic.config(n1, n2, dx1, dx2, dt, alpha=1.0, precision=prec)])
+    k1i, k2i = 41, 1
+    k1 = 2 * np.pi * k1i / (n1 * dx1)
+    kk2 = np.sin(np.pi * k2i / n2) / (dx2 / 2)
+    theta = 2 * np.arcsin(0.5 * dt * np.hypot(k1, kk2))
+    X1, X2 = np.meshgrid(np.arange(n1), np.arange(n2))
+    E = np.zeros((3, n2, n1))
+    E[2] = np.cos(2 * np.pi * (k1i * X1 / n1 + k2i * X2 / n2))
+    sim.set_fields(0, E, np.zeros_like(E))
+    sim.step(1000)
+    assert np.abs(sim.field(0, 2) - np.cos(1000 * theta) * E[2]).max() < tol
+    sim.close()
+
+
+def test_fp32_laser_vacuum_1000_steps_matches_oracle(hpic):
+    """The Gaussian laser pulse of the benchmark workload (k0 = 10, moving
+    -x1) on a 256 x 32 grid without plasma, 1000 steps: relative L2 error of E
+    and B of the FP32 form against the oracle's FP64 update at most 1e-5."""
+    n1, n2, dx1, dx2, dt = 256, 32, 0.1, 0.2, 0.045
+    laser = dict(a0=2.0, waist=1.5, length=2.0, k0=10.0, x1c=0.5 * n1 * dx1, x2c=0.5 * n2 * dx2)
+    E0, B0 = W.laser_2d(n1, n2, dx1, dx2, **laser)
+    sim = hpic.Sim([hpic.config(n1, n2, dx1, dx2, dt)])
+    sim.set_fields(0, E0, B0)
+    sim.step(1000)
+    E1, B1 = sim.fields(0)
+    g = oracle.grid2(n1, n2, dx1, dx2, dt, alpha=0.5)
+    Eo, Bo = E0, B0
+    J = np.zeros_like(E0)
+    for _ in range(1000):
+        Eo, Bo = oracle.field_update2(g, Eo, Bo, J)
+    err = np.linalg.norm(np.concatenate([(E1 - Eo).ravel(), (B1 - Bo).ravel()])) / \
+        np.linalg.norm(np.concatenate([Eo.ravel(), Bo.ravel()]))
+    assert err <= 1e-5, err
+    sim.close()
+
+
 def test_fd_mode_matches_oracle_yee(hpic):
     """deriv1 = 1 turns the hybrid kernels into the Yee scheme (end of Sec. 2.1)."""
     n1, n2 = 32, 16
