@@ -188,17 +188,31 @@ template <class R> __device__ __forceinline__ void spline3(R d, R w[3]) {
 
 // Quantised quadratic shape of one coordinate (cell + FP32 offset): integers
 // s[0..2] of the nodes m-1, m, m+1 with exact sum 2^P; returns m.  The same
-// definition as the FP32-precision reference deposit.
+// definition as the FP32-precision reference deposit:
+//   s[0] = floor(((2^(P-1) - D)^2 + 2^P) / 2^(P+1)), s[2] likewise with +D,
+// D = rint(d 2^P).  SMALL (P <= 22): the square is a full-rate 24-bit
+// multiply pair and floor((x^2 + 2^P) / 2^(P+1)) is evaluated as
+// (floor(x^2 / 2^P) + 1) >> 1, which is the same integer.
+template <bool SMALL>
 __device__ __forceinline__ int fixed_shape(int cell, float f, int P, int s[3]) {
   const int up = (f >= 0.5f) ? 1 : 0;
   const float d = up ? (f - 1.0f) : f;             // exact
   const float scaled = d * (float)(1 << P);         // exact
   const int D = (int)rintf(scaled);                 // |D| <= 2^(P-1)
   const int h = 1 << (P - 1);
-  const long long bias = 1ll << P;
   const int lo = h - D, hi = h + D;                 // in [0, 2^P]
-  s[0] = (int)(((long long)lo * lo + bias) >> (P + 1));
-  s[2] = (int)(((long long)hi * hi + bias) >> (P + 1));
+  if (SMALL) {
+    const unsigned long long l2 = (unsigned long long)(unsigned)(lo & 0xffffff) * (unsigned)(lo & 0xffffff);
+    const unsigned long long h2 = (unsigned long long)(unsigned)(hi & 0xffffff) * (unsigned)(hi & 0xffffff);
+    const unsigned ql = __builtin_amdgcn_alignbit((unsigned)(l2 >> 32), (unsigned)l2, (unsigned)P);
+    const unsigned qh = __builtin_amdgcn_alignbit((unsigned)(h2 >> 32), (unsigned)h2, (unsigned)P);
+    s[0] = (int)((ql + 1u) >> 1);
+    s[2] = (int)((qh + 1u) >> 1);
+  } else {
+    const long long bias = 1ll << P;
+    s[0] = (int)(((long long)lo * lo + bias) >> (P + 1));
+    s[2] = (int)(((long long)hi * hi + bias) >> (P + 1));
+  }
   s[1] = (1 << P) - s[0] - s[2];
   return cell + up;
 }
@@ -235,8 +249,9 @@ constexpr int PUSH_LDS_MAX = 64512;  // with the static LDS, under 64 KiB
 // Host-side launch wrappers (kernels.hip), one instantiation per precision.
 template <class R>
 struct Launch {
+  // unit: every run's charges satisfy the 24-bit product bound (FP32 form)
   static void push_deposit(const Run<R> *runs, const Item *items, int nitems, int parity,
-                           int pp, int lds_bytes, unsigned *err, unsigned *stats,
+                           int pp, int lds_bytes, bool unit, unsigned *err, unsigned *stats,
                            hipStream_t s);
   // tile sort of the particles of all runs: items are (run, first particle,
   // count) chunks; per_run lists (run, 0, 0) once per run.  scramble = true

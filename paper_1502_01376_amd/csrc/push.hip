@@ -224,22 +224,33 @@ struct LdsFp64 {
 __device__ __forceinline__ long long mul24_wide(int a, int b) {
   return (long long)((a << 8) >> 8) * (long long)((b << 8) >> 8);
 }
+// Product of two integers in [-2^23, 2^23) whose value fits 32 bits: one
+// v_mul_i32_i24 (written out, as the compiler otherwise folds the sign
+// extensions into a quarter-rate 32-bit multiply).
+__device__ __forceinline__ int mul24_lo(int a, int b) {
+  int r;
+  asm("v_mul_i32_i24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
 
 // Fixed-point Esirkepov deposit of one particle (2D).  Integer shapes with
 // exact sum 2^P make 2 (rho_new - rho_old) = div J hold exactly in the
 // integers; j3 is FP32 rounded once per node.  The arithmetic is the one of the
 // FP32-precision reference deposit, operation for operation.
-template <class Sink>
+//
+// UNIT (|charge| 2^P < 2^23, so Q C1 and Q C2 fit 24 signed bits) selects the
+// full-rate 24-bit integer products; it is a template parameter so that the
+// general 64-bit products are not compiled into the common kernel.
+template <bool UNIT, class Sink>
 __device__ __forceinline__ void deposit2_fixed(const Sink &K, int P, float inv_wunit, float c3,
-                                               bool unit_charge, int i1, int i2, float fa1,
-                                               float fa2, int d1, int d2, float fb1, float fb2,
-                                               float v3, float qw) {
+                                               int i1, int i2, float fa1, float fa2, int d1,
+                                               int d2, float fb1, float fb2, float v3, float qw) {
 #pragma clang fp contract(off)
   int sa1[3], sb1[3], sa2[3], sb2[3];
-  const int na1 = fixed_shape(i1, fa1, P, sa1);
-  const int nb1 = fixed_shape(i1 + d1, fb1, P, sb1);
-  const int na2 = fixed_shape(i2, fa2, P, sa2);
-  const int nb2 = fixed_shape(i2 + d2, fb2, P, sb2);
+  const int na1 = fixed_shape<UNIT>(i1, fa1, P, sa1);
+  const int nb1 = fixed_shape<UNIT>(i1 + d1, fb1, P, sb1);
+  const int na2 = fixed_shape<UNIT>(i2, fa2, P, sa2);
+  const int nb2 = fixed_shape<UNIT>(i2 + d2, fb2, P, sb2);
   const int base1 = min(na1, nb1) - 1, base2 = min(na2, nb2) - 1;
   int S0x[4], S1x[4], S0y[4], S1y[4];
   place4(sa1, na1 - 1 - base1, S0x);
@@ -270,22 +281,22 @@ __device__ __forceinline__ void deposit2_fixed(const Sink &K, int P, float inv_w
   // 48-bit product is one pair of full-rate 24-bit multiplies.
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int qc = Q * C1[a];
+    const int qc = UNIT ? mul24_lo(Q, C1[a]) : 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       long long v;
-      if (unit_charge) v = mul24_wide(qc, A2[b]);
+      if (UNIT) v = mul24_wide(qc, A2[b]);
       else v = ((long long)Q * (long long)C1[a]) * (long long)A2[b];
       K.add(0, ro[b] + co[a], v);
     }
   }
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
-    const int qc = Q * C2[b];
+    const int qc = UNIT ? mul24_lo(Q, C2[b]) : 0;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       long long v;
-      if (unit_charge) v = mul24_wide(qc, A1[a]);
+      if (UNIT) v = mul24_wide(qc, A1[a]);
       else v = ((long long)Q * (long long)C2[b]) * (long long)A1[a];
       K.add(1, ro[b] + co[a], v);
     }
@@ -370,14 +381,13 @@ __device__ __forceinline__ void deposit2_fp64(const Sink &K, double jfx1, double
   }
 }
 
-template <class Sink>
+template <bool UNIT, class Sink>
 __device__ __forceinline__ void deposit_one(const Run<float> &r, const Sink &K, int i1, int i2,
                                             float fa1, float fa2, int d1, int d2, float fb1,
                                             float fb2, float v3, float qw) {
-  deposit2_fixed(K, r.P, r.inv_wunit, r.c3, r.unit_charge != 0, i1, i2, fa1, fa2, d1, d2, fb1,
-                 fb2, v3, qw);
+  deposit2_fixed<UNIT>(K, r.P, r.inv_wunit, r.c3, i1, i2, fa1, fa2, d1, d2, fb1, fb2, v3, qw);
 }
-template <class Sink>
+template <bool UNIT, class Sink>
 __device__ __forceinline__ void deposit_one(const Run<double> &r, const Sink &K, int i1, int i2,
                                             double fa1, double fa2, int d1, int d2, double fb1,
                                             double fb2, double v3, double qw) {
@@ -413,7 +423,7 @@ __device__ __forceinline__ PState<R> load_state(const Parts<R> &P, int p) {
 // same frame, store.  (gi1, gi2) is the global cell.  Returns the global cell
 // after the step (unchanged if the particle was rejected: a non-finite or a
 // too-long move leaves it as it was and sets the error word).
-template <class R, class Src, class Sink>
+template <class R, bool UNIT, class Src, class Sink>
 __device__ __forceinline__ int push_one(const Run<R> &r, const Parts<R> &P, int p,
                                         const PState<R> &s, int gi1, int gi2, int li1, int li2,
                                         const Src &S, const Sink &K, unsigned *err) {
@@ -435,7 +445,7 @@ __device__ __forceinline__ int push_one(const Run<R> &r, const Parts<R> &P, int 
   R g1, g2;
   const int d1 = advance<R>(s.f1, m1, g1);
   const int d2 = advance<R>(s.f2, m2, g2);
-  deposit_one(r, K, li1, li2, s.f1, s.f2, d1, d2, g1, g2, v[2], s.qw);
+  deposit_one<UNIT>(r, K, li1, li2, s.f1, s.f2, d1, d2, g1, g2, v[2], s.qw);
   const int j1 = wrap_pow2(gi1 + d1, r.n1), j2 = wrap_small(gi2 + d2, r.n2);
   const int cell = (j2 << r.log2n1) | j1;
   G(P.cell)[p] = cell;
@@ -466,7 +476,7 @@ __device__ __forceinline__ int wave_max(int v) {
 // One workgroup per (run, tile).  The tile's bounding box (from the previous
 // push, or the tile itself right after a sort) sizes the LDS staging; the new
 // box of the pushed particles is written back for the next step.
-template <class R>
+template <class R, bool UNIT>
 __global__ void __launch_bounds__(PUSH_THREADS)
 k_push_deposit(const Run<R> *__restrict__ runs, const Item *__restrict__ items, int parity, int pp,
                int lds_bytes, unsigned *err, unsigned *stats) {
@@ -510,7 +520,7 @@ k_push_deposit(const Run<R> *__restrict__ runs, const Item *__restrict__ items, 
     for (int p = start + threadIdx.x; p < end; p += PUSH_THREADS) {
       const PState<R> s = load_state(P, p);
       const int i1 = s.cell & (n1 - 1), i2 = s.cell >> r.log2n1;
-      track(push_one<R>(r, P, p, s, i1, i2, i1, i2, S, K, err));
+      track(push_one<R, UNIT>(r, P, p, s, i1, i2, i1, i2, S, K, err));
     }
   } else {
     // LDS layout: current accumulators first, then the fields (16-byte aligned)
@@ -557,7 +567,7 @@ k_push_deposit(const Run<R> *__restrict__ runs, const Item *__restrict__ items, 
         if (p < end) {
           const int i1 = st[k].cell & (n1 - 1), i2 = st[k].cell >> r.log2n1;
           const int d1 = wrap_delta_pow2(i1 - ref1, n1), d2 = wrap_delta(i2 - ref2, n2);
-          track(push_one<R>(r, P, p, st[k], i1, i2, d1 - lo1 + 1, d2 - lo2 + 1, S, K, err));
+          track(push_one<R, UNIT>(r, P, p, st[k], i1, i2, d1 - lo1 + 1, d2 - lo2 + 1, S, K, err));
         }
       }
     }
@@ -725,7 +735,7 @@ __global__ void k_debug_deposit(int n1, int n2, int P, float inv_wunit, float c3
     return;
   }
   const GlobalFixed K{G((unsigned long long *)J), n1, n2, n1 * n2};
-  deposit2_fixed(K, P, inv_wunit, c3, false, a1, a2, off0[p], off0[np + p], d1, d2, off1[p],
+  deposit2_fixed<false>(K, P, inv_wunit, c3, a1, a2, off0[p], off0[np + p], d1, d2, off1[p],
                  off1[np + p], v3[p], qw[p]);
 }
 
@@ -738,8 +748,8 @@ __global__ void k_rho_fixed(const Run<float> *run, int pp, long long *rho) {
   const int cell = P.cell[p];
   const int i1 = cell & (r.n1 - 1), i2 = cell >> r.log2n1;
   int s1[3], s2[3];
-  const int m1 = fixed_shape(i1, P.f1[p], r.P, s1);
-  const int m2 = fixed_shape(i2, P.f2[p], r.P, s2);
+  const int m1 = fixed_shape<false>(i1, P.f1[p], r.P, s1);
+  const int m2 = fixed_shape<false>(i2, P.f2[p], r.P, s2);
   const long long Q = (long long)rintf(P.qw[p] * r.inv_wunit);
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
@@ -798,10 +808,18 @@ __global__ void k_kinetic(const Run<R> *run, int pp, double *partial) {
 // ---------------------------------------------------------------- launches
 template <class R>
 void Launch<R>::push_deposit(const Run<R> *runs, const Item *items, int nitems, int parity, int pp,
-                             int lds_bytes, unsigned *err, unsigned *stats, hipStream_t s) {
+                             int lds_bytes, bool unit, unsigned *err, unsigned *stats,
+                             hipStream_t s) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_push_deposit<R>, dim3(nitems), dim3(PUSH_THREADS), lds_bytes, s, runs,
-                     items, parity, pp, lds_bytes, err, stats);
+  if constexpr (std::is_same<R, float>::value) {
+    if (unit) {
+      hipLaunchKernelGGL((k_push_deposit<R, true>), dim3(nitems), dim3(PUSH_THREADS), lds_bytes, s,
+                         runs, items, parity, pp, lds_bytes, err, stats);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_push_deposit<R, false>), dim3(nitems), dim3(PUSH_THREADS), lds_bytes, s,
+                     runs, items, parity, pp, lds_bytes, err, stats);
 }
 
 template <class R>

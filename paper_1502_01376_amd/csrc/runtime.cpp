@@ -371,8 +371,8 @@ class Sim : public SimBase {
       since_sort_ = 0;
     }
     mark(HP_K_PUSH_DEPOSIT, true);
-    Launch<R>::push_deposit(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, d_err_, d_stats_,
-                            stream_);
+    Launch<R>::push_deposit(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, all_unit(), d_err_,
+                            d_stats_, stream_);
     mark(HP_K_PUSH_DEPOSIT, false);
     ++since_sort_;
     mark(HP_K_FFT_J, true);
@@ -1063,6 +1063,14 @@ class Sim : public SimBase {
     d_tiles_ = nullptr;
     n_tiles_ = 0;
     return tiles.empty() ? HP_OK : upload_items(tiles, &d_tiles_, &n_tiles_);
+  }
+
+  // every run with particles has the 24-bit product bound (FP32 form)
+  bool all_unit() const {
+    if (!FIXED) return false;
+    for (const RunHost &h : runs_)
+      if (h.np > 0 && !h.d.unit_charge) return false;
+    return true;
   }
 
   int rebuild_sort_items() {
