@@ -45,6 +45,8 @@ def parse():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--tune-steps", type=int, default=1200,
                     help="steps advanced by the autotuner before the warm-up (0: default tiling)")
+    ap.add_argument("--tiling", type=str, default="",
+                    help="T1,T2,K: fixed tile shape and sort interval instead of the autotuner")
     ap.add_argument("--scan-steps", type=int, default=200,
                     help="steps of the 64-run parameter scan (0: skip)")
     ap.add_argument("--n1", type=int, default=2048)
@@ -66,14 +68,16 @@ def timed_steps(torch, sim, warmup, steps):
     return t1 - t0
 
 
-def run_form(hpic, torch, ds, precision, warmup, steps, profile=False, tune_steps=0):
+def run_form(hpic, torch, ds, precision, warmup, steps, profile=False, tune_steps=0, tiling=None):
     """Untimed: the autotuner (tune_steps steps, picking tile shape and sort
     interval on the live runs) and `warmup` steps.  Timed region: `steps`
     steps with the captured-graph step (the library's default).  With
     `profile`, a second pass of the same length launches every kernel with HIP
     events around it on the library's stream for per-kernel durations."""
     sim = hpic.from_workloads(ds, precision, stream=torch.cuda.current_stream())
-    if tune_steps > 0:
+    if tiling:
+        sim.set_tiling(*tiling)
+    elif tune_steps > 0:
         sim.autotune(tune_steps)
     t = timed_steps(torch, sim, warmup, steps)
     kt = None
@@ -193,9 +197,10 @@ def main():
     npart = d["w"].size
     ncell = d["n"][0] * d["n"][1]
 
+    tiling = [int(v) for v in args.tiling.split(",")] if args.tiling else None
     sim32, t32, kt = run_form(hpic, torch, [d], "fp32", args.warmup, args.steps, profile=True,
-                              tune_steps=args.tune_steps)
-    tiling = sim32.tiling()
+                              tune_steps=args.tune_steps, tiling=tiling)
+    chosen = sim32.tiling()
     profiled_wall = kt.pop("profiled_wall_s")
     value = npart * args.steps / t32
     ms_step = 1e3 * t32 / args.steps
@@ -228,7 +233,7 @@ def main():
                    "filter_frac": d["alpha"], "deposit_accumulator": "int64 fixed point",
                    "parallelism": "single GPU"},
         "kernels": kernels,
-        "tiling": tiling,
+        "tiling": chosen,
         "roofline": {"bound": "hbm", "kernel": "push_deposit", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(), "alg_bytes_per_launch": alg_bytes,
@@ -242,7 +247,7 @@ def main():
         args.fp64_steps = args.steps
     if args.fp64_steps > 0:
         sim64, t64, _ = run_form(hpic, torch, [d], "fp64", args.warmup, args.fp64_steps,
-                                 tune_steps=args.tune_steps)
+                                 tune_steps=args.tune_steps, tiling=tiling)
         sim64.close()
         out["fp64_form"] = {"value": npart * args.fp64_steps / t64,
                             "ms_per_step": 1e3 * t64 / args.fp64_steps,
