@@ -35,6 +35,18 @@ class Grid2(ctypes.Structure):
     ]
 
 
+class Grid3(ctypes.Structure):
+    """Mirror of ``or_grid3`` (3D grid and solver options)."""
+
+    _fields_ = [
+        ("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("n3", ctypes.c_int32),
+        ("dx1", ctypes.c_double), ("dx2", ctypes.c_double), ("dx3", ctypes.c_double),
+        ("dt", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("deriv1", ctypes.c_int32), ("correct", ctypes.c_int32),
+        ("jbg", ctypes.c_double * 3),
+    ]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -43,6 +55,7 @@ def lib():
             _build.build()
         L = ctypes.CDLL(_LIBPATH)
         G = ctypes.POINTER(Grid2)
+        G3 = ctypes.POINTER(Grid3)
         sig = {
             "or_fft": (ctypes.c_int, [ctypes.c_int32, _D, _D, ctypes.c_int32]),
             "or_rfft_rows": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _D, _D, _D]),
@@ -62,6 +75,17 @@ def lib():
                                                  _I64]),
             "or_rho2_fixed": (None, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                                      ctypes.c_int64, _I32, _I32, _F, _F, _F, _I64]),
+            "or_gather3": (None, [G3, _D, _D, ctypes.c_int64, _D, _D, _D, _D, _D]),
+            "or_deposit3": (ctypes.c_int, [G3, ctypes.c_int64, _D, _D, _D, _D, _D, _D, _D, _D]),
+            "or_rho3": (None, [G3, ctypes.c_int64, _D, _D, _D, _D, _D]),
+            "or_field_update3": (ctypes.c_int, [G3, _D, _D, _D]),
+            "or_yee_update3": (None, [G3, _D, _D, _D]),
+            "or_step3": (ctypes.c_int, [G3, ctypes.c_double, ctypes.c_int64, _D, _D, _D, _D, _D,
+                                        _D, _D, _D, _D, _D]),
+            "or_gauss3": (ctypes.c_int, [G3, _D, _D, _D, _D]),
+            "or_deposit3_fixed": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                 ctypes.c_float, ctypes.c_float, ctypes.c_int64,
+                                                 _I32, _F, _I32, _F, _F, _I64]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -242,3 +266,121 @@ def rho2_fixed(n1, n2, P, inv_wunit, c1, c2, f1, f2, qw):
 def courant_limit2(dx1, dx2):
     """Largest stable time step of the hybrid solver, Eq. (22)."""
     return 2.0 / np.sqrt(np.pi ** 2 / dx1 ** 2 + 4.0 / dx2 ** 2)
+
+
+# ------------------------------------------------------------------------ 3D
+def grid3(n1, n2, n3, dx1, dx2, dx3, dt, alpha=1.0, deriv1=0, correct=1, jbg=(0.0, 0.0, 0.0)):
+    g = Grid3()
+    g.n1, g.n2, g.n3 = int(n1), int(n2), int(n3)
+    g.dx1, g.dx2, g.dx3, g.dt = float(dx1), float(dx2), float(dx3), float(dt)
+    g.alpha = float(alpha)
+    g.deriv1, g.correct = int(deriv1), int(correct)
+    for c in range(3):
+        g.jbg[c] = float(jbg[c])
+    return g
+
+
+def _shape3(g):
+    return (3, g.n3, g.n2, g.n1)
+
+
+def gather3(g, E, B, xi):
+    E, B = _f64(E), _f64(B)
+    x1, x2, x3 = (_f64(xi[d]) for d in range(3))
+    n = len(x1)
+    Ep = np.zeros((3, n))
+    Bp = np.zeros((3, n))
+    lib().or_gather3(ctypes.byref(g), _p(E), _p(B), n, _p(x1), _p(x2), _p(x3), _p(Ep), _p(Bp))
+    return Ep, Bp
+
+
+def deposit3(g, xa, xb, qw):
+    """Esirkepov current of moves xa -> xb ([3][np], cell units, xb unwrapped)."""
+    a = [_f64(xa[d]) for d in range(3)]
+    b = [_f64(xb[d]) for d in range(3)]
+    qw = _f64(qw)
+    J = np.zeros(_shape3(g))
+    st = lib().or_deposit3(ctypes.byref(g), len(qw), _p(a[0]), _p(a[1]), _p(a[2]), _p(b[0]),
+                           _p(b[1]), _p(b[2]), _p(qw), _p(J))
+    if st != 0:
+        raise ValueError("a particle moved a cell or more in one step")
+    return J
+
+
+def rho3(g, xi, qw):
+    x = [_f64(xi[d]) for d in range(3)]
+    qw = _f64(qw)
+    rho = np.zeros(_shape3(g)[1:])
+    lib().or_rho3(ctypes.byref(g), len(qw), _p(x[0]), _p(x[1]), _p(x[2]), _p(qw), _p(rho))
+    return rho
+
+
+def field_update3(g, E, B, J):
+    E, B, J = _f64(E).copy(), _f64(B).copy(), _f64(J)
+    if lib().or_field_update3(ctypes.byref(g), _p(E), _p(B), _p(J)) != 0:
+        raise ValueError("bad grid")
+    return E, B
+
+
+def yee_update3(g, E, B, J):
+    E, B, J = _f64(E).copy(), _f64(B).copy(), _f64(J)
+    lib().or_yee_update3(ctypes.byref(g), _p(E), _p(B), _p(J))
+    return E, B
+
+
+def gauss3(g, E, rho):
+    E, rho = _f64(E), _f64(rho)
+    nk = g.n1 // 2 + 1
+    n = g.n3 * g.n2 * nk
+    re, im = np.zeros(n), np.zeros(n)
+    lib().or_gauss3(ctypes.byref(g), _p(E), _p(rho), _p(re), _p(im))
+    return (re + 1j * im).reshape(g.n3, g.n2, nk)
+
+
+class State3:
+    """Particles and fields of one 3D run, advanced by ``step``."""
+
+    def __init__(self, g, qm, xi, u, qw, E=None, B=None):
+        self.g, self.qm = g, float(qm)
+        self.xi = [_f64(xi[d]).copy() for d in range(3)]
+        self.u = _f64(u).copy()
+        self.qw = _f64(qw).copy()
+        shape = _shape3(g)
+        self.E = np.zeros(shape) if E is None else _f64(E).copy()
+        self.B = np.zeros(shape) if B is None else _f64(B).copy()
+        self.J = np.zeros(shape)
+
+    def step(self, n=1):
+        g = self.g
+        u1, u2, u3 = (np.ascontiguousarray(self.u[c]) for c in range(3))
+        for _ in range(n):
+            st = lib().or_step3(ctypes.byref(g), self.qm, len(self.qw), _p(self.xi[0]),
+                                _p(self.xi[1]), _p(self.xi[2]), _p(u1), _p(u2), _p(u3),
+                                _p(self.qw), _p(self.E), _p(self.B), _p(self.J))
+            if st != 0:
+                raise ValueError("oracle step failed (move of a cell or more)")
+        self.u = np.stack([u1, u2, u3])
+        return self
+
+
+def deposit3_fixed(n, inv_wunit, cj, ca, fa, cb, fb, qw):
+    """Kernel-precision 3D deposit: ca, cb int cell indices [3][np], fa, fb FP32
+    offsets [3][np]; returns int64 [3][n3][n2][n1]."""
+    ca = np.ascontiguousarray(ca, dtype=np.int32)
+    cb = np.ascontiguousarray(cb, dtype=np.int32)
+    fa = np.ascontiguousarray(fa, dtype=np.float32)
+    fb = np.ascontiguousarray(fb, dtype=np.float32)
+    qw = np.ascontiguousarray(qw, dtype=np.float32)
+    n1, n2, n3 = (int(v) for v in n)
+    J = np.zeros((3, n3, n2, n1), dtype=np.int64)
+    st = lib().or_deposit3_fixed(n1, n2, n3, float(inv_wunit), float(cj), len(qw), _p(ca, _I32),
+                                 _p(fa, _F), _p(cb, _I32), _p(fb, _F), _p(qw, _F), _p(J, _I64))
+    if st != 0:
+        raise ValueError("a particle moved a cell or more in one step")
+    return J
+
+
+def courant_limit3(dx1, dx2, dx3):
+    """Largest stable time step of the 3D hybrid solver: Eq. (22) with the x3
+    difference added, 2 / sqrt(pi^2/dx1^2 + 4/dx2^2 + 4/dx3^2)."""
+    return 2.0 / np.sqrt(np.pi ** 2 / dx1 ** 2 + 4.0 / dx2 ** 2 + 4.0 / dx3 ** 2)

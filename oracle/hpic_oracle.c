@@ -588,3 +588,378 @@ void or_rho2_fixed(int32_t n1, int32_t n2, int32_t P, float inv_wunit, int64_t n
         rho[(int64_t)wrapi(m2 - 1 + b, n2) * n1 + wrapi(m1 - 1 + a, n1)] += Q * s1[a] * s2[b];
   }
 }
+
+/* ======================================================================== */
+/* 3D Cartesian                                                              */
+/* ======================================================================== */
+/*
+ * Grid n1 x n2 x n3, periodic, arrays [comp][i3][i2][i1].  Yee staggering
+ * extended to three dimensions in the standard way (Sec. 2.2 gives the 3D
+ * form by adding the x3 differences): E1 at (i1+1/2, i2, i3), E2 at
+ * (i1, i2+1/2, i3), E3 at (i1, i2, i3+1/2), B1 at (i1, i2+1/2, i3+1/2),
+ * B2 at (i1+1/2, i2, i3+1/2), B3 at (i1+1/2, i2+1/2, i3).  The hybrid solver
+ * transforms along x1 only; x2 and x3 use centred finite differences.
+ */
+
+static const double STAG3_E[3][3] = {{0.5, 0.0, 0.0}, {0.0, 0.5, 0.0}, {0.0, 0.0, 0.5}};
+static const double STAG3_B[3][3] = {{0.0, 0.5, 0.5}, {0.5, 0.0, 0.5}, {0.5, 0.5, 0.0}};
+
+static int64_t idx3(const or_grid3 *g, int64_t a, int64_t b, int64_t c) {
+  return ((int64_t)wrapi(c, g->n3) * g->n2 + wrapi(b, g->n2)) * g->n1 + wrapi(a, g->n1);
+}
+
+static double interp3(const or_grid3 *g, const double *F, const double s[3], double x1,
+                      double x2, double x3) {
+  double e1 = x1 - s[0], e2 = x2 - s[1], e3 = x3 - s[2];
+  int64_t m1 = (int64_t)floor(e1 + 0.5), m2 = (int64_t)floor(e2 + 0.5), m3 = (int64_t)floor(e3 + 0.5);
+  double acc = 0.0;
+  for (int64_t c = m3 - 1; c <= m3 + 1; ++c) {
+    double w3 = spline2(e3 - (double)c);
+    for (int64_t b = m2 - 1; b <= m2 + 1; ++b) {
+      double w2 = spline2(e2 - (double)b);
+      for (int64_t a = m1 - 1; a <= m1 + 1; ++a)
+        acc += spline2(e1 - (double)a) * w2 * w3 * F[idx3(g, a, b, c)];
+    }
+  }
+  return acc;
+}
+
+void or_gather3(const or_grid3 *g, const double *E, const double *B, int64_t np,
+                const double *xi1, const double *xi2, const double *xi3, double *Ep, double *Bp) {
+  int64_t cells = (int64_t)g->n1 * g->n2 * g->n3;
+  for (int64_t p = 0; p < np; ++p)
+    for (int c = 0; c < 3; ++c) {
+      Ep[c * np + p] = interp3(g, E + c * cells, STAG3_E[c], xi1[p], xi2[p], xi3[p]);
+      Bp[c * np + p] = interp3(g, B + c * cells, STAG3_B[c], xi1[p], xi2[p], xi3[p]);
+    }
+}
+
+/* Esirkepov deposit in 3D (quadratic shape).  With S0, S1 the old and new
+ * shape factors per coordinate on a common 4-node window and DS = S1 - S0,
+ *   W1 = DS1 (S0_2 S0_3 + DS2 S0_3 / 2 + S0_2 DS3 / 2 + DS2 DS3 / 3)
+ * and cyclically for W2, W3; then W1 + W2 + W3 = S1_1 S1_2 S1_3 - S0_1 S0_2 S0_3
+ * and j_d is the running sum of -q w (dx_d / dt) W_d along x_d, which makes the
+ * continuity equation hold node by node. */
+int or_deposit3(const or_grid3 *g, int64_t np, const double *xa1, const double *xa2,
+                const double *xa3, const double *xb1, const double *xb2, const double *xb3,
+                const double *qw, double *J) {
+  int64_t cells = (int64_t)g->n1 * g->n2 * g->n3;
+  const double *xa[3] = {xa1, xa2, xa3}, *xb[3] = {xb1, xb2, xb3};
+  const double dx[3] = {g->dx1, g->dx2, g->dx3};
+  int status = 0;
+  for (int64_t p = 0; p < np; ++p) {
+    int bad = 0;
+    for (int d = 0; d < 3; ++d) bad |= fabs(xb[d][p] - xa[d][p]) >= 1.0;
+    if (bad) { status = -1; continue; }
+    int64_t base[3];
+    double S0[3][4], S1[3][4], DS[3][4];
+    for (int d = 0; d < 3; ++d) {
+      base[d] = (int64_t)fmin(floor(xa[d][p] + 0.5), floor(xb[d][p] + 0.5)) - 1;
+      for (int k = 0; k < 4; ++k) {
+        S0[d][k] = spline2(xa[d][p] - (double)(base[d] + k));
+        S1[d][k] = spline2(xb[d][p] - (double)(base[d] + k));
+        DS[d][k] = S1[d][k] - S0[d][k];
+      }
+    }
+    /* component d: running sum along x_d; (e, f) are the other two axes */
+    for (int d = 0; d < 3; ++d) {
+      int e = (d + 1) % 3, f = (d + 2) % 3;
+      double fac = -qw[p] * dx[d] / g->dt;
+      for (int i = 0; i < 4; ++i) {
+        for (int j = 0; j < 4; ++j) {
+          double tr = S0[e][i] * S0[f][j] + 0.5 * DS[e][i] * S0[f][j] +
+                      0.5 * S0[e][i] * DS[f][j] + DS[e][i] * DS[f][j] / 3.0;
+          double acc = 0.0;
+          for (int k = 0; k < 4; ++k) {
+            acc += fac * DS[d][k] * tr;
+            int64_t n[3];
+            n[d] = base[d] + k;
+            n[e] = base[e] + i;
+            n[f] = base[f] + j;
+            J[d * cells + idx3(g, n[0], n[1], n[2])] += acc;
+          }
+        }
+      }
+    }
+  }
+  return status;
+}
+
+void or_rho3(const or_grid3 *g, int64_t np, const double *xi1, const double *xi2,
+             const double *xi3, const double *qw, double *rho) {
+  for (int64_t p = 0; p < np; ++p) {
+    int64_t m1 = (int64_t)floor(xi1[p] + 0.5), m2 = (int64_t)floor(xi2[p] + 0.5),
+            m3 = (int64_t)floor(xi3[p] + 0.5);
+    for (int64_t c = m3 - 1; c <= m3 + 1; ++c)
+      for (int64_t b = m2 - 1; b <= m2 + 1; ++b)
+        for (int64_t a = m1 - 1; a <= m1 + 1; ++a)
+          rho[idx3(g, a, b, c)] += qw[p] * spline2(xi1[p] - (double)a) *
+                                   spline2(xi2[p] - (double)b) * spline2(xi3[p] - (double)c);
+  }
+}
+
+static xsym x1_symbols3(const or_grid3 *g, int32_t kappa) {
+  or_grid2 g2;
+  g2.n1 = g->n1; g2.n2 = g->n2; g2.dx1 = g->dx1; g2.dx2 = g->dx2; g2.dt = g->dt;
+  g2.alpha = g->alpha; g2.deriv1 = g->deriv1; g2.correct = g->correct;
+  return x1_symbols(&g2, kappa);
+}
+
+/* Faraday half step B -= (dt/2) curl E in (kappa1, x2, x3) space:
+ * curl E = (D2+ E3 - D3+ E2, D3+ E1 - D1+ E3, D1+ E2 - D2+ E1). */
+static void faraday_half3(const or_grid3 *g, const double complex *Ek, double complex *Bk) {
+  int32_t n2 = g->n2, n3 = g->n3, nk = g->n1 / 2 + 1;
+  int64_t vol = (int64_t)n3 * n2 * nk;
+  const double complex *E1 = Ek, *E2 = Ek + vol, *E3 = Ek + 2 * vol;
+  double complex *B1 = Bk, *B2 = Bk + vol, *B3 = Bk + 2 * vol;
+  double hdt = 0.5 * g->dt;
+  for (int32_t k = 0; k < nk; ++k) {
+    xsym s = x1_symbols3(g, k);
+    for (int32_t i3 = 0; i3 < n3; ++i3)
+      for (int32_t i2 = 0; i2 < n2; ++i2) {
+        int64_t c = ((int64_t)i3 * n2 + i2) * nk + k;
+        int64_t u2 = ((int64_t)i3 * n2 + wrapi(i2 + 1, n2)) * nk + k;
+        int64_t u3 = ((int64_t)wrapi(i3 + 1, n3) * n2 + i2) * nk + k;
+        double complex cE1 = (E3[u2] - E3[c]) / g->dx2 - (E2[u3] - E2[c]) / g->dx3;
+        double complex cE2 = (E1[u3] - E1[c]) / g->dx3 - s.dp * E3[c];
+        double complex cE3 = s.dp * E2[c] - (E1[u2] - E1[c]) / g->dx2;
+        B1[c] -= hdt * cE1;
+        B2[c] -= hdt * cE2;
+        B3[c] -= hdt * cE3;
+      }
+  }
+}
+
+int or_field_update3(const or_grid3 *g, double *E, double *B, const double *J) {
+  int32_t n1 = g->n1, n2 = g->n2, n3 = g->n3, nk = n1 / 2 + 1;
+  if (!is_pow2(n1) || n1 < 2 || n2 < 1 || n3 < 1) return -1;
+  int32_t rows = n2 * n3;
+  int64_t cells = (int64_t)n1 * rows, vol = (int64_t)rows * nk;
+  double complex *Ek = malloc(sizeof(double complex) * 3 * vol);
+  double complex *Bk = malloc(sizeof(double complex) * 3 * vol);
+  double complex *Jk = malloc(sizeof(double complex) * 3 * vol);
+  double *tmp = malloc(sizeof(double) * cells);
+  for (int c = 0; c < 3; ++c) {
+    to_k(n1, rows, E + c * cells, Ek + c * vol);
+    to_k(n1, rows, B + c * cells, Bk + c * vol);
+    for (int64_t i = 0; i < cells; ++i) tmp[i] = J[c * cells + i] + g->jbg[c];
+    to_k(n1, rows, tmp, Jk + c * vol);
+  }
+  for (int32_t k = 0; k < nk; ++k) {
+    xsym s = x1_symbols3(g, k);
+    for (int32_t r = 0; r < rows; ++r) {
+      int64_t c = (int64_t)r * nk + k;
+      Jk[c] *= s.corr * s.filt;
+      Jk[vol + c] *= s.filt;
+      Jk[2 * vol + c] *= s.filt;
+    }
+  }
+  faraday_half3(g, Ek, Bk);
+  {
+    double complex *E1 = Ek, *E2 = Ek + vol, *E3 = Ek + 2 * vol;
+    const double complex *B1 = Bk, *B2 = Bk + vol, *B3 = Bk + 2 * vol;
+    /* curl B = (D2- B3 - D3- B2, D3- B1 - D1- B3, D1- B2 - D2- B1) */
+    for (int32_t k = 0; k < nk; ++k) {
+      xsym s = x1_symbols3(g, k);
+      for (int32_t i3 = 0; i3 < n3; ++i3)
+        for (int32_t i2 = 0; i2 < n2; ++i2) {
+          int64_t c = ((int64_t)i3 * n2 + i2) * nk + k;
+          int64_t d2 = ((int64_t)i3 * n2 + wrapi(i2 - 1, n2)) * nk + k;
+          int64_t d3 = ((int64_t)wrapi(i3 - 1, n3) * n2 + i2) * nk + k;
+          double complex cB1 = (B3[c] - B3[d2]) / g->dx2 - (B2[c] - B2[d3]) / g->dx3;
+          double complex cB2 = (B1[c] - B1[d3]) / g->dx3 - s.dm * B3[c];
+          double complex cB3 = s.dm * B2[c] - (B1[c] - B1[d2]) / g->dx2;
+          E1[c] += g->dt * (cB1 - Jk[c]);
+          E2[c] += g->dt * (cB2 - Jk[vol + c]);
+          E3[c] += g->dt * (cB3 - Jk[2 * vol + c]);
+        }
+    }
+  }
+  faraday_half3(g, Ek, Bk);
+  for (int c = 0; c < 3; ++c) {
+    from_k(n1, rows, Ek + c * vol, E + c * cells);
+    from_k(n1, rows, Bk + c * vol, B + c * cells);
+  }
+  free(Ek); free(Bk); free(Jk); free(tmp);
+  return 0;
+}
+
+/* Direct real-space Yee update in 3D (Yee's centred differences in all three
+ * directions; no FFT, filter or correction; jbg added). */
+static void yee_faraday_half3(const or_grid3 *g, const double *E, double *B) {
+  int64_t cells = (int64_t)g->n1 * g->n2 * g->n3;
+  const double *E1 = E, *E2 = E + cells, *E3 = E + 2 * cells;
+  double *B1 = B, *B2 = B + cells, *B3 = B + 2 * cells;
+  double h = 0.5 * g->dt;
+  for (int32_t i3 = 0; i3 < g->n3; ++i3)
+    for (int32_t i2 = 0; i2 < g->n2; ++i2)
+      for (int32_t i1 = 0; i1 < g->n1; ++i1) {
+        int64_t c = idx3(g, i1, i2, i3);
+        int64_t p1 = idx3(g, i1 + 1, i2, i3), p2 = idx3(g, i1, i2 + 1, i3), p3 = idx3(g, i1, i2, i3 + 1);
+        B1[c] -= h * ((E3[p2] - E3[c]) / g->dx2 - (E2[p3] - E2[c]) / g->dx3);
+        B2[c] -= h * ((E1[p3] - E1[c]) / g->dx3 - (E3[p1] - E3[c]) / g->dx1);
+        B3[c] -= h * ((E2[p1] - E2[c]) / g->dx1 - (E1[p2] - E1[c]) / g->dx2);
+      }
+}
+
+void or_yee_update3(const or_grid3 *g, double *E, double *B, const double *J) {
+  int64_t cells = (int64_t)g->n1 * g->n2 * g->n3;
+  yee_faraday_half3(g, E, B);
+  double *E1 = E, *E2 = E + cells, *E3 = E + 2 * cells;
+  const double *B1 = B, *B2 = B + cells, *B3 = B + 2 * cells;
+  for (int32_t i3 = 0; i3 < g->n3; ++i3)
+    for (int32_t i2 = 0; i2 < g->n2; ++i2)
+      for (int32_t i1 = 0; i1 < g->n1; ++i1) {
+        int64_t c = idx3(g, i1, i2, i3);
+        int64_t m1 = idx3(g, i1 - 1, i2, i3), m2 = idx3(g, i1, i2 - 1, i3), m3 = idx3(g, i1, i2, i3 - 1);
+        E1[c] += g->dt * ((B3[c] - B3[m2]) / g->dx2 - (B2[c] - B2[m3]) / g->dx3 - (J[c] + g->jbg[0]));
+        E2[c] += g->dt * ((B1[c] - B1[m3]) / g->dx3 - (B3[c] - B3[m1]) / g->dx1 -
+                          (J[cells + c] + g->jbg[1]));
+        E3[c] += g->dt * ((B2[c] - B2[m1]) / g->dx1 - (B1[c] - B1[m2]) / g->dx2 -
+                          (J[2 * cells + c] + g->jbg[2]));
+      }
+  yee_faraday_half3(g, E, B);
+}
+
+int or_step3(const or_grid3 *g, double qm, int64_t np, double *xi1, double *xi2, double *xi3,
+             double *u1, double *u2, double *u3, const double *qw, double *E, double *B,
+             double *J) {
+  int64_t cells = (int64_t)g->n1 * g->n2 * g->n3;
+  int64_t m = np > 0 ? np : 1;
+  double *Ep = malloc(sizeof(double) * 3 * m), *Bp = malloc(sizeof(double) * 3 * m);
+  double *xn1 = malloc(sizeof(double) * m), *xn2 = malloc(sizeof(double) * m),
+         *xn3 = malloc(sizeof(double) * m);
+  or_gather3(g, E, B, np, xi1, xi2, xi3, Ep, Bp);
+  or_boris(np, qm, g->dt, Ep, Bp, u1, u2, u3);
+  for (int64_t p = 0; p < np; ++p) {
+    double gam = sqrt(1.0 + u1[p] * u1[p] + u2[p] * u2[p] + u3[p] * u3[p]);
+    xn1[p] = xi1[p] + g->dt * (u1[p] / gam) / g->dx1;
+    xn2[p] = xi2[p] + g->dt * (u2[p] / gam) / g->dx2;
+    xn3[p] = xi3[p] + g->dt * (u3[p] / gam) / g->dx3;
+  }
+  memset(J, 0, sizeof(double) * 3 * cells);
+  int status = or_deposit3(g, np, xi1, xi2, xi3, xn1, xn2, xn3, qw, J);
+  if (or_field_update3(g, E, B, J) != 0) status = -1;
+  double *xs[3] = {xi1, xi2, xi3}, *xn[3] = {xn1, xn2, xn3};
+  const int32_t n[3] = {g->n1, g->n2, g->n3};
+  for (int d = 0; d < 3; ++d)
+    for (int64_t p = 0; p < np; ++p) {
+      double v = fmod(xn[d][p], (double)n[d]);
+      xs[d][p] = v < 0.0 ? v + (double)n[d] : v;
+    }
+  free(Ep); free(Bp); free(xn1); free(xn2); free(xn3);
+  return status;
+}
+
+int or_gauss3(const or_grid3 *g, const double *E, const double *rho, double *Rre, double *Rim) {
+  int32_t n1 = g->n1, n2 = g->n2, n3 = g->n3, nk = n1 / 2 + 1;
+  if (!is_pow2(n1) || n1 < 2) return -1;
+  int32_t rows = n2 * n3;
+  int64_t cells = (int64_t)n1 * rows, vol = (int64_t)rows * nk;
+  double complex *E1 = malloc(sizeof(double complex) * vol);
+  double complex *E2 = malloc(sizeof(double complex) * vol);
+  double complex *E3 = malloc(sizeof(double complex) * vol);
+  double complex *R = malloc(sizeof(double complex) * vol);
+  to_k(n1, rows, E, E1);
+  to_k(n1, rows, E + cells, E2);
+  to_k(n1, rows, E + 2 * cells, E3);
+  to_k(n1, rows, rho, R);
+  for (int32_t k = 0; k < nk; ++k) {
+    xsym s = x1_symbols3(g, k);
+    for (int32_t i3 = 0; i3 < n3; ++i3)
+      for (int32_t i2 = 0; i2 < n2; ++i2) {
+        int64_t c = ((int64_t)i3 * n2 + i2) * nk + k;
+        int64_t d2 = ((int64_t)i3 * n2 + wrapi(i2 - 1, n2)) * nk + k;
+        int64_t d3 = ((int64_t)wrapi(i3 - 1, n3) * n2 + i2) * nk + k;
+        double complex div = s.dm * E1[c] + (E2[c] - E2[d2]) / g->dx2 + (E3[c] - E3[d3]) / g->dx3;
+        R[c] = div - s.filt * R[c];
+      }
+  }
+  for (int64_t i = 0; i < vol; ++i) { Rre[i] = creal(R[i]); Rim[i] = cimag(R[i]); }
+  free(E1); free(E2); free(E3); free(R);
+  return 0;
+}
+
+/* ---- 3D deposit in the kernel's precision ----
+ * The product of three shape factors does not fit the 64-bit budget of an
+ * exact integer scheme with arbitrary charges, so the 3D FP32 form computes
+ * the Esirkepov weights in FP32 and rounds each node's contribution once to an
+ * integer (the integers then add up in any order to the same 64-bit total).
+ * Per coordinate, FP32 shape factors at the three nodes around the nearest
+ * node m (d = offset from m, exact):
+ *   a = 0.5 - d, b = 0.5 + d:  s(-1) = 0.5 (a a),  s(0) = 0.75 - d d,  s(+1) = 0.5 (b b)
+ * placed on the common 4-node window; DS = S1 - S0; running sums
+ * C[k] = C[k-1] + DS[k] in order.  For component d with the other two axes
+ * (e, f) in cyclic order:
+ *   u0[j] = 2 S0_f[j] + S1_f[j],  u1[j] = S0_f[j] + 2 S1_f[j]
+ *   T[i][j] = fma(S0_e[i], u0[j], S1_e[i] u1[j])      (6 times the Esirkepov bracket)
+ *   J_d[k][i][j] += rint((C_d[k] g) T[i][j]),  g = qw inv_wunit cj,  k = 0..2
+ * each FP32 operation rounded once in this order, so that
+ * j_d = -(dx_d / dt) J_d / (6 inv_wunit cj).  |J| per particle <= 6 cj < 2^31. */
+static int32_t fshape3(int32_t cell, float f, float s[3]) {
+  int32_t up = (f >= 0.5f);
+  float d = up ? (f - 1.0f) : f;
+  float a = 0.5f - d, b = 0.5f + d;
+  s[0] = 0.5f * (a * a);
+  s[1] = 0.75f - d * d;
+  s[2] = 0.5f * (b * b);
+  return cell + up;
+}
+
+int or_deposit3_fixed(int32_t n1, int32_t n2, int32_t n3, float inv_wunit, float cj, int64_t np,
+                      const int32_t *ca, const float *fa, const int32_t *cb, const float *fb,
+                      const float *qw, int64_t *J) {
+  or_grid3 g;
+  memset(&g, 0, sizeof g);
+  g.n1 = n1; g.n2 = n2; g.n3 = n3;
+  int64_t cells = (int64_t)n1 * n2 * n3;
+  const int32_t n[3] = {n1, n2, n3};
+  int status = 0;
+  for (int64_t p = 0; p < np; ++p) {
+    float S0[3][4], S1[3][4], C[3][4];
+    int32_t base[3], bad = 0;
+    for (int d = 0; d < 3; ++d) {
+      int32_t dd = wrap_delta(cb[d * np + p] - ca[d * np + p], n[d]);
+      if (dd < -1 || dd > 1) bad = 1;
+      float sa[3], sb[3];
+      int32_t na = fshape3(ca[d * np + p], fa[d * np + p], sa);
+      int32_t nb = fshape3(ca[d * np + p] + dd, fb[d * np + p], sb);
+      if (na - nb > 1 || nb - na > 1) bad = 1;
+      base[d] = (na < nb ? na : nb) - 1;
+      for (int k = 0; k < 4; ++k) S0[d][k] = S1[d][k] = 0.0f;
+      if (!bad)
+        for (int k = 0; k < 3; ++k) {
+          S0[d][na - 1 - base[d] + k] = sa[k];
+          S1[d][nb - 1 - base[d] + k] = sb[k];
+        }
+      float acc = 0.0f;
+      for (int k = 0; k < 4; ++k) {
+        acc = acc + (S1[d][k] - S0[d][k]);
+        C[d][k] = acc;
+      }
+    }
+    if (bad) { status = -1; continue; }
+    float gq = (qw[p] * inv_wunit) * cj;
+    for (int d = 0; d < 3; ++d) {
+      int e = (d + 1) % 3, f = (d + 2) % 3;
+      float u0[4], u1[4];
+      for (int j = 0; j < 4; ++j) {
+        u0[j] = 2.0f * S0[f][j] + S1[f][j];
+        u1[j] = S0[f][j] + 2.0f * S1[f][j];
+      }
+      for (int k = 0; k < 3; ++k) {
+        float cg = C[d][k] * gq;
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) {
+            float T = fmaf(S0[e][i], u0[j], S1[e][i] * u1[j]);
+            int64_t m[3];
+            m[d] = base[d] + k;
+            m[e] = base[e] + i;
+            m[f] = base[f] + j;
+            J[d * cells + idx3(&g, m[0], m[1], m[2])] += (int64_t)rintf(cg * T);
+          }
+      }
+    }
+  }
+  return status;
+}

@@ -115,6 +115,41 @@ void or_rho2_fixed(int32_t n1, int32_t n2, int32_t P, float inv_wunit, int64_t n
                    const int32_t *c1, const int32_t *c2, const float *f1, const float *f2,
                    const float *qw, int64_t *rho);
 
+/* ---- 3D Cartesian ----
+ * n1 x n2 x n3 cells, periodic; arrays [comp][i3][i2][i1], x1 fastest; Yee
+ * staggering E1 (i1+1/2, i2, i3), E2 (i1, i2+1/2, i3), E3 (i1, i2, i3+1/2),
+ * B1 (i1, i2+1/2, i3+1/2), B2 (i1+1/2, i2, i3+1/2), B3 (i1+1/2, i2+1/2, i3).
+ * The hybrid solver transforms along x1 and differences along x2 and x3
+ * (Sec. 2.2).  Same options as or_grid2. */
+typedef struct or_grid3 {
+  int32_t n1, n2, n3;
+  double dx1, dx2, dx3, dt;
+  double alpha;
+  int32_t deriv1;
+  int32_t correct;
+  double jbg[3];
+} or_grid3;
+
+void or_gather3(const or_grid3 *g, const double *E, const double *B, int64_t np,
+                const double *xi1, const double *xi2, const double *xi3, double *Ep, double *Bp);
+int or_deposit3(const or_grid3 *g, int64_t np, const double *xa1, const double *xa2,
+                const double *xa3, const double *xb1, const double *xb2, const double *xb3,
+                const double *qw, double *J);
+void or_rho3(const or_grid3 *g, int64_t np, const double *xi1, const double *xi2,
+             const double *xi3, const double *qw, double *rho);
+int or_field_update3(const or_grid3 *g, double *E, double *B, const double *J);
+void or_yee_update3(const or_grid3 *g, double *E, double *B, const double *J);
+int or_step3(const or_grid3 *g, double qm, int64_t np, double *xi1, double *xi2, double *xi3,
+             double *u1, double *u2, double *u3, const double *qw, double *E, double *B,
+             double *J);
+int or_gauss3(const or_grid3 *g, const double *E, const double *rho, double *Rre, double *Rim);
+/* Kernel-precision 3D deposit (FP32 Esirkepov weights, each node's
+ * contribution rounded once to an integer; see the .c file).  ca, cb are cell
+ * indices [3][np], fa, fb FP32 offsets [3][np]; J is int64 [3][cells]. */
+int or_deposit3_fixed(int32_t n1, int32_t n2, int32_t n3, float inv_wunit, float cj, int64_t np,
+                      const int32_t *ca, const float *fa, const int32_t *cb, const float *fb,
+                      const float *qw, int64_t *J);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,10 @@ The named workloads are the drifting-plasma set-ups of the benchmark suite:
   particles per cell at uniformly random positions in each cell, dx = 0.2,
   dt = 0.05, thermal spread 1e-4, filter 0.5, 200 steps.
 
+* ``drift3d``  -- 512 x 128 x 128 cells, dx = 0.2, dt = 0.05, a 2x1x1
+  lattice (2 per cell, 16 777 216 particles), gamma = 50 cold along x1, per-cell
+  density multiplier U[0.95, 1.05] carried in the weights, 500 steps.
+
 The NCI test set-up of Table 1 (dx = 0.2, dt = 0.4 dx1, periodic,
 51.2 x 51.2, gamma = 50, n = 100) is ``nci_table1``.
 """
@@ -213,6 +217,42 @@ def scan2d_run(p, dx=0.2, dt=0.05, sigma_u=1e-4, alpha=0.5):
 def scan2d(nruns=64, seed=SEED0 + 4, shrink=1):
     """All runs of the parameter scan (see scan2d_params, scan2d_run)."""
     return [scan2d_run(p) for p in scan2d_params(nruns, seed, shrink)]
+
+
+def drift3d(n1=512, n2=128, n3=128, dx=0.2, dt=0.05, sub=(2, 1, 1), gamma=50.0, sigma_u=0.0,
+            spread=0.05, jitter=False, alpha=0.5, seed=SEED0 + 2, name=None):
+    """A 3D electron plasma drifting along x1 over a neutralising background:
+    a sub-lattice in every cell (offsets (k + 1/2) / sub, or uniform inside
+    the sub-cell with ``jitter``), weights n_cell / ppc with n_cell drawn per
+    cell from U[1 - spread, 1 + spread].  Positions ``xi`` are [3][np] in cell
+    units, fields [3][n3][n2][n1]."""
+    gen = rng(seed)
+    ppc = sub[0] * sub[1] * sub[2]
+    cells = n1 * n2 * n3
+    dens = 1.0 + spread * (2.0 * gen.random(cells) - 1.0)
+    offs = [(np.arange(sub[d], dtype=np.float64) + 0.5) / sub[d] for d in range(3)]
+    o1, o2, o3 = np.meshgrid(offs[0], offs[1], offs[2], indexing="ij")
+    o = np.stack([o1.ravel(), o2.ravel(), o3.ravel()])          # [3][ppc]
+    cell = np.arange(cells, dtype=np.int64)
+    i1 = cell % n1
+    i2 = (cell // n1) % n2
+    i3 = cell // (n1 * n2)
+    base = np.stack([i1, i2, i3]).astype(np.float64)            # [3][cells]
+    xi = (base[:, :, None] + o[:, None, :]).reshape(3, -1)       # cell-major
+    if jitter:
+        for d in range(3):
+            xi[d] += (gen.random(xi.shape[1]) - 0.5) / sub[d]
+    for d, n in enumerate((n1, n2, n3)):
+        xi[d] = np.mod(xi[d], n)
+    npart = xi.shape[1]
+    u = drift_momenta(npart, gamma, sigma_u, gen)
+    w = np.repeat(dens / ppc, ppc)
+    q, qm = -1.0, -1.0
+    E = np.zeros((3, n3, n2, n1))
+    jbg = -mean_current(u, w, q, cells)
+    return dict(name=name or "drift3d_%dx%dx%d_g%g" % (n1, n2, n3, gamma), geom=3,
+                n=(n1, n2, n3), dx=(dx, dx, dx), dt=dt, alpha=alpha, xi=xi, u=u, w=w, q=q, qm=qm,
+                E=E, B=E.copy(), jbg=jbg, seed=seed, steps=500)
 
 
 def nci_table1(seed=SEED0 + 10, ppc=(2, 2), n=(256, 256)):
