@@ -49,6 +49,8 @@ def parse():
                     help="T1,T2,K: fixed tile shape and sort interval instead of the autotuner")
     ap.add_argument("--scan-steps", type=int, default=200,
                     help="steps of the 64-run parameter scan (0: skip)")
+    ap.add_argument("--d3-steps", type=int, default=500,
+                    help="steps of the 3D 512x128x128 drifting-plasma leg (0: skip)")
     ap.add_argument("--n1", type=int, default=2048)
     ap.add_argument("--n2", type=int, default=512)
     return ap.parse_args()
@@ -183,6 +185,48 @@ def scan_leg(hpic, torch, W, steps, tune_steps):
                     "errors after all %d steps" % (tune_steps, warm, tune_steps + warm + steps)}
 
 
+def d3_leg(hpic, torch, W, steps, tune_steps):
+    """3D Cartesian leg: 512 x 128 x 128 cells, 16.8M particles, gamma = 50,
+    density +-5%.  Particle-steps/s of the FP32 form (graph-replayed) and the
+    FP64 form over `steps` steps, then the FP32-vs-FP64 relative L2 error of E,
+    B and J and the Gauss and continuity residuals of the FP32 form."""
+    d = W.drift3d()
+    npart = d["w"].size
+    warm = 10
+    tune = min(tune_steps, 400)
+    a, t32, kt = run_form(hpic, torch, [d], "fp32", warm, steps, profile=True, tune_steps=tune)
+    kt.pop("profiled_wall_s")
+    push_stats = kt.pop("push_stats")
+    tiling = a.tiling()
+    b, t64, _ = run_form(hpic, torch, [d], "fp64", warm, steps, tune_steps=tune)
+    a.diagnostics(0)
+    b.diagnostics(0)
+    a.step(1)
+    b.step(1)
+    da = a.diagnostics(0)
+    Ea, Ba = a.fields(0)
+    Eb, Bb = b.fields(0)
+    ja = np.stack([a.current(0, c) for c in range(3)])
+    jb = np.stack([b.current(0, c) for c in range(3)])
+    a.close()
+    b.close()
+    v32 = npart * steps / t32
+    pd_ms, pd_n = kt["push_deposit"]
+    cells = int(np.prod(d["n"]))
+    rho_scale = abs(da["charge_total"]) / (cells * float(np.prod(d["dx"])))
+    return {"workload": d["name"], "n": list(d["n"]), "particles": npart, "steps": steps,
+            "value": v32, "unit": "particle-steps/s", "ms_per_step": 1e3 * t32 / steps,
+            "fp64_form": {"value": npart * steps / t64, "ms_per_step": 1e3 * t64 / steps,
+                          "fp32_speedup": t64 / t32},
+            "kernels": {k: {"avg_us": 1e3 * ms / max(n, 1), "launches": n} for k, (ms, n) in kt.items()},
+            "lds_fallback_tiles": push_stats["fallback_tiles"], "tiling": tiling,
+            "err_vs_fp64": {"after_steps": tune + warm + steps + 1, "E_rel_l2": rel_l2(Ea, Eb),
+                            "B_rel_l2": rel_l2(Ba, Bb), "J_rel_l2": rel_l2(ja, jb),
+                            "gauss_rel_l2_fp32": da["gauss_l2"] / max(da["gauss_ref_l2"], 1e-300),
+                            "continuity_linf_rel_fp32": da["cont_linf"] * d["dt"] / max(rho_scale, 1e-300)},
+            "push_deposit_alg_GBps": (60 * npart + 72 * cells) / (pd_ms / max(pd_n, 1) * 1e-3) / 1e9}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -270,6 +314,8 @@ def main():
         b.close()
     if args.scan_steps > 0:
         out["scan2d"] = scan_leg(hpic, torch, W, args.scan_steps, args.tune_steps)
+    if args.d3_steps > 0:
+        out["drift3d"] = d3_leg(hpic, torch, W, args.d3_steps, args.tune_steps)
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
         x = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -19,6 +19,11 @@
  * fastest; Yee staggering of Eqs. (1)-(6): E1 (i1+1/2, i2), E2 (i1, i2+1/2),
  * E3 (i1, i2), B1 (i1, i2+1/2), B2 (i1+1/2, i2), B3 (i1+1/2, i2+1/2), j like E,
  * rho on (i1, i2); a half-integer position i+1/2 is stored at index i.
+ * 3D (HP_GEOM_3D, Sec. 2.2: the x3 differences added to the hybrid update):
+ * n1 x n2 x n3 cells, arrays [i3][i2][i1], E1 (i1+1/2, i2, i3), E2 (i1, i2+1/2,
+ * i3), E3 (i1, i2, i3+1/2), B1 (i1, i2+1/2, i3+1/2), B2 (i1+1/2, i2, i3+1/2),
+ * B3 (i1+1/2, i2+1/2, i3); the transforms run along x1 over the n2 n3 rows.
+ * Below, "[dim]" is 2 or 3 and "cells" n1 n2 (2D) or n1 n2 n3 (3D).
  * Units: c = 1, t in 1/w_p, x in c/w_p, E and B in m c w_p / e, density in
  * n_p, current in e n_p c (the 4 pi of the paper's Gaussian form is 1).
  *
@@ -46,6 +51,7 @@ extern "C" {
 #define HP_ESTATE (-7)   /* call out of order (e.g. step before particles) */
 
 #define HP_GEOM_2D 2
+#define HP_GEOM_3D 3
 
 #define HP_PREC_FP32_FIXED 0 /* FP32 push/FFT/update, 64-bit fixed-point deposit */
 #define HP_PREC_FP64 1       /* FP64 everywhere, FP64 atomics in the deposit */
@@ -63,7 +69,7 @@ extern "C" {
  * dt <= 2 / sqrt(pi^2/dx1^2 + 4/dx2^2) of Eq. (22) (for deriv1 = 1 the Yee
  * limit 1/sqrt(1/dx1^2 + 1/dx2^2)), otherwise HP_ECOURANT. */
 typedef struct hp_config {
-  int32_t geom;              /* HP_GEOM_2D */
+  int32_t geom;              /* HP_GEOM_2D or HP_GEOM_3D (same for all runs of a handle) */
   int32_t n[3];              /* cells per direction (n[2] unused in 2D) */
   double dx[3];              /* cell sizes */
   double dt;                 /* time step */
@@ -113,7 +119,7 @@ const char *hp_last_error(void);
 int hp_set_stream(hp_sim *sim, void *hip_stream);
 
 /* Loads n particles of one species into a run (replacing any previous ones).
- * x is [2][n] in physical units (wrapped into the box), u = gamma v is [3][n],
+ * x is [dim][n] in physical units (wrapped into the box), u = gamma v is [3][n],
  * w[n] the density weight (charge density = q sum w S).  Host buffers are
  * caller-owned and copied before return.  Sets the fixed-point charge unit of
  * the run.  Errors: HP_EINVAL (species != 0, n out of range, non-finite
@@ -121,8 +127,8 @@ int hp_set_stream(hp_sim *sim, void *hip_stream);
 int hp_set_particles(hp_sim *sim, int32_t run, int32_t species, int64_t n, const double *x,
                      const double *u, const double *w, double q_over_m, double q);
 
-/* Sets E^0 and B^0 of a run from host arrays E[3][n2][n1], B[3][n2][n1] at
- * their Yee nodes (mode must be 0 in 2D). */
+/* Sets E^0 and B^0 of a run from host arrays E[3][cells], B[3][cells] at
+ * their Yee nodes (mode must be 0). */
 int hp_set_fields(hp_sim *sim, int32_t run, int32_t mode, const double *E, const double *B);
 
 /* Background of a run: with rho_from_particles = 1 the fixed charge density
@@ -148,7 +154,8 @@ typedef struct hp_tune {
   int32_t steps;          /* hp_autotune: steps advanced */
 } hp_tune;
 
-/* Sets the tile shape (1..4096 cells per direction) and sort interval
+/* Sets the tile shape (1..4096 cells per direction; 3D tiles are
+ * tile1 x tile2 x tile2) and sort interval
  * (1..1024 steps) and re-sorts the particles.  Results of the FP32_FIXED form
  * are bit-identical for every setting.  HP_EINVAL out of range. */
 int hp_set_tiling(hp_sim *sim, int32_t tile1, int32_t tile2, int32_t sort_interval);
@@ -171,7 +178,7 @@ int hp_use_graphs(hp_sim *sim, int32_t enable);
 int hp_synchronize(hp_sim *sim);
 
 /* Copies field component comp (0..2 = E1..E3, 3..5 = B1..B3) of a run into
- * out[count], count = n1 n2 (else HP_EINVAL).  Synchronous. */
+ * out[count], count = cells (else HP_EINVAL).  Synchronous. */
 int hp_get_field(hp_sim *sim, int32_t run, int32_t comp, int32_t mode, double *out,
                  size_t count);
 
@@ -187,13 +194,13 @@ int hp_get_current_fixed(hp_sim *sim, int32_t run, int32_t comp, int64_t *out, s
 /* Number of particles of a run. */
 int hp_get_particle_count(hp_sim *sim, int32_t run, int64_t *n);
 
-/* Particles of a run in the library's current order: x[2][n] physical
+/* Particles of a run in the library's current order: x[dim][n] physical
  * positions, u[3][n], w[n], id[n] (index given at hp_set_particles).  Any
  * pointer may be NULL.  n must equal the particle count. */
 int hp_get_particles(hp_sim *sim, int32_t run, int64_t n, double *x, double *u, double *w,
                      int64_t *id);
 
-/* FP32_FIXED only: raw state, cell[2][n] (i1, i2), off[2][n] in [0,1),
+/* FP32_FIXED only: raw state, cell[dim][n] (i1, i2, i3), off[dim][n] in [0,1),
  * u[3][n], qw[n] (charge times weight), id[n].  Any pointer may be NULL. */
 int hp_get_particles_raw(hp_sim *sim, int32_t run, int64_t n, int32_t *cell, float *off,
                          float *u, float *qw, int32_t *id);
@@ -216,7 +223,9 @@ int hp_debug_deposit(hp_sim *sim, int32_t run, int64_t n, const int32_t *cell0,
                      const float *v3, const float *qw, int64_t *j_out);
 
 /* FP32_FIXED only: out[0] = P, out[1] = inv_wunit, out[2] = c3, out[3] = Q of a
- * run (the fixed-point parameters of the deposit). */
+ * run (the fixed-point parameters of the deposit).  3D: out[0] = 0, out[2] = cj,
+ * the integer scale of the per-node contributions (j_d = -(dx_d/dt) J_d /
+ * (6 inv_wunit cj)). */
 int hp_get_fixed_params(hp_sim *sim, int32_t run, double *out);
 
 /* Per-kernel timing with HIP events on the handle's stream: enable = 1 starts

@@ -25,13 +25,14 @@ struct Item {
   int b;
 };
 
-// Particle state (structure of arrays): cell[np] (linear i2*n1 + i1),
-// f1/f2[np] offsets in [0,1), u1..u3[np] momenta u = gamma v, qw[np] charge
-// times weight, id[np] load index.
+// Particle state (structure of arrays): cell[np] packed cell index
+// i1 | i2 << log2n1 | i3 << sh3 (2D: i3 = 0, so the packed index is the
+// linear one), f1/f2/f3[np] offsets in [0,1) (f3 only in 3D), u1..u3[np]
+// momenta u = gamma v, qw[np] charge times weight, id[np] load index.
 template <class R>
 struct Parts {
   int *cell, *id;
-  R *f1, *f2, *u1, *u2, *u3, *qw;
+  R *f1, *f2, *f3, *u1, *u2, *u3, *qw;
 };
 
 // Device-side description of one 2D run.  Arrays are owned by the host runtime.
@@ -52,7 +53,11 @@ template <class R>
 struct Run {
   using C = typename Cplx<R>::T;
   using Acc = typename AccOf<R>::T;
-  int n1, n2, log2n1, nk;
+  int dim;           // 2 or 3
+  int n1, n2, n3, log2n1, nk;
+  int sh3;           // 3D: shift of i3 in the packed cell index
+  int rows;          // n2 * n3: rows of the x1 transforms
+  int cells;         // n1 * rows
   int np;
   int P;             // fixed point: shape factors in units of 2^-P
   float inv_wunit;   // fixed point: integer charge = rint(qw * inv_wunit)
@@ -62,12 +67,14 @@ struct Run {
   R dtdx1, dtdx2;    // dt/dx1, dt/dx2 (position advance in cells per unit velocity)
   R qmhdt;           // (q/m) dt/2
   R jfx1, jfx2;      // FP64 form: -dx1/dt, -dx2/dt (current of a unit-charge move)
+  R idx3, dtdx3, jfx3;  // 3D: 1/dx3, dt/dx3, -dx3/dt
+  float cj;          // 3D FP32 form: integer scale of the per-node contributions
   R inv_m;           // 1/M, M = n1/2 (inverse real FFT normalisation)
   R jbg0[3];         // n1 * j_bg: added to the kappa = 0 bin of every row
   Parts<R> pt[2];
-  int T1, T2, nt1, nt2, ntiles;
+  int T1, T2, T3, nt1, nt2, nt3, ntiles;
   int *tile_start, *tile_cnt;
-  int *tile_box;     // [ntiles][4]: lo1, hi1, lo2, hi2 of the tile's particle cells
+  int *tile_box;     // [ntiles][6]: lo1, hi1, lo2, hi2, lo3, hi3 of the tile's particle cells
                      // relative to the tile origin (updated by every push)
   R *F;
   double2 *Fk[2];
@@ -75,7 +82,7 @@ struct Run {
   C *Jk;
   const C *tw;       // [n1]: exp(-2 pi i m / n1)
   const double *sym; // [nk][4]: i k1 xi+ (re, im), i k1 xi- (re, im)
-  double mdt, mhdt, midx2;  // dt, dt/2, 1/dx2 of the FP64 field update
+  double mdt, mhdt, midx2, midx3;  // dt, dt/2, 1/dx2, 1/dx3 of the FP64 field update
   const R *jfac;     // [nk][3]: factor on the transformed accumulator per component
 };
 
@@ -263,6 +270,12 @@ struct Launch {
                     hipStream_t s);
   static void kupdate(const Run<R> *runs, const Item *items, int nitems, int parity,
                       hipStream_t s);
+  // 3D: the same update as two passes (E and the half-step B, then B)
+  static void kupdate3(const Run<R> *runs, const Item *items, int nitems, int parity,
+                       hipStream_t s);
+  static void push_deposit3(const Run<R> *runs, const Item *items, int nitems, int parity,
+                            int pp, int lds_bytes, unsigned *err, unsigned *stats,
+                            hipStream_t s);
   static void ifft_eb(const Run<R> *runs, const Item *items, int nitems, int parity, int maxM,
                       hipStream_t s);
   static void fields_to_k(const Run<R> *runs, const Item *items, int nitems, int parity,
@@ -270,6 +283,19 @@ struct Launch {
 };
 
 // Diagnostics and helpers (FP64 unless noted).
+// 3D: charge density in FP64 from the particle state (any form).
+template <class R>
+void launch_rho3(const Run<R> *run_dev, int pp, int np, double *rho, hipStream_t s);
+// 3D Gauss residual per row (i2, i3) of the k-space master copy; rows_out [rows][3].
+template <class R>
+void launch_gauss3(const Run<R> *run_dev, int rows, int n1, int parity, const double *rho,
+                   const double2 *tw64, const double *sym64, const double *filt, double idx2,
+                   double idx3, double *rows_out, hipStream_t s);
+// 3D continuity residual max |(rho_n - rho_o)/dt + div j| with j = fac[d] * J.
+template <class A>
+void launch_cont3(const double *rn, const double *ro, const A *J, int n1, int n2, int n3,
+                  double dt, double f1, double f2, double f3, double idx1, double idx2,
+                  double idx3, double *partial, int nblocks, hipStream_t s);
 void launch_rho_fixed(const Run<float> *run_dev, int pp, int np, long long *rho, hipStream_t s);
 void launch_rho_fp64(const Run<double> *run_dev, int pp, int np, double *rho, hipStream_t s);
 template <class R>

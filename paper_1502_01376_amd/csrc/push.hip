@@ -493,7 +493,7 @@ k_push_deposit(const Run<R> *__restrict__ runs, const Item *__restrict__ items, 
   const int n1 = r.n1, n2 = r.n2, cells = n1 * n2;
   const int t2 = t / r.nt1, t1 = t - t2 * r.nt1;
   const int ref1 = t1 * r.T1, ref2 = t2 * r.T2;  // tile origin
-  const int *box = r.tile_box + 4 * t;
+  const int *box = r.tile_box + 6 * t;
   const int lo1 = box[0], hi1 = box[1], lo2 = box[2], hi2 = box[3];
   if (threadIdx.x == 0) {
     nbox[0] = 1 << 30; nbox[1] = -(1 << 30); nbox[2] = 1 << 30; nbox[3] = -(1 << 30);
@@ -595,7 +595,7 @@ k_push_deposit(const Run<R> *__restrict__ runs, const Item *__restrict__ items, 
     atomicMin(&nbox[2], blo2); atomicMax(&nbox[3], bhi2);
   }
   __syncthreads();
-  if (threadIdx.x < 4) r.tile_box[4 * t + threadIdx.x] = nbox[threadIdx.x];
+  if (threadIdx.x < 4) r.tile_box[6 * t + threadIdx.x] = nbox[threadIdx.x];
 }
 
 // ---------------------------------------------------------------- tile sort
@@ -605,7 +605,12 @@ k_push_deposit(const Run<R> *__restrict__ runs, const Item *__restrict__ items, 
 // step's results do not depend on it.
 template <class R>
 __device__ __forceinline__ int tile_of(const Run<R> &r, int cell) {
-  const int i1 = cell & (r.n1 - 1), i2 = cell >> r.log2n1;
+  const int i1 = cell & (r.n1 - 1);
+  if (r.dim == 3) {
+    const int i2 = (cell >> r.log2n1) & ((1 << (r.sh3 - r.log2n1)) - 1), i3 = cell >> r.sh3;
+    return ((i3 / r.T3) * r.nt2 + i2 / r.T2) * r.nt1 + i1 / r.T1;
+  }
+  const int i2 = cell >> r.log2n1;
   return (i2 / r.T2) * r.nt1 + i1 / r.T1;
 }
 
@@ -674,13 +679,17 @@ __global__ void __launch_bounds__(1024) k_sort_scan(const Run<R> *runs, const It
     // is expressed in the frame the push uses (cell minus tile origin, wrapped
     // into [-n/2, n - n/2)), so a tile wider than half the grid covers the
     // whole wrapped range
-    const int t2 = t / r.nt1, t1 = t - t2 * r.nt1;
-    const int w1 = min(r.T1, r.n1 - t1 * r.T1), w2 = min(r.T2, r.n2 - t2 * r.T2);
-    const bool full1 = w1 > r.n1 - (r.n1 >> 1), full2 = w2 > r.n2 - (r.n2 >> 1);
-    r.tile_box[4 * t + 0] = full1 ? -(r.n1 >> 1) : 0;
-    r.tile_box[4 * t + 1] = full1 ? r.n1 - (r.n1 >> 1) - 1 : w1 - 1;
-    r.tile_box[4 * t + 2] = full2 ? -(r.n2 >> 1) : 0;
-    r.tile_box[4 * t + 3] = full2 ? r.n2 - (r.n2 >> 1) - 1 : w2 - 1;
+    const int t3 = t / (r.nt1 * r.nt2), t12 = t - t3 * r.nt1 * r.nt2;
+    const int t2 = t12 / r.nt1, t1 = t12 - t2 * r.nt1;
+    const int w[3] = {min(r.T1, r.n1 - t1 * r.T1), min(r.T2, r.n2 - t2 * r.T2),
+                      min(r.T3, r.n3 - t3 * r.T3)};
+    const int nn[3] = {r.n1, r.n2, r.n3};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const bool full = w[d] > nn[d] - (nn[d] >> 1);
+      r.tile_box[6 * t + 2 * d] = full ? -(nn[d] >> 1) : 0;
+      r.tile_box[6 * t + 2 * d + 1] = full ? nn[d] - (nn[d] >> 1) - 1 : w[d] - 1;
+    }
   }
   if (threadIdx.x == 1023) r.tile_start[nt] = part[1023];
 }
@@ -713,6 +722,7 @@ __global__ void k_sort_scatter(const Run<R> *runs, const Item *chunks, int pp, i
   B.id[slot] = A.id[p];
   B.f1[slot] = A.f1[p];
   B.f2[slot] = A.f2[p];
+  if (r.dim == 3) B.f3[slot] = A.f3[p];
   B.u1[slot] = A.u1[p];
   B.u2[slot] = A.u2[p];
   B.u3[slot] = A.u3[p];

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -50,16 +51,21 @@ int ilog2(int n) {
 
 // Stability limit of the time step: Eq. (22) for the hybrid solver, the Yee
 // limit when the finite-difference x1 symbol is used.
+// In 3D the x3 difference adds 4/dx3^2 (1/dx3^2 for Yee) under the root.
 double courant_limit(const hp_config &c) {
-  const double a = c.dx[0], b = c.dx[1];
-  if (c.deriv1) return 1.0 / std::sqrt(1.0 / (a * a) + 1.0 / (b * b));
-  return 2.0 / std::sqrt(PI * PI / (a * a) + 4.0 / (b * b));
+  const double a = c.dx[0], b = c.dx[1], e = c.dx[2];
+  const bool three = c.geom == HP_GEOM_3D;
+  if (c.deriv1)
+    return 1.0 / std::sqrt(1.0 / (a * a) + 1.0 / (b * b) + (three ? 1.0 / (e * e) : 0.0));
+  return 2.0 / std::sqrt(PI * PI / (a * a) + 4.0 / (b * b) + (three ? 4.0 / (e * e) : 0.0));
 }
 
 const int SORT_CHUNK = 256;   // particles per sort workgroup
 const int UPD_BLOCK = 256;    // (i2, kappa) elements per update workgroup
 const int TILE1 = 32, TILE2 = 8;  // default particle tile (cells along x1, x2)
 const int SLACK1 = 2, SLACK2 = 1;  // drift beyond the tile the LDS budget allows for
+const int TILE1_3D = 8, TILE2_3D = 4;  // default 3D tile: 8 x 4 x 4 cells
+const double CJ3 = 268435456.0;        // 2^28: integer scale of the 3D FP32 deposit
 const int DEFAULT_SORT_INTERVAL = 16;
 
 struct Event2 {
@@ -127,6 +133,7 @@ class Sim : public SimBase {
     // diagnostics state
     Acc *rho0 = nullptr;   // rho_e at hp_set_background (nullptr: none)
     Acc *rho_prev = nullptr;
+    double *rho0_3 = nullptr, *rho_prev_3 = nullptr;  // 3D: FP64 charge density
     int64_t rho_prev_step = -2;
     int row0 = 0, grp0 = 0;  // first items of the run in the row/group lists
     // per-run particle count cells for headroom
@@ -158,7 +165,12 @@ class Sim : public SimBase {
       std::memset(&d, 0, sizeof d);
       d.n1 = c.n[0];
       d.n2 = c.n[1];
+      d.dim = c.geom == HP_GEOM_3D ? 3 : 2;
+      d.n3 = d.dim == 3 ? c.n[2] : 1;
+      d.rows = d.n2 * d.n3;
+      d.cells = d.n1 * d.rows;
       d.log2n1 = ilog2(d.n1);
+      d.sh3 = d.log2n1 + ilog2(d.n2);
       d.nk = d.n1 / 2 + 1;
       d.dt = (R)c.dt;
       d.hdt = (R)(0.5 * c.dt);
@@ -167,12 +179,18 @@ class Sim : public SimBase {
       d.dtdx2 = (R)(c.dt / c.dx[1]);
       d.jfx1 = (R)(-c.dx[0] / c.dt);
       d.jfx2 = (R)(-c.dx[1] / c.dt);
+      if (d.dim == 3) {
+        d.idx3 = (R)(1.0 / c.dx[2]);
+        d.dtdx3 = (R)(c.dt / c.dx[2]);
+        d.jfx3 = (R)(-c.dx[2] / c.dt);
+        d.cj = (float)CJ3;
+      }
       d.inv_m = (R)(2.0 / d.n1);
       d.P = c.fixed_shape_bits > 0 ? c.fixed_shape_bits : 20;
       d.inv_wunit = 1.0f;
       d.c3 = (float)(std::ldexp(1.0, 30 - 2 * d.P) / 6.0);
       maxM_ = std::max(maxM_, d.n1 / 2);
-      const size_t cells = (size_t)d.n1 * d.n2, kpl = (size_t)d.n2 * d.nk;
+      const size_t cells = (size_t)d.cells, kpl = (size_t)d.rows * d.nk;
       int rc;
       if ((rc = alloc(&d.F, 6 * cells))) return rc;
       if ((rc = alloc(&d.Fk[0], 6 * kpl))) return rc;  // FP64 master (both forms)
@@ -213,16 +231,17 @@ class Sim : public SimBase {
       d.mdt = c.dt;
       d.mhdt = 0.5 * c.dt;
       d.midx2 = 1.0 / c.dx[1];
+      d.midx3 = d.dim == 3 ? 1.0 / c.dx[2] : 0.0;
       d.jfac = djfac;
       if ((rc = upload_jfac(i))) return rc;
       h.row0 = (int)rows.size();
-      for (int r = 0; r < d.n2; ++r) rows.push_back(Item{i, r, 0});
+      for (int r = 0; r < d.rows; ++r) rows.push_back(Item{i, r, 0});
       h.grp0 = (int)grps.size();
-      for (int r = 0; r < d.n2; ++r) {
+      for (int r = 0; r < d.rows; ++r) {
         grps.push_back(Item{i, r, 0});
         grps.push_back(Item{i, r, 1});
       }
-      const int nel = d.n2 * d.nk;
+      const int nel = d.rows * d.nk;
       for (int e = 0; e < nel; e += UPD_BLOCK) upd.push_back(Item{i, e, 0});
       perrun.push_back(Item{i, 0, 0});
     }
@@ -230,7 +249,12 @@ class Sim : public SimBase {
       if (cfgs[i].sort_interval > 0) sort_interval_ = cfgs[i].sort_interval;
     int rc;
     if ((rc = alloc(&d_stats_, NSTAT))) return rc;
-    if ((rc = make_tiles(TILE1, TILE2))) return rc;
+    dim_ = runs_[0].d.dim;
+    if (dim_ == 3) {
+      tile1_ = TILE1_3D;
+      tile2_ = TILE2_3D;
+    }
+    if ((rc = make_tiles(tile1_, tile2_))) return rc;
     if ((rc = upload_items(perrun, &d_perrun_, &n_perrun_))) return rc;
     if ((rc = alloc(&d_runs_, nruns))) return rc;
     if ((rc = upload_items(rows, &d_rows_, &n_rows_))) return rc;
@@ -251,23 +275,26 @@ class Sim : public SimBase {
     if (n < 0 || n > 1000000000) return fail(HP_EINVAL, "particle count %lld out of range", (long long)n);
     if (n > 0 && (!x || !u || !w)) return fail(HP_EINVAL, "null particle array");
     if (!std::isfinite(qm) || !std::isfinite(q) || qm == 0.0) return fail(HP_EINVAL, "bad q/m or q");
-    const double L1 = h.cfg.dx[0] * d.n1, L2 = h.cfg.dx[1] * d.n2;
+    const double L1 = h.cfg.dx[0] * d.n1, L2 = h.cfg.dx[1] * d.n2, L3 = h.cfg.dx[2] * d.n3;
+    const bool three = d.dim == 3;
     std::vector<int> cell(n), id(n);
-    std::vector<R> f1(n), f2(n), u1(n), u2(n), u3(n), qw(n);
-    std::vector<int> count((size_t)d.n1 * d.n2, 0);
+    std::vector<R> f1(n), f2(n), f3(three ? n : 0), u1(n), u2(n), u3(n), qw(n);
+    std::vector<int> count((size_t)d.cells, 0);
     double qmax = 0.0, qmin = INFINITY;
     for (int64_t p = 0; p < n; ++p) {
-      const double x1 = x[p], x2 = x[n + p];
-      if (!std::isfinite(x1) || !std::isfinite(x2) || !std::isfinite(u[p]) ||
+      const double x1 = x[p], x2 = x[n + p], x3 = three ? x[2 * n + p] : 0.0;
+      if (!std::isfinite(x1) || !std::isfinite(x2) || !std::isfinite(x3) || !std::isfinite(u[p]) ||
           !std::isfinite(u[n + p]) || !std::isfinite(u[2 * n + p]) || !std::isfinite(w[p]))
         return fail(HP_EINVAL, "non-finite particle input at %lld", (long long)p);
-      int c1, c2;
-      R g1, g2;
+      int c1, c2, c3 = 0;
+      R g1, g2, g3 = 0;
       split(x1, L1, h.cfg.dx[0], d.n1, c1, g1);
       split(x2, L2, h.cfg.dx[1], d.n2, c2, g2);
-      cell[p] = (c2 << d.log2n1) | c1;
+      if (three) split(x3, L3, h.cfg.dx[2], d.n3, c3, g3);
+      cell[p] = (c3 << d.sh3) | (c2 << d.log2n1) | c1;
       f1[p] = g1;
       f2[p] = g2;
+      if (three) f3[p] = g3;
       u1[p] = (R)u[p];
       u2[p] = (R)u[n + p];
       u3[p] = (R)u[2 * n + p];
@@ -276,9 +303,20 @@ class Sim : public SimBase {
       qmax = std::max(qmax, std::fabs((double)qw[p]));
       qmin = std::min(qmin, std::fabs((double)qw[p]));
       id[p] = (int)p;
-      count[(size_t)c2 * d.n1 + c1]++;
+      count[((size_t)c3 * d.n2 + c2) * d.n1 + c1]++;
     }
-    if (FIXED && n > 0) {
+    if (FIXED && n > 0 && three) {
+      // 3D: each node's contribution is at most 3.4 cj in integers, a node
+      // collects from the particles of 4 x 4 x 4 cells
+      if (!(qmax > 0.0)) return fail(HP_EINVAL, "all particle charges are zero");
+      const int cmax = *std::max_element(count.begin(), count.end());
+      if (64.0 * std::max(cmax, 1) * 4.0 * CJ3 >= std::ldexp(1.0, 62))
+        return fail(HP_ERANGE, "fixed-point headroom: %d particles in one cell", cmax);
+      h.Qbits = 0;
+      d.unit_charge = 0;
+      d.inv_wunit = (float)(1.0 / qmax);
+      d.cj = (float)CJ3;
+    } else if (FIXED && n > 0) {
       if (!(qmax > 0.0)) return fail(HP_EINVAL, "all particle charges are zero");
       const int cmax = *std::max_element(count.begin(), count.end());
       // per node |J| <= 24 * (particles per cell) * 2^(2P+Q): keep below 2^62
@@ -318,7 +356,8 @@ class Sim : public SimBase {
     if ((rc = h2d(A.cell, cell.data(), n)) || (rc = h2d(A.id, id.data(), n)) ||
         (rc = h2d(A.f1, f1.data(), n)) || (rc = h2d(A.f2, f2.data(), n)) ||
         (rc = h2d(A.u1, u1.data(), n)) || (rc = h2d(A.u2, u2.data(), n)) ||
-        (rc = h2d(A.u3, u3.data(), n)) || (rc = h2d(A.qw, qw.data(), n)))
+        (rc = h2d(A.u3, u3.data(), n)) || (rc = h2d(A.qw, qw.data(), n)) ||
+        (three && (rc = h2d(A.f3, f3.data(), n))))
       return rc;
     if ((rc = upload_jfac(run))) return rc;
     if ((rc = rebuild_sort_items())) return rc;
@@ -329,7 +368,7 @@ class Sim : public SimBase {
   int set_fields(int run, const double *E, const double *B) override {
     RunHost &h = runs_[run];
     Run<R> &d = h.d;
-    const size_t cells = (size_t)d.n1 * d.n2;
+    const size_t cells = (size_t)d.cells;
     std::vector<R> F(6 * cells);
     for (size_t i = 0; i < 3 * cells; ++i) {
       if (!std::isfinite(E[i]) || !std::isfinite(B[i])) return fail(HP_EINVAL, "non-finite field");
@@ -338,7 +377,7 @@ class Sim : public SimBase {
     }
     int rc;
     if ((rc = h2d(d.F, F.data(), 6 * cells))) return rc;
-    Launch<R>::fields_to_k(d_runs_, d_grps_ + h.grp0, 2 * d.n2, parity_, maxM_, stream_);
+    Launch<R>::fields_to_k(d_runs_, d_grps_ + h.grp0, 2 * d.rows, parity_, maxM_, stream_);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream_));
     return HP_OK;
@@ -353,8 +392,13 @@ class Sim : public SimBase {
     }
     if (rho_from_particles) {
       int rc;
-      if (!h.rho0 && (rc = alloc(&h.rho0, (size_t)d.n1 * d.n2))) return rc;
-      if ((rc = deposit_rho(run, h.rho0))) return rc;
+      if (d.dim == 3) {
+        if (!h.rho0_3 && (rc = alloc(&h.rho0_3, (size_t)d.cells))) return rc;
+        if ((rc = deposit_rho3(run, h.rho0_3))) return rc;
+      } else {
+        if (!h.rho0 && (rc = alloc(&h.rho0, (size_t)d.cells))) return rc;
+        if ((rc = deposit_rho(run, h.rho0))) return rc;
+      }
     }
     return upload_runs();
   }
@@ -371,15 +415,22 @@ class Sim : public SimBase {
       since_sort_ = 0;
     }
     mark(HP_K_PUSH_DEPOSIT, true);
-    Launch<R>::push_deposit(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, all_unit(), d_err_,
-                            d_stats_, stream_);
+    if (dim_ == 3)
+      Launch<R>::push_deposit3(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, d_err_, d_stats_,
+                               stream_);
+    else
+      Launch<R>::push_deposit(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, all_unit(), d_err_,
+                              d_stats_, stream_);
     mark(HP_K_PUSH_DEPOSIT, false);
     ++since_sort_;
     mark(HP_K_FFT_J, true);
     Launch<R>::fft_j(d_runs_, d_rows_, n_rows_, p, maxM_, stream_);
     mark(HP_K_FFT_J, false);
     mark(HP_K_KUPDATE, true);
-    Launch<R>::kupdate(d_runs_, d_upd_, n_upd_, p, stream_);
+    if (dim_ == 3)
+      Launch<R>::kupdate3(d_runs_, d_upd_, n_upd_, p, stream_);
+    else
+      Launch<R>::kupdate(d_runs_, d_upd_, n_upd_, p, stream_);
     mark(HP_K_KUPDATE, false);
     mark(HP_K_IFFT_EB, true);
     Launch<R>::ifft_eb(d_runs_, d_grps_, n_grps_, p ^ 1, maxM_, stream_);
@@ -507,7 +558,11 @@ class Sim : public SimBase {
     };
     int best1 = tile1_, best2 = tile2_, bestK = sort_interval_ > 0 ? sort_interval_ : 16;
     double best = INFINITY;
-    const int shapes[][2] = {{32, 8}, {64, 4}, {16, 16}, {64, 8}, {32, 16}, {128, 4}, {16, 8}, {128, 2}};
+    // 2D tiles t1 x t2; 3D tiles t1 x t2 x t2
+    const std::vector<std::array<int, 2>> shapes =
+        dim_ == 3 ? std::vector<std::array<int, 2>>{{8, 4}, {16, 4}, {8, 8}, {16, 2}, {4, 4}, {32, 2}}
+                  : std::vector<std::array<int, 2>>{{32, 8}, {64, 4}, {16, 16}, {64, 8}, {32, 16},
+                                                    {128, 4}, {16, 8}, {128, 2}};
     std::vector<std::vector<int>> seen;
     const int K0 = bestK;
     for (const auto &sh : shapes) {
@@ -515,6 +570,7 @@ class Sim : public SimBase {
       for (const RunHost &h : runs_) {
         key.push_back(std::min(sh[0], h.d.n1));
         key.push_back(std::min(sh[1], h.d.n2));
+        key.push_back(std::min(sh[1], h.d.n3));
       }
       if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
       seen.push_back(key);
@@ -563,7 +619,7 @@ class Sim : public SimBase {
 
   int get_field(int run, int comp, double *out, size_t count) override {
     const Run<R> &d = runs_[run].d;
-    const size_t cells = (size_t)d.n1 * d.n2;
+    const size_t cells = (size_t)d.cells;
     if (comp < 0 || comp > 5 || count != cells || !out) return fail(HP_EINVAL, "bad field request");
     int rc;
     if ((rc = sync())) return rc;
@@ -576,15 +632,15 @@ class Sim : public SimBase {
   int get_current(int run, int comp, int corrected, double *out, size_t count) override {
     const RunHost &h = runs_[run];
     const Run<R> &d = h.d;
-    const size_t cells = (size_t)d.n1 * d.n2;
+    const size_t cells = (size_t)d.cells;
     if (comp < 0 || comp > 2 || count != cells || !out) return fail(HP_EINVAL, "bad current request");
     int rc;
     if ((rc = sync())) return rc;
     if (corrected) {
       R *tmp;
       if ((rc = alloc(&tmp, cells))) return rc;
-      launch_inverse_rows<R>(d.Jk + (size_t)comp * d.n2 * d.nk, d.nk, d.n1, d.n2, d.tw, d.inv_m,
-                             tmp, stream_);
+      launch_inverse_rows<R>(d.Jk + (size_t)comp * d.rows * d.nk, d.nk, d.n1, d.rows, d.tw,
+                             d.inv_m, tmp, stream_);
       std::vector<R> host(cells);
       rc = d2h(host.data(), tmp, cells);
       release(tmp);
@@ -602,7 +658,7 @@ class Sim : public SimBase {
   int get_current_fixed(int run, int comp, int64_t *out, size_t count) override {
     if (!FIXED) return fail(HP_EINVAL, "fixed-point current exists only in the FP32 form");
     const Run<R> &d = runs_[run].d;
-    const size_t cells = (size_t)d.n1 * d.n2;
+    const size_t cells = (size_t)d.cells;
     if (comp < 0 || comp > 2 || count != cells || !out) return fail(HP_EINVAL, "bad current request");
     int rc;
     if ((rc = sync())) return rc;
@@ -621,19 +677,23 @@ class Sim : public SimBase {
     if (n != h.np) return fail(HP_EINVAL, "particle count mismatch");
     int rc;
     if ((rc = sync())) return rc;
+    const bool three = d.dim == 3;
     std::vector<int> cell(n), pid(n);
-    std::vector<R> f1(n), f2(n), a(n), b(n), c(n), qw(n);
+    std::vector<R> f1(n), f2(n), f3(three ? n : 0), a(n), b(n), c(n), qw(n);
     const Parts<R> &A = d.pt[pp_];
     if ((rc = d2h(cell.data(), A.cell, n)) || (rc = d2h(pid.data(), A.id, n)) ||
         (rc = d2h(f1.data(), A.f1, n)) || (rc = d2h(f2.data(), A.f2, n)) ||
         (rc = d2h(a.data(), A.u1, n)) || (rc = d2h(b.data(), A.u2, n)) ||
-        (rc = d2h(c.data(), A.u3, n)) || (rc = d2h(qw.data(), A.qw, n)))
+        (rc = d2h(c.data(), A.u3, n)) || (rc = d2h(qw.data(), A.qw, n)) ||
+        (three && (rc = d2h(f3.data(), A.f3, n))))
       return rc;
     for (int64_t p = 0; p < n; ++p) {
-      const int i1 = cell[p] & (d.n1 - 1), i2 = cell[p] >> d.log2n1;
+      int i1, i2, i3;
+      unpack_cell(d, cell[p], i1, i2, i3);
       if (x) {
         x[p] = ((double)i1 + (double)f1[p]) * h.cfg.dx[0];
         x[n + p] = ((double)i2 + (double)f2[p]) * h.cfg.dx[1];
+        if (three) x[2 * n + p] = ((double)i3 + (double)f3[p]) * h.cfg.dx[2];
       }
       if (u) {
         u[p] = a[p];
@@ -657,12 +717,18 @@ class Sim : public SimBase {
     const Parts<R> &A = d.pt[pp_];
     std::vector<int> cell(n);
     if ((rc = d2h(cell.data(), A.cell, n))) return rc;
+    const bool three = d.dim == 3;
     if (cellout)
       for (int64_t p = 0; p < n; ++p) {
-        cellout[p] = cell[p] & (d.n1 - 1);
-        cellout[n + p] = cell[p] >> d.log2n1;
+        int i1, i2, i3;
+        unpack_cell(d, cell[p], i1, i2, i3);
+        cellout[p] = i1;
+        cellout[n + p] = i2;
+        if (three) cellout[2 * n + p] = i3;
       }
-    if (off && ((rc = d2h((R *)off, A.f1, n)) || (rc = d2h((R *)off + n, A.f2, n)))) return rc;
+    if (off && ((rc = d2h((R *)off, A.f1, n)) || (rc = d2h((R *)off + n, A.f2, n)) ||
+                (three && (rc = d2h((R *)off + 2 * n, A.f3, n)))))
+      return rc;
     if (u && ((rc = d2h((R *)u, A.u1, n)) || (rc = d2h((R *)u + n, A.u2, n)) ||
               (rc = d2h((R *)u + 2 * n, A.u3, n))))
       return rc;
@@ -671,7 +737,97 @@ class Sim : public SimBase {
     return HP_OK;
   }
 
+  // 3D diagnostics: energies, kinetic energy, FP64 charge density, Gauss
+  // residual over the rows (i2, i3) and the FP64 continuity residual of the
+  // last step (the 3D deposit is exact to FP32 rounding, so cont_int is -1).
+  int diagnostics3(int run, hp_diag *out) {
+    RunHost &h = runs_[run];
+    Run<R> &d = h.d;
+    const size_t cells = (size_t)d.cells;
+    const double dV = h.cfg.dx[0] * h.cfg.dx[1] * h.cfg.dx[2];
+    int rc;
+    if ((rc = sync())) return rc;
+    std::memset(out, 0, sizeof *out);
+    out->step = step_;
+    const int nb = 256;
+    double *part;
+    if ((rc = alloc(&part, 6 * nb))) return rc;
+    launch_energy<R>(d.F, (long long)cells, part, nb, stream_);
+    std::vector<double> hp(6 * nb);
+    rc = d2h(hp.data(), part, 6 * nb);
+    if (rc) { release(part); return rc; }
+    for (int b = 0; b < nb; ++b)
+      for (int c = 0; c < 3; ++c) {
+        out->W_E[c] += 0.5 * dV * hp[6 * b + c];
+        out->W_B[c] += 0.5 * dV * hp[6 * b + 3 + c];
+      }
+    if (h.np > 0) {
+      launch_kinetic<R>(d_runs_ + run, pp_, part, nb, stream_);
+      rc = d2h(hp.data(), part, nb);
+      if (rc) { release(part); return rc; }
+      double sk = 0;
+      for (int b = 0; b < nb; ++b) sk += hp[b];
+      out->kinetic = sk * dV / h.qm;
+    }
+    release(part);
+    double *rho;
+    if ((rc = alloc(&rho, cells))) return rc;
+    if ((rc = deposit_rho3(run, rho))) { release(rho); return rc; }
+    std::vector<double> rn(cells), r0;
+    if ((rc = d2h(rn.data(), rho, cells))) { release(rho); return rc; }
+    if (h.rho0_3) {
+      r0.resize(cells);
+      if ((rc = d2h(r0.data(), h.rho0_3, cells))) { release(rho); return rc; }
+    }
+    std::vector<double> tot(cells);
+    double qsum = 0;
+    for (size_t i = 0; i < cells; ++i) {
+      tot[i] = h.rho0_3 ? rn[i] - r0[i] : rn[i];
+      qsum += rn[i];
+    }
+    out->charge_total = qsum * dV;
+    double *dtot, *rows;
+    if ((rc = alloc(&dtot, cells)) || (rc = alloc(&rows, 3 * (size_t)d.rows))) { release(rho); return rc; }
+    if ((rc = h2d(dtot, tot.data(), cells))) { release(rho); release(dtot); release(rows); return rc; }
+    launch_gauss3<R>(d_runs_ + run, d.rows, d.n1, parity_, dtot, h.tw64, h.sym64, h.filt64,
+                     1.0 / h.cfg.dx[1], 1.0 / h.cfg.dx[2], rows, stream_);
+    std::vector<double> hr(3 * (size_t)d.rows);
+    rc = d2h(hr.data(), rows, 3 * (size_t)d.rows);
+    release(dtot);
+    release(rows);
+    if (rc) { release(rho); return rc; }
+    double s2 = 0, smax = 0, sref = 0;
+    for (int r = 0; r < d.rows; ++r) {
+      s2 += hr[3 * r];
+      smax = std::max(smax, hr[3 * r + 1]);
+      sref += hr[3 * r + 2];
+    }
+    out->gauss_l2 = std::sqrt(s2);
+    out->gauss_linf = smax;
+    out->gauss_ref_l2 = std::sqrt(sref);
+    out->cont_linf = -1.0;
+    out->cont_int = -1;
+    if (h.rho_prev_3 && h.rho_prev_step == step_ - 1 && step_ > 0) {
+      const int nbc = 256;
+      double *pm;
+      if ((rc = alloc(&pm, nbc))) { release(rho); return rc; }
+      launch_cont3<Acc>(rho, h.rho_prev_3, d.J[parity_ ^ 1], d.n1, d.n2, d.n3, h.cfg.dt,
+                        acc_factor(h, 0), acc_factor(h, 1), acc_factor(h, 2), 1.0 / h.cfg.dx[0],
+                        1.0 / h.cfg.dx[1], 1.0 / h.cfg.dx[2], pm, nbc, stream_);
+      std::vector<double> hm(nbc);
+      rc = d2h(hm.data(), pm, nbc);
+      release(pm);
+      if (rc) { release(rho); return rc; }
+      out->cont_linf = *std::max_element(hm.begin(), hm.end());
+    }
+    if (h.rho_prev_3) release(h.rho_prev_3);
+    h.rho_prev_3 = rho;
+    h.rho_prev_step = step_;
+    return HP_OK;
+  }
+
   int diagnostics(int run, hp_diag *out) override {
+    if (runs_[run].d.dim == 3) return diagnostics3(run, out);
     RunHost &h = runs_[run];
     Run<R> &d = h.d;
     const size_t cells = (size_t)d.n1 * d.n2;
@@ -791,26 +947,36 @@ class Sim : public SimBase {
       std::memcpy(o, src, bytes);
       o += bytes;
     };
-    const int64_t hdr[6] = {0x48504943, 2, (int64_t)runs_.size(), FIXED ? 0 : 1, step_, parity_};
+    const int64_t hdr[6] = {0x48504943, 3, (int64_t)runs_.size(), FIXED ? 0 : 1, step_, parity_};
     put(hdr, sizeof hdr);
     for (RunHost &h : runs_) {
       Run<R> &d = h.d;
-      const size_t cells = (size_t)d.n1 * d.n2, kpl = (size_t)d.n2 * d.nk;
+      const size_t cells = (size_t)d.cells, kpl = (size_t)d.rows * d.nk;
+      const bool has_rho0 = d.dim == 3 ? h.rho0_3 != nullptr : h.rho0 != nullptr;
       const double meta[12] = {(double)h.np, h.qm, h.q, (double)h.Qbits, (double)d.inv_wunit,
-                               (double)d.c3, h.jbg[0], h.jbg[1], h.jbg[2], h.rho0 ? 1.0 : 0.0,
-                               0, 0};
+                               (double)d.c3, h.jbg[0], h.jbg[1], h.jbg[2], has_rho0 ? 1.0 : 0.0,
+                               (double)d.P, 0};
       put(meta, sizeof meta);
       const int64_t n = h.np;
       const Parts<R> &A = d.pt[pp_];
       if ((rc = d2h((int *)o, A.cell, n))) return rc; o += sizeof(int) * n;
       if ((rc = d2h((int *)o, A.id, n))) return rc; o += sizeof(int) * n;
-      R *arrs[6] = {A.f1, A.f2, A.u1, A.u2, A.u3, A.qw};
-      for (R *a : arrs) { if ((rc = d2h((R *)o, a, n))) return rc; o += sizeof(R) * n; }
+      R *arrs[7] = {A.f1, A.f2, A.u1, A.u2, A.u3, A.qw, A.f3};
+      for (int k = 0; k < (d.dim == 3 ? 7 : 6); ++k) {
+        if ((rc = d2h((R *)o, arrs[k], n))) return rc;
+        o += sizeof(R) * n;
+      }
       if ((rc = d2h((R *)o, d.F, 6 * cells))) return rc; o += sizeof(R) * 6 * cells;
       if ((rc = d2h((double2 *)o, d.Fk[parity_], 6 * kpl))) return rc; o += sizeof(double2) * 6 * kpl;
       if ((rc = d2h((Acc *)o, d.J[parity_ ^ 1], 3 * cells))) return rc; o += sizeof(Acc) * 3 * cells;
       if ((rc = d2h((C *)o, d.Jk, 3 * kpl))) return rc; o += sizeof(C) * 3 * kpl;
-      if (h.rho0) { if ((rc = d2h((Acc *)o, h.rho0, cells))) return rc; o += sizeof(Acc) * cells; }
+      if (d.dim == 3 && h.rho0_3) {
+        if ((rc = d2h((double *)o, h.rho0_3, cells))) return rc;
+        o += sizeof(double) * cells;
+      } else if (d.dim == 2 && h.rho0) {
+        if ((rc = d2h((Acc *)o, h.rho0, cells))) return rc;
+        o += sizeof(Acc) * cells;
+      }
     }
     *size = need;
     return HP_OK;
@@ -826,7 +992,7 @@ class Sim : public SimBase {
       return true;
     };
     int64_t hdr[6];
-    if (!take(hdr, sizeof hdr) || hdr[0] != 0x48504943 || hdr[1] != 2 ||
+    if (!take(hdr, sizeof hdr) || hdr[0] != 0x48504943 || hdr[1] != 3 ||
         hdr[2] != (int64_t)runs_.size() || hdr[3] != (FIXED ? 0 : 1))
       return fail(HP_EINVAL, "state blob does not match this handle");
     int rc;
@@ -836,20 +1002,24 @@ class Sim : public SimBase {
     for (int i = 0; i < (int)runs_.size(); ++i) {
       RunHost &h = runs_[i];
       Run<R> &d = h.d;
-      const size_t cells = (size_t)d.n1 * d.n2, kpl = (size_t)d.n2 * d.nk;
+      const size_t cells = (size_t)d.cells, kpl = (size_t)d.rows * d.nk;
       double meta[12];
       if (!take(meta, sizeof meta)) return fail(HP_EINVAL, "truncated state");
       const int64_t n = (int64_t)meta[0];
-      const size_t pbytes = n * (2 * sizeof(int) + 6 * sizeof(R));
+      const int nR = d.dim == 3 ? 7 : 6;
+      const size_t rho_bytes = d.dim == 3 ? sizeof(double) : sizeof(Acc);
+      const size_t pbytes = n * (2 * sizeof(int) + nR * sizeof(R));
       const size_t fbytes = sizeof(R) * 6 * cells + sizeof(double2) * 6 * kpl +
                             sizeof(C) * 3 * kpl + sizeof(Acc) * 3 * cells +
-                            (meta[9] != 0 ? sizeof(Acc) * cells : 0);
+                            (meta[9] != 0 ? rho_bytes * cells : 0);
       if (o + pbytes + fbytes > end) return fail(HP_EINVAL, "truncated state");
       h.qm = meta[1];
       h.q = meta[2];
       h.Qbits = (int)meta[3];
       d.inv_wunit = (float)meta[4];
       d.c3 = (float)meta[5];
+      d.P = (int)meta[10];
+      d.unit_charge = (d.dim == 2 && h.Qbits + d.P <= 22) ? 1 : 0;
       for (int c = 0; c < 3; ++c) {
         h.jbg[c] = meta[6 + c];
         d.jbg0[c] = (R)(d.n1 * h.jbg[c]);
@@ -861,19 +1031,30 @@ class Sim : public SimBase {
       const Parts<R> &A = d.pt[pp_];
       if ((rc = h2d(A.cell, (const int *)o, n))) return rc; o += sizeof(int) * n;
       if ((rc = h2d(A.id, (const int *)o, n))) return rc; o += sizeof(int) * n;
-      R *arrs[6] = {A.f1, A.f2, A.u1, A.u2, A.u3, A.qw};
-      for (R *a : arrs) { if ((rc = h2d(a, (const R *)o, n))) return rc; o += sizeof(R) * n; }
+      R *arrs[7] = {A.f1, A.f2, A.u1, A.u2, A.u3, A.qw, A.f3};
+      for (int k = 0; k < nR; ++k) {
+        if ((rc = h2d(arrs[k], (const R *)o, n))) return rc;
+        o += sizeof(R) * n;
+      }
       if ((rc = h2d(d.F, (const R *)o, 6 * cells))) return rc; o += sizeof(R) * 6 * cells;
       if ((rc = h2d(d.Fk[parity_], (const double2 *)o, 6 * kpl))) return rc; o += sizeof(double2) * 6 * kpl;
       if ((rc = h2d(d.J[parity_ ^ 1], (const Acc *)o, 3 * cells))) return rc; o += sizeof(Acc) * 3 * cells;
       HIPCHK(hipMemsetAsync(d.J[parity_], 0, sizeof(Acc) * 3 * cells, stream_));
       if ((rc = h2d(d.Jk, (const C *)o, 3 * kpl))) return rc; o += sizeof(C) * 3 * kpl;
-      if (meta[9] != 0) {
+      if (meta[9] != 0 && d.dim == 3) {
+        if (!h.rho0_3 && (rc = alloc(&h.rho0_3, cells))) return rc;
+        if ((rc = h2d(h.rho0_3, (const double *)o, cells))) return rc;
+        o += sizeof(double) * cells;
+      } else if (meta[9] != 0) {
         if (!h.rho0 && (rc = alloc(&h.rho0, cells))) return rc;
         if ((rc = h2d(h.rho0, (const Acc *)o, cells))) return rc;
         o += sizeof(Acc) * cells;
       }
       h.rho_prev_step = -2;
+      if (h.rho_prev_3) {
+        release(h.rho_prev_3);
+        h.rho_prev_3 = nullptr;
+      }
       if ((rc = upload_jfac(i))) return rc;
     }
     if ((rc = rebuild_sort_items())) return rc;
@@ -885,6 +1066,7 @@ class Sim : public SimBase {
                     const float *o1, const float *v3, const float *qw, int64_t *J) override {
     if (!FIXED) return fail(HP_EINVAL, "the fixed-point deposit exists only in the FP32 form");
     const Run<R> &d = runs_[run].d;
+    if (d.dim != 2) return fail(HP_EINVAL, "the deposit test hook is 2D only");
     const size_t cells = (size_t)d.n1 * d.n2;
     if (n < 0 || n > 0x7fffffff) return fail(HP_EINVAL, "bad count");
     for (int64_t p = 0; p < n; ++p) {
@@ -921,9 +1103,9 @@ class Sim : public SimBase {
   int fixed_params(int run, double *out) override {
     if (!FIXED) return fail(HP_EINVAL, "fixed-point parameters exist only in the FP32 form");
     const RunHost &h = runs_[run];
-    out[0] = h.d.P;
+    out[0] = h.d.dim == 3 ? 0 : h.d.P;
     out[1] = h.d.inv_wunit;
-    out[2] = h.d.c3;
+    out[2] = h.d.dim == 3 ? h.d.cj : h.d.c3;
     out[3] = h.Qbits;
     return HP_OK;
   }
@@ -1042,22 +1224,26 @@ class Sim : public SimBase {
         }
       d.T1 = std::min(t1, d.n1);
       d.T2 = std::min(t2, d.n2);
+      d.T3 = d.dim == 3 ? std::min(t2, d.n3) : 1;
       d.nt1 = (d.n1 + d.T1 - 1) / d.T1;
       d.nt2 = (d.n2 + d.T2 - 1) / d.T2;
-      d.ntiles = d.nt1 * d.nt2;
+      d.nt3 = (d.n3 + d.T3 - 1) / d.T3;
+      d.ntiles = d.nt1 * d.nt2 * d.nt3;
       int rc;
       if ((rc = alloc(&d.tile_start, d.ntiles + 1)) || (rc = alloc(&d.tile_cnt, d.ntiles)) ||
-          (rc = alloc(&d.tile_box, 4 * d.ntiles)))
+          (rc = alloc(&d.tile_box, 6 * d.ntiles)))
         return rc;
       for (int t = 0; t < d.ntiles; ++t) tiles.push_back(Item{i, t, 0});
       // staged box of a tile whose particles spread SLACK cells beyond it
       const int b1 = std::min(d.T1 + 2 * SLACK1, d.n1) + 6;
       const int b2 = std::min(d.T2 + 2 * SLACK2, d.n2) + 6;
-      maxbox = std::max(maxbox, b1 * b2);
+      const int b3 = d.dim == 3 ? std::min(d.T3 + 2 * SLACK2, d.n3) + 6 : 1;
+      maxbox = std::max(maxbox, b1 * b2 * b3);
     }
     tile1_ = t1;
     tile2_ = t2;
-    const int node_bytes = FIXED ? 48 : 72;
+    // per node: 2D 3 accumulators + 6 staged field values; 3D accumulators only
+    const int node_bytes = dim_ == 3 ? 24 : (FIXED ? 48 : 72);
     push_lds_ = std::min(PUSH_LDS_MAX, std::max(PUSH_LDS_MIN, ((maxbox * node_bytes + 1023) / 1024) * 1024));
     if (d_tiles_) release(d_tiles_);
     d_tiles_ = nullptr;
@@ -1090,13 +1276,15 @@ class Sim : public SimBase {
     Run<R> &d = runs_[run].d;
     for (int b = 0; b < 2; ++b) {
       Parts<R> &A = d.pt[b];
-      void *old[8] = {A.cell, A.id, A.f1, A.f2, A.u1, A.u2, A.u3, A.qw};
+      void *old[9] = {A.cell, A.id, A.f1, A.f2, A.f3, A.u1, A.u2, A.u3, A.qw};
       for (void *o : old)
         if (o) release(o);
+      A.f3 = nullptr;
       int rc;
       if ((rc = alloc(&A.cell, n)) || (rc = alloc(&A.id, n)) || (rc = alloc(&A.f1, n)) ||
           (rc = alloc(&A.f2, n)) || (rc = alloc(&A.u1, n)) || (rc = alloc(&A.u2, n)) ||
-          (rc = alloc(&A.u3, n)) || (rc = alloc(&A.qw, n)))
+          (rc = alloc(&A.u3, n)) || (rc = alloc(&A.qw, n)) ||
+          (d.dim == 3 && (rc = alloc(&A.f3, n))))
         return rc;
     }
     return HP_OK;
@@ -1111,9 +1299,29 @@ class Sim : public SimBase {
     since_sort_ = 0;
     return HP_OK;
   }
+  static void unpack_cell(const Run<R> &d, int cell, int &i1, int &i2, int &i3) {
+    i1 = cell & (d.n1 - 1);
+    if (d.dim == 3) {
+      i2 = (cell >> d.log2n1) & ((1 << (d.sh3 - d.log2n1)) - 1);
+      i3 = cell >> d.sh3;
+    } else {
+      i2 = cell >> d.log2n1;
+      i3 = 0;
+    }
+  }
+  int deposit_rho3(int run, double *rho) {
+    RunHost &h = runs_[run];
+    HIPCHK(hipMemsetAsync(rho, 0, sizeof(double) * (size_t)h.d.cells, stream_));
+    launch_rho3<R>(d_runs_ + run, pp_, (int)h.np, rho, stream_);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream_));
+    return HP_OK;
+  }
   // Factor from the deposit accumulator to physical current (before filtering).
   double acc_factor(const RunHost &h, int comp) const {
     if (!FIXED) return 1.0;
+    if (h.d.dim == 3)
+      return -(h.cfg.dx[comp] / h.cfg.dt) / (6.0 * (double)h.d.inv_wunit * (double)h.d.cj);
     const int P = h.d.P;
     const double iw = (double)h.d.inv_wunit;
     if (comp == 0) return -(h.cfg.dx[0] / h.cfg.dt) / (iw * std::ldexp(1.0, 2 * P + 1));
@@ -1155,10 +1363,12 @@ class Sim : public SimBase {
   size_t state_size() const {
     size_t s = 6 * sizeof(int64_t);
     for (const RunHost &h : runs_) {
-      const size_t cells = (size_t)h.d.n1 * h.d.n2, kpl = (size_t)h.d.n2 * h.d.nk;
-      s += 12 * sizeof(double) + h.np * (2 * sizeof(int) + 6 * sizeof(R)) + sizeof(R) * 6 * cells +
-           sizeof(double2) * 6 * kpl + sizeof(C) * 3 * kpl + sizeof(Acc) * 3 * cells +
-           (h.rho0 ? sizeof(Acc) * cells : 0);
+      const size_t cells = (size_t)h.d.cells, kpl = (size_t)h.d.rows * h.d.nk;
+      const int nR = h.d.dim == 3 ? 7 : 6;
+      const size_t rho = h.d.dim == 3 ? (h.rho0_3 ? sizeof(double) * cells : 0)
+                                      : (h.rho0 ? sizeof(Acc) * cells : 0);
+      s += 12 * sizeof(double) + h.np * (2 * sizeof(int) + nR * sizeof(R)) + sizeof(R) * 6 * cells +
+           sizeof(double2) * 6 * kpl + sizeof(C) * 3 * kpl + sizeof(Acc) * 3 * cells + rho;
     }
     return s;
   }
@@ -1205,6 +1415,7 @@ class Sim : public SimBase {
   int sort_interval_ = DEFAULT_SORT_INTERVAL, since_sort_ = 0;
   unsigned *d_stats_ = nullptr;
   int tile1_ = TILE1, tile2_ = TILE2, push_lds_ = PUSH_LDS_MIN;
+  int dim_ = 2;
   double tuned_ms_ = 0.0;
   bool use_graphs_ = true;
   hipGraphExec_t graph_[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
@@ -1237,12 +1448,22 @@ int hp_create(const hp_config *cfgs, int32_t nruns, hp_sim **out) {
   const int prec = cfgs[0].precision;
   for (int i = 0; i < nruns; ++i) {
     const hp_config &c = cfgs[i];
-    if (c.geom != HP_GEOM_2D) return fail(HP_EINVAL, "run %d: only 2D Cartesian geometry is built", i);
+    if (c.geom != HP_GEOM_2D && c.geom != HP_GEOM_3D)
+      return fail(HP_EINVAL, "run %d: geometry must be 2D or 3D Cartesian", i);
+    if (c.geom != cfgs[0].geom) return fail(HP_EINVAL, "run %d: all runs of a handle share the geometry", i);
+    if (c.geom == HP_GEOM_3D) {
+      if (c.n[2] < 4 || !(c.dx[2] > 0))
+        return fail(HP_EINVAL, "run %d: n3 >= 4 and dx3 > 0 in 3D", i);
+      int b2 = 0;
+      while ((1 << b2) < c.n[1]) ++b2;
+      if ((int64_t)c.n[0] * ((int64_t)1 << b2) * c.n[2] > ((int64_t)1 << 31) - 1)
+        return fail(HP_EINVAL, "run %d: grid too large for the packed cell index", i);
+    }
     if (c.precision != prec || (prec != HP_PREC_FP32_FIXED && prec != HP_PREC_FP64))
       return fail(HP_EINVAL, "run %d: precision must be one of the two forms and equal for all runs", i);
     if (!is_pow2(c.n[0]) || c.n[0] < 8 || c.n[0] > 4096)
       return fail(HP_EINVAL, "run %d: n1 = %d must be a power of two in [8, 4096]", i, c.n[0]);
-    if (c.n[1] < 4 || (int64_t)c.n[0] * c.n[1] > (int64_t)1 << 30)
+    if (c.n[1] < 4 || (int64_t)c.n[0] * c.n[1] * (c.geom == HP_GEOM_3D ? c.n[2] : 1) > (int64_t)1 << 30)
       return fail(HP_EINVAL, "run %d: n2 = %d out of range", i, c.n[1]);
     if (!(c.dx[0] > 0) || !(c.dx[1] > 0) || !(c.dt > 0) || !std::isfinite(c.dt))
       return fail(HP_EINVAL, "run %d: non-positive cell size or time step", i);

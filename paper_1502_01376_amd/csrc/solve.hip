@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(256) k_fft_j(const Run<R> *__restrict__ runs,
   const Item it = items[blockIdx.x];
   const Run<R> &r = runs[it.run];
   const int row = it.a;
-  const int n1 = r.n1, M = n1 >> 1, log2M = r.log2n1 - 1, cells = n1 * r.n2;
+  const int n1 = r.n1, M = n1 >> 1, log2M = r.log2n1 - 1, cells = r.cells;
   const auto *Jin = r.J[parity];
   auto *Jz = r.J[parity ^ 1];
   for (int c = 0; c < 3; ++c) {
@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(256) k_fft_j(const Run<R> *__restrict__ runs,
       const R fk = r.jfac[k * 3 + c];
       Xk = cscale(Xk, fk);
       if (k == 0) Xk.x += r.jbg0[c];
-      C *out = r.Jk + (long long)c * r.n2 * nk + (long long)row * nk;
+      C *out = r.Jk + (long long)c * r.rows * nk + (long long)row * nk;
       out[k] = Xk;
       if (mk != k) {
         C Xm = r2c_post(Zmk, Zk, Wmk);
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(256) k_fields_to_k(const Run<R> *__restrict__ 
   const Item it = items[blockIdx.x];
   const Run<R> &r = runs[it.run];
   const int row = it.a, grp = it.b;
-  const int n1 = r.n1, M = n1 >> 1, log2M = r.log2n1 - 1, cells = n1 * r.n2, nk = r.nk;
+  const int n1 = r.n1, M = n1 >> 1, log2M = r.log2n1 - 1, cells = r.cells, nk = r.nk;
   for (int c = 0; c < 3; ++c) {
     const R *src = r.F + (long long)(3 * grp + c) * cells + (long long)row * n1;
     for (int n = threadIdx.x; n < M; n += blockDim.x) lds[c * M + n] = cmk(src[2 * n], src[2 * n + 1]);
@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(256) k_fields_to_k(const Run<R> *__restrict__ 
     for (int c = 0; c < 3; ++c) {
       const C Zk = lds[c * M + k];
       const C Zmk = lds[c * M + (mk & (M - 1))];
-      double2 *out = r.Fk[parity] + (long long)(3 * grp + c) * r.n2 * nk + (long long)row * nk;
+      double2 *out = r.Fk[parity] + (long long)(3 * grp + c) * r.rows * nk + (long long)row * nk;
       out[k] = to_d2(r2c_post(Zk, Zmk, r.tw[k]));
       if (mk != k) out[mk] = to_d2(r2c_post(Zmk, Zk, r.tw[mk]));
     }
@@ -190,6 +190,106 @@ __global__ void __launch_bounds__(256) k_kupdate(const Run<R> *__restrict__ runs
 }
 
 // =====================================================================
+// 3D hybrid Maxwell update: x1 spectral, x2 and x3 finite differences
+// =====================================================================
+// Two passes per step over (i3, i2, kappa1), FP64 master copy:
+//   pass A: B^{n+1/2} = B^n - (dt/2) C_E E^n (on the thread's row and, by
+//           recomputation, the parts of the rows i2-1 and i3-1 that the
+//           backward differences need), E^{n+1} = E^n + dt (C_B B^{n+1/2} - j~);
+//           writes E^{n+1} and B^{n+1/2} into the other master buffer;
+//   pass B: B^{n+1} = B^{n+1/2} - (dt/2) C_E E^{n+1} in that buffer.
+// C_E E = (D2+ E3 - D3+ E2, D3+ E1 - D1+ E3, D1+ E2 - D2+ E1) and
+// C_B B = (D2- B3 - D3- B2, D3- B1 - D1- B3, D1- B2 - D2- B1) (the Yee curl of
+// Sec. 2.2 with the x1 derivative replaced by i k1 xi+-).
+template <class R>
+__global__ void __launch_bounds__(256) k_kupdate3a(const Run<R> *__restrict__ runs,
+                                                   const Item *__restrict__ items, int parity) {
+  using C = double2;
+  const Item it = items[blockIdx.x];
+  const Run<R> &r = runs[it.run];
+  const int nk = r.nk, n2 = r.n2, n3 = r.n3;
+  const int e = it.a + threadIdx.x;
+  if (e >= r.rows * nk) return;
+  const int row = e / nk, k = e - row * nk;
+  const int i3 = row / n2, i2 = row - i3 * n2;
+  const long long vol = (long long)r.rows * nk;
+  const C *Fi = r.Fk[parity];
+  C *Fo = r.Fk[parity ^ 1];
+  const int a2p = wrap_small(i2 + 1, n2), a2m = wrap_small(i2 - 1, n2);
+  const int a3p = wrap_small(i3 + 1, n3), a3m = wrap_small(i3 - 1, n3);
+  auto at = [&](int comp, int j2, int j3) { return Fi[comp * vol + ((long long)j3 * n2 + j2) * nk + k]; };
+  const C dp = cmk(r.sym[4 * k + 0], r.sym[4 * k + 1]);
+  const C dm = cmk(r.sym[4 * k + 2], r.sym[4 * k + 3]);
+  const double hdt = r.mhdt, dt = r.mdt, i2x = r.midx2, i3x = r.midx3;
+  // E^n on the rows the half-step B needs
+  const C E1 = at(0, i2, i3), E2 = at(1, i2, i3), E3 = at(2, i2, i3);
+  const C E1_2p = at(0, a2p, i3), E3_2p = at(2, a2p, i3);            // (i2+1, i3)
+  const C E1_3p = at(0, i2, a3p), E2_3p = at(1, i2, a3p);            // (i2, i3+1)
+  const C E1_2m = at(0, a2m, i3), E2_2m = at(1, a2m, i3), E3_2m = at(2, a2m, i3);  // (i2-1, i3)
+  const C E2_2m3p = at(1, a2m, a3p);                                  // (i2-1, i3+1)
+  const C E1_3m = at(0, i2, a3m), E2_3m = at(1, i2, a3m), E3_3m = at(2, i2, a3m);  // (i2, i3-1)
+  const C E3_2p3m = at(2, a2p, a3m);                                  // (i2+1, i3-1)
+  // curl E components, forward differences
+  auto cE1 = [&](C e3, C e3n2, C e2, C e2n3) {
+    return csub(cscale(csub(e3n2, e3), i2x), cscale(csub(e2n3, e2), i3x));
+  };
+  auto cE2 = [&](C e1, C e1n3, C e3) { return csub(cscale(csub(e1n3, e1), i3x), cmul(dp, e3)); };
+  auto cE3 = [&](C e2, C e1, C e1n2) { return csub(cmul(dp, e2), cscale(csub(e1n2, e1), i2x)); };
+  // B^{n+1/2} on (i2, i3)
+  const C B1h = csub(at(3, i2, i3), cscale(cE1(E3, E3_2p, E2, E2_3p), hdt));
+  const C B2h = csub(at(4, i2, i3), cscale(cE2(E1, E1_3p, E3), hdt));
+  const C B3h = csub(at(5, i2, i3), cscale(cE3(E2, E1, E1_2p), hdt));
+  // on (i2-1, i3): B1 and B3
+  const C B1h_2m = csub(at(3, a2m, i3), cscale(cE1(E3_2m, E3, E2_2m, E2_2m3p), hdt));
+  const C B3h_2m = csub(at(5, a2m, i3), cscale(cE3(E2_2m, E1_2m, E1), hdt));
+  // on (i2, i3-1): B1 and B2
+  const C B1h_3m = csub(at(3, i2, a3m), cscale(cE1(E3_3m, E3_2p3m, E2_3m, E2), hdt));
+  const C B2h_3m = csub(at(4, i2, a3m), cscale(cE2(E1_3m, E1, E3_3m), hdt));
+  // curl B, backward differences
+  const C cB1 = csub(cscale(csub(B3h, B3h_2m), i2x), cscale(csub(B2h, B2h_3m), i3x));
+  const C cB2 = csub(cscale(csub(B1h, B1h_3m), i3x), cmul(dm, B3h));
+  const C cB3 = csub(cmul(dm, B2h), cscale(csub(B1h, B1h_2m), i2x));
+  const auto *Jk = r.Jk;
+  const long long o = (long long)row * nk + k;
+  const C j1 = to_d2(Jk[o]), j2 = to_d2(Jk[vol + o]), j3 = to_d2(Jk[2 * vol + o]);
+  Fo[o] = cadd(E1, cscale(csub(cB1, j1), dt));
+  Fo[vol + o] = cadd(E2, cscale(csub(cB2, j2), dt));
+  Fo[2 * vol + o] = cadd(E3, cscale(csub(cB3, j3), dt));
+  Fo[3 * vol + o] = B1h;
+  Fo[4 * vol + o] = B2h;
+  Fo[5 * vol + o] = B3h;
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_kupdate3b(const Run<R> *__restrict__ runs,
+                                                   const Item *__restrict__ items, int parity) {
+  using C = double2;
+  const Item it = items[blockIdx.x];
+  const Run<R> &r = runs[it.run];
+  const int nk = r.nk, n2 = r.n2, n3 = r.n3;
+  const int e = it.a + threadIdx.x;
+  if (e >= r.rows * nk) return;
+  const int row = e / nk, k = e - row * nk;
+  const int i3 = row / n2, i2 = row - i3 * n2;
+  const long long vol = (long long)r.rows * nk;
+  C *F = r.Fk[parity ^ 1];
+  const int a2p = wrap_small(i2 + 1, n2), a3p = wrap_small(i3 + 1, n3);
+  auto at = [&](int comp, int j2, int j3) { return F[comp * vol + ((long long)j3 * n2 + j2) * nk + k]; };
+  const C dp = cmk(r.sym[4 * k + 0], r.sym[4 * k + 1]);
+  const double hdt = r.mhdt, i2x = r.midx2, i3x = r.midx3;
+  const C E1 = at(0, i2, i3), E2 = at(1, i2, i3), E3 = at(2, i2, i3);
+  const C E1_2p = at(0, a2p, i3), E3_2p = at(2, a2p, i3);
+  const C E1_3p = at(0, i2, a3p), E2_3p = at(1, i2, a3p);
+  const C c1 = csub(cscale(csub(E3_2p, E3), i2x), cscale(csub(E2_3p, E2), i3x));
+  const C c2 = csub(cscale(csub(E1_3p, E1), i3x), cmul(dp, E3));
+  const C c3 = csub(cmul(dp, E2), cscale(csub(E1_2p, E1), i2x));
+  const long long o = (long long)row * nk + k;
+  F[3 * vol + o] = csub(F[3 * vol + o], cscale(c1, hdt));
+  F[4 * vol + o] = csub(F[4 * vol + o], cscale(c2, hdt));
+  F[5 * vol + o] = csub(F[5 * vol + o], cscale(c3, hdt));
+}
+
+// =====================================================================
 // inverse FFT of E and B
 // =====================================================================
 // Item = (run, row, group): components 3g..3g+2 of the master buffer of the
@@ -203,11 +303,11 @@ __global__ void __launch_bounds__(256) k_ifft_eb(const Run<R> *__restrict__ runs
   const Item it = items[blockIdx.x];
   const Run<R> &r = runs[it.run];
   const int row = it.a, grp = it.b;
-  const int n1 = r.n1, M = n1 >> 1, log2M = r.log2n1 - 1, cells = n1 * r.n2, nk = r.nk;
+  const int n1 = r.n1, M = n1 >> 1, log2M = r.log2n1 - 1, cells = r.cells, nk = r.nk;
   for (int k = threadIdx.x; k <= (M >> 1); k += blockDim.x) {
     const int mk = M - k;
     for (int c = 0; c < 3; ++c) {
-      const double2 *X = r.Fk[parity] + (long long)(3 * grp + c) * r.n2 * nk + (long long)row * nk;
+      const double2 *X = r.Fk[parity] + (long long)(3 * grp + c) * r.rows * nk + (long long)row * nk;
       const C Xk = from_d2<C>(X[k]), Xmk = from_d2<C>(X[mk]);
       lds[c * M + k] = c2r_pre(Xk, Xmk, r.tw[k]);
       if (k != 0 && mk != k) lds[c * M + mk] = c2r_pre(Xmk, Xk, r.tw[mk]);
@@ -400,6 +500,102 @@ void Launch<R>::fft_j(const Run<R> *runs, const Item *items, int nitems, int par
   hipLaunchKernelGGL(k_fft_j<R>, dim3(nitems), dim3(256), lds, s, runs, items, parity);
 }
 
+// 3D Gauss residual on the row (i2, i3): R = D1- E1 + D2- E2 + D3- E3 - f rho
+// in (kappa1, i2, i3) space, FP64.
+template <class R>
+__global__ void __launch_bounds__(256) k_gauss3(const Run<R> *run, int parity, const double *rho,
+                                                const double2 *tw64, const double *sym64,
+                                                const double *filt, double idx2, double idx3,
+                                                double *rows_out) {
+  extern __shared__ unsigned char smem_raw[];
+  double2 *lds = (double2 *)smem_raw;
+  __shared__ double red[256][3];
+  const Run<R> &r = *run;
+  const int row = blockIdx.x;
+  const int n1 = r.n1, M = n1 >> 1, log2M = r.log2n1 - 1, nk = r.nk, n2 = r.n2, n3 = r.n3;
+  const int i3 = row / n2, i2 = row - i3 * n2;
+  for (int n = threadIdx.x; n < M; n += blockDim.x)
+    lds[n] = make_double2(rho[(long long)row * n1 + 2 * n], rho[(long long)row * n1 + 2 * n + 1]);
+  __syncthreads();
+  lds_fft<double2, 6>(lds, M, log2M, 1, tw64, 2, false);
+  const long long vol = (long long)r.rows * nk;
+  const double2 *Fk = r.Fk[parity];
+  const long long rm2 = ((long long)i3 * n2 + wrap_small(i2 - 1, n2)) * nk;
+  const long long rm3 = ((long long)wrap_small(i3 - 1, n3) * n2 + i2) * nk;
+  double s2 = 0, smax = 0, sref = 0;
+  for (int k = threadIdx.x; k <= (M >> 1); k += blockDim.x) {
+    const int mk = M - k;
+    for (int side = 0; side < 2; ++side) {
+      const int kk = side ? mk : k;
+      if (side && mk == k) break;
+      const double2 Zk = lds[kk & (M - 1)], Zmk = lds[(M - kk) & (M - 1)];
+      const double2 rh = r2c_post(Zk, Zmk, tw64[kk]);
+      const double2 e1 = Fk[(long long)row * nk + kk];
+      const double2 e2 = Fk[vol + (long long)row * nk + kk], e2m = Fk[vol + rm2 + kk];
+      const double2 e3 = Fk[2 * vol + (long long)row * nk + kk], e3m = Fk[2 * vol + rm3 + kk];
+      const double2 dm = make_double2(sym64[4 * kk + 2], sym64[4 * kk + 3]);
+      double2 div = cmul(dm, e1);
+      div.x += (e2.x - e2m.x) * idx2 + (e3.x - e3m.x) * idx3;
+      div.y += (e2.y - e2m.y) * idx2 + (e3.y - e3m.y) * idx3;
+      const double fr_x = filt[kk] * rh.x, fr_y = filt[kk] * rh.y;
+      const double rx = div.x - fr_x, ry = div.y - fr_y;
+      const double wgt = (kk == 0 || kk == M) ? 1.0 : 2.0;
+      const double a2 = rx * rx + ry * ry;
+      s2 += wgt * a2;
+      smax = fmax(smax, sqrt(a2));
+      sref += wgt * (fr_x * fr_x + fr_y * fr_y);
+    }
+  }
+  red[threadIdx.x][0] = s2;
+  red[threadIdx.x][1] = smax;
+  red[threadIdx.x][2] = sref;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[threadIdx.x][0] += red[threadIdx.x + w][0];
+      red[threadIdx.x][1] = fmax(red[threadIdx.x][1], red[threadIdx.x + w][1]);
+      red[threadIdx.x][2] += red[threadIdx.x + w][2];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    rows_out[3 * row + 0] = red[0][0];
+    rows_out[3 * row + 1] = red[0][1];
+    rows_out[3 * row + 2] = red[0][2];
+  }
+}
+
+// 3D continuity residual (Eq. (23) with the x3 term) in FP64: the current of
+// the last step is fac[d] * J (J the deposit accumulators of either form).
+template <class A>
+__global__ void k_cont3(const double *rn, const double *ro, const A *J, int n1, int n2, int n3,
+                        double dt, double f1, double f2, double f3, double idx1, double idx2,
+                        double idx3, double *partial) {
+  __shared__ double red[256];
+  const long long cells = (long long)n1 * n2 * n3;
+  double m = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < cells;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int i1 = (int)(i % n1);
+    const long long rr = i / n1;
+    const int i2 = (int)(rr % n2), i3 = (int)(rr / n2);
+    const long long w1 = (long long)(rr * n1) + wrap_small(i1 - 1, n1);
+    const long long w2 = ((long long)i3 * n2 + wrap_small(i2 - 1, n2)) * n1 + i1;
+    const long long w3 = ((long long)wrap_small(i3 - 1, n3) * n2 + i2) * n1 + i1;
+    const double div = f1 * ((double)J[i] - (double)J[w1]) * idx1 +
+                       f2 * ((double)J[cells + i] - (double)J[cells + w2]) * idx2 +
+                       f3 * ((double)J[2 * cells + i] - (double)J[2 * cells + w3]) * idx3;
+    m = fmax(m, fabs((rn[i] - ro[i]) / dt + div));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 template <class R>
 void Launch<R>::kupdate(const Run<R> *runs, const Item *items, int nitems, int parity,
                         hipStream_t s) {
@@ -423,8 +619,45 @@ void Launch<R>::fields_to_k(const Run<R> *runs, const Item *items, int nitems, i
   hipLaunchKernelGGL(k_fields_to_k<R>, dim3(nitems), dim3(256), lds, s, runs, items, parity);
 }
 
+template <class R>
+void Launch<R>::kupdate3(const Run<R> *runs, const Item *items, int nitems, int parity,
+                         hipStream_t s) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(k_kupdate3a<R>, dim3(nitems), dim3(256), 0, s, runs, items, parity);
+  hipLaunchKernelGGL(k_kupdate3b<R>, dim3(nitems), dim3(256), 0, s, runs, items, parity);
+}
+
 template struct Launch<float>;
 template struct Launch<double>;
+
+template <class R>
+void launch_gauss3(const Run<R> *run_dev, int rows, int n1, int parity, const double *rho,
+                   const double2 *tw64, const double *sym64, const double *filt, double idx2,
+                   double idx3, double *rows_out, hipStream_t s) {
+  const size_t lds = (size_t)(n1 / 2) * sizeof(double2);
+  hipLaunchKernelGGL(k_gauss3<R>, dim3(rows), dim3(256), lds, s, run_dev, parity, rho, tw64,
+                     sym64, filt, idx2, idx3, rows_out);
+}
+template void launch_gauss3<float>(const Run<float> *, int, int, int, const double *,
+                                   const double2 *, const double *, const double *, double, double,
+                                   double *, hipStream_t);
+template void launch_gauss3<double>(const Run<double> *, int, int, int, const double *,
+                                    const double2 *, const double *, const double *, double,
+                                    double, double *, hipStream_t);
+
+template <class A>
+void launch_cont3(const double *rn, const double *ro, const A *J, int n1, int n2, int n3,
+                  double dt, double f1, double f2, double f3, double idx1, double idx2,
+                  double idx3, double *partial, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_cont3<A>, dim3(nblocks), dim3(256), 0, s, rn, ro, J, n1, n2, n3, dt, f1,
+                     f2, f3, idx1, idx2, idx3, partial);
+}
+template void launch_cont3<long long>(const double *, const double *, const long long *, int, int,
+                                      int, double, double, double, double, double, double, double,
+                                      double *, int, hipStream_t);
+template void launch_cont3<double>(const double *, const double *, const double *, int, int, int,
+                                   double, double, double, double, double, double, double,
+                                   double *, int, hipStream_t);
 
 template <class R>
 void launch_energy(const R *F, long long cells, double *partial, int nblocks, hipStream_t s) {

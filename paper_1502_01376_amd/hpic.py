@@ -14,6 +14,7 @@ LIBPATH = os.path.join(_HERE, "_lib", "libhpic.so")
 HP_OK, HP_EINVAL, HP_ECOURANT, HP_ENOMEM, HP_EDEVICE, HP_ERANGE, HP_ENUMERIC, HP_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
 HP_GEOM_2D = 2
+HP_GEOM_3D = 3
 HP_PREC_FP32_FIXED, HP_PREC_FP64 = 0, 1
 KERNELS = ("push_deposit", "fft_j", "kupdate", "ifft_eb", "sort")
 HP_NK = len(KERNELS)
@@ -127,11 +128,12 @@ def _ptr(a):
 
 
 def config(n1, n2, dx1, dx2, dt, alpha=0.5, deriv1=0, correct=1, precision="fp32",
-           shape_bits=0, weight_bits=0, sort_interval=0):
+           shape_bits=0, weight_bits=0, sort_interval=0, n3=0, dx3=0.0):
+    """Configuration of one run; n3 > 0 makes it a 3D run (n1 x n2 x n3 cells)."""
     c = Config()
-    c.geom = HP_GEOM_2D
-    c.n[0], c.n[1], c.n[2] = int(n1), int(n2), 1
-    c.dx[0], c.dx[1], c.dx[2] = float(dx1), float(dx2), 1.0
+    c.geom = HP_GEOM_3D if n3 > 0 else HP_GEOM_2D
+    c.n[0], c.n[1], c.n[2] = int(n1), int(n2), int(n3) if n3 > 0 else 1
+    c.dx[0], c.dx[1], c.dx[2] = float(dx1), float(dx2), float(dx3) if n3 > 0 else 1.0
     c.dt = float(dt)
     c.shape_order, c.interp = 2, 0
     c.filter_frac = float(alpha)
@@ -168,8 +170,14 @@ class Sim:
             pass
 
     def shape(self, run):
+        """Grid shape of a run's field arrays: (n2, n1) or (n3, n2, n1)."""
         c = self.cfgs[run]
+        if c.geom == HP_GEOM_3D:
+            return c.n[2], c.n[1], c.n[0]
         return c.n[1], c.n[0]
+
+    def dim(self, run):
+        return 3 if self.cfgs[run].geom == HP_GEOM_3D else 2
 
     def set_stream(self, stream):
         s = getattr(stream, "cuda_stream", stream)
@@ -180,15 +188,15 @@ class Sim:
         u = np.ascontiguousarray(u, dtype=np.float64)
         w = np.ascontiguousarray(w, dtype=np.float64)
         n = w.size
-        assert x.shape == (2, n) and u.shape == (3, n)
+        assert x.shape == (self.dim(run), n) and u.shape == (3, n)
         _check(lib().hp_set_particles(self.h, run, 0, n, _ptr(x), _ptr(u), _ptr(w),
                                       float(q_over_m), float(q)))
 
     def set_fields(self, run, E, B):
-        n2, n1 = self.shape(run)
+        sh = (3,) + self.shape(run)
         E = np.ascontiguousarray(E, dtype=np.float64)
         B = np.ascontiguousarray(B, dtype=np.float64)
-        assert E.shape == (3, n2, n1) and B.shape == (3, n2, n1)
+        assert E.shape == sh and B.shape == sh
         _check(lib().hp_set_fields(self.h, run, 0, _ptr(E), _ptr(B)))
 
     def set_background(self, run, rho_from_particles=True, jbg=(0.0, 0.0, 0.0)):
@@ -218,8 +226,7 @@ class Sim:
         _check(lib().hp_synchronize(self.h))
 
     def field(self, run, comp):
-        n2, n1 = self.shape(run)
-        out = np.empty((n2, n1))
+        out = np.empty(self.shape(run))
         _check(lib().hp_get_field(self.h, run, comp, 0, _ptr(out), out.size))
         return out
 
@@ -228,16 +235,14 @@ class Sim:
         return F[:3], F[3:]
 
     def current(self, run, comp, corrected=False):
-        n2, n1 = self.shape(run)
-        out = np.empty((n2, n1))
+        out = np.empty(self.shape(run))
         _check(lib().hp_get_current(self.h, run, comp, int(corrected), _ptr(out), out.size))
         return out
 
     def current_fixed(self, run):
-        n2, n1 = self.shape(run)
-        out = np.empty((3, n2, n1), dtype=np.int64)
+        out = np.empty((3,) + self.shape(run), dtype=np.int64)
         for c in range(3):
-            _check(lib().hp_get_current_fixed(self.h, run, c, _ptr(out[c]), n1 * n2))
+            _check(lib().hp_get_current_fixed(self.h, run, c, _ptr(out[c]), out[c].size))
         return out
 
     def count(self, run):
@@ -247,7 +252,7 @@ class Sim:
 
     def particles(self, run):
         n = self.count(run)
-        x = np.empty((2, n))
+        x = np.empty((self.dim(run), n))
         u = np.empty((3, n))
         w = np.empty(n)
         pid = np.empty(n, dtype=np.int64)
@@ -256,8 +261,8 @@ class Sim:
 
     def particles_raw(self, run):
         n = self.count(run)
-        cell = np.empty((2, n), dtype=np.int32)
-        off = np.empty((2, n), dtype=np.float32)
+        cell = np.empty((self.dim(run), n), dtype=np.int32)
+        off = np.empty((self.dim(run), n), dtype=np.float32)
         u = np.empty((3, n), dtype=np.float32)
         qw = np.empty(n, dtype=np.float32)
         pid = np.empty(n, dtype=np.int32)
@@ -302,7 +307,7 @@ class Sim:
         out = np.empty(4)
         _check(lib().hp_get_fixed_params(self.h, run, _ptr(out)))
         return dict(P=int(out[0]), inv_wunit=np.float32(out[1]), c3=np.float32(out[2]),
-                    Q=int(out[3]))
+                    cj=np.float32(out[2]), Q=int(out[3]))
 
     def profile(self, enable=True):
         _check(lib().hp_profile(self.h, int(bool(enable))))
@@ -325,14 +330,16 @@ def from_workloads(ds, precision="fp32", alpha=None, deriv1=0, correct=1, backgr
     background current and charge), all advanced together."""
     cfgs = []
     for d in ds:
-        n1, n2, _ = d["n"]
-        dx1, dx2, _ = d["dx"]
+        n1, n2, n3 = d["n"]
+        dx1, dx2, dx3 = d["dx"]
+        three = d.get("geom", 2) == 3
         cfgs.append(config(n1, n2, dx1, dx2, d["dt"], alpha=d["alpha"] if alpha is None else alpha,
-                           deriv1=deriv1, correct=correct, precision=precision, **cfg_kw))
+                           deriv1=deriv1, correct=correct, precision=precision,
+                           n3=n3 if three else 0, dx3=dx3 if three else 0.0, **cfg_kw))
     sim = Sim(cfgs, stream=stream)
     for r, d in enumerate(ds):
-        dx1, dx2, _ = d["dx"]
-        x = np.stack([d["xi"][0] * dx1, d["xi"][1] * dx2])
+        dim = 3 if d.get("geom", 2) == 3 else 2
+        x = np.stack([d["xi"][k] * d["dx"][k] for k in range(dim)])
         sim.set_particles(r, x, d["u"], d["w"], d["qm"], d["q"])
         if np.any(d["E"]) or np.any(d["B"]):
             sim.set_fields(r, d["E"], d["B"])

@@ -1,0 +1,223 @@
+"""3D Cartesian path on the GPU against the 3D oracle.
+
+The FP32 form's deposit is compared bit for bit with the oracle's
+kernel-precision 3D deposit of the same moves; fields after one step with the
+oracle's FP64 update of the same current; several whole steps with the
+oracle's FP64 step; the FP64 form with the oracle to round-off; the vacuum
+dispersion closed form; the finite-difference x1 mode with the direct Yee
+update; conservation diagnostics; and invariance of the results to tiling,
+sort interval and graph replay.  Full size: 512 x 128 x 128 cells, 16.8M
+particles, one step, deposit bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1502_01376_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _small(seed=11, n=(16, 8, 8), gamma=3.0, sigma_u=0.3):
+    return W.drift3d(*n, spread=0.05, sigma_u=sigma_u, gamma=gamma, jitter=True, seed=seed,
+                     sub=(2, 1, 1))
+
+
+def _grid(d, **kw):
+    return oracle.grid3(*d["n"], *d["dx"], d["dt"], alpha=d["alpha"], jbg=d["jbg"], **kw)
+
+
+def _by_id(raw):
+    o = np.argsort(raw["id"])
+    return {k: v[..., o] for k, v in raw.items()}
+
+
+def _oracle_fixed_of_moves(d, b, a, fp):
+    return oracle.deposit3_fixed(d["n"], fp["inv_wunit"], fp["cj"], b["cell"], b["off"],
+                                 a["cell"], a["off"], b["qw"])
+
+
+def _moves64(d, b, a):
+    n = np.array(d["n"])[:, None]
+    step = a["cell"].astype(np.int64) - b["cell"]
+    step = (step + n // 2) % n - n // 2
+    xa = b["cell"] + b["off"].astype(np.float64)
+    xb = b["cell"] + step + a["off"].astype(np.float64)
+    return xa, xb
+
+
+def test_3d_one_step_deposit_bitexact_and_update(hpic):
+    d = _small()
+    sim = hpic.from_workload(d, "fp32")
+    b = sim.particles_raw(0)
+    E0, B0 = sim.fields(0)
+    fp = sim.fixed_params(0)
+    sim.step(1)
+    a = sim.particles_raw(0)
+    assert np.array_equal(b["id"], a["id"])
+    Jg = sim.current_fixed(0)
+    Jo = _oracle_fixed_of_moves(d, b, a, fp)
+    assert np.array_equal(Jg, Jo)
+    # sampled push against the oracle's FP64 gather + Boris from the GPU's fields
+    g = _grid(d)
+    xa = b["cell"] + b["off"].astype(np.float64)
+    Ep, Bp = oracle.gather3(g, E0, B0, xa)
+    u = oracle.boris(d["qm"], d["dt"], Ep, Bp, b["u"].astype(np.float64))
+    assert np.abs(a["u"] - u).max() <= 8e-6 * (1 + np.abs(u).max())
+    # field update with the FP64 current of the GPU's moves
+    xa, xb = _moves64(d, b, a)
+    J64 = oracle.deposit3(g, xa, xb, b["qw"].astype(np.float64))
+    Eo, Bo = oracle.field_update3(g, E0, B0, J64)
+    E1, B1 = sim.fields(0)
+    scale = max(np.abs(Eo).max(), np.abs(Bo).max())
+    assert np.abs(E1 - Eo).max() <= 2e-5 * scale
+    assert np.abs(B1 - Bo).max() <= 2e-5 * scale
+    sim.close()
+
+
+def test_3d_fp32_steps_track_oracle(hpic):
+    d = _small(seed=12)
+    sim = hpic.from_workload(d, "fp32")
+    raw = _by_id(sim.particles_raw(0))
+    g = _grid(d)
+    st = oracle.State3(g, d["qm"], raw["cell"] + raw["off"].astype(np.float64), raw["u"], raw["qw"])
+    sim.step(8)
+    st.step(8)
+    E1, B1 = sim.fields(0)
+    scale = max(np.abs(st.E).max(), np.abs(st.B).max())
+    assert np.abs(E1 - st.E).max() <= 1e-4 * scale
+    assert np.abs(B1 - st.B).max() <= 1e-4 * scale
+    sim.close()
+
+
+def test_3d_fp64_form_matches_oracle(hpic):
+    d = _small(seed=13)
+    sim = hpic.from_workload(d, "fp64")
+    p = sim.particles(0)
+    o = np.argsort(p["id"])
+    g = _grid(d)
+    xi = p["x"][:, o] / np.array(d["dx"])[:, None]
+    st = oracle.State3(g, d["qm"], xi, p["u"][:, o], d["q"] * p["w"][o])
+    sim.step(10)
+    st.step(10)
+    E1, B1 = sim.fields(0)
+    scale = max(np.abs(st.E).max(), np.abs(st.B).max())
+    assert np.abs(E1 - st.E).max() <= 1e-9 * scale
+    assert np.abs(B1 - st.B).max() <= 1e-9 * scale
+    q = sim.particles(0)
+    oq = np.argsort(q["id"])
+    assert np.abs(q["u"][:, oq] - st.u).max() <= 1e-9 * np.abs(st.u).max()
+    sim.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("fp64", 1e-10)])
+def test_3d_vacuum_dispersion(hpic, prec, tol):
+    n, dx = (32, 8, 8), (0.2, 0.25, 0.3)
+    dt = 0.9 * oracle.courant_limit3(*dx)
+    kap = (5, 1, 2)
+    k = [2 * np.pi * kap[i] / (n[i] * dx[i]) for i in range(3)]
+    dm = (1j * k[0] * np.exp(-1j * k[0] * dx[0] / 2), (1 - np.exp(-1j * k[1] * dx[1])) / dx[1],
+          (1 - np.exp(-1j * k[2] * dx[2])) / dx[2])
+    i3, i2, i1 = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    ph = np.exp(1j * (k[0] * i1 * dx[0] + k[1] * i2 * dx[1] + k[2] * i3 * dx[2]))
+    Eh = np.array([dm[1], -dm[0], 0])
+    E0 = np.real(Eh[:, None, None, None] * ph[None])
+    K2 = k[0] ** 2 + sum((2 * np.sin(k[i] * dx[i] / 2) / dx[i]) ** 2 for i in (1, 2))
+    theta = 2 * np.arcsin(0.5 * dt * np.sqrt(K2))
+    sim = hpic.Sim([hpic.config(n[0], n[1], dx[0], dx[1], dt, alpha=1.0, precision=prec,
+                                n3=n[2], dx3=dx[2])])
+    sim.set_fields(0, E0, np.zeros_like(E0))
+    steps = 400
+    sim.step(steps)
+    E, _ = sim.fields(0)
+    assert np.abs(E - np.cos(steps * theta) * E0).max() < tol * np.abs(E0).max()
+    sim.close()
+
+
+def test_3d_fd_mode_matches_oracle_yee(hpic):
+    n, dx, dt = (16, 8, 4), (0.2, 0.3, 0.25), 0.05
+    gen = np.random.default_rng(8)
+    E0 = gen.standard_normal((3, n[2], n[1], n[0]))
+    B0 = gen.standard_normal((3, n[2], n[1], n[0]))
+    sim = hpic.Sim([hpic.config(n[0], n[1], dx[0], dx[1], dt, alpha=1.0, deriv1=1,
+                                precision="fp64", n3=n[2], dx3=dx[2])])
+    sim.set_fields(0, E0, B0)
+    sim.step(5)
+    g = oracle.grid3(*n, *dx, dt, alpha=1.0, deriv1=1)
+    E, B = E0, B0
+    J = np.zeros_like(E0)
+    for _ in range(5):
+        E, B = oracle.yee_update3(g, E, B, J)
+    E1, B1 = sim.fields(0)
+    assert np.abs(E1 - E).max() < 1e-10 * np.abs(E).max()
+    assert np.abs(B1 - B).max() < 1e-10 * np.abs(B).max()
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_3d_gauss_and_continuity(hpic, prec):
+    d = _small(seed=14)
+    sim = hpic.from_workload(d, prec)
+    sim.step(19)
+    sim.diagnostics(0)
+    sim.step(1)
+    dg = sim.diagnostics(0)
+    ref = dg["gauss_ref_l2"]
+    rho_scale = abs(dg["charge_total"]) / (np.prod(d["n"]) * np.prod(d["dx"]))
+    tol_g, tol_c = (2e-5, 1e-5) if prec == "fp32" else (1e-11, 1e-11)
+    assert dg["gauss_l2"] <= tol_g * max(ref, 1e-12)
+    assert 0 <= dg["cont_linf"] <= tol_c * rho_scale / d["dt"]
+    sim.close()
+
+
+def _state(sim):
+    E, B = sim.fields(0)
+    raw = _by_id(sim.particles_raw(0))
+    return [E, B, sim.current_fixed(0)] + [raw[k] for k in sorted(raw)]
+
+
+def test_3d_tiling_sort_and_graph_invariance(hpic):
+    d = _small(seed=15, n=(32, 16, 8))
+    ref = hpic.from_workload(d, "fp32")
+    ref.use_graphs(False)
+    ref.step(12)
+    want = _state(ref)
+    ref.close()
+    for t1, t2, K in [(8, 4, 4), (16, 2, 6), (4, 8, 1), (32, 16, 2)]:
+        sim = hpic.from_workload(d, "fp32")
+        sim.set_tiling(t1, t2, K)
+        sim.step(12)
+        for x, y in zip(_state(sim), want):
+            assert np.array_equal(x, y), (t1, t2, K)
+        sim.close()
+
+
+def test_3d_state_resume_bitexact(hpic):
+    d = _small(seed=16)
+    a = hpic.from_workload(d, "fp32")
+    a.step(3)
+    blob = a.get_state()
+    a.step(4)
+    b = hpic.from_workload(d, "fp32")
+    b.set_state(blob)
+    b.step(4)
+    for x, y in zip(_state(a), _state(b)):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()
+
+
+@pytest.mark.timeout(600)
+def test_3d_full_size_one_step(hpic):
+    """512 x 128 x 128 cells, 2 per cell (16 777 216 particles), gamma = 50,
+    density +-5%: one step in the benchmark's launch configuration, deposit
+    bit for bit against the oracle's kernel-precision deposit of the moves."""
+    d = W.drift3d()
+    sim = hpic.from_workload(d, "fp32")
+    b = sim.particles_raw(0)
+    fp = sim.fixed_params(0)
+    sim.step(1)
+    a = sim.particles_raw(0)
+    Jo = _oracle_fixed_of_moves(d, b, a, fp)
+    assert np.array_equal(sim.current_fixed(0), Jo)
+    sim.close()
