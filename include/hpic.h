@@ -87,7 +87,12 @@ typedef struct hp_config {
                                 0 = automatic (exact for equal weights, else the
                                 largest Q <= 15 the headroom allows) */
   int32_t sort_interval;     /* particle tile sort every K steps; 0 = automatic */
-  int32_t reserved[8];
+  int32_t kmod;              /* 1: modified spectral symbol of Eq. (29) (Sec. 4),
+                                [k]1 = k1 + dk_max cos^2((k1 - k1m)/(k1l - k1m) pi/2)
+                                on k1l <= k1 <= k1u with k1l = 0.15 kg1, k1u = 0.26 kg1,
+                                dk_max = 0.01 kg1, kg1 = 2 pi/dx1; the j1 correction
+                                becomes [k]1,FD/[k]1,mod.  0: off */
+  int32_t reserved[7];
 } hp_config;
 
 /* FP64 diagnostics of one run (Sec. 2.3 and energies), see hp_diagnostics. */

@@ -31,7 +31,7 @@ class Grid2(ctypes.Structure):
         ("dx1", ctypes.c_double), ("dx2", ctypes.c_double), ("dt", ctypes.c_double),
         ("alpha", ctypes.c_double),
         ("deriv1", ctypes.c_int32), ("correct", ctypes.c_int32),
-        ("jbg", ctypes.c_double * 3),
+        ("jbg", ctypes.c_double * 3), ("kmod", ctypes.c_int32),
     ]
 
 
@@ -43,7 +43,7 @@ class Grid3(ctypes.Structure):
         ("dx1", ctypes.c_double), ("dx2", ctypes.c_double), ("dx3", ctypes.c_double),
         ("dt", ctypes.c_double), ("alpha", ctypes.c_double),
         ("deriv1", ctypes.c_int32), ("correct", ctypes.c_int32),
-        ("jbg", ctypes.c_double * 3),
+        ("jbg", ctypes.c_double * 3), ("kmod", ctypes.c_int32),
     ]
 
 
@@ -103,8 +103,9 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def grid2(n1, n2, dx1, dx2, dt, alpha=1.0, deriv1=0, correct=1, jbg=(0.0, 0.0, 0.0)):
+def grid2(n1, n2, dx1, dx2, dt, alpha=1.0, deriv1=0, correct=1, jbg=(0.0, 0.0, 0.0), kmod=0):
     g = Grid2()
+    g.kmod = int(kmod)
     g.n1, g.n2 = int(n1), int(n2)
     g.dx1, g.dx2, g.dt = float(dx1), float(dx2), float(dt)
     g.alpha = float(alpha)
@@ -269,8 +270,10 @@ def courant_limit2(dx1, dx2):
 
 
 # ------------------------------------------------------------------------ 3D
-def grid3(n1, n2, n3, dx1, dx2, dx3, dt, alpha=1.0, deriv1=0, correct=1, jbg=(0.0, 0.0, 0.0)):
+def grid3(n1, n2, n3, dx1, dx2, dx3, dt, alpha=1.0, deriv1=0, correct=1, jbg=(0.0, 0.0, 0.0),
+          kmod=0):
     g = Grid3()
+    g.kmod = int(kmod)
     g.n1, g.n2, g.n3 = int(n1), int(n2), int(n3)
     g.dx1, g.dx2, g.dx3, g.dt = float(dx1), float(dx2), float(dx3), float(dt)
     g.alpha = float(alpha)

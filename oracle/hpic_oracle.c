@@ -269,14 +269,25 @@ typedef struct {
   double corr, filt;
 } xsym;
 
+/* The modification of Eq. (29) to the spectral x1 symbol (zero outside the
+ * bump [k1l, k1u]); coefficients of Sec. 4 for the Table 1 set-up. */
+static double dk_mod(double k1, double dx1) {
+  double kg = 2.0 * PI / dx1;
+  double kl = 0.15 * kg, ku = 0.26 * kg, dkmax = 0.01 * kg, km = 0.5 * (kl + ku);
+  if (fabs(k1) < kl || fabs(k1) > ku) return 0.0;
+  double c = cos((fabs(k1) - km) / (kl - km) * PI / 2.0);
+  return dkmax * c * c;
+}
+
 static xsym x1_symbols(const or_grid2 *g, int32_t kappa) {
   xsym s;
   double k1 = 2.0 * PI * (double)kappa / ((double)g->n1 * g->dx1);
   double h = 0.5 * k1 * g->dx1;
-  double kk = g->deriv1 ? sin(h) / (0.5 * g->dx1) : k1;
-  s.dp = I * kk * cexp(I * h);  /* i k1 xi+ */
-  s.dm = I * kk * cexp(-I * h); /* i k1 xi- */
-  s.corr = (g->deriv1 || !g->correct || kappa == 0) ? 1.0 : sin(h) / h;
+  double kfd = sin(h) / (0.5 * g->dx1);
+  double kk = g->deriv1 ? kfd : k1 + (g->kmod ? dk_mod(k1, g->dx1) : 0.0);
+  s.dp = I * kk * cexp(I * h);  /* i [k]1 xi+ */
+  s.dm = I * kk * cexp(-I * h); /* i [k]1 xi- */
+  s.corr = (g->deriv1 || !g->correct || kappa == 0) ? 1.0 : kfd / kk;
   s.filt = ((double)kappa <= g->alpha * 0.5 * (double)g->n1) ? 1.0 : 0.0;
   return s;
 }
@@ -702,6 +713,7 @@ static xsym x1_symbols3(const or_grid3 *g, int32_t kappa) {
   or_grid2 g2;
   g2.n1 = g->n1; g2.n2 = g->n2; g2.dx1 = g->dx1; g2.dx2 = g->dx2; g2.dt = g->dt;
   g2.alpha = g->alpha; g2.deriv1 = g->deriv1; g2.correct = g->correct;
+  g2.kmod = g->kmod;
   return x1_symbols(&g2, kappa);
 }
 

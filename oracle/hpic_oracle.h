@@ -35,7 +35,12 @@ extern "C" {
  * uses the finite-difference symbol [k]1 of Eq. (28), which turns the hybrid
  * update back into the Yee scheme (end of Sec. 2.1).  correct = 1 applies the
  * current correction of Eq. (11); 0 is an ablation used by tests.  jbg is a
- * uniform background current added to the deposited current. */
+ * uniform background current added to the deposited current.  kmod = 1 uses
+ * the modified spectral symbol of Eq. (29), [k]1 = k1 + dk_mod(k1) with
+ * dk_mod = dk_max cos^2((k1 - k1m)/(k1l - k1m) pi/2) for k1l <= k1 <= k1u,
+ * k1l = 0.15 kg1, k1u = 0.26 kg1, dk_max = 0.01 kg1, kg1 = 2 pi / dx1 (the
+ * values Sec. 4 gives for the Table 1 set-up); the current correction is then
+ * [k]1,FD / [k]1,mod so that the Gauss law still holds. */
 typedef struct or_grid2 {
   int32_t n1, n2;
   double dx1, dx2, dt;
@@ -43,6 +48,7 @@ typedef struct or_grid2 {
   int32_t deriv1;
   int32_t correct;
   double jbg[3];
+  int32_t kmod;  /* 1: [k]1 = k1 + dk_mod(k1) of Eq. (29), Table 1 coefficients */
 } or_grid2;
 
 /* Complex FFT of length n (power of two), in place.  sign = -1 computes
@@ -128,6 +134,7 @@ typedef struct or_grid3 {
   int32_t deriv1;
   int32_t correct;
   double jbg[3];
+  int32_t kmod;
 } or_grid3;
 
 void or_gather3(const or_grid3 *g, const double *E, const double *B, int64_t np,

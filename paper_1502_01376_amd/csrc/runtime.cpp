@@ -60,6 +60,18 @@ double courant_limit(const hp_config &c) {
   return 2.0 / std::sqrt(PI * PI / (a * a) + 4.0 / (b * b) + (three ? 4.0 / (e * e) : 0.0));
 }
 
+// Eq. (29): the bump added to the spectral x1 symbol with the coefficients
+// Sec. 4 gives for the Table 1 set-up (k1l = 0.15 kg1, k1u = 0.26 kg1,
+// dk_max = 0.01 kg1, kg1 = 2 pi / dx1); zero when kmod is off.
+double dk_mod(const hp_config &c, double k1) {
+  if (!c.kmod || c.deriv1) return 0.0;
+  const double kg = 2.0 * PI / c.dx[0];
+  const double kl = 0.15 * kg, ku = 0.26 * kg, dmax = 0.01 * kg, km = 0.5 * (kl + ku);
+  if (k1 < kl || k1 > ku) return 0.0;
+  const double t = std::cos((k1 - km) / (kl - km) * PI / 2.0);
+  return dmax * t * t;
+}
+
 const int SORT_CHUNK = 256;   // particles per sort workgroup
 const int UPD_BLOCK = 256;    // (i2, kappa) elements per update workgroup
 const int TILE1 = 32, TILE2 = 8;  // default particle tile (cells along x1, x2)
@@ -211,7 +223,7 @@ class Sim : public SimBase {
       for (int k = 0; k < d.nk; ++k) {
         const double k1 = 2.0 * PI * k / (d.n1 * c.dx[0]);
         const double hh = 0.5 * k1 * c.dx[0];
-        const double kk = c.deriv1 ? std::sin(hh) / (0.5 * c.dx[0]) : k1;
+        const double kk = c.deriv1 ? std::sin(hh) / (0.5 * c.dx[0]) : k1 + dk_mod(c, k1);
         const double v[4] = {-kk * std::sin(hh), kk * std::cos(hh), kk * std::sin(hh),
                              kk * std::cos(hh)};  // i kk exp(+ih), i kk exp(-ih)
         for (int j = 0; j < 4; ++j) sym64[4 * k + j] = v[j];
@@ -1339,7 +1351,9 @@ class Sim : public SimBase {
     for (int k = 0; k < d.nk; ++k) {
       const double hh = PI * k / d.n1;  // k1 dx1 / 2
       const bool corr = !h.cfg.deriv1 && h.cfg.correct && k > 0;
-      const double sinc = corr ? std::sin(hh) / hh : 1.0;
+      // Eq. (11): [k]1,FD / [k]1 (sin(h)/h without the Eq. (29) bump)
+      const double k1 = 2.0 * hh / h.cfg.dx[0];
+      const double sinc = corr ? (std::sin(hh) / (0.5 * h.cfg.dx[0])) / (k1 + dk_mod(h.cfg, k1)) : 1.0;
       const double filt = (k <= h.cfg.filter_frac * 0.5 * d.n1) ? 1.0 : 0.0;
       jf[3 * k + 0] = (R)(acc_factor(h, 0) * sinc * filt);
       jf[3 * k + 1] = (R)(acc_factor(h, 1) * filt);
@@ -1471,6 +1485,7 @@ int hp_create(const hp_config *cfgs, int32_t nruns, hp_sim **out) {
       return fail(HP_EINVAL, "run %d: quadratic shape with momentum-conserving gather only", i);
     if (!(c.filter_frac > 0)) return fail(HP_EINVAL, "run %d: filter_frac must be > 0", i);
     if (c.deriv1 != 0 && c.deriv1 != 1) return fail(HP_EINVAL, "run %d: bad deriv1", i);
+    if (c.kmod != 0 && c.kmod != 1) return fail(HP_EINVAL, "run %d: bad kmod", i);
     if (c.fixed_shape_bits != 0 && (c.fixed_shape_bits < 8 || c.fixed_shape_bits > 24))
       return fail(HP_EINVAL, "run %d: fixed_shape_bits in [8, 24]", i);
     if (c.fixed_weight_bits < 0 || c.fixed_weight_bits > 24)

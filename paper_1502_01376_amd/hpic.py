@@ -43,7 +43,8 @@ class Config(ctypes.Structure):
         ("filter_frac", ctypes.c_double), ("deriv1", ctypes.c_int32), ("correct", ctypes.c_int32),
         ("n_modes", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("fixed_shape_bits", ctypes.c_int32), ("fixed_weight_bits", ctypes.c_int32),
-        ("sort_interval", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8),
+        ("sort_interval", ctypes.c_int32), ("kmod", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
     ]
 
 
@@ -128,7 +129,7 @@ def _ptr(a):
 
 
 def config(n1, n2, dx1, dx2, dt, alpha=0.5, deriv1=0, correct=1, precision="fp32",
-           shape_bits=0, weight_bits=0, sort_interval=0, n3=0, dx3=0.0):
+           shape_bits=0, weight_bits=0, sort_interval=0, n3=0, dx3=0.0, kmod=0):
     """Configuration of one run; n3 > 0 makes it a 3D run (n1 x n2 x n3 cells)."""
     c = Config()
     c.geom = HP_GEOM_3D if n3 > 0 else HP_GEOM_2D
@@ -141,6 +142,7 @@ def config(n1, n2, dx1, dx2, dt, alpha=0.5, deriv1=0, correct=1, precision="fp32
     c.precision = HP_PREC_FP32_FIXED if precision == "fp32" else HP_PREC_FP64
     c.fixed_shape_bits, c.fixed_weight_bits = int(shape_bits), int(weight_bits)
     c.sort_interval = int(sort_interval)
+    c.kmod = int(kmod)
     return c
 
 

@@ -353,3 +353,56 @@ def test_results_independent_of_sort_interval(hpic):
     for other in outs[1:]:
         for a, b in zip(outs[0], other):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 5e-6), ("fp64", 1e-10)])
+def test_kmod_dispersion_gpu(hpic, prec, tol):
+    """Eq. (29) on the GPU: a mode inside the bump (k1/kg1 = 0.215) follows the
+    closed form with [k]1 = k1 + dk_mod, coefficients of Sec. 4."""
+    from tests.golden import load
+    c = load("dkmod_table1.txt")
+    n1, n2, dx1, dx2 = 256, 8, 0.2, 0.2
+    dt = 0.9 * oracle.courant_limit2(dx1, dx2)
+    k1i = 55
+    k1 = 2 * np.pi * k1i / (n1 * dx1)
+    kg = 2 * np.pi / dx1
+    kl, ku = c["k1l_over_kg1"] * kg, c["k1u_over_kg1"] * kg
+    km = 0.5 * (kl + ku)
+    dk = c["dkmax_over_kg1"] * kg * np.cos((k1 - km) / (kl - km) * np.pi / 2) ** 2
+    kk2 = np.sin(np.pi / n2) / (dx2 / 2)
+    theta = 2 * np.arcsin(0.5 * dt * np.hypot(k1 + dk, kk2))
+    sim = hpic.Sim([hpic.config(n1, n2, dx1, dx2, dt, alpha=1.0, precision=prec, kmod=1)])
+    X1, X2 = np.meshgrid(np.arange(n1), np.arange(n2))
+    E = np.zeros((3, n2, n1))
+    E[2] = np.cos(2 * np.pi * (k1i * X1 / n1 + X2 / n2))
+    sim.set_fields(0, E, np.zeros_like(E))
+    sim.step(200)
+    assert np.abs(sim.field(0, 2) - np.cos(200 * theta) * E[2]).max() < tol
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_kmod_gauss_and_oracle_gpu(hpic, prec):
+    """With the Eq. (29) symbol the GPU step follows the oracle and keeps the
+    Gauss residual (the correction is [k]1,FD/[k]1,mod)."""
+    d = W.drift2d(64, 16, 0.2, 0.2, 0.05, sub=(2, 2), gamma=5.0, sigma_u=0.1, jitter=True, seed=22)
+    sim = hpic.from_workload(d, prec, kmod=1)
+    g = oracle.grid2(64, 16, 0.2, 0.2, 0.05, alpha=d["alpha"], jbg=d["jbg"], kmod=1)
+    if prec == "fp32":
+        raw = sim.particles_raw(0)
+        o = np.argsort(raw["id"])
+        xa = raw["cell"][:, o] + raw["off"][:, o].astype(np.float64)
+        st = oracle.State2(g, d["qm"], xa[0], xa[1], raw["u"][:, o], raw["qw"][o])
+    else:
+        p = sim.particles(0)
+        o = np.argsort(p["id"])
+        st = oracle.State2(g, d["qm"], p["x"][0, o] / 0.2, p["x"][1, o] / 0.2, p["u"][:, o],
+                           d["q"] * p["w"][o])
+    sim.step(20)
+    st.step(20)
+    E1, _ = sim.fields(0)
+    scale = max(np.abs(st.E).max(), 1e-3)
+    assert np.abs(E1 - st.E).max() <= (1e-4 if prec == "fp32" else 1e-9) * scale
+    dg = sim.diagnostics(0)
+    assert dg["gauss_l2"] <= (2e-5 if prec == "fp32" else 1e-11) * dg["gauss_ref_l2"]
+    sim.close()
