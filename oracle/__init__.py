@@ -47,6 +47,17 @@ class Grid3(ctypes.Structure):
     ]
 
 
+class GridQ(ctypes.Structure):
+    """Mirror of ``or_gridq`` (quasi-3D r-z grid with azimuthal modes)."""
+
+    _fields_ = [
+        ("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("nmodes", ctypes.c_int32),
+        ("dz", ctypes.c_double), ("dr", ctypes.c_double), ("dt", ctypes.c_double),
+        ("alpha", ctypes.c_double), ("deriv1", ctypes.c_int32), ("correct", ctypes.c_int32),
+        ("kmod", ctypes.c_int32),
+    ]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -56,6 +67,7 @@ def lib():
         L = ctypes.CDLL(_LIBPATH)
         G = ctypes.POINTER(Grid2)
         G3 = ctypes.POINTER(Grid3)
+        GQ = ctypes.POINTER(GridQ)
         sig = {
             "or_fft": (ctypes.c_int, [ctypes.c_int32, _D, _D, ctypes.c_int32]),
             "or_rfft_rows": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _D, _D, _D]),
@@ -83,6 +95,9 @@ def lib():
             "or_step3": (ctypes.c_int, [G3, ctypes.c_double, ctypes.c_int64, _D, _D, _D, _D, _D,
                                         _D, _D, _D, _D, _D]),
             "or_gauss3": (ctypes.c_int, [G3, _D, _D, _D, _D]),
+            "or_field_update_q": (ctypes.c_int, [GQ, _D, _D, _D]),
+            "or_yee_update_q": (ctypes.c_int, [GQ, _D, _D, _D]),
+            "or_gauss_q": (ctypes.c_int, [GQ, _D, _D, _D]),
             "or_deposit3_fixed": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                  ctypes.c_float, ctypes.c_float, ctypes.c_int64,
                                                  _I32, _F, _I32, _F, _F, _I64]),
@@ -387,3 +402,39 @@ def courant_limit3(dx1, dx2, dx3):
     """Largest stable time step of the 3D hybrid solver: Eq. (22) with the x3
     difference added, 2 / sqrt(pi^2/dx1^2 + 4/dx2^2 + 4/dx3^2)."""
     return 2.0 / np.sqrt(np.pi ** 2 / dx1 ** 2 + 4.0 / dx2 ** 2 + 4.0 / dx3 ** 2)
+
+
+# ------------------------------------------------------------------ quasi-3D
+def gridq(n1, n2, nmodes, dz, dr, dt, alpha=1.0, deriv1=0, correct=1, kmod=0):
+    g = GridQ()
+    g.n1, g.n2, g.nmodes = int(n1), int(n2), int(nmodes)
+    g.dz, g.dr, g.dt = float(dz), float(dr), float(dt)
+    g.alpha = float(alpha)
+    g.deriv1, g.correct, g.kmod = int(deriv1), int(correct), int(kmod)
+    return g
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def field_update_q(g, E, B, J):
+    """E, B, J: complex [nmodes][3][n2+1][n1]; returns the updated (E, B)."""
+    E, B, J = _c128(E).copy(), _c128(B).copy(), _c128(J)
+    if lib().or_field_update_q(ctypes.byref(g), _p(E), _p(B), _p(J)) != 0:
+        raise ValueError("bad grid")
+    return E, B
+
+
+def yee_update_q(g, E, B, J):
+    E, B, J = _c128(E).copy(), _c128(B).copy(), _c128(J)
+    lib().or_yee_update_q(ctypes.byref(g), _p(E), _p(B), _p(J))
+    return E, B
+
+
+def gauss_q(g, E, rho):
+    """Gauss residual per mode on the integer nodes: [nmodes][n2+1][n1] complex."""
+    E, rho = _c128(E), _c128(rho)
+    R = np.zeros((g.nmodes, g.n2 + 1, g.n1), dtype=np.complex128)
+    lib().or_gauss_q(ctypes.byref(g), _p(E), _p(rho), _p(R))
+    return R

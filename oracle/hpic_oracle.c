@@ -975,3 +975,261 @@ int or_deposit3_fixed(int32_t n1, int32_t n2, int32_t n3, float inv_wunit, float
   }
   return status;
 }
+
+/* ======================================================================== */
+/* Quasi-3D (r-z with azimuthal modes): field solver                         */
+/* ======================================================================== */
+/*
+ * Fields are expanded in azimuthal modes F(z, r, th) = sum_m Re(F_m(z, r) e^{i m th});
+ * each mode is a complex field on an r-z Yee grid, with z = x1 (the FFT
+ * direction, periodic) and r = x2 (finite differences, axis at r = 0,
+ * conducting wall at r = n2 dr).  Storage per mode: [6][n2+1][n1] complex,
+ * components Ez, Er, Eth, Bz, Br, Bth (the Cartesian order with x1 = z,
+ * x2 = r, x3 = th) on the staggered nodes Ez (z+1/2, r_j), Er (z, r_{j+1/2}),
+ * Eth (z, r_j), Bz (z, r_{j+1/2}), Br (z+1/2, r_j), Bth (z+1/2, r_{j+1/2}),
+ * r_j = j dr; half-r components use rows 0..n2-1.  The curls, with
+ * d/dth -> i m:
+ *   (curl E)_z  = (1/r) d_r(r Eth) - (i m / r) Er
+ *   (curl E)_r  = (i m / r) Ez - d_z Eth
+ *   (curl E)_th = d_z Er - d_r Ez
+ * and the same for B; d_z is i k1 xi+- (the hybrid symbol, FD symbol for
+ * deriv1 = 1), d_r the staggered difference, (1/r) d_r (r .) its volume form.
+ * Axis rules (from the behaviour ~ r^|m| of the z components and ~ r^(|m|-1)
+ * of the r, th components near r = 0): m = 0: Eth = Br = 0 on the axis and
+ * (curl B)_z = 4 Bth(dr/2) / dr there (Stokes over the disc of radius dr/2);
+ * m = 1: Ez = 0 on the axis, (i m / r) Ez -> i Ez(dr) / dr and
+ * d_r Bz -> 2 Bz(dr/2) / dr; m >= 2: every component is zero on the axis.
+ * Wall: Ez = Eth = 0 (and Br keeps its initial zero).
+ */
+static double complex *qf(const or_gridq *g, double complex *F, int m, int c) {
+  return F + ((int64_t)m * 6 + c) * (int64_t)(g->n2 + 1) * g->n1;
+}
+
+/* x1 symbol for the complex (c2c) transform: kappa in [0, n1), signed k1 */
+static xsym x1_symbols_q(const or_gridq *g, int32_t kappa) {
+  or_grid2 g2;
+  memset(&g2, 0, sizeof g2);
+  int32_t ks = kappa <= g->n1 / 2 ? kappa : kappa - g->n1;
+  g2.n1 = g->n1; g2.dx1 = g->dz; g2.dt = g->dt; g2.alpha = g->alpha;
+  g2.deriv1 = g->deriv1; g2.correct = g->correct; g2.kmod = g->kmod;
+  xsym s = x1_symbols(&g2, ks < 0 ? -ks : ks);
+  if (ks < 0) {  /* symbols of -|k| are the conjugates: i(-k) e^{-i k dz/2} */
+    s.dp = conj(s.dp);
+    s.dm = conj(s.dm);
+  }
+  return s;
+}
+
+/* B -= h curl E for one mode in (kappa, r) space (h = dt/2). */
+static void q_faraday(const or_gridq *g, int m, double complex *F, double h) {
+  int32_t n1 = g->n1, n2 = g->n2;
+  double dr = g->dr;
+  double complex *Ez = qf(g, F, m, 0), *Er = qf(g, F, m, 1), *Et = qf(g, F, m, 2);
+  double complex *Bz = qf(g, F, m, 3), *Br = qf(g, F, m, 4), *Bt = qf(g, F, m, 5);
+  double complex im = I * (double)m;
+  for (int32_t k = 0; k < n1; ++k) {
+    xsym s = x1_symbols_q(g, k);
+    for (int32_t j = 0; j < n2; ++j) {          /* half-r rows: Bz, Bth */
+      int64_t c = (int64_t)j * n1 + k, u = (int64_t)(j + 1) * n1 + k;
+      double rh = (j + 0.5) * dr;
+      double complex cz = ((j + 1) * dr * Et[u] - j * dr * Et[c]) / (rh * dr) - im / rh * Er[c];
+      double complex ct = s.dp * Er[c] - (Ez[u] - Ez[c]) / dr;
+      Bz[c] -= h * cz;
+      Bt[c] -= h * ct;
+    }
+    for (int32_t j = 0; j <= n2; ++j) {         /* integer-r rows: Br */
+      int64_t c = (int64_t)j * n1 + k;
+      double complex cr;
+      if (j == n2) continue;                    /* wall: stays zero */
+      if (j == 0) {
+        if (m != 1) continue;                   /* zero on the axis */
+        cr = I * Ez[(int64_t)n1 + k] / dr - s.dp * Et[c];
+      } else {
+        cr = im / (j * dr) * Ez[c] - s.dp * Et[c];
+      }
+      Br[c] -= h * cr;
+    }
+  }
+}
+
+/* E += dt (curl B - J) for one mode. */
+static void q_ampere(const or_gridq *g, int m, double complex *F, const double complex *Jm) {
+  int32_t n1 = g->n1, n2 = g->n2;
+  double dr = g->dr, dt = g->dt;
+  double complex *Ez = qf(g, F, m, 0), *Er = qf(g, F, m, 1), *Et = qf(g, F, m, 2);
+  double complex *Bz = qf(g, F, m, 3), *Br = qf(g, F, m, 4), *Bt = qf(g, F, m, 5);
+  int64_t plane = (int64_t)(n2 + 1) * n1;
+  const double complex *Jz = Jm, *Jr = Jm + plane, *Jt = Jm + 2 * plane;
+  double complex im = I * (double)m;
+  for (int32_t k = 0; k < n1; ++k) {
+    xsym s = x1_symbols_q(g, k);
+    for (int32_t j = 0; j < n2; ++j) {          /* Er on half-r rows */
+      int64_t c = (int64_t)j * n1 + k;
+      double rh = (j + 0.5) * dr;
+      Er[c] += dt * (im / rh * Bz[c] - s.dm * Bt[c] - Jr[c]);
+    }
+    for (int32_t j = 0; j < n2; ++j) {          /* Ez, Eth on integer rows; wall stays 0 */
+      int64_t c = (int64_t)j * n1 + k, d = (int64_t)(j - 1) * n1 + k;
+      if (j == 0) {
+        if (m == 0) Ez[c] += dt * (4.0 * Bt[c] / dr - Jz[c]);
+        if (m == 1) Et[c] += dt * (s.dm * Br[c] - 2.0 * Bz[c] / dr - Jt[c]);
+        continue;
+      }
+      double rj = j * dr;
+      double complex cz = ((j + 0.5) * dr * Bt[c] - (j - 0.5) * dr * Bt[d]) / (rj * dr) - im / rj * Br[c];
+      double complex ct = s.dm * Br[c] - (Bz[c] - Bz[d]) / dr;
+      Ez[c] += dt * (cz - Jz[c]);
+      Et[c] += dt * (ct - Jt[c]);
+    }
+  }
+}
+
+/* Complex transform of every row of a mode's component along z. */
+static void q_rows(const or_gridq *g, double complex *F, int32_t nrows, int sign) {
+  int32_t n1 = g->n1;
+  double *re = malloc(sizeof(double) * n1), *im = malloc(sizeof(double) * n1);
+  for (int32_t r = 0; r < nrows; ++r) {
+    double complex *row = F + (int64_t)r * n1;
+    for (int32_t i = 0; i < n1; ++i) { re[i] = creal(row[i]); im[i] = cimag(row[i]); }
+    or_fft(n1, re, im, sign);
+    double sc = sign > 0 ? 1.0 / n1 : 1.0;
+    for (int32_t i = 0; i < n1; ++i) row[i] = sc * (re[i] + I * im[i]);
+  }
+  free(re); free(im);
+}
+
+int or_field_update_q(const or_gridq *g, double *Ed, double *Bd, const double *Jd) {
+  int32_t n1 = g->n1, n2 = g->n2, M = g->nmodes;
+  if (!is_pow2(n1) || n1 < 2 || n2 < 2 || M < 1) return -1;
+  int64_t plane = (int64_t)(n2 + 1) * n1;
+  /* work array [m][6][rows][n1] with E and B of each mode */
+  double complex *F = malloc(sizeof(double complex) * 6 * plane * M);
+  double complex *Jk = malloc(sizeof(double complex) * 3 * plane);
+  const double complex *E = (const double complex *)Ed, *B = (const double complex *)Bd,
+                       *J = (const double complex *)Jd;
+  for (int m = 0; m < M; ++m) {
+    memcpy(qf(g, F, m, 0), E + (int64_t)m * 3 * plane, sizeof(double complex) * 3 * plane);
+    memcpy(qf(g, F, m, 3), B + (int64_t)m * 3 * plane, sizeof(double complex) * 3 * plane);
+    q_rows(g, qf(g, F, m, 0), 6 * (n2 + 1), -1);
+    memcpy(Jk, J + (int64_t)m * 3 * plane, sizeof(double complex) * 3 * plane);
+    q_rows(g, Jk, 3 * (n2 + 1), -1);
+    for (int32_t k = 0; k < n1; ++k) {
+      xsym s = x1_symbols_q(g, k);
+      for (int32_t j = 0; j <= n2; ++j) {
+        int64_t c = (int64_t)j * n1 + k;
+        Jk[c] *= s.corr * s.filt;           /* Eq. (11) on jz, then the filter */
+        Jk[plane + c] *= s.filt;
+        Jk[2 * plane + c] *= s.filt;
+      }
+    }
+    q_faraday(g, m, F, 0.5 * g->dt);
+    q_ampere(g, m, F, Jk);
+    q_faraday(g, m, F, 0.5 * g->dt);
+    q_rows(g, qf(g, F, m, 0), 6 * (n2 + 1), +1);
+    memcpy((double complex *)Ed + (int64_t)m * 3 * plane, qf(g, F, m, 0), sizeof(double complex) * 3 * plane);
+    memcpy((double complex *)Bd + (int64_t)m * 3 * plane, qf(g, F, m, 3), sizeof(double complex) * 3 * plane);
+  }
+  free(F); free(Jk);
+  return 0;
+}
+
+/* The same update directly in real space with Yee differences along z (no
+ * transform, filter or correction): the reference for deriv1 = 1. */
+int or_yee_update_q(const or_gridq *g, double *Ed, double *Bd, const double *Jd) {
+  int32_t n1 = g->n1, n2 = g->n2, M = g->nmodes;
+  int64_t plane = (int64_t)(n2 + 1) * n1;
+  double dz = g->dz, dr = g->dr, dt = g->dt;
+  for (int m = 0; m < M; ++m) {
+    double complex *Ez = (double complex *)Ed + (int64_t)m * 3 * plane, *Er = Ez + plane, *Et = Ez + 2 * plane;
+    double complex *Bz = (double complex *)Bd + (int64_t)m * 3 * plane, *Br = Bz + plane, *Bt = Bz + 2 * plane;
+    const double complex *Jz = (const double complex *)Jd + (int64_t)m * 3 * plane, *Jr = Jz + plane, *Jt = Jz + 2 * plane;
+    double complex im = I * (double)m;
+    for (int half = 0; half < 3; ++half) {
+      if (half == 1) {
+        for (int32_t j = 0; j < n2; ++j)
+          for (int32_t i = 0; i < n1; ++i) {
+            int64_t c = (int64_t)j * n1 + i, w = (int64_t)j * n1 + wrapi(i - 1, n1);
+            double rh = (j + 0.5) * dr;
+            Er[c] += dt * (im / rh * Bz[c] - (Bt[c] - Bt[w]) / dz - Jr[c]);
+          }
+        for (int32_t j = 0; j < n2; ++j)
+          for (int32_t i = 0; i < n1; ++i) {
+            int64_t c = (int64_t)j * n1 + i, d = (int64_t)(j - 1) * n1 + i;
+            int64_t w = (int64_t)j * n1 + wrapi(i - 1, n1);
+            double complex dzBr = (Br[c] - Br[w]) / dz;
+            if (j == 0) {
+              if (m == 0) Ez[c] += dt * (4.0 * Bt[c] / dr - Jz[c]);
+              if (m == 1) Et[c] += dt * (dzBr - 2.0 * Bz[c] / dr - Jt[c]);
+              continue;
+            }
+            double rj = j * dr;
+            Ez[c] += dt * (((j + 0.5) * dr * Bt[c] - (j - 0.5) * dr * Bt[d]) / (rj * dr) - im / rj * Br[c] - Jz[c]);
+            Et[c] += dt * (dzBr - (Bz[c] - Bz[d]) / dr - Jt[c]);
+          }
+        continue;
+      }
+      double h = 0.5 * dt;
+      for (int32_t j = 0; j < n2; ++j)
+        for (int32_t i = 0; i < n1; ++i) {
+          int64_t c = (int64_t)j * n1 + i, u = (int64_t)(j + 1) * n1 + i;
+          int64_t e = (int64_t)j * n1 + wrapi(i + 1, n1);
+          double rh = (j + 0.5) * dr;
+          double complex cz = ((j + 1) * dr * Et[u] - j * dr * Et[c]) / (rh * dr) - im / rh * Er[c];
+          double complex ct = (Er[e] - Er[c]) / dz - (Ez[u] - Ez[c]) / dr;
+          Bz[c] -= h * cz;
+          Bt[c] -= h * ct;
+        }
+      for (int32_t j = 0; j < n2; ++j)
+        for (int32_t i = 0; i < n1; ++i) {
+          int64_t c = (int64_t)j * n1 + i, e = (int64_t)j * n1 + wrapi(i + 1, n1);
+          double complex cr;
+          if (j == 0) {
+            if (m != 1) continue;
+            cr = I * Ez[(int64_t)n1 + i] / dr - (Et[e] - Et[c]) / dz;
+          } else {
+            cr = im / (j * dr) * Ez[c] - (Et[e] - Et[c]) / dz;
+          }
+          Br[c] -= h * cr;
+        }
+    }
+  }
+  return 0;
+}
+
+/* Gauss residual of each mode on the integer nodes (z_i, r_j), j = 0..n2-1:
+ * D.E - f rho with D.E = (1/r) d_r(r Er) + (i m / r) Eth + d_z Ez in (kappa, r)
+ * space; on the axis only m = 0 is defined (4 Er(dr/2)/dr + d_z Ez), other
+ * modes get 0 there.  rho and R are [m][n2+1][n1] complex (row n2 of R is 0). */
+int or_gauss_q(const or_gridq *g, const double *Ed, const double *rhod, double *Rd) {
+  int32_t n1 = g->n1, n2 = g->n2, M = g->nmodes;
+  int64_t plane = (int64_t)(n2 + 1) * n1;
+  double complex *T = malloc(sizeof(double complex) * 4 * plane);
+  double complex *R = (double complex *)Rd;
+  for (int m = 0; m < M; ++m) {
+    memcpy(T, (const double complex *)Ed + (int64_t)m * 3 * plane, sizeof(double complex) * 3 * plane);
+    memcpy(T + 3 * plane, (const double complex *)rhod + (int64_t)m * plane, sizeof(double complex) * plane);
+    q_rows(g, T, 4 * (n2 + 1), -1);
+    double complex *Ez = T, *Er = T + plane, *Et = T + 2 * plane, *rh = T + 3 * plane;
+    double complex *Rm = R + (int64_t)m * plane;
+    for (int32_t k = 0; k < n1; ++k) {
+      xsym s = x1_symbols_q(g, k);
+      for (int32_t j = 0; j <= n2; ++j) {
+        int64_t c = (int64_t)j * n1 + k, d = (int64_t)(j - 1) * n1 + k;
+        double complex div = 0;
+        if (j == n2) { Rm[c] = 0; continue; }
+        if (j == 0) {
+          if (m != 0) { Rm[c] = 0; continue; }
+          div = 4.0 * Er[c] / g->dr + s.dm * Ez[c];
+        } else {
+          double rj = j * g->dr;
+          div = ((j + 0.5) * Er[c] - (j - 0.5) * Er[d]) / (j * g->dr) + I * (double)m / rj * Et[c] +
+                s.dm * Ez[c];
+        }
+        Rm[c] = div - s.filt * rh[c];
+      }
+    }
+    q_rows(g, Rm, n2 + 1, +1);
+  }
+  free(T);
+  return 0;
+}

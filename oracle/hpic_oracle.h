@@ -157,6 +157,25 @@ int or_deposit3_fixed(int32_t n1, int32_t n2, int32_t n3, float inv_wunit, float
                       const int32_t *ca, const float *fa, const int32_t *cb, const float *fb,
                       const float *qw, int64_t *J);
 
+/* ---- Quasi-3D (r-z, azimuthal modes m = 0..nmodes-1): field solver ----
+ * z = x1 (FFT, periodic, n1 points, dz), r = x2 (n2 cells of dr, axis at r = 0,
+ * conducting wall at r = n2 dr).  Per mode complex arrays [3][n2+1][n1]
+ * (components Ez, Er, Eth, or Bz, Br, Bth; see the .c file for the staggering
+ * and the axis rules); E, B, J pass all modes back to back as interleaved
+ * (re, im) doubles: [nmodes][3][n2+1][n1][2]. */
+typedef struct or_gridq {
+  int32_t n1, n2, nmodes;
+  double dz, dr, dt;
+  double alpha;
+  int32_t deriv1;
+  int32_t correct;
+  int32_t kmod;
+} or_gridq;
+
+int or_field_update_q(const or_gridq *g, double *E, double *B, const double *J);
+int or_yee_update_q(const or_gridq *g, double *E, double *B, const double *J);
+int or_gauss_q(const or_gridq *g, const double *E, const double *rho, double *R);
+
 #ifdef __cplusplus
 }
 #endif
