@@ -24,6 +24,15 @@
  * i3), E3 (i1, i2, i3+1/2), B1 (i1, i2+1/2, i3+1/2), B2 (i1+1/2, i2, i3+1/2),
  * B3 (i1+1/2, i2+1/2, i3); the transforms run along x1 over the n2 n3 rows.
  * Below, "[dim]" is 2 or 3 and "cells" n1 n2 (2D) or n1 n2 n3 (3D).
+ * Quasi-3D (HP_GEOM_Q3D, Sec. 5: the hybrid update per azimuthal mode):
+ * z = x1 (n[0] points, dx[0], FFT), r = x2 (n[1] cells of dx[1], axis at
+ * r = 0, conducting wall at r = n[1] dx[1]), modes m = 0..n_modes-1 of
+ * F = sum_m Re(F_m e^{i m theta}); per mode complex fields [3][n2+1][n1]
+ * (Ez, Er, Eth and Bz, Br, Bth on the r-z Yee nodes) passed as interleaved
+ * (re, im) doubles.  Only the field solver is built for this geometry:
+ * hp_set_fields / hp_get_field (with mode), hp_step (vacuum update of every
+ * mode), hp_diagnostics (energies, Gauss residual D.E), timing; the particle
+ * calls return HP_EINVAL.
  * Units: c = 1, t in 1/w_p, x in c/w_p, E and B in m c w_p / e, density in
  * n_p, current in e n_p c (the 4 pi of the paper's Gaussian form is 1).
  *
@@ -52,6 +61,7 @@ extern "C" {
 
 #define HP_GEOM_2D 2
 #define HP_GEOM_3D 3
+#define HP_GEOM_Q3D 4  /* quasi-3D r-z with azimuthal modes (field solver only) */
 
 #define HP_PREC_FP32_FIXED 0 /* FP32 push/FFT/update, 64-bit fixed-point deposit */
 #define HP_PREC_FP64 1       /* FP64 everywhere, FP64 atomics in the deposit */
@@ -133,7 +143,8 @@ int hp_set_particles(hp_sim *sim, int32_t run, int32_t species, int64_t n, const
                      const double *u, const double *w, double q_over_m, double q);
 
 /* Sets E^0 and B^0 of a run from host arrays E[3][cells], B[3][cells] at
- * their Yee nodes (mode must be 0). */
+ * their Yee nodes (mode must be 0).  Quasi-3D: mode m, complex interleaved
+ * E[3][n2+1][n1][2], B likewise. */
 int hp_set_fields(hp_sim *sim, int32_t run, int32_t mode, const double *E, const double *B);
 
 /* Background of a run: with rho_from_particles = 1 the fixed charge density
@@ -183,7 +194,8 @@ int hp_use_graphs(hp_sim *sim, int32_t enable);
 int hp_synchronize(hp_sim *sim);
 
 /* Copies field component comp (0..2 = E1..E3, 3..5 = B1..B3) of a run into
- * out[count], count = cells (else HP_EINVAL).  Synchronous. */
+ * out[count], count = cells (else HP_EINVAL).  Synchronous.  Quasi-3D: mode
+ * m, complex interleaved, count = 2 (n2+1) n1. */
 int hp_get_field(hp_sim *sim, int32_t run, int32_t comp, int32_t mode, double *out,
                  size_t count);
 

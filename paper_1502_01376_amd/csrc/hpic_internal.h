@@ -282,6 +282,39 @@ struct Launch {
                           int maxM, hipStream_t s);
 };
 
+// ---------------------------------------------------------------- quasi-3D
+// One quasi-3D run: azimuthal modes m = 0..M-1 of an r-z grid, z = x1 (n1
+// points, FFT, periodic), r = x2 (n2 cells, nr = n2 + 1 rows, axis at j = 0,
+// conducting wall at j = n2).  Per mode complex arrays [6][nr][n1] in the
+// order Ez, Er, Eth, Bz, Br, Bth, staggered Ez (z+1/2, r_j), Er (z, r_j+1/2),
+// Eth (z, r_j), Bz (z, r_j+1/2), Br (z+1/2, r_j), Bth (z+1/2, r_j+1/2).
+template <class R>
+struct RunQ {
+  using C = typename Cplx<R>::T;
+  int n1, n2, nr, M, log2n1;
+  long long plane;   // nr * n1
+  double dz, dr, dt, hdt;
+  double2 *Fk[2];    // [M][6][nr][n1] k-space master (FP64), ping-pong by step parity
+  C *F;              // [M][6][nr][n1] real-space fields (complex)
+  const C *tw;       // [n1]: exp(-2 pi i m / n1)
+  const double *sym; // [n1][4]: i [k]1 xi+ (re, im), i [k]1 xi- (re, im), signed k1
+};
+template <class R>
+struct LaunchQ {
+  // forward transform of the real-space fields into the master of a parity
+  static void fields_to_k(const RunQ<R> *runs, const Item *items, int nitems, int parity,
+                          int maxn1, hipStream_t s);
+  // the hybrid update of every mode, parity -> parity ^ 1 (two passes)
+  static void kupdate(const RunQ<R> *runs, const Item *items, int nitems, int parity,
+                      hipStream_t s);
+  // inverse transform of the master of a parity into the real-space fields
+  static void ifft(const RunQ<R> *runs, const Item *items, int nitems, int parity, int maxn1,
+                   hipStream_t s);
+  // per (run, mode, row): sum |D.E|^2 and max |D.E| of the master (vacuum Gauss)
+  static void gauss(const RunQ<R> *runs, const Item *items, int nitems, int parity,
+                    double *rows_out, hipStream_t s);
+};
+
 // Diagnostics and helpers (FP64 unless noted).
 // 3D: charge density in FP64 from the particle state (any form).
 template <class R>

@@ -15,6 +15,7 @@ HP_OK, HP_EINVAL, HP_ECOURANT, HP_ENOMEM, HP_EDEVICE, HP_ERANGE, HP_ENUMERIC, HP
     0, -1, -2, -3, -4, -5, -6, -7)
 HP_GEOM_2D = 2
 HP_GEOM_3D = 3
+HP_GEOM_Q3D = 4
 HP_PREC_FP32_FIXED, HP_PREC_FP64 = 0, 1
 KERNELS = ("push_deposit", "fft_j", "kupdate", "ifft_eb", "sort")
 HP_NK = len(KERNELS)
@@ -129,10 +130,13 @@ def _ptr(a):
 
 
 def config(n1, n2, dx1, dx2, dt, alpha=0.5, deriv1=0, correct=1, precision="fp32",
-           shape_bits=0, weight_bits=0, sort_interval=0, n3=0, dx3=0.0, kmod=0):
-    """Configuration of one run; n3 > 0 makes it a 3D run (n1 x n2 x n3 cells)."""
+           shape_bits=0, weight_bits=0, sort_interval=0, n3=0, dx3=0.0, kmod=0, modes=0):
+    """Configuration of one run; n3 > 0 makes it a 3D run (n1 x n2 x n3 cells);
+    modes > 0 a quasi-3D run (n1 points along z of dx1, n2 radial cells of dx2,
+    azimuthal modes 0..modes-1)."""
     c = Config()
-    c.geom = HP_GEOM_3D if n3 > 0 else HP_GEOM_2D
+    c.geom = HP_GEOM_3D if n3 > 0 else (HP_GEOM_Q3D if modes > 0 else HP_GEOM_2D)
+    c.n_modes = int(modes)
     c.n[0], c.n[1], c.n[2] = int(n1), int(n2), int(n3) if n3 > 0 else 1
     c.dx[0], c.dx[1], c.dx[2] = float(dx1), float(dx2), float(dx3) if n3 > 0 else 1.0
     c.dt = float(dt)
@@ -176,6 +180,8 @@ class Sim:
         c = self.cfgs[run]
         if c.geom == HP_GEOM_3D:
             return c.n[2], c.n[1], c.n[0]
+        if c.geom == HP_GEOM_Q3D:
+            return c.n[1] + 1, c.n[0]
         return c.n[1], c.n[0]
 
     def dim(self, run):
@@ -193,6 +199,20 @@ class Sim:
         assert x.shape == (self.dim(run), n) and u.shape == (3, n)
         _check(lib().hp_set_particles(self.h, run, 0, n, _ptr(x), _ptr(u), _ptr(w),
                                       float(q_over_m), float(q)))
+
+    def set_fields_mode(self, run, mode, E, B):
+        """Quasi-3D: complex E, B [3][n2+1][n1] of azimuthal mode `mode`."""
+        sh = (3,) + self.shape(run)
+        E = np.ascontiguousarray(E, dtype=np.complex128)
+        B = np.ascontiguousarray(B, dtype=np.complex128)
+        assert E.shape == sh and B.shape == sh
+        _check(lib().hp_set_fields(self.h, run, int(mode), _ptr(E), _ptr(B)))
+
+    def field_mode(self, run, comp, mode):
+        """Quasi-3D: complex field component comp of mode `mode`, [n2+1][n1]."""
+        out = np.empty(self.shape(run), dtype=np.complex128)
+        _check(lib().hp_get_field(self.h, run, comp, int(mode), _ptr(out), 2 * out.size))
+        return out
 
     def set_fields(self, run, E, B):
         sh = (3,) + self.shape(run)
