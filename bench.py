@@ -51,6 +51,8 @@ def parse():
                     help="steps of the 64-run parameter scan (0: skip)")
     ap.add_argument("--d3-steps", type=int, default=500,
                     help="steps of the 3D 512x128x128 drifting-plasma leg (0: skip)")
+    ap.add_argument("--q3d-steps", type=int, default=200,
+                    help="steps of the quasi-3D 4096x256 three-mode field solve (0: skip)")
     ap.add_argument("--n1", type=int, default=2048)
     ap.add_argument("--n2", type=int, default=512)
     return ap.parse_args()
@@ -229,6 +231,43 @@ def d3_leg(hpic, torch, W, steps, tune_steps):
             "push_deposit_alg_GBps": (60 * npart + 72 * cells) / (pd_ms / max(pd_n, 1) * 1e-3) / 1e9}
 
 
+def q3d_leg(hpic, torch, steps):
+    """Quasi-3D field solver: 4096 (z) x 256 (r) cells, dz = 0.1, dr = 0.2,
+    dt = 0.04, azimuthal modes 0, 1, 2 advanced together (one launch per
+    stage), seeded with an m = 1 laser-like field a0 = 1 (synthetic).  Only the
+    field solver is built for this geometry, so the figure is mode-cells per
+    second, with per-kernel times and the FP64 form beside it."""
+    n1, n2, M, dz, dr, dt = 4096, 256, 3, 0.1, 0.2, 0.04
+    z = np.arange(n1) * dz
+    r = np.arange(n2 + 1) * dr
+    env = np.exp(-((z - 0.6 * n1 * dz) / 4.0) ** 2)[None, :] * np.exp(-(r / 8.0) ** 2)[:, None]
+    out = {"workload": "quasi3d_4096x256_m012_fields", "n": [n1, n2], "modes": M, "steps": steps}
+    for prec in ("fp32", "fp64"):
+        sim = hpic.Sim([hpic.config(n1, n2, dz, dr, dt, alpha=0.5, precision=prec, modes=M)],
+                       stream=torch.cuda.current_stream())
+        E = np.zeros((3, n2 + 1, n1), complex)
+        B = np.zeros_like(E)
+        E[1] = env * np.exp(10j * z)[None, :]          # E_r + i E_th of an m = 1 field
+        E[2] = 1j * E[1]
+        B[1] = -E[2]
+        B[2] = E[1]
+        E[:, n2] = 0
+        B[:, n2] = 0
+        sim.set_fields_mode(0, 1, E, B)
+        t = timed_steps(torch, sim, 10, steps)
+        sim.profile(True)
+        sim.step(steps)
+        kt = sim.kernel_times()
+        d = sim.diagnostics(0)
+        sim.close()
+        out[prec] = {"ms_per_step": 1e3 * t / steps,
+                     "mode_cells_per_s": M * n1 * (n2 + 1) * steps / t,
+                     "kernels": {k: {"avg_us": 1e3 * ms / n, "launches": n}
+                                 for k, (ms, n) in kt.items() if n > 0},
+                     "field_energy": sum(d["W_E"]) + sum(d["W_B"])}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -318,6 +357,8 @@ def main():
         out["scan2d"] = scan_leg(hpic, torch, W, args.scan_steps, args.tune_steps)
     if args.d3_steps > 0:
         out["drift3d"] = d3_leg(hpic, torch, W, args.d3_steps, args.tune_steps)
+    if args.q3d_steps > 0:
+        out["quasi3d"] = q3d_leg(hpic, torch, args.q3d_steps)
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
         x = torch.ones(n, dtype=torch.float32, device="cuda")
