@@ -98,6 +98,12 @@ def lib():
             "or_field_update_q": (ctypes.c_int, [GQ, _D, _D, _D]),
             "or_yee_update_q": (ctypes.c_int, [GQ, _D, _D, _D]),
             "or_gauss_q": (ctypes.c_int, [GQ, _D, _D, _D]),
+            "or_gather_q": (ctypes.c_int, [GQ, _D, _D, ctypes.c_int64, _D, _D, _D, _D, _D]),
+            "or_deposit_q": (ctypes.c_int, [GQ, ctypes.c_int64, _D, _D, _D, _D, _D, _D, _D, _D]),
+            "or_rho_q": (ctypes.c_int, [GQ, ctypes.c_int64, _D, _D, _D, _D, _D]),
+            "or_jbg_q": (ctypes.c_int, [GQ, ctypes.c_int64, _D, _D, _D, _D, _D, _D, _D]),
+            "or_step_q": (ctypes.c_int, [GQ, ctypes.c_double, ctypes.c_int64, _D, _D, _D, _D, _D,
+                                         _D, _D, _D, _D, _D, _D]),
             "or_deposit3_fixed": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                  ctypes.c_float, ctypes.c_float, ctypes.c_int64,
                                                  _I32, _F, _I32, _F, _F, _I64]),
@@ -438,3 +444,87 @@ def gauss_q(g, E, rho):
     R = np.zeros((g.nmodes, g.n2 + 1, g.n1), dtype=np.complex128)
     lib().or_gauss_q(ctypes.byref(g), _p(E), _p(rho), _p(R))
     return R
+
+
+# ------------------------------------------------------- quasi-3D particles
+def _shapeq(g):
+    return (g.nmodes, 3, g.n2 + 1, g.n1)
+
+
+def gather_q(g, E, B, pos):
+    """Cartesian E, B (order z, x, y) at particles pos = (z, x, y)."""
+    E, B = _c128(E), _c128(B)
+    z, x, y = (_f64(pos[d]) for d in range(3))
+    n = len(z)
+    Ep = np.zeros((3, n))
+    Bp = np.zeros((3, n))
+    st = lib().or_gather_q(ctypes.byref(g), _p(E), _p(B), n, _p(z), _p(x), _p(y), _p(Ep), _p(Bp))
+    if st != 0:
+        raise ValueError("a particle is outside r < (n2 - 3) dr")
+    return Ep, Bp
+
+
+def deposit_q(g, pa, pb, qw):
+    """Per-mode current [nmodes][3][n2+1][n1] of the moves pa -> pb (each
+    (z, x, y), z unwrapped) over one step."""
+    a = [_f64(pa[d]) for d in range(3)]
+    b = [_f64(pb[d]) for d in range(3)]
+    qw = _f64(qw)
+    J = np.zeros(_shapeq(g), dtype=np.complex128)
+    st = lib().or_deposit_q(ctypes.byref(g), len(qw), _p(a[0]), _p(a[1]), _p(a[2]), _p(b[0]),
+                            _p(b[1]), _p(b[2]), _p(qw), _p(J))
+    if st != 0:
+        raise ValueError("a particle moved a cell or more, or is outside r < (n2 - 3) dr")
+    return J
+
+
+def rho_q(g, pos, qw):
+    z, x, y = (_f64(pos[d]) for d in range(3))
+    qw = _f64(qw)
+    rho = np.zeros((g.nmodes, g.n2 + 1, g.n1), dtype=np.complex128)
+    if lib().or_rho_q(ctypes.byref(g), len(qw), _p(z), _p(x), _p(y), _p(qw), _p(rho)) != 0:
+        raise ValueError("a particle is outside r < (n2 - 3) dr")
+    return rho
+
+
+def jbg_q(g, pos, u, qw):
+    """Co-drifting background current profile [n2+1] (m = 0, z component)."""
+    x, y = _f64(pos[1]), _f64(pos[2])
+    uz, ux, uy = (_f64(u[d]) for d in range(3))
+    qw = _f64(qw)
+    out = np.zeros(g.n2 + 1)
+    if lib().or_jbg_q(ctypes.byref(g), len(qw), _p(x), _p(y), _p(uz), _p(ux), _p(uy), _p(qw),
+                      _p(out)) != 0:
+        raise ValueError("a particle is outside r < (n2 - 3) dr")
+    return out
+
+
+class StateQ:
+    """Particles and per-mode fields of one quasi-3D run, advanced by ``step``."""
+
+    def __init__(self, g, qm, pos, u, qw, E=None, B=None, jbg=None):
+        self.g, self.qm = g, float(qm)
+        self.pos = [_f64(pos[d]).copy() for d in range(3)]
+        self.u = _f64(u).copy()
+        self.qw = _f64(qw).copy()
+        shape = _shapeq(g)
+        self.E = np.zeros(shape, dtype=np.complex128) if E is None else _c128(E).copy()
+        self.B = np.zeros(shape, dtype=np.complex128) if B is None else _c128(B).copy()
+        self.J = np.zeros(shape, dtype=np.complex128)
+        self.jbg = None if jbg is None else _f64(jbg).copy()
+
+    def rho(self):
+        return rho_q(self.g, self.pos, self.qw)
+
+    def step(self, n=1):
+        g = self.g
+        uz, ux, uy = (np.ascontiguousarray(self.u[c]) for c in range(3))
+        jb = _p(self.jbg) if self.jbg is not None else None
+        for _ in range(n):
+            st = lib().or_step_q(ctypes.byref(g), self.qm, len(self.qw), _p(self.pos[0]),
+                                 _p(self.pos[1]), _p(self.pos[2]), _p(uz), _p(ux), _p(uy),
+                                 _p(self.qw), _p(self.E), _p(self.B), _p(self.J), jb)
+            if st != 0:
+                raise ValueError("oracle step failed (move of a cell or more, or r too large)")
+        self.u = np.stack([uz, ux, uy])
+        return self

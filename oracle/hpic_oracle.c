@@ -1233,3 +1233,297 @@ int or_gauss_q(const or_gridq *g, const double *Ed, const double *rhod, double *
   free(T);
   return 0;
 }
+
+/* ======================================================================== */
+/* Quasi-3D particles: gather from the modes, push, per-mode charge-        */
+/* conserving deposit                                                        */
+/* ======================================================================== */
+/*
+ * Particles carry Cartesian positions (z, x, y) and momenta (uz, ux, uy);
+ * r = hypot(x, y) and the phase of mode m is P_m = e^{-i m th} =
+ * ((x - i y) / r)^m (1 on the axis).  Node weights in (z, r) are the
+ * quadratic B-spline products of the Cartesian code with z and r in cell
+ * units, at the staggered node of each component (the r-z Yee nodes of the
+ * field solver above).  A stencil row below the axis (row -1) is the mirror
+ * point (|r|, th + pi) of row 1 (integer-r nodes) or row 0 (half-r nodes): a
+ * scalar or z component of mode m there is (-1)^m times the mirror value, an
+ * r or th component -(-1)^m times it.
+ *
+ * Gather: F_c = sum_m Re(F_{c,m}(z, r) e^{i m th}), then
+ * (F_r, F_th) -> (F_x, F_y) by the rotation through th.
+ *
+ * Charge per node: rho_m = c_m q w P_m W / V_j, c_0 = 1 and c_m = 2 for m >= 1
+ * (so that sum_m Re(rho_m e^{i m th}) is the particle's density), volumes
+ * V_0 = pi (dr/2)^2 dz (the disc around the axis) and V_j = 2 pi j dr^2 dz.
+ *
+ * Current, charge-conserving per mode.  With W^0, W^1 the old and new node
+ * weights and P^0, P^1 the old and new phases,
+ *   W^1 P^1 - W^0 P^0 = (W^1 - W^0) (P^0 + P^1)/2 + (W^0 + W^1)/2 (P^1 - P^0):
+ * the first term is split into fluxes through the z and r faces by the
+ * Esirkepov decomposition in (z, r) index space (carrying the mean phase),
+ * the second is an azimuthal flux Phi_th with i m dt Phi_th = -c_m q w
+ * (W^0 + W^1)/2 (P^1 - P^0).  The ghost row folds onto its mirror with the
+ * factor (-1)^m for node fluxes (z, th) and -(-1)^m for the flux through the
+ * face at r = -dr/2 (it lands on the face at +dr/2), which keeps continuity
+ * exact on the folded grid.  Densities: Jz = Phi_z / (A_j dt) with the face
+ * areas A_0 = pi dr^2 / 4 and A_j = 2 pi j dr^2, Jr = Phi_r / (2 pi (j+1/2) dr
+ * dz dt), Jth = Phi_th / (2 pi dr dz) (rows j >= 1), where the Phi_z, Phi_r
+ * here are the flux charges (per step).  Then per mode
+ *   rho^{n+1} - rho^n + dt [(Jz_i - Jz_{i-1})/dz
+ *     + ((j+1/2) Jr_j - (j-1/2) Jr_{j-1}) / (j dr) + (i m / (j dr)) Jth_j] = 0
+ * on the rows j >= 1 and, for m = 0, 4 Jr_0 / dr in place of the radial term
+ * on the axis: the discrete divergence of the Gauss residual of the solver.
+ * Where continuity fixes no azimuthal current (m = 0 everywhere, m = 1 on the
+ * axis) Jth is the direct deposit c_m q w P W3 v_th / V_j with the
+ * time-averaged weight W3 of the Cartesian out-of-plane current, the mean
+ * phase, and v_th the azimuthal velocity at the mid point of the move; its
+ * ghost row folds with -(-1)^m (the azimuthal direction reverses across the
+ * axis).  m >= 2 on the axis: no azimuthal current (the fields are zero
+ * there).
+ *
+ * Particles must stay at r < (n2 - 3) dr (no particle boundary at the wall);
+ * the functions report -1 otherwise.
+ */
+static double q_rmax(const or_gridq *g) { return (g->n2 - 3) * g->dr; }
+
+static double q_area(const or_gridq *g, int64_t j) {
+  return j == 0 ? 0.25 * PI * g->dr * g->dr : 2.0 * PI * (double)j * g->dr * g->dr;
+}
+
+static double complex q_phase(double x, double y, int m) {
+  double r = hypot(x, y);
+  double complex u = r > 0.0 ? (x - I * y) / r : 1.0;
+  double complex p = 1.0;
+  for (int k = 0; k < m; ++k) p *= u;
+  return p;
+}
+
+/* mode m of component Fc (one [n2+1][n1] plane) at node (a, b), b >= -1 */
+static double complex q_node(const or_gridq *g, const double complex *Fc, int half_r, int vec,
+                             int m, int64_t a, int64_t b) {
+  double sign = 1.0;
+  if (b < 0) {
+    b = half_r ? -b - 1 : -b;
+    sign = ((m & 1) ? -1.0 : 1.0) * (vec ? -1.0 : 1.0);
+  }
+  return sign * Fc[b * g->n1 + wrapi(a, g->n1)];
+}
+
+/* Fields F[nmodes][3][n2+1][n1] (E or B), component c with staggering s */
+static double q_interp(const or_gridq *g, const double complex *F, int c, const double s[2],
+                       double zeta, double rho, double x, double y) {
+  int64_t plane = (int64_t)(g->n2 + 1) * g->n1;
+  double e1 = zeta - s[0], e2 = rho - s[1];
+  int64_t m1 = (int64_t)floor(e1 + 0.5), m2 = (int64_t)floor(e2 + 0.5);
+  double acc = 0.0;
+  for (int m = 0; m < g->nmodes; ++m) {
+    const double complex *Fc = F + ((int64_t)m * 3 + c) * plane;
+    double complex v = 0.0;
+    for (int64_t b = m2 - 1; b <= m2 + 1; ++b) {
+      double w2 = spline2(e2 - (double)b);
+      for (int64_t a = m1 - 1; a <= m1 + 1; ++a)
+        v += spline2(e1 - (double)a) * w2 * q_node(g, Fc, s[1] > 0.0, c != 0, m, a, b);
+    }
+    acc += creal(v * conj(q_phase(x, y, m)));
+  }
+  return acc;
+}
+
+int or_gather_q(const or_gridq *g, const double *Ed, const double *Bd, int64_t np,
+                const double *z, const double *x, const double *y, double *Ep, double *Bp) {
+  const double complex *E = (const double complex *)Ed, *B = (const double complex *)Bd;
+  int status = 0;
+  for (int64_t p = 0; p < np; ++p) {
+    double r = hypot(x[p], y[p]);
+    double fe[3] = {0, 0, 0}, fb[3] = {0, 0, 0};
+    if (r < q_rmax(g)) {
+      double zeta = z[p] / g->dz, rho = r / g->dr;
+      for (int c = 0; c < 3; ++c) {
+        fe[c] = q_interp(g, E, c, STAG_E[c], zeta, rho, x[p], y[p]);
+        fb[c] = q_interp(g, B, c, STAG_B[c], zeta, rho, x[p], y[p]);
+      }
+    } else {
+      status = -1;
+    }
+    double ct = r > 0.0 ? x[p] / r : 1.0, st = r > 0.0 ? y[p] / r : 0.0;
+    Ep[p] = fe[0];
+    Ep[np + p] = fe[1] * ct - fe[2] * st;
+    Ep[2 * np + p] = fe[1] * st + fe[2] * ct;
+    Bp[p] = fb[0];
+    Bp[np + p] = fb[1] * ct - fb[2] * st;
+    Bp[2 * np + p] = fb[1] * st + fb[2] * ct;
+  }
+  return status;
+}
+
+/* J[nmodes][3][n2+1][n1] complex (Jz, Jr, Jth) += the current of the moves
+ * (za, xa, ya) -> (zb, xb, yb) (zb not wrapped) over one step dt. */
+int or_deposit_q(const or_gridq *g, int64_t np, const double *za, const double *xa,
+                 const double *ya, const double *zb, const double *xb, const double *yb,
+                 const double *qw, double *Jd) {
+  int64_t plane = (int64_t)(g->n2 + 1) * g->n1;
+  double complex *J = (double complex *)Jd;
+  double dz = g->dz, dr = g->dr, dt = g->dt;
+  int status = 0;
+  for (int64_t p = 0; p < np; ++p) {
+    double ra = hypot(xa[p], ya[p]), rb = hypot(xb[p], yb[p]);
+    double z0 = za[p] / dz, z1 = zb[p] / dz, r0 = ra / dr, r1 = rb / dr;
+    if (fabs(z1 - z0) >= 1.0 || fabs(r1 - r0) >= 1.0 || !(ra < q_rmax(g)) || !(rb < q_rmax(g))) {
+      status = -1;
+      continue;
+    }
+    int64_t b1 = (int64_t)fmin(floor(z0 + 0.5), floor(z1 + 0.5)) - 1;
+    int64_t b2 = (int64_t)fmin(floor(r0 + 0.5), floor(r1 + 0.5)) - 1;
+    double S0z[4], S1z[4], S0r[4], S1r[4];
+    for (int a = 0; a < 4; ++a) {
+      S0z[a] = spline2(z0 - (double)(b1 + a));
+      S1z[a] = spline2(z1 - (double)(b1 + a));
+      S0r[a] = spline2(r0 - (double)(b2 + a));
+      S1r[a] = spline2(r1 - (double)(b2 + a));
+    }
+    double xm = 0.5 * (xa[p] + xb[p]), ym = 0.5 * (ya[p] + yb[p]), rm = hypot(xm, ym);
+    double vth = rm > 0.0 ? (xm * (yb[p] - ya[p]) - ym * (xb[p] - xa[p])) / (rm * dt) : 0.0;
+    for (int m = 0; m < g->nmodes; ++m) {
+      double cm = m == 0 ? 1.0 : 2.0, sm = (m & 1) ? -1.0 : 1.0;
+      double complex P0 = q_phase(xa[p], ya[p], m), P1 = q_phase(xb[p], yb[p], m);
+      double complex Pm = 0.5 * (P0 + P1);
+      double complex *Jz = J + ((int64_t)m * 3 + 0) * plane;
+      double complex *Jr = J + ((int64_t)m * 3 + 1) * plane;
+      double complex *Jt = J + ((int64_t)m * 3 + 2) * plane;
+      double complex q = -cm * qw[p] * Pm; /* charge carried by a unit Esirkepov weight */
+      /* z faces: running sum along z of (S1z - S0z)(S0r + S1r)/2 */
+      for (int b = 0; b < 4; ++b) {
+        int64_t row = b2 + b;
+        double f = 1.0;
+        if (row < 0) { row = -row; f = sm; }
+        double acc = 0.0;
+        for (int a = 0; a < 4; ++a) {
+          acc += (S1z[a] - S0z[a]) * 0.5 * (S0r[b] + S1r[b]);
+          Jz[row * g->n1 + wrapi(b1 + a, g->n1)] += f * q * acc / (q_area(g, row) * dt);
+        }
+      }
+      /* r faces: running sum along r of (S1r - S0r)(S0z + S1z)/2; face j is
+       * at (j + 1/2) dr */
+      for (int a = 0; a < 4; ++a) {
+        double acc = 0.0;
+        for (int b = 0; b < 4; ++b) {
+          acc += (S1r[b] - S0r[b]) * 0.5 * (S0z[a] + S1z[a]);
+          int64_t face = b2 + b;
+          double f = 1.0;
+          if (face < 0) { face = 0; f = -sm; }
+          Jr[face * g->n1 + wrapi(b1 + a, g->n1)] +=
+              f * q * acc / (2.0 * PI * (face + 0.5) * dr * dz * dt);
+        }
+      }
+      /* azimuthal current */
+      for (int b = 0; b < 4; ++b) {
+        int64_t row = b2 + b;
+        int ghost = row < 0;
+        if (ghost) row = -row;
+        for (int a = 0; a < 4; ++a) {
+          int64_t o = row * g->n1 + wrapi(b1 + a, g->n1);
+          if (m == 0 || (m == 1 && row == 0)) {
+            double W3 = S0z[a] * S0r[b] / 3.0 + S1z[a] * S0r[b] / 6.0 + S0z[a] * S1r[b] / 6.0 +
+                        S1z[a] * S1r[b] / 3.0;
+            double f = ghost ? -sm : 1.0;
+            Jt[o] += f * cm * qw[p] * Pm * W3 * vth / (q_area(g, row) * dz);
+          } else if (row > 0) {
+            double Wb = 0.5 * (S0z[a] * S0r[b] + S1z[a] * S1r[b]);
+            double f = ghost ? sm : 1.0;
+            double complex phi = I * cm * qw[p] * Wb * (P1 - P0) / ((double)m * dt);
+            Jt[o] += f * phi / (2.0 * PI * dr * dz);
+          }
+        }
+      }
+    }
+  }
+  return status;
+}
+
+/* rho[nmodes][n2+1][n1] complex += the charge density of the particles */
+int or_rho_q(const or_gridq *g, int64_t np, const double *z, const double *x, const double *y,
+             const double *qw, double *rhod) {
+  int64_t plane = (int64_t)(g->n2 + 1) * g->n1;
+  double complex *rho = (double complex *)rhod;
+  int status = 0;
+  for (int64_t p = 0; p < np; ++p) {
+    double r = hypot(x[p], y[p]);
+    if (!(r < q_rmax(g))) { status = -1; continue; }
+    double zeta = z[p] / g->dz, rr = r / g->dr;
+    int64_t m1 = (int64_t)floor(zeta + 0.5), m2 = (int64_t)floor(rr + 0.5);
+    for (int m = 0; m < g->nmodes; ++m) {
+      double cm = m == 0 ? 1.0 : 2.0, sm = (m & 1) ? -1.0 : 1.0;
+      double complex P = q_phase(x[p], y[p], m);
+      for (int64_t b = m2 - 1; b <= m2 + 1; ++b) {
+        int64_t row = b < 0 ? -b : b;
+        double f = b < 0 ? sm : 1.0;
+        for (int64_t a = m1 - 1; a <= m1 + 1; ++a) {
+          double W = spline2(zeta - (double)a) * spline2(rr - (double)b);
+          rho[(int64_t)m * plane + row * g->n1 + wrapi(a, g->n1)] +=
+              f * cm * qw[p] * P * W / (q_area(g, row) * g->dz);
+        }
+      }
+    }
+  }
+  return status;
+}
+
+/* Co-drifting background current (m = 0, z component, one value per integer
+ * row): minus the z-average of the particles' current, from their momenta
+ * uz/gamma and radial weights, jbg[j] = -sum_p q w v_z S_r / (n1 dz A_j). */
+int or_jbg_q(const or_gridq *g, int64_t np, const double *x, const double *y, const double *uz,
+             const double *ux, const double *uy, const double *qw, double *jbg) {
+  int status = 0;
+  for (int64_t j = 0; j <= g->n2; ++j) jbg[j] = 0.0;
+  for (int64_t p = 0; p < np; ++p) {
+    double r = hypot(x[p], y[p]);
+    if (!(r < q_rmax(g))) { status = -1; continue; }
+    double gam = sqrt(1.0 + uz[p] * uz[p] + ux[p] * ux[p] + uy[p] * uy[p]);
+    double rr = r / g->dr;
+    int64_t m2 = (int64_t)floor(rr + 0.5);
+    for (int64_t b = m2 - 1; b <= m2 + 1; ++b) {
+      int64_t row = b < 0 ? -b : b;
+      jbg[row] -= qw[p] * (uz[p] / gam) * spline2(rr - (double)b) /
+                  ((double)g->n1 * g->dz * q_area(g, row));
+    }
+  }
+  return status;
+}
+
+/* One quasi-3D step: gather, Boris, move, deposit (J: deposited current, jbg
+ * (NULL: none) added to the m = 0 z current of each row), field update, z
+ * wrapped into [0, n1 dz). */
+int or_step_q(const or_gridq *g, double qm, int64_t np, double *z, double *x, double *y,
+              double *uz, double *ux, double *uy, const double *qw, double *E, double *B,
+              double *J, const double *jbg) {
+  int64_t plane = (int64_t)(g->n2 + 1) * g->n1;
+  int64_t n = np > 0 ? np : 1;
+  double *Ep = malloc(sizeof(double) * 3 * n), *Bp = malloc(sizeof(double) * 3 * n);
+  double *zn = malloc(sizeof(double) * n), *xn = malloc(sizeof(double) * n),
+         *yn = malloc(sizeof(double) * n);
+  int status = or_gather_q(g, E, B, np, z, x, y, Ep, Bp);
+  or_boris(np, qm, g->dt, Ep, Bp, uz, ux, uy);
+  for (int64_t p = 0; p < np; ++p) {
+    double gam = sqrt(1.0 + uz[p] * uz[p] + ux[p] * ux[p] + uy[p] * uy[p]);
+    zn[p] = z[p] + g->dt * uz[p] / gam;
+    xn[p] = x[p] + g->dt * ux[p] / gam;
+    yn[p] = y[p] + g->dt * uy[p] / gam;
+  }
+  memset(J, 0, sizeof(double complex) * 3 * plane * g->nmodes);
+  if (or_deposit_q(g, np, z, x, y, zn, xn, yn, qw, J) != 0) status = -1;
+  if (jbg) {
+    double complex *Jz = (double complex *)J;
+    for (int64_t j = 0; j <= g->n2; ++j)
+      for (int64_t i = 0; i < g->n1; ++i) Jz[j * g->n1 + i] += jbg[j];
+  }
+  if (or_field_update_q(g, E, B, J) != 0) status = -1;
+  double L = g->n1 * g->dz;
+  for (int64_t p = 0; p < np; ++p) {
+    z[p] = fmod(zn[p], L);
+    if (z[p] < 0.0) z[p] += L;
+    x[p] = xn[p];
+    y[p] = yn[p];
+  }
+  free(Ep); free(Bp); free(zn); free(xn); free(yn);
+  return status;
+}

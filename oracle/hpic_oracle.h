@@ -176,6 +176,26 @@ int or_field_update_q(const or_gridq *g, double *E, double *B, const double *J);
 int or_yee_update_q(const or_gridq *g, double *E, double *B, const double *J);
 int or_gauss_q(const or_gridq *g, const double *E, const double *rho, double *R);
 
+/* ---- Quasi-3D particles (see the .c file for the mode convention, the
+ * axis mirror rule and the per-mode charge-conserving deposit).  Positions
+ * z, x, y and momenta uz, ux, uy are Cartesian (physical units); fields and
+ * currents are [nmodes][3][n2+1][n1] complex, rho [nmodes][n2+1][n1] complex;
+ * Ep, Bp are Cartesian [3][np] in the order (z, x, y).  Every function
+ * returns -1 if a particle is at r >= (n2 - 3) dr (or, for the deposit, moved
+ * a cell or more), 0 otherwise. */
+int or_gather_q(const or_gridq *g, const double *E, const double *B, int64_t np,
+                const double *z, const double *x, const double *y, double *Ep, double *Bp);
+int or_deposit_q(const or_gridq *g, int64_t np, const double *za, const double *xa,
+                 const double *ya, const double *zb, const double *xb, const double *yb,
+                 const double *qw, double *J);
+int or_rho_q(const or_gridq *g, int64_t np, const double *z, const double *x, const double *y,
+             const double *qw, double *rho);
+int or_jbg_q(const or_gridq *g, int64_t np, const double *x, const double *y, const double *uz,
+             const double *ux, const double *uy, const double *qw, double *jbg);
+int or_step_q(const or_gridq *g, double qm, int64_t np, double *z, double *x, double *y,
+              double *uz, double *ux, double *uy, const double *qw, double *E, double *B,
+              double *J, const double *jbg);
+
 #ifdef __cplusplus
 }
 #endif
