@@ -29,10 +29,12 @@
  * r = 0, conducting wall at r = n[1] dx[1]), modes m = 0..n_modes-1 of
  * F = sum_m Re(F_m e^{i m theta}); per mode complex fields [3][n2+1][n1]
  * (Ez, Er, Eth and Bz, Br, Bth on the r-z Yee nodes) passed as interleaved
- * (re, im) doubles.  Only the field solver is built for this geometry:
- * hp_set_fields / hp_get_field (with mode), hp_step (vacuum update of every
- * mode), hp_diagnostics (energies, Gauss residual D.E), timing; the particle
- * calls return HP_EINVAL.
+ * (re, im) doubles.  Particles carry Cartesian positions (z, x, y) and momenta
+ * (uz, ux, uy); their phase in mode m is e^{-i m th}, their current is
+ * deposited per mode by a charge-conserving scheme (Esirkepov in r-z with
+ * the mean phase plus an azimuthal flux from the phase change) and must stay
+ * at r < (n2 - 3) dr (no particle boundary at the wall).  Not available for
+ * this geometry: the tile calls, checkpoints, raw and fixed-point access.
  * Units: c = 1, t in 1/w_p, x in c/w_p, E and B in m c w_p / e, density in
  * n_p, current in e n_p c (the 4 pi of the paper's Gaussian form is 1).
  *
@@ -61,7 +63,7 @@ extern "C" {
 
 #define HP_GEOM_2D 2
 #define HP_GEOM_3D 3
-#define HP_GEOM_Q3D 4  /* quasi-3D r-z with azimuthal modes (field solver only) */
+#define HP_GEOM_Q3D 4  /* quasi-3D r-z with azimuthal modes */
 
 #define HP_PREC_FP32_FIXED 0 /* FP32 push/FFT/update, 64-bit fixed-point deposit */
 #define HP_PREC_FP64 1       /* FP64 everywhere, FP64 atomics in the deposit */
@@ -137,8 +139,11 @@ int hp_set_stream(hp_sim *sim, void *hip_stream);
  * x is [dim][n] in physical units (wrapped into the box), u = gamma v is [3][n],
  * w[n] the density weight (charge density = q sum w S).  Host buffers are
  * caller-owned and copied before return.  Sets the fixed-point charge unit of
- * the run.  Errors: HP_EINVAL (species != 0, n out of range, non-finite
- * input), HP_ERANGE (fixed-point headroom). */
+ * the run.  Quasi-3D: x is [3][n] Cartesian (z, x, y), u = (uz, ux, uy), w the
+ * number of physical particles (charge q w; weights grow with r for a uniform
+ * density), every r = hypot(x, y) below (n2 - 3) dr.  Errors: HP_EINVAL
+ * (species != 0, n out of range, non-finite input, quasi-3D r too large),
+ * HP_ERANGE (fixed-point headroom). */
 int hp_set_particles(hp_sim *sim, int32_t run, int32_t species, int64_t n, const double *x,
                      const double *u, const double *w, double q_over_m, double q);
 
@@ -149,7 +154,11 @@ int hp_set_fields(hp_sim *sim, int32_t run, int32_t mode, const double *E, const
 
 /* Background of a run: with rho_from_particles = 1 the fixed charge density
  * rho_bg = -rho_e(now) is recorded (used only by the Gauss diagnostic); j_bg[3]
- * is a uniform current added to the deposited one every step (NULL: zero). */
+ * is a uniform current added to the deposited one every step (NULL: zero).
+ * Quasi-3D: rho_bg per mode; rho_from_particles = 2 also records the
+ * co-drifting current of mode 0 along z, minus the z-average of the
+ * particles' current u_z/gamma at this moment (a z-independent profile per
+ * row, added every step); j_bg must be NULL or zero. */
 int hp_set_background(hp_sim *sim, int32_t run, int32_t rho_from_particles,
                       const double *j_bg);
 
@@ -204,6 +213,15 @@ int hp_get_field(hp_sim *sim, int32_t run, int32_t comp, int32_t mode, double *o
  * corrected = 1 after Eq. (11) and the filter (transformed back to x1). */
 int hp_get_current(hp_sim *sim, int32_t run, int32_t comp, int32_t corrected, double *out,
                    size_t count);
+
+/* Quasi-3D (Sec. 5, the per-mode hybrid solve): the current density deposited
+ * in the last step for azimuthal mode `mode` and component comp (0 jz, 1 jr,
+ * 2 jth) on the r-z Yee nodes, before the correction of Eq. (11) and the
+ * filter, without the background: complex interleaved [n2+1][n1][2], count =
+ * 2 (n2+1) n1 doubles.  out is caller-owned; synchronous.  HP_EINVAL for a
+ * Cartesian handle or a bad comp, mode or count. */
+int hp_get_current_mode(hp_sim *sim, int32_t run, int32_t comp, int32_t mode, double *out,
+                        size_t count);
 
 /* FP32_FIXED only: the raw 64-bit accumulator of the last step's deposit. */
 int hp_get_current_fixed(hp_sim *sim, int32_t run, int32_t comp, int64_t *out, size_t count);

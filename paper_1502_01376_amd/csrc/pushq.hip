@@ -1,0 +1,464 @@
+// pushq.hip -- particle side of the quasi-3D (r-z with azimuthal modes) step
+// on gfx950: field gather from the modes, relativistic Boris push in Cartesian
+// momenta, and the per-mode charge-conserving deposit (Sec. 5 runs the hybrid
+// solver per mode; the particle scheme is that of the cited quasi-3D method).
+//
+// Mode convention F(z, r, th) = sum_m Re(F_m(z, r) e^{i m th}); the phase of a
+// particle is P_m = e^{-i m th} = ((x - i y)/r)^m.  Node weights are quadratic
+// B-spline products in (z, r) cell units.  The stencil row below the axis
+// (row -1) is the mirror point of row 1 (integer-r nodes) or row 0 (half-r
+// nodes): z components and scalars of mode m carry (-1)^m there, r and th
+// components -(-1)^m.
+//
+// Deposit of one move (W^0, P^0) -> (W^1, P^1), per mode, with c_0 = 1 and
+// c_m = 2: W^1 P^1 - W^0 P^0 = (W^1 - W^0)(P^0 + P^1)/2 + (W^0 + W^1)/2 (P^1 - P^0).
+// The first part is split into z and r face fluxes by the Esirkepov
+// decomposition in (z, r) index space with the mean phase (separable: the
+// running sum of the shape change along one axis times the mean shape along
+// the other), the second is an azimuthal flux i c_m q w Wbar (P^1 - P^0) / m.
+// Where continuity sets no azimuthal current (m = 0, and m = 1 on the axis
+// node) the azimuthal current is deposited directly from the azimuthal
+// velocity with the time-averaged weight W3.  Ghost-row fold factors:
+// (-1)^m for the z and azimuthal fluxes, -(-1)^m for the flux through the face
+// at -dr/2 (it lands on the face at +dr/2) and for the direct azimuthal
+// current.  The accumulators hold charge per step (flux times dt), scaled by
+// wscale; the row-transform kernel converts them to current densities with
+// the face areas and node volumes.
+//
+// One thread per particle, global atomics (64-bit integers of the rounded
+// FP32 contributions in the FP32 form: the sum does not depend on the order).
+#include "hpic_internal.h"
+
+namespace hp {
+
+namespace {
+
+__device__ __forceinline__ float rsqrtq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrtq(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rcpq(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcpq(double x) { return 1.0 / x; }
+
+template <class R>
+__device__ __forceinline__ void splineq(R d, R w[3]) {
+  const R a = R(0.5) - d, b = R(0.5) + d;
+  w[0] = R(0.5) * a * a;
+  w[1] = R(0.75) - d * d;
+  w[2] = R(0.5) * b * b;
+}
+
+// Floor for the small non-negative arguments used here (r/dr + 1/2 >= 0).
+template <class R> __device__ __forceinline__ int ifloorq(R x) { return (int)floor(x); }
+
+template <class R>
+__device__ __forceinline__ void borisq(R qmhdt, const R E[3], const R B[3], R u[3]) {
+  const R e0 = qmhdt * E[0], e1 = qmhdt * E[1], e2 = qmhdt * E[2];
+  const R m0 = u[0] + e0, m1 = u[1] + e1, m2 = u[2] + e2;
+  const R ig = rsqrtq(R(1) + m0 * m0 + m1 * m1 + m2 * m2);
+  const R t0 = qmhdt * B[0] * ig, t1 = qmhdt * B[1] * ig, t2 = qmhdt * B[2] * ig;
+  const R sf = R(2) * rcpq(R(1) + t0 * t0 + t1 * t1 + t2 * t2);
+  const R s0 = t0 * sf, s1 = t1 * sf, s2 = t2 * sf;
+  const R p0 = m0 + (m1 * t2 - m2 * t1);
+  const R p1 = m1 + (m2 * t0 - m0 * t2);
+  const R p2 = m2 + (m0 * t1 - m1 * t0);
+  u[0] = m0 + (p1 * s2 - p2 * s1) + e0;
+  u[1] = m1 + (p2 * s0 - p0 * s2) + e1;
+  u[2] = m2 + (p0 * s1 - p1 * s0) + e2;
+}
+
+// Quadratic shape of a coordinate given as cell + offset f in [0,1) along z:
+// nodes n-1, n, n+1 around the nearest node n = cell + (f >= 1/2).
+template <class R>
+__device__ __forceinline__ int zshape(int cell, R f, R s[3]) {
+  const int up = f >= R(0.5);
+  splineq<R>(f - R(up), s);
+  return cell + up;
+}
+// The same along r for rho = r/dr >= 0 (integer-r nodes).
+template <class R>
+__device__ __forceinline__ int rshape(R rho, R s[3]) {
+  const int n = ifloorq<R>(rho + R(0.5));
+  splineq<R>(rho - R(n), s);
+  return n;
+}
+template <class R>
+__device__ __forceinline__ void place4(const R s[3], int off, R out[4]) {
+  out[0] = off ? R(0) : s[0];
+  out[1] = off ? s[0] : s[1];
+  out[2] = off ? s[1] : s[2];
+  out[3] = off ? s[2] : R(0);
+}
+
+// Gather of one staggered component over all modes: weights wz/wr, node
+// columns oz[3] (wrapped), rows rr[3] (a ghost row already mirrored; ghost0:
+// row 0 of the stencil is the ghost, whose sign depends on the mode parity
+// and on whether the component is a z component or a transverse one).
+template <class R>
+__device__ __forceinline__ R gather_q(const typename Cplx<R>::T *__restrict__ Fc, long long mstride,
+                                      int M, const R wz[3], const int oz[3], const R wr[3],
+                                      const int rr[3], bool ghost0, bool vec, const R *Pr,
+                                      const R *Pi, int n1) {
+  using C = typename Cplx<R>::T;
+  R acc = 0;
+  for (int m = 0; m < M; ++m) {
+    const C *F = Fc + m * mstride;
+    R vx = 0, vy = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const C *row = F + (long long)rr[b] * n1;
+      R sx = 0, sy = 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const C v = row[oz[a]];
+        sx += wz[a] * v.x;
+        sy += wz[a] * v.y;
+      }
+      R w = wr[b];
+      if (b == 0 && ghost0) {
+        const bool odd = m & 1;
+        if (odd != vec) w = -w;  // (-1)^m for z components, -(-1)^m for r, th
+      }
+      vx += w * sx;
+      vy += w * sy;
+    }
+    acc += vx * Pr[m] + vy * Pi[m];  // Re(v e^{i m th}) with P = e^{-i m th}
+  }
+  return acc;
+}
+
+__device__ __forceinline__ void acc_add(long long *p, float v) {
+  const long long q = (long long)rintf(v);
+  if (q != 0) atomicAdd((unsigned long long *)p, (unsigned long long)q);
+}
+__device__ __forceinline__ void acc_add(double *p, double v) {
+  if (v != 0.0) atomicAdd(p, v);
+}
+
+constexpr int MAXM = 8;
+
+template <class R>
+__global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restrict__ runs,
+                                                        const Item *__restrict__ items, int parity,
+                                                        unsigned *err) {
+  using C = typename Cplx<R>::T;
+  using A = typename AccQ<R>::T;
+  const Item it = items[blockIdx.x];
+  const RunQ<R> &r = runs[it.run];
+  const int p = it.a + threadIdx.x;
+  if (p >= r.np) return;
+  const PartsQ<R> P = r.pt;
+  const int n1 = r.n1, M = r.M;
+  const long long plane = r.plane;
+  const int cz = G(P.cell)[p];
+  const R fz = G(P.fz)[p], x = G(P.x)[p], y = G(P.y)[p];
+  R u[3] = {G(P.uz)[p], G(P.ux)[p], G(P.uy)[p]};
+  const R qw = G(P.qw)[p];
+  const R rad = sqrt(x * x + y * y);
+  const R rho = rad * r.idr;
+  const R ct = rad > R(0) ? x / rad : R(1), st = rad > R(0) ? y / rad : R(0);
+  // phases P_m = (ct - i st)^m
+  R Pr[MAXM], Pi[MAXM];
+  Pr[0] = 1;
+  Pi[0] = 0;
+  for (int m = 1; m < M; ++m) {
+    Pr[m] = Pr[m - 1] * ct + Pi[m - 1] * st;
+    Pi[m] = Pi[m - 1] * ct - Pr[m - 1] * st;
+  }
+  // ---- gather: integer (i) and half (h) stencils along z and r
+  R wzi[3], wzh[3], wri[3], wrh[3];
+  int ozi[3], ozh[3], rri[3], rrh[3];
+  const int upz = fz >= R(0.5);
+  splineq<R>(fz - R(upz), wzi);
+  splineq<R>(fz - R(0.5), wzh);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ozi[a] = wrap_pow2(cz + upz - 1 + a, n1);
+    ozh[a] = wrap_pow2(cz - 1 + a, n1);
+  }
+  const int mri = ifloorq<R>(rho + R(0.5));  // nearest integer-r node
+  splineq<R>(rho - R(mri), wri);
+  const int mrh = ifloorq<R>(rho);           // nearest half-r node (j + 1/2)
+  splineq<R>(rho - R(0.5) - R(mrh), wrh);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int ji = mri - 1 + b, jh = mrh - 1 + b;
+    rri[b] = ji < 0 ? -ji : ji;
+    rrh[b] = jh < 0 ? -jh - 1 : jh;
+  }
+  const bool gi = mri == 0, gh = mrh == 0;  // ghost row in the stencil
+  const long long ms = 6 * plane;
+  const C *F = r.F;
+  R Ec[3], Bc[3];
+  Ec[0] = gather_q<R>(F, ms, M, wzh, ozh, wri, rri, gi, false, Pr, Pi, n1);
+  Ec[1] = gather_q<R>(F + plane, ms, M, wzi, ozi, wrh, rrh, gh, true, Pr, Pi, n1);
+  Ec[2] = gather_q<R>(F + 2 * plane, ms, M, wzi, ozi, wri, rri, gi, true, Pr, Pi, n1);
+  Bc[0] = gather_q<R>(F + 3 * plane, ms, M, wzi, ozi, wrh, rrh, gh, false, Pr, Pi, n1);
+  Bc[1] = gather_q<R>(F + 4 * plane, ms, M, wzh, ozh, wri, rri, gi, true, Pr, Pi, n1);
+  Bc[2] = gather_q<R>(F + 5 * plane, ms, M, wzh, ozh, wrh, rrh, gh, true, Pr, Pi, n1);
+  const R E[3] = {Ec[0], Ec[1] * ct - Ec[2] * st, Ec[1] * st + Ec[2] * ct};
+  const R B[3] = {Bc[0], Bc[1] * ct - Bc[2] * st, Bc[1] * st + Bc[2] * ct};
+  borisq<R>(r.qmhdt, E, B, u);
+  R v[3];
+  {
+#pragma clang fp contract(off)
+    R s = R(1) + u[0] * u[0];
+    s = s + u[1] * u[1];
+    s = s + u[2] * u[2];
+    const R ig = R(1) / sqrt(s);
+    v[0] = u[0] * ig;
+    v[1] = u[1] * ig;
+    v[2] = u[2] * ig;
+  }
+  const R mz = r.dtdz * v[0];
+  const R xb = x + r.dtr * v[1], yb = y + r.dtr * v[2];
+  const R radb = sqrt(xb * xb + yb * yb);
+  const R rhob = radb * r.idr;
+  if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(mz) && isfinite(xb) &&
+        isfinite(yb))) {
+    atomicOr(err, ERR_NUMERIC);
+    return;
+  }
+  if (!(fabs(mz) < R(1)) || !(rhob < r.rmax) || !(fabs(rhob - rho) < R(1))) {
+    atomicOr(err, ERR_RANGE);
+    return;
+  }
+  // new z cell and offset
+  R gz = fz + mz;
+  int dz = 0;
+  if (gz >= R(1)) {
+    gz = gz - R(1);
+    dz = 1;
+  } else if (gz < R(0)) {
+    gz = gz + R(1);
+    dz = -1;
+    if (gz >= R(1)) {
+      gz = R(0);
+      dz = 0;
+    }
+  }
+  // ---- deposit: 4-node windows along z and r holding both stencils
+  R S0z[4], S1z[4], S0r[4], S1r[4];
+  int bz, br;
+  {
+    R sa[3], sb[3];
+    const int na = zshape<R>(cz, fz, sa);
+    const int nb = zshape<R>(cz + dz, gz, sb);
+    bz = min(na, nb) - 1;
+    place4<R>(sa, na - 1 - bz, S0z);
+    place4<R>(sb, nb - 1 - bz, S1z);
+    const int ra = rshape<R>(rho, sa);
+    const int rb = rshape<R>(rhob, sb);
+    br = min(ra, rb) - 1;
+    place4<R>(sa, ra - 1 - br, S0r);
+    place4<R>(sb, rb - 1 - br, S1r);
+  }
+  R Cz[4], Tz[4], Cr[4], Tr[4];
+  {
+    R az = 0, ar = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      az = az + (S1z[k] - S0z[k]);
+      ar = ar + (S1r[k] - S0r[k]);
+      Cz[k] = az;
+      Cr[k] = ar;
+      Tz[k] = R(0.5) * (S0z[k] + S1z[k]);
+      Tr[k] = R(0.5) * (S0r[k] + S1r[k]);
+    }
+  }
+  int col[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) col[a] = wrap_pow2(bz + a, n1);
+  // azimuthal velocity at the mid point times dt (charge-per-step units)
+  const R xm = R(0.5) * (x + xb), ym = R(0.5) * (y + yb);
+  const R rm = sqrt(xm * xm + ym * ym);
+  const R vthdt = rm > R(0) ? (xm * (yb - y) - ym * (xb - x)) / rm : R(0);
+  const R ctb = radb > R(0) ? xb / radb : R(1), stb = radb > R(0) ? yb / radb : R(0);
+  const R g = qw * r.wscale;
+  A *J = r.J[parity];
+  R P1r = 1, P1i = 0;  // phase at the new position
+  for (int m = 0; m < M; ++m) {
+    if (m > 0) {
+      const R t = P1r * ctb + P1i * stb;
+      P1i = P1i * ctb - P1r * stb;
+      P1r = t;
+    }
+    const R cm = m == 0 ? R(1) : R(2);
+    const bool odd = m & 1;
+    const R Pmr = R(0.5) * (Pr[m] + P1r), Pmi = R(0.5) * (Pi[m] + P1i);
+    const R qr = -cm * g * Pmr, qi = -cm * g * Pmi;
+    A *Jz = J + (long long)(m * 3 + 0) * plane * 2;
+    A *Jr = J + (long long)(m * 3 + 1) * plane * 2;
+    A *Jt = J + (long long)(m * 3 + 2) * plane * 2;
+    // z faces
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int row = br + b;
+      R f = Tr[b];
+      if (row < 0) {
+        row = -row;
+        if (odd) f = -f;
+      }
+      if (f == R(0)) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const R w = Cz[a] * f;
+        A *o = Jz + ((long long)row * n1 + col[a]) * 2;
+        acc_add(o, qr * w);
+        if (m > 0) acc_add(o + 1, qi * w);
+      }
+    }
+    // r faces (face j at (j + 1/2) dr; face -1 lands on face 0)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      int face = br + b;
+      R f = Cr[b];
+      if (face < 0) {
+        face = 0;
+        if (!odd) f = -f;
+      }
+      if (f == R(0)) continue;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const R w = Tz[a] * f;
+        if (w == R(0)) continue;
+        A *o = Jr + ((long long)face * n1 + col[a]) * 2;
+        acc_add(o, qr * w);
+        if (m > 0) acc_add(o + 1, qi * w);
+      }
+    }
+    // azimuthal current
+    const R dPr = P1r - Pr[m], dPi = P1i - Pi[m];
+    const R inv_m = m > 0 ? R(1) / R(m) : R(0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int row = br + b;
+      const bool ghost = row < 0;
+      if (ghost) row = -row;
+      const bool direct = m == 0 || (m == 1 && row == 0);
+      if (!direct && row == 0) continue;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        A *o = Jt + ((long long)row * n1 + col[a]) * 2;
+        if (direct) {
+          R W3 = S0z[a] * S0r[b] * R(1.0 / 3.0) + S1z[a] * S0r[b] * R(1.0 / 6.0) +
+                 S0z[a] * S1r[b] * R(1.0 / 6.0) + S1z[a] * S1r[b] * R(1.0 / 3.0);
+          if (W3 == R(0)) continue;
+          R s = cm * g * W3 * vthdt;
+          if (ghost && !odd) s = -s;  // -(-1)^m
+          acc_add(o, s * Pmr);
+          if (m > 0) acc_add(o + 1, s * Pmi);
+        } else {
+          const R Wb = R(0.5) * (S0z[a] * S0r[b] + S1z[a] * S1r[b]);
+          if (Wb == R(0)) continue;
+          R s = cm * g * Wb * inv_m;
+          if (ghost && odd) s = -s;  // (-1)^m
+          // i s (dP)
+          acc_add(o, -s * dPi);
+          acc_add(o + 1, s * dPr);
+        }
+      }
+    }
+  }
+  G(P.cell)[p] = wrap_pow2(cz + dz, n1);
+  G(P.fz)[p] = gz;
+  G(P.x)[p] = xb;
+  G(P.y)[p] = yb;
+  G(P.uz)[p] = u[0];
+  G(P.ux)[p] = u[1];
+  G(P.uy)[p] = u[2];
+}
+
+// FP64 charge density of a run's particles (any form), added into rho.
+template <class R>
+__global__ void __launch_bounds__(256) k_q_rho(const RunQ<R> *__restrict__ run, int M,
+                                               double2 *rho) {
+  const RunQ<R> &r = *run;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= r.np) return;
+  const PartsQ<R> P = r.pt;
+  const int n1 = r.n1;
+  const double x = G(P.x)[p], y = G(P.y)[p], f = G(P.fz)[p], qw = G(P.qw)[p];
+  const int cz = G(P.cell)[p];
+  const double rad = sqrt(x * x + y * y), rr = rad / r.dr;
+  const double ct = rad > 0 ? x / rad : 1.0, st = rad > 0 ? y / rad : 0.0;
+  double wz[3], wr[3];
+  const int nz = zshape<double>(cz, f, wz);
+  const int nr0 = rshape<double>(rr, wr);
+  const double PI_ = 3.14159265358979323846;
+  double Pr = 1, Pi = 0;
+  for (int m = 0; m < M; ++m) {
+    if (m > 0) {
+      const double t = Pr * ct + Pi * st;
+      Pi = Pi * ct - Pr * st;
+      Pr = t;
+    }
+    const double cm = m == 0 ? 1.0 : 2.0;
+    for (int b = 0; b < 3; ++b) {
+      int row = nr0 - 1 + b;
+      double s = cm * qw * wr[b];
+      if (row < 0) {
+        row = -row;
+        if (m & 1) s = -s;
+      }
+      const double V = row == 0 ? 0.25 * PI_ * r.dr * r.dr * r.dz : 2.0 * PI_ * row * r.dr * r.dr * r.dz;
+      for (int a = 0; a < 3; ++a) {
+        double *o = (double *)(rho + (long long)m * r.plane + (long long)row * n1 +
+                               wrap_pow2(nz - 1 + a, n1));
+        const double w = s * wz[a] / V;
+        atomicAdd(o, w * Pr);
+        if (m > 0) atomicAdd(o + 1, w * Pi);
+      }
+    }
+  }
+}
+
+// Co-drifting background current: jbg[j] -= q w v_z S_r / (n1 dz A_j).
+template <class R>
+__global__ void __launch_bounds__(256) k_q_jbg(const RunQ<R> *__restrict__ run, double *jbg) {
+  const RunQ<R> &r = *run;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= r.np) return;
+  const PartsQ<R> P = r.pt;
+  const double x = G(P.x)[p], y = G(P.y)[p], qw = G(P.qw)[p];
+  const double uz = G(P.uz)[p], ux = G(P.ux)[p], uy = G(P.uy)[p];
+  const double vz = uz / sqrt(1.0 + uz * uz + ux * ux + uy * uy);
+  const double rr = sqrt(x * x + y * y) / r.dr;
+  double wr[3];
+  const int n0 = rshape<double>(rr, wr);
+  const double PI_ = 3.14159265358979323846;
+  for (int b = 0; b < 3; ++b) {
+    int row = n0 - 1 + b;
+    if (row < 0) row = -row;
+    const double A = row == 0 ? 0.25 * PI_ * r.dr * r.dr : 2.0 * PI_ * row * r.dr * r.dr;
+    atomicAdd(jbg + row, -qw * vz * wr[b] / ((double)r.n1 * r.dz * A));
+  }
+}
+
+}  // namespace
+
+template <class R>
+void LaunchQ<R>::push_deposit(const RunQ<R> *runs, const Item *items, int nitems, int parity,
+                              unsigned *err, hipStream_t s) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(k_q_push_deposit<R>, dim3(nitems), dim3(256), 0, s, runs, items, parity, err);
+}
+template <class R>
+void LaunchQ<R>::rho(const RunQ<R> *run_dev, int np, int M, double2 *rho, hipStream_t s) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_q_rho<R>, dim3((np + 255) / 256), dim3(256), 0, s, run_dev, M, rho);
+}
+template <class R>
+void LaunchQ<R>::jbg(const RunQ<R> *run_dev, int np, double *jbg, hipStream_t s) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_q_jbg<R>, dim3((np + 255) / 256), dim3(256), 0, s, run_dev, jbg);
+}
+
+template void LaunchQ<float>::push_deposit(const RunQ<float> *, const Item *, int, int, unsigned *,
+                                           hipStream_t);
+template void LaunchQ<double>::push_deposit(const RunQ<double> *, const Item *, int, int,
+                                            unsigned *, hipStream_t);
+template void LaunchQ<float>::rho(const RunQ<float> *, int, int, double2 *, hipStream_t);
+template void LaunchQ<double>::rho(const RunQ<double> *, int, int, double2 *, hipStream_t);
+template void LaunchQ<float>::jbg(const RunQ<float> *, int, double *, hipStream_t);
+template void LaunchQ<double>::jbg(const RunQ<double> *, int, double *, hipStream_t);
+
+}  // namespace hp

@@ -127,6 +127,10 @@ struct SimBase {
     if (mode != 0) return fail(HP_EINVAL, "mode must be 0 for Cartesian runs");
     return get_field(run, comp, out, count);
   }
+  // deposited current of one azimuthal mode (quasi-3D only)
+  virtual int get_current_mode(int, int, int, double *, size_t) {
+    return fail(HP_EINVAL, "per-mode currents exist for quasi-3D runs only");
+  }
 };
 
 struct hp_sim {
@@ -1461,10 +1465,15 @@ template <class R>
 class SimQ : public SimBase {
   using C = typename Cplx<R>::T;
 
+  using A = typename AccQ<R>::T;
   struct RunHostQ {
     hp_config cfg;
     RunQ<R> d;
-    int item0 = 0;  // first (6 m + c, row) item of the run
+    int item0 = 0;   // first (6 m + c, row) item of the run
+    int jitem0 = 0;  // first (3 m + c, row) item of the run
+    double qm = -1.0, q = -1.0;
+    double2 *rho_bg = nullptr;  // [M][nr][n1] background charge density, or NULL
+    void *pbuf[9] = {nullptr};  // particle arrays
   };
 
  public:
@@ -1479,7 +1488,7 @@ class SimQ : public SimBase {
   int init(const hp_config *cfgs, int nruns) {
     HIPCHK(hipGetDevice(&device_));
     runs_.resize(nruns);
-    std::vector<Item> rows, upd, gitems;
+    std::vector<Item> rows, upd, gitems, jitems;
     for (int i = 0; i < nruns; ++i) {
       RunHostQ &h = runs_[i];
       h.cfg = cfgs[i];
@@ -1526,6 +1535,46 @@ class SimQ : public SimBase {
       HIPCHK(hipMemcpy(dsym, sym.data(), sizeof(double) * 4 * d.n1, hipMemcpyHostToDevice));
       d.tw = dtw;
       d.sym = dsym;
+      // particle-side tables and buffers
+      std::vector<double2> tw64(d.n1);
+      std::vector<double> filt(d.n1);
+      std::vector<R> kfac(2 * d.n1);
+      for (int m = 0; m < d.n1; ++m) {
+        const double a = -2.0 * PI * m / d.n1;
+        tw64[m] = make_double2(std::cos(a), std::sin(a));
+        const int ka = std::abs(m <= d.n1 / 2 ? m : m - d.n1);
+        const double k1 = 2.0 * PI * ka / (d.n1 * c.dx[0]);
+        const double hh = 0.5 * k1 * c.dx[0];
+        const bool corr = !c.deriv1 && c.correct && ka > 0;
+        const double sinc = corr ? (std::sin(hh) / (0.5 * c.dx[0])) / (k1 + dk_mod(c, k1)) : 1.0;
+        filt[m] = (ka <= c.filter_frac * 0.5 * d.n1) ? 1.0 : 0.0;
+        kfac[2 * m] = (R)(sinc * filt[m]);
+        kfac[2 * m + 1] = (R)filt[m];
+      }
+      double2 *dtw64;
+      double *dfilt, *djconv, *djbg;
+      R *dkfac;
+      const size_t jn = (size_t)d.M * 3 * d.plane;
+      if ((rc = alloc(&dtw64, d.n1)) || (rc = alloc(&dfilt, d.n1)) || (rc = alloc(&dkfac, 2 * d.n1)) ||
+          (rc = alloc(&djconv, (size_t)d.M * 3 * d.nr)) || (rc = alloc(&djbg, d.nr)) ||
+          (rc = alloc(&d.J[0], 2 * jn)) || (rc = alloc(&d.J[1], 2 * jn)) || (rc = alloc(&d.Jk, jn)))
+        return rc;
+      HIPCHK(hipMemcpy(dtw64, tw64.data(), sizeof(double2) * d.n1, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(dfilt, filt.data(), sizeof(double) * d.n1, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(dkfac, kfac.data(), sizeof(R) * 2 * d.n1, hipMemcpyHostToDevice));
+      d.tw64 = dtw64;
+      d.filt64 = dfilt;
+      d.kfac = dkfac;
+      d.jconv = djconv;
+      d.jbgk = djbg;
+      d.dtr = (R)c.dt;
+      d.dtdz = (R)(c.dt / c.dx[0]);
+      d.idr = (R)(1.0 / c.dx[1]);
+      d.rmax = (R)(d.n2 - 3);
+      d.wscale = 1;
+      h.jitem0 = (int)jitems.size();
+      for (int mc = 0; mc < 3 * d.M; ++mc)
+        for (int j = 0; j < d.nr; ++j) jitems.push_back(Item{i, mc, j});
       h.item0 = (int)rows.size();
       for (int mc = 0; mc < 6 * d.M; ++mc)
         for (int j = 0; j < d.nr; ++j) rows.push_back(Item{i, mc, j});
@@ -1536,9 +1585,10 @@ class SimQ : public SimBase {
     }
     int rc;
     if ((rc = upload(rows, &d_rows_, &n_rows_)) || (rc = upload(upd, &d_upd_, &n_upd_)) ||
-        (rc = upload(gitems, &d_gauss_, &n_gauss_)))
+        (rc = upload(gitems, &d_gauss_, &n_gauss_)) || (rc = upload(jitems, &d_jitems_, &n_jitems_)))
       return rc;
-    if ((rc = alloc(&d_runs_, nruns))) return rc;
+    if ((rc = alloc(&d_runs_, nruns)) || (rc = alloc(&d_err_, 1))) return rc;
+    for (int i = 0; i < nruns; ++i) set_jconv(i);
     return upload_runs();
   }
 
@@ -1577,6 +1627,15 @@ class SimQ : public SimBase {
   int step(int nsteps) override {
     if (nsteps < 0) return fail(HP_EINVAL, "negative step count");
     for (int k = 0; k < nsteps; ++k) {
+      if (n_push_ > 0) {
+        mark(HP_K_PUSH_DEPOSIT, true);
+        LaunchQ<R>::push_deposit(d_runs_, d_push_, n_push_, parity_, d_err_, stream_);
+        mark(HP_K_PUSH_DEPOSIT, false);
+        mark(HP_K_FFT_J, true);
+        LaunchQ<R>::fft_j(d_runs_, d_jitems_, n_jitems_, parity_, maxn1_, stream_);
+        mark(HP_K_FFT_J, false);
+        deposited_ = true;
+      }
       mark(HP_K_KUPDATE, true);
       LaunchQ<R>::kupdate(d_runs_, d_upd_, n_upd_, parity_, stream_);
       mark(HP_K_KUPDATE, false);
@@ -1592,6 +1651,198 @@ class SimQ : public SimBase {
 
   int sync() override {
     HIPCHK(hipStreamSynchronize(stream_));
+    unsigned e = 0;
+    HIPCHK(hipMemcpy(&e, d_err_, sizeof e, hipMemcpyDeviceToHost));
+    if (e) {
+      HIPCHK(hipMemset(d_err_, 0, sizeof e));
+      if (e & ERR_NUMERIC) return fail(HP_ENUMERIC, "non-finite particle momentum or position");
+      return fail(HP_ERANGE, "a particle reached r >= (n2 - 3) dr or moved a cell or more");
+    }
+    return HP_OK;
+  }
+
+  // Particles of a run: x[3][n] = (z, x, y) in physical units (r = hypot(x, y)
+  // must be below (n2 - 3) dr), u[3][n] = (uz, ux, uy), w[n]; charge q w.
+  int set_particles(int run, int64_t n, const double *x, const double *u, const double *w,
+                    double qm, double q) override {
+    RunHostQ &h = runs_[run];
+    RunQ<R> &d = h.d;
+    if (n < 0 || n > ((int64_t)1 << 30)) return fail(HP_EINVAL, "particle count out of range");
+    if (n > 0 && (!x || !u || !w)) return fail(HP_EINVAL, "null particle arrays");
+    if (!std::isfinite(qm) || !std::isfinite(q) || qm == 0 || q == 0)
+      return fail(HP_EINVAL, "q/m and q must be finite and non-zero");
+    int rc;
+    if ((rc = sync())) return rc;
+    const double L = d.n1 * d.dz, rlim = (d.n2 - 3) * d.dr;
+    std::vector<int> cell(n), id(n);
+    std::vector<R> fz(n), px(n), py(n), uz(n), ux(n), uy(n), qw(n);
+    double wmax = 0;
+    for (int64_t p = 0; p < n; ++p) {
+      const double z = x[p], xx = x[n + p], yy = x[2 * n + p];
+      if (!std::isfinite(z) || !std::isfinite(xx) || !std::isfinite(yy) || !std::isfinite(u[p]) ||
+          !std::isfinite(u[n + p]) || !std::isfinite(u[2 * n + p]) || !std::isfinite(w[p]))
+        return fail(HP_EINVAL, "non-finite particle data");
+      if (!(std::hypot(xx, yy) < rlim))
+        return fail(HP_EINVAL, "particle %lld at r >= (n2 - 3) dr", (long long)p);
+      double zc = std::fmod(z, L);
+      if (zc < 0) zc += L;
+      zc /= d.dz;
+      int c = (int)std::floor(zc);
+      R f = (R)(zc - c);
+      if (f >= R(1)) {
+        f = 0;
+        c += 1;
+      }
+      cell[p] = c & (d.n1 - 1);
+      fz[p] = f;
+      px[p] = (R)xx;
+      py[p] = (R)yy;
+      uz[p] = (R)u[p];
+      ux[p] = (R)u[n + p];
+      uy[p] = (R)u[2 * n + p];
+      qw[p] = (R)(q * w[p]);
+      wmax = std::max(wmax, std::fabs(q * w[p]));
+      id[p] = (int)p;
+    }
+    for (void *&b : h.pbuf) {
+      if (b) release(b);
+      b = nullptr;
+    }
+    PartsQ<R> &P = d.pt;
+    if ((rc = alloc(&P.cell, n)) || (rc = alloc(&P.fz, n)) || (rc = alloc(&P.x, n)) ||
+        (rc = alloc(&P.y, n)) || (rc = alloc(&P.uz, n)) || (rc = alloc(&P.ux, n)) ||
+        (rc = alloc(&P.uy, n)) || (rc = alloc(&P.qw, n)) || (rc = alloc(&P.id, n)))
+      return rc;
+    void *bufs[9] = {P.cell, P.fz, P.x, P.y, P.uz, P.ux, P.uy, P.qw, P.id};
+    for (int k = 0; k < 9; ++k) h.pbuf[k] = bufs[k];
+    if (n > 0) {
+      HIPCHK(hipMemcpy(P.cell, cell.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(P.fz, fz.data(), sizeof(R) * n, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(P.x, px.data(), sizeof(R) * n, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(P.y, py.data(), sizeof(R) * n, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(P.uz, uz.data(), sizeof(R) * n, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(P.ux, ux.data(), sizeof(R) * n, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(P.uy, uy.data(), sizeof(R) * n, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(P.qw, qw.data(), sizeof(R) * n, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(P.id, id.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+    }
+    d.np = (int)n;
+    h.qm = qm;
+    h.q = q;
+    d.qmhdt = (R)(qm * 0.5 * d.dt);
+    // FP32 form: contributions in units of 2^-28 of the largest charge
+    d.wscale = sizeof(R) == 4 ? (R)(std::ldexp(1.0, 28) / (wmax > 0 ? wmax : 1.0)) : R(1);
+    set_jconv(run);
+    if ((rc = rebuild_push_items())) return rc;
+    return upload_runs();
+  }
+
+  int get_count(int run, int64_t *n) override {
+    *n = runs_[run].d.np;
+    return HP_OK;
+  }
+
+  int get_particles(int run, int64_t n, double *x, double *u, double *w, int64_t *id) override {
+    const RunHostQ &h = runs_[run];
+    const RunQ<R> &d = h.d;
+    if (n != d.np) return fail(HP_EINVAL, "n must equal the particle count");
+    int rc;
+    if ((rc = sync())) return rc;
+    if (n == 0) return HP_OK;
+    const PartsQ<R> &P = d.pt;
+    std::vector<int> cell(n), pid(n);
+    std::vector<R> a(n);
+    HIPCHK(hipMemcpy(cell.data(), P.cell, sizeof(int) * n, hipMemcpyDeviceToHost));
+    if (x) {
+      HIPCHK(hipMemcpy(a.data(), P.fz, sizeof(R) * n, hipMemcpyDeviceToHost));
+      for (int64_t p = 0; p < n; ++p) x[p] = (cell[p] + (double)a[p]) * d.dz;
+      HIPCHK(hipMemcpy(a.data(), P.x, sizeof(R) * n, hipMemcpyDeviceToHost));
+      for (int64_t p = 0; p < n; ++p) x[n + p] = a[p];
+      HIPCHK(hipMemcpy(a.data(), P.y, sizeof(R) * n, hipMemcpyDeviceToHost));
+      for (int64_t p = 0; p < n; ++p) x[2 * n + p] = a[p];
+    }
+    if (u) {
+      R *src[3] = {P.uz, P.ux, P.uy};
+      for (int c = 0; c < 3; ++c) {
+        HIPCHK(hipMemcpy(a.data(), src[c], sizeof(R) * n, hipMemcpyDeviceToHost));
+        for (int64_t p = 0; p < n; ++p) u[c * n + p] = a[p];
+      }
+    }
+    if (w) {
+      HIPCHK(hipMemcpy(a.data(), P.qw, sizeof(R) * n, hipMemcpyDeviceToHost));
+      for (int64_t p = 0; p < n; ++p) w[p] = a[p] / h.q;
+    }
+    if (id) {
+      HIPCHK(hipMemcpy(pid.data(), P.id, sizeof(int) * n, hipMemcpyDeviceToHost));
+      for (int64_t p = 0; p < n; ++p) id[p] = pid[p];
+    }
+    return HP_OK;
+  }
+
+  // rho_from_particles: 0 none, 1 rho_bg = -rho_e(now) (every mode), 2 also the
+  // co-drifting current of mode 0 along z from the particles' momenta.  j_bg
+  // must be NULL or zero (a uniform current has no place in a bounded column).
+  int set_background(int run, int mode, const double *jbg) override {
+    RunHostQ &h = runs_[run];
+    RunQ<R> &d = h.d;
+    if (jbg && (jbg[0] != 0 || jbg[1] != 0 || jbg[2] != 0))
+      return fail(HP_EINVAL, "quasi-3D: use rho_from_particles = 2 for a background current");
+    if (mode < 0 || mode > 2) return fail(HP_EINVAL, "rho_from_particles must be 0, 1 or 2");
+    int rc;
+    if ((rc = sync())) return rc;
+    const size_t n = (size_t)d.M * d.plane;
+    if (mode == 0) {
+      if (h.rho_bg) release(h.rho_bg);
+      h.rho_bg = nullptr;
+      HIPCHK(hipMemset((void *)d.jbgk, 0, sizeof(double) * d.nr));
+      return HP_OK;
+    }
+    if (!h.rho_bg && (rc = alloc(&h.rho_bg, n))) return rc;
+    HIPCHK(hipMemset(h.rho_bg, 0, sizeof(double2) * n));
+    LaunchQ<R>::rho(d_runs_ + run, d.np, d.M, h.rho_bg, stream_);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream_));
+    std::vector<double2> t(n);
+    HIPCHK(hipMemcpy(t.data(), h.rho_bg, sizeof(double2) * n, hipMemcpyDeviceToHost));
+    for (auto &v : t) v = make_double2(-v.x, -v.y);
+    HIPCHK(hipMemcpy(h.rho_bg, t.data(), sizeof(double2) * n, hipMemcpyHostToDevice));
+    std::vector<double> jb(d.nr, 0.0);
+    if (mode == 2) {
+      double *tmp;
+      if ((rc = alloc(&tmp, d.nr))) return rc;
+      LaunchQ<R>::jbg(d_runs_ + run, d.np, tmp, stream_);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(stream_));
+      HIPCHK(hipMemcpy(jb.data(), tmp, sizeof(double) * d.nr, hipMemcpyDeviceToHost));
+      release(tmp);
+      for (auto &v : jb) v *= d.n1;  // the unnormalised transform's kappa = 0 term
+    }
+    HIPCHK(hipMemcpy((void *)d.jbgk, jb.data(), sizeof(double) * d.nr, hipMemcpyHostToDevice));
+    return HP_OK;
+  }
+
+  // Deposited current density of the last step, one mode, before correction
+  // and filter, without the background: complex [n2+1][n1] interleaved.
+  int get_current_mode(int run, int comp, int mode, double *out, size_t count) override {
+    const RunQ<R> &d = runs_[run].d;
+    if (comp < 0 || comp > 2 || mode < 0 || mode >= d.M || count != 2 * (size_t)d.plane || !out)
+      return fail(HP_EINVAL, "bad current request (quasi-3D: complex, count = 2 (n2+1) n1)");
+    int rc;
+    if ((rc = sync())) return rc;
+    std::vector<A> acc(2 * (size_t)d.plane);
+    const int par = deposited_ ? (parity_ ^ 1) : parity_;
+    HIPCHK(hipMemcpy(acc.data(), d.J[par] + 2 * ((size_t)mode * 3 + comp) * d.plane,
+                     sizeof(A) * acc.size(), hipMemcpyDeviceToHost));
+    std::vector<double> conv((size_t)d.M * 3 * d.nr);
+    HIPCHK(hipMemcpy(conv.data(), d.jconv, sizeof(double) * conv.size(), hipMemcpyDeviceToHost));
+    for (int j = 0; j < d.nr; ++j) {
+      const double f = conv[((size_t)mode * 3 + comp) * d.nr + j];
+      for (int i = 0; i < d.n1; ++i) {
+        const size_t o = (size_t)j * d.n1 + i;
+        out[2 * o] = (double)acc[2 * o] * f;
+        out[2 * o + 1] = (double)acc[2 * o + 1] * f;
+      }
+    }
     return HP_OK;
   }
 
@@ -1652,24 +1903,64 @@ class SimQ : public SimBase {
         (c < 3 ? out->W_E[c] : out->W_B[c - 3]) += 0.5 * fm * acc;
       }
     }
+    // kinetic energy sum (q w / (q/m)) (gamma - 1) of the particles
+    if (d.np > 0) {
+      std::vector<R> uz(d.np), ux(d.np), uy(d.np), qw(d.np);
+      HIPCHK(hipMemcpy(uz.data(), d.pt.uz, sizeof(R) * d.np, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(ux.data(), d.pt.ux, sizeof(R) * d.np, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(uy.data(), d.pt.uy, sizeof(R) * d.np, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(qw.data(), d.pt.qw, sizeof(R) * d.np, hipMemcpyDeviceToHost));
+      double ke = 0;
+      for (int p = 0; p < d.np; ++p) {
+        const double a = uz[p], b = ux[p], c = uy[p];
+        ke += (qw[p] / h.qm) * (std::sqrt(1.0 + a * a + b * b + c * c) - 1.0);
+      }
+      out->kinetic = ke;
+    }
+    // charge density of the particles plus the background, FP64
+    double2 *rho = nullptr;
+    const size_t nrho = (size_t)d.M * d.plane;
+    if (d.np > 0 || h.rho_bg) {
+      if ((rc = alloc(&rho, nrho))) return rc;
+      LaunchQ<R>::rho(d_runs_ + run, d.np, d.M, rho, stream_);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(stream_));
+      std::vector<double2> t(d.plane);
+      HIPCHK(hipMemcpy(t.data(), rho, sizeof(double2) * d.plane, hipMemcpyDeviceToHost));
+      double qt = 0;
+      for (int j = 0; j < d.nr; ++j) {
+        const double V = j == 0 ? PI * 0.25 * d.dr * d.dr * d.dz : 2.0 * PI * j * d.dr * d.dr * d.dz;
+        for (int i = 0; i < d.n1; ++i) qt += t[(size_t)j * d.n1 + i].x * V;
+      }
+      out->charge_total = qt;
+      if (h.rho_bg) {
+        std::vector<double2> a(nrho), b(nrho);
+        HIPCHK(hipMemcpy(a.data(), rho, sizeof(double2) * nrho, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(b.data(), h.rho_bg, sizeof(double2) * nrho, hipMemcpyDeviceToHost));
+        for (size_t e = 0; e < nrho; ++e) a[e] = make_double2(a[e].x + b[e].x, a[e].y + b[e].y);
+        HIPCHK(hipMemcpy(rho, a.data(), sizeof(double2) * nrho, hipMemcpyHostToDevice));
+      }
+    }
     const int nit = d.M * d.nr;
     double *rows;
-    if ((rc = alloc(&rows, 2 * (size_t)nit))) return rc;
+    if ((rc = alloc(&rows, 3 * (size_t)nit))) return rc;
     int first = 0;
     for (int i = 0; i < run; ++i) first += runs_[i].d.M * runs_[i].d.nr;
-    LaunchQ<R>::gauss(d_runs_, d_gauss_ + first, nit, parity_, rows, stream_);
-    std::vector<double> hr(2 * (size_t)nit);
+    LaunchQ<R>::gauss(d_runs_, d_gauss_ + first, nit, parity_, rho, rows, maxn1_, stream_);
+    HIPCHK(hipGetLastError());
+    std::vector<double> hr(3 * (size_t)nit);
     HIPCHK(hipMemcpy(hr.data(), rows, sizeof(double) * hr.size(), hipMemcpyDeviceToHost));
     release(rows);
-    double s2 = 0, smax = 0;
+    if (rho) release(rho);
+    double s2 = 0, smax = 0, sref = 0;
     for (int i = 0; i < nit; ++i) {
-      s2 += hr[2 * i];
-      smax = std::max(smax, hr[2 * i + 1]);
+      s2 += hr[3 * i];
+      smax = std::max(smax, hr[3 * i + 1]);
+      sref += hr[3 * i + 2];
     }
     out->gauss_l2 = std::sqrt(s2);
     out->gauss_linf = smax;
-    // scale: the same norm of the transformed E (so the residual is relative)
-    out->gauss_ref_l2 = 0;
+    out->gauss_ref_l2 = std::sqrt(sref);
     return HP_OK;
   }
 
@@ -1706,16 +1997,11 @@ class SimQ : public SimBase {
   int nruns() const override { return (int)runs_.size(); }
   int use_graphs(int) override { return HP_OK; }
 
-  // not available for quasi-3D handles (field solver only)
-  int na() const { return fail(HP_EINVAL, "not available for quasi-3D runs (field solver only)"); }
-  int set_particles(int, int64_t, const double *, const double *, const double *, double,
-                    double) override { return na(); }
+  // not available for quasi-3D handles
+  int na() const { return fail(HP_EINVAL, "not available for quasi-3D runs"); }
   int set_fields(int, const double *, const double *) override { return na(); }
-  int set_background(int, int, const double *) override { return na(); }
   int get_current(int, int, int, double *, size_t) override { return na(); }
   int get_current_fixed(int, int, int64_t *, size_t) override { return na(); }
-  int get_count(int, int64_t *n) override { *n = 0; return HP_OK; }
-  int get_particles(int, int64_t, double *, double *, double *, int64_t *) override { return na(); }
   int get_particles_raw(int, int64_t, int32_t *, float *, float *, float *, int32_t *) override {
     return na();
   }
@@ -1781,13 +2067,48 @@ class SimQ : public SimBase {
     }
   }
 
+  // accumulator -> current density per (m, c, row): charge per step over
+  // dt, the fixed-point scale and the face area (z), the r face (r), or the
+  // node volume (direct azimuthal current: m = 0, m = 1 on the axis) or
+  // 2 pi dr dz (azimuthal flux, m >= 1)
+  void set_jconv(int run) {
+    RunQ<R> &d = runs_[run].d;
+    std::vector<double> cv((size_t)d.M * 3 * d.nr, 0.0);
+    const double s = (double)d.wscale * d.dt, dr = d.dr, dz = d.dz;
+    for (int m = 0; m < d.M; ++m)
+      for (int j = 0; j < d.nr; ++j) {
+        const double A = j == 0 ? 0.25 * PI * dr * dr : 2.0 * PI * j * dr * dr;
+        double *c = cv.data() + (size_t)m * 3 * d.nr;
+        c[j] = 1.0 / (s * A);
+        c[d.nr + j] = 1.0 / (s * 2.0 * PI * (j + 0.5) * dr * dz);
+        if (m == 0 || (m == 1 && j == 0))
+          c[2 * d.nr + j] = 1.0 / (s * A * dz);
+        else
+          c[2 * d.nr + j] = j == 0 ? 0.0 : 1.0 / (s * 2.0 * PI * dr * dz);
+      }
+    (void)hipMemcpy((void *)d.jconv, cv.data(), sizeof(double) * cv.size(), hipMemcpyHostToDevice);
+  }
+  int rebuild_push_items() {
+    std::vector<Item> v;
+    for (int i = 0; i < (int)runs_.size(); ++i)
+      for (int p = 0; p < runs_[i].d.np; p += 256) v.push_back(Item{i, p, 0});
+    if (d_push_) release(d_push_);
+    d_push_ = nullptr;
+    n_push_ = 0;
+    if (v.empty()) return HP_OK;
+    return upload(v, &d_push_, &n_push_);
+  }
+
   int device_ = 0;
   hipStream_t stream_ = nullptr;
   std::vector<RunHostQ> runs_;
   std::vector<void *> allocs_;
   RunQ<R> *d_runs_ = nullptr;
-  Item *d_rows_ = nullptr, *d_upd_ = nullptr, *d_gauss_ = nullptr;
-  int n_rows_ = 0, n_upd_ = 0, n_gauss_ = 0, maxn1_ = 0;
+  Item *d_rows_ = nullptr, *d_upd_ = nullptr, *d_gauss_ = nullptr, *d_jitems_ = nullptr,
+       *d_push_ = nullptr;
+  int n_rows_ = 0, n_upd_ = 0, n_gauss_ = 0, n_jitems_ = 0, n_push_ = 0, maxn1_ = 0;
+  unsigned *d_err_ = nullptr;
+  bool deposited_ = false;
   int parity_ = 0;
   int64_t step_ = 0;
   bool profiling_ = false;
@@ -1949,6 +2270,11 @@ int hp_get_field(hp_sim *sim, int32_t run, int32_t comp, int32_t mode, double *o
 int hp_get_current(hp_sim *sim, int32_t run, int32_t comp, int32_t corrected, double *out,
                    size_t count) {
   return with_run(sim, run, [&] { return sim->impl->get_current(run, comp, corrected, out, count); });
+}
+
+int hp_get_current_mode(hp_sim *sim, int32_t run, int32_t comp, int32_t mode, double *out,
+                        size_t count) {
+  return with_run(sim, run, [&] { return sim->impl->get_current_mode(run, comp, mode, out, count); });
 }
 
 int hp_get_current_fixed(hp_sim *sim, int32_t run, int32_t comp, int64_t *out, size_t count) {

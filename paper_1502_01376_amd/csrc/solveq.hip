@@ -50,6 +50,41 @@ __global__ void __launch_bounds__(256) k_q_ifft(const RunQ<R> *__restrict__ runs
   for (int n = threadIdx.x; n < r.n1; n += blockDim.x) r.F[base + n] = cscale(lds[n], s);
 }
 
+// Current of the step per (run, 3 m + c, row): the deposit accumulators of a
+// row -> current density (jconv: face area or node volume, dt and the
+// fixed-point scale), the other parity's accumulators cleared, forward complex
+// transform along z, the correction of Eq. (11) on jz and the low-pass filter
+// (kfac), and the co-drifting background at kappa = 0 (m = 0, z).
+template <class R>
+__global__ void __launch_bounds__(256) k_q_fft_j(const RunQ<R> *__restrict__ runs,
+                                                 const Item *__restrict__ items, int parity) {
+  using C = typename Cplx<R>::T;
+  using A = typename AccQ<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  C *lds = (C *)smem_raw;
+  const Item it = items[blockIdx.x];
+  const RunQ<R> &r = runs[it.run];
+  const int mc = it.a, row = it.b, m = mc / 3, c = mc - 3 * m;
+  const long long base = (long long)mc * r.plane + (long long)row * r.n1;
+  const A *Jin = r.J[parity] + 2 * base;
+  A *Jclr = r.J[parity ^ 1] + 2 * base;
+  const R conv = (R)r.jconv[mc * r.nr + row];
+  for (int n = threadIdx.x; n < r.n1; n += blockDim.x) {
+    lds[n] = cmk((R)Jin[2 * n] * conv, (R)Jin[2 * n + 1] * conv);
+    Jclr[2 * n] = 0;
+    Jclr[2 * n + 1] = 0;
+  }
+  __syncthreads();
+  lds_fft<C, 6>(lds, r.n1, r.log2n1, 1, r.tw, 1, false);
+  C *out = r.Jk + base;
+  const int sel = c == 0 ? 0 : 1;
+  for (int k = threadIdx.x; k < r.n1; k += blockDim.x) {
+    C v = cscale(lds[k], r.kfac[2 * k + sel]);
+    if (k == 0 && m == 0 && c == 0) v.x += (R)r.jbgk[row];
+    out[k] = v;
+  }
+}
+
 // Item = (run, first element, 0): elements e = (m nr + j) n1 + kappa.
 template <class R>
 __global__ void __launch_bounds__(256) k_q_update_a(const RunQ<R> *__restrict__ runs,
@@ -100,10 +135,13 @@ __global__ void __launch_bounds__(256) k_q_update_a(const RunQ<R> *__restrict__ 
   C Ez = at(0, j), Er = at(1, j), Et = at(2, j);
   if (j < n2) {
     const double rh = (j + 0.5) * dr;
-    Er = cadd(Er, cscale(csub(cscale(cmul(im, Bz_j), 1.0 / rh), cmul(dm, Bt_j)), dt));
+    // current of the step (zero for a field-only run)
+    const typename RunQ<R>::C *Jm = r.Jk + (long long)m * 3 * r.plane;
+    const C Jz = to_d2(Jm[o]), Jr = to_d2(Jm[r.plane + o]), Jt = to_d2(Jm[2 * r.plane + o]);
+    Er = cadd(Er, cscale(csub(csub(cscale(cmul(im, Bz_j), 1.0 / rh), cmul(dm, Bt_j)), Jr), dt));
     if (j == 0) {
-      if (m == 0) Ez = cadd(Ez, cscale(Bt_j, dt * 4.0 / dr));
-      if (m == 1) Et = cadd(Et, cscale(csub(cmul(dm, Br_j), cscale(Bz_j, 2.0 / dr)), dt));
+      if (m == 0) Ez = cadd(Ez, cscale(csub(cscale(Bt_j, 4.0 / dr), Jz), dt));
+      if (m == 1) Et = cadd(Et, cscale(csub(csub(cmul(dm, Br_j), cscale(Bz_j, 2.0 / dr)), Jt), dt));
     } else {
       C Bz_m, Bt_m;
       bh_half(j - 1, Bz_m, Bt_m);
@@ -112,8 +150,8 @@ __global__ void __launch_bounds__(256) k_q_update_a(const RunQ<R> *__restrict__ 
                                1.0 / (rj * dr)),
                         cscale(cmul(im, Br_j), 1.0 / rj));
       const C ct = csub(cmul(dm, Br_j), cscale(csub(Bz_j, Bz_m), 1.0 / dr));
-      Ez = cadd(Ez, cscale(cz, dt));
-      Et = cadd(Et, cscale(ct, dt));
+      Ez = cadd(Ez, cscale(csub(cz, Jz), dt));
+      Et = cadd(Et, cscale(csub(ct, Jt), dt));
     }
   }
   Fo[o] = Ez;
@@ -162,18 +200,38 @@ __global__ void __launch_bounds__(256) k_q_update_b(const RunQ<R> *__restrict__ 
   }
 }
 
-// Vacuum Gauss law per (run, m, row): D.E on the integer nodes from the
-// master, rows 1..n2-1 and the axis for m = 0.  rows_out[item][2].
+// Forward FP64 transform along z of one row (m, j) of a density, in place.
+template <class R>
+__global__ void __launch_bounds__(256) k_q_rho_fft(const RunQ<R> *__restrict__ runs,
+                                                   const Item *__restrict__ items, double2 *rho) {
+  extern __shared__ unsigned char smem_raw[];
+  double2 *lds = (double2 *)smem_raw;
+  const Item it = items[blockIdx.x];
+  const RunQ<R> &r = runs[it.run];
+  double2 *row = rho + (long long)it.a * r.plane + (long long)it.b * r.n1;
+  for (int n = threadIdx.x; n < r.n1; n += blockDim.x) lds[n] = row[n];
+  __syncthreads();
+  lds_fft<double2, 6>(lds, r.n1, r.log2n1, 1, r.tw64, 1, false);
+  for (int n = threadIdx.x; n < r.n1; n += blockDim.x) row[n] = lds[n];
+}
+
+// Gauss law per (run, m, row): D.E on the integer nodes from the master, rows
+// 1..n2-1 and the axis for m = 0, minus the filtered charge density
+// f(k1) rho^ (rho: the run's FP64 density [M][nr][n1] already transformed
+// along z; NULL: the vacuum law).  rows_out[item][3] = sum |res|^2, max |res|,
+// sum |f rho^|^2.
 template <class R>
 __global__ void __launch_bounds__(256) k_q_gauss(const RunQ<R> *__restrict__ runs,
                                                  const Item *__restrict__ items, int parity,
+                                                 const double2 *__restrict__ rho,
                                                  double *rows_out) {
-  __shared__ double red[256][2];
+  __shared__ double red[256][3];
   const Item it = items[blockIdx.x];
   const RunQ<R> &r = runs[it.run];
   const int m = it.a, j = it.b, n1 = r.n1;
   const double2 *F = r.Fk[parity] + (long long)m * 6 * r.plane;
-  double s2 = 0, smax = 0;
+  const double2 *rk = rho ? rho + (long long)m * r.plane + (long long)j * n1 : nullptr;
+  double s2 = 0, smax = 0, sref = 0;
   const bool on = (j > 0 && j < r.n2) || (j == 0 && m == 0);
   for (int k = threadIdx.x; on && k < n1; k += blockDim.x) {
     const double2 dm = make_double2(r.sym[4 * k + 2], r.sym[4 * k + 3]);
@@ -190,23 +248,33 @@ __global__ void __launch_bounds__(256) k_q_gauss(const RunQ<R> *__restrict__ run
       div.x += ((j + 0.5) * Er.x - (j - 0.5) * Erm.x) / (j * r.dr) - m / rj * Et.y;
       div.y += ((j + 0.5) * Er.y - (j - 0.5) * Erm.y) / (j * r.dr) + m / rj * Et.x;
     }
+    if (rk) {
+      const double f = r.filt64[k];
+      const double2 q = rk[k];
+      div.x -= f * q.x;
+      div.y -= f * q.y;
+      sref += f * f * (q.x * q.x + q.y * q.y);
+    }
     const double a2 = div.x * div.x + div.y * div.y;
     s2 += a2;
     smax = fmax(smax, sqrt(a2));
   }
   red[threadIdx.x][0] = s2;
   red[threadIdx.x][1] = smax;
+  red[threadIdx.x][2] = sref;
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
       red[threadIdx.x][0] += red[threadIdx.x + w][0];
       red[threadIdx.x][1] = fmax(red[threadIdx.x][1], red[threadIdx.x + w][1]);
+      red[threadIdx.x][2] += red[threadIdx.x + w][2];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    rows_out[2 * blockIdx.x] = red[0][0];
-    rows_out[2 * blockIdx.x + 1] = red[0][1];
+    rows_out[3 * blockIdx.x] = red[0][0];
+    rows_out[3 * blockIdx.x + 1] = red[0][1];
+    rows_out[3 * blockIdx.x + 2] = red[0][2];
   }
 }
 
@@ -233,9 +301,20 @@ void LaunchQ<R>::kupdate(const RunQ<R> *runs, const Item *items, int nitems, int
 }
 template <class R>
 void LaunchQ<R>::gauss(const RunQ<R> *runs, const Item *items, int nitems, int parity,
-                       double *rows_out, hipStream_t s) {
+                       const double2 *rho, double *rows_out, int maxn1, hipStream_t s) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_q_gauss<R>, dim3(nitems), dim3(256), 0, s, runs, items, parity, rows_out);
+  if (rho)
+    hipLaunchKernelGGL(k_q_rho_fft<R>, dim3(nitems), dim3(256), (size_t)maxn1 * sizeof(double2), s,
+                       runs, items, const_cast<double2 *>(rho));
+  hipLaunchKernelGGL(k_q_gauss<R>, dim3(nitems), dim3(256), 0, s, runs, items, parity, rho,
+                     rows_out);
+}
+template <class R>
+void LaunchQ<R>::fft_j(const RunQ<R> *runs, const Item *items, int nitems, int parity, int maxn1,
+                       hipStream_t s) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(k_q_fft_j<R>, dim3(nitems), dim3(256),
+                     (size_t)maxn1 * sizeof(typename Cplx<R>::T), s, runs, items, parity);
 }
 template struct LaunchQ<float>;
 template struct LaunchQ<double>;

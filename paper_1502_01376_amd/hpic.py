@@ -28,6 +28,7 @@ ABI = (
     "hp_get_particles_raw", "hp_diagnostics", "hp_get_state", "hp_set_state",
     "hp_debug_deposit", "hp_get_fixed_params", "hp_profile", "hp_get_kernel_times",
     "hp_get_push_stats", "hp_use_graphs", "hp_set_tiling", "hp_get_tiling", "hp_autotune",
+    "hp_get_current_mode",
 )
 
 
@@ -110,6 +111,7 @@ def lib():
             "hp_set_tiling": [_P, i32, i32, i32],
             "hp_get_tiling": [_P, _P],
             "hp_autotune": [_P, i32, _P],
+            "hp_get_current_mode": [_P, i32, i32, i32, _P, sz],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -185,7 +187,8 @@ class Sim:
         return c.n[1], c.n[0]
 
     def dim(self, run):
-        return 3 if self.cfgs[run].geom == HP_GEOM_3D else 2
+        """Position components of a particle: 2 (2D), 3 (3D; quasi-3D z, x, y)."""
+        return 3 if self.cfgs[run].geom in (HP_GEOM_3D, HP_GEOM_Q3D) else 2
 
     def set_stream(self, stream):
         s = getattr(stream, "cuda_stream", stream)
@@ -222,8 +225,10 @@ class Sim:
         _check(lib().hp_set_fields(self.h, run, 0, _ptr(E), _ptr(B)))
 
     def set_background(self, run, rho_from_particles=True, jbg=(0.0, 0.0, 0.0)):
+        """rho_from_particles: False/0 none, True/1 rho_bg = -rho_e(now), 2
+        (quasi-3D) also the co-drifting current of the particles."""
         j = np.ascontiguousarray(jbg, dtype=np.float64)
-        _check(lib().hp_set_background(self.h, run, int(bool(rho_from_particles)), _ptr(j)))
+        _check(lib().hp_set_background(self.h, run, int(rho_from_particles), _ptr(j)))
 
     def step(self, n=1):
         _check(lib().hp_step(self.h, int(n)))
@@ -259,6 +264,13 @@ class Sim:
     def current(self, run, comp, corrected=False):
         out = np.empty(self.shape(run))
         _check(lib().hp_get_current(self.h, run, comp, int(corrected), _ptr(out), out.size))
+        return out
+
+    def current_mode(self, run, comp, mode):
+        """Quasi-3D: deposited current density of the last step, mode `mode`,
+        complex [n2+1][n1] (before correction and filter)."""
+        out = np.empty(self.shape(run), dtype=np.complex128)
+        _check(lib().hp_get_current_mode(self.h, run, comp, int(mode), _ptr(out), 2 * out.size))
         return out
 
     def current_fixed(self, run):

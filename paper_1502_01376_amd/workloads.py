@@ -28,6 +28,16 @@ The named workloads are the drifting-plasma set-ups of the benchmark suite:
   lattice (2 per cell, 16 777 216 particles), gamma = 50 cold along x1, per-cell
   density multiplier U[0.95, 1.05] carried in the weights, 500 steps.
 
+* ``drift_q3d``  -- quasi-3D, 4096 (z) x 256 (r) cells, dz = 0.1, dr = 0.2,
+  dt = 0.04, modes m = 0, 1, 2; a plasma column of radius 250 dr (the wall is
+  at 256 dr) with 2 (z) x 1 (r) x 4 (theta, equally spaced with a random phase
+  per cell) particles per cell, weights proportional to r (uniform density 1),
+  gamma = 20 cold along z, and an m = 1 seed: a linearly polarised Gaussian
+  pulse E_x = a0 exp(-((z - zc)/L)^2 - (r/W)^2) cos(k0 (z - zc)), B_y = -E_x
+  (moving along -z), a0 = 1, W = 8, L = 4, k0 = 10.  Positions are Cartesian
+  (z, x, y) in physical units, ``w`` the number of physical particles (charge
+  q w), fields per mode complex [M][3][n2+1][n1].
+
 The NCI test set-up of Table 1 (dx = 0.2, dt = 0.4 dx1, periodic,
 51.2 x 51.2, gamma = 50, n = 100) is ``nci_table1``.
 """
@@ -261,3 +271,54 @@ def nci_table1(seed=SEED0 + 10, ppc=(2, 2), n=(256, 256)):
     d = drift2d(n[0], n[1], 0.2, 0.2, 0.08, sub=ppc, gamma=50.0, sigma_u=1e-4, density=100.0,
                 seed=seed, name="nci_table1")
     return d
+
+
+def drift_q3d(n1=4096, n2=256, dz=0.1, dr=0.2, dt=0.04, modes=3, sub=(2, 1, 4), rfill=None,
+              gamma=20.0, sigma_u=0.0, density=1.0, a0=1.0, waist=8.0, length=4.0, k0=10.0,
+              alpha=0.5, seed=SEED0 + 3, name=None):
+    """Quasi-3D drifting plasma column with an m = 1 seed pulse (see the module
+    docstring).  Particles of cell (i, j): z = (i + (a + 1/2)/sub_z) dz,
+    r = (j + (b + 1/2)/sub_r) dr, theta = phase_ij + 2 pi c / sub_t; weight
+    density * 2 pi r dr dz / ppc (the volume each represents)."""
+    gen = rng(seed)
+    if rfill is None:
+        rfill = n2 - 6
+    ppc = sub[0] * sub[1] * sub[2]
+    iz, jr = np.meshgrid(np.arange(n1), np.arange(rfill), indexing="ij")
+    iz, jr = iz.ravel(), jr.ravel()
+    phase = 2.0 * math.pi * gen.random(iz.size)
+    oz = (np.arange(sub[0]) + 0.5) / sub[0]
+    orr = (np.arange(sub[1]) + 0.5) / sub[1]
+    ot = 2.0 * math.pi * np.arange(sub[2]) / sub[2]
+    a, b, c = np.meshgrid(oz, orr, ot, indexing="ij")
+    a, b, c = a.ravel(), b.ravel(), c.ravel()                      # [ppc]
+    z = ((iz[:, None] + a[None, :]) * dz).ravel()
+    r = ((jr[:, None] + b[None, :]) * dr).ravel()
+    th = (phase[:, None] + c[None, :]).ravel()
+    x = np.stack([z, r * np.cos(th), r * np.sin(th)])
+    npart = z.size
+    u = drift_momenta(npart, gamma, sigma_u, gen)
+    w = density * 2.0 * math.pi * r * dr * dz / ppc
+    # m = 1 seed: E_x (Er_1 = E_x, Eth_1 = i E_x), B_y = -E_x (Br_1 = i E_x,
+    # Bth_1 = -E_x), each at its staggered node
+    zc = 0.75 * n1 * dz
+    nr = n2 + 1
+    zi, zh = np.arange(n1) * dz, (np.arange(n1) + 0.5) * dz
+    ri, rh = np.arange(nr) * dr, (np.arange(nr) + 0.5) * dr
+
+    def pulse(zz, rr):
+        return a0 * np.exp(-((zz[None, :] - zc) / length) ** 2 - (rr[:, None] / waist) ** 2) * \
+            np.cos(k0 * (zz[None, :] - zc))
+
+    E = np.zeros((modes, 3, nr, n1), dtype=np.complex128)
+    B = np.zeros_like(E)
+    if modes > 1 and a0 != 0:
+        E[1, 1] = pulse(zi, rh)
+        E[1, 2] = 1j * pulse(zi, ri)
+        B[1, 1] = 1j * pulse(zh, ri)
+        B[1, 2] = -pulse(zh, rh)
+        for F in (E, B):
+            F[1, :, n2] = 0.0
+    return dict(name=name or "drift_q3d_%dx%d_m%d_g%g" % (n1, n2, modes, gamma), geom=4,
+                n=(n1, n2), dx=(dz, dr), dt=dt, modes=modes, alpha=alpha, x=x, u=u, w=w,
+                q=-1.0, qm=-1.0, E=E, B=B, seed=seed, steps=500)
