@@ -25,8 +25,10 @@
 // wscale; the row-transform kernel converts them to current densities with
 // the face areas and node volumes.
 //
-// One thread per particle, global atomics (64-bit integers of the rounded
-// FP32 contributions in the FP32 form: the sum does not depend on the order).
+// One thread per particle; each wave accumulates into an LDS box (global
+// atomics if its particles spread too far), then adds the box to the global
+// accumulators.  FP32 form: 64-bit integers of the rounded FP32 contributions,
+// so the sums do not depend on the order.
 #include "hpic_internal.h"
 
 namespace hp {
@@ -134,17 +136,49 @@ __device__ __forceinline__ void acc_add(double *p, double v) {
 }
 
 constexpr int MAXM = 8;
+// LDS of one push workgroup: a private current box per wave of WAVE_CAP
+// accumulators (the wave's particles are consecutive, hence close together).
+constexpr int QLDS_BYTES = 64512;
+constexpr int WAVE_CAP = QLDS_BYTES / 4 / 8;
 
+__device__ __forceinline__ int wmin(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wmax(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ void lds_add(long long *p, float v) {
+  const long long q = (long long)rintf(v);
+  if (q != 0) atomicAdd((unsigned long long *)p, (unsigned long long)q);
+}
+__device__ __forceinline__ void lds_add(double *p, double v) {
+  if (v != 0.0) atomicAdd(p, v);
+}
+__device__ __forceinline__ void glob_add(long long *p, long long v) {
+  atomicAdd((unsigned long long *)p, (unsigned long long)v);
+}
+__device__ __forceinline__ void glob_add(double *p, double v) { atomicAdd(p, v); }
+
+// One thread per particle (items: run, first particle of 256).  Each wave
+// bounds the deposit footprint of its 64 particles before the push (a move is
+// less than a cell: columns cz-2 .. cz+3, rows m-2 .. m+2 around the nearest
+// integer-r node m, ghost rows folded onto rows 0 and 1) and, if the box fits,
+// deposits into its LDS box and adds the box to the global accumulators
+// afterwards; otherwise it deposits with global atomics.
 template <class R>
 __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restrict__ runs,
                                                         const Item *__restrict__ items, int parity,
                                                         unsigned *err) {
   using C = typename Cplx<R>::T;
   using A = typename AccQ<R>::T;
+  extern __shared__ unsigned char smem_raw[];
   const Item it = items[blockIdx.x];
   const RunQ<R> &r = runs[it.run];
-  const int p = it.a + threadIdx.x;
-  if (p >= r.np) return;
+  const int p0 = it.a + threadIdx.x;
+  const bool active = p0 < r.np;
+  const int p = active ? p0 : it.a;  // inactive lanes shadow a valid particle
   const PartsQ<R> P = r.pt;
   const int n1 = r.n1, M = r.M;
   const long long plane = r.plane;
@@ -155,6 +189,23 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
   const R rad = sqrt(x * x + y * y);
   const R rho = rad * r.idr;
   const R ct = rad > R(0) ? x / rad : R(1), st = rad > R(0) ? y / rad : R(0);
+  const int mri = ifloorq<R>(rho + R(0.5));  // nearest integer-r node
+  // ---- the wave's deposit box (relative z columns, absolute rows)
+  const int NS = 3 * (2 * M - 1);  // accumulator slots per node
+  const int cz0 = __shfl(cz, 0);
+  const int relz = ((cz - cz0 + (n1 >> 1)) & (n1 - 1)) - (n1 >> 1);
+  const int zlo = wmin(active ? relz : (1 << 29)) - 2;
+  const int zhi = wmax(active ? relz : -(1 << 29)) + 3;
+  const int rlo = max(0, wmin(active ? mri : (1 << 29)) - 2);
+  const int rhi = wmax(active ? mri : -(1 << 29)) + 2;
+  const int W = zhi - zlo + 1, H = rhi - rlo + 1;
+  const bool any = zhi >= zlo;
+  const bool use_lds = any && W <= n1 && (long long)W * H * NS <= WAVE_CAP;
+  A *box = (A *)smem_raw + (threadIdx.x >> 6) * WAVE_CAP;
+  const int lane = threadIdx.x & 63;
+  if (use_lds)
+    for (int e = lane; e < W * H * NS; e += 64) box[e] = 0;
+  __syncthreads();
   // phases P_m = (ct - i st)^m
   R Pr[MAXM], Pi[MAXM];
   Pr[0] = 1;
@@ -174,9 +225,8 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
     ozi[a] = wrap_pow2(cz + upz - 1 + a, n1);
     ozh[a] = wrap_pow2(cz - 1 + a, n1);
   }
-  const int mri = ifloorq<R>(rho + R(0.5));  // nearest integer-r node
   splineq<R>(rho - R(mri), wri);
-  const int mrh = ifloorq<R>(rho);           // nearest half-r node (j + 1/2)
+  const int mrh = ifloorq<R>(rho);  // nearest half-r node (j + 1/2)
   splineq<R>(rho - R(0.5) - R(mrh), wrh);
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
@@ -212,159 +262,182 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
   const R xb = x + r.dtr * v[1], yb = y + r.dtr * v[2];
   const R radb = sqrt(xb * xb + yb * yb);
   const R rhob = radb * r.idr;
-  if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(mz) && isfinite(xb) &&
-        isfinite(yb))) {
+  bool ok = active;
+  if (ok && !(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(mz) && isfinite(xb) &&
+              isfinite(yb))) {
     atomicOr(err, ERR_NUMERIC);
-    return;
+    ok = false;
   }
-  if (!(fabs(mz) < R(1)) || !(rhob < r.rmax) || !(fabs(rhob - rho) < R(1))) {
+  if (ok && (!(fabs(mz) < R(1)) || !(rhob < r.rmax) || !(fabs(rhob - rho) < R(1)))) {
     atomicOr(err, ERR_RANGE);
-    return;
+    ok = false;
   }
-  // new z cell and offset
-  R gz = fz + mz;
-  int dz = 0;
-  if (gz >= R(1)) {
-    gz = gz - R(1);
-    dz = 1;
-  } else if (gz < R(0)) {
-    gz = gz + R(1);
-    dz = -1;
+  if (ok) {
+    // new z cell and offset
+    R gz = fz + mz;
+    int dz = 0;
     if (gz >= R(1)) {
-      gz = R(0);
-      dz = 0;
-    }
-  }
-  // ---- deposit: 4-node windows along z and r holding both stencils
-  R S0z[4], S1z[4], S0r[4], S1r[4];
-  int bz, br;
-  {
-    R sa[3], sb[3];
-    const int na = zshape<R>(cz, fz, sa);
-    const int nb = zshape<R>(cz + dz, gz, sb);
-    bz = min(na, nb) - 1;
-    place4<R>(sa, na - 1 - bz, S0z);
-    place4<R>(sb, nb - 1 - bz, S1z);
-    const int ra = rshape<R>(rho, sa);
-    const int rb = rshape<R>(rhob, sb);
-    br = min(ra, rb) - 1;
-    place4<R>(sa, ra - 1 - br, S0r);
-    place4<R>(sb, rb - 1 - br, S1r);
-  }
-  R Cz[4], Tz[4], Cr[4], Tr[4];
-  {
-    R az = 0, ar = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      az = az + (S1z[k] - S0z[k]);
-      ar = ar + (S1r[k] - S0r[k]);
-      Cz[k] = az;
-      Cr[k] = ar;
-      Tz[k] = R(0.5) * (S0z[k] + S1z[k]);
-      Tr[k] = R(0.5) * (S0r[k] + S1r[k]);
-    }
-  }
-  int col[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) col[a] = wrap_pow2(bz + a, n1);
-  // azimuthal velocity at the mid point times dt (charge-per-step units)
-  const R xm = R(0.5) * (x + xb), ym = R(0.5) * (y + yb);
-  const R rm = sqrt(xm * xm + ym * ym);
-  const R vthdt = rm > R(0) ? (xm * (yb - y) - ym * (xb - x)) / rm : R(0);
-  const R ctb = radb > R(0) ? xb / radb : R(1), stb = radb > R(0) ? yb / radb : R(0);
-  const R g = qw * r.wscale;
-  A *J = r.J[parity];
-  R P1r = 1, P1i = 0;  // phase at the new position
-  for (int m = 0; m < M; ++m) {
-    if (m > 0) {
-      const R t = P1r * ctb + P1i * stb;
-      P1i = P1i * ctb - P1r * stb;
-      P1r = t;
-    }
-    const R cm = m == 0 ? R(1) : R(2);
-    const bool odd = m & 1;
-    const R Pmr = R(0.5) * (Pr[m] + P1r), Pmi = R(0.5) * (Pi[m] + P1i);
-    const R qr = -cm * g * Pmr, qi = -cm * g * Pmi;
-    A *Jz = J + (long long)(m * 3 + 0) * plane * 2;
-    A *Jr = J + (long long)(m * 3 + 1) * plane * 2;
-    A *Jt = J + (long long)(m * 3 + 2) * plane * 2;
-    // z faces
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int row = br + b;
-      R f = Tr[b];
-      if (row < 0) {
-        row = -row;
-        if (odd) f = -f;
-      }
-      if (f == R(0)) continue;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const R w = Cz[a] * f;
-        A *o = Jz + ((long long)row * n1 + col[a]) * 2;
-        acc_add(o, qr * w);
-        if (m > 0) acc_add(o + 1, qi * w);
+      gz = gz - R(1);
+      dz = 1;
+    } else if (gz < R(0)) {
+      gz = gz + R(1);
+      dz = -1;
+      if (gz >= R(1)) {
+        gz = R(0);
+        dz = 0;
       }
     }
-    // r faces (face j at (j + 1/2) dr; face -1 lands on face 0)
+    // ---- deposit: 4-node windows along z and r holding both stencils
+    R S0z[4], S1z[4], S0r[4], S1r[4];
+    int bz, br;
+    {
+      R sa[3], sb[3];
+      const int na = zshape<R>(cz, fz, sa);
+      const int nb = zshape<R>(cz + dz, gz, sb);
+      bz = min(na, nb) - 1;
+      place4<R>(sa, na - 1 - bz, S0z);
+      place4<R>(sb, nb - 1 - bz, S1z);
+      const int ra = rshape<R>(rho, sa);
+      const int rb = rshape<R>(rhob, sb);
+      br = min(ra, rb) - 1;
+      place4<R>(sa, ra - 1 - br, S0r);
+      place4<R>(sb, rb - 1 - br, S1r);
+    }
+    R Cz[4], Tz[4], Cr[4], Tr[4];
+    {
+      R az = 0, ar = 0;
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      int face = br + b;
-      R f = Cr[b];
-      if (face < 0) {
-        face = 0;
-        if (!odd) f = -f;
-      }
-      if (f == R(0)) continue;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const R w = Tz[a] * f;
-        if (w == R(0)) continue;
-        A *o = Jr + ((long long)face * n1 + col[a]) * 2;
-        acc_add(o, qr * w);
-        if (m > 0) acc_add(o + 1, qi * w);
+      for (int k = 0; k < 4; ++k) {
+        az = az + (S1z[k] - S0z[k]);
+        ar = ar + (S1r[k] - S0r[k]);
+        Cz[k] = az;
+        Cr[k] = ar;
+        Tz[k] = R(0.5) * (S0z[k] + S1z[k]);
+        Tr[k] = R(0.5) * (S0r[k] + S1r[k]);
       }
     }
-    // azimuthal current
-    const R dPr = P1r - Pr[m], dPi = P1i - Pi[m];
-    const R inv_m = m > 0 ? R(1) / R(m) : R(0);
+    const int bzrel = bz - cz + relz - zlo;  // window column 0 in the box
+    int col[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int row = br + b;
-      const bool ghost = row < 0;
-      if (ghost) row = -row;
-      const bool direct = m == 0 || (m == 1 && row == 0);
-      if (!direct && row == 0) continue;
+    for (int a = 0; a < 4; ++a) col[a] = wrap_pow2(bz + a, n1);
+    A *J = r.J[parity];
+    // one contribution v (charge per step, scaled) to component c, mode m,
+    // real (part 0) or imaginary (part 1) part, node (row, window column a)
+    auto put = [&](int c, int m, int part, int row, int a, R val) {
+      if (use_lds) {
+        const int slot = c * (2 * M - 1) + (m == 0 ? 0 : 2 * m - 1 + part);
+        lds_add(box + ((long long)slot * H + (row - rlo)) * W + (bzrel + a), val);
+      } else {
+        acc_add(J + ((long long)(m * 3 + c) * plane + (long long)row * n1 + col[a]) * 2 + part, val);
+      }
+    };
+    // azimuthal velocity at the mid point times dt
+    const R xm = R(0.5) * (x + xb), ym = R(0.5) * (y + yb);
+    const R rm = sqrt(xm * xm + ym * ym);
+    const R vthdt = rm > R(0) ? (xm * (yb - y) - ym * (xb - x)) / rm : R(0);
+    const R ctb = radb > R(0) ? xb / radb : R(1), stb = radb > R(0) ? yb / radb : R(0);
+    const R g = qw * r.wscale;
+    R P1r = 1, P1i = 0;  // phase at the new position
+    for (int m = 0; m < M; ++m) {
+      if (m > 0) {
+        const R t = P1r * ctb + P1i * stb;
+        P1i = P1i * ctb - P1r * stb;
+        P1r = t;
+      }
+      const R cm = m == 0 ? R(1) : R(2);
+      const bool odd = m & 1;
+      const R Pmr = R(0.5) * (Pr[m] + P1r), Pmi = R(0.5) * (Pi[m] + P1i);
+      const R qr = -cm * g * Pmr, qi = -cm * g * Pmi;
+      // z faces
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        A *o = Jt + ((long long)row * n1 + col[a]) * 2;
-        if (direct) {
-          R W3 = S0z[a] * S0r[b] * R(1.0 / 3.0) + S1z[a] * S0r[b] * R(1.0 / 6.0) +
-                 S0z[a] * S1r[b] * R(1.0 / 6.0) + S1z[a] * S1r[b] * R(1.0 / 3.0);
-          if (W3 == R(0)) continue;
-          R s = cm * g * W3 * vthdt;
-          if (ghost && !odd) s = -s;  // -(-1)^m
-          acc_add(o, s * Pmr);
-          if (m > 0) acc_add(o + 1, s * Pmi);
-        } else {
-          const R Wb = R(0.5) * (S0z[a] * S0r[b] + S1z[a] * S1r[b]);
-          if (Wb == R(0)) continue;
-          R s = cm * g * Wb * inv_m;
-          if (ghost && odd) s = -s;  // (-1)^m
-          // i s (dP)
-          acc_add(o, -s * dPi);
-          acc_add(o + 1, s * dPr);
+      for (int b = 0; b < 4; ++b) {
+        int row = br + b;
+        R f = Tr[b];
+        if (row < 0) {
+          row = -row;
+          if (odd) f = -f;
+        }
+        if (f == R(0)) continue;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const R w = Cz[a] * f;
+          put(0, m, 0, row, a, qr * w);
+          if (m > 0) put(0, m, 1, row, a, qi * w);
+        }
+      }
+      // r faces (face j at (j + 1/2) dr; face -1 lands on face 0)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        int face = br + b;
+        R f = Cr[b];
+        if (face < 0) {
+          face = 0;
+          if (!odd) f = -f;
+        }
+        if (f == R(0)) continue;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const R w = Tz[a] * f;
+          if (w == R(0)) continue;
+          put(1, m, 0, face, a, qr * w);
+          if (m > 0) put(1, m, 1, face, a, qi * w);
+        }
+      }
+      // azimuthal current
+      const R dPr = P1r - Pr[m], dPi = P1i - Pi[m];
+      const R inv_m = m > 0 ? R(1) / R(m) : R(0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        int row = br + b;
+        const bool ghost = row < 0;
+        if (ghost) row = -row;
+        const bool direct = m == 0 || (m == 1 && row == 0);
+        if (!direct && row == 0) continue;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          if (direct) {
+            const R W3 = S0z[a] * S0r[b] * R(1.0 / 3.0) + S1z[a] * S0r[b] * R(1.0 / 6.0) +
+                         S0z[a] * S1r[b] * R(1.0 / 6.0) + S1z[a] * S1r[b] * R(1.0 / 3.0);
+            if (W3 == R(0)) continue;
+            R sv = cm * g * W3 * vthdt;
+            if (ghost && !odd) sv = -sv;  // -(-1)^m
+            put(2, m, 0, row, a, sv * Pmr);
+            if (m > 0) put(2, m, 1, row, a, sv * Pmi);
+          } else {
+            const R Wb = R(0.5) * (S0z[a] * S0r[b] + S1z[a] * S1r[b]);
+            if (Wb == R(0)) continue;
+            R sv = cm * g * Wb * inv_m;
+            if (ghost && odd) sv = -sv;  // (-1)^m
+            // i sv dP
+            put(2, m, 0, row, a, -sv * dPi);
+            put(2, m, 1, row, a, sv * dPr);
+          }
         }
       }
     }
+    G(P.cell)[p] = wrap_pow2(cz + dz, n1);
+    G(P.fz)[p] = gz;
+    G(P.x)[p] = xb;
+    G(P.y)[p] = yb;
+    G(P.uz)[p] = u[0];
+    G(P.ux)[p] = u[1];
+    G(P.uy)[p] = u[2];
   }
-  G(P.cell)[p] = wrap_pow2(cz + dz, n1);
-  G(P.fz)[p] = gz;
-  G(P.x)[p] = xb;
-  G(P.y)[p] = yb;
-  G(P.uz)[p] = u[0];
-  G(P.ux)[p] = u[1];
-  G(P.uy)[p] = u[2];
+  __syncthreads();
+  if (use_lds) {
+    A *J = r.J[parity];
+    const int per = 2 * M - 1;
+    for (int e = lane; e < W * H * NS; e += 64) {
+      const A v = box[e];
+      if (v == A(0)) continue;
+      const int cc = e % W, rest = e / W;
+      const int row = rlo + rest % H, slot = rest / H;
+      const int c = slot / per, s2 = slot - c * per;
+      const int m = (s2 + 1) >> 1, part = s2 == 0 ? 0 : (s2 - 1) & 1;
+      const int col = wrap_pow2(cz0 + zlo + cc, n1);
+      glob_add(J + ((long long)(m * 3 + c) * plane + (long long)row * n1 + col) * 2 + part, v);
+    }
+  }
 }
 
 // FP64 charge density of a run's particles (any form), added into rho.
@@ -439,7 +512,8 @@ template <class R>
 void LaunchQ<R>::push_deposit(const RunQ<R> *runs, const Item *items, int nitems, int parity,
                               unsigned *err, hipStream_t s) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_q_push_deposit<R>, dim3(nitems), dim3(256), 0, s, runs, items, parity, err);
+  hipLaunchKernelGGL(k_q_push_deposit<R>, dim3(nitems), dim3(256), (size_t)QLDS_BYTES, s, runs,
+                     items, parity, err);
 }
 template <class R>
 void LaunchQ<R>::rho(const RunQ<R> *run_dev, int np, int M, double2 *rho, hipStream_t s) {
