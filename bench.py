@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--d3-steps", type=int, default=500,
                     help="steps of the 3D 512x128x128 drifting-plasma leg (0: skip)")
     ap.add_argument("--q3d-steps", type=int, default=200,
-                    help="steps of the quasi-3D 4096x256 three-mode field solve (0: skip)")
+                    help="steps of the quasi-3D 4096x256 three-mode PIC leg (0: skip)")
     ap.add_argument("--n1", type=int, default=2048)
     ap.add_argument("--n2", type=int, default=512)
     return ap.parse_args()
@@ -231,40 +231,49 @@ def d3_leg(hpic, torch, W, steps, tune_steps):
             "push_deposit_alg_GBps": (60 * npart + 72 * cells) / (pd_ms / max(pd_n, 1) * 1e-3) / 1e9}
 
 
-def q3d_leg(hpic, torch, steps):
-    """Quasi-3D field solver: 4096 (z) x 256 (r) cells, dz = 0.1, dr = 0.2,
-    dt = 0.04, azimuthal modes 0, 1, 2 advanced together (one launch per
-    stage), seeded with an m = 1 laser-like field a0 = 1 (synthetic).  Only the
-    field solver is built for this geometry, so the figure is mode-cells per
-    second, with per-kernel times and the FP64 form beside it."""
-    n1, n2, M, dz, dr, dt = 4096, 256, 3, 0.1, 0.2, 0.04
-    z = np.arange(n1) * dz
-    r = np.arange(n2 + 1) * dr
-    env = np.exp(-((z - 0.6 * n1 * dz) / 4.0) ** 2)[None, :] * np.exp(-(r / 8.0) ** 2)[:, None]
-    out = {"workload": "quasi3d_4096x256_m012_fields", "n": [n1, n2], "modes": M, "steps": steps}
+def q3d_leg(hpic, torch, W, steps):
+    """Quasi-3D PIC step: 4096 (z) x 256 (r) cells, dz = 0.1, dr = 0.2, dt =
+    0.04, azimuthal modes 0, 1, 2 advanced together (one launch per stage), a
+    plasma column of 8 192 000 particles drifting at gamma = 20 over a
+    co-drifting background, and an m = 1 seed pulse (synthetic, seeded).  Both
+    forms over the same steps: particle-steps/s, per-kernel times, the
+    FP32-vs-FP64 relative L2 error of every mode's E and B, and the change of
+    the Gauss residual norm (constant in exact arithmetic)."""
+    d = W.drift_q3d()
+    n1, n2 = d["n"]
+    M = d["modes"]
+    npart = d["w"].size
+    out = {"workload": d["name"], "n": [n1, n2], "modes": M, "particles": npart, "steps": steps}
+    fields = {}
     for prec in ("fp32", "fp64"):
-        sim = hpic.Sim([hpic.config(n1, n2, dz, dr, dt, alpha=0.5, precision=prec, modes=M)],
-                       stream=torch.cuda.current_stream())
-        E = np.zeros((3, n2 + 1, n1), complex)
-        B = np.zeros_like(E)
-        E[1] = env * np.exp(10j * z)[None, :]          # E_r + i E_th of an m = 1 field
-        E[2] = 1j * E[1]
-        B[1] = -E[2]
-        B[2] = E[1]
-        E[:, n2] = 0
-        B[:, n2] = 0
-        sim.set_fields_mode(0, 1, E, B)
+        sim = hpic.Sim([hpic.config(n1, n2, d["dx"][0], d["dx"][1], d["dt"], alpha=d["alpha"],
+                                    precision=prec, modes=M)], stream=torch.cuda.current_stream())
+        for m in range(M):
+            sim.set_fields_mode(0, m, d["E"][m], d["B"][m])
+        sim.set_particles(0, d["x"], d["u"], d["w"], q_over_m=d["qm"], q=d["q"])
+        sim.set_background(0, 2)
+        g0 = sim.diagnostics(0)["gauss_l2"]
         t = timed_steps(torch, sim, 10, steps)
         sim.profile(True)
         sim.step(steps)
         kt = sim.kernel_times()
-        d = sim.diagnostics(0)
+        sim.profile(False)
+        dg = sim.diagnostics(0)
+        fields[prec] = np.stack([np.stack([sim.field_mode(0, c, m) for c in range(6)])
+                                 for m in range(M)])
         sim.close()
         out[prec] = {"ms_per_step": 1e3 * t / steps,
-                     "mode_cells_per_s": M * n1 * (n2 + 1) * steps / t,
+                     "particle_steps_per_s": npart * steps / t,
                      "kernels": {k: {"avg_us": 1e3 * ms / n, "launches": n}
                                  for k, (ms, n) in kt.items() if n > 0},
-                     "field_energy": sum(d["W_E"]) + sum(d["W_B"])}
+                     "gauss_l2_change": abs(dg["gauss_l2"] - g0) / max(g0, 1e-300),
+                     "kinetic": dg["kinetic"],
+                     "field_energy": sum(dg["W_E"]) + sum(dg["W_B"])}
+    a, b = fields["fp32"], fields["fp64"]
+    out["err_vs_fp64"] = {"after_steps": 10 + 2 * steps,
+                          "E_rel_l2": rel_l2(a[:, :3], b[:, :3]),
+                          "B_rel_l2": rel_l2(a[:, 3:], b[:, 3:])}
+    out["fp32_over_fp64"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
     return out
 
 
@@ -358,7 +367,7 @@ def main():
     if args.d3_steps > 0:
         out["drift3d"] = d3_leg(hpic, torch, W, args.d3_steps, args.tune_steps)
     if args.q3d_steps > 0:
-        out["quasi3d"] = q3d_leg(hpic, torch, args.q3d_steps)
+        out["quasi3d"] = q3d_leg(hpic, torch, W, args.q3d_steps)
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
         x = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -127,12 +127,12 @@ __device__ __forceinline__ R gather_q(const typename Cplx<R>::T *__restrict__ Fc
   return acc;
 }
 
-__device__ __forceinline__ void acc_add(long long *p, float v) {
-  const long long q = (long long)rintf(v);
-  if (q != 0) atomicAdd((unsigned long long *)p, (unsigned long long)q);
+__device__ __forceinline__ void acc_add(gptr<long long> p, float v) {
+  const long long q = (long long)(int)rintf(v);  // |v| < 2^31
+  if (q != 0) __hip_atomic_fetch_add(p, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void acc_add(double *p, double v) {
-  if (v != 0.0) atomicAdd(p, v);
+__device__ __forceinline__ void acc_add(gptr<double> p, double v) {
+  if (v != 0.0) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 constexpr int MAXM = 8;
@@ -149,17 +149,146 @@ __device__ __forceinline__ int wmax(int v) {
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
   return v;
 }
-__device__ __forceinline__ void lds_add(long long *p, float v) {
-  const long long q = (long long)rintf(v);
-  if (q != 0) atomicAdd((unsigned long long *)p, (unsigned long long)q);
+template <class T> using lptr = T __attribute__((address_space(3))) *;
+
+// Integer of one FP32 contribution: |v| < 2^31 (charges are scaled to at most
+// 2^28 and every weight factor is at most 4 in magnitude).
+__device__ __forceinline__ long long to_fixed(float v) { return (long long)(int)rintf(v); }
+__device__ __forceinline__ double to_fixed(double v) { return v; }
+
+// Deposit targets: the wave's LDS box, or the global accumulators.
+template <class A>
+struct SinkLdsQ {
+  lptr<A> box;
+  int H, W, rlo, bzrel, per;
+  template <class V>
+  __device__ __forceinline__ void operator()(int c, int m, int part, int row, int a, V v) const {
+    const int slot = c * per + (m == 0 ? 0 : 2 * m - 1 + part);
+    const auto q = to_fixed(v);
+    if (q != 0)
+      __hip_atomic_fetch_add(box + (slot * H + (row - rlo)) * W + (bzrel + a), q, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+template <class A>
+struct SinkGlobQ {
+  A *J;
+  long long plane;
+  int n1, col[4];
+  template <class V>
+  __device__ __forceinline__ void operator()(int c, int m, int part, int row, int a, V v) const {
+    acc_add(G(J) + ((long long)(m * 3 + c) * plane + (long long)row * n1 + col[a]) * 2 + part, v);
+  }
+};
+__device__ __forceinline__ void glob_add(gptr<long long> p, long long v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void lds_add(double *p, double v) {
-  if (v != 0.0) atomicAdd(p, v);
+__device__ __forceinline__ void glob_add(gptr<double> p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void glob_add(long long *p, long long v) {
-  atomicAdd((unsigned long long *)p, (unsigned long long)v);
+
+// Per-mode deposit of one move (see the file header): window shapes S0/S1
+// along z and r, their running sums C and means T, window row base br, the
+// old phases P (mode m: Pr[m] - i Pi[m]... stored as (Pr, Pi) of e^{-i m th}),
+// the new direction (ctb, stb), scaled charge g and v_th dt.
+template <class R, class Sink>
+__device__ __forceinline__ void deposit_q(const Sink &put, int M, const R S0z[4], const R S1z[4],
+                                          const R S0r[4], const R S1r[4], const R Cz[4],
+                                          const R Tz[4], const R Cr[4], const R Tr[4], int br,
+                                          const R *Pr, const R *Pi, R ctb, R stb, R g, R vthdt) {
+  R P1r = 1, P1i = 0;  // phase at the new position
+  for (int m = 0; m < M; ++m) {
+    if (m > 0) {
+      const R t = P1r * ctb + P1i * stb;
+      P1i = P1i * ctb - P1r * stb;
+      P1r = t;
+    }
+    const R cm = m == 0 ? R(1) : R(2);
+    const bool odd = m & 1;
+    const R Pmr = R(0.5) * (Pr[m] + P1r), Pmi = R(0.5) * (Pi[m] + P1i);
+    const R qr = -cm * g * Pmr, qi = -cm * g * Pmi;
+    // z faces
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int row = br + b;
+      R f = Tr[b];
+      if (row < 0) {
+        row = -row;
+        if (odd) f = -f;
+      }
+      if (f == R(0)) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const R w = Cz[a] * f;
+        put(0, m, 0, row, a, qr * w);
+        if (m > 0) put(0, m, 1, row, a, qi * w);
+      }
+    }
+    // r faces (face j at (j + 1/2) dr; face -1 lands on face 0)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      int face = br + b;
+      R f = Cr[b];
+      if (face < 0) {
+        face = 0;
+        if (!odd) f = -f;
+      }
+      if (f == R(0)) continue;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const R w = Tz[a] * f;
+        if (w == R(0)) continue;
+        put(1, m, 0, face, a, qr * w);
+        if (m > 0) put(1, m, 1, face, a, qi * w);
+      }
+    }
+    // azimuthal current
+    const R dPr = P1r - Pr[m], dPi = P1i - Pi[m];
+    const R inv_m = m > 0 ? R(1) / R(m) : R(0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int row = br + b;
+      const bool ghost = row < 0;
+      if (ghost) row = -row;
+      const bool direct = m == 0 || (m == 1 && row == 0);
+      if (!direct && row == 0) continue;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (direct) {
+          const R W3 = S0z[a] * S0r[b] * R(1.0 / 3.0) + S1z[a] * S0r[b] * R(1.0 / 6.0) +
+                       S0z[a] * S1r[b] * R(1.0 / 6.0) + S1z[a] * S1r[b] * R(1.0 / 3.0);
+          if (W3 == R(0)) continue;
+          R sv = cm * g * W3 * vthdt;
+          if (ghost && !odd) sv = -sv;  // -(-1)^m
+          put(2, m, 0, row, a, sv * Pmr);
+          if (m > 0) put(2, m, 1, row, a, sv * Pmi);
+        } else {
+          const R Wb = R(0.5) * (S0z[a] * S0r[b] + S1z[a] * S1r[b]);
+          if (Wb == R(0)) continue;
+          R sv = cm * g * Wb * inv_m;
+          if (ghost && odd) sv = -sv;  // (-1)^m
+          // i sv dP
+          put(2, m, 0, row, a, -sv * dPi);
+          put(2, m, 1, row, a, sv * dPr);
+        }
+      }
+    }
+  }
 }
-__device__ __forceinline__ void glob_add(double *p, double v) { atomicAdd(p, v); }
+
+// The rare global-atomic path out of line (FP64 form), so that it does not add
+// to the register budget of the LDS path (measured: faster in FP64, slower in
+// FP32, where the path stays inline).
+template <class R>
+__device__ __noinline__ void deposit_q_global(const SinkGlobQ<typename AccQ<R>::T> &K, int M,
+                                              const R *S0z, const R *S1z, const R *S0r,
+                                              const R *S1r, const R *Cz, const R *Tz, const R *Cr,
+                                              const R *Tr, int br, const R *Pr, const R *Pi, R ctb,
+                                              R stb, R g, R vthdt) {
+  deposit_q<R>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, Pr, Pi, ctb, stb, g, vthdt);
+}
+
+}  // namespace
 
 // One thread per particle (items: run, first particle of 256).  Each wave
 // bounds the deposit footprint of its 64 particles before the push (a move is
@@ -201,7 +330,7 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
   const int W = zhi - zlo + 1, H = rhi - rlo + 1;
   const bool any = zhi >= zlo;
   const bool use_lds = any && W <= n1 && (long long)W * H * NS <= WAVE_CAP;
-  A *box = (A *)smem_raw + (threadIdx.x >> 6) * WAVE_CAP;
+  const lptr<A> box = (lptr<A>)smem_raw + (threadIdx.x >> 6) * WAVE_CAP;
   const int lane = threadIdx.x & 63;
   if (use_lds)
     for (int e = lane; e < W * H * NS; e += 64) box[e] = 0;
@@ -320,100 +449,27 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
     int col[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) col[a] = wrap_pow2(bz + a, n1);
-    A *J = r.J[parity];
-    // one contribution v (charge per step, scaled) to component c, mode m,
-    // real (part 0) or imaginary (part 1) part, node (row, window column a)
-    auto put = [&](int c, int m, int part, int row, int a, R val) {
-      if (use_lds) {
-        const int slot = c * (2 * M - 1) + (m == 0 ? 0 : 2 * m - 1 + part);
-        lds_add(box + ((long long)slot * H + (row - rlo)) * W + (bzrel + a), val);
-      } else {
-        acc_add(J + ((long long)(m * 3 + c) * plane + (long long)row * n1 + col[a]) * 2 + part, val);
-      }
-    };
     // azimuthal velocity at the mid point times dt
     const R xm = R(0.5) * (x + xb), ym = R(0.5) * (y + yb);
     const R rm = sqrt(xm * xm + ym * ym);
     const R vthdt = rm > R(0) ? (xm * (yb - y) - ym * (xb - x)) / rm : R(0);
     const R ctb = radb > R(0) ? xb / radb : R(1), stb = radb > R(0) ? yb / radb : R(0);
     const R g = qw * r.wscale;
-    R P1r = 1, P1i = 0;  // phase at the new position
-    for (int m = 0; m < M; ++m) {
-      if (m > 0) {
-        const R t = P1r * ctb + P1i * stb;
-        P1i = P1i * ctb - P1r * stb;
-        P1r = t;
-      }
-      const R cm = m == 0 ? R(1) : R(2);
-      const bool odd = m & 1;
-      const R Pmr = R(0.5) * (Pr[m] + P1r), Pmi = R(0.5) * (Pi[m] + P1i);
-      const R qr = -cm * g * Pmr, qi = -cm * g * Pmi;
-      // z faces
+    if (use_lds) {
+      SinkLdsQ<A> K{(lptr<A>)smem_raw + (threadIdx.x >> 6) * WAVE_CAP, H, W, rlo, bzrel, 2 * M - 1};
+      deposit_q<R>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, Pr, Pi, ctb, stb, g, vthdt);
+    } else {
+      SinkGlobQ<A> K;
+      K.J = r.J[parity];
+      K.plane = plane;
+      K.n1 = n1;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        int row = br + b;
-        R f = Tr[b];
-        if (row < 0) {
-          row = -row;
-          if (odd) f = -f;
-        }
-        if (f == R(0)) continue;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const R w = Cz[a] * f;
-          put(0, m, 0, row, a, qr * w);
-          if (m > 0) put(0, m, 1, row, a, qi * w);
-        }
-      }
-      // r faces (face j at (j + 1/2) dr; face -1 lands on face 0)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        int face = br + b;
-        R f = Cr[b];
-        if (face < 0) {
-          face = 0;
-          if (!odd) f = -f;
-        }
-        if (f == R(0)) continue;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const R w = Tz[a] * f;
-          if (w == R(0)) continue;
-          put(1, m, 0, face, a, qr * w);
-          if (m > 0) put(1, m, 1, face, a, qi * w);
-        }
-      }
-      // azimuthal current
-      const R dPr = P1r - Pr[m], dPi = P1i - Pi[m];
-      const R inv_m = m > 0 ? R(1) / R(m) : R(0);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        int row = br + b;
-        const bool ghost = row < 0;
-        if (ghost) row = -row;
-        const bool direct = m == 0 || (m == 1 && row == 0);
-        if (!direct && row == 0) continue;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          if (direct) {
-            const R W3 = S0z[a] * S0r[b] * R(1.0 / 3.0) + S1z[a] * S0r[b] * R(1.0 / 6.0) +
-                         S0z[a] * S1r[b] * R(1.0 / 6.0) + S1z[a] * S1r[b] * R(1.0 / 3.0);
-            if (W3 == R(0)) continue;
-            R sv = cm * g * W3 * vthdt;
-            if (ghost && !odd) sv = -sv;  // -(-1)^m
-            put(2, m, 0, row, a, sv * Pmr);
-            if (m > 0) put(2, m, 1, row, a, sv * Pmi);
-          } else {
-            const R Wb = R(0.5) * (S0z[a] * S0r[b] + S1z[a] * S1r[b]);
-            if (Wb == R(0)) continue;
-            R sv = cm * g * Wb * inv_m;
-            if (ghost && odd) sv = -sv;  // (-1)^m
-            // i sv dP
-            put(2, m, 0, row, a, -sv * dPi);
-            put(2, m, 1, row, a, sv * dPr);
-          }
-        }
-      }
+      for (int a = 0; a < 4; ++a) K.col[a] = col[a];
+      if constexpr (sizeof(R) == 4)
+        deposit_q<R>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, Pr, Pi, ctb, stb, g, vthdt);
+      else
+        deposit_q_global<R>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, Pr, Pi, ctb, stb, g,
+                            vthdt);
     }
     G(P.cell)[p] = wrap_pow2(cz + dz, n1);
     G(P.fz)[p] = gz;
@@ -435,7 +491,7 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
       const int c = slot / per, s2 = slot - c * per;
       const int m = (s2 + 1) >> 1, part = s2 == 0 ? 0 : (s2 - 1) & 1;
       const int col = wrap_pow2(cz0 + zlo + cc, n1);
-      glob_add(J + ((long long)(m * 3 + c) * plane + (long long)row * n1 + col) * 2 + part, v);
+      glob_add(G(J) + ((long long)(m * 3 + c) * plane + (long long)row * n1 + col) * 2 + part, v);
     }
   }
 }
@@ -505,8 +561,6 @@ __global__ void __launch_bounds__(256) k_q_jbg(const RunQ<R> *__restrict__ run, 
     atomicAdd(jbg + row, -qw * vz * wr[b] / ((double)r.n1 * r.dz * A));
   }
 }
-
-}  // namespace
 
 template <class R>
 void LaunchQ<R>::push_deposit(const RunQ<R> *runs, const Item *items, int nitems, int parity,
