@@ -288,12 +288,14 @@ struct Launch {
 // conducting wall at j = n2).  Per mode complex arrays [6][nr][n1] in the
 // order Ez, Er, Eth, Bz, Br, Bth, staggered Ez (z+1/2, r_j), Er (z, r_j+1/2),
 // Eth (z, r_j), Bz (z, r_j+1/2), Br (z+1/2, r_j), Bth (z+1/2, r_j+1/2).
-// Quasi-3D particles: z as cell + offset in [0,1), transverse Cartesian x, y,
-// momenta (uz, ux, uy), charge times weight qw.
+// Quasi-3D particles: z as cell + offset in [0,1) (cells of dz), transverse
+// Cartesian x, y likewise on a lattice of spacing dr (cell ix, iy, offsets fx,
+// fy: the position keeps single-precision resolution within a cell anywhere in
+// the column), momenta (uz, ux, uy), charge times weight qw.
 template <class R>
 struct PartsQ {
-  int *cell;
-  R *fz, *x, *y, *uz, *ux, *uy, *qw;
+  int *cell, *ix, *iy;
+  R *fz, *fx, *fy, *uz, *ux, *uy, *qw;
   int *id;
 };
 // Accumulator of the quasi-3D deposit: 64-bit fixed point in the FP32 form
@@ -316,7 +318,7 @@ struct RunQ {
   // particle side (np = 0: field solve only)
   PartsQ<R> pt;
   int np;
-  R qmhdt, dtdz, dtr, idr, rmax;  // q/m dt/2, dt/dz, dt, 1/dr, limit of r/dr
+  R qmhdt, dtdz, dtdr, rmax;  // q/m dt/2, dt/dz, dt/dr, limit of r/dr
   R wscale;                       // contribution scale: inv_wunit cj (FP32), 1 (FP64)
   A *J[2];           // [M][3][nr][n1][2] deposit accumulators (re, im), by step parity
   C *Jk;             // [M][3][nr][n1] corrected, filtered current in k space

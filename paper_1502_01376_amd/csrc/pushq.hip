@@ -51,6 +51,44 @@ __device__ __forceinline__ void splineq(R d, R w[3]) {
 // Floor for the small non-negative arguments used here (r/dr + 1/2 >= 0).
 template <class R> __device__ __forceinline__ int ifloorq(R x) { return (int)floor(x); }
 
+// r / dr of a transverse position given as cells + offsets, as its nearest
+// integer node m and the offset d = r/dr - m, and the direction (c, s).  The
+// offset is formed from the exact integer part of (r/dr)^2 - m^2, so it keeps
+// the resolution of the stored offsets anywhere in the column: with
+// S = (ix + fx)^2 + (iy + fy)^2, d = (S - m^2) / (r/dr + m).
+template <class R>
+__device__ __forceinline__ void radial(int ix, R fx, int iy, R fy, int &m, R &d, R &c, R &s) {
+  const int si = ix * ix + iy * iy;
+  const R sf = fx * (R(2 * ix) + fx) + fy * (R(2 * iy) + fy);
+  const R rho0 = sqrt(fmax(R(si) + sf, R(0)));
+  m = (int)floor(rho0 + R(0.5));
+  const R X = R(ix) + fx, Y = R(iy) + fy;
+  // within half a cell of the axis ix, iy are 0 or -1 and X, Y are exact
+  d = m == 0 ? sqrt(X * X + Y * Y) : (R(si - m * m) + sf) / (rho0 + R(m));
+  const R rho = R(m) + d;
+  c = rho > R(0) ? X / rho : R(1);
+  s = rho > R(0) ? Y / rho : R(0);
+}
+
+// New offset in [0,1) and cell shift in {-1, 0, 1} after a move d (|d| < 1).
+template <class R>
+__device__ __forceinline__ int advq(R f, R d, R &g) {
+  g = f + d;
+  int s = 0;
+  if (g >= R(1)) {
+    g = g - R(1);
+    s = 1;
+  } else if (g < R(0)) {
+    g = g + R(1);
+    s = -1;
+    if (g >= R(1)) {
+      g = R(0);
+      s = 0;
+    }
+  }
+  return s;
+}
+
 template <class R>
 __device__ __forceinline__ void borisq(R qmhdt, const R E[3], const R B[3], R u[3]) {
   const R e0 = qmhdt * E[0], e1 = qmhdt * E[1], e2 = qmhdt * E[2];
@@ -311,14 +349,17 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
   const PartsQ<R> P = r.pt;
   const int n1 = r.n1, M = r.M;
   const long long plane = r.plane;
-  const int cz = G(P.cell)[p];
-  const R fz = G(P.fz)[p], x = G(P.x)[p], y = G(P.y)[p];
+  const int cz = G(P.cell)[p], ix = G(P.ix)[p], iy = G(P.iy)[p];
+  const R fz = G(P.fz)[p], fx = G(P.fx)[p], fy = G(P.fy)[p];
   R u[3] = {G(P.uz)[p], G(P.ux)[p], G(P.uy)[p]};
   const R qw = G(P.qw)[p];
-  const R rad = sqrt(x * x + y * y);
-  const R rho = rad * r.idr;
-  const R ct = rad > R(0) ? x / rad : R(1), st = rad > R(0) ? y / rad : R(0);
-  const int mri = ifloorq<R>(rho + R(0.5));  // nearest integer-r node
+  // nearest integer-r node mri with offset dri, nearest half-r node (j + 1/2)
+  // mrh with offset drh, direction (ct, st)
+  int mri;
+  R dri, ct, st;
+  radial<R>(ix, fx, iy, fy, mri, dri, ct, st);
+  const int mrh = dri >= R(0) ? mri : mri - 1;
+  const R drh = dri >= R(0) ? dri - R(0.5) : dri + R(0.5);
   // ---- the wave's deposit box (relative z columns, absolute rows)
   const int NS = 3 * (2 * M - 1);  // accumulator slots per node
   const int cz0 = __shfl(cz, 0);
@@ -354,9 +395,8 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
     ozi[a] = wrap_pow2(cz + upz - 1 + a, n1);
     ozh[a] = wrap_pow2(cz - 1 + a, n1);
   }
-  splineq<R>(rho - R(mri), wri);
-  const int mrh = ifloorq<R>(rho);  // nearest half-r node (j + 1/2)
-  splineq<R>(rho - R(0.5) - R(mrh), wrh);
+  splineq<R>(dri, wri);
+  splineq<R>(drh, wrh);
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
     const int ji = mri - 1 + b, jh = mrh - 1 + b;
@@ -387,35 +427,36 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
     v[1] = u[1] * ig;
     v[2] = u[2] * ig;
   }
-  const R mz = r.dtdz * v[0];
-  const R xb = x + r.dtr * v[1], yb = y + r.dtr * v[2];
-  const R radb = sqrt(xb * xb + yb * yb);
-  const R rhob = radb * r.idr;
+  // moves in cells
+  const R mz = r.dtdz * v[0], mx = r.dtdr * v[1], my = r.dtdr * v[2];
   bool ok = active;
-  if (ok && !(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(mz) && isfinite(xb) &&
-              isfinite(yb))) {
+  if (ok && !(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(mz) && isfinite(mx) &&
+              isfinite(my))) {
     atomicOr(err, ERR_NUMERIC);
     ok = false;
   }
-  if (ok && (!(fabs(mz) < R(1)) || !(rhob < r.rmax) || !(fabs(rhob - rho) < R(1)))) {
-    atomicOr(err, ERR_RANGE);
-    ok = false;
-  }
+  R gz = fz, gx = fx, gy = fy;
+  int dz = 0, dx = 0, dy = 0, mrb = mri;
+  R drb = dri, ctb = ct, stb = st;
   if (ok) {
-    // new z cell and offset
-    R gz = fz + mz;
-    int dz = 0;
-    if (gz >= R(1)) {
-      gz = gz - R(1);
-      dz = 1;
-    } else if (gz < R(0)) {
-      gz = gz + R(1);
-      dz = -1;
-      if (gz >= R(1)) {
-        gz = R(0);
-        dz = 0;
+    if (!(fabs(mz) < R(1)) || !(fabs(mx) < R(1)) || !(fabs(my) < R(1))) {
+      atomicOr(err, ERR_RANGE);
+      ok = false;
+    } else {
+      dz = advq<R>(fz, mz, gz);
+      dx = advq<R>(fx, mx, gx);
+      dy = advq<R>(fy, my, gy);
+      radial<R>(ix + dx, gx, iy + dy, gy, mrb, drb, ctb, stb);
+      // within the wall margin, and less than a cell in r (the deposit window
+      // and the wave's box assume it)
+      const R dmove = R(mrb - mri) + (drb - dri);
+      if (!(R(mrb) + drb < r.rmax) || !(fabs(dmove) < R(1)) || abs(mrb - mri) > 1) {
+        atomicOr(err, ERR_RANGE);
+        ok = false;
       }
     }
+  }
+  if (ok) {
     // ---- deposit: 4-node windows along z and r holding both stencils
     R S0z[4], S1z[4], S0r[4], S1r[4];
     int bz, br;
@@ -426,8 +467,9 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
       bz = min(na, nb) - 1;
       place4<R>(sa, na - 1 - bz, S0z);
       place4<R>(sb, nb - 1 - bz, S1z);
-      const int ra = rshape<R>(rho, sa);
-      const int rb = rshape<R>(rhob, sb);
+      const int ra = mri, rb = mrb;
+      splineq<R>(dri, sa);
+      splineq<R>(drb, sb);
       br = min(ra, rb) - 1;
       place4<R>(sa, ra - 1 - br, S0r);
       place4<R>(sb, rb - 1 - br, S1r);
@@ -449,11 +491,11 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
     int col[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) col[a] = wrap_pow2(bz + a, n1);
-    // azimuthal velocity at the mid point times dt
-    const R xm = R(0.5) * (x + xb), ym = R(0.5) * (y + yb);
-    const R rm = sqrt(xm * xm + ym * ym);
-    const R vthdt = rm > R(0) ? (xm * (yb - y) - ym * (xb - x)) / rm : R(0);
-    const R ctb = radb > R(0) ? xb / radb : R(1), stb = radb > R(0) ? yb / radb : R(0);
+    // azimuthal velocity at the mid point times dt: the move (mx, my) dr
+    // projected on the azimuthal direction of the mid point
+    const R xmid = R(ix) + fx + R(0.5) * mx, ymid = R(iy) + fy + R(0.5) * my;
+    const R rmid = sqrt(xmid * xmid + ymid * ymid);
+    const R vthdt = rmid > R(0) ? (xmid * my - ymid * mx) / rmid * (R)r.dr : R(0);
     const R g = qw * r.wscale;
     if (use_lds) {
       SinkLdsQ<A> K{(lptr<A>)smem_raw + (threadIdx.x >> 6) * WAVE_CAP, H, W, rlo, bzrel, 2 * M - 1};
@@ -473,8 +515,10 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
     }
     G(P.cell)[p] = wrap_pow2(cz + dz, n1);
     G(P.fz)[p] = gz;
-    G(P.x)[p] = xb;
-    G(P.y)[p] = yb;
+    G(P.ix)[p] = ix + dx;
+    G(P.fx)[p] = gx;
+    G(P.iy)[p] = iy + dy;
+    G(P.fy)[p] = gy;
     G(P.uz)[p] = u[0];
     G(P.ux)[p] = u[1];
     G(P.uy)[p] = u[2];
@@ -505,10 +549,12 @@ __global__ void __launch_bounds__(256) k_q_rho(const RunQ<R> *__restrict__ run, 
   if (p >= r.np) return;
   const PartsQ<R> P = r.pt;
   const int n1 = r.n1;
-  const double x = G(P.x)[p], y = G(P.y)[p], f = G(P.fz)[p], qw = G(P.qw)[p];
+  const double f = G(P.fz)[p], qw = G(P.qw)[p];
+  const double x = (double)G(P.ix)[p] + (double)G(P.fx)[p];
+  const double y = (double)G(P.iy)[p] + (double)G(P.fy)[p];
   const int cz = G(P.cell)[p];
-  const double rad = sqrt(x * x + y * y), rr = rad / r.dr;
-  const double ct = rad > 0 ? x / rad : 1.0, st = rad > 0 ? y / rad : 0.0;
+  const double rr = sqrt(x * x + y * y);  // r / dr
+  const double ct = rr > 0 ? x / rr : 1.0, st = rr > 0 ? y / rr : 0.0;
   double wz[3], wr[3];
   const int nz = zshape<double>(cz, f, wz);
   const int nr0 = rshape<double>(rr, wr);
@@ -547,10 +593,12 @@ __global__ void __launch_bounds__(256) k_q_jbg(const RunQ<R> *__restrict__ run, 
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= r.np) return;
   const PartsQ<R> P = r.pt;
-  const double x = G(P.x)[p], y = G(P.y)[p], qw = G(P.qw)[p];
+  const double qw = G(P.qw)[p];
+  const double x = (double)G(P.ix)[p] + (double)G(P.fx)[p];
+  const double y = (double)G(P.iy)[p] + (double)G(P.fy)[p];
   const double uz = G(P.uz)[p], ux = G(P.ux)[p], uy = G(P.uy)[p];
   const double vz = uz / sqrt(1.0 + uz * uz + ux * ux + uy * uy);
-  const double rr = sqrt(x * x + y * y) / r.dr;
+  const double rr = sqrt(x * x + y * y);  // r / dr
   double wr[3];
   const int n0 = rshape<double>(rr, wr);
   const double PI_ = 3.14159265358979323846;

@@ -1473,7 +1473,7 @@ class SimQ : public SimBase {
     int jitem0 = 0;  // first (3 m + c, row) item of the run
     double qm = -1.0, q = -1.0;
     double2 *rho_bg = nullptr;  // [M][nr][n1] background charge density, or NULL
-    void *pbuf[9] = {nullptr};  // particle arrays
+    void *pbuf[11] = {nullptr};  // particle arrays
   };
 
  public:
@@ -1567,9 +1567,8 @@ class SimQ : public SimBase {
       d.kfac = dkfac;
       d.jconv = djconv;
       d.jbgk = djbg;
-      d.dtr = (R)c.dt;
       d.dtdz = (R)(c.dt / c.dx[0]);
-      d.idr = (R)(1.0 / c.dx[1]);
+      d.dtdr = (R)(c.dt / c.dx[1]);
       d.rmax = (R)(d.n2 - 3);
       d.wscale = 1;
       h.jitem0 = (int)jitems.size();
@@ -1674,8 +1673,17 @@ class SimQ : public SimBase {
     int rc;
     if ((rc = sync())) return rc;
     const double L = d.n1 * d.dz, rlim = (d.n2 - 3) * d.dr;
-    std::vector<int> cell(n), id(n);
-    std::vector<R> fz(n), px(n), py(n), uz(n), ux(n), uy(n), qw(n);
+    std::vector<int> cell(n), cx(n), cy(n), id(n);
+    std::vector<R> fz(n), fx(n), fy(n), uz(n), ux(n), uy(n), qw(n);
+    // coordinate in cells -> cell index + offset in [0, 1)
+    auto split = [](double v, int &c, R &f) {
+      c = (int)std::floor(v);
+      f = (R)(v - c);
+      if (f >= R(1)) {
+        f = 0;
+        c += 1;
+      }
+    };
     double wmax = 0;
     for (int64_t p = 0; p < n; ++p) {
       const double z = x[p], xx = x[n + p], yy = x[2 * n + p];
@@ -1686,17 +1694,11 @@ class SimQ : public SimBase {
         return fail(HP_EINVAL, "particle %lld at r >= (n2 - 3) dr", (long long)p);
       double zc = std::fmod(z, L);
       if (zc < 0) zc += L;
-      zc /= d.dz;
-      int c = (int)std::floor(zc);
-      R f = (R)(zc - c);
-      if (f >= R(1)) {
-        f = 0;
-        c += 1;
-      }
+      int c;
+      split(zc / d.dz, c, fz[p]);
       cell[p] = c & (d.n1 - 1);
-      fz[p] = f;
-      px[p] = (R)xx;
-      py[p] = (R)yy;
+      split(xx / d.dr, cx[p], fx[p]);
+      split(yy / d.dr, cy[p], fy[p]);
       uz[p] = (R)u[p];
       ux[p] = (R)u[n + p];
       uy[p] = (R)u[2 * n + p];
@@ -1709,17 +1711,20 @@ class SimQ : public SimBase {
       b = nullptr;
     }
     PartsQ<R> &P = d.pt;
-    if ((rc = alloc(&P.cell, n)) || (rc = alloc(&P.fz, n)) || (rc = alloc(&P.x, n)) ||
-        (rc = alloc(&P.y, n)) || (rc = alloc(&P.uz, n)) || (rc = alloc(&P.ux, n)) ||
-        (rc = alloc(&P.uy, n)) || (rc = alloc(&P.qw, n)) || (rc = alloc(&P.id, n)))
+    if ((rc = alloc(&P.cell, n)) || (rc = alloc(&P.fz, n)) || (rc = alloc(&P.ix, n)) ||
+        (rc = alloc(&P.fx, n)) || (rc = alloc(&P.iy, n)) || (rc = alloc(&P.fy, n)) ||
+        (rc = alloc(&P.uz, n)) || (rc = alloc(&P.ux, n)) || (rc = alloc(&P.uy, n)) ||
+        (rc = alloc(&P.qw, n)) || (rc = alloc(&P.id, n)))
       return rc;
-    void *bufs[9] = {P.cell, P.fz, P.x, P.y, P.uz, P.ux, P.uy, P.qw, P.id};
-    for (int k = 0; k < 9; ++k) h.pbuf[k] = bufs[k];
+    void *bufs[11] = {P.cell, P.fz, P.ix, P.fx, P.iy, P.fy, P.uz, P.ux, P.uy, P.qw, P.id};
+    for (int k = 0; k < 11; ++k) h.pbuf[k] = bufs[k];
     if (n > 0) {
       HIPCHK(hipMemcpy(P.cell, cell.data(), sizeof(int) * n, hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(P.fz, fz.data(), sizeof(R) * n, hipMemcpyHostToDevice));
-      HIPCHK(hipMemcpy(P.x, px.data(), sizeof(R) * n, hipMemcpyHostToDevice));
-      HIPCHK(hipMemcpy(P.y, py.data(), sizeof(R) * n, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(P.ix, cx.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(P.fx, fx.data(), sizeof(R) * n, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(P.iy, cy.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(P.fy, fy.data(), sizeof(R) * n, hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(P.uz, uz.data(), sizeof(R) * n, hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(P.ux, ux.data(), sizeof(R) * n, hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(P.uy, uy.data(), sizeof(R) * n, hipMemcpyHostToDevice));
@@ -1756,10 +1761,12 @@ class SimQ : public SimBase {
     if (x) {
       HIPCHK(hipMemcpy(a.data(), P.fz, sizeof(R) * n, hipMemcpyDeviceToHost));
       for (int64_t p = 0; p < n; ++p) x[p] = (cell[p] + (double)a[p]) * d.dz;
-      HIPCHK(hipMemcpy(a.data(), P.x, sizeof(R) * n, hipMemcpyDeviceToHost));
-      for (int64_t p = 0; p < n; ++p) x[n + p] = a[p];
-      HIPCHK(hipMemcpy(a.data(), P.y, sizeof(R) * n, hipMemcpyDeviceToHost));
-      for (int64_t p = 0; p < n; ++p) x[2 * n + p] = a[p];
+      HIPCHK(hipMemcpy(cell.data(), P.ix, sizeof(int) * n, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(a.data(), P.fx, sizeof(R) * n, hipMemcpyDeviceToHost));
+      for (int64_t p = 0; p < n; ++p) x[n + p] = (cell[p] + (double)a[p]) * d.dr;
+      HIPCHK(hipMemcpy(cell.data(), P.iy, sizeof(int) * n, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(a.data(), P.fy, sizeof(R) * n, hipMemcpyDeviceToHost));
+      for (int64_t p = 0; p < n; ++p) x[2 * n + p] = (cell[p] + (double)a[p]) * d.dr;
     }
     if (u) {
       R *src[3] = {P.uz, P.ux, P.uy};
