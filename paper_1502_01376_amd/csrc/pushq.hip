@@ -29,7 +29,7 @@
 // atomics if its particles spread too far), then adds the box to the global
 // accumulators.  FP32 form: 64-bit integers of the rounded FP32 contributions,
 // so the sums do not depend on the order.
-#include "hpic_internal.h"
+#include "hpic_q3d.h"
 
 namespace hp {
 

@@ -16,7 +16,7 @@
 #include <vector>
 
 #include "hpic.h"
-#include "hpic_internal.h"
+#include "hpic_q3d.h"
 
 using namespace hp;
 

@@ -12,7 +12,7 @@
 // axis rules: m = 0: Eth = Br = 0 on the axis, (curl B)_z = 4 Bth(dr/2)/dr;
 // m = 1: Ez = 0 on the axis, (i m/r) Ez -> i Ez(dr)/dr, d_r Bz -> 2 Bz(dr/2)/dr;
 // m >= 2: zero on the axis.  Wall: Ez = Eth = 0, Br stays zero.
-#include "hpic_internal.h"
+#include "hpic_q3d.h"
 
 namespace hp {
 
