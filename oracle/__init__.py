@@ -31,7 +31,7 @@ class Grid2(ctypes.Structure):
         ("dx1", ctypes.c_double), ("dx2", ctypes.c_double), ("dt", ctypes.c_double),
         ("alpha", ctypes.c_double),
         ("deriv1", ctypes.c_int32), ("correct", ctypes.c_int32),
-        ("jbg", ctypes.c_double * 3), ("kmod", ctypes.c_int32),
+        ("jbg", ctypes.c_double * 3), ("kmod", ctypes.c_int32), ("interp", ctypes.c_int32),
     ]
 
 
@@ -43,7 +43,7 @@ class Grid3(ctypes.Structure):
         ("dx1", ctypes.c_double), ("dx2", ctypes.c_double), ("dx3", ctypes.c_double),
         ("dt", ctypes.c_double), ("alpha", ctypes.c_double),
         ("deriv1", ctypes.c_int32), ("correct", ctypes.c_int32),
-        ("jbg", ctypes.c_double * 3), ("kmod", ctypes.c_int32),
+        ("jbg", ctypes.c_double * 3), ("kmod", ctypes.c_int32), ("interp", ctypes.c_int32),
     ]
 
 
@@ -54,7 +54,7 @@ class GridQ(ctypes.Structure):
         ("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("nmodes", ctypes.c_int32),
         ("dz", ctypes.c_double), ("dr", ctypes.c_double), ("dt", ctypes.c_double),
         ("alpha", ctypes.c_double), ("deriv1", ctypes.c_int32), ("correct", ctypes.c_int32),
-        ("kmod", ctypes.c_int32),
+        ("kmod", ctypes.c_int32), ("interp", ctypes.c_int32),
     ]
 
 
@@ -124,9 +124,11 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def grid2(n1, n2, dx1, dx2, dt, alpha=1.0, deriv1=0, correct=1, jbg=(0.0, 0.0, 0.0), kmod=0):
+def grid2(n1, n2, dx1, dx2, dt, alpha=1.0, deriv1=0, correct=1, jbg=(0.0, 0.0, 0.0), kmod=0,
+          interp=0):
     g = Grid2()
     g.kmod = int(kmod)
+    g.interp = int(interp)
     g.n1, g.n2 = int(n1), int(n2)
     g.dx1, g.dx2, g.dt = float(dx1), float(dx2), float(dt)
     g.alpha = float(alpha)
@@ -292,8 +294,9 @@ def courant_limit2(dx1, dx2):
 
 # ------------------------------------------------------------------------ 3D
 def grid3(n1, n2, n3, dx1, dx2, dx3, dt, alpha=1.0, deriv1=0, correct=1, jbg=(0.0, 0.0, 0.0),
-          kmod=0):
+          kmod=0, interp=0):
     g = Grid3()
+    g.interp = int(interp)
     g.kmod = int(kmod)
     g.n1, g.n2, g.n3 = int(n1), int(n2), int(n3)
     g.dx1, g.dx2, g.dx3, g.dt = float(dx1), float(dx2), float(dx3), float(dt)
@@ -411,12 +414,13 @@ def courant_limit3(dx1, dx2, dx3):
 
 
 # ------------------------------------------------------------------ quasi-3D
-def gridq(n1, n2, nmodes, dz, dr, dt, alpha=1.0, deriv1=0, correct=1, kmod=0):
+def gridq(n1, n2, nmodes, dz, dr, dt, alpha=1.0, deriv1=0, correct=1, kmod=0, interp=0):
     g = GridQ()
     g.n1, g.n2, g.nmodes = int(n1), int(n2), int(nmodes)
     g.dz, g.dr, g.dt = float(dz), float(dr), float(dt)
     g.alpha = float(alpha)
     g.deriv1, g.correct, g.kmod = int(deriv1), int(correct), int(kmod)
+    g.interp = int(interp)
     return g
 
 

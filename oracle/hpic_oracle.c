@@ -136,6 +136,21 @@ static double spline2(double delta) {
   return 0.0;
 }
 
+/* Linear (first-order) B-spline: weight of a node at signed distance delta. */
+static double spline1(double delta) {
+  double a = fabs(delta);
+  return a < 1.0 ? 1.0 - a : 0.0;
+}
+
+/* Weight of a node along one direction for a component with staggering s
+ * (0 or 1/2 cell) there: the quadratic spline, except that the energy-
+ * conserving variant (Appendix A, second variant) lowers the order by one
+ * along the staggered directions, which makes the work of the gathered field
+ * on a particle equal to J.E of its Esirkepov current. */
+static double gather_w(int interp, double s, double delta) {
+  return (interp == 1 && s > 0.0) ? spline1(delta) : spline2(delta);
+}
+
 /* Staggering offsets (in cells) of E1..E3 and B1..B3 along x1 and x2, from the
  * index subscripts of Eqs. (1)-(6). */
 static const double STAG_E[3][2] = {{0.5, 0.0}, {0.0, 0.5}, {0.0, 0.0}};
@@ -148,9 +163,9 @@ static double interp2(const or_grid2 *g, const double *F, double s1, double s2, 
   int64_t m1 = (int64_t)floor(e1 + 0.5), m2 = (int64_t)floor(e2 + 0.5);
   double acc = 0.0;
   for (int64_t b = m2 - 1; b <= m2 + 1; ++b) {
-    double w2 = spline2(e2 - (double)b);
+    double w2 = gather_w(g->interp, s2, e2 - (double)b);
     for (int64_t a = m1 - 1; a <= m1 + 1; ++a) {
-      double w1 = spline2(e1 - (double)a);
+      double w1 = gather_w(g->interp, s1, e1 - (double)a);
       acc += w1 * w2 * F[(int64_t)wrapi(b, g->n2) * g->n1 + wrapi(a, g->n1)];
     }
   }
@@ -625,11 +640,11 @@ static double interp3(const or_grid3 *g, const double *F, const double s[3], dou
   int64_t m1 = (int64_t)floor(e1 + 0.5), m2 = (int64_t)floor(e2 + 0.5), m3 = (int64_t)floor(e3 + 0.5);
   double acc = 0.0;
   for (int64_t c = m3 - 1; c <= m3 + 1; ++c) {
-    double w3 = spline2(e3 - (double)c);
+    double w3 = gather_w(g->interp, s[2], e3 - (double)c);
     for (int64_t b = m2 - 1; b <= m2 + 1; ++b) {
-      double w2 = spline2(e2 - (double)b);
+      double w2 = gather_w(g->interp, s[1], e2 - (double)b);
       for (int64_t a = m1 - 1; a <= m1 + 1; ++a)
-        acc += spline2(e1 - (double)a) * w2 * w3 * F[idx3(g, a, b, c)];
+        acc += gather_w(g->interp, s[0], e1 - (double)a) * w2 * w3 * F[idx3(g, a, b, c)];
     }
   }
   return acc;
@@ -1320,9 +1335,10 @@ static double q_interp(const or_gridq *g, const double complex *F, int c, const 
     const double complex *Fc = F + ((int64_t)m * 3 + c) * plane;
     double complex v = 0.0;
     for (int64_t b = m2 - 1; b <= m2 + 1; ++b) {
-      double w2 = spline2(e2 - (double)b);
+      double w2 = gather_w(g->interp, s[1], e2 - (double)b);
       for (int64_t a = m1 - 1; a <= m1 + 1; ++a)
-        v += spline2(e1 - (double)a) * w2 * q_node(g, Fc, s[1] > 0.0, c != 0, m, a, b);
+        v += gather_w(g->interp, s[0], e1 - (double)a) * w2 *
+             q_node(g, Fc, s[1] > 0.0, c != 0, m, a, b);
     }
     acc += creal(v * conj(q_phase(x, y, m)));
   }

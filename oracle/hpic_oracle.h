@@ -49,6 +49,8 @@ typedef struct or_grid2 {
   int32_t correct;
   double jbg[3];
   int32_t kmod;  /* 1: [k]1 = k1 + dk_mod(k1) of Eq. (29), Table 1 coefficients */
+  int32_t interp; /* 0: momentum-conserving gather; 1: energy-conserving (linear
+                     weights along each staggered direction, Appendix A) */
 } or_grid2;
 
 /* Complex FFT of length n (power of two), in place.  sign = -1 computes
@@ -135,6 +137,7 @@ typedef struct or_grid3 {
   int32_t correct;
   double jbg[3];
   int32_t kmod;
+  int32_t interp; /* as in or_grid2 */
 } or_grid3;
 
 void or_gather3(const or_grid3 *g, const double *E, const double *B, int64_t np,
@@ -170,6 +173,7 @@ typedef struct or_gridq {
   int32_t deriv1;
   int32_t correct;
   int32_t kmod;
+  int32_t interp; /* as in or_grid2 */
 } or_gridq;
 
 int or_field_update_q(const or_gridq *g, double *E, double *B, const double *J);
