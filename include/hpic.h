@@ -86,7 +86,12 @@ typedef struct hp_config {
   double dx[3];              /* cell sizes */
   double dt;                 /* time step */
   int32_t shape_order;       /* particle shape order, 2 (quadratic) */
-  int32_t interp;            /* 0: momentum-conserving gather (Appendix A) */
+  int32_t interp;            /* 0: momentum-conserving gather (Appendix A, first
+                                variant: the quadratic spline at every component's
+                                node); 1: energy-conserving (second variant: linear
+                                weights along the component's staggered directions,
+                                so that J.E of the Esirkepov current is the work on
+                                the particle) */
   double filter_frac;        /* low-pass cutoff alpha: keep |k1| <= alpha pi/dx1
                                 (Sec. 4); >= 1 disables */
   int32_t deriv1;            /* 0: spectral k1 (Eq. (20)); 1: FD [k]1 (Eq. (28)) */

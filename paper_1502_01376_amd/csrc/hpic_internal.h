@@ -54,6 +54,8 @@ struct Run {
   using C = typename Cplx<R>::T;
   using Acc = typename AccOf<R>::T;
   int dim;           // 2 or 3
+  int interp;        // 0 momentum-conserving gather, 1 energy-conserving (3D
+                     // kernel; the 2D kernel takes it as a template argument)
   int n1, n2, n3, log2n1, nk;
   int sh3;           // 3D: shift of i3 in the packed cell index
   int rows;          // n2 * n3: rows of the x1 transforms
@@ -192,6 +194,21 @@ template <class R> __device__ __forceinline__ void spline3(R d, R w[3]) {
   w[1] = R(0.75) - d * d;
   w[2] = R(0.5) * b * b;
 }
+// Linear B-spline on the same three nodes (energy-conserving gather along a
+// staggered direction): for d in [-1/2, 1/2) the weights of m-1, m, m+1.
+template <class R> __device__ __forceinline__ void line3(R d, R w[3]) {
+  w[0] = d < R(0) ? -d : R(0);
+  w[1] = R(1) - (d < R(0) ? -d : d);
+  w[2] = d > R(0) ? d : R(0);
+}
+// Weights of a half-node (staggered) stencil: quadratic, or linear for the
+// energy-conserving gather.
+template <class R> __device__ __forceinline__ void half3(R d, R w[3], bool ec) {
+  if (ec)
+    line3<R>(d, w);
+  else
+    spline3<R>(d, w);
+}
 
 // Quantised quadratic shape of one coordinate (cell + FP32 offset): integers
 // s[0..2] of the nodes m-1, m, m+1 with exact sum 2^P; returns m.  The same
@@ -256,10 +273,11 @@ constexpr int PUSH_LDS_MAX = 64512;  // with the static LDS, under 64 KiB
 // Host-side launch wrappers (kernels.hip), one instantiation per precision.
 template <class R>
 struct Launch {
-  // unit: every run's charges satisfy the 24-bit product bound (FP32 form)
+  // unit: every run's charges satisfy the 24-bit product bound (FP32 form);
+  // ec: energy-conserving gather (all runs of a handle share it)
   static void push_deposit(const Run<R> *runs, const Item *items, int nitems, int parity,
-                           int pp, int lds_bytes, bool unit, unsigned *err, unsigned *stats,
-                           hipStream_t s);
+                           int pp, int lds_bytes, bool unit, bool ec, unsigned *err,
+                           unsigned *stats, hipStream_t s);
   // tile sort of the particles of all runs: items are (run, first particle,
   // count) chunks; per_run lists (run, 0, 0) once per run.  scramble = true
   // spreads the particles of one cell over a tile's slots (for input in cell

@@ -33,6 +33,7 @@ struct RunQ {
   using C = typename Cplx<R>::T;
   using A = typename AccQ<R>::T;
   int n1, n2, nr, M, log2n1;
+  int interp;        // 0 momentum-conserving gather, 1 energy-conserving
   long long plane;   // nr * n1
   double dz, dr, dt, hdt;
   double2 *Fk[2];    // [M][6][nr][n1] k-space master (FP64), ping-pong by step parity

@@ -60,17 +60,18 @@ struct LdsFields {
   __device__ R b3(int r, int c) const { return B3[r + c]; }
 };
 
-// Momentum-conserving quadratic gather (Appendix A, first variant): every
-// component uses the quadratic B-spline around its own staggered node.
+// Quadratic gather (Appendix A): momentum-conserving (every component uses the
+// quadratic B-spline around its own staggered node) or, with ec, energy-
+// conserving (linear weights along the component's staggered directions).
 template <class R, class Src>
 __device__ __forceinline__ void gather2(const Src &S, int i1, int i2, R f1, R f2, R Ef[3],
-                                        R Bf[3]) {
+                                        R Bf[3], bool ec) {
   const int up1 = f1 >= R(0.5), up2 = f2 >= R(0.5);
   R wi1[3], wh1[3], wi2[3], wh2[3];
-  spline3<R>(f1 - R(up1), wi1);  // integer nodes along x1
-  spline3<R>(f1 - R(0.5), wh1);  // half nodes along x1
+  spline3<R>(f1 - R(up1), wi1);   // integer nodes along x1
+  half3<R>(f1 - R(0.5), wh1, ec);  // half nodes along x1
   spline3<R>(f2 - R(up2), wi2);
-  spline3<R>(f2 - R(0.5), wh2);
+  half3<R>(f2 - R(0.5), wh2, ec);
   int ci[3], ch[3], ri[3], rh[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -423,13 +424,13 @@ __device__ __forceinline__ PState<R> load_state(const Parts<R> &P, int p) {
 // same frame, store.  (gi1, gi2) is the global cell.  Returns the global cell
 // after the step (unchanged if the particle was rejected: a non-finite or a
 // too-long move leaves it as it was and sets the error word).
-template <class R, bool UNIT, class Src, class Sink>
+template <class R, bool UNIT, bool EC, class Src, class Sink>
 __device__ __forceinline__ int push_one(const Run<R> &r, const Parts<R> &P, int p,
                                         const PState<R> &s, int gi1, int gi2, int li1, int li2,
                                         const Src &S, const Sink &K, unsigned *err) {
   R u[3] = {s.u1, s.u2, s.u3};
   R Ef[3], Bf[3];
-  gather2<R>(S, li1, li2, s.f1, s.f2, Ef, Bf);
+  gather2<R>(S, li1, li2, s.f1, s.f2, Ef, Bf, EC);
   boris<R>(r.qmhdt, Ef, Bf, u);
   R v[3];
   velocity<R>(u, v);
@@ -476,7 +477,7 @@ __device__ __forceinline__ int wave_max(int v) {
 // One workgroup per (run, tile).  The tile's bounding box (from the previous
 // push, or the tile itself right after a sort) sizes the LDS staging; the new
 // box of the pushed particles is written back for the next step.
-template <class R, bool UNIT>
+template <class R, bool UNIT, bool EC>
 __global__ void __launch_bounds__(PUSH_THREADS)
 k_push_deposit(const Run<R> *__restrict__ runs, const Item *__restrict__ items, int parity, int pp,
                int lds_bytes, unsigned *err, unsigned *stats) {
@@ -520,7 +521,7 @@ k_push_deposit(const Run<R> *__restrict__ runs, const Item *__restrict__ items, 
     for (int p = start + threadIdx.x; p < end; p += PUSH_THREADS) {
       const PState<R> s = load_state(P, p);
       const int i1 = s.cell & (n1 - 1), i2 = s.cell >> r.log2n1;
-      track(push_one<R, UNIT>(r, P, p, s, i1, i2, i1, i2, S, K, err));
+      track(push_one<R, UNIT, EC>(r, P, p, s, i1, i2, i1, i2, S, K, err));
     }
   } else {
     // LDS layout: current accumulators first, then the fields (16-byte aligned)
@@ -567,7 +568,7 @@ k_push_deposit(const Run<R> *__restrict__ runs, const Item *__restrict__ items, 
         if (p < end) {
           const int i1 = st[k].cell & (n1 - 1), i2 = st[k].cell >> r.log2n1;
           const int d1 = wrap_delta_pow2(i1 - ref1, n1), d2 = wrap_delta(i2 - ref2, n2);
-          track(push_one<R, UNIT>(r, P, p, st[k], i1, i2, d1 - lo1 + 1, d2 - lo2 + 1, S, K, err));
+          track(push_one<R, UNIT, EC>(r, P, p, st[k], i1, i2, d1 - lo1 + 1, d2 - lo2 + 1, S, K, err));
         }
       }
     }
@@ -818,18 +819,26 @@ __global__ void k_kinetic(const Run<R> *run, int pp, double *partial) {
 // ---------------------------------------------------------------- launches
 template <class R>
 void Launch<R>::push_deposit(const Run<R> *runs, const Item *items, int nitems, int parity, int pp,
-                             int lds_bytes, bool unit, unsigned *err, unsigned *stats,
+                             int lds_bytes, bool unit, bool ec, unsigned *err, unsigned *stats,
                              hipStream_t s) {
   if (nitems <= 0) return;
   if constexpr (std::is_same<R, float>::value) {
     if (unit) {
-      hipLaunchKernelGGL((k_push_deposit<R, true>), dim3(nitems), dim3(PUSH_THREADS), lds_bytes, s,
-                         runs, items, parity, pp, lds_bytes, err, stats);
+      if (ec)
+        hipLaunchKernelGGL((k_push_deposit<R, true, true>), dim3(nitems), dim3(PUSH_THREADS),
+                           lds_bytes, s, runs, items, parity, pp, lds_bytes, err, stats);
+      else
+        hipLaunchKernelGGL((k_push_deposit<R, true, false>), dim3(nitems), dim3(PUSH_THREADS),
+                           lds_bytes, s, runs, items, parity, pp, lds_bytes, err, stats);
       return;
     }
   }
-  hipLaunchKernelGGL((k_push_deposit<R, false>), dim3(nitems), dim3(PUSH_THREADS), lds_bytes, s,
-                     runs, items, parity, pp, lds_bytes, err, stats);
+  if (ec)
+    hipLaunchKernelGGL((k_push_deposit<R, false, true>), dim3(nitems), dim3(PUSH_THREADS),
+                       lds_bytes, s, runs, items, parity, pp, lds_bytes, err, stats);
+  else
+    hipLaunchKernelGGL((k_push_deposit<R, false, false>), dim3(nitems), dim3(PUSH_THREADS),
+                       lds_bytes, s, runs, items, parity, pp, lds_bytes, err, stats);
 }
 
 template <class R>

@@ -326,7 +326,7 @@ __device__ __forceinline__ int push_one3(const Run<R> &r, const Parts<R> &P, int
   for (int d = 0; d < 3; ++d) {
     const int up = f[d] >= R(0.5);
     spline3<R>(f[d] - R(up), wi[d]);
-    spline3<R>(f[d] - R(0.5), wh[d]);
+    half3<R>(f[d] - R(0.5), wh[d], r.interp != 0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int ni = gc[d] + up - 1 + a, nh = gc[d] - 1 + a;

@@ -389,14 +389,14 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
   int ozi[3], ozh[3], rri[3], rrh[3];
   const int upz = fz >= R(0.5);
   splineq<R>(fz - R(upz), wzi);
-  splineq<R>(fz - R(0.5), wzh);
+  half3<R>(fz - R(0.5), wzh, r.interp != 0);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     ozi[a] = wrap_pow2(cz + upz - 1 + a, n1);
     ozh[a] = wrap_pow2(cz - 1 + a, n1);
   }
   splineq<R>(dri, wri);
-  splineq<R>(drh, wrh);
+  half3<R>(drh, wrh, r.interp != 0);
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
     const int ji = mri - 1 + b, jh = mrh - 1 + b;

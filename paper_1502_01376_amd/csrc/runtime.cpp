@@ -191,6 +191,7 @@ class Sim : public SimBase {
       d.n1 = c.n[0];
       d.n2 = c.n[1];
       d.dim = c.geom == HP_GEOM_3D ? 3 : 2;
+      d.interp = c.interp;
       d.n3 = d.dim == 3 ? c.n[2] : 1;
       d.rows = d.n2 * d.n3;
       d.cells = d.n1 * d.rows;
@@ -444,7 +445,8 @@ class Sim : public SimBase {
       Launch<R>::push_deposit3(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, d_err_, d_stats_,
                                stream_);
     else
-      Launch<R>::push_deposit(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, all_unit(), d_err_,
+      Launch<R>::push_deposit(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, all_unit(),
+                              runs_[0].cfg.interp == 1, d_err_,
                               d_stats_, stream_);
     mark(HP_K_PUSH_DEPOSIT, false);
     ++since_sort_;
@@ -1499,6 +1501,7 @@ class SimQ : public SimBase {
       d.n2 = c.n[1];
       d.nr = d.n2 + 1;
       d.M = c.n_modes;
+      d.interp = c.interp;
       d.log2n1 = ilog2(d.n1);
       d.plane = (long long)d.nr * d.n1;
       d.dz = c.dx[0];
@@ -2147,6 +2150,8 @@ int hp_create(const hp_config *cfgs, int32_t nruns, hp_sim **out) {
     if (c.geom == HP_GEOM_Q3D && (c.n_modes < 1 || c.n_modes > 8))
       return fail(HP_EINVAL, "run %d: quasi-3D needs 1..8 azimuthal modes", i);
     if (c.geom != cfgs[0].geom) return fail(HP_EINVAL, "run %d: all runs of a handle share the geometry", i);
+    if (c.interp != cfgs[0].interp)
+      return fail(HP_EINVAL, "run %d: all runs of a handle share the gather variant", i);
     if (c.geom == HP_GEOM_3D) {
       if (c.n[2] < 4 || !(c.dx[2] > 0))
         return fail(HP_EINVAL, "run %d: n3 >= 4 and dx3 > 0 in 3D", i);
@@ -2163,8 +2168,8 @@ int hp_create(const hp_config *cfgs, int32_t nruns, hp_sim **out) {
       return fail(HP_EINVAL, "run %d: n2 = %d out of range", i, c.n[1]);
     if (!(c.dx[0] > 0) || !(c.dx[1] > 0) || !(c.dt > 0) || !std::isfinite(c.dt))
       return fail(HP_EINVAL, "run %d: non-positive cell size or time step", i);
-    if (c.shape_order != 2 || c.interp != 0)
-      return fail(HP_EINVAL, "run %d: quadratic shape with momentum-conserving gather only", i);
+    if (c.shape_order != 2 || (c.interp != 0 && c.interp != 1))
+      return fail(HP_EINVAL, "run %d: quadratic shape; interp 0 (momentum-) or 1 (energy-conserving)", i);
     if (!(c.filter_frac > 0)) return fail(HP_EINVAL, "run %d: filter_frac must be > 0", i);
     if (c.deriv1 != 0 && c.deriv1 != 1) return fail(HP_EINVAL, "run %d: bad deriv1", i);
     if (c.kmod != 0 && c.kmod != 1) return fail(HP_EINVAL, "run %d: bad kmod", i);
