@@ -32,6 +32,7 @@ class Grid2(ctypes.Structure):
         ("alpha", ctypes.c_double),
         ("deriv1", ctypes.c_int32), ("correct", ctypes.c_int32),
         ("jbg", ctypes.c_double * 3), ("kmod", ctypes.c_int32), ("interp", ctypes.c_int32),
+        ("shape", ctypes.c_int32),
     ]
 
 
@@ -125,10 +126,11 @@ def _f64(a):
 
 
 def grid2(n1, n2, dx1, dx2, dt, alpha=1.0, deriv1=0, correct=1, jbg=(0.0, 0.0, 0.0), kmod=0,
-          interp=0):
+          interp=0, shape=2):
     g = Grid2()
     g.kmod = int(kmod)
     g.interp = int(interp)
+    g.shape = int(shape)
     g.n1, g.n2 = int(n1), int(n2)
     g.dx1, g.dx2, g.dt = float(dx1), float(dx2), float(dt)
     g.alpha = float(alpha)

@@ -142,6 +142,22 @@ static double spline1(double delta) {
   return a < 1.0 ? 1.0 - a : 0.0;
 }
 
+/* Cubic B-spline: (4 - 6 a^2 + 3 a^3)/6 for a < 1, (2 - a)^3/6 for 1 <= a < 2. */
+static double spline3c(double delta) {
+  double a = fabs(delta);
+  if (a < 1.0) return (4.0 - 6.0 * a * a + 3.0 * a * a * a) / 6.0;
+  if (a < 2.0) return (2.0 - a) * (2.0 - a) * (2.0 - a) / 6.0;
+  return 0.0;
+}
+
+/* B-spline of order 1, 2 or 3. */
+static double spline_n(int order, double delta) {
+  return order == 3 ? spline3c(delta) : order == 1 ? spline1(delta) : spline2(delta);
+}
+
+/* Shape order of a 2D grid (0 reads as the quadratic default). */
+static int shape2(const or_grid2 *g) { return g->shape == 3 ? 3 : 2; }
+
 /* Weight of a node along one direction for a component with staggering s
  * (0 or 1/2 cell) there: the quadratic spline, except that the energy-
  * conserving variant (Appendix A, second variant) lowers the order by one
@@ -149,6 +165,10 @@ static double spline1(double delta) {
  * on a particle equal to J.E of its Esirkepov current. */
 static double gather_w(int interp, double s, double delta) {
   return (interp == 1 && s > 0.0) ? spline1(delta) : spline2(delta);
+}
+/* The same for a shape of order l (the variant lowers it to l - 1). */
+static double gather_wn(int order, int interp, double s, double delta) {
+  return spline_n((interp == 1 && s > 0.0) ? order - 1 : order, delta);
 }
 
 /* Staggering offsets (in cells) of E1..E3 and B1..B3 along x1 and x2, from the
@@ -160,12 +180,14 @@ static const double STAG_B[3][2] = {{0.0, 0.5}, {0.5, 0.0}, {0.5, 0.5}};
 static double interp2(const or_grid2 *g, const double *F, double s1, double s2, double xi1,
                       double xi2) {
   double e1 = xi1 - s1, e2 = xi2 - s2;
-  int64_t m1 = (int64_t)floor(e1 + 0.5), m2 = (int64_t)floor(e2 + 0.5);
+  int l = shape2(g);
+  /* every node within two cells; the spline is zero beyond its support */
+  int64_t m1 = (int64_t)floor(e1), m2 = (int64_t)floor(e2);
   double acc = 0.0;
-  for (int64_t b = m2 - 1; b <= m2 + 1; ++b) {
-    double w2 = gather_w(g->interp, s2, e2 - (double)b);
-    for (int64_t a = m1 - 1; a <= m1 + 1; ++a) {
-      double w1 = gather_w(g->interp, s1, e1 - (double)a);
+  for (int64_t b = m2 - 2; b <= m2 + 3; ++b) {
+    double w2 = gather_wn(l, g->interp, s2, e2 - (double)b);
+    for (int64_t a = m1 - 2; a <= m1 + 3; ++a) {
+      double w1 = gather_wn(l, g->interp, s1, e1 - (double)a);
       acc += w1 * w2 * F[(int64_t)wrapi(b, g->n2) * g->n1 + wrapi(a, g->n1)];
     }
   }
@@ -218,41 +240,43 @@ int or_deposit2(const or_grid2 *g, int64_t np, const double *xa1, const double *
                 double *J) {
   int64_t cells = (int64_t)g->n1 * g->n2;
   double *J1 = J, *J2 = J + cells, *J3 = J + 2 * cells;
-  int status = 0;
+  int status = 0, l = shape2(g);
   for (int64_t p = 0; p < np; ++p) {
     if (fabs(xb1[p] - xa1[p]) >= 1.0 || fabs(xb2[p] - xa2[p]) >= 1.0) { status = -1; continue; }
-    /* a common 4-node window per coordinate holds the old and new stencils */
-    int64_t b1 = (int64_t)fmin(floor(xa1[p] + 0.5), floor(xb1[p] + 0.5)) - 1;
-    int64_t b2 = (int64_t)fmin(floor(xa2[p] + 0.5), floor(xb2[p] + 0.5)) - 1;
-    double S0x[4], S1x[4], S0y[4], S1y[4];
-    for (int a = 0; a < 4; ++a) {
-      S0x[a] = spline2(xa1[p] - (double)(b1 + a));
-      S1x[a] = spline2(xb1[p] - (double)(b1 + a));
-      S0y[a] = spline2(xa2[p] - (double)(b2 + a));
-      S1y[a] = spline2(xb2[p] - (double)(b2 + a));
+    /* a common window per coordinate holds the old and new stencils: the
+     * nodes within two cells of either position (W = 6 covers the quadratic
+     * and the cubic shape; the spline is zero beyond its support) */
+    int64_t b1 = (int64_t)floor(fmin(xa1[p], xb1[p])) - 2;
+    int64_t b2 = (int64_t)floor(fmin(xa2[p], xb2[p])) - 2;
+    double S0x[6], S1x[6], S0y[6], S1y[6];
+    for (int a = 0; a < 6; ++a) {
+      S0x[a] = spline_n(l, xa1[p] - (double)(b1 + a));
+      S1x[a] = spline_n(l, xb1[p] - (double)(b1 + a));
+      S0y[a] = spline_n(l, xa2[p] - (double)(b2 + a));
+      S1y[a] = spline_n(l, xb2[p] - (double)(b2 + a));
     }
     double f1 = -qw[p] * g->dx1 / g->dt, f2 = -qw[p] * g->dx2 / g->dt;
     /* j1: running sum along x1 of the W1 weights (continuity, Eq. (23)) */
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < 6; ++b) {
       double acc = 0.0;
-      for (int a = 0; a < 4; ++a) {
+      for (int a = 0; a < 6; ++a) {
         double W1 = (S1x[a] - S0x[a]) * 0.5 * (S0y[b] + S1y[b]);
         acc += f1 * W1;
         J1[(int64_t)wrapi(b2 + b, g->n2) * g->n1 + wrapi(b1 + a, g->n1)] += acc;
       }
     }
     /* j2: running sum along x2 of the W2 weights */
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < 6; ++a) {
       double acc = 0.0;
-      for (int b = 0; b < 4; ++b) {
+      for (int b = 0; b < 6; ++b) {
         double W2 = (S1y[b] - S0y[b]) * 0.5 * (S0x[a] + S1x[a]);
         acc += f2 * W2;
         J2[(int64_t)wrapi(b2 + b, g->n2) * g->n1 + wrapi(b1 + a, g->n1)] += acc;
       }
     }
     /* j3: out-of-plane current with the time-averaged shape W3 */
-    for (int b = 0; b < 4; ++b) {
-      for (int a = 0; a < 4; ++a) {
+    for (int b = 0; b < 6; ++b) {
+      for (int a = 0; a < 6; ++a) {
         double W3 = S0x[a] * S0y[b] / 3.0 + S1x[a] * S0y[b] / 6.0 + S0x[a] * S1y[b] / 6.0 +
                     S1x[a] * S1y[b] / 3.0;
         J3[(int64_t)wrapi(b2 + b, g->n2) * g->n1 + wrapi(b1 + a, g->n1)] += qw[p] * v3[p] * W3;
@@ -264,12 +288,13 @@ int or_deposit2(const or_grid2 *g, int64_t np, const double *xa1, const double *
 
 void or_rho2(const or_grid2 *g, int64_t np, const double *xi1, const double *xi2,
              const double *qw, double *rho) {
+  int l = shape2(g);
   for (int64_t p = 0; p < np; ++p) {
-    int64_t m1 = (int64_t)floor(xi1[p] + 0.5), m2 = (int64_t)floor(xi2[p] + 0.5);
-    for (int64_t b = m2 - 1; b <= m2 + 1; ++b)
-      for (int64_t a = m1 - 1; a <= m1 + 1; ++a)
+    int64_t m1 = (int64_t)floor(xi1[p]), m2 = (int64_t)floor(xi2[p]);
+    for (int64_t b = m2 - 2; b <= m2 + 3; ++b)
+      for (int64_t a = m1 - 2; a <= m1 + 3; ++a)
         rho[(int64_t)wrapi(b, g->n2) * g->n1 + wrapi(a, g->n1)] +=
-            qw[p] * spline2(xi1[p] - (double)a) * spline2(xi2[p] - (double)b);
+            qw[p] * spline_n(l, xi1[p] - (double)a) * spline_n(l, xi2[p] - (double)b);
   }
 }
 

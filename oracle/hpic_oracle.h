@@ -51,6 +51,7 @@ typedef struct or_grid2 {
   int32_t kmod;  /* 1: [k]1 = k1 + dk_mod(k1) of Eq. (29), Table 1 coefficients */
   int32_t interp; /* 0: momentum-conserving gather; 1: energy-conserving (linear
                      weights along each staggered direction, Appendix A) */
+  int32_t shape;  /* particle shape order: 2 quadratic (0 reads as 2), 3 cubic */
 } or_grid2;
 
 /* Complex FFT of length n (power of two), in place.  sign = -1 computes
