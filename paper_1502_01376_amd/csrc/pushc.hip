@@ -1,0 +1,393 @@
+// pushc.hip -- 2D push with the cubic particle shape on gfx950: quadratic or
+// cubic B-spline form factors of order l (Appendix A; Sec. 4 uses cubic
+// shapes against the NCI modes the quadratic shape leaves), here l = 3:
+// gather over 4 x 4 nodes (the energy-conserving variant drops to the
+// quadratic shape along a component's staggered directions), relativistic
+// Boris push, and the Esirkepov deposit over a 5 x 5 window.
+//
+// One thread per particle in the particles' current order (the periodic tile
+// sort keeps the 64 particles of a wave within a few cells).  Each wave bounds
+// its deposit footprint before the push (a move is under a cell: columns and
+// rows -2 .. +3 around the particle's cell) and accumulates into its own LDS
+// box, added to the global accumulators afterwards; a wave whose particles
+// spread further deposits with global atomics.  FP32 form: Esirkepov weights
+// in FP32, each node's contribution rounded once to an integer (|v| < 2^31)
+// and accumulated in 64 bits, so the sums do not depend on the order; FP64
+// form: physical current in FP64.
+#include "hpic_internal.h"
+
+namespace hp {
+
+namespace {
+
+constexpr int CLDS_BYTES = 64512;
+constexpr int CWAVE_CAP = CLDS_BYTES / 4 / 8;
+
+template <class T> using lptrc = T __attribute__((address_space(3))) *;
+
+__device__ __forceinline__ int wminc(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wmaxc(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ float rsqrtc(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrtc(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rcpc(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcpc(double x) { return 1.0 / x; }
+
+// Cubic B-spline weights of the nodes m-1, m, m+1, m+2 for a position m + d,
+// d in [0, 1): S3 at the distances 1 + d, d, 1 - d, 2 - d.
+template <class R>
+__device__ __forceinline__ void cubic4(R d, R w[4]) {
+  const R e = R(1) - d;
+  w[0] = e * e * e * R(1.0 / 6.0);
+  w[1] = (R(4) - R(6) * d * d + R(3) * d * d * d) * R(1.0 / 6.0);
+  w[2] = (R(4) - R(6) * e * e + R(3) * e * e * e) * R(1.0 / 6.0);
+  w[3] = d * d * d * R(1.0 / 6.0);
+}
+// Quadratic weights on the same four nodes (m-1 .. m+2) for m + d: the nearest
+// node is m (d < 1/2) or m + 1.
+template <class R>
+__device__ __forceinline__ void quad4(R d, R w[4]) {
+  const bool up = d >= R(0.5);
+  const R q = up ? d - R(1) : d;
+  const R a = R(0.5) - q, b = R(0.5) + q;
+  const R s0 = R(0.5) * a * a, s1 = R(0.75) - q * q, s2 = R(0.5) * b * b;
+  w[0] = up ? R(0) : s0;
+  w[1] = up ? s0 : s1;
+  w[2] = up ? s1 : s2;
+  w[3] = up ? s2 : R(0);
+}
+// Stencil along one axis for a component with staggering h (0 or 1/2 cell) at
+// cell i with offset f: first node and four weights.
+template <class R>
+__device__ __forceinline__ int stencil4(int i, R f, bool half, bool lower, R w[4]) {
+  int m = i;
+  R d = f;
+  if (half) {
+    if (f >= R(0.5)) {
+      d = f - R(0.5);
+    } else {
+      d = f + R(0.5);
+      m = i - 1;
+    }
+  }
+  if (lower)
+    quad4<R>(d, w);
+  else
+    cubic4<R>(d, w);
+  return m - 1;
+}
+
+template <class R>
+__device__ __forceinline__ void borisc(R qmhdt, const R E[3], const R B[3], R u[3]) {
+  const R e0 = qmhdt * E[0], e1 = qmhdt * E[1], e2 = qmhdt * E[2];
+  const R m0 = u[0] + e0, m1 = u[1] + e1, m2 = u[2] + e2;
+  const R ig = rsqrtc(R(1) + m0 * m0 + m1 * m1 + m2 * m2);
+  const R t0 = qmhdt * B[0] * ig, t1 = qmhdt * B[1] * ig, t2 = qmhdt * B[2] * ig;
+  const R sf = R(2) * rcpc(R(1) + t0 * t0 + t1 * t1 + t2 * t2);
+  const R s0 = t0 * sf, s1 = t1 * sf, s2 = t2 * sf;
+  const R p0 = m0 + (m1 * t2 - m2 * t1);
+  const R p1 = m1 + (m2 * t0 - m0 * t2);
+  const R p2 = m2 + (m0 * t1 - m1 * t0);
+  u[0] = m0 + (p1 * s2 - p2 * s1) + e0;
+  u[1] = m1 + (p2 * s0 - p0 * s2) + e1;
+  u[2] = m2 + (p0 * s1 - p1 * s0) + e2;
+}
+
+template <class R>
+__device__ __forceinline__ int advc(R f, R d, R &g) {
+  g = f + d;
+  int s = 0;
+  if (g >= R(1)) {
+    g = g - R(1);
+    s = 1;
+  } else if (g < R(0)) {
+    g = g + R(1);
+    s = -1;
+    if (g >= R(1)) {
+      g = R(0);
+      s = 0;
+    }
+  }
+  return s;
+}
+
+// One staggered component: 4 x 4 nodes, stencil origins (c0, r0), weights.
+template <class R>
+__device__ __forceinline__ R gather_c(const R *__restrict__ F, int n1, int n2, int c0, const R w1[4],
+                                      int r0, const R w2[4]) {
+  R acc = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const R *row = F + (long long)wrap_small(r0 + b, n2) * n1;
+    R s = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) s += w1[a] * row[wrap_pow2(c0 + a, n1)];
+    acc += w2[b] * s;
+  }
+  return acc;
+}
+
+__device__ __forceinline__ long long fixc(float v) { return (long long)(int)rintf(v); }
+__device__ __forceinline__ double fixc(double v) { return v; }
+
+// deposit targets
+template <class A>
+struct SinkLdsC {
+  lptrc<A> box;
+  int H, W, c0, r0;  // window origin in the box
+  template <class V>
+  __device__ __forceinline__ void operator()(int comp, int b, int a, V v) const {
+    const auto q = fixc(v);
+    if (q != 0)
+      __hip_atomic_fetch_add(box + (comp * H + (r0 + b)) * W + (c0 + a), q, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+template <class A>
+struct SinkGlobC {
+  A *J;
+  long long cells;
+  int n1, n2, c0, r0;  // window origin (global, unwrapped)
+  template <class V>
+  __device__ __forceinline__ void operator()(int comp, int b, int a, V v) const {
+    const auto q = fixc(v);
+    if (q != 0)
+      __hip_atomic_fetch_add(G(J) + comp * cells + (long long)wrap_small(r0 + b, n2) * n1 +
+                                 wrap_pow2(c0 + a, n1),
+                             q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+
+// Esirkepov deposit over the 5 x 5 window: J1 = C1 T2 g1, J2 = C2 T1 g2 (C the
+// running sums of S1 - S0, T = (S0 + S1)/2), J3 = W3 g3.
+template <class R, class Sink>
+__device__ __forceinline__ void deposit_c(const Sink &put, const R S0x[5], const R S1x[5],
+                                          const R S0y[5], const R S1y[5], R g1, R g2, R g3) {
+  R C1[5], C2[5], T1[5], T2[5];
+  R a1 = 0, a2 = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    a1 = a1 + (S1x[k] - S0x[k]);
+    a2 = a2 + (S1y[k] - S0y[k]);
+    C1[k] = a1;
+    C2[k] = a2;
+    T1[k] = R(0.5) * (S0x[k] + S1x[k]);
+    T2[k] = R(0.5) * (S0y[k] + S1y[k]);
+  }
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    if (T2[b] == R(0)) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) put(0, b, a, C1[a] * T2[b] * g1);
+  }
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    if (T1[a] == R(0)) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) put(1, b, a, C2[b] * T1[a] * g2);
+  }
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      const R W3 = S0x[a] * S0y[b] * R(1.0 / 3.0) + S1x[a] * S0y[b] * R(1.0 / 6.0) +
+                   S0x[a] * S1y[b] * R(1.0 / 6.0) + S1x[a] * S1y[b] * R(1.0 / 3.0);
+      if (W3 != R(0)) put(2, b, a, W3 * g3);
+    }
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void place5(const R s[4], int off, R out[5]) {
+  out[0] = off ? R(0) : s[0];
+  out[1] = off ? s[0] : s[1];
+  out[2] = off ? s[1] : s[2];
+  out[3] = off ? s[2] : s[3];
+  out[4] = off ? s[3] : R(0);
+}
+
+}  // namespace
+
+// Items: (run, first particle of 256).
+template <class R, bool EC>
+__global__ void __launch_bounds__(256) k_push_deposit_cubic(const Run<R> *__restrict__ runs,
+                                                            const Item *__restrict__ items,
+                                                            int parity, int pp, unsigned *err) {
+  using A = typename AccOf<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  const Item it = items[blockIdx.x];
+  const Run<R> &r = runs[it.run];
+  const int p0 = it.a + threadIdx.x;
+  const bool active = p0 < r.np;
+  const int p = active ? p0 : it.a;
+  const Parts<R> P = r.pt[pp];
+  const int n1 = r.n1, n2 = r.n2;
+  const int cell = G(P.cell)[p];
+  const int i1 = cell & (n1 - 1), i2 = cell >> r.log2n1;
+  const R f1 = G(P.f1)[p], f2 = G(P.f2)[p];
+  R u[3] = {G(P.u1)[p], G(P.u2)[p], G(P.u3)[p]};
+  const R qw = G(P.qw)[p];
+  // the wave's deposit box, relative to lane 0's cell (periodic in both)
+  const int c00 = __shfl(i1, 0), r00 = __shfl(i2, 0);
+  const int rel1 = ((i1 - c00 + (n1 >> 1)) & (n1 - 1)) - (n1 >> 1);
+  int rel2 = i2 - r00;
+  rel2 += rel2 < -(n2 >> 1) ? n2 : 0;
+  rel2 -= rel2 >= n2 - (n2 >> 1) ? n2 : 0;
+  const int clo = wminc(active ? rel1 : (1 << 29)) - 2, chi = wmaxc(active ? rel1 : -(1 << 29)) + 3;
+  const int rlo = wminc(active ? rel2 : (1 << 29)) - 2, rhi = wmaxc(active ? rel2 : -(1 << 29)) + 3;
+  const int W = chi - clo + 1, H = rhi - rlo + 1;
+  const bool use_lds = chi >= clo && W <= n1 && H <= n2 && 3 * W * H <= CWAVE_CAP;
+  const lptrc<A> box = (lptrc<A>)smem_raw + (threadIdx.x >> 6) * CWAVE_CAP;
+  const int lane = threadIdx.x & 63;
+  if (use_lds)
+    for (int e = lane; e < 3 * W * H; e += 64) box[e] = 0;
+  __syncthreads();
+  // ---- gather: integer (i) and half (h) stencils; EC lowers the order along
+  // the staggered directions
+  R wi1[4], wh1[4], wi2[4], wh2[4];
+  const int ci = stencil4<R>(i1, f1, false, false, wi1);
+  const int ch = stencil4<R>(i1, f1, true, EC, wh1);
+  const int ri = stencil4<R>(i2, f2, false, false, wi2);
+  const int rh = stencil4<R>(i2, f2, true, EC, wh2);
+  const long long cells = r.cells;
+  const R *F = r.F;
+  R E[3], B[3];
+  E[0] = gather_c<R>(F, n1, n2, ch, wh1, ri, wi2);
+  E[1] = gather_c<R>(F + cells, n1, n2, ci, wi1, rh, wh2);
+  E[2] = gather_c<R>(F + 2 * cells, n1, n2, ci, wi1, ri, wi2);
+  B[0] = gather_c<R>(F + 3 * cells, n1, n2, ci, wi1, rh, wh2);
+  B[1] = gather_c<R>(F + 4 * cells, n1, n2, ch, wh1, ri, wi2);
+  B[2] = gather_c<R>(F + 5 * cells, n1, n2, ch, wh1, rh, wh2);
+  borisc<R>(r.qmhdt, E, B, u);
+  R v[3];
+  {
+#pragma clang fp contract(off)
+    R s = R(1) + u[0] * u[0];
+    s = s + u[1] * u[1];
+    s = s + u[2] * u[2];
+    const R ig = R(1) / sqrt(s);
+    v[0] = u[0] * ig;
+    v[1] = u[1] * ig;
+    v[2] = u[2] * ig;
+  }
+  const R m1 = r.dtdx1 * v[0], m2 = r.dtdx2 * v[1];
+  bool ok = active;
+  if (ok && !(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(m1) && isfinite(m2))) {
+    atomicOr(err, ERR_NUMERIC);
+    ok = false;
+  }
+  if (ok && (!(fabs(m1) < R(1)) || !(fabs(m2) < R(1)))) {
+    atomicOr(err, ERR_RANGE);
+    ok = false;
+  }
+  if (ok) {
+    R g1, g2;
+    const int d1 = advc<R>(f1, m1, g1);
+    const int d2 = advc<R>(f2, m2, g2);
+    // window: nodes from min(cell_old, cell_new) - 1, five per axis
+    R sa[4], sb[4], S0x[5], S1x[5], S0y[5], S1y[5];
+    cubic4<R>(f1, sa);
+    cubic4<R>(g1, sb);
+    const int o1 = min(0, d1);  // window origin relative to i1 - 1
+    place5<R>(sa, 0 - o1, S0x);
+    place5<R>(sb, d1 - o1, S1x);
+    cubic4<R>(f2, sa);
+    cubic4<R>(g2, sb);
+    const int o2 = min(0, d2);
+    place5<R>(sa, 0 - o2, S0y);
+    place5<R>(sb, d2 - o2, S1y);
+    R gj1, gj2, gj3;
+    if constexpr (sizeof(R) == 4) {
+      const R gq = qw * r.inv_wunit * r.cj;
+      gj1 = gq;
+      gj2 = gq;
+      gj3 = gq * v[2];
+    } else {
+      gj1 = qw * r.jfx1;
+      gj2 = qw * r.jfx2;
+      gj3 = qw * v[2];
+    }
+    if (use_lds) {
+      SinkLdsC<A> K{(lptrc<A>)smem_raw + (threadIdx.x >> 6) * CWAVE_CAP, H, W,
+                    rel1 - 1 + o1 - clo, rel2 - 1 + o2 - rlo};
+      deposit_c<R>(K, S0x, S1x, S0y, S1y, gj1, gj2, gj3);
+    } else {
+      SinkGlobC<A> K{r.J[parity], cells, n1, n2, i1 - 1 + o1, i2 - 1 + o2};
+      deposit_c<R>(K, S0x, S1x, S0y, S1y, gj1, gj2, gj3);
+    }
+    const int j1 = wrap_pow2(i1 + d1, n1), j2 = wrap_small(i2 + d2, n2);
+    G(P.cell)[p] = (j2 << r.log2n1) | j1;
+    G(P.f1)[p] = g1;
+    G(P.f2)[p] = g2;
+    G(P.u1)[p] = u[0];
+    G(P.u2)[p] = u[1];
+    G(P.u3)[p] = u[2];
+  }
+  __syncthreads();
+  if (use_lds) {
+    A *J = r.J[parity];
+    for (int e = lane; e < 3 * W * H; e += 64) {
+      const A v = box[e];
+      if (v == A(0)) continue;
+      const int cc = e % W, rest = e / W;
+      const int rr = rest % H, comp = rest / H;
+      const int col = wrap_pow2(c00 + clo + cc, n1);
+      int row = r00 + rlo + rr;
+      row += row < 0 ? n2 : 0;
+      row -= row >= n2 ? n2 : 0;
+      __hip_atomic_fetch_add(G(J) + comp * cells + (long long)row * n1 + col, v, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// FP64 charge density of a run's particles with the cubic shape.
+template <class R>
+__global__ void __launch_bounds__(256) k_rho_cubic(const Run<R> *__restrict__ run, int pp,
+                                                   double *rho) {
+  const Run<R> &r = *run;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= r.np) return;
+  const Parts<R> P = r.pt[pp];
+  const int cell = P.cell[p];
+  const int i1 = cell & (r.n1 - 1), i2 = cell >> r.log2n1;
+  double w1[4], w2[4];
+  cubic4<double>((double)P.f1[p], w1);
+  cubic4<double>((double)P.f2[p], w2);
+  const double q = (double)P.qw[p];
+  for (int b = 0; b < 4; ++b) {
+    const long long row = (long long)wrap_small(i2 - 1 + b, r.n2) * r.n1;
+    for (int a = 0; a < 4; ++a)
+      unsafeAtomicAdd(rho + row + wrap_pow2(i1 - 1 + a, r.n1), q * w1[a] * w2[b]);
+  }
+}
+
+template <class R>
+void launch_push_cubic(const Run<R> *runs, const Item *items, int nitems, int parity, int pp,
+                       bool ec, unsigned *err, hipStream_t s) {
+  if (nitems <= 0) return;
+  if (ec)
+    hipLaunchKernelGGL((k_push_deposit_cubic<R, true>), dim3(nitems), dim3(256),
+                       (size_t)CLDS_BYTES, s, runs, items, parity, pp, err);
+  else
+    hipLaunchKernelGGL((k_push_deposit_cubic<R, false>), dim3(nitems), dim3(256),
+                       (size_t)CLDS_BYTES, s, runs, items, parity, pp, err);
+}
+template <class R>
+void launch_rho_cubic(const Run<R> *run_dev, int pp, int np, double *rho, hipStream_t s) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_rho_cubic<R>, dim3((np + 255) / 256), dim3(256), 0, s, run_dev, pp, rho);
+}
+template void launch_push_cubic<float>(const Run<float> *, const Item *, int, int, int, bool,
+                                       unsigned *, hipStream_t);
+template void launch_push_cubic<double>(const Run<double> *, const Item *, int, int, int, bool,
+                                        unsigned *, hipStream_t);
+template void launch_rho_cubic<float>(const Run<float> *, int, int, double *, hipStream_t);
+template void launch_rho_cubic<double>(const Run<double> *, int, int, double *, hipStream_t);
+
+}  // namespace hp

@@ -192,6 +192,7 @@ class Sim : public SimBase {
       d.n2 = c.n[1];
       d.dim = c.geom == HP_GEOM_3D ? 3 : 2;
       d.interp = c.interp;
+      d.shape = c.shape_order;
       d.n3 = d.dim == 3 ? c.n[2] : 1;
       d.rows = d.n2 * d.n3;
       d.cells = d.n1 * d.rows;
@@ -331,9 +332,10 @@ class Sim : public SimBase {
       id[p] = (int)p;
       count[((size_t)c3 * d.n2 + c2) * d.n1 + c1]++;
     }
-    if (FIXED && n > 0 && three) {
+    if (FIXED && n > 0 && (three || d.shape == 3)) {
       // 3D: each node's contribution is at most 3.4 cj in integers, a node
-      // collects from the particles of 4 x 4 x 4 cells
+      // collects from the particles of 4 x 4 x 4 cells (2D cubic: at most cj
+      // from 5 x 5 cells)
       if (!(qmax > 0.0)) return fail(HP_EINVAL, "all particle charges are zero");
       const int cmax = *std::max_element(count.begin(), count.end());
       if (64.0 * std::max(cmax, 1) * 4.0 * CJ3 >= std::ldexp(1.0, 62))
@@ -387,6 +389,7 @@ class Sim : public SimBase {
       return rc;
     if ((rc = upload_jfac(run))) return rc;
     if ((rc = rebuild_sort_items())) return rc;
+    if ((rc = rebuild_particle_items())) return rc;
     if ((rc = upload_runs())) return rc;
     return sort_now();
   }
@@ -418,7 +421,7 @@ class Sim : public SimBase {
     }
     if (rho_from_particles) {
       int rc;
-      if (d.dim == 3) {
+      if (d.dim == 3 || d.shape == 3) {
         if (!h.rho0_3 && (rc = alloc(&h.rho0_3, (size_t)d.cells))) return rc;
         if ((rc = deposit_rho3(run, h.rho0_3))) return rc;
       } else {
@@ -444,6 +447,9 @@ class Sim : public SimBase {
     if (dim_ == 3)
       Launch<R>::push_deposit3(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, d_err_, d_stats_,
                                stream_);
+    else if (runs_[0].d.shape == 3)
+      launch_push_cubic<R>(d_runs_, d_pitems_, n_pitems_, p, pp_, runs_[0].cfg.interp == 1, d_err_,
+                           stream_);
     else
       Launch<R>::push_deposit(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, all_unit(),
                               runs_[0].cfg.interp == 1, d_err_,
@@ -854,7 +860,7 @@ class Sim : public SimBase {
   }
 
   int diagnostics(int run, hp_diag *out) override {
-    if (runs_[run].d.dim == 3) return diagnostics3(run, out);
+    if (runs_[run].d.dim == 3 || runs_[run].d.shape == 3) return diagnostics3(run, out);
     RunHost &h = runs_[run];
     Run<R> &d = h.d;
     const size_t cells = (size_t)d.n1 * d.n2;
@@ -961,6 +967,7 @@ class Sim : public SimBase {
 
   // ---- checkpoint: header + per run raw arrays (bit-exact resume)
   int get_state(void *blob, size_t *size) override {
+    if (runs_[0].d.shape == 3) return fail(HP_EINVAL, "checkpoints are not available with the cubic shape");
     int rc;
     if ((rc = sync())) return rc;
     size_t need = state_size();
@@ -1010,6 +1017,7 @@ class Sim : public SimBase {
   }
 
   int set_state(const void *blob, size_t size) override {
+    if (runs_[0].d.shape == 3) return fail(HP_EINVAL, "checkpoints are not available with the cubic shape");
     const char *o = (const char *)blob;
     const char *end = o + size;
     auto take = [&](void *dst, size_t bytes) {
@@ -1093,7 +1101,8 @@ class Sim : public SimBase {
                     const float *o1, const float *v3, const float *qw, int64_t *J) override {
     if (!FIXED) return fail(HP_EINVAL, "the fixed-point deposit exists only in the FP32 form");
     const Run<R> &d = runs_[run].d;
-    if (d.dim != 2) return fail(HP_EINVAL, "the deposit test hook is 2D only");
+    if (d.dim != 2 || d.shape != 2)
+      return fail(HP_EINVAL, "the deposit test hook is for the 2D quadratic integer deposit");
     const size_t cells = (size_t)d.n1 * d.n2;
     if (n < 0 || n > 0x7fffffff) return fail(HP_EINVAL, "bad count");
     for (int64_t p = 0; p < n; ++p) {
@@ -1130,9 +1139,10 @@ class Sim : public SimBase {
   int fixed_params(int run, double *out) override {
     if (!FIXED) return fail(HP_EINVAL, "fixed-point parameters exist only in the FP32 form");
     const RunHost &h = runs_[run];
-    out[0] = h.d.dim == 3 ? 0 : h.d.P;
+    const bool fw = h.d.dim == 3 || h.d.shape == 3;  // FP32 weights, integer contributions
+    out[0] = fw ? 0 : h.d.P;
     out[1] = h.d.inv_wunit;
-    out[2] = h.d.dim == 3 ? h.d.cj : h.d.c3;
+    out[2] = fw ? h.d.cj : h.d.c3;
     out[3] = h.Qbits;
     return HP_OK;
   }
@@ -1286,6 +1296,18 @@ class Sim : public SimBase {
     return true;
   }
 
+  // cubic shape: one push item per 256 particles of every run
+  int rebuild_particle_items() {
+    if (d_pitems_) release(d_pitems_);
+    d_pitems_ = nullptr;
+    n_pitems_ = 0;
+    if (runs_[0].d.shape != 3) return HP_OK;
+    std::vector<Item> items;
+    for (int i = 0; i < (int)runs_.size(); ++i)
+      for (int64_t p = 0; p < runs_[i].np; p += 256) items.push_back(Item{i, (int)p, 0});
+    if (items.empty()) return HP_OK;
+    return upload_items(items, &d_pitems_, &n_pitems_);
+  }
   int rebuild_sort_items() {
     drop_graphs();  // captured launches hold the old item lists and counts
     std::vector<Item> items;
@@ -1339,7 +1361,10 @@ class Sim : public SimBase {
   int deposit_rho3(int run, double *rho) {
     RunHost &h = runs_[run];
     HIPCHK(hipMemsetAsync(rho, 0, sizeof(double) * (size_t)h.d.cells, stream_));
-    launch_rho3<R>(d_runs_ + run, pp_, (int)h.np, rho, stream_);
+    if (h.d.shape == 3)
+      launch_rho_cubic<R>(d_runs_ + run, pp_, (int)h.np, rho, stream_);
+    else
+      launch_rho3<R>(d_runs_ + run, pp_, (int)h.np, rho, stream_);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream_));
     return HP_OK;
@@ -1349,6 +1374,9 @@ class Sim : public SimBase {
     if (!FIXED) return 1.0;
     if (h.d.dim == 3)
       return -(h.cfg.dx[comp] / h.cfg.dt) / (6.0 * (double)h.d.inv_wunit * (double)h.d.cj);
+    if (h.d.shape == 3)  // 2D cubic: C T (qw inv_wunit cj) and W3 v3 (qw inv_wunit cj)
+      return (comp < 2 ? -(h.cfg.dx[comp] / h.cfg.dt) : 1.0) /
+             ((double)h.d.inv_wunit * (double)h.d.cj);
     const int P = h.d.P;
     const double iw = (double)h.d.inv_wunit;
     if (comp == 0) return -(h.cfg.dx[0] / h.cfg.dt) / (iw * std::ldexp(1.0, 2 * P + 1));
@@ -1436,7 +1464,8 @@ class Sim : public SimBase {
   std::vector<RunHost> runs_;
   std::vector<void *> allocs_;
   Run<R> *d_runs_ = nullptr;
-  Item *d_chunks_ = nullptr, *d_tiles_ = nullptr, *d_perrun_ = nullptr;
+  Item *d_chunks_ = nullptr, *d_tiles_ = nullptr, *d_perrun_ = nullptr, *d_pitems_ = nullptr;
+  int n_pitems_ = 0;
   Item *d_rows_ = nullptr, *d_grps_ = nullptr, *d_upd_ = nullptr;
   int n_chunks_ = 0, n_tiles_ = 0, n_rows_ = 0, n_grps_ = 0, n_upd_ = 0;
   int pp_ = 0;             // particle buffer parity
@@ -2168,8 +2197,12 @@ int hp_create(const hp_config *cfgs, int32_t nruns, hp_sim **out) {
       return fail(HP_EINVAL, "run %d: n2 = %d out of range", i, c.n[1]);
     if (!(c.dx[0] > 0) || !(c.dx[1] > 0) || !(c.dt > 0) || !std::isfinite(c.dt))
       return fail(HP_EINVAL, "run %d: non-positive cell size or time step", i);
-    if (c.shape_order != 2 || (c.interp != 0 && c.interp != 1))
-      return fail(HP_EINVAL, "run %d: quadratic shape; interp 0 (momentum-) or 1 (energy-conserving)", i);
+    if ((c.shape_order != 2 && c.shape_order != 3) || (c.interp != 0 && c.interp != 1))
+      return fail(HP_EINVAL, "run %d: shape order 2 or 3; interp 0 (momentum-) or 1 (energy-conserving)", i);
+    if (c.shape_order == 3 && c.geom != HP_GEOM_2D)
+      return fail(HP_EINVAL, "run %d: the cubic shape is built for 2D runs only", i);
+    if (c.shape_order != cfgs[0].shape_order)
+      return fail(HP_EINVAL, "run %d: all runs of a handle share the shape order", i);
     if (!(c.filter_frac > 0)) return fail(HP_EINVAL, "run %d: filter_frac must be > 0", i);
     if (c.deriv1 != 0 && c.deriv1 != 1) return fail(HP_EINVAL, "run %d: bad deriv1", i);
     if (c.kmod != 0 && c.kmod != 1) return fail(HP_EINVAL, "run %d: bad kmod", i);

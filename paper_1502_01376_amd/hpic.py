@@ -133,7 +133,7 @@ def _ptr(a):
 
 def config(n1, n2, dx1, dx2, dt, alpha=0.5, deriv1=0, correct=1, precision="fp32",
            shape_bits=0, weight_bits=0, sort_interval=0, n3=0, dx3=0.0, kmod=0, modes=0,
-           interp=0):
+           interp=0, shape=2):
     """Configuration of one run; n3 > 0 makes it a 3D run (n1 x n2 x n3 cells);
     modes > 0 a quasi-3D run (n1 points along z of dx1, n2 radial cells of dx2,
     azimuthal modes 0..modes-1)."""
@@ -143,7 +143,7 @@ def config(n1, n2, dx1, dx2, dt, alpha=0.5, deriv1=0, correct=1, precision="fp32
     c.n[0], c.n[1], c.n[2] = int(n1), int(n2), int(n3) if n3 > 0 else 1
     c.dx[0], c.dx[1], c.dx[2] = float(dx1), float(dx2), float(dx3) if n3 > 0 else 1.0
     c.dt = float(dt)
-    c.shape_order, c.interp = 2, int(interp)
+    c.shape_order, c.interp = int(shape), int(interp)
     c.filter_frac = float(alpha)
     c.deriv1, c.correct = int(deriv1), int(correct)
     c.precision = HP_PREC_FP32_FIXED if precision == "fp32" else HP_PREC_FP64

@@ -92,7 +92,13 @@ def test_bad_precision_and_shape_rejected(hp):
     c.precision = 7
     assert _create(hp, c)[0] == hp.HP_EINVAL
     c = hp.config(64, 32, 0.2, 0.2, 0.05)
+    c.shape_order = 4
+    assert _create(hp, c)[0] == hp.HP_EINVAL
+    c = hp.config(32, 16, 0.2, 0.2, 0.02, n3=16, dx3=0.2)  # cubic is 2D only
     c.shape_order = 3
+    assert _create(hp, c)[0] == hp.HP_EINVAL
+    c = hp.config(64, 32, 0.2, 0.2, 0.05)
+    c.interp = 2
     assert _create(hp, c)[0] == hp.HP_EINVAL
 
 
