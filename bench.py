@@ -51,6 +51,9 @@ def parse():
                     help="steps of the 64-run parameter scan (0: skip)")
     ap.add_argument("--d3-steps", type=int, default=500,
                     help="steps of the 3D 512x128x128 drifting-plasma leg (0: skip)")
+    ap.add_argument("--shape-steps", type=int, default=200,
+                    help="steps of the benchmark workload with the energy-conserving gather "
+                         "and with the cubic shape (0: skip)")
     ap.add_argument("--q3d-steps", type=int, default=200,
                     help="steps of the quasi-3D 4096x256 three-mode PIC leg (0: skip)")
     ap.add_argument("--n1", type=int, default=2048)
@@ -72,13 +75,14 @@ def timed_steps(torch, sim, warmup, steps):
     return t1 - t0
 
 
-def run_form(hpic, torch, ds, precision, warmup, steps, profile=False, tune_steps=0, tiling=None):
+def run_form(hpic, torch, ds, precision, warmup, steps, profile=False, tune_steps=0, tiling=None,
+             **cfg_kw):
     """Untimed: the autotuner (tune_steps steps, picking tile shape and sort
     interval on the live runs) and `warmup` steps.  Timed region: `steps`
     steps with the captured-graph step (the library's default).  With
     `profile`, a second pass of the same length launches every kernel with HIP
     events around it on the library's stream for per-kernel durations."""
-    sim = hpic.from_workloads(ds, precision, stream=torch.cuda.current_stream())
+    sim = hpic.from_workloads(ds, precision, stream=torch.cuda.current_stream(), **cfg_kw)
     if tiling:
         sim.set_tiling(*tiling)
     elif tune_steps > 0:
@@ -277,6 +281,25 @@ def q3d_leg(hpic, torch, W, steps):
     return out
 
 
+def shape_leg(hpic, torch, d, steps, tune_steps, tiling):
+    """The benchmark workload (2048x512, 8 388 608 particles, FP32 form) with
+    the energy-conserving gather and with the cubic shape, each over `steps`
+    steps after the same warm-up: particle-steps/s and push+deposit time."""
+    npart = d["w"].size
+    out = {"steps": steps}
+    for name, kw in (("energy_conserving", dict(interp=1)), ("cubic", dict(shape=3)),
+                     ("cubic_energy_conserving", dict(shape=3, interp=1))):
+        sim, t, kt = run_form(hpic, torch, [d], "fp32", 20, steps, profile=True,
+                              tune_steps=tune_steps if "cubic" not in name else 0,
+                              tiling=tiling, **kw)
+        kt.pop("profiled_wall_s", None)
+        pd_ms, pd_n = kt["push_deposit"]
+        out[name] = {"particle_steps_per_s": npart * steps / t, "ms_per_step": 1e3 * t / steps,
+                     "push_deposit_us": 1e3 * pd_ms / max(pd_n, 1)}
+        sim.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -368,6 +391,8 @@ def main():
         out["drift3d"] = d3_leg(hpic, torch, W, args.d3_steps, args.tune_steps)
     if args.q3d_steps > 0:
         out["quasi3d"] = q3d_leg(hpic, torch, W, args.q3d_steps)
+    if args.shape_steps > 0:
+        out["shapes2d"] = shape_leg(hpic, torch, d, args.shape_steps, args.tune_steps, tiling)
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
         x = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -317,11 +317,11 @@ void launch_cont3(const double *rn, const double *ro, const A *J, int n1, int n2
                   double dt, double f1, double f2, double f3, double idx1, double idx2,
                   double idx3, double *partial, int nblocks, hipStream_t s);
 void launch_rho_fixed(const Run<float> *run_dev, int pp, int np, long long *rho, hipStream_t s);
-// 2D with the cubic shape: push + deposit (items: run, first particle of 256),
-// and the FP64 charge density
+// 2D with the cubic shape: push + deposit (items: run, tile), and the FP64
+// charge density
 template <class R>
 void launch_push_cubic(const Run<R> *runs, const Item *items, int nitems, int parity, int pp,
-                       bool ec, unsigned *err, hipStream_t s);
+                       int lds_bytes, bool ec, unsigned *err, hipStream_t s);
 template <class R>
 void launch_rho_cubic(const Run<R> *run_dev, int pp, int np, double *rho, hipStream_t s);
 void launch_rho_fp64(const Run<double> *run_dev, int pp, int np, double *rho, hipStream_t s);

@@ -5,12 +5,11 @@
 // quadratic shape along a component's staggered directions), relativistic
 // Boris push, and the Esirkepov deposit over a 5 x 5 window.
 //
-// One thread per particle in the particles' current order (the periodic tile
-// sort keeps the 64 particles of a wave within a few cells).  Each wave bounds
-// its deposit footprint before the push (a move is under a cell: columns and
-// rows -2 .. +3 around the particle's cell) and accumulates into its own LDS
-// box, added to the global accumulators afterwards; a wave whose particles
-// spread further deposits with global atomics.  FP32 form: Esirkepov weights
+// One workgroup per particle tile of the periodic tile sort.  The workgroup
+// bounds its tile's particle cells, accumulates the current of all of them
+// into one LDS box (a move is under a cell: columns and rows -2 .. +3 around
+// the cells) and adds the box to the global accumulators at the end; a box
+// too large for LDS falls back to global atomics.  FP32 form: Esirkepov weights
 // in FP32, each node's contribution rounded once to an integer (|v| < 2^31)
 // and accumulated in 64 bits, so the sums do not depend on the order; FP64
 // form: physical current in FP64.
@@ -21,7 +20,6 @@ namespace hp {
 namespace {
 
 constexpr int CLDS_BYTES = 64512;
-constexpr int CWAVE_CAP = CLDS_BYTES / 4 / 8;
 
 template <class T> using lptrc = T __attribute__((address_space(3))) *;
 
@@ -213,79 +211,113 @@ __device__ __forceinline__ void place5(const R s[4], int off, R out[5]) {
 
 }  // namespace
 
-// Items: (run, first particle of 256).
+// One workgroup per particle tile (items: run, tile).  The tile's particles
+// are bounded first (cells relative to the tile origin, periodic), the
+// current box (bounds -2 .. +3) is accumulated in LDS by all of them and added
+// to the global accumulators at the end; a box too large for LDS falls back to
+// global atomics.
 template <class R, bool EC>
 __global__ void __launch_bounds__(256) k_push_deposit_cubic(const Run<R> *__restrict__ runs,
                                                             const Item *__restrict__ items,
-                                                            int parity, int pp, unsigned *err) {
+                                                            int parity, int pp, int lds_bytes,
+                                                            unsigned *err) {
   using A = typename AccOf<R>::T;
   extern __shared__ unsigned char smem_raw[];
+  __shared__ int red[4][4];
   const Item it = items[blockIdx.x];
   const Run<R> &r = runs[it.run];
-  const int p0 = it.a + threadIdx.x;
-  const bool active = p0 < r.np;
-  const int p = active ? p0 : it.a;
+  const int t = it.a;
+  const int start = r.tile_start[t], end = r.tile_start[t + 1];
+  if (start >= end) return;  // the whole workgroup
   const Parts<R> P = r.pt[pp];
   const int n1 = r.n1, n2 = r.n2;
-  const int cell = G(P.cell)[p];
-  const int i1 = cell & (n1 - 1), i2 = cell >> r.log2n1;
-  const R f1 = G(P.f1)[p], f2 = G(P.f2)[p];
-  R u[3] = {G(P.u1)[p], G(P.u2)[p], G(P.u3)[p]};
-  const R qw = G(P.qw)[p];
-  // the wave's deposit box, relative to lane 0's cell (periodic in both)
-  const int c00 = __shfl(i1, 0), r00 = __shfl(i2, 0);
-  const int rel1 = ((i1 - c00 + (n1 >> 1)) & (n1 - 1)) - (n1 >> 1);
-  int rel2 = i2 - r00;
-  rel2 += rel2 < -(n2 >> 1) ? n2 : 0;
-  rel2 -= rel2 >= n2 - (n2 >> 1) ? n2 : 0;
-  const int clo = wminc(active ? rel1 : (1 << 29)) - 2, chi = wmaxc(active ? rel1 : -(1 << 29)) + 3;
-  const int rlo = wminc(active ? rel2 : (1 << 29)) - 2, rhi = wmaxc(active ? rel2 : -(1 << 29)) + 3;
-  const int W = chi - clo + 1, H = rhi - rlo + 1;
-  const bool use_lds = chi >= clo && W <= n1 && H <= n2 && 3 * W * H <= CWAVE_CAP;
-  const lptrc<A> box = (lptrc<A>)smem_raw + (threadIdx.x >> 6) * CWAVE_CAP;
-  const int lane = threadIdx.x & 63;
-  if (use_lds)
-    for (int e = lane; e < 3 * W * H; e += 64) box[e] = 0;
+  const int t2i = t / r.nt1, t1i = t - t2i * r.nt1;
+  const int ref1 = t1i * r.T1, ref2 = t2i * r.T2;
+  auto rel = [&](int c, int &a, int &b) {
+    const int i1 = c & (n1 - 1), i2 = c >> r.log2n1;
+    a = ((i1 - ref1 + (n1 >> 1)) & (n1 - 1)) - (n1 >> 1);
+    int d = i2 - ref2;
+    d += d < -(n2 >> 1) ? n2 : 0;
+    d -= d >= n2 - (n2 >> 1) ? n2 : 0;
+    b = d;
+  };
+  // ---- bounds of the tile's particle cells
+  int lo1 = 1 << 29, hi1 = -(1 << 29), lo2 = 1 << 29, hi2 = -(1 << 29);
+  for (int p = start + (int)threadIdx.x; p < end; p += 256) {
+    int a, b;
+    rel(G(P.cell)[p], a, b);
+    lo1 = min(lo1, a);
+    hi1 = max(hi1, a);
+    lo2 = min(lo2, b);
+    hi2 = max(hi2, b);
+  }
+  lo1 = wminc(lo1);
+  hi1 = wmaxc(hi1);
+  lo2 = wminc(lo2);
+  hi2 = wmaxc(hi2);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    red[wave][0] = lo1;
+    red[wave][1] = hi1;
+    red[wave][2] = lo2;
+    red[wave][3] = hi2;
+  }
   __syncthreads();
-  // ---- gather: integer (i) and half (h) stencils; EC lowers the order along
-  // the staggered directions
-  R wi1[4], wh1[4], wi2[4], wh2[4];
-  const int ci = stencil4<R>(i1, f1, false, false, wi1);
-  const int ch = stencil4<R>(i1, f1, true, EC, wh1);
-  const int ri = stencil4<R>(i2, f2, false, false, wi2);
-  const int rh = stencil4<R>(i2, f2, true, EC, wh2);
+  lo1 = min(min(red[0][0], red[1][0]), min(red[2][0], red[3][0])) - 2;
+  hi1 = max(max(red[0][1], red[1][1]), max(red[2][1], red[3][1])) + 3;
+  lo2 = min(min(red[0][2], red[1][2]), min(red[2][2], red[3][2])) - 2;
+  hi2 = max(max(red[0][3], red[1][3]), max(red[2][3], red[3][3])) + 3;
+  const int W = hi1 - lo1 + 1, H = hi2 - lo2 + 1;
+  const bool use_lds = W <= n1 && H <= n2 && 3LL * W * H * (long long)sizeof(A) <= lds_bytes;
+  const lptrc<A> box = (lptrc<A>)smem_raw;
+  if (use_lds)
+    for (int e = threadIdx.x; e < 3 * W * H; e += 256) box[e] = 0;
+  __syncthreads();
   const long long cells = r.cells;
   const R *F = r.F;
-  R E[3], B[3];
-  E[0] = gather_c<R>(F, n1, n2, ch, wh1, ri, wi2);
-  E[1] = gather_c<R>(F + cells, n1, n2, ci, wi1, rh, wh2);
-  E[2] = gather_c<R>(F + 2 * cells, n1, n2, ci, wi1, ri, wi2);
-  B[0] = gather_c<R>(F + 3 * cells, n1, n2, ci, wi1, rh, wh2);
-  B[1] = gather_c<R>(F + 4 * cells, n1, n2, ch, wh1, ri, wi2);
-  B[2] = gather_c<R>(F + 5 * cells, n1, n2, ch, wh1, rh, wh2);
-  borisc<R>(r.qmhdt, E, B, u);
-  R v[3];
-  {
+  for (int p = start + (int)threadIdx.x; p < end; p += 256) {
+    const int cell = G(P.cell)[p];
+    const int i1 = cell & (n1 - 1), i2 = cell >> r.log2n1;
+    int rel1, rel2;
+    rel(cell, rel1, rel2);
+    const R f1 = G(P.f1)[p], f2 = G(P.f2)[p];
+    R u[3] = {G(P.u1)[p], G(P.u2)[p], G(P.u3)[p]};
+    const R qw = G(P.qw)[p];
+    // ---- gather: integer (i) and half (h) stencils; EC lowers the order
+    // along the staggered directions
+    R wi1[4], wh1[4], wi2[4], wh2[4];
+    const int ci = stencil4<R>(i1, f1, false, false, wi1);
+    const int ch = stencil4<R>(i1, f1, true, EC, wh1);
+    const int ri = stencil4<R>(i2, f2, false, false, wi2);
+    const int rh = stencil4<R>(i2, f2, true, EC, wh2);
+    R E[3], B[3];
+    E[0] = gather_c<R>(F, n1, n2, ch, wh1, ri, wi2);
+    E[1] = gather_c<R>(F + cells, n1, n2, ci, wi1, rh, wh2);
+    E[2] = gather_c<R>(F + 2 * cells, n1, n2, ci, wi1, ri, wi2);
+    B[0] = gather_c<R>(F + 3 * cells, n1, n2, ci, wi1, rh, wh2);
+    B[1] = gather_c<R>(F + 4 * cells, n1, n2, ch, wh1, ri, wi2);
+    B[2] = gather_c<R>(F + 5 * cells, n1, n2, ch, wh1, rh, wh2);
+    borisc<R>(r.qmhdt, E, B, u);
+    R v[3];
+    {
 #pragma clang fp contract(off)
-    R s = R(1) + u[0] * u[0];
-    s = s + u[1] * u[1];
-    s = s + u[2] * u[2];
-    const R ig = R(1) / sqrt(s);
-    v[0] = u[0] * ig;
-    v[1] = u[1] * ig;
-    v[2] = u[2] * ig;
-  }
-  const R m1 = r.dtdx1 * v[0], m2 = r.dtdx2 * v[1];
-  bool ok = active;
-  if (ok && !(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(m1) && isfinite(m2))) {
-    atomicOr(err, ERR_NUMERIC);
-    ok = false;
-  }
-  if (ok && (!(fabs(m1) < R(1)) || !(fabs(m2) < R(1)))) {
-    atomicOr(err, ERR_RANGE);
-    ok = false;
-  }
-  if (ok) {
+      R s = R(1) + u[0] * u[0];
+      s = s + u[1] * u[1];
+      s = s + u[2] * u[2];
+      const R ig = R(1) / sqrt(s);
+      v[0] = u[0] * ig;
+      v[1] = u[1] * ig;
+      v[2] = u[2] * ig;
+    }
+    const R m1 = r.dtdx1 * v[0], m2 = r.dtdx2 * v[1];
+    if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(m1) && isfinite(m2))) {
+      atomicOr(err, ERR_NUMERIC);
+      continue;
+    }
+    if (!(fabs(m1) < R(1)) || !(fabs(m2) < R(1))) {
+      atomicOr(err, ERR_RANGE);
+      continue;
+    }
     R g1, g2;
     const int d1 = advc<R>(f1, m1, g1);
     const int d2 = advc<R>(f2, m2, g2);
@@ -313,8 +345,7 @@ __global__ void __launch_bounds__(256) k_push_deposit_cubic(const Run<R> *__rest
       gj3 = qw * v[2];
     }
     if (use_lds) {
-      SinkLdsC<A> K{(lptrc<A>)smem_raw + (threadIdx.x >> 6) * CWAVE_CAP, H, W,
-                    rel1 - 1 + o1 - clo, rel2 - 1 + o2 - rlo};
+      SinkLdsC<A> K{box, H, W, rel1 - 1 + o1 - lo1, rel2 - 1 + o2 - lo2};
       deposit_c<R>(K, S0x, S1x, S0y, S1y, gj1, gj2, gj3);
     } else {
       SinkGlobC<A> K{r.J[parity], cells, n1, n2, i1 - 1 + o1, i2 - 1 + o2};
@@ -331,15 +362,14 @@ __global__ void __launch_bounds__(256) k_push_deposit_cubic(const Run<R> *__rest
   __syncthreads();
   if (use_lds) {
     A *J = r.J[parity];
-    for (int e = lane; e < 3 * W * H; e += 64) {
+    for (int e = threadIdx.x; e < 3 * W * H; e += 256) {
       const A v = box[e];
       if (v == A(0)) continue;
       const int cc = e % W, rest = e / W;
       const int rr = rest % H, comp = rest / H;
-      const int col = wrap_pow2(c00 + clo + cc, n1);
-      int row = r00 + rlo + rr;
+      const int col = wrap_pow2(ref1 + lo1 + cc, n1);
+      int row = (ref2 + lo2 + rr) % n2;
       row += row < 0 ? n2 : 0;
-      row -= row >= n2 ? n2 : 0;
       __hip_atomic_fetch_add(G(J) + comp * cells + (long long)row * n1 + col, v, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -369,24 +399,25 @@ __global__ void __launch_bounds__(256) k_rho_cubic(const Run<R> *__restrict__ ru
 
 template <class R>
 void launch_push_cubic(const Run<R> *runs, const Item *items, int nitems, int parity, int pp,
-                       bool ec, unsigned *err, hipStream_t s) {
+                       int lds_bytes, bool ec, unsigned *err, hipStream_t s) {
   if (nitems <= 0) return;
+  lds_bytes = min(lds_bytes, CLDS_BYTES);
   if (ec)
     hipLaunchKernelGGL((k_push_deposit_cubic<R, true>), dim3(nitems), dim3(256),
-                       (size_t)CLDS_BYTES, s, runs, items, parity, pp, err);
+                       (size_t)lds_bytes, s, runs, items, parity, pp, lds_bytes, err);
   else
     hipLaunchKernelGGL((k_push_deposit_cubic<R, false>), dim3(nitems), dim3(256),
-                       (size_t)CLDS_BYTES, s, runs, items, parity, pp, err);
+                       (size_t)lds_bytes, s, runs, items, parity, pp, lds_bytes, err);
 }
 template <class R>
 void launch_rho_cubic(const Run<R> *run_dev, int pp, int np, double *rho, hipStream_t s) {
   if (np <= 0) return;
   hipLaunchKernelGGL(k_rho_cubic<R>, dim3((np + 255) / 256), dim3(256), 0, s, run_dev, pp, rho);
 }
-template void launch_push_cubic<float>(const Run<float> *, const Item *, int, int, int, bool,
+template void launch_push_cubic<float>(const Run<float> *, const Item *, int, int, int, int, bool,
                                        unsigned *, hipStream_t);
-template void launch_push_cubic<double>(const Run<double> *, const Item *, int, int, int, bool,
-                                        unsigned *, hipStream_t);
+template void launch_push_cubic<double>(const Run<double> *, const Item *, int, int, int, int,
+                                        bool, unsigned *, hipStream_t);
 template void launch_rho_cubic<float>(const Run<float> *, int, int, double *, hipStream_t);
 template void launch_rho_cubic<double>(const Run<double> *, int, int, double *, hipStream_t);
 

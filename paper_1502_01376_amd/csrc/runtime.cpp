@@ -389,7 +389,6 @@ class Sim : public SimBase {
       return rc;
     if ((rc = upload_jfac(run))) return rc;
     if ((rc = rebuild_sort_items())) return rc;
-    if ((rc = rebuild_particle_items())) return rc;
     if ((rc = upload_runs())) return rc;
     return sort_now();
   }
@@ -448,8 +447,8 @@ class Sim : public SimBase {
       Launch<R>::push_deposit3(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, d_err_, d_stats_,
                                stream_);
     else if (runs_[0].d.shape == 3)
-      launch_push_cubic<R>(d_runs_, d_pitems_, n_pitems_, p, pp_, runs_[0].cfg.interp == 1, d_err_,
-                           stream_);
+      launch_push_cubic<R>(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, runs_[0].cfg.interp == 1,
+                           d_err_, stream_);
     else
       Launch<R>::push_deposit(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, all_unit(),
                               runs_[0].cfg.interp == 1, d_err_,
@@ -1279,8 +1278,9 @@ class Sim : public SimBase {
     }
     tile1_ = t1;
     tile2_ = t2;
-    // per node: 2D 3 accumulators + 6 staged field values; 3D accumulators only
-    const int node_bytes = dim_ == 3 ? 24 : (FIXED ? 48 : 72);
+    // per node: 2D 3 accumulators + 6 staged field values; 3D and the 2D cubic
+    // shape (fields gathered through the cache) accumulators only
+    const int node_bytes = (dim_ == 3 || runs_[0].d.shape == 3) ? 24 : (FIXED ? 48 : 72);
     push_lds_ = std::min(PUSH_LDS_MAX, std::max(PUSH_LDS_MIN, ((maxbox * node_bytes + 1023) / 1024) * 1024));
     if (d_tiles_) release(d_tiles_);
     d_tiles_ = nullptr;
@@ -1296,18 +1296,6 @@ class Sim : public SimBase {
     return true;
   }
 
-  // cubic shape: one push item per 256 particles of every run
-  int rebuild_particle_items() {
-    if (d_pitems_) release(d_pitems_);
-    d_pitems_ = nullptr;
-    n_pitems_ = 0;
-    if (runs_[0].d.shape != 3) return HP_OK;
-    std::vector<Item> items;
-    for (int i = 0; i < (int)runs_.size(); ++i)
-      for (int64_t p = 0; p < runs_[i].np; p += 256) items.push_back(Item{i, (int)p, 0});
-    if (items.empty()) return HP_OK;
-    return upload_items(items, &d_pitems_, &n_pitems_);
-  }
   int rebuild_sort_items() {
     drop_graphs();  // captured launches hold the old item lists and counts
     std::vector<Item> items;
@@ -1464,8 +1452,7 @@ class Sim : public SimBase {
   std::vector<RunHost> runs_;
   std::vector<void *> allocs_;
   Run<R> *d_runs_ = nullptr;
-  Item *d_chunks_ = nullptr, *d_tiles_ = nullptr, *d_perrun_ = nullptr, *d_pitems_ = nullptr;
-  int n_pitems_ = 0;
+  Item *d_chunks_ = nullptr, *d_tiles_ = nullptr, *d_perrun_ = nullptr;
   Item *d_rows_ = nullptr, *d_grps_ = nullptr, *d_upd_ = nullptr;
   int n_chunks_ = 0, n_tiles_ = 0, n_rows_ = 0, n_grps_ = 0, n_upd_ = 0;
   int pp_ = 0;             // particle buffer parity
