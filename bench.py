@@ -56,6 +56,8 @@ def parse():
                          "and with the cubic shape (0: skip)")
     ap.add_argument("--q3d-steps", type=int, default=200,
                     help="steps of the quasi-3D 4096x256 three-mode PIC leg (0: skip)")
+    ap.add_argument("--nci-steps", type=int, default=40000,
+                    help="steps of the Table 1 NCI contrast (four 256x256 runs; 0: skip)")
     ap.add_argument("--n1", type=int, default=2048)
     ap.add_argument("--n2", type=int, default=512)
     return ap.parse_args()
@@ -281,6 +283,28 @@ def q3d_leg(hpic, torch, W, steps):
     return out
 
 
+def nci_leg(steps):
+    """The Table 1 drift (256x256, gamma = 50, n = 100, FP32 form) without the
+    k1 filter, with it, with the Eq. (29) modification and with that and the
+    cubic shape: log10 of the E2 energy at t = 160, 320 and the end, the
+    wavenumber of the strongest E2 mode at the end, and the wall time."""
+    import math
+    from paper_1502_01376_amd import nci
+    t0 = time.time()
+    res = nci.run(tuple(nci.CASES), steps=steps, every=500)
+    out = {"steps": steps, "t_end": steps * 0.08}
+    for name, r in res.items():
+        t = np.asarray(r["t"])
+        lw = [math.log10(max(w, 1e-300)) for w in r["W_E2"]]
+        pick = {"log10_W_E2_t%g" % tt: round(lw[int(np.argmin(np.abs(t - tt)))], 3)
+                for tt in (160.0, 320.0) if tt <= t[-1]}
+        out[name] = dict(pick, log10_W_E2_end=round(lw[-1], 3),
+                         peak_k1_over_kg1=round(r["peak"]["k1_over_kg1"], 4),
+                         peak_k2=round(r["peak"]["k2"], 4))
+    out["wall_s"] = round(time.time() - t0, 2)
+    return out
+
+
 def shape_leg(hpic, torch, d, steps, tune_steps, tiling):
     """The benchmark workload (2048x512, 8 388 608 particles, FP32 form) with
     the energy-conserving gather and with the cubic shape, each over `steps`
@@ -393,6 +417,8 @@ def main():
         out["quasi3d"] = q3d_leg(hpic, torch, W, args.q3d_steps)
     if args.shape_steps > 0:
         out["shapes2d"] = shape_leg(hpic, torch, d, args.shape_steps, args.tune_steps, tiling)
+    if args.nci_steps > 0:
+        out["nci_table1"] = nci_leg(args.nci_steps)
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
         x = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -85,9 +85,10 @@ typedef struct hp_config {
   int32_t n[3];              /* cells per direction (n[2] unused in 2D) */
   double dx[3];              /* cell sizes */
   double dt;                 /* time step */
-  int32_t shape_order;       /* particle shape order: 2 (quadratic) or 3 (cubic, 2D
-                                only: FP32 weights with one rounding per node
-                                contribution in the FP32 form; no checkpoints) */
+  int32_t shape_order;       /* particle shape order: 2 (quadratic) or 3 (cubic
+                                B-spline, Sec. 4 and Appendix A; 2D only).  The
+                                FP32 form keeps continuity exact in integers for
+                                both (integer weights with exact sum 2^P) */
   int32_t interp;            /* 0: momentum-conserving gather (Appendix A, first
                                 variant: the quadratic spline at every component's
                                 node); 1: energy-conserving (second variant: linear

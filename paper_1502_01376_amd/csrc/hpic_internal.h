@@ -242,6 +242,21 @@ __device__ __forceinline__ int fixed_shape(int cell, float f, int P, int s[3]) {
   return cell + up;
 }
 
+// Exact product of two integers in [-2^23, 2^23) as a 64-bit value.  The
+// explicit sign extension from 24 bits lets the compiler select the full-rate
+// v_mul_i32_i24 / v_mul_hi_i32_i24 pair.
+__device__ __forceinline__ long long mul24_wide(int a, int b) {
+  return (long long)((a << 8) >> 8) * (long long)((b << 8) >> 8);
+}
+// Product of two integers in [-2^23, 2^23) whose value fits 32 bits: one
+// v_mul_i32_i24 (written out, as the compiler otherwise folds the sign
+// extensions into a quarter-rate 32-bit multiply).
+__device__ __forceinline__ int mul24_lo(int a, int b) {
+  int r;
+  asm("v_mul_i32_i24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // Global-memory view of a pointer held in a descriptor: lets the compiler use
 // global (not flat) loads, stores and atomics.
 template <class T> using gptr = T __attribute__((address_space(1))) *;
@@ -317,13 +332,15 @@ void launch_cont3(const double *rn, const double *ro, const A *J, int n1, int n2
                   double dt, double f1, double f2, double f3, double idx1, double idx2,
                   double idx3, double *partial, int nblocks, hipStream_t s);
 void launch_rho_fixed(const Run<float> *run_dev, int pp, int np, long long *rho, hipStream_t s);
-// 2D with the cubic shape: push + deposit (items: run, tile), and the FP64
-// charge density
+// 2D with the cubic shape: push + deposit (items: run, tile; unit: every
+// run's |charge| 2^P fits the 24-bit products), and the charge density in the
+// deposit's units (FP32 form: integers, FP64 form: physical)
 template <class R>
 void launch_push_cubic(const Run<R> *runs, const Item *items, int nitems, int parity, int pp,
-                       int lds_bytes, bool ec, unsigned *err, hipStream_t s);
+                       int lds_bytes, bool unit, bool ec, unsigned *err, hipStream_t s);
 template <class R>
-void launch_rho_cubic(const Run<R> *run_dev, int pp, int np, double *rho, hipStream_t s);
+void launch_rho_cubic(const Run<R> *run_dev, int pp, int np, typename AccOf<R>::T *rho,
+                      hipStream_t s);
 void launch_rho_fp64(const Run<double> *run_dev, int pp, int np, double *rho, hipStream_t s);
 template <class R>
 void launch_energy(const R *F, long long cells, double *partial, int nblocks, hipStream_t s);

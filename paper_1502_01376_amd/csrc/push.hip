@@ -219,21 +219,6 @@ struct LdsFp64 {
   }
 };
 
-// Exact product of two integers in [-2^23, 2^23) as a 64-bit value.  The
-// explicit sign extension from 24 bits lets the compiler select the full-rate
-// v_mul_i32_i24 / v_mul_hi_i32_i24 pair.
-__device__ __forceinline__ long long mul24_wide(int a, int b) {
-  return (long long)((a << 8) >> 8) * (long long)((b << 8) >> 8);
-}
-// Product of two integers in [-2^23, 2^23) whose value fits 32 bits: one
-// v_mul_i32_i24 (written out, as the compiler otherwise folds the sign
-// extensions into a quarter-rate 32-bit multiply).
-__device__ __forceinline__ int mul24_lo(int a, int b) {
-  int r;
-  asm("v_mul_i32_i24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
-
 // Fixed-point Esirkepov deposit of one particle (2D).  Integer shapes with
 // exact sum 2^P make 2 (rho_new - rho_old) = div J hold exactly in the
 // integers; j3 is FP32 rounded once per node.  The arithmetic is the one of the

@@ -9,10 +9,11 @@
 // bounds its tile's particle cells, accumulates the current of all of them
 // into one LDS box (a move is under a cell: columns and rows -2 .. +3 around
 // the cells) and adds the box to the global accumulators at the end; a box
-// too large for LDS falls back to global atomics.  FP32 form: Esirkepov weights
-// in FP32, each node's contribution rounded once to an integer (|v| < 2^31)
-// and accumulated in 64 bits, so the sums do not depend on the order; FP64
-// form: physical current in FP64.
+// too large for LDS falls back to global atomics.  FP32 form: integer cubic
+// weights with exact sum 2^P and the integer Esirkepov products of the
+// quadratic kernel, so 2 (rho_new - rho_old) = div J holds exactly in the
+// integers and the sums do not depend on the order; FP64 form: physical
+// current in FP64.
 #include "hpic_internal.h"
 
 namespace hp {
@@ -130,19 +131,29 @@ __device__ __forceinline__ R gather_c(const R *__restrict__ F, int n1, int n2, i
   return acc;
 }
 
-__device__ __forceinline__ long long fixc(float v) { return (long long)(int)rintf(v); }
-__device__ __forceinline__ double fixc(double v) { return v; }
+// Integer cubic weights of the nodes m-1 .. m+2 for a position m + d: the
+// spline values in FP32 (no contraction, so every call site computes the same
+// integers from the same offset) scaled by 2^P and rounded, the node m+1
+// taking the remainder, so the four sum to 2^P exactly.  |error| of each is a
+// few units of 2^-P.
+__device__ __forceinline__ void cubic_fixed(float d, int P, int s[4]) {
+#pragma clang fp contract(off)
+  const float e = 1.0f - d;
+  const float sc = (float)(1 << P) * (1.0f / 6.0f);
+  s[0] = (int)rintf(e * e * e * sc);
+  s[1] = (int)rintf((4.0f - 6.0f * d * d + 3.0f * d * d * d) * sc);
+  s[3] = (int)rintf(d * d * d * sc);
+  s[2] = (1 << P) - s[0] - s[1] - s[3];
+}
 
-// deposit targets
+// deposit targets (values already in the accumulator's type)
 template <class A>
 struct SinkLdsC {
   lptrc<A> box;
   int H, W, c0, r0;  // window origin in the box
-  template <class V>
-  __device__ __forceinline__ void operator()(int comp, int b, int a, V v) const {
-    const auto q = fixc(v);
-    if (q != 0)
-      __hip_atomic_fetch_add(box + (comp * H + (r0 + b)) * W + (c0 + a), q, __ATOMIC_RELAXED,
+  __device__ __forceinline__ void operator()(int comp, int b, int a, A v) const {
+    if (v != A(0))
+      __hip_atomic_fetch_add(box + (comp * H + (r0 + b)) * W + (c0 + a), v, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 };
@@ -151,18 +162,16 @@ struct SinkGlobC {
   A *J;
   long long cells;
   int n1, n2, c0, r0;  // window origin (global, unwrapped)
-  template <class V>
-  __device__ __forceinline__ void operator()(int comp, int b, int a, V v) const {
-    const auto q = fixc(v);
-    if (q != 0)
+  __device__ __forceinline__ void operator()(int comp, int b, int a, A v) const {
+    if (v != A(0))
       __hip_atomic_fetch_add(G(J) + comp * cells + (long long)wrap_small(r0 + b, n2) * n1 +
                                  wrap_pow2(c0 + a, n1),
-                             q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                             v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 };
 
-// Esirkepov deposit over the 5 x 5 window: J1 = C1 T2 g1, J2 = C2 T1 g2 (C the
-// running sums of S1 - S0, T = (S0 + S1)/2), J3 = W3 g3.
+// FP64 Esirkepov deposit over the 5 x 5 window: J1 = C1 T2 g1, J2 = C2 T1 g2
+// (C the running sums of S1 - S0, T = (S0 + S1)/2), J3 = W3 g3.
 template <class R, class Sink>
 __device__ __forceinline__ void deposit_c(const Sink &put, const R S0x[5], const R S1x[5],
                                           const R S0y[5], const R S1y[5], R g1, R g2, R g3) {
@@ -200,6 +209,71 @@ __device__ __forceinline__ void deposit_c(const Sink &put, const R S0x[5], const
   }
 }
 
+// Fixed-point Esirkepov deposit over the 5 x 5 window from integer weights
+// with exact sum 2^P: J1 = Q C1[a] A2[b], J2 = Q C2[b] A1[a] (C the running
+// sums of S1 - S0, A = S0 + S1) as exact integer products, so the integer
+// divergence equals twice the integer change of Q S_x S_y node by node; J3 as
+// the quadratic kernel's: rint(x0 t0 + x1 t1), x = S h, t0 = 2 S0y + S1y,
+// t1 = S0y + 2 S1y (|value| < 2^31 by the choice of c3).  UNIT: |Q C| and A
+// fit 24 signed bits, so each product is one full-rate 24-bit pair.
+template <bool UNIT, class Sink>
+__device__ __forceinline__ void deposit_cf(const Sink &put, const int S0x[5], const int S1x[5],
+                                           const int S0y[5], const int S1y[5], int Q, float h) {
+#pragma clang fp contract(off)
+  int C1[5], C2[5], A1[5], A2[5];
+  int a1 = 0, a2 = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    a1 += S1x[k] - S0x[k];
+    a2 += S1y[k] - S0y[k];
+    C1[k] = a1;
+    C2[k] = a2;
+    A1[k] = S0x[k] + S1x[k];
+    A2[k] = S0y[k] + S1y[k];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    if (C1[a] == 0) continue;
+    const int qc = UNIT ? mul24_lo(Q, C1[a]) : 0;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      const long long v = UNIT ? mul24_wide(qc, A2[b])
+                               : ((long long)Q * (long long)C1[a]) * (long long)A2[b];
+      put(0, b, a, v);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    if (C2[b] == 0) continue;
+    const int qc = UNIT ? mul24_lo(Q, C2[b]) : 0;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      const long long v = UNIT ? mul24_wide(qc, A1[a])
+                               : ((long long)Q * (long long)C2[b]) * (long long)A1[a];
+      put(1, b, a, v);
+    }
+  }
+  float x0[5], x1[5];
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    x0[a] = (float)S0x[a] * h;
+    x1[a] = (float)S1x[a] * h;
+  }
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    const float B0 = (float)S0y[b], B1 = (float)S1y[b];
+    if (B0 == 0.0f && B1 == 0.0f) continue;
+    const float t0 = 2.0f * B0 + B1;
+    const float t1 = B0 + 2.0f * B1;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      const float p1 = x1[a] * t1;
+      const float v = __builtin_fmaf(x0[a], t0, p1);
+      put(2, b, a, (long long)(int)rintf(v));
+    }
+  }
+}
+
 template <class R>
 __device__ __forceinline__ void place5(const R s[4], int off, R out[5]) {
   out[0] = off ? R(0) : s[0];
@@ -216,7 +290,7 @@ __device__ __forceinline__ void place5(const R s[4], int off, R out[5]) {
 // current box (bounds -2 .. +3) is accumulated in LDS by all of them and added
 // to the global accumulators at the end; a box too large for LDS falls back to
 // global atomics.
-template <class R, bool EC>
+template <class R, bool UNIT, bool EC>
 __global__ void __launch_bounds__(256) k_push_deposit_cubic(const Run<R> *__restrict__ runs,
                                                             const Item *__restrict__ items,
                                                             int parity, int pp, int lds_bytes,
@@ -322,35 +396,38 @@ __global__ void __launch_bounds__(256) k_push_deposit_cubic(const Run<R> *__rest
     const int d1 = advc<R>(f1, m1, g1);
     const int d2 = advc<R>(f2, m2, g2);
     // window: nodes from min(cell_old, cell_new) - 1, five per axis
-    R sa[4], sb[4], S0x[5], S1x[5], S0y[5], S1y[5];
-    cubic4<R>(f1, sa);
-    cubic4<R>(g1, sb);
-    const int o1 = min(0, d1);  // window origin relative to i1 - 1
-    place5<R>(sa, 0 - o1, S0x);
-    place5<R>(sb, d1 - o1, S1x);
-    cubic4<R>(f2, sa);
-    cubic4<R>(g2, sb);
-    const int o2 = min(0, d2);
-    place5<R>(sa, 0 - o2, S0y);
-    place5<R>(sb, d2 - o2, S1y);
-    R gj1, gj2, gj3;
-    if constexpr (sizeof(R) == 4) {
-      const R gq = qw * r.inv_wunit * r.cj;
-      gj1 = gq;
-      gj2 = gq;
-      gj3 = gq * v[2];
-    } else {
-      gj1 = qw * r.jfx1;
-      gj2 = qw * r.jfx2;
-      gj3 = qw * v[2];
-    }
-    if (use_lds) {
-      SinkLdsC<A> K{box, H, W, rel1 - 1 + o1 - lo1, rel2 - 1 + o2 - lo2};
-      deposit_c<R>(K, S0x, S1x, S0y, S1y, gj1, gj2, gj3);
-    } else {
-      SinkGlobC<A> K{r.J[parity], cells, n1, n2, i1 - 1 + o1, i2 - 1 + o2};
-      deposit_c<R>(K, S0x, S1x, S0y, S1y, gj1, gj2, gj3);
-    }
+    const int o1 = min(0, d1), o2 = min(0, d2);  // window origin relative to i - 1
+    auto deposit = [&](const auto &K) {
+      if constexpr (sizeof(R) == 4) {
+        int sa[4], sb[4], S0x[5], S1x[5], S0y[5], S1y[5];
+        cubic_fixed(f1, r.P, sa);
+        cubic_fixed(g1, r.P, sb);
+        place5<int>(sa, 0 - o1, S0x);
+        place5<int>(sb, d1 - o1, S1x);
+        cubic_fixed(f2, r.P, sa);
+        cubic_fixed(g2, r.P, sb);
+        place5<int>(sa, 0 - o2, S0y);
+        place5<int>(sb, d2 - o2, S1y);
+        const float qs = qw * r.inv_wunit;
+        const float hv = qs * v[2];
+        deposit_cf<UNIT>(K, S0x, S1x, S0y, S1y, (int)rintf(qs), hv * r.c3);
+      } else {
+        R sa[4], sb[4], S0x[5], S1x[5], S0y[5], S1y[5];
+        cubic4<R>(f1, sa);
+        cubic4<R>(g1, sb);
+        place5<R>(sa, 0 - o1, S0x);
+        place5<R>(sb, d1 - o1, S1x);
+        cubic4<R>(f2, sa);
+        cubic4<R>(g2, sb);
+        place5<R>(sa, 0 - o2, S0y);
+        place5<R>(sb, d2 - o2, S1y);
+        deposit_c<R>(K, S0x, S1x, S0y, S1y, qw * r.jfx1, qw * r.jfx2, qw * v[2]);
+      }
+    };
+    if (use_lds)
+      deposit(SinkLdsC<A>{box, H, W, rel1 - 1 + o1 - lo1, rel2 - 1 + o2 - lo2});
+    else
+      deposit(SinkGlobC<A>{r.J[parity], cells, n1, n2, i1 - 1 + o1, i2 - 1 + o2});
     const int j1 = wrap_pow2(i1 + d1, n1), j2 = wrap_small(i2 + d2, n2);
     G(P.cell)[p] = (j2 << r.log2n1) | j1;
     G(P.f1)[p] = g1;
@@ -376,49 +453,76 @@ __global__ void __launch_bounds__(256) k_push_deposit_cubic(const Run<R> *__rest
   }
 }
 
-// FP64 charge density of a run's particles with the cubic shape.
+// Charge density of a run's particles with the cubic shape in the deposit's
+// units: FP32 form Q S_x S_y with the integer weights of the deposit (so the
+// integer continuity check is exact), FP64 form q w S_x S_y.
 template <class R>
 __global__ void __launch_bounds__(256) k_rho_cubic(const Run<R> *__restrict__ run, int pp,
-                                                   double *rho) {
+                                                   typename AccOf<R>::T *rho) {
   const Run<R> &r = *run;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= r.np) return;
   const Parts<R> P = r.pt[pp];
   const int cell = P.cell[p];
   const int i1 = cell & (r.n1 - 1), i2 = cell >> r.log2n1;
-  double w1[4], w2[4];
-  cubic4<double>((double)P.f1[p], w1);
-  cubic4<double>((double)P.f2[p], w2);
-  const double q = (double)P.qw[p];
-  for (int b = 0; b < 4; ++b) {
-    const long long row = (long long)wrap_small(i2 - 1 + b, r.n2) * r.n1;
-    for (int a = 0; a < 4; ++a)
-      unsafeAtomicAdd(rho + row + wrap_pow2(i1 - 1 + a, r.n1), q * w1[a] * w2[b]);
+  if constexpr (sizeof(R) == 4) {
+    int w1[4], w2[4];
+    cubic_fixed(P.f1[p], r.P, w1);
+    cubic_fixed(P.f2[p], r.P, w2);
+    const long long Q = (long long)rintf(P.qw[p] * r.inv_wunit);
+    for (int b = 0; b < 4; ++b) {
+      const long long row = (long long)wrap_small(i2 - 1 + b, r.n2) * r.n1;
+      for (int a = 0; a < 4; ++a) {
+        const long long v = Q * (long long)w1[a] * (long long)w2[b];
+        if (v != 0)
+          atomicAdd((unsigned long long *)(rho + row + wrap_pow2(i1 - 1 + a, r.n1)),
+                    (unsigned long long)v);
+      }
+    }
+  } else {
+    double w1[4], w2[4];
+    cubic4<double>(P.f1[p], w1);
+    cubic4<double>(P.f2[p], w2);
+    const double q = P.qw[p];
+    for (int b = 0; b < 4; ++b) {
+      const long long row = (long long)wrap_small(i2 - 1 + b, r.n2) * r.n1;
+      for (int a = 0; a < 4; ++a)
+        unsafeAtomicAdd(rho + row + wrap_pow2(i1 - 1 + a, r.n1), q * w1[a] * w2[b]);
+    }
   }
 }
 
 template <class R>
 void launch_push_cubic(const Run<R> *runs, const Item *items, int nitems, int parity, int pp,
-                       int lds_bytes, bool ec, unsigned *err, hipStream_t s) {
+                       int lds_bytes, bool unit, bool ec, unsigned *err, hipStream_t s) {
   if (nitems <= 0) return;
   lds_bytes = min(lds_bytes, CLDS_BYTES);
-  if (ec)
-    hipLaunchKernelGGL((k_push_deposit_cubic<R, true>), dim3(nitems), dim3(256),
-                       (size_t)lds_bytes, s, runs, items, parity, pp, lds_bytes, err);
-  else
-    hipLaunchKernelGGL((k_push_deposit_cubic<R, false>), dim3(nitems), dim3(256),
-                       (size_t)lds_bytes, s, runs, items, parity, pp, lds_bytes, err);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(nitems), dim3(256), (size_t)lds_bytes, s, runs, items, parity,
+                       pp, lds_bytes, err);
+  };
+  // UNIT selects the 24-bit integer products of the FP32 form; the FP64 form
+  // has no integer products and is instantiated without it
+  constexpr bool U = sizeof(R) == 4;
+  if (U && unit) {
+    if (ec) go(k_push_deposit_cubic<R, U, true>);
+    else go(k_push_deposit_cubic<R, U, false>);
+  } else {
+    if (ec) go(k_push_deposit_cubic<R, false, true>);
+    else go(k_push_deposit_cubic<R, false, false>);
+  }
 }
 template <class R>
-void launch_rho_cubic(const Run<R> *run_dev, int pp, int np, double *rho, hipStream_t s) {
+void launch_rho_cubic(const Run<R> *run_dev, int pp, int np, typename AccOf<R>::T *rho,
+                      hipStream_t s) {
   if (np <= 0) return;
   hipLaunchKernelGGL(k_rho_cubic<R>, dim3((np + 255) / 256), dim3(256), 0, s, run_dev, pp, rho);
 }
 template void launch_push_cubic<float>(const Run<float> *, const Item *, int, int, int, int, bool,
-                                       unsigned *, hipStream_t);
+                                       bool, unsigned *, hipStream_t);
 template void launch_push_cubic<double>(const Run<double> *, const Item *, int, int, int, int,
-                                        bool, unsigned *, hipStream_t);
-template void launch_rho_cubic<float>(const Run<float> *, int, int, double *, hipStream_t);
+                                        bool, bool, unsigned *, hipStream_t);
+template void launch_rho_cubic<float>(const Run<float> *, int, int, long long *, hipStream_t);
 template void launch_rho_cubic<double>(const Run<double> *, int, int, double *, hipStream_t);
 
 }  // namespace hp

@@ -332,10 +332,9 @@ class Sim : public SimBase {
       id[p] = (int)p;
       count[((size_t)c3 * d.n2 + c2) * d.n1 + c1]++;
     }
-    if (FIXED && n > 0 && (three || d.shape == 3)) {
+    if (FIXED && n > 0 && three) {
       // 3D: each node's contribution is at most 3.4 cj in integers, a node
-      // collects from the particles of 4 x 4 x 4 cells (2D cubic: at most cj
-      // from 5 x 5 cells)
+      // collects from the particles of 4 x 4 x 4 cells
       if (!(qmax > 0.0)) return fail(HP_EINVAL, "all particle charges are zero");
       const int cmax = *std::max_element(count.begin(), count.end());
       if (64.0 * std::max(cmax, 1) * 4.0 * CJ3 >= std::ldexp(1.0, 62))
@@ -347,9 +346,12 @@ class Sim : public SimBase {
     } else if (FIXED && n > 0) {
       if (!(qmax > 0.0)) return fail(HP_EINVAL, "all particle charges are zero");
       const int cmax = *std::max_element(count.begin(), count.end());
-      // per node |J| <= 24 * (particles per cell) * 2^(2P+Q): keep below 2^62
+      // per node |J| <= K * (particles per cell) * 2^(2P+Q): keep below 2^62.
+      // Quadratic: 3 x 3 cells reach a node, |C| <= 2^P, A <= 1.5 2^P (K = 24);
+      // cubic: 5 x 5 cells, A <= (4/3) 2^P (K = 34)
+      const double K = d.shape == 3 ? 34.0 : 24.0;
       auto room_for = [&](int P) {
-        return std::ldexp(1.0, 62 - 2 * P) / (24.0 * std::max(cmax, 1));
+        return std::ldexp(1.0, 62 - 2 * P) / (K * std::max(cmax, 1));
       };
       // automatic shape bits: 22 when all charges are equal (no charge bits
       // needed, products still fit 24 bits), else 20
@@ -420,7 +422,7 @@ class Sim : public SimBase {
     }
     if (rho_from_particles) {
       int rc;
-      if (d.dim == 3 || d.shape == 3) {
+      if (d.dim == 3) {
         if (!h.rho0_3 && (rc = alloc(&h.rho0_3, (size_t)d.cells))) return rc;
         if ((rc = deposit_rho3(run, h.rho0_3))) return rc;
       } else {
@@ -447,8 +449,8 @@ class Sim : public SimBase {
       Launch<R>::push_deposit3(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, d_err_, d_stats_,
                                stream_);
     else if (runs_[0].d.shape == 3)
-      launch_push_cubic<R>(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, runs_[0].cfg.interp == 1,
-                           d_err_, stream_);
+      launch_push_cubic<R>(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, all_unit(),
+                           runs_[0].cfg.interp == 1, d_err_, stream_);
     else
       Launch<R>::push_deposit(d_runs_, d_tiles_, n_tiles_, p, pp_, push_lds_, all_unit(),
                               runs_[0].cfg.interp == 1, d_err_,
@@ -859,7 +861,7 @@ class Sim : public SimBase {
   }
 
   int diagnostics(int run, hp_diag *out) override {
-    if (runs_[run].d.dim == 3 || runs_[run].d.shape == 3) return diagnostics3(run, out);
+    if (runs_[run].d.dim == 3) return diagnostics3(run, out);
     RunHost &h = runs_[run];
     Run<R> &d = h.d;
     const size_t cells = (size_t)d.n1 * d.n2;
@@ -966,7 +968,6 @@ class Sim : public SimBase {
 
   // ---- checkpoint: header + per run raw arrays (bit-exact resume)
   int get_state(void *blob, size_t *size) override {
-    if (runs_[0].d.shape == 3) return fail(HP_EINVAL, "checkpoints are not available with the cubic shape");
     int rc;
     if ((rc = sync())) return rc;
     size_t need = state_size();
@@ -1016,7 +1017,6 @@ class Sim : public SimBase {
   }
 
   int set_state(const void *blob, size_t size) override {
-    if (runs_[0].d.shape == 3) return fail(HP_EINVAL, "checkpoints are not available with the cubic shape");
     const char *o = (const char *)blob;
     const char *end = o + size;
     auto take = [&](void *dst, size_t bytes) {
@@ -1138,7 +1138,7 @@ class Sim : public SimBase {
   int fixed_params(int run, double *out) override {
     if (!FIXED) return fail(HP_EINVAL, "fixed-point parameters exist only in the FP32 form");
     const RunHost &h = runs_[run];
-    const bool fw = h.d.dim == 3 || h.d.shape == 3;  // FP32 weights, integer contributions
+    const bool fw = h.d.dim == 3;  // FP32 weights, integer contributions
     out[0] = fw ? 0 : h.d.P;
     out[1] = h.d.inv_wunit;
     out[2] = fw ? h.d.cj : h.d.c3;
@@ -1349,10 +1349,7 @@ class Sim : public SimBase {
   int deposit_rho3(int run, double *rho) {
     RunHost &h = runs_[run];
     HIPCHK(hipMemsetAsync(rho, 0, sizeof(double) * (size_t)h.d.cells, stream_));
-    if (h.d.shape == 3)
-      launch_rho_cubic<R>(d_runs_ + run, pp_, (int)h.np, rho, stream_);
-    else
-      launch_rho3<R>(d_runs_ + run, pp_, (int)h.np, rho, stream_);
+    launch_rho3<R>(d_runs_ + run, pp_, (int)h.np, rho, stream_);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream_));
     return HP_OK;
@@ -1362,9 +1359,6 @@ class Sim : public SimBase {
     if (!FIXED) return 1.0;
     if (h.d.dim == 3)
       return -(h.cfg.dx[comp] / h.cfg.dt) / (6.0 * (double)h.d.inv_wunit * (double)h.d.cj);
-    if (h.d.shape == 3)  // 2D cubic: C T (qw inv_wunit cj) and W3 v3 (qw inv_wunit cj)
-      return (comp < 2 ? -(h.cfg.dx[comp] / h.cfg.dt) : 1.0) /
-             ((double)h.d.inv_wunit * (double)h.d.cj);
     const int P = h.d.P;
     const double iw = (double)h.d.inv_wunit;
     if (comp == 0) return -(h.cfg.dx[0] / h.cfg.dt) / (iw * std::ldexp(1.0, 2 * P + 1));
@@ -1397,7 +1391,9 @@ class Sim : public SimBase {
     const Run<R> &d = h.d;
     const size_t cells = (size_t)d.n1 * d.n2;
     HIPCHK(hipMemsetAsync(rho, 0, sizeof(Acc) * cells, stream_));
-    if constexpr (FIXED)
+    if (d.shape == 3)
+      launch_rho_cubic<R>(d_runs_ + run, pp_, (int)h.np, rho, stream_);
+    else if constexpr (FIXED)
       launch_rho_fixed(d_runs_ + run, pp_, (int)h.np, rho, stream_);
     else
       launch_rho_fp64(d_runs_ + run, pp_, (int)h.np, rho, stream_);
