@@ -935,26 +935,28 @@ int or_gauss3(const or_grid3 *g, const double *E, const double *rho, double *Rre
 /* ---- 3D deposit in the kernel's precision ----
  * The product of three shape factors does not fit the 64-bit budget of an
  * exact integer scheme with arbitrary charges, so the 3D FP32 form computes
- * the Esirkepov weights in FP32 and rounds each node's contribution once to an
- * integer (the integers then add up in any order to the same 64-bit total).
- * Per coordinate, FP32 shape factors at the three nodes around the nearest
- * node m (d = offset from m, exact):
+ * the Esirkepov weights of its FP32 particle offsets in FP64 and rounds each
+ * node's contribution once to an integer on a fine scale (cj = 2^40 per unit
+ * charge); the integers then add up in any order to the same 64-bit total, and
+ * continuity (Eq. (23)) holds to about 2^-41 of a particle's charge per node
+ * and step instead of to FP32 rounding.  Per coordinate, FP64 shape factors at
+ * the three nodes around the nearest node m (d = offset from m, exact):
  *   a = 0.5 - d, b = 0.5 + d:  s(-1) = 0.5 (a a),  s(0) = 0.75 - d d,  s(+1) = 0.5 (b b)
  * placed on the common 4-node window; DS = S1 - S0; running sums
  * C[k] = C[k-1] + DS[k] in order.  For component d with the other two axes
  * (e, f) in cyclic order:
  *   u0[j] = 2 S0_f[j] + S1_f[j],  u1[j] = S0_f[j] + 2 S1_f[j]
- *   T[i][j] = fma(S0_e[i], u0[j], S1_e[i] u1[j])      (6 times the Esirkepov bracket)
- *   J_d[k][i][j] += rint((C_d[k] g) T[i][j]),  g = qw inv_wunit cj,  k = 0..2
- * each FP32 operation rounded once in this order, so that
- * j_d = -(dx_d / dt) J_d / (6 inv_wunit cj).  |J| per particle <= 6 cj < 2^31. */
-static int32_t fshape3(int32_t cell, float f, float s[3]) {
+ *   T[i][j] = S0_e[i] u0[j] + S1_e[i] u1[j]          (6 times the Esirkepov bracket)
+ *   J_d[k][i][j] += rint((C_d[k] g) T[i][j]),  g = (qw inv_wunit) cj,  k = 0..2
+ * each FP64 operation rounded once in this order (no contraction), so that
+ * j_d = -(dx_d / dt) J_d / (6 inv_wunit cj).  |J| per particle <= 6 cj. */
+static int32_t dshape3_fixed(int32_t cell, float f, double s[3]) {
   int32_t up = (f >= 0.5f);
-  float d = up ? (f - 1.0f) : f;
-  float a = 0.5f - d, b = 0.5f + d;
-  s[0] = 0.5f * (a * a);
-  s[1] = 0.75f - d * d;
-  s[2] = 0.5f * (b * b);
+  double d = up ? ((double)f - 1.0) : (double)f;
+  double a = 0.5 - d, b = 0.5 + d;
+  s[0] = 0.5 * (a * a);
+  s[1] = 0.75 - d * d;
+  s[2] = 0.5 * (b * b);
   return cell + up;
 }
 
@@ -968,47 +970,47 @@ int or_deposit3_fixed(int32_t n1, int32_t n2, int32_t n3, float inv_wunit, float
   const int32_t n[3] = {n1, n2, n3};
   int status = 0;
   for (int64_t p = 0; p < np; ++p) {
-    float S0[3][4], S1[3][4], C[3][4];
+    double S0[3][4], S1[3][4], C[3][4];
     int32_t base[3], bad = 0;
     for (int d = 0; d < 3; ++d) {
       int32_t dd = wrap_delta(cb[d * np + p] - ca[d * np + p], n[d]);
       if (dd < -1 || dd > 1) bad = 1;
-      float sa[3], sb[3];
-      int32_t na = fshape3(ca[d * np + p], fa[d * np + p], sa);
-      int32_t nb = fshape3(ca[d * np + p] + dd, fb[d * np + p], sb);
+      double sa[3], sb[3];
+      int32_t na = dshape3_fixed(ca[d * np + p], fa[d * np + p], sa);
+      int32_t nb = dshape3_fixed(ca[d * np + p] + dd, fb[d * np + p], sb);
       if (na - nb > 1 || nb - na > 1) bad = 1;
       base[d] = (na < nb ? na : nb) - 1;
-      for (int k = 0; k < 4; ++k) S0[d][k] = S1[d][k] = 0.0f;
+      for (int k = 0; k < 4; ++k) S0[d][k] = S1[d][k] = 0.0;
       if (!bad)
         for (int k = 0; k < 3; ++k) {
           S0[d][na - 1 - base[d] + k] = sa[k];
           S1[d][nb - 1 - base[d] + k] = sb[k];
         }
-      float acc = 0.0f;
+      double acc = 0.0;
       for (int k = 0; k < 4; ++k) {
         acc = acc + (S1[d][k] - S0[d][k]);
         C[d][k] = acc;
       }
     }
     if (bad) { status = -1; continue; }
-    float gq = (qw[p] * inv_wunit) * cj;
+    double gq = ((double)qw[p] * (double)inv_wunit) * (double)cj;
     for (int d = 0; d < 3; ++d) {
       int e = (d + 1) % 3, f = (d + 2) % 3;
-      float u0[4], u1[4];
+      double u0[4], u1[4];
       for (int j = 0; j < 4; ++j) {
-        u0[j] = 2.0f * S0[f][j] + S1[f][j];
-        u1[j] = S0[f][j] + 2.0f * S1[f][j];
+        u0[j] = 2.0 * S0[f][j] + S1[f][j];
+        u1[j] = S0[f][j] + 2.0 * S1[f][j];
       }
       for (int k = 0; k < 3; ++k) {
-        float cg = C[d][k] * gq;
+        double cg = C[d][k] * gq;
         for (int i = 0; i < 4; ++i)
           for (int j = 0; j < 4; ++j) {
-            float T = fmaf(S0[e][i], u0[j], S1[e][i] * u1[j]);
+            double T = S0[e][i] * u0[j] + S1[e][i] * u1[j];
             int64_t m[3];
             m[d] = base[d] + k;
             m[e] = base[e] + i;
             m[f] = base[f] + j;
-            J[d * cells + idx3(&g, m[0], m[1], m[2])] += (int64_t)rintf(cg * T);
+            J[d * cells + idx3(&g, m[0], m[1], m[2])] += (int64_t)rint(cg * T);
           }
       }
     }

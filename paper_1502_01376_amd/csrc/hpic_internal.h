@@ -257,6 +257,16 @@ __device__ __forceinline__ int mul24_lo(int a, int b) {
   return r;
 }
 
+// Nearest integer (ties to even) of |v| < 2^51 as a 64-bit integer: adding
+// 1.5 2^52 rounds v to an integer held in the low mantissa bits (one FP64 add
+// and one 64-bit subtract instead of the multi-instruction FP64 -> int64
+// conversion).
+__device__ __forceinline__ long long rint_i64(double v) {
+#pragma clang fp contract(off)
+  const double t = v + 6755399441055744.0;
+  return __double_as_longlong(t) - 0x4338000000000000LL;
+}
+
 // Global-memory view of a pointer held in a descriptor: lets the compiler use
 // global (not flat) loads, stores and atomics.
 template <class T> using gptr = T __attribute__((address_space(1))) *;

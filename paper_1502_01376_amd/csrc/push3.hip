@@ -108,19 +108,12 @@ __device__ __forceinline__ int advance3(R f, R d, R &g) {
   return s;
 }
 
-// FP32 shape factors of one coordinate at the nodes m-1, m, m+1 around the
-// nearest node m = cell + (f >= 1/2); d = offset from m (exact).
-__device__ __forceinline__ int fshape3(int cell, float f, float s[3]) {
-#pragma clang fp contract(off)
-  const int up = (f >= 0.5f) ? 1 : 0;
-  const float d = up ? (f - 1.0f) : f;
-  const float a = 0.5f - d, b = 0.5f + d;
-  s[0] = 0.5f * (a * a);
-  s[1] = 0.75f - d * d;
-  s[2] = 0.5f * (b * b);
-  return cell + up;
-}
+// FP64 shape factors of one coordinate at the nodes m-1, m, m+1 around the
+// nearest node m = cell + (f >= 1/2); d = offset from m (exact).  No
+// contraction: the FP32 form's integer deposit is defined operation by
+// operation.
 __device__ __forceinline__ int dshape3(int cell, double f, double s[3]) {
+#pragma clang fp contract(off)
   const int up = (f >= 0.5) ? 1 : 0;
   const double d = up ? (f - 1.0) : f;
   const double a = 0.5 - d, b = 0.5 + d;
@@ -184,25 +177,29 @@ struct Sink3GlobalF64 {
 //   T[i][j] = S0e[i] (2 S0f[j] + S1f[j]) + S1e[i] (S0f[j] + 2 S1f[j])
 //           (6 times the Esirkepov bracket), C[k] = running sum of S1d - S0d,
 //   J_d[k][i][j] += C[k] g T[i][j],  k = 0..2.
-// FP32 form: g = qw inv_wunit cj, every FP32 operation rounded once in the
-// order written, the node value rounded to an integer (j_d = -(dx_d/dt) J /
-// (6 inv_wunit cj)).  FP64 form: g = qw (-dx_d/dt) / 6, physical current.
+// FP32 form: the weights of the FP32 offsets in FP64, g = (qw inv_wunit) cj
+// with cj = 2^40, every FP64 operation rounded once in the order written, the
+// node value rounded to a 64-bit integer (j_d = -(dx_d/dt) J / (6 inv_wunit
+// cj)): the sums are independent of the order of the atomics and continuity
+// holds to about 2^-41 of a particle's charge per node and step (with FP32
+// weights and a 2^28 scale, long drifting-beam runs grew a spurious k1 = 0
+// mode).  FP64 form: g = qw (-dx_d/dt) / 6, physical current.
 template <class Sink>
 __device__ __forceinline__ void deposit3_fixed(const Sink &K, float inv_wunit, float cj,
                                                const int l[3], const float fa[3], const int dd[3],
                                                const float fb[3], float qw) {
 #pragma clang fp contract(off)
-  float S0[3][4], S1[3][4], C[3][4];
+  double S0[3][4], S1[3][4], C[3][4];
   int o[3][4];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    float sa[3], sb[3];
-    const int na = fshape3(l[d], fa[d], sa);
-    const int nb = fshape3(l[d] + dd[d], fb[d], sb);
+    double sa[3], sb[3];
+    const int na = dshape3(l[d], (double)fa[d], sa);
+    const int nb = dshape3(l[d] + dd[d], (double)fb[d], sb);
     const int base = min(na, nb) - 1;
     place4_3(sa, na - 1 - base, S0[d]);
     place4_3(sb, nb - 1 - base, S1[d]);
-    float acc = 0.0f;
+    double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       acc = acc + (S1[d][k] - S0[d][k]);
@@ -210,30 +207,28 @@ __device__ __forceinline__ void deposit3_fixed(const Sink &K, float inv_wunit, f
       o[d][k] = K.offs(d, base + k);
     }
   }
-  const float gq = (qw * inv_wunit) * cj;
+  const double gq = ((double)qw * (double)inv_wunit) * (double)cj;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int e = (d + 1) % 3, f = (d + 2) % 3;
-    float u0[4], u1[4], T[4][4];
+    double u0[4], u1[4], T[4][4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      u0[j] = 2.0f * S0[f][j] + S1[f][j];
-      u1[j] = S0[f][j] + 2.0f * S1[f][j];
+      u0[j] = 2.0 * S0[f][j] + S1[f][j];
+      u1[j] = S0[f][j] + 2.0 * S1[f][j];
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) T[i][j] = __builtin_fmaf(S0[e][i], u0[j], S1[e][i] * u1[j]);
+      for (int j = 0; j < 4; ++j) T[i][j] = S0[e][i] * u0[j] + S1[e][i] * u1[j];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const float cg = C[d][k] * gq;
+      const double cg = C[d][k] * gq;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float v = rintf(cg * T[i][j]);
-          K.add(d, o[d][k] + o[e][i] + o[f][j], (long long)(int)v);
-        }
+        for (int j = 0; j < 4; ++j)
+          K.add(d, o[d][k] + o[e][i] + o[f][j], rint_i64(cg * T[i][j]));
     }
   }
 }

@@ -27,8 +27,12 @@
 //
 // One thread per particle; each wave accumulates into an LDS box (global
 // atomics if its particles spread too far), then adds the box to the global
-// accumulators.  FP32 form: 64-bit integers of the rounded FP32 contributions,
-// so the sums do not depend on the order.
+// accumulators.  The deposit's arithmetic (shapes, phases and fluxes of the
+// stored positions, their radius and direction in R) is FP64 in both forms; the FP32 form rounds each contribution once to
+// a 64-bit integer on a fine scale (2^40 per unit charge), so the sums do not
+// depend on the order and continuity holds to about 2^-41 of a particle's
+// charge per node and step.  (With FP32 weights and a 2^28 scale, long
+// drifting-beam runs grew a spurious k1 = 0 mode.)
 #include "hpic_q3d.h"
 
 namespace hp {
@@ -58,6 +62,7 @@ template <class R> __device__ __forceinline__ int ifloorq(R x) { return (int)flo
 // S = (ix + fx)^2 + (iy + fy)^2, d = (S - m^2) / (r/dr + m).
 template <class R>
 __device__ __forceinline__ void radial(int ix, R fx, int iy, R fy, int &m, R &d, R &c, R &s) {
+#pragma clang fp contract(off)
   const int si = ix * ix + iy * iy;
   const R sf = fx * (R(2 * ix) + fx) + fy * (R(2 * iy) + fy);
   const R rho0 = sqrt(fmax(R(si) + sf, R(0)));
@@ -165,13 +170,6 @@ __device__ __forceinline__ R gather_q(const typename Cplx<R>::T *__restrict__ Fc
   return acc;
 }
 
-__device__ __forceinline__ void acc_add(gptr<long long> p, float v) {
-  const long long q = (long long)(int)rintf(v);  // |v| < 2^31
-  if (q != 0) __hip_atomic_fetch_add(p, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void acc_add(gptr<double> p, double v) {
-  if (v != 0.0) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 constexpr int MAXM = 8;
 // LDS of one push workgroup: a private current box per wave of WAVE_CAP
@@ -189,21 +187,24 @@ __device__ __forceinline__ int wmax(int v) {
 }
 template <class T> using lptr = T __attribute__((address_space(3))) *;
 
-// Integer of one FP32 contribution: |v| < 2^31 (charges are scaled to at most
-// 2^28 and every weight factor is at most 4 in magnitude).
-__device__ __forceinline__ long long to_fixed(float v) { return (long long)(int)rintf(v); }
-__device__ __forceinline__ double to_fixed(double v) { return v; }
+// One FP64 contribution in the accumulator's type: FP32 form the nearest 64-bit
+// integer (|v| < 2^44: charges are scaled to at most 2^40 and every weight
+// factor is at most 4 in magnitude), FP64 form the value.
+template <class A> __device__ __forceinline__ A to_acc(double v);
+template <> __device__ __forceinline__ long long to_acc<long long>(double v) {
+  return rint_i64(v);
+}
+template <> __device__ __forceinline__ double to_acc<double>(double v) { return v; }
 
 // Deposit targets: the wave's LDS box, or the global accumulators.
 template <class A>
 struct SinkLdsQ {
   lptr<A> box;
   int H, W, rlo, bzrel, per;
-  template <class V>
-  __device__ __forceinline__ void operator()(int c, int m, int part, int row, int a, V v) const {
+  __device__ __forceinline__ void operator()(int c, int m, int part, int row, int a, double v) const {
     const int slot = c * per + (m == 0 ? 0 : 2 * m - 1 + part);
-    const auto q = to_fixed(v);
-    if (q != 0)
+    const A q = to_acc<A>(v);
+    if (q != A(0))
       __hip_atomic_fetch_add(box + (slot * H + (row - rlo)) * W + (bzrel + a), q, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);
   }
@@ -213,9 +214,12 @@ struct SinkGlobQ {
   A *J;
   long long plane;
   int n1, col[4];
-  template <class V>
-  __device__ __forceinline__ void operator()(int c, int m, int part, int row, int a, V v) const {
-    acc_add(G(J) + ((long long)(m * 3 + c) * plane + (long long)row * n1 + col[a]) * 2 + part, v);
+  __device__ __forceinline__ void operator()(int c, int m, int part, int row, int a, double v) const {
+    const A q = to_acc<A>(v);
+    if (q != A(0))
+      __hip_atomic_fetch_add(
+          G(J) + ((long long)(m * 3 + c) * plane + (long long)row * n1 + col[a]) * 2 + part, q,
+          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 };
 __device__ __forceinline__ void glob_add(gptr<long long> p, long long v) {
@@ -227,23 +231,29 @@ __device__ __forceinline__ void glob_add(gptr<double> p, double v) {
 
 // Per-mode deposit of one move (see the file header): window shapes S0/S1
 // along z and r, their running sums C and means T, window row base br, the
-// old phases P (mode m: Pr[m] - i Pi[m]... stored as (Pr, Pi) of e^{-i m th}),
-// the new direction (ctb, stb), scaled charge g and v_th dt.
+// old and new directions (cta, sta), (ctb, stb) (phases P_m = (c - i s)^m by
+// the same recurrence for both, so the new phase of one step is bit for bit
+// the old phase of the next), scaled charge g and v_th dt.
 template <class R, class Sink>
 __device__ __forceinline__ void deposit_q(const Sink &put, int M, const R S0z[4], const R S1z[4],
                                           const R S0r[4], const R S1r[4], const R Cz[4],
                                           const R Tz[4], const R Cr[4], const R Tr[4], int br,
-                                          const R *Pr, const R *Pi, R ctb, R stb, R g, R vthdt) {
+                                          R cta, R sta, R ctb, R stb, R g, R vthdt) {
+#pragma clang fp contract(off)
+  R P0r = 1, P0i = 0;  // phase at the old position
   R P1r = 1, P1i = 0;  // phase at the new position
   for (int m = 0; m < M; ++m) {
     if (m > 0) {
+      const R t0 = P0r * cta + P0i * sta;
+      P0i = P0i * cta - P0r * sta;
+      P0r = t0;
       const R t = P1r * ctb + P1i * stb;
       P1i = P1i * ctb - P1r * stb;
       P1r = t;
     }
     const R cm = m == 0 ? R(1) : R(2);
     const bool odd = m & 1;
-    const R Pmr = R(0.5) * (Pr[m] + P1r), Pmi = R(0.5) * (Pi[m] + P1i);
+    const R Pmr = R(0.5) * (P0r + P1r), Pmi = R(0.5) * (P0i + P1i);
     const R qr = -cm * g * Pmr, qi = -cm * g * Pmi;
     // z faces
 #pragma unroll
@@ -281,7 +291,7 @@ __device__ __forceinline__ void deposit_q(const Sink &put, int M, const R S0z[4]
       }
     }
     // azimuthal current
-    const R dPr = P1r - Pr[m], dPi = P1i - Pi[m];
+    const R dPr = P1r - P0r, dPi = P1i - P0i;
     const R inv_m = m > 0 ? R(1) / R(m) : R(0);
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -314,16 +324,16 @@ __device__ __forceinline__ void deposit_q(const Sink &put, int M, const R S0z[4]
   }
 }
 
-// The rare global-atomic path out of line (FP64 form), so that it does not add
-// to the register budget of the LDS path (measured: faster in FP64, slower in
-// FP32, where the path stays inline).
-template <class R>
-__device__ __noinline__ void deposit_q_global(const SinkGlobQ<typename AccQ<R>::T> &K, int M,
-                                              const R *S0z, const R *S1z, const R *S0r,
-                                              const R *S1r, const R *Cz, const R *Tz, const R *Cr,
-                                              const R *Tr, int br, const R *Pr, const R *Pi, R ctb,
-                                              R stb, R g, R vthdt) {
-  deposit_q<R>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, Pr, Pi, ctb, stb, g, vthdt);
+// The rare global-atomic path out of line, so that it does not add to the
+// register budget of the LDS path.
+template <class A>
+__device__ __noinline__ void deposit_q_global(const SinkGlobQ<A> &K, int M, const double *S0z,
+                                              const double *S1z, const double *S0r,
+                                              const double *S1r, const double *Cz,
+                                              const double *Tz, const double *Cr, const double *Tr,
+                                              int br, double cta, double sta, double ctb,
+                                              double stb, double g, double vthdt) {
+  deposit_q<double>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, cta, sta, ctb, stb, g, vthdt);
 }
 
 }  // namespace
@@ -457,34 +467,35 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
     }
   }
   if (ok) {
-    // ---- deposit: 4-node windows along z and r holding both stencils
-    R S0z[4], S1z[4], S0r[4], S1r[4];
+    // ---- deposit (FP64): 4-node windows along z and r holding both stencils
+    using D = double;
+    D S0z[4], S1z[4], S0r[4], S1r[4];
     int bz, br;
     {
-      R sa[3], sb[3];
-      const int na = zshape<R>(cz, fz, sa);
-      const int nb = zshape<R>(cz + dz, gz, sb);
+      D sa[3], sb[3];
+      const int na = zshape<D>(cz, (D)fz, sa);
+      const int nb = zshape<D>(cz + dz, (D)gz, sb);
       bz = min(na, nb) - 1;
-      place4<R>(sa, na - 1 - bz, S0z);
-      place4<R>(sb, nb - 1 - bz, S1z);
+      place4<D>(sa, na - 1 - bz, S0z);
+      place4<D>(sb, nb - 1 - bz, S1z);
       const int ra = mri, rb = mrb;
-      splineq<R>(dri, sa);
-      splineq<R>(drb, sb);
+      splineq<D>((D)dri, sa);
+      splineq<D>((D)drb, sb);
       br = min(ra, rb) - 1;
-      place4<R>(sa, ra - 1 - br, S0r);
-      place4<R>(sb, rb - 1 - br, S1r);
+      place4<D>(sa, ra - 1 - br, S0r);
+      place4<D>(sb, rb - 1 - br, S1r);
     }
-    R Cz[4], Tz[4], Cr[4], Tr[4];
+    D Cz[4], Tz[4], Cr[4], Tr[4];
     {
-      R az = 0, ar = 0;
+      D az = 0, ar = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         az = az + (S1z[k] - S0z[k]);
         ar = ar + (S1r[k] - S0r[k]);
         Cz[k] = az;
         Cr[k] = ar;
-        Tz[k] = R(0.5) * (S0z[k] + S1z[k]);
-        Tr[k] = R(0.5) * (S0r[k] + S1r[k]);
+        Tz[k] = 0.5 * (S0z[k] + S1z[k]);
+        Tr[k] = 0.5 * (S0r[k] + S1r[k]);
       }
     }
     const int bzrel = bz - cz + relz - zlo;  // window column 0 in the box
@@ -493,13 +504,14 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
     for (int a = 0; a < 4; ++a) col[a] = wrap_pow2(bz + a, n1);
     // azimuthal velocity at the mid point times dt: the move (mx, my) dr
     // projected on the azimuthal direction of the mid point
-    const R xmid = R(ix) + fx + R(0.5) * mx, ymid = R(iy) + fy + R(0.5) * my;
-    const R rmid = sqrt(xmid * xmid + ymid * ymid);
-    const R vthdt = rmid > R(0) ? (xmid * my - ymid * mx) / rmid * (R)r.dr : R(0);
-    const R g = qw * r.wscale;
+    const D xmid = D(ix) + (D)fx + 0.5 * (D)mx, ymid = D(iy) + (D)fy + 0.5 * (D)my;
+    const D rmid = sqrt(xmid * xmid + ymid * ymid);
+    const D vthdt = rmid > 0.0 ? (xmid * (D)my - ymid * (D)mx) / rmid * (D)r.dr : 0.0;
+    const D g = (D)qw * (D)r.wscale;
     if (use_lds) {
       SinkLdsQ<A> K{(lptr<A>)smem_raw + (threadIdx.x >> 6) * WAVE_CAP, H, W, rlo, bzrel, 2 * M - 1};
-      deposit_q<R>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, Pr, Pi, ctb, stb, g, vthdt);
+      deposit_q<D>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, (D)ct, (D)st, (D)ctb, (D)stb, g,
+                   vthdt);
     } else {
       SinkGlobQ<A> K;
       K.J = r.J[parity];
@@ -507,11 +519,8 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
       K.n1 = n1;
 #pragma unroll
       for (int a = 0; a < 4; ++a) K.col[a] = col[a];
-      if constexpr (sizeof(R) == 4)
-        deposit_q<R>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, Pr, Pi, ctb, stb, g, vthdt);
-      else
-        deposit_q_global<R>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, Pr, Pi, ctb, stb, g,
-                            vthdt);
+      deposit_q_global<A>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, (D)ct, (D)st, (D)ctb,
+                          (D)stb, g, vthdt);
     }
     G(P.cell)[p] = wrap_pow2(cz + dz, n1);
     G(P.fz)[p] = gz;

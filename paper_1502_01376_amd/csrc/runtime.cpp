@@ -77,7 +77,7 @@ const int UPD_BLOCK = 256;    // (i2, kappa) elements per update workgroup
 const int TILE1 = 32, TILE2 = 8;  // default particle tile (cells along x1, x2)
 const int SLACK1 = 2, SLACK2 = 1;  // drift beyond the tile the LDS budget allows for
 const int TILE1_3D = 8, TILE2_3D = 4;  // default 3D tile: 8 x 4 x 4 cells
-const double CJ3 = 268435456.0;        // 2^28: integer scale of the 3D FP32 deposit
+const double CJ3 = 1099511627776.0;     // 2^40: integer scale of the 3D FP32 deposit
 const int DEFAULT_SORT_INTERVAL = 16;
 
 struct Event2 {
@@ -1750,8 +1750,21 @@ class SimQ : public SimBase {
     h.qm = qm;
     h.q = q;
     d.qmhdt = (R)(qm * 0.5 * d.dt);
-    // FP32 form: contributions in units of 2^-28 of the largest charge
-    d.wscale = sizeof(R) == 4 ? (R)(std::ldexp(1.0, 28) / (wmax > 0 ? wmax : 1.0)) : R(1);
+    // FP32 form: contributions in units of 2^-40 of the largest charge.  One
+    // contribution is at most 2^42 max(1, dr) in magnitude and a node collects
+    // from the particles of 5 x 5 (z, r) cells: keep the sums below 2^62.
+    d.wscale = sizeof(R) == 4 ? (R)(std::ldexp(1.0, 40) / (wmax > 0 ? wmax : 1.0)) : R(1);
+    if (sizeof(R) == 4 && n > 0) {
+      std::vector<int> count((size_t)d.n1 * d.nr, 0);
+      int cmax = 0;
+      for (int64_t p = 0; p < n; ++p) {
+        const double rr = std::hypot((double)cx[p] + (double)fx[p], (double)cy[p] + (double)fy[p]);
+        const int ir = std::min((int)rr, d.nr - 1);
+        cmax = std::max(cmax, ++count[(size_t)ir * d.n1 + cell[p]]);
+      }
+      if (25.0 * cmax * std::ldexp(1.0, 42) * std::max(1.0, d.dr) >= std::ldexp(1.0, 62))
+        return fail(HP_ERANGE, "fixed-point headroom: %d particles in one (z, r) cell", cmax);
+    }
     set_jconv(run);
     if ((rc = rebuild_push_items())) return rc;
     return upload_runs();
