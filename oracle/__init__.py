@@ -80,7 +80,8 @@ def lib():
             "or_field_update2": (ctypes.c_int, [G, _D, _D, _D]),
             "or_yee_update2": (None, [G, _D, _D, _D]),
             "or_step2": (ctypes.c_int, [G, ctypes.c_double, ctypes.c_int64, _D, _D, _D, _D, _D,
-                                        _D, _D, _D, _D]),
+                                        _D, _D, _D, _D, ctypes.c_void_p, ctypes.c_double]),
+            "or_antenna2": (None, [G, ctypes.c_void_p, ctypes.c_double, _D]),
             "or_gauss2": (ctypes.c_int, [G, _D, _D, _D, _D]),
             "or_deposit2_fixed": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                  ctypes.c_float, ctypes.c_float, ctypes.c_int64,
@@ -235,10 +236,30 @@ def gauss2(g, E, rho):
     return (re + 1j * im).reshape(g.n2, nk)
 
 
-class State2:
-    """Particles and fields of one 2D run, advanced by ``step``."""
+class Antenna(ctypes.Structure):
+    """Moving current-sheet antenna (see ``or_antenna`` in the C header)."""
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("x0", "v", "t0", "T", "K0", "omega", "phase", "x2c", "waist")]
 
-    def __init__(self, g, qm, xi1, xi2, u, qw, E=None, B=None):
+
+def antenna(x0, v, t0, T, K0, omega, phase=0.0, x2c=0.0, waist=0.0):
+    return Antenna(float(x0), float(v), float(t0), float(T), float(K0), float(omega),
+                   float(phase), float(x2c), float(waist))
+
+
+def antenna2(g, a, t, J=None):
+    """The antenna's current j3 at time t added to J ([3][n2][n1], zeros if None)."""
+    J = np.zeros((3, g.n2, g.n1)) if J is None else _f64(J).copy()
+    lib().or_antenna2(ctypes.byref(g), ctypes.byref(a), float(t), _p(J))
+    return J
+
+
+class State2:
+    """Particles and fields of one 2D run, advanced by ``step``; ``t`` is the
+    time, ``antenna`` an optional ``Antenna`` whose current is added each step."""
+
+    def __init__(self, g, qm, xi1, xi2, u, qw, E=None, B=None, antenna=None, t=0.0):
+        self.antenna, self.t = antenna, float(t)
         self.g, self.qm = g, float(qm)
         self.xi1, self.xi2 = _f64(xi1).copy(), _f64(xi2).copy()
         self.u = _f64(u).copy()
@@ -252,11 +273,13 @@ class State2:
         g = self.g
         u1, u2, u3 = (np.ascontiguousarray(self.u[c]) for c in range(3))
         for _ in range(n):
+            ant = ctypes.byref(self.antenna) if self.antenna is not None else None
             st = lib().or_step2(ctypes.byref(g), self.qm, len(self.xi1), _p(self.xi1), _p(self.xi2),
                                 _p(u1), _p(u2), _p(u3), _p(self.qw), _p(self.E), _p(self.B),
-                                _p(self.J))
+                                _p(self.J), ant, self.t)
             if st != 0:
                 raise ValueError("oracle step failed (move of a cell or more)")
+            self.t += g.dt
         self.u = np.stack([u1, u2, u3])
         return self
 

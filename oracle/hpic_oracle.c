@@ -465,9 +465,39 @@ void or_yee_update2(const or_grid2 *g, double *E, double *B, const double *J) {
 /* Whole step                                                                */
 /* ------------------------------------------------------------------------ */
 
+/* Antenna current (reading of Sec. 6, see the header): surface current K(t)
+ * of a sheet at x_a(t), spread over x1 with the quadratic B-spline. */
+void or_antenna2(const or_grid2 *g, const or_antenna *a, double t, double *J) {
+  double s = t - a->t0;
+  if (!(s >= 0.0 && s <= a->T) || !(a->T > 0.0)) return;
+  double env = sin(PI * s / a->T);
+  double K = a->K0 * env * env * sin(a->omega * s + a->phase);
+  double L1 = g->n1 * g->dx1, L2 = g->n2 * g->dx2;
+  double xa = fmod(a->x0 + a->v * t, L1);
+  if (xa < 0.0) xa += L1;
+  double sa = xa / g->dx1;
+  int64_t cells = (int64_t)g->n1 * g->n2;
+  double *J3 = J + 2 * cells;
+  for (int32_t j = 0; j < g->n2; ++j) {
+    double gx = 1.0;
+    if (a->waist > 0.0) {
+      double d = fmod(j * g->dx2 - a->x2c, L2);
+      if (d < -0.5 * L2) d += L2;
+      if (d >= 0.5 * L2) d -= L2;
+      gx = exp(-(d / a->waist) * (d / a->waist));
+    }
+    /* every node whose spline support contains the sheet */
+    for (int32_t i = (int32_t)floor(sa) - 2; i <= (int32_t)floor(sa) + 3; ++i) {
+      double w = spline2(sa - i);
+      if (w == 0.0) continue;
+      J3[(int64_t)j * g->n1 + wrapi(i, g->n1)] += K * gx * w / g->dx1;
+    }
+  }
+}
+
 int or_step2(const or_grid2 *g, double qm, int64_t np, double *xi1, double *xi2,
              double *u1, double *u2, double *u3, const double *qw, double *E, double *B,
-             double *J) {
+             double *J, const or_antenna *ant, double t) {
   int64_t cells = (int64_t)g->n1 * g->n2;
   double *Ep = malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
   double *Bp = malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
@@ -484,6 +514,7 @@ int or_step2(const or_grid2 *g, double qm, int64_t np, double *xi1, double *xi2,
   }
   memset(J, 0, sizeof(double) * 3 * cells);
   int status = or_deposit2(g, np, xi1, xi2, xn1, xn2, v3, qw, J);
+  if (ant) or_antenna2(g, ant, t + 0.5 * g->dt, J);
   if (or_field_update2(g, E, B, J) != 0) status = -1;
   for (int64_t p = 0; p < np; ++p) {
     xi1[p] = fmod(xn1[p], (double)g->n1);

@@ -97,12 +97,33 @@ int or_field_update2(const or_grid2 *g, double *E, double *B, const double *J);
  * Eqs. (1)-(6) (no FFT, no filter, no correction; jbg is added). */
 void or_yee_update2(const or_grid2 *g, double *E, double *B, const double *J);
 
+/* Moving antenna (Sec. 6 launches the laser of the boosted-frame runs with a
+ * moving antenna; the text gives no form, this is the reading used here): a
+ * sheet of out-of-plane surface current K(t) g(x2) at x1 = x_a(t) = x0 + v t
+ * (periodic in x1), K(t) = K0 sin^2(pi s / T) sin(omega s + phase) for
+ * 0 <= s = t - t0 <= T and 0 otherwise, g(x2) = exp(-((x2 - x2c)/waist)^2)
+ * with the periodic distance (waist <= 0: g = 1).  A sheet with K(t) emits
+ * E3 = -K(t_ret) / (2 (1 -+ v)) towards +-x1, at the Doppler-shifted
+ * frequency omega / (1 -+ v); j3 has no divergence in 2D, so it carries no
+ * charge. */
+typedef struct or_antenna {
+  double x0, v, t0, T, K0, omega, phase, x2c, waist;
+} or_antenna;
+
+/* Adds the antenna's current at time t to J3 (J is [3][n2][n1]): the sheet
+ * is spread over the x1 nodes with the quadratic B-spline of its position,
+ * j3(i, j) += K(t) g(j dx2) S2(x_a/dx1 - i) / dx1 (integer nodes in x2, where
+ * j3 lives). */
+void or_antenna2(const or_grid2 *g, const or_antenna *a, double t, double *J);
+
 /* One whole step: gather, Boris push, move, deposit, field update.  Positions
  * are wrapped back into [0, n) at the end.  J receives the deposited current
- * (without background).  Returns 0, or -1 on a move of a cell or more. */
+ * (without background).  ant (or NULL): an antenna whose current at the time
+ * centre t + dt/2 of the step is added before the field update (t: time at
+ * the start of the step).  Returns 0, or -1 on a move of a cell or more. */
 int or_step2(const or_grid2 *g, double qm, int64_t np, double *xi1, double *xi2,
              double *u1, double *u2, double *u3, const double *qw, double *E, double *B,
-             double *J);
+             double *J, const or_antenna *ant, double t);
 
 /* Gauss-law residual of Eq. (27) in (kappa1, i2) space: R = D.E - f rho, with
  * the same x1 derivative as the update and f the current filter.  rho is the
