@@ -170,6 +170,35 @@ int hp_set_fields(hp_sim *sim, int32_t run, int32_t mode, const double *E, const
 int hp_set_background(hp_sim *sim, int32_t run, int32_t rho_from_particles,
                       const double *j_bg);
 
+/* Moving antenna of a 2D run (Sec. 6 launches the laser of its boosted-frame
+ * runs with a moving antenna and gives no form; this is the form used here):
+ * a sheet of out-of-plane surface current K(t) g(x2) at x1 = x0 + v t
+ * (periodic), K(t) = K0 sin^2(pi s / T) sin(omega s + phase) for
+ * 0 <= s = t - t0 <= T and 0 otherwise, g(x2) = exp(-((x2 - x2c)/waist)^2)
+ * with the periodic distance (waist <= 0: g = 1).  Each step adds
+ * j3(i, j) += K(t) g(j dx2) S2(x_a/dx1 - i) / dx1 (S2 the quadratic B-spline)
+ * at the step's time centre t = (n + 1/2) dt, where n counts the handle's
+ * steps.  Such a sheet radiates E3 = -K(t_ret) / (2 (1 -+ v)) towards +-x1 at
+ * the Doppler-shifted frequency omega / (1 -+ v); j3 carries no charge in 2D.
+ * Lengths, times and velocities in the units of hp_config. */
+typedef struct hp_antenna {
+  double x0;       /* position along x1 at t = 0 */
+  double v;        /* velocity along x1, |v| < 1 */
+  double t0, T;    /* on for t0 <= t <= t0 + T, T > 0 */
+  double K0;       /* surface-current amplitude */
+  double omega;    /* angular frequency of the drive */
+  double phase;    /* phase of the drive at t = t0 */
+  double x2c;      /* centre of the transverse profile */
+  double waist;    /* 1/e half width of the field profile (<= 0: uniform) */
+} hp_antenna;
+
+/* Sets (a != NULL) or removes (a == NULL) the antenna of a 2D run; one per
+ * run, copied.  HP_EINVAL for a 3D or quasi-3D run or a parameter out of
+ * range (non-finite, |v| >= 1, T <= 0).  The time of the handle's step counter
+ * is used, so an antenna set after some steps sees the time those steps
+ * reached; checkpoints keep the counter, not the antenna. */
+int hp_set_antenna(hp_sim *sim, int32_t run, const hp_antenna *a);
+
 /* Advances every run nsteps steps, asynchronously on the handle's stream.
  * Kernel-detected errors (HP_ERANGE, HP_ENUMERIC) are reported by the next
  * synchronous call. */

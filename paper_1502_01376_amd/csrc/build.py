@@ -12,7 +12,8 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libhpic.so")
-SOURCES = ["push.hip", "push3.hip", "pushc.hip", "pushq.hip", "solve.hip", "solveq.hip", "runtime.cpp"]
+SOURCES = ["push.hip", "push3.hip", "pushc.hip", "pushq.hip", "solve.hip", "solveq.hip",
+           "antenna.hip", "runtime.cpp"]
 ARCH = os.environ.get("HPIC_ARCH", "gfx950")
 
 

@@ -352,6 +352,21 @@ template <class R>
 void launch_rho_cubic(const Run<R> *run_dev, int pp, int np, typename AccOf<R>::T *rho,
                       hipStream_t s);
 void launch_rho_fp64(const Run<double> *run_dev, int pp, int np, double *rho, hipStream_t s);
+// Moving antenna of a 2D run (see hp_set_antenna): device parameters.
+struct AntennaDev {
+  int run;             // run index in the handle
+  int n1, n2;
+  double dx1, dx2, dt;
+  double x0, v, t0, T, K0, omega, phase, x2c, waist;
+  double scale;        // physical j3 -> accumulator units
+};
+// Adds every antenna's current of the step (time (*step + 1/2) dt) to j3 of
+// the run's accumulators of the given parity; then, in a separate launch,
+// the step counter advances by one (both are captured in step graphs).
+template <class R>
+void launch_antenna(const Run<R> *runs, const AntennaDev *ants, int nant, int maxn2, int parity,
+                    const long long *step, hipStream_t s);
+void launch_step_tick(long long *step, hipStream_t s);
 template <class R>
 void launch_energy(const R *F, long long cells, double *partial, int nblocks, hipStream_t s);
 template <class R>

@@ -131,6 +131,10 @@ struct SimBase {
   virtual int get_current_mode(int, int, int, double *, size_t) {
     return fail(HP_EINVAL, "per-mode currents exist for quasi-3D runs only");
   }
+  // moving antenna (2D Cartesian runs only)
+  virtual int set_antenna(int, const hp_antenna *) {
+    return fail(HP_EINVAL, "the antenna is built for 2D runs only");
+  }
 };
 
 struct hp_sim {
@@ -161,7 +165,8 @@ class Sim : public SimBase {
     double *rho0_3 = nullptr, *rho_prev_3 = nullptr;  // 3D: FP64 charge density
     int64_t rho_prev_step = -2;
     int row0 = 0, grp0 = 0;  // first items of the run in the row/group lists
-    // per-run particle count cells for headroom
+    bool has_ant = false;    // moving antenna (hp_set_antenna)
+    hp_antenna ant{};
   };
 
  public:
@@ -180,6 +185,11 @@ class Sim : public SimBase {
     HIPCHK(hipMalloc(&d_err_, sizeof(unsigned)));
     allocs_.push_back(d_err_);
     HIPCHK(hipMemset(d_err_, 0, sizeof(unsigned)));
+    HIPCHK(hipMalloc(&d_step_, sizeof(long long)));
+    allocs_.push_back(d_step_);
+    HIPCHK(hipMemset(d_step_, 0, sizeof(long long)));
+    HIPCHK(hipMalloc(&d_ant_, sizeof(AntennaDev) * std::max(nruns, 1)));
+    allocs_.push_back(d_ant_);
     runs_.resize(nruns);
     std::vector<Item> rows, grps, upd, perrun;
     for (int i = 0; i < nruns; ++i) {
@@ -457,6 +467,7 @@ class Sim : public SimBase {
                               d_stats_, stream_);
     mark(HP_K_PUSH_DEPOSIT, false);
     ++since_sort_;
+    if (n_ant_ > 0) launch_antenna<R>(d_runs_, d_ant_, n_ant_, ant_maxn2_, p, d_step_, stream_);
     mark(HP_K_FFT_J, true);
     Launch<R>::fft_j(d_runs_, d_rows_, n_rows_, p, maxM_, stream_);
     mark(HP_K_FFT_J, false);
@@ -469,8 +480,68 @@ class Sim : public SimBase {
     mark(HP_K_IFFT_EB, true);
     Launch<R>::ifft_eb(d_runs_, d_grps_, n_grps_, p ^ 1, maxM_, stream_);
     mark(HP_K_IFFT_EB, false);
+    if (n_ant_ > 0) launch_step_tick(d_step_, stream_);
     parity_ ^= 1;
     ++step_;
+  }
+
+  // ---- moving antenna
+  int set_antenna(int run, const hp_antenna *a) override {
+    RunHost &h = runs_[run];
+    if (h.d.dim != 2) return fail(HP_EINVAL, "run %d: the antenna is built for 2D runs only", run);
+    if (a) {
+      const double f[9] = {a->x0, a->v, a->t0, a->T, a->K0, a->omega, a->phase, a->x2c, a->waist};
+      for (double x : f)
+        if (!std::isfinite(x)) return fail(HP_EINVAL, "run %d: non-finite antenna parameter", run);
+      if (!(std::fabs(a->v) < 1.0)) return fail(HP_EINVAL, "run %d: antenna speed |v| >= 1", run);
+      if (!(a->T > 0.0)) return fail(HP_EINVAL, "run %d: antenna duration T <= 0", run);
+    }
+    int rc;
+    if ((rc = sync())) return rc;
+    drop_graphs();
+    h.has_ant = a != nullptr;
+    if (a) h.ant = *a;
+    const long long s = step_;
+    HIPCHK(hipMemcpy(d_step_, &s, sizeof s, hipMemcpyHostToDevice));
+    return upload_antennas();
+  }
+  // Device table of the runs' antennas (the accumulator scale follows the
+  // run's fixed-point set-up, so it is rebuilt with every upload of the runs).
+  int upload_antennas() {
+    std::vector<AntennaDev> v;
+    int maxn2 = 0;
+    for (int i = 0; i < (int)runs_.size(); ++i) {
+      const RunHost &h = runs_[i];
+      if (!h.has_ant) continue;
+      AntennaDev a{};
+      a.run = i;
+      a.n1 = h.d.n1;
+      a.n2 = h.d.n2;
+      a.dx1 = h.cfg.dx[0];
+      a.dx2 = h.cfg.dx[1];
+      a.dt = h.cfg.dt;
+      a.x0 = h.ant.x0;
+      a.v = h.ant.v;
+      a.t0 = h.ant.t0;
+      a.T = h.ant.T;
+      a.K0 = h.ant.K0;
+      a.omega = h.ant.omega;
+      a.phase = h.ant.phase;
+      a.x2c = h.ant.x2c;
+      a.waist = h.ant.waist;
+      a.scale = 1.0 / acc_factor(h, 2);
+      // FP32 form: a node's contribution (at most 0.75 |K0| / dx1 scaled) must
+      // stay well inside the 64-bit accumulators and the rounding helper
+      if (FIXED && std::fabs(a.K0) / a.dx1 * a.scale >= std::ldexp(1.0, 50))
+        return fail(HP_ERANGE, "run %d: antenna current too large for the fixed-point accumulators", i);
+      v.push_back(a);
+      maxn2 = std::max(maxn2, a.n2);
+    }
+    if (!v.empty()) HIPCHK(hipMemcpy(d_ant_, v.data(), sizeof(AntennaDev) * v.size(), hipMemcpyHostToDevice));
+    if ((int)v.size() != n_ant_) drop_graphs();
+    n_ant_ = (int)v.size();
+    ant_maxn2_ = maxn2;
+    return HP_OK;
   }
 
   // A block of one sort followed by K steps (K = sort interval, even), as a
@@ -1033,6 +1104,10 @@ class Sim : public SimBase {
     if ((rc = sync())) return rc;
     step_ = hdr[4];
     parity_ = (int)hdr[5];
+    {
+      const long long s = step_;
+      HIPCHK(hipMemcpy(d_step_, &s, sizeof s, hipMemcpyHostToDevice));
+    }
     for (int i = 0; i < (int)runs_.size(); ++i) {
       RunHost &h = runs_[i];
       Run<R> &d = h.d;
@@ -1240,7 +1315,8 @@ class Sim : public SimBase {
   int upload_runs() {
     std::vector<Run<R>> v(runs_.size());
     for (size_t i = 0; i < runs_.size(); ++i) v[i] = runs_[i].d;
-    return h2d(d_runs_, v.data(), v.size());
+    const int rc = h2d(d_runs_, v.data(), v.size());
+    return rc ? rc : upload_antennas();
   }
   // Sort chunks: (run, first particle, count <= SORT_CHUNK) over all particles.
   // Particle tiles of every run (t1 x t2 cells, clipped to the grid), the
@@ -1465,6 +1541,9 @@ class Sim : public SimBase {
   int parity_ = 0;
   int64_t step_ = 0;
   unsigned *d_err_ = nullptr;
+  long long *d_step_ = nullptr;    // step counter on the device (antenna time)
+  AntennaDev *d_ant_ = nullptr;    // antennas of the runs that have one
+  int n_ant_ = 0, ant_maxn2_ = 0;
   bool profiling_ = false;
   std::vector<Event2> events_;
   double kms_[HP_NK] = {0};
@@ -2290,6 +2369,10 @@ int hp_set_fields(hp_sim *sim, int32_t run, int32_t mode, const double *E, const
 
 int hp_set_background(hp_sim *sim, int32_t run, int32_t rho_from_particles, const double *j_bg) {
   return with_run(sim, run, [&] { return sim->impl->set_background(run, rho_from_particles, j_bg); });
+}
+
+int hp_set_antenna(hp_sim *sim, int32_t run, const hp_antenna *a) {
+  return with_run(sim, run, [&] { return sim->impl->set_antenna(run, a); });
 }
 
 int hp_step(hp_sim *sim, int32_t nsteps) {

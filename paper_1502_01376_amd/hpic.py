@@ -23,7 +23,7 @@ HP_NK = len(KERNELS)
 # every function of the C ABI (checked against the header by the tests)
 ABI = (
     "hp_create", "hp_destroy", "hp_last_error", "hp_set_stream", "hp_set_particles",
-    "hp_set_fields", "hp_set_background", "hp_step", "hp_synchronize", "hp_get_field",
+    "hp_set_fields", "hp_set_background", "hp_set_antenna", "hp_step", "hp_synchronize", "hp_get_field",
     "hp_get_current", "hp_get_current_fixed", "hp_get_particle_count", "hp_get_particles",
     "hp_get_particles_raw", "hp_diagnostics", "hp_get_state", "hp_set_state",
     "hp_debug_deposit", "hp_get_fixed_params", "hp_profile", "hp_get_kernel_times",
@@ -63,6 +63,12 @@ class Tune(ctypes.Structure):
                     candidates=self.candidates, steps=self.steps)
 
 
+class Antenna(ctypes.Structure):
+    """hp_antenna: moving current-sheet antenna of a 2D run."""
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("x0", "v", "t0", "T", "K0", "omega", "phase", "x2c", "waist")]
+
+
 class Diag(ctypes.Structure):
     _fields_ = [
         ("W_E", ctypes.c_double * 3), ("W_B", ctypes.c_double * 3), ("kinetic", ctypes.c_double),
@@ -91,6 +97,7 @@ def lib():
             "hp_set_particles": [_P, i32, i32, i64, _P, _P, _P, ctypes.c_double, ctypes.c_double],
             "hp_set_fields": [_P, i32, i32, _P, _P],
             "hp_set_background": [_P, i32, i32, _P],
+            "hp_set_antenna": [_P, i32, _P],
             "hp_step": [_P, i32],
             "hp_synchronize": [_P],
             "hp_get_field": [_P, i32, i32, i32, _P, sz],
@@ -230,6 +237,16 @@ class Sim:
         (quasi-3D) also the co-drifting current of the particles."""
         j = np.ascontiguousarray(jbg, dtype=np.float64)
         _check(lib().hp_set_background(self.h, run, int(rho_from_particles), _ptr(j)))
+
+    def set_antenna(self, run, x0=None, v=0.0, t0=0.0, T=1.0, K0=0.0, omega=0.0, phase=0.0,
+                    x2c=0.0, waist=0.0):
+        """Moving antenna of a 2D run (see hp_set_antenna); x0=None removes it."""
+        if x0 is None:
+            _check(lib().hp_set_antenna(self.h, run, None))
+            return
+        a = Antenna(float(x0), float(v), float(t0), float(T), float(K0), float(omega),
+                    float(phase), float(x2c), float(waist))
+        _check(lib().hp_set_antenna(self.h, run, ctypes.byref(a)))
 
     def step(self, n=1):
         _check(lib().hp_step(self.h, int(n)))
