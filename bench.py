@@ -56,6 +56,9 @@ def parse():
                          "and with the cubic shape (0: skip)")
     ap.add_argument("--q3d-steps", type=int, default=200,
                     help="steps of the quasi-3D 4096x256 three-mode PIC leg (0: skip)")
+    ap.add_argument("--lwfa-steps", type=int, default=6400,
+                    help="steps of the Table 2 boosted-frame laser wakefield run (8192x512, "
+                         "FP32, with and without the k1 filter; 0: skip)")
     ap.add_argument("--nci-steps", type=int, default=40000,
                     help="steps of the Table 1 NCI contrast (four 256x256 runs; 0: skip)")
     ap.add_argument("--n1", type=int, default=2048)
@@ -305,6 +308,50 @@ def nci_leg(steps):
     return out
 
 
+def lwfa_leg(hpic, torch, W, steps):
+    """The Table 2 boosted-frame laser wakefield run (8192x512, gamma_b = 14,
+    16 777 216 particles, laser from the moving antenna), FP32 form, graph-
+    replayed: particle-steps/s and per-kernel times of the filtered run, then on
+    axis the laser amplitude against a0 omega', the wake's peak E1 and the
+    largest E1 ahead of the laser (numerical Cherenkov noise), with the k1
+    filter and without it."""
+    d = W.lwfa_boosted()
+    npart = d["w"].size
+    lz = d["laser"]
+    out = {"workload": d["name"], "n": list(d["n"][:2]), "particles": npart, "steps": steps,
+           "t_end": steps * d["dt"]}
+    for alpha in (0.5, 1.0):
+        sim = hpic.from_workload(d, "fp32", alpha=alpha)
+        sim.use_graphs(True)
+        if alpha == 0.5:
+            sim.step(20)
+            sim.synchronize()
+            sim.profile(True)
+            sim.step(100)
+            sim.synchronize()
+            kt = sim.kernel_times()
+            sim.profile(False)
+            done = 120
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(steps - done)
+            sim.synchronize()
+            t = time.perf_counter() - t0
+            out["ms_per_step"] = 1e3 * t / (steps - done)
+            out["particle_steps_per_s"] = npart * (steps - done) / t
+            out["kernels_us"] = {k: 1e3 * ms / max(n, 1) for k, (ms, n) in kt.items() if n > 0}
+        else:
+            sim.step(steps)
+        E, _ = sim.fields(0)
+        e1, e3 = E[0, d["n"][1] // 2], E[2, d["n"][1] // 2]
+        key = "filter" if alpha == 0.5 else "no_filter"
+        out[key] = {"laser_amplitude_over_a0_omega": float(np.abs(e3).max() / (lz["a0"] * lz["omega"])),
+                    "wake_E1_max": float(np.abs(e1).max()),
+                    "E1_max_ahead_of_laser": float(np.abs(e1[2000:7000]).max())}
+        sim.close()
+    return out
+
+
 def shape_leg(hpic, torch, d, steps, tune_steps, tiling):
     """The benchmark workload (2048x512, 8 388 608 particles, FP32 form) with
     the energy-conserving gather and with the cubic shape, each over `steps`
@@ -419,6 +466,8 @@ def main():
         out["shapes2d"] = shape_leg(hpic, torch, d, args.shape_steps, args.tune_steps, tiling)
     if args.nci_steps > 0:
         out["nci_table1"] = nci_leg(args.nci_steps)
+    if args.lwfa_steps > 0:
+        out["lwfa_boosted"] = lwfa_leg(hpic, torch, W, args.lwfa_steps)
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
         x = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -186,6 +186,20 @@ __device__ void lds_fft(C *buf, int M, int log2M, int NF, const C *__restrict__ 
   }
 }
 
+// NF transforms of length M in LDS (as lds_fft), one transform at a time when
+// the radix-4 passes of all NF at once would need more than MAXB butterflies
+// per thread (n1 = 8192 rows: three components of M = 4096).  The choice is
+// uniform over the block, so the barriers inside stay uniform.
+template <class C, int MAXB>
+__device__ void lds_fft_rows(C *buf, int M, int log2M, int NF, const C *__restrict__ tw, int tws,
+                             bool inverse) {
+  if (NF * (M >> 2) <= MAXB * (int)blockDim.x) {
+    lds_fft<C, MAXB>(buf, M, log2M, NF, tw, tws, inverse);
+    return;
+  }
+  for (int f = 0; f < NF; ++f) lds_fft<C, MAXB>(buf + f * M, M, log2M, 1, tw, tws, inverse);
+}
+
 // ---------------------------------------------------------------- shapes
 // Quadratic B-spline weights of the nodes m-1, m, m+1 for a particle at signed
 // distance d in [-1/2, 1/2) from its nearest node m.

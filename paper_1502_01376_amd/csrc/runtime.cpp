@@ -182,6 +182,16 @@ class Sim : public SimBase {
 
   int init(const hp_config *cfgs, int nruns) {
     HIPCHK(hipGetDevice(&device_));
+    {
+      // LDS of the row transforms: three components of n1/2 complex values
+      int lim = 0, n1max = 0;
+      HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device_));
+      for (int i = 0; i < nruns; ++i) n1max = std::max(n1max, cfgs[i].n[0]);
+      const size_t need = 3 * (size_t)(n1max / 2) * sizeof(C);
+      if (need > (size_t)lim)
+        return fail(HP_EINVAL, "n1 = %d needs %zu bytes of LDS per row transform, the device allows %d",
+                    n1max, need, lim);
+    }
     HIPCHK(hipMalloc(&d_err_, sizeof(unsigned)));
     allocs_.push_back(d_err_);
     HIPCHK(hipMemset(d_err_, 0, sizeof(unsigned)));
@@ -2266,8 +2276,13 @@ int hp_create(const hp_config *cfgs, int32_t nruns, hp_sim **out) {
     }
     if (c.precision != prec || (prec != HP_PREC_FP32_FIXED && prec != HP_PREC_FP64))
       return fail(HP_EINVAL, "run %d: precision must be one of the two forms and equal for all runs", i);
-    if (!is_pow2(c.n[0]) || c.n[0] < 8 || c.n[0] > 4096)
-      return fail(HP_EINVAL, "run %d: n1 = %d must be a power of two in [8, 4096]", i, c.n[0]);
+    // the row transforms hold a row's three components (n1/2 complex values
+    // each) in LDS: up to n1 = 8192 in the FP32 form of Cartesian runs
+    // (96 KiB), 4096 otherwise
+    const int n1max = (c.geom != HP_GEOM_Q3D && prec == HP_PREC_FP32_FIXED) ? 8192 : 4096;
+    if (!is_pow2(c.n[0]) || c.n[0] < 8 || c.n[0] > n1max)
+      return fail(HP_EINVAL, "run %d: n1 = %d must be a power of two in [8, %d] for this form", i,
+                  c.n[0], n1max);
     if (c.n[1] < 4 || (int64_t)c.n[0] * c.n[1] * (c.geom == HP_GEOM_3D ? c.n[2] : 1) > (int64_t)1 << 30)
       return fail(HP_EINVAL, "run %d: n2 = %d out of range", i, c.n[1]);
     if (!(c.dx[0] > 0) || !(c.dx[1] > 0) || !(c.dt > 0) || !std::isfinite(c.dt))

@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(256) k_fft_j(const Run<R> *__restrict__ runs,
     }
   }
   __syncthreads();
-  lds_fft<C, 6>(lds, M, log2M, 3, r.tw, 2, false);
+  lds_fft_rows<C, 6>(lds, M, log2M, 3, r.tw, 2, false);
   const int nk = r.nk;
   for (int k = threadIdx.x; k <= (M >> 1); k += blockDim.x) {
     const int mk = M - k;
@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(256) k_fields_to_k(const Run<R> *__restrict__ 
     for (int n = threadIdx.x; n < M; n += blockDim.x) lds[c * M + n] = cmk(src[2 * n], src[2 * n + 1]);
   }
   __syncthreads();
-  lds_fft<C, 6>(lds, M, log2M, 3, r.tw, 2, false);
+  lds_fft_rows<C, 6>(lds, M, log2M, 3, r.tw, 2, false);
   for (int k = threadIdx.x; k <= (M >> 1); k += blockDim.x) {
     const int mk = M - k;
     for (int c = 0; c < 3; ++c) {
@@ -314,7 +314,7 @@ __global__ void __launch_bounds__(256) k_ifft_eb(const Run<R> *__restrict__ runs
     }
   }
   __syncthreads();
-  lds_fft<C, 6>(lds, M, log2M, 3, r.tw, 2, true);
+  lds_fft_rows<C, 6>(lds, M, log2M, 3, r.tw, 2, true);
   const R s = r.inv_m;
   for (int c = 0; c < 3; ++c) {
     R *dst = r.F + (long long)(3 * grp + c) * cells + (long long)row * n1;

@@ -397,6 +397,8 @@ def from_workloads(ds, precision="fp32", alpha=None, deriv1=0, correct=1, backgr
             sim.set_fields(r, d["E"], d["B"])
         if background:
             sim.set_background(r, True, d["jbg"])
+        if d.get("antenna"):
+            sim.set_antenna(r, **d["antenna"])
     return sim
 
 

@@ -39,7 +39,9 @@ The named workloads are the drifting-plasma set-ups of the benchmark suite:
   q w), fields per mode complex [M][3][n2+1][n1].
 
 The NCI test set-up of Table 1 (dx = 0.2, dt = 0.4 dx1, periodic,
-51.2 x 51.2, gamma = 50, n = 100) is ``nci_table1``.
+51.2 x 51.2, gamma = 50, n = 100) is ``nci_table1``; the Lorentz-boosted laser
+wakefield set-up of Table 2 (8192 x 512, gamma_b = 14, a moving antenna) is
+``lwfa_boosted``.
 """
 import math
 
@@ -271,6 +273,55 @@ def nci_table1(seed=SEED0 + 10, ppc=(2, 2), n=(256, 256)):
     d = drift2d(n[0], n[1], 0.2, 0.2, 0.08, sub=ppc, gamma=50.0, sigma_u=1e-4, density=100.0,
                 seed=seed, name="nci_table1")
     return d
+
+
+def lwfa_boosted(n1=8192, n2=512, gamma_b=14.0, ppc=(2, 2), seed=SEED0 + 13, name=None):
+    """Lorentz-boosted 2D laser wakefield set-up of Table 2 (Sec. 6), in the
+    boosted frame with lab-frame laser units (k0 = omega0 = 1, c = 1, density
+    in units of the lab critical density):
+
+    * grid dx1 = dx2 = 0.0982 gamma_b (1 + beta_b) (2.746 for gamma_b = 14),
+      dt = 0.225 dx1, 8192 x 512 cells, filter at half the x1 Nyquist
+      wavenumber;
+    * plasma of density 1.148e-3 gamma_b streaming along -x1 with
+      u1 = -gamma_b beta_b, cold, on a quiet ppc sub-lattice (2 x 2, 16 777 216
+      particles), filling the periodic box, with co-streaming ions as a fixed
+      neutralising background (charge and uniform current);
+    * the laser (a0 = 4, waist 117.81, polarised along x3, field FWHM
+      70.64 gamma_b (1 + beta_b) in the boosted frame) launched by a moving
+      antenna at rest in the lab frame (v = -beta_b): surface current
+      K = 2 (1 + beta_b) a0 omega' sin^2(pi s/T) sin(omega s), omega' =
+      1/(gamma_b (1 + beta_b)) the boosted laser frequency, omega =
+      omega' (1 + beta_b) the drive frequency, T = 2 FWHM / (1 + beta_b);
+    * 6400 steps (t' = 3955, the time of Fig. 4's boosted-frame snapshots).
+
+    Returns a ``drift2d``-style dict plus ``antenna`` (keyword arguments of
+    ``hpic.Sim.set_antenna``) and ``laser`` (the boosted-frame parameters)."""
+    gen = rng(seed)
+    beta_b = math.sqrt(1.0 - 1.0 / (gamma_b * gamma_b))
+    dx = 0.0982 * gamma_b * (1.0 + beta_b)
+    dt = 0.225 * dx
+    density = 1.148e-3 * gamma_b
+    x1, x2 = lattice_2d(n1, n2, ppc[0], ppc[1], False, gen)
+    npart = x1.size
+    u = np.zeros((3, npart))
+    u[0] = -gamma_b * beta_b
+    w = np.full(npart, density / (ppc[0] * ppc[1]))
+    q, qm = -1.0, -1.0
+    a0, waist = 4.0, 117.81
+    fwhm = 70.64 * gamma_b * (1.0 + beta_b)
+    omega_b = 1.0 / (gamma_b * (1.0 + beta_b))
+    L1, L2 = n1 * dx, n2 * dx
+    antenna = dict(x0=0.125 * L1, v=-beta_b, t0=0.0, T=2.0 * fwhm / (1.0 + beta_b),
+                   K0=2.0 * (1.0 + beta_b) * a0 * omega_b, omega=omega_b * (1.0 + beta_b),
+                   phase=0.0, x2c=0.5 * L2, waist=waist)
+    E = np.zeros((3, n2, n1))
+    jbg = -mean_current(u, w, q, n1 * n2)
+    return dict(name=name or "lwfa_boosted_%dx%d_g%g" % (n1, n2, gamma_b), geom=2,
+                n=(n1, n2, 1), dx=(dx, dx, 1.0), dt=dt, alpha=0.5, xi=np.stack([x1, x2]), u=u,
+                w=w, q=q, qm=qm, E=E, B=E.copy(), jbg=jbg, seed=seed, steps=6400,
+                antenna=antenna, laser=dict(gamma_b=gamma_b, beta_b=beta_b, a0=a0, waist=waist,
+                                            fwhm=fwhm, omega=omega_b, density=density))
 
 
 def drift_q3d(n1=4096, n2=256, dz=0.1, dr=0.2, dt=0.04, modes=3, sub=(2, 1, 4), rfill=None,

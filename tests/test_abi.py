@@ -81,9 +81,15 @@ def test_courant_violation_rejected(hp):
     assert rc != hp.HP_ECOURANT
 
 
-@pytest.mark.parametrize("n1,n2", [(48, 32), (4, 32), (8192, 8), (64, 3)])
-def test_bad_grid_rejected(hp, n1, n2):
-    rc, msg = _create(hp, hp.config(n1, n2, 0.2, 0.2, 0.05))
+@pytest.mark.parametrize("n1,n2,prec", [(48, 32, "fp32"), (4, 32, "fp32"), (16384, 8, "fp32"),
+                                        (8192, 8, "fp64"), (64, 3, "fp32")])
+def test_bad_grid_rejected(hp, n1, n2, prec):
+    rc, msg = _create(hp, hp.config(n1, n2, 0.2, 0.2, 0.05, precision=prec))
+    assert rc == hp.HP_EINVAL, msg
+
+
+def test_q3d_n1_limit(hp):
+    rc, msg = _create(hp, hp.config(8192, 16, 0.2, 0.2, 0.05, modes=2))
     assert rc == hp.HP_EINVAL, msg
 
 
