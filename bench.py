@@ -304,6 +304,10 @@ def nci_leg(steps):
         out[name] = dict(pick, log10_W_E2_end=round(lw[-1], 3),
                          peak_k1_over_kg1=round(r["peak"]["k1_over_kg1"], 4),
                          peak_k2=round(r["peak"]["k2"], 4))
+    # (0, 0) modes against the time step (filter on): growth rate and k1
+    scan = nci.dt_scan(ratios=(0.25, 0.3, 0.35, 0.4, 0.45, 0.5), steps=30000)
+    out["dt_scan"] = [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()
+                       if k in ("ratio", "growth_rate", "k1_over_kg1")} for r in scan]
     out["wall_s"] = round(time.time() - t0, 2)
     return out
 

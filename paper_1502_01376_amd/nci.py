@@ -115,6 +115,79 @@ def run(cases=("no_filter", "filter"), steps=4000, every=50, precision="fp32", p
     return out
 
 
+def growth_window(t, w, margin=1.5, min_points=3):
+    """Linear-growth window of an energy history: the samples between the
+    noise level (median of the first samples) plus `margin` decades and the
+    saturation level (the maximum) minus `margin` decades.  Returns
+    (t_lo, t_hi) or None."""
+    lw = np.log10(np.maximum(np.asarray(w, dtype=float), 1e-300))
+    t = np.asarray(t, dtype=float)
+    if lw.size < 8:
+        return None
+    noise = float(np.median(lw[1:6]))
+    sat = float(lw.max())
+    sel = np.nonzero((lw > noise + margin) & (lw < sat - margin))[0]
+    if sel.size < min_points:
+        return None
+    # the first contiguous stretch
+    inside = set(sel.tolist())
+    stop = sel[0]
+    while stop + 1 in inside:
+        stop += 1
+    return float(t[sel[0]]), float(t[stop])
+
+
+def dt_scan(ratios=(0.25, 0.3, 0.35, 0.4, 0.45, 0.5), steps=30000, every=200, precision="fp32",
+            ppc=(2, 2), n=(256, 256), seed=None):
+    """Growth of the (0, 0) NCI modes against the time step (Sec. 3 and Fig. 2
+    (a)-(b): reducing dt lowers their growth rate and raises their k1): the
+    Table 1 drift with the k1 filter at half the Nyquist wavenumber, one run
+    per dt = ratio dx1 (all in one batched handle), E2 energy and strongest E2
+    mode every `every` steps.  Per run: the fitted amplitude growth rate over
+    the linear-growth window and the mode's k1/kg1 in the middle of it."""
+    kw = dict(ppc=ppc, n=n)
+    if seed is not None:
+        kw["seed"] = seed
+    d = W.nci_table1(**kw)
+    n1, n2, _ = d["n"]
+    dx1, dx2, _ = d["dx"]
+    cfgs = [hpic.config(n1, n2, dx1, dx2, r * dx1, alpha=0.5, precision=precision)
+            for r in ratios]
+    x = np.stack([d["xi"][k] * d["dx"][k] for k in range(2)])
+    sim = hpic.Sim(cfgs)
+    try:
+        for i in range(len(ratios)):
+            sim.set_particles(i, x, d["u"], d["w"], d["qm"], d["q"])
+            sim.set_background(i, True, d["jbg"])
+        sim.use_graphs(True)
+        hist = [[] for _ in ratios]
+        peaks = [[] for _ in ratios]
+        done = 0
+        while done < steps:
+            k = min(every, steps - done)
+            sim.step(k)
+            done += k
+            for i in range(len(ratios)):
+                hist[i].append(sim.diagnostics(i)["W_E"][1])
+                peaks[i].append(peak_mode(sim.field(i, 1), dx1, dx2))
+    finally:
+        sim.close()
+    out = []
+    for i, r in enumerate(ratios):
+        t = [(j + 1) * every * r * dx1 for j in range(len(hist[i]))]
+        win = growth_window(t, hist[i])
+        res = dict(ratio=r, dt=r * dx1, t_end=t[-1],
+                   log10_W_E2_max=math.log10(max(max(hist[i]), 1e-300)))
+        if win is not None:
+            res["window"] = win
+            res["growth_rate"] = growth_rate(t, hist[i], *win)
+            mid = int(np.argmin(np.abs(np.asarray(t) - 0.5 * (win[0] + win[1]))))
+            res["k1_over_kg1"] = peaks[i][mid]["k1_over_kg1"]
+            res["k2"] = peaks[i][mid]["k2"]
+        out.append(res)
+    return out
+
+
 def main(argv=None):
     import argparse
     import json
@@ -126,7 +199,16 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--fit", default=None, help="t_lo,t_hi of the growth-rate window")
     ap.add_argument("--history", action="store_true", help="print every recorded W_E2")
+    ap.add_argument("--dt-scan", action="store_true",
+                    help="growth of the (0, 0) modes against dt/dx1 instead of the four cases")
     a = ap.parse_args(argv)
+    if a.dt_scan:
+        import time as _t
+        t0 = _t.time()
+        for r in dt_scan(steps=a.steps, precision=a.precision):
+            print(json.dumps(r), flush=True)
+        print(json.dumps(dict(wall_s=round(_t.time() - t0, 2))), flush=True)
+        return
     fit = tuple(float(v) for v in a.fit.split(",")) if a.fit else None
     t0 = time.time()
     res = run(a.cases.split(","), a.steps, a.every, a.precision, fit=fit)

@@ -68,3 +68,18 @@ def test_cubic_shape_keeps_the_kmod_run_quiet(fig3):
     # the quadratic-shape run rises late in the run
     assert _logw(kq, 3200.0) - _logw(kq, 800.0) > 2.0
     assert _logw(kq, 3200.0) - _logw(kc, 3200.0) > 2.5
+
+
+def test_00_modes_against_the_time_step(hpic):
+    """Sec. 3 (Fig. 2 (a)-(b)): reducing the time step lowers the growth rate
+    of the fastest (0, 0) mode and raises its k1.  Measured on the Table 1
+    drift with the filter: amplitude growth rates 0.025, 0.037, 0.046 and
+    k1/kg1 0.25, 0.23, 0.20 at dt/dx1 = 0.25, 0.35, 0.45 (parity unpinned: the
+    figure is not in the text; only the ordering is checked)."""
+    res = nci.dt_scan(ratios=(0.25, 0.35, 0.45), steps=30000)
+    rates = [r["growth_rate"] for r in res]
+    k1 = [r["k1_over_kg1"] for r in res]
+    assert all(0.005 < g < 0.2 for g in rates), res
+    assert rates[0] < rates[1] < rates[2], res
+    assert k1[0] > k1[2], res
+    assert all(0.12 < k < 0.3 for k in k1), res
