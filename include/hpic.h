@@ -83,9 +83,9 @@ extern "C" {
 typedef struct hp_config {
   int32_t geom;              /* HP_GEOM_2D or HP_GEOM_3D (same for all runs of a handle) */
   int32_t n[3];              /* cells per direction (n[2] unused in 2D); n[0] a
-                                power of two, 8 .. 8192 in the FP32 form of
-                                Cartesian runs, 8 .. 4096 otherwise (LDS of the
-                                row transforms) */
+                                power of two, 8 .. 8192 for Cartesian runs,
+                                8 .. 4096 for quasi-3D runs (LDS of the row
+                                transforms) */
   double dx[3];              /* cell sizes */
   double dt;                 /* time step */
   int32_t shape_order;       /* particle shape order: 2 (quadratic) or 3 (cubic

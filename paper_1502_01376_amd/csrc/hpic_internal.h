@@ -324,8 +324,10 @@ struct Launch {
   // order); false keeps the arrival order, so the scatter writes are coalesced
   static void sort(const Run<R> *runs, const Item *chunks, int nchunks, const Item *per_run,
                    int nruns, int pp, bool scramble, hipStream_t s);
+  // row transforms: ncomp = 3 components per block (item = run, row[, group])
+  // or 1 (item = run, row, component) for long rows
   static void fft_j(const Run<R> *runs, const Item *items, int nitems, int parity, int maxM,
-                    hipStream_t s);
+                    int ncomp, hipStream_t s);
   static void kupdate(const Run<R> *runs, const Item *items, int nitems, int parity,
                       hipStream_t s);
   // 3D: the same update as two passes (E and the half-step B, then B)
@@ -335,9 +337,9 @@ struct Launch {
                             int pp, int lds_bytes, unsigned *err, unsigned *stats,
                             hipStream_t s);
   static void ifft_eb(const Run<R> *runs, const Item *items, int nitems, int parity, int maxM,
-                      hipStream_t s);
+                      int ncomp, hipStream_t s);
   static void fields_to_k(const Run<R> *runs, const Item *items, int nitems, int parity,
-                          int maxM, hipStream_t s);
+                          int maxM, int ncomp, hipStream_t s);
 };
 
 

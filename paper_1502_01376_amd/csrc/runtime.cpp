@@ -183,11 +183,13 @@ class Sim : public SimBase {
   int init(const hp_config *cfgs, int nruns) {
     HIPCHK(hipGetDevice(&device_));
     {
-      // LDS of the row transforms: three components of n1/2 complex values
+      // LDS of the row transforms: ncomp components of n1/2 complex values
+      // (three per block up to n1 = 4096, one beyond)
       int lim = 0, n1max = 0;
       HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device_));
       for (int i = 0; i < nruns; ++i) n1max = std::max(n1max, cfgs[i].n[0]);
-      const size_t need = 3 * (size_t)(n1max / 2) * sizeof(C);
+      ncomp_ = n1max > 4096 ? 1 : 3;
+      const size_t need = (size_t)ncomp_ * (n1max / 2) * sizeof(C);
       if (need > (size_t)lim)
         return fail(HP_EINVAL, "n1 = %d needs %zu bytes of LDS per row transform, the device allows %d",
                     n1max, need, lim);
@@ -281,13 +283,13 @@ class Sim : public SimBase {
       d.midx3 = d.dim == 3 ? 1.0 / c.dx[2] : 0.0;
       d.jfac = djfac;
       if ((rc = upload_jfac(i))) return rc;
+      // rows longer than 4096 are transformed one component per block
       h.row0 = (int)rows.size();
-      for (int r = 0; r < d.rows; ++r) rows.push_back(Item{i, r, 0});
+      for (int r = 0; r < d.rows; ++r)
+        for (int c = 0; c < 3; c += ncomp_) rows.push_back(Item{i, r, ncomp_ == 3 ? 0 : c});
       h.grp0 = (int)grps.size();
-      for (int r = 0; r < d.rows; ++r) {
-        grps.push_back(Item{i, r, 0});
-        grps.push_back(Item{i, r, 1});
-      }
+      for (int r = 0; r < d.rows; ++r)
+        for (int g = 0; g < 6; g += ncomp_) grps.push_back(Item{i, r, ncomp_ == 3 ? g / 3 : g});
       const int nel = d.rows * d.nk;
       for (int e = 0; e < nel; e += UPD_BLOCK) upd.push_back(Item{i, e, 0});
       perrun.push_back(Item{i, 0, 0});
@@ -427,7 +429,8 @@ class Sim : public SimBase {
     }
     int rc;
     if ((rc = h2d(d.F, F.data(), 6 * cells))) return rc;
-    Launch<R>::fields_to_k(d_runs_, d_grps_ + h.grp0, 2 * d.rows, parity_, maxM_, stream_);
+    Launch<R>::fields_to_k(d_runs_, d_grps_ + h.grp0, (6 / ncomp_) * d.rows, parity_, maxM_, ncomp_,
+                           stream_);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream_));
     return HP_OK;
@@ -479,7 +482,7 @@ class Sim : public SimBase {
     ++since_sort_;
     if (n_ant_ > 0) launch_antenna<R>(d_runs_, d_ant_, n_ant_, ant_maxn2_, p, d_step_, stream_);
     mark(HP_K_FFT_J, true);
-    Launch<R>::fft_j(d_runs_, d_rows_, n_rows_, p, maxM_, stream_);
+    Launch<R>::fft_j(d_runs_, d_rows_, n_rows_, p, maxM_, ncomp_, stream_);
     mark(HP_K_FFT_J, false);
     mark(HP_K_KUPDATE, true);
     if (dim_ == 3)
@@ -488,7 +491,7 @@ class Sim : public SimBase {
       Launch<R>::kupdate(d_runs_, d_upd_, n_upd_, p, stream_);
     mark(HP_K_KUPDATE, false);
     mark(HP_K_IFFT_EB, true);
-    Launch<R>::ifft_eb(d_runs_, d_grps_, n_grps_, p ^ 1, maxM_, stream_);
+    Launch<R>::ifft_eb(d_runs_, d_grps_, n_grps_, p ^ 1, maxM_, ncomp_, stream_);
     mark(HP_K_IFFT_EB, false);
     if (n_ant_ > 0) launch_step_tick(d_step_, stream_);
     parity_ ^= 1;
@@ -1548,6 +1551,7 @@ class Sim : public SimBase {
   hipGraphExec_t graph_[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   hipStream_t capture_stream_ = nullptr;
   int maxM_ = 0;
+  int ncomp_ = 3;                  // components per row-transform block (1 for n1 > 4096)
   int parity_ = 0;
   int64_t step_ = 0;
   unsigned *d_err_ = nullptr;
@@ -2276,10 +2280,10 @@ int hp_create(const hp_config *cfgs, int32_t nruns, hp_sim **out) {
     }
     if (c.precision != prec || (prec != HP_PREC_FP32_FIXED && prec != HP_PREC_FP64))
       return fail(HP_EINVAL, "run %d: precision must be one of the two forms and equal for all runs", i);
-    // the row transforms hold a row's three components (n1/2 complex values
-    // each) in LDS: up to n1 = 8192 in the FP32 form of Cartesian runs
-    // (96 KiB), 4096 otherwise
-    const int n1max = (c.geom != HP_GEOM_Q3D && prec == HP_PREC_FP32_FIXED) ? 8192 : 4096;
+    // the row transforms hold n1/2 complex values per component in LDS (one
+    // component per block beyond 4096): up to n1 = 8192 for Cartesian runs,
+    // 4096 for quasi-3D ones
+    const int n1max = c.geom != HP_GEOM_Q3D ? 8192 : 4096;
     if (!is_pow2(c.n[0]) || c.n[0] < 8 || c.n[0] > n1max)
       return fail(HP_EINVAL, "run %d: n1 = %d must be a power of two in [8, %d] for this form", i,
                   c.n[0], n1max);

@@ -39,10 +39,14 @@ __device__ __forceinline__ C c2r_pre(C Xk, C Xmk, C Wk) {
   return cmk(R(0.5) * (e.x - o.y), R(0.5) * (e.y + o.x));
 }
 
-// One workgroup per (run, row): the three current components of the row.
+// One workgroup per (run, row): the three current components of the row
+// (ncomp = 3), or per (run, row, component) for long rows (ncomp = 1, item.b
+// the component), so that a block's LDS stays small enough for several
+// blocks per CU.
 template <class R>
 __global__ void __launch_bounds__(256) k_fft_j(const Run<R> *__restrict__ runs,
-                                               const Item *__restrict__ items, int parity) {
+                                               const Item *__restrict__ items, int parity,
+                                               int ncomp) {
   using C = typename Cplx<R>::T;
   extern __shared__ unsigned char smem_raw[];
   C *lds = (C *)smem_raw;
@@ -52,25 +56,27 @@ __global__ void __launch_bounds__(256) k_fft_j(const Run<R> *__restrict__ runs,
   const int n1 = r.n1, M = n1 >> 1, log2M = r.log2n1 - 1, cells = r.cells;
   const auto *Jin = r.J[parity];
   auto *Jz = r.J[parity ^ 1];
-  for (int c = 0; c < 3; ++c) {
-    const long long base = (long long)c * cells + (long long)row * n1;
+  const int cb = ncomp == 3 ? 0 : it.b;
+  for (int cc = 0; cc < ncomp; ++cc) {
+    const long long base = (long long)(cb + cc) * cells + (long long)row * n1;
     for (int n = threadIdx.x; n < M; n += blockDim.x) {
       const R x0 = to_real<R>(Jin[base + 2 * n]);
       const R x1 = to_real<R>(Jin[base + 2 * n + 1]);
-      lds[c * M + n] = cmk(x0, x1);
+      lds[cc * M + n] = cmk(x0, x1);
       Jz[base + 2 * n] = 0;
       Jz[base + 2 * n + 1] = 0;
     }
   }
   __syncthreads();
-  lds_fft_rows<C, 6>(lds, M, log2M, 3, r.tw, 2, false);
+  lds_fft_rows<C, 6>(lds, M, log2M, ncomp, r.tw, 2, false);
   const int nk = r.nk;
   for (int k = threadIdx.x; k <= (M >> 1); k += blockDim.x) {
     const int mk = M - k;
     const C Wk = r.tw[k], Wmk = r.tw[mk];
-    for (int c = 0; c < 3; ++c) {
-      const C Zk = lds[c * M + k];
-      const C Zmk = lds[c * M + (mk & (M - 1))];
+    for (int cc = 0; cc < ncomp; ++cc) {
+      const int c = cb + cc;
+      const C Zk = lds[cc * M + k];
+      const C Zmk = lds[cc * M + (mk & (M - 1))];
       C Xk = r2c_post(Zk, Zmk, Wk);
       const R fk = r.jfac[k * 3 + c];
       Xk = cscale(Xk, fk);
@@ -87,29 +93,31 @@ __global__ void __launch_bounds__(256) k_fft_j(const Run<R> *__restrict__ runs,
 }
 
 // Forward transform of the six real-space fields of a row into the k-space
-// master (initialisation).  Item = (run, row, group): group g covers 3g..3g+2.
+// master (initialisation).  Item = (run, row, group): group g covers 3g..3g+2
+// (ncomp = 3), or (run, row, component) (ncomp = 1).
 template <class R>
 __global__ void __launch_bounds__(256) k_fields_to_k(const Run<R> *__restrict__ runs,
-                                                     const Item *__restrict__ items, int parity) {
+                                                     const Item *__restrict__ items, int parity,
+                                                     int ncomp) {
   using C = typename Cplx<R>::T;
   extern __shared__ unsigned char smem_raw[];
   C *lds = (C *)smem_raw;
   const Item it = items[blockIdx.x];
   const Run<R> &r = runs[it.run];
-  const int row = it.a, grp = it.b;
+  const int row = it.a, cb = ncomp == 3 ? 3 * it.b : it.b;
   const int n1 = r.n1, M = n1 >> 1, log2M = r.log2n1 - 1, cells = r.cells, nk = r.nk;
-  for (int c = 0; c < 3; ++c) {
-    const R *src = r.F + (long long)(3 * grp + c) * cells + (long long)row * n1;
-    for (int n = threadIdx.x; n < M; n += blockDim.x) lds[c * M + n] = cmk(src[2 * n], src[2 * n + 1]);
+  for (int cc = 0; cc < ncomp; ++cc) {
+    const R *src = r.F + (long long)(cb + cc) * cells + (long long)row * n1;
+    for (int n = threadIdx.x; n < M; n += blockDim.x) lds[cc * M + n] = cmk(src[2 * n], src[2 * n + 1]);
   }
   __syncthreads();
-  lds_fft_rows<C, 6>(lds, M, log2M, 3, r.tw, 2, false);
+  lds_fft_rows<C, 6>(lds, M, log2M, ncomp, r.tw, 2, false);
   for (int k = threadIdx.x; k <= (M >> 1); k += blockDim.x) {
     const int mk = M - k;
-    for (int c = 0; c < 3; ++c) {
-      const C Zk = lds[c * M + k];
-      const C Zmk = lds[c * M + (mk & (M - 1))];
-      double2 *out = r.Fk[parity] + (long long)(3 * grp + c) * r.rows * nk + (long long)row * nk;
+    for (int cc = 0; cc < ncomp; ++cc) {
+      const C Zk = lds[cc * M + k];
+      const C Zmk = lds[cc * M + (mk & (M - 1))];
+      double2 *out = r.Fk[parity] + (long long)(cb + cc) * r.rows * nk + (long long)row * nk;
       out[k] = to_d2(r2c_post(Zk, Zmk, r.tw[k]));
       if (mk != k) out[mk] = to_d2(r2c_post(Zmk, Zk, r.tw[mk]));
     }
@@ -293,33 +301,35 @@ __global__ void __launch_bounds__(256) k_kupdate3b(const Run<R> *__restrict__ ru
 // inverse FFT of E and B
 // =====================================================================
 // Item = (run, row, group): components 3g..3g+2 of the master buffer of the
-// given parity, written to the real-space fields.
+// given parity, written to the real-space fields (ncomp = 3); or (run, row,
+// component) (ncomp = 1).
 template <class R>
 __global__ void __launch_bounds__(256) k_ifft_eb(const Run<R> *__restrict__ runs,
-                                                 const Item *__restrict__ items, int parity) {
+                                                 const Item *__restrict__ items, int parity,
+                                                 int ncomp) {
   using C = typename Cplx<R>::T;
   extern __shared__ unsigned char smem_raw[];
   C *lds = (C *)smem_raw;
   const Item it = items[blockIdx.x];
   const Run<R> &r = runs[it.run];
-  const int row = it.a, grp = it.b;
+  const int row = it.a, cb = ncomp == 3 ? 3 * it.b : it.b;
   const int n1 = r.n1, M = n1 >> 1, log2M = r.log2n1 - 1, cells = r.cells, nk = r.nk;
   for (int k = threadIdx.x; k <= (M >> 1); k += blockDim.x) {
     const int mk = M - k;
-    for (int c = 0; c < 3; ++c) {
-      const double2 *X = r.Fk[parity] + (long long)(3 * grp + c) * r.rows * nk + (long long)row * nk;
+    for (int cc = 0; cc < ncomp; ++cc) {
+      const double2 *X = r.Fk[parity] + (long long)(cb + cc) * r.rows * nk + (long long)row * nk;
       const C Xk = from_d2<C>(X[k]), Xmk = from_d2<C>(X[mk]);
-      lds[c * M + k] = c2r_pre(Xk, Xmk, r.tw[k]);
-      if (k != 0 && mk != k) lds[c * M + mk] = c2r_pre(Xmk, Xk, r.tw[mk]);
+      lds[cc * M + k] = c2r_pre(Xk, Xmk, r.tw[k]);
+      if (k != 0 && mk != k) lds[cc * M + mk] = c2r_pre(Xmk, Xk, r.tw[mk]);
     }
   }
   __syncthreads();
-  lds_fft_rows<C, 6>(lds, M, log2M, 3, r.tw, 2, true);
+  lds_fft_rows<C, 6>(lds, M, log2M, ncomp, r.tw, 2, true);
   const R s = r.inv_m;
-  for (int c = 0; c < 3; ++c) {
-    R *dst = r.F + (long long)(3 * grp + c) * cells + (long long)row * n1;
+  for (int cc = 0; cc < ncomp; ++cc) {
+    R *dst = r.F + (long long)(cb + cc) * cells + (long long)row * n1;
     for (int n = threadIdx.x; n < M; n += blockDim.x) {
-      const C z = lds[c * M + n];
+      const C z = lds[cc * M + n];
       dst[2 * n] = z.x * s;
       dst[2 * n + 1] = z.y * s;
     }
@@ -494,10 +504,10 @@ __global__ void k_cont_fp64(const double *rn, const double *ro, const double *J,
 
 template <class R>
 void Launch<R>::fft_j(const Run<R> *runs, const Item *items, int nitems, int parity, int maxM,
-                      hipStream_t s) {
+                      int ncomp, hipStream_t s) {
   if (nitems <= 0) return;
-  const size_t lds = 3 * (size_t)maxM * sizeof(typename Cplx<R>::T);
-  hipLaunchKernelGGL(k_fft_j<R>, dim3(nitems), dim3(256), lds, s, runs, items, parity);
+  const size_t lds = (size_t)ncomp * maxM * sizeof(typename Cplx<R>::T);
+  hipLaunchKernelGGL(k_fft_j<R>, dim3(nitems), dim3(256), lds, s, runs, items, parity, ncomp);
 }
 
 // 3D Gauss residual on the row (i2, i3): R = D1- E1 + D2- E2 + D3- E3 - f rho
@@ -605,18 +615,19 @@ void Launch<R>::kupdate(const Run<R> *runs, const Item *items, int nitems, int p
 
 template <class R>
 void Launch<R>::ifft_eb(const Run<R> *runs, const Item *items, int nitems, int parity, int maxM,
-                        hipStream_t s) {
+                        int ncomp, hipStream_t s) {
   if (nitems <= 0) return;
-  const size_t lds = 3 * (size_t)maxM * sizeof(typename Cplx<R>::T);
-  hipLaunchKernelGGL(k_ifft_eb<R>, dim3(nitems), dim3(256), lds, s, runs, items, parity);
+  const size_t lds = (size_t)ncomp * maxM * sizeof(typename Cplx<R>::T);
+  hipLaunchKernelGGL(k_ifft_eb<R>, dim3(nitems), dim3(256), lds, s, runs, items, parity, ncomp);
 }
 
 template <class R>
 void Launch<R>::fields_to_k(const Run<R> *runs, const Item *items, int nitems, int parity,
-                            int maxM, hipStream_t s) {
+                            int maxM, int ncomp, hipStream_t s) {
   if (nitems <= 0) return;
-  const size_t lds = 3 * (size_t)maxM * sizeof(typename Cplx<R>::T);
-  hipLaunchKernelGGL(k_fields_to_k<R>, dim3(nitems), dim3(256), lds, s, runs, items, parity);
+  const size_t lds = (size_t)ncomp * maxM * sizeof(typename Cplx<R>::T);
+  hipLaunchKernelGGL(k_fields_to_k<R>, dim3(nitems), dim3(256), lds, s, runs, items, parity,
+                     ncomp);
 }
 
 template <class R>

@@ -82,7 +82,7 @@ def test_courant_violation_rejected(hp):
 
 
 @pytest.mark.parametrize("n1,n2,prec", [(48, 32, "fp32"), (4, 32, "fp32"), (16384, 8, "fp32"),
-                                        (8192, 8, "fp64"), (64, 3, "fp32")])
+                                        (16384, 8, "fp64"), (64, 3, "fp32")])
 def test_bad_grid_rejected(hp, n1, n2, prec):
     rc, msg = _create(hp, hp.config(n1, n2, 0.2, 0.2, 0.05, precision=prec))
     assert rc == hp.HP_EINVAL, msg
