@@ -119,11 +119,11 @@ template <class C> __device__ __forceinline__ C cmuli(C a, bool plus) {
 // (no 1/M).  MAXB bounds the radix-4 butterflies per thread per pass.
 template <class C, int MAXB>
 __device__ void lds_fft(C *buf, int M, int log2M, int NF, const C *__restrict__ tw, int tws,
-                        bool inverse) {
+                        bool inverse, int s0 = 0) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int Q = M >> 2;
   const int log2Q = log2M - 2;
-  int s = 0;  // log2 of the span Ns already transformed
+  int s = s0;  // log2 of the span Ns already transformed
   for (; s + 2 <= log2M; s += 2) {
     const int Ns = 1 << s;
     C v[MAXB][4];
@@ -186,6 +186,93 @@ __device__ void lds_fft(C *buf, int M, int log2M, int NF, const C *__restrict__ 
   }
 }
 
+// 4-point DFT in place (forward: X_q = sum_r a_r exp(-2 pi i r q / 4)).
+template <class C>
+__device__ __forceinline__ void dft4(C &a0, C &a1, C &a2, C &a3, bool inverse) {
+  const C b0 = cadd(a0, a2), b1 = csub(a0, a2), b2 = cadd(a1, a3);
+  const C b3 = cmuli(csub(a1, a3), inverse);
+  a0 = cadd(b0, b2);
+  a1 = cadd(b1, b3);
+  a2 = csub(b0, b2);
+  a3 = csub(b1, b3);
+}
+// exp(-2 pi i m / 16) (conjugate for the inverse) of the 16-point DFT's
+// inner twiddles, m = r2 q1 in {1, 2, 3, 4, 6, 9}
+template <class C>
+__device__ __forceinline__ C w16(int m, bool inverse) {
+  using R = decltype(C().x);
+  const R c1 = R(0.92387953251128675613), s1 = R(0.38268343236508977173);
+  const R h = R(0.70710678118654752440);
+  R x, y;
+  switch (m) {
+    case 1: x = c1; y = -s1; break;
+    case 2: x = h; y = -h; break;
+    case 3: x = s1; y = -c1; break;
+    case 4: x = 0; y = -1; break;
+    case 6: x = -h; y = -h; break;
+    default: x = -c1; y = s1; break;  // 9
+  }
+  return cmk(x, inverse ? -y : y);
+}
+// 16-point DFT in registers as 4 x 4: a[r] -> y_q with q = q1 + 4 q2 stored
+// at a[4 q1 + q2].
+template <class C>
+__device__ __forceinline__ void dft16(C a[16], bool inverse) {
+#pragma unroll
+  for (int r2 = 0; r2 < 4; ++r2) dft4(a[r2], a[4 + r2], a[8 + r2], a[12 + r2], inverse);
+#pragma unroll
+  for (int q1 = 1; q1 < 4; ++q1)
+#pragma unroll
+    for (int r2 = 1; r2 < 4; ++r2) a[4 * q1 + r2] = cmul(a[4 * q1 + r2], w16<C>(r2 * q1, inverse));
+#pragma unroll
+  for (int q1 = 0; q1 < 4; ++q1) dft4(a[4 * q1], a[4 * q1 + 1], a[4 * q1 + 2], a[4 * q1 + 3], inverse);
+}
+// NF transforms of length M in LDS, radix-16 Stockham passes (one 16-point
+// butterfly per thread, all of them held in registers across the barrier)
+// while they fit the block, then the radix-4/2 passes of lds_fft.  Same
+// result as lds_fft.
+template <class C, int MAXB>
+__device__ void lds_fft16(C *buf, int M, int log2M, int NF, const C *__restrict__ tw, int tws,
+                          bool inverse) {
+  int s = 0;
+  if (NF * (M >> 4) <= (int)blockDim.x) {
+    const int Q = M >> 4, log2Q = log2M - 4, g = threadIdx.x;
+    for (; s + 4 <= log2M; s += 4) {
+      const int Ns = 1 << s;
+      C v[16];
+      int ob = 0;
+      const bool act = g < NF * Q;
+      if (act) {
+        const int f = g >> log2Q, j = g & (Q - 1), k = j & (Ns - 1);
+        const C *x = buf + f * M;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = x[j + r * Q];
+        if (s > 0) {
+          // twiddle w^(r k), w = exp(-+2 pi i / (16 Ns)): table index r k M / (16 Ns)
+          const int e = k << (log2Q - s);
+#pragma unroll
+          for (int r = 1; r < 16; ++r) {
+            C t = tw[(r * e) * tws];
+            if (inverse) t = cconj(t);
+            v[r] = cmul(v[r], t);
+          }
+        }
+        dft16(v, inverse);
+        ob = f * M + ((j >> s) << (s + 4)) + k;
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int q1 = 0; q1 < 4; ++q1)
+#pragma unroll
+          for (int q2 = 0; q2 < 4; ++q2) buf[ob + (q1 + 4 * q2) * Ns] = v[4 * q1 + q2];
+      }
+      __syncthreads();
+    }
+  }
+  lds_fft<C, MAXB>(buf, M, log2M, NF, tw, tws, inverse, s);
+}
+
 // NF transforms of length M in LDS (as lds_fft), one transform at a time when
 // the radix-4 passes of all NF at once would need more than MAXB butterflies
 // per thread (n1 = 8192 rows: three components of M = 4096).  The choice is
@@ -194,10 +281,10 @@ template <class C, int MAXB>
 __device__ void lds_fft_rows(C *buf, int M, int log2M, int NF, const C *__restrict__ tw, int tws,
                              bool inverse) {
   if (NF * (M >> 2) <= MAXB * (int)blockDim.x) {
-    lds_fft<C, MAXB>(buf, M, log2M, NF, tw, tws, inverse);
+    lds_fft16<C, MAXB>(buf, M, log2M, NF, tw, tws, inverse);
     return;
   }
-  for (int f = 0; f < NF; ++f) lds_fft<C, MAXB>(buf + f * M, M, log2M, 1, tw, tws, inverse);
+  for (int f = 0; f < NF; ++f) lds_fft16<C, MAXB>(buf + f * M, M, log2M, 1, tw, tws, inverse);
 }
 
 // ---------------------------------------------------------------- shapes

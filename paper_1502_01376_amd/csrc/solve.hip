@@ -43,7 +43,7 @@ __device__ __forceinline__ C c2r_pre(C Xk, C Xmk, C Wk) {
 // (ncomp = 3), or per (run, row, component) for long rows (ncomp = 1, item.b
 // the component), so that a block's LDS stays small enough for several
 // blocks per CU.
-template <class R>
+template <class R, int MAXB>
 __global__ void __launch_bounds__(256) k_fft_j(const Run<R> *__restrict__ runs,
                                                const Item *__restrict__ items, int parity,
                                                int ncomp) {
@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(256) k_fft_j(const Run<R> *__restrict__ runs,
     }
   }
   __syncthreads();
-  lds_fft_rows<C, 6>(lds, M, log2M, ncomp, r.tw, 2, false);
+  lds_fft_rows<C, MAXB>(lds, M, log2M, ncomp, r.tw, 2, false);
   const int nk = r.nk;
   for (int k = threadIdx.x; k <= (M >> 1); k += blockDim.x) {
     const int mk = M - k;
@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(256) k_fft_j(const Run<R> *__restrict__ runs,
 // Forward transform of the six real-space fields of a row into the k-space
 // master (initialisation).  Item = (run, row, group): group g covers 3g..3g+2
 // (ncomp = 3), or (run, row, component) (ncomp = 1).
-template <class R>
+template <class R, int MAXB>
 __global__ void __launch_bounds__(256) k_fields_to_k(const Run<R> *__restrict__ runs,
                                                      const Item *__restrict__ items, int parity,
                                                      int ncomp) {
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(256) k_fields_to_k(const Run<R> *__restrict__ 
     for (int n = threadIdx.x; n < M; n += blockDim.x) lds[cc * M + n] = cmk(src[2 * n], src[2 * n + 1]);
   }
   __syncthreads();
-  lds_fft_rows<C, 6>(lds, M, log2M, ncomp, r.tw, 2, false);
+  lds_fft_rows<C, MAXB>(lds, M, log2M, ncomp, r.tw, 2, false);
   for (int k = threadIdx.x; k <= (M >> 1); k += blockDim.x) {
     const int mk = M - k;
     for (int cc = 0; cc < ncomp; ++cc) {
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(256) k_kupdate3b(const Run<R> *__restrict__ ru
 // Item = (run, row, group): components 3g..3g+2 of the master buffer of the
 // given parity, written to the real-space fields (ncomp = 3); or (run, row,
 // component) (ncomp = 1).
-template <class R>
+template <class R, int MAXB>
 __global__ void __launch_bounds__(256) k_ifft_eb(const Run<R> *__restrict__ runs,
                                                  const Item *__restrict__ items, int parity,
                                                  int ncomp) {
@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(256) k_ifft_eb(const Run<R> *__restrict__ runs
     }
   }
   __syncthreads();
-  lds_fft_rows<C, 6>(lds, M, log2M, ncomp, r.tw, 2, true);
+  lds_fft_rows<C, MAXB>(lds, M, log2M, ncomp, r.tw, 2, true);
   const R s = r.inv_m;
   for (int cc = 0; cc < ncomp; ++cc) {
     R *dst = r.F + (long long)(cb + cc) * cells + (long long)row * n1;
@@ -502,12 +502,21 @@ __global__ void k_cont_fp64(const double *rn, const double *ro, const double *J,
 // =====================================================================
 #define HP_CHECK_LAUNCH() (void)hipGetLastError()
 
+// Row transforms whose radix-4 passes need at most 3 butterflies per thread
+// (256 threads): rows of up to 2048 points with three components per block,
+// or one component per block (the radix-16 passes then cover up to 4096).
+// Their kernels are built with the smaller register buffer.
+static bool small_rows(int maxM, int ncomp) { return maxM <= 1024 || ncomp == 1; }
+
 template <class R>
 void Launch<R>::fft_j(const Run<R> *runs, const Item *items, int nitems, int parity, int maxM,
                       int ncomp, hipStream_t s) {
   if (nitems <= 0) return;
   const size_t lds = (size_t)ncomp * maxM * sizeof(typename Cplx<R>::T);
-  hipLaunchKernelGGL(k_fft_j<R>, dim3(nitems), dim3(256), lds, s, runs, items, parity, ncomp);
+  if (small_rows(maxM, ncomp))
+    hipLaunchKernelGGL((k_fft_j<R, 3>), dim3(nitems), dim3(256), lds, s, runs, items, parity, ncomp);
+  else
+    hipLaunchKernelGGL((k_fft_j<R, 6>), dim3(nitems), dim3(256), lds, s, runs, items, parity, ncomp);
 }
 
 // 3D Gauss residual on the row (i2, i3): R = D1- E1 + D2- E2 + D3- E3 - f rho
@@ -618,7 +627,10 @@ void Launch<R>::ifft_eb(const Run<R> *runs, const Item *items, int nitems, int p
                         int ncomp, hipStream_t s) {
   if (nitems <= 0) return;
   const size_t lds = (size_t)ncomp * maxM * sizeof(typename Cplx<R>::T);
-  hipLaunchKernelGGL(k_ifft_eb<R>, dim3(nitems), dim3(256), lds, s, runs, items, parity, ncomp);
+  if (small_rows(maxM, ncomp))
+    hipLaunchKernelGGL((k_ifft_eb<R, 3>), dim3(nitems), dim3(256), lds, s, runs, items, parity, ncomp);
+  else
+    hipLaunchKernelGGL((k_ifft_eb<R, 6>), dim3(nitems), dim3(256), lds, s, runs, items, parity, ncomp);
 }
 
 template <class R>
@@ -626,8 +638,12 @@ void Launch<R>::fields_to_k(const Run<R> *runs, const Item *items, int nitems, i
                             int maxM, int ncomp, hipStream_t s) {
   if (nitems <= 0) return;
   const size_t lds = (size_t)ncomp * maxM * sizeof(typename Cplx<R>::T);
-  hipLaunchKernelGGL(k_fields_to_k<R>, dim3(nitems), dim3(256), lds, s, runs, items, parity,
-                     ncomp);
+  if (small_rows(maxM, ncomp))
+    hipLaunchKernelGGL((k_fields_to_k<R, 3>), dim3(nitems), dim3(256), lds, s, runs, items, parity,
+                       ncomp);
+  else
+    hipLaunchKernelGGL((k_fields_to_k<R, 6>), dim3(nitems), dim3(256), lds, s, runs, items, parity,
+                       ncomp);
 }
 
 template <class R>
