@@ -131,6 +131,23 @@ __device__ __forceinline__ R gather_c(const R *__restrict__ F, int n1, int n2, i
   return acc;
 }
 
+// The same from the tile's field box in LDS (row stride FW, box-local first
+// nodes c0, r0).
+template <class R>
+__device__ __forceinline__ R gather_cl(const lptrc<R> Fl, int FW, int c0, const R w1[4], int r0,
+                                       const R w2[4]) {
+  R acc = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const lptrc<R> row = Fl + (r0 + b) * FW + c0;
+    R s = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) s += w1[a] * row[a];
+    acc += w2[b] * s;
+  }
+  return acc;
+}
+
 // Integer cubic weights of the nodes m-1 .. m+2 for a position m + d: the
 // spline values in FP32 (no contraction, so every call site computes the same
 // integers from the same offset) scaled by 2^P and rounded, the node m+1
@@ -342,13 +359,28 @@ __global__ void __launch_bounds__(256) k_push_deposit_cubic(const Run<R> *__rest
   lo2 = min(min(red[0][2], red[1][2]), min(red[2][2], red[3][2])) - 2;
   hi2 = max(max(red[0][3], red[1][3]), max(red[2][3], red[3][3])) + 3;
   const int W = hi1 - lo1 + 1, H = hi2 - lo2 + 1;
-  const bool use_lds = W <= n1 && H <= n2 && 3LL * W * H * (long long)sizeof(A) <= lds_bytes;
+  // field box: relative cells lo1 .. hi1 - 1 (a stencil reaches cell - 2 .. cell + 2)
+  const int FW = W - 1, FH = H - 1;
+  const long long jbytes = (3LL * W * H * (long long)sizeof(A) + 15) & ~15LL;
+  const bool use_lds = W <= n1 && H <= n2 && jbytes <= lds_bytes;
+  const bool use_fl = use_lds && jbytes + 6LL * FW * FH * (long long)sizeof(R) <= lds_bytes;
   const lptrc<A> box = (lptrc<A>)smem_raw;
-  if (use_lds)
-    for (int e = threadIdx.x; e < 3 * W * H; e += 256) box[e] = 0;
-  __syncthreads();
+  const lptrc<R> fl = (lptrc<R>)(smem_raw + jbytes);
   const long long cells = r.cells;
   const R *F = r.F;
+  if (use_lds)
+    for (int e = threadIdx.x; e < 3 * W * H; e += 256) box[e] = 0;
+  if (use_fl) {
+    const int plane = FW * FH;
+    for (int e = threadIdx.x; e < 6 * plane; e += 256) {
+      const int comp = e / plane, q = e - comp * plane;
+      const int b = q / FW, a = q - b * FW;
+      int g2 = (ref2 + lo2 + b) % n2;
+      g2 += g2 < 0 ? n2 : 0;
+      fl[e] = G(F)[comp * cells + (long long)g2 * n1 + wrap_pow2(ref1 + lo1 + a, n1)];
+    }
+  }
+  __syncthreads();
   for (int p = start + (int)threadIdx.x; p < end; p += 256) {
     const int cell = G(P.cell)[p];
     const int i1 = cell & (n1 - 1), i2 = cell >> r.log2n1;
@@ -365,12 +397,25 @@ __global__ void __launch_bounds__(256) k_push_deposit_cubic(const Run<R> *__rest
     const int ri = stencil4<R>(i2, f2, false, false, wi2);
     const int rh = stencil4<R>(i2, f2, true, EC, wh2);
     R E[3], B[3];
-    E[0] = gather_c<R>(F, n1, n2, ch, wh1, ri, wi2);
-    E[1] = gather_c<R>(F + cells, n1, n2, ci, wi1, rh, wh2);
-    E[2] = gather_c<R>(F + 2 * cells, n1, n2, ci, wi1, ri, wi2);
-    B[0] = gather_c<R>(F + 3 * cells, n1, n2, ci, wi1, rh, wh2);
-    B[1] = gather_c<R>(F + 4 * cells, n1, n2, ch, wh1, ri, wi2);
-    B[2] = gather_c<R>(F + 5 * cells, n1, n2, ch, wh1, rh, wh2);
+    if (use_fl) {
+      // box-local first nodes: the stencil starts 1 or 2 cells before the cell
+      const int lci = rel1 - lo1 + (ci - i1), lch = rel1 - lo1 + (ch - i1);
+      const int lri = rel2 - lo2 + (ri - i2), lrh = rel2 - lo2 + (rh - i2);
+      const int plane = FW * FH;
+      E[0] = gather_cl<R>(fl, FW, lch, wh1, lri, wi2);
+      E[1] = gather_cl<R>(fl + plane, FW, lci, wi1, lrh, wh2);
+      E[2] = gather_cl<R>(fl + 2 * plane, FW, lci, wi1, lri, wi2);
+      B[0] = gather_cl<R>(fl + 3 * plane, FW, lci, wi1, lrh, wh2);
+      B[1] = gather_cl<R>(fl + 4 * plane, FW, lch, wh1, lri, wi2);
+      B[2] = gather_cl<R>(fl + 5 * plane, FW, lch, wh1, lrh, wh2);
+    } else {
+      E[0] = gather_c<R>(F, n1, n2, ch, wh1, ri, wi2);
+      E[1] = gather_c<R>(F + cells, n1, n2, ci, wi1, rh, wh2);
+      E[2] = gather_c<R>(F + 2 * cells, n1, n2, ci, wi1, ri, wi2);
+      B[0] = gather_c<R>(F + 3 * cells, n1, n2, ci, wi1, rh, wh2);
+      B[1] = gather_c<R>(F + 4 * cells, n1, n2, ch, wh1, ri, wi2);
+      B[2] = gather_c<R>(F + 5 * cells, n1, n2, ch, wh1, rh, wh2);
+    }
     borisc<R>(r.qmhdt, E, B, u);
     R v[3];
     {
