@@ -324,8 +324,8 @@ __device__ __forceinline__ void deposit_q(const Sink &put, int M, const R S0z[4]
   }
 }
 
-// The rare global-atomic path out of line, so that it does not add to the
-// register budget of the LDS path.
+// The rare global-atomic path of the FP64 form out of line, so that it does
+// not add to the register budget of the LDS path.
 template <class A>
 __device__ __noinline__ void deposit_q_global(const SinkGlobQ<A> &K, int M, const double *S0z,
                                               const double *S1z, const double *S0r,
@@ -519,8 +519,14 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
       K.n1 = n1;
 #pragma unroll
       for (int a = 0; a < 4; ++a) K.col[a] = col[a];
-      deposit_q_global<A>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, (D)ct, (D)st, (D)ctb,
-                          (D)stb, g, vthdt);
+      // FP32 form inline (a call would put the weight arrays in scratch
+      // memory), FP64 form out of line (inlining it costs occupancy)
+      if constexpr (sizeof(R) == 4)
+        deposit_q<D>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, (D)ct, (D)st, (D)ctb, (D)stb,
+                     g, vthdt);
+      else
+        deposit_q_global<A>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, (D)ct, (D)st, (D)ctb,
+                            (D)stb, g, vthdt);
     }
     G(P.cell)[p] = wrap_pow2(cz + dz, n1);
     G(P.fz)[p] = gz;
