@@ -28,7 +28,7 @@ __global__ void __launch_bounds__(256) k_q_fields_to_k(const RunQ<R> *__restrict
   const long long base = (long long)it.a * r.plane + (long long)it.b * r.n1;
   for (int n = threadIdx.x; n < r.n1; n += blockDim.x) lds[n] = r.F[base + n];
   __syncthreads();
-  lds_fft<C, 6>(lds, r.n1, r.log2n1, 1, r.tw, 1, false);
+  lds_fft16<C, 6>(lds, r.n1, r.log2n1, 1, r.tw, 1, false);
   double2 *out = r.Fk[parity] + base;
   for (int n = threadIdx.x; n < r.n1; n += blockDim.x) out[n] = to_d2(lds[n]);
 }
@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(256) k_q_ifft(const RunQ<R> *__restrict__ runs
   const double2 *X = r.Fk[parity] + base;
   for (int n = threadIdx.x; n < r.n1; n += blockDim.x) lds[n] = from_d2<C>(X[n]);
   __syncthreads();
-  lds_fft<C, 6>(lds, r.n1, r.log2n1, 1, r.tw, 1, true);
+  lds_fft16<C, 6>(lds, r.n1, r.log2n1, 1, r.tw, 1, true);
   const R s = R(1) / (R)r.n1;
   for (int n = threadIdx.x; n < r.n1; n += blockDim.x) r.F[base + n] = cscale(lds[n], s);
 }
@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(256) k_q_fft_j(const RunQ<R> *__restrict__ run
     Jclr[2 * n + 1] = 0;
   }
   __syncthreads();
-  lds_fft<C, 6>(lds, r.n1, r.log2n1, 1, r.tw, 1, false);
+  lds_fft16<C, 6>(lds, r.n1, r.log2n1, 1, r.tw, 1, false);
   C *out = r.Jk + base;
   const int sel = c == 0 ? 0 : 1;
   for (int k = threadIdx.x; k < r.n1; k += blockDim.x) {
@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(256) k_q_rho_fft(const RunQ<R> *__restrict__ r
   double2 *row = rho + (long long)it.a * r.plane + (long long)it.b * r.n1;
   for (int n = threadIdx.x; n < r.n1; n += blockDim.x) lds[n] = row[n];
   __syncthreads();
-  lds_fft<double2, 6>(lds, r.n1, r.log2n1, 1, r.tw64, 1, false);
+  lds_fft16<double2, 6>(lds, r.n1, r.log2n1, 1, r.tw64, 1, false);
   for (int n = threadIdx.x; n < r.n1; n += blockDim.x) row[n] = lds[n];
 }
 
