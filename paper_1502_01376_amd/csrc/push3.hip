@@ -41,17 +41,16 @@ __device__ __forceinline__ double rcp3(double x) { return 1.0 / x; }
 // Momentum-conserving quadratic gather of one staggered component: the
 // weights along each axis are those of the integer (h = 0) or half (h = 1)
 // node stencil; o_d[3] are the node offsets (already wrapped and scaled).
-template <class R>
-__device__ __forceinline__ R gather_comp(const R *__restrict__ F, const R w1[3], const int o1[3],
-                                         const R w2[3], const int o2[3], const R w3[3],
-                                         const int o3[3]) {
+template <class R, class PT>
+__device__ __forceinline__ R gather_comp(PT F, const R w1[3], const int o1[3], const R w2[3],
+                                         const int o2[3], const R w3[3], const int o3[3]) {
   R acc = 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     R s2 = 0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const R *row = F + o3[c] + o2[b];
+      const PT row = F + o3[c] + o2[b];
       const R s1 = w1[0] * row[o1[0]] + w1[1] * row[o1[1]] + w1[2] * row[o1[2]];
       s2 += w2[b] * s1;
     }
@@ -302,13 +301,28 @@ __device__ __forceinline__ void unpack3(int cell, int log2n1, int sh3, int n1, i
   i3 = cell >> sh3;
 }
 
-// Push one particle p: gather at global cell (g1, g2, g3), Boris, move,
-// deposit into K in the sink's frame (cell l[]), store.  Returns the new
-// packed cell (the old one if the particle was rejected).
-template <class R, class Sink>
+template <class T> using lptr3 = T __attribute__((address_space(3))) *;
+
+// Field sources of the gather: the whole grid in global memory, or the tile's
+// field box in LDS ([6][FD][FH][FW], origin one cell below the tile's particle
+// box, i.e. sink-frame cell - 1 along each axis).
+template <class R> struct GlobalF3 {
+  static constexpr bool local = false;
+};
+template <class R> struct LdsF3 {
+  static constexpr bool local = true;
+  lptr3<R> F;
+  int FW, FWH, plane;
+};
+
+// Push one particle p: gather at global cell (g1, g2, g3) (from the field box
+// when S is local), Boris, move, deposit into K in the sink's frame (cell
+// l[]), store.  Returns the new packed cell (the old one if the particle was
+// rejected).
+template <class R, class Src, class Sink>
 __device__ __forceinline__ int push_one3(const Run<R> &r, const Parts<R> &P, int p, int cell,
-                                         int g1, int g2, int g3, const int l[3], const Sink &K,
-                                         unsigned *err) {
+                                         int g1, int g2, int g3, const int l[3], const Src &S,
+                                         const Sink &K, unsigned *err) {
   const R f[3] = {G(P.f1)[p], G(P.f2)[p], G(P.f3)[p]};
   R u[3] = {G(P.u1)[p], G(P.u2)[p], G(P.u3)[p]};
   const R qw = G(P.qw)[p];
@@ -324,27 +338,40 @@ __device__ __forceinline__ int push_one3(const Run<R> &r, const Parts<R> &P, int
     half3<R>(f[d] - R(0.5), wh[d], r.interp != 0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const int ni = gc[d] + up - 1 + a, nh = gc[d] - 1 + a;
-      if (d == 0) {
-        oi[0][a] = wrap_pow2(ni, n1);
-        oh[0][a] = wrap_pow2(nh, n1);
-      } else if (d == 1) {
-        oi[1][a] = wrap_small(ni, n2) * n1;
-        oh[1][a] = wrap_small(nh, n2) * n1;
+      if constexpr (Src::local) {
+        // box-local nodes: sink-frame cell - 1, then the stencil
+        const int ni = l[d] - 1 + up - 1 + a, nh = l[d] - 1 - 1 + a;
+        const int sc = d == 0 ? 1 : (d == 1 ? S.FW : S.FWH);
+        oi[d][a] = ni * sc;
+        oh[d][a] = nh * sc;
       } else {
-        oi[2][a] = wrap_small(ni, n3) * n12;
-        oh[2][a] = wrap_small(nh, n3) * n12;
+        const int ni = gc[d] + up - 1 + a, nh = gc[d] - 1 + a;
+        if (d == 0) {
+          oi[0][a] = wrap_pow2(ni, n1);
+          oh[0][a] = wrap_pow2(nh, n1);
+        } else if (d == 1) {
+          oi[1][a] = wrap_small(ni, n2) * n1;
+          oh[1][a] = wrap_small(nh, n2) * n1;
+        } else {
+          oi[2][a] = wrap_small(ni, n3) * n12;
+          oh[2][a] = wrap_small(nh, n3) * n12;
+        }
       }
     }
   }
-  const R *F = r.F;
   R E[3], B[3];
-  E[0] = gather_comp<R>(F, wh[0], oh[0], wi[1], oi[1], wi[2], oi[2]);
-  E[1] = gather_comp<R>(F + cells, wi[0], oi[0], wh[1], oh[1], wi[2], oi[2]);
-  E[2] = gather_comp<R>(F + 2 * cells, wi[0], oi[0], wi[1], oi[1], wh[2], oh[2]);
-  B[0] = gather_comp<R>(F + 3 * cells, wi[0], oi[0], wh[1], oh[1], wh[2], oh[2]);
-  B[1] = gather_comp<R>(F + 4 * cells, wh[0], oh[0], wi[1], oi[1], wh[2], oh[2]);
-  B[2] = gather_comp<R>(F + 5 * cells, wh[0], oh[0], wh[1], oh[1], wi[2], oi[2]);
+  auto gather6 = [&](auto F, int stride) {
+    E[0] = gather_comp<R>(F, wh[0], oh[0], wi[1], oi[1], wi[2], oi[2]);
+    E[1] = gather_comp<R>(F + stride, wi[0], oi[0], wh[1], oh[1], wi[2], oi[2]);
+    E[2] = gather_comp<R>(F + 2 * stride, wi[0], oi[0], wi[1], oi[1], wh[2], oh[2]);
+    B[0] = gather_comp<R>(F + 3 * stride, wi[0], oi[0], wh[1], oh[1], wh[2], oh[2]);
+    B[1] = gather_comp<R>(F + 4 * stride, wh[0], oh[0], wi[1], oi[1], wh[2], oh[2]);
+    B[2] = gather_comp<R>(F + 5 * stride, wh[0], oh[0], wh[1], oh[1], wi[2], oi[2]);
+  };
+  if constexpr (Src::local)
+    gather6(S.F, S.plane);
+  else
+    gather6((const R *)r.F, cells);
   boris3<R>(r.qmhdt, E, B, u);
   R v[3];
   velocity3<R>(u, v);
@@ -433,14 +460,36 @@ k_push_deposit3(const Run<R> *__restrict__ runs, const Item *__restrict__ items,
       int i1, i2, i3;
       unpack3(cell, r.log2n1, r.sh3, n1, i1, i2, i3);
       const int l[3] = {i1, i2, i3};
-      track(push_one3<R>(r, P, p, cell, i1, i2, i3, l, K, err));
+      track(push_one3<R>(r, P, p, cell, i1, i2, i3, l, GlobalF3<R>{}, K, err));
     }
   } else {
     typename SK::T *lj = (typename SK::T *)smem_raw;
     const int vol = (int)jn;
+    // field box: cells lo-1 .. hi+2 per axis, after the current box when both fit
+    const int FW = hi[0] - lo[0] + 4, FH = hi[1] - lo[1] + 4, FD = hi[2] - lo[2] + 4;
+    const int fplane = FW * FH * FD;
+    const size_t jbytes = (need + 15) & ~(size_t)15;
+    const bool use_fl = jbytes + (size_t)6 * fplane * sizeof(R) <= (size_t)lds_bytes;
+    const lptr3<R> fl = (lptr3<R>)(smem_raw + jbytes);
     for (int q = threadIdx.x; q < 3 * vol; q += 256) lj[q] = 0;
+    if (use_fl) {
+      const gptr<const R> F = G((const R *)r.F);
+      const long long cells = r.cells;
+      const int o1 = ref[0] + lo[0] - 1, o2 = ref[1] + lo[1] - 1, o3 = ref[2] + lo[2] - 1;
+      for (int q = threadIdx.x; q < 6 * fplane; q += 256) {
+        const int comp = q / fplane, e = q - comp * fplane;
+        const int k = e / (FW * FH), rem = e - k * FW * FH;
+        const int b = rem / FW, a = rem - b * FW;
+        int g3 = (o3 + k) % n3;
+        g3 += g3 < 0 ? n3 : 0;
+        int g2 = (o2 + b) % n2;
+        g2 += g2 < 0 ? n2 : 0;
+        fl[q] = F[comp * cells + ((long long)g3 * n2 + g2) * n1 + wrap_pow2(o1 + a, n1)];
+      }
+    }
     __syncthreads();
     const typename SK::L K{lj, W, W * H, vol};
+    const LdsF3<R> SL{fl, FW, FW * FH, fplane};
     for (int p = start + threadIdx.x; p < end; p += 256) {
       const int cell = G(P.cell)[p];
       int i1, i2, i3;
@@ -448,7 +497,10 @@ k_push_deposit3(const Run<R> *__restrict__ runs, const Item *__restrict__ items,
       const int l[3] = {wrap_delta_pow2_3(i1 - ref[0], n1) - lo[0] + 2,
                         wrap_delta_3(i2 - ref[1], n2) - lo[1] + 2,
                         wrap_delta_3(i3 - ref[2], n3) - lo[2] + 2};
-      track(push_one3<R>(r, P, p, cell, i1, i2, i3, l, K, err));
+      if (use_fl)
+        track(push_one3<R>(r, P, p, cell, i1, i2, i3, l, SL, K, err));
+      else
+        track(push_one3<R>(r, P, p, cell, i1, i2, i3, l, GlobalF3<R>{}, K, err));
     }
     __syncthreads();
     const auto J = G((typename SK::T *)r.J[parity]);
