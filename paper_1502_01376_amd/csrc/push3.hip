@@ -305,7 +305,7 @@ template <class T> using lptr3 = T __attribute__((address_space(3))) *;
 
 // Field sources of the gather: the whole grid in global memory, or the tile's
 // field box in LDS ([6][FD][FH][FW], origin one cell below the tile's particle
-// box, i.e. sink-frame cell - 1 along each axis).
+// box, i.e. sink-frame cell - 1 along each axis; FP32 form only).
 template <class R> struct GlobalF3 {
   static constexpr bool local = false;
 };
@@ -469,7 +469,8 @@ k_push_deposit3(const Run<R> *__restrict__ runs, const Item *__restrict__ items,
     const int FW = hi[0] - lo[0] + 4, FH = hi[1] - lo[1] + 4, FD = hi[2] - lo[2] + 4;
     const int fplane = FW * FH * FD;
     const size_t jbytes = (need + 15) & ~(size_t)15;
-    const bool use_fl = jbytes + (size_t)6 * fplane * sizeof(R) <= (size_t)lds_bytes;
+    const bool use_fl =
+        sizeof(R) == 4 && jbytes + (size_t)6 * fplane * sizeof(R) <= (size_t)lds_bytes;
     const lptr3<R> fl = (lptr3<R>)(smem_raw + jbytes);
     for (int q = threadIdx.x; q < 3 * vol; q += 256) lj[q] = 0;
     if (use_fl) {

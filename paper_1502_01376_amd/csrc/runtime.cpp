@@ -1368,8 +1368,9 @@ class Sim : public SimBase {
     tile1_ = t1;
     tile2_ = t2;
     // per node: 3 accumulators + 6 staged field values (a 3D tile whose two
-    // boxes do not fit gathers its fields through the cache)
-    const int node_bytes = FIXED ? 48 : 72;
+    // boxes do not fit gathers its fields through the cache; the 3D FP64 form
+    // always does, it was measured faster so)
+    const int node_bytes = FIXED ? 48 : (dim_ == 3 ? 24 : 72);
     push_lds_ = std::min(PUSH_LDS_MAX, std::max(PUSH_LDS_MIN, ((maxbox * node_bytes + 1023) / 1024) * 1024));
     if (d_tiles_) release(d_tiles_);
     d_tiles_ = nullptr;
