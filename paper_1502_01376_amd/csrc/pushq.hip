@@ -137,23 +137,25 @@ __device__ __forceinline__ void place4(const R s[3], int off, R out[4]) {
 // columns oz[3] (wrapped), rows rr[3] (a ghost row already mirrored; ghost0:
 // row 0 of the stencil is the ghost, whose sign depends on the mode parity
 // and on whether the component is a z component or a transverse one).
-template <class R>
-__device__ __forceinline__ R gather_q(const typename Cplx<R>::T *__restrict__ Fc, long long mstride,
-                                      int M, const R wz[3], const int oz[3], const R wr[3],
-                                      const int rr[3], bool ghost0, bool vec, const R *Pr,
-                                      const R *Pi, int n1) {
+// Fc points at mode 0 of the component, in global memory (row stride n1,
+// mode stride 6 planes) or in a wave's LDS copy of the fields around its
+// particles (row stride the box width, columns relative to the box).
+template <class R, class PC, class I>
+__device__ __forceinline__ R gather_q(PC Fc, I mstride, int M, const R wz[3], const int oz[3],
+                                      const R wr[3], const int rr[3], bool ghost0, bool vec,
+                                      const R *Pr, const R *Pi, I rowstride) {
   using C = typename Cplx<R>::T;
   R acc = 0;
   for (int m = 0; m < M; ++m) {
-    const C *F = Fc + m * mstride;
+    const PC F = Fc + m * mstride;
     R vx = 0, vy = 0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const C *row = F + (long long)rr[b] * n1;
+      const PC row = F + rr[b] * rowstride;
       R sx = 0, sy = 0;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const C v = row[oz[a]];
+        const auto v = row[oz[a]];
         sx += wz[a] * v.x;
         sy += wz[a] * v.y;
       }
@@ -186,6 +188,10 @@ __device__ __forceinline__ int wmax(int v) {
   return v;
 }
 template <class T> using lptr = T __attribute__((address_space(3))) *;
+// A complex value as a clang vector (copyable to and from LDS).
+template <class R> struct LdsC;
+template <> struct LdsC<float> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct LdsC<double> { typedef double T __attribute__((ext_vector_type(2))); };
 
 // One FP64 contribution in the accumulator's type: FP32 form the nearest 64-bit
 // integer (|v| < 2^44: charges are scaled to at most 2^40 and every weight
@@ -355,7 +361,9 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
   const RunQ<R> &r = runs[it.run];
   const int p0 = it.a + threadIdx.x;
   const bool active = p0 < r.np;
-  const int p = active ? p0 : it.a;  // inactive lanes shadow a valid particle
+  // inactive lanes shadow the run's last particle, which lies in their wave's
+  // box whenever the wave has an active lane
+  const int p = active ? p0 : r.np - 1;
   const PartsQ<R> P = r.pt;
   const int n1 = r.n1, M = r.M;
   const long long plane = r.plane;
@@ -383,8 +391,35 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
   const bool use_lds = any && W <= n1 && (long long)W * H * NS <= WAVE_CAP;
   const lptr<A> box = (lptr<A>)smem_raw + (threadIdx.x >> 6) * WAVE_CAP;
   const int lane = threadIdx.x & 63;
-  if (use_lds)
-    for (int e = lane; e < W * H * NS; e += 64) box[e] = 0;
+  const C *F = r.F;
+  // FP32 form: before the push the wave's LDS region holds a copy of the
+  // fields its particles gather (all modes and components over columns
+  // relz - 1 .. relz + 2 and rows rlo .. rhi - 1), laid out
+  // [mode][component][row][column]
+  constexpr bool STAGE = sizeof(R) == 4;
+  const int fzlo = zlo + 1, Wf = W - 2, Hf = H - 1;
+  const bool use_fl = STAGE && any && Wf <= 64 &&
+                      (long long)6 * M * Wf * Hf * (long long)sizeof(C) <=
+                          (long long)WAVE_CAP * (long long)sizeof(A);
+  using V2 = typename LdsC<R>::T;
+  const lptr<V2> fbox =
+      (lptr<V2>)smem_raw + (threadIdx.x >> 6) * (int)(WAVE_CAP * sizeof(A) / sizeof(V2));
+  if constexpr (STAGE) {
+    if (use_fl) {
+      // lane -> (row in a group of rpi rows, column)
+      const int rpi = 64 / Wf, sub = lane / Wf, cc = lane - sub * Wf;
+      const int col = wrap_pow2(cz0 + fzlo + cc, n1);
+      if (sub < rpi)
+        for (int cm = 0; cm < 6 * M; ++cm)  // cm = 6 m + component
+          for (int r0 = sub; r0 < Hf; r0 += rpi) {
+            const C v = F[(long long)cm * plane + (long long)(rlo + r0) * n1 + col];
+            fbox[(cm * Hf + r0) * Wf + cc] = V2{v.x, v.y};
+          }
+    }
+  } else {
+    if (use_lds)
+      for (int e = lane; e < W * H * NS; e += 64) box[e] = 0;
+  }
   __syncthreads();
   // phases P_m = (ct - i st)^m
   R Pr[MAXM], Pi[MAXM];
@@ -414,15 +449,41 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
     rrh[b] = jh < 0 ? -jh - 1 : jh;
   }
   const bool gi = mri == 0, gh = mrh == 0;  // ghost row in the stencil
-  const long long ms = 6 * plane;
-  const C *F = r.F;
   R Ec[3], Bc[3];
-  Ec[0] = gather_q<R>(F, ms, M, wzh, ozh, wri, rri, gi, false, Pr, Pi, n1);
-  Ec[1] = gather_q<R>(F + plane, ms, M, wzi, ozi, wrh, rrh, gh, true, Pr, Pi, n1);
-  Ec[2] = gather_q<R>(F + 2 * plane, ms, M, wzi, ozi, wri, rri, gi, true, Pr, Pi, n1);
-  Bc[0] = gather_q<R>(F + 3 * plane, ms, M, wzi, ozi, wrh, rrh, gh, false, Pr, Pi, n1);
-  Bc[1] = gather_q<R>(F + 4 * plane, ms, M, wzh, ozh, wri, rri, gi, true, Pr, Pi, n1);
-  Bc[2] = gather_q<R>(F + 5 * plane, ms, M, wzh, ozh, wrh, rrh, gh, true, Pr, Pi, n1);
+  if (use_fl) {
+    // the same stencils in box coordinates
+    int lzi[3], lzh[3], lri[3], lrh[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lzi[a] = relz - fzlo + upz - 1 + a;
+      lzh[a] = relz - fzlo - 1 + a;
+      lri[a] = rri[a] - rlo;
+      lrh[a] = rrh[a] - rlo;
+    }
+    const int fp = Wf * Hf, fm = 6 * fp;
+    const lptr<V2> fb = fbox;
+    Ec[0] = gather_q<R>(fb, fm, M, wzh, lzh, wri, lri, gi, false, Pr, Pi, Wf);
+    Ec[1] = gather_q<R>(fb + fp, fm, M, wzi, lzi, wrh, lrh, gh, true, Pr, Pi, Wf);
+    Ec[2] = gather_q<R>(fb + 2 * fp, fm, M, wzi, lzi, wri, lri, gi, true, Pr, Pi, Wf);
+    Bc[0] = gather_q<R>(fb + 3 * fp, fm, M, wzi, lzi, wrh, lrh, gh, false, Pr, Pi, Wf);
+    Bc[1] = gather_q<R>(fb + 4 * fp, fm, M, wzh, lzh, wri, lri, gi, true, Pr, Pi, Wf);
+    Bc[2] = gather_q<R>(fb + 5 * fp, fm, M, wzh, lzh, wrh, lrh, gh, true, Pr, Pi, Wf);
+  } else {
+    const long long ms = 6 * plane, rs = n1;
+    Ec[0] = gather_q<R>(F, ms, M, wzh, ozh, wri, rri, gi, false, Pr, Pi, rs);
+    Ec[1] = gather_q<R>(F + plane, ms, M, wzi, ozi, wrh, rrh, gh, true, Pr, Pi, rs);
+    Ec[2] = gather_q<R>(F + 2 * plane, ms, M, wzi, ozi, wri, rri, gi, true, Pr, Pi, rs);
+    Bc[0] = gather_q<R>(F + 3 * plane, ms, M, wzi, ozi, wrh, rrh, gh, false, Pr, Pi, rs);
+    Bc[1] = gather_q<R>(F + 4 * plane, ms, M, wzh, ozh, wri, rri, gi, true, Pr, Pi, rs);
+    Bc[2] = gather_q<R>(F + 5 * plane, ms, M, wzh, ozh, wrh, rrh, gh, true, Pr, Pi, rs);
+  }
+  if constexpr (STAGE) {
+    // the region becomes the wave's current box
+    __syncthreads();
+    if (use_lds)
+      for (int e = lane; e < W * H * NS; e += 64) box[e] = 0;
+    __syncthreads();
+  }
   const R E[3] = {Ec[0], Ec[1] * ct - Ec[2] * st, Ec[1] * st + Ec[2] * ct};
   const R B[3] = {Bc[0], Bc[1] * ct - Bc[2] * st, Bc[1] * st + Bc[2] * ct};
   borisq<R>(r.qmhdt, E, B, u);
