@@ -133,51 +133,51 @@ __device__ __forceinline__ void place4(const R s[3], int off, R out[4]) {
   out[3] = off ? s[2] : R(0);
 }
 
-// Gather of one staggered component over all modes: weights wz/wr, node
-// columns oz[3] (wrapped), rows rr[3] (a ghost row already mirrored; ghost0:
-// row 0 of the stencil is the ghost, whose sign depends on the mode parity
-// and on whether the component is a z component or a transverse one).
-// Fc points at mode 0 of the component, in global memory (row stride n1,
-// mode stride 6 planes) or in a wave's LDS copy of the fields around its
-// particles (row stride the box width, columns relative to the box).
+// One mode of one staggered component at the particle: the complex
+// interpolated value (vx, vy) from weights wz/wr, node columns oz[3] and rows
+// rr[3] (a ghost row already mirrored; ghost0: row 0 of the stencil is the
+// ghost, whose sign depends on the mode parity and on whether the component is
+// a z component or a transverse one).  F points at the mode's plane of the
+// component, in global memory (row stride n1) or in a wave's LDS copy of the
+// fields around its particles (row stride the box width, columns relative to
+// the box).
 template <class R, class PC, class I>
-__device__ __forceinline__ R gather_q(PC Fc, I mstride, int M, const R wz[3], const int oz[3],
-                                      const R wr[3], const int rr[3], bool ghost0, bool vec,
-                                      const R *Pr, const R *Pi, I rowstride) {
-  using C = typename Cplx<R>::T;
-  R acc = 0;
-  for (int m = 0; m < M; ++m) {
-    const PC F = Fc + m * mstride;
-    R vx = 0, vy = 0;
+__device__ __forceinline__ void gather_q(PC F, const R wz[3], const int oz[3], const R wr[3],
+                                         const int rr[3], bool ghost0, bool odd, bool vec,
+                                         I rowstride, R &vx, R &vy) {
+  vx = 0;
+  vy = 0;
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const PC row = F + rr[b] * rowstride;
-      R sx = 0, sy = 0;
+  for (int b = 0; b < 3; ++b) {
+    const PC row = F + rr[b] * rowstride;
+    R sx = 0, sy = 0;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const auto v = row[oz[a]];
-        sx += wz[a] * v.x;
-        sy += wz[a] * v.y;
-      }
-      R w = wr[b];
-      if (b == 0 && ghost0) {
-        const bool odd = m & 1;
-        if (odd != vec) w = -w;  // (-1)^m for z components, -(-1)^m for r, th
-      }
-      vx += w * sx;
-      vy += w * sy;
+    for (int a = 0; a < 3; ++a) {
+      const auto v = row[oz[a]];
+      sx += wz[a] * v.x;
+      sy += wz[a] * v.y;
     }
-    acc += vx * Pr[m] + vy * Pi[m];  // Re(v e^{i m th}) with P = e^{-i m th}
+    R w = wr[b];
+    if (b == 0 && ghost0 && odd != vec) w = -w;  // (-1)^m for z components, -(-1)^m for r, th
+    vx += w * sx;
+    vy += w * sy;
   }
-  return acc;
 }
 
-
-constexpr int MAXM = 8;
-// LDS of one push workgroup: a private current box per wave of WAVE_CAP
+// LDS of one push workgroup: a private region per wave of WAVE_CAP 64-bit
 // accumulators (the wave's particles are consecutive, hence close together).
-constexpr int QLDS_BYTES = 64512;
-constexpr int WAVE_CAP = QLDS_BYTES / 4 / 8;
+// FP32 form: three workgroups per compute unit (3 waves per SIMD, the register
+// budget 168; the compiler spills a little, which costs less than the lost
+// occupancy); FP64 form: two.
+template <class R> struct QPush;
+template <> struct QPush<float> {
+  static constexpr int LDS = 53248;
+  static constexpr int WAVES_PER_SIMD = 3;
+};
+template <> struct QPush<double> {
+  static constexpr int LDS = 64512;
+  static constexpr int WAVES_PER_SIMD = 2;
+};
 
 __device__ __forceinline__ int wmin(int v) {
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
@@ -206,7 +206,9 @@ template <> __device__ __forceinline__ double to_acc<double>(double v) { return 
 template <class A>
 struct SinkLdsQ {
   lptr<A> box;
-  int H, W, rlo, bzrel, per;
+  int H, W, rlo, z0, per;  // z0: box column of global column 0 of the window frame
+  int bzrel;               // box column of the window's first column
+  __device__ __forceinline__ void window(int bz) { bzrel = bz + z0; }
   __device__ __forceinline__ void operator()(int c, int m, int part, int row, int a, double v) const {
     const int slot = c * per + (m == 0 ? 0 : 2 * m - 1 + part);
     const A q = to_acc<A>(v);
@@ -220,6 +222,10 @@ struct SinkGlobQ {
   A *J;
   long long plane;
   int n1, col[4];
+  __device__ __forceinline__ void window(int bz) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) col[a] = wrap_pow2(bz + a, n1);
+  }
   __device__ __forceinline__ void operator()(int c, int m, int part, int row, int a, double v) const {
     const A q = to_acc<A>(v);
     if (q != A(0))
@@ -330,16 +336,62 @@ __device__ __forceinline__ void deposit_q(const Sink &put, int M, const R S0z[4]
   }
 }
 
-// The rare global-atomic path of the FP64 form out of line, so that it does
-// not add to the register budget of the LDS path.
+// Deposit of one move from the particle's old and new positions: cell cz
+// with z offset fz, moved by dz cells to offset gz; radial nodes mri, mrb with
+// offsets dri, drb; old and new directions; scaled charge g; v_th dt.  Builds
+// the 4-node windows along z and r holding both stencils, their running sums
+// and means, and deposits through K (whose column origin follows the window).
+template <class Sink>
+__device__ __forceinline__ void deposit_move(Sink K, int M, int cz, double fz, int dz, double gz,
+                                             int mri, double dri, int mrb, double drb, double ct,
+                                             double st, double ctb, double stb, double g,
+                                             double vthdt) {
+  using D = double;
+  D S0z[4], S1z[4], S0r[4], S1r[4];
+  int bz, br;
+  {
+    D sa[3], sb[3];
+    const int na = zshape<D>(cz, fz, sa);
+    const int nb = zshape<D>(cz + dz, gz, sb);
+    bz = min(na, nb) - 1;
+    place4<D>(sa, na - 1 - bz, S0z);
+    place4<D>(sb, nb - 1 - bz, S1z);
+    splineq<D>(dri, sa);
+    splineq<D>(drb, sb);
+    br = min(mri, mrb) - 1;
+    place4<D>(sa, mri - 1 - br, S0r);
+    place4<D>(sb, mrb - 1 - br, S1r);
+  }
+  D Cz[4], Tz[4], Cr[4], Tr[4];
+  {
+    D az = 0, ar = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      az = az + (S1z[k] - S0z[k]);
+      ar = ar + (S1r[k] - S0r[k]);
+      Cz[k] = az;
+      Cr[k] = ar;
+      Tz[k] = 0.5 * (S0z[k] + S1z[k]);
+      Tr[k] = 0.5 * (S0r[k] + S1r[k]);
+    }
+  }
+  K.window(bz);
+  deposit_q<D>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, ct, st, ctb, stb, g, vthdt);
+}
+
+// The rare global-atomic path out of line, with plain arguments (no array
+// whose address is taken), so that it adds neither registers nor scratch
+// memory to the LDS path.
 template <class A>
-__device__ __noinline__ void deposit_q_global(const SinkGlobQ<A> &K, int M, const double *S0z,
-                                              const double *S1z, const double *S0r,
-                                              const double *S1r, const double *Cz,
-                                              const double *Tz, const double *Cr, const double *Tr,
-                                              int br, double cta, double sta, double ctb,
-                                              double stb, double g, double vthdt) {
-  deposit_q<double>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, cta, sta, ctb, stb, g, vthdt);
+__device__ __noinline__ void deposit_move_global(A *J, long long plane, int n1, int M, int cz,
+                                                 double fz, int dz, double gz, int mri, double dri,
+                                                 int mrb, double drb, double ct, double st,
+                                                 double ctb, double stb, double g, double vthdt) {
+  SinkGlobQ<A> K;
+  K.J = J;
+  K.plane = plane;
+  K.n1 = n1;
+  deposit_move(K, M, cz, fz, dz, gz, mri, dri, mrb, drb, ct, st, ctb, stb, g, vthdt);
 }
 
 }  // namespace
@@ -351,12 +403,13 @@ __device__ __noinline__ void deposit_q_global(const SinkGlobQ<A> &K, int M, cons
 // deposits into its LDS box and adds the box to the global accumulators
 // afterwards; otherwise it deposits with global atomics.
 template <class R>
-__global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restrict__ runs,
+__global__ void __launch_bounds__(256, QPush<R>::WAVES_PER_SIMD) k_q_push_deposit(const RunQ<R> *__restrict__ runs,
                                                         const Item *__restrict__ items, int parity,
                                                         unsigned *err) {
   using C = typename Cplx<R>::T;
   using A = typename AccQ<R>::T;
   extern __shared__ unsigned char smem_raw[];
+  constexpr int WAVE_CAP = QPush<R>::LDS / 4 / 8;
   const Item it = items[blockIdx.x];
   const RunQ<R> &r = runs[it.run];
   const int p0 = it.a + threadIdx.x;
@@ -421,14 +474,6 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
       for (int e = lane; e < W * H * NS; e += 64) box[e] = 0;
   }
   __syncthreads();
-  // phases P_m = (ct - i st)^m
-  R Pr[MAXM], Pi[MAXM];
-  Pr[0] = 1;
-  Pi[0] = 0;
-  for (int m = 1; m < M; ++m) {
-    Pr[m] = Pr[m - 1] * ct + Pi[m - 1] * st;
-    Pi[m] = Pi[m - 1] * ct - Pr[m - 1] * st;
-  }
   // ---- gather: integer (i) and half (h) stencils along z and r
   R wzi[3], wzh[3], wri[3], wrh[3];
   int ozi[3], ozh[3], rri[3], rrh[3];
@@ -449,33 +494,51 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
     rrh[b] = jh < 0 ? -jh - 1 : jh;
   }
   const bool gi = mri == 0, gh = mrh == 0;  // ghost row in the stencil
-  R Ec[3], Bc[3];
-  if (use_fl) {
-    // the same stencils in box coordinates
-    int lzi[3], lzh[3], lri[3], lrh[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      lzi[a] = relz - fzlo + upz - 1 + a;
-      lzh[a] = relz - fzlo - 1 + a;
-      lri[a] = rri[a] - rlo;
-      lrh[a] = rrh[a] - rlo;
+  // sum over the modes of Re(F_m e^{i m th}), with P_m = (ct - i st)^m by
+  // recurrence
+  R Ec[3] = {0, 0, 0}, Bc[3] = {0, 0, 0};
+  R Pr = 1, Pi = 0;
+  for (int m = 0; m < M; ++m) {
+    if (m > 0) {
+      const R t = Pr * ct + Pi * st;
+      Pi = Pi * ct - Pr * st;
+      Pr = t;
     }
-    const int fp = Wf * Hf, fm = 6 * fp;
-    const lptr<V2> fb = fbox;
-    Ec[0] = gather_q<R>(fb, fm, M, wzh, lzh, wri, lri, gi, false, Pr, Pi, Wf);
-    Ec[1] = gather_q<R>(fb + fp, fm, M, wzi, lzi, wrh, lrh, gh, true, Pr, Pi, Wf);
-    Ec[2] = gather_q<R>(fb + 2 * fp, fm, M, wzi, lzi, wri, lri, gi, true, Pr, Pi, Wf);
-    Bc[0] = gather_q<R>(fb + 3 * fp, fm, M, wzi, lzi, wrh, lrh, gh, false, Pr, Pi, Wf);
-    Bc[1] = gather_q<R>(fb + 4 * fp, fm, M, wzh, lzh, wri, lri, gi, true, Pr, Pi, Wf);
-    Bc[2] = gather_q<R>(fb + 5 * fp, fm, M, wzh, lzh, wrh, lrh, gh, true, Pr, Pi, Wf);
-  } else {
-    const long long ms = 6 * plane, rs = n1;
-    Ec[0] = gather_q<R>(F, ms, M, wzh, ozh, wri, rri, gi, false, Pr, Pi, rs);
-    Ec[1] = gather_q<R>(F + plane, ms, M, wzi, ozi, wrh, rrh, gh, true, Pr, Pi, rs);
-    Ec[2] = gather_q<R>(F + 2 * plane, ms, M, wzi, ozi, wri, rri, gi, true, Pr, Pi, rs);
-    Bc[0] = gather_q<R>(F + 3 * plane, ms, M, wzi, ozi, wrh, rrh, gh, false, Pr, Pi, rs);
-    Bc[1] = gather_q<R>(F + 4 * plane, ms, M, wzh, ozh, wri, rri, gi, true, Pr, Pi, rs);
-    Bc[2] = gather_q<R>(F + 5 * plane, ms, M, wzh, ozh, wrh, rrh, gh, true, Pr, Pi, rs);
+    const bool odd = m & 1;
+    R vx[6], vy[6];
+    if (use_fl) {
+      // the same stencils in box coordinates
+      int lzi[3], lzh[3], lri[3], lrh[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lzi[a] = relz - fzlo + upz - 1 + a;
+        lzh[a] = relz - fzlo - 1 + a;
+        lri[a] = rri[a] - rlo;
+        lrh[a] = rrh[a] - rlo;
+      }
+      const int fp = Wf * Hf;
+      const lptr<V2> fb = fbox + 6 * m * fp;
+      gather_q<R>(fb, wzh, lzh, wri, lri, gi, odd, false, Wf, vx[0], vy[0]);
+      gather_q<R>(fb + fp, wzi, lzi, wrh, lrh, gh, odd, true, Wf, vx[1], vy[1]);
+      gather_q<R>(fb + 2 * fp, wzi, lzi, wri, lri, gi, odd, true, Wf, vx[2], vy[2]);
+      gather_q<R>(fb + 3 * fp, wzi, lzi, wrh, lrh, gh, odd, false, Wf, vx[3], vy[3]);
+      gather_q<R>(fb + 4 * fp, wzh, lzh, wri, lri, gi, odd, true, Wf, vx[4], vy[4]);
+      gather_q<R>(fb + 5 * fp, wzh, lzh, wrh, lrh, gh, odd, true, Wf, vx[5], vy[5]);
+    } else {
+      const long long rs = n1;
+      const C *Fm = F + 6 * m * plane;
+      gather_q<R>(Fm, wzh, ozh, wri, rri, gi, odd, false, rs, vx[0], vy[0]);
+      gather_q<R>(Fm + plane, wzi, ozi, wrh, rrh, gh, odd, true, rs, vx[1], vy[1]);
+      gather_q<R>(Fm + 2 * plane, wzi, ozi, wri, rri, gi, odd, true, rs, vx[2], vy[2]);
+      gather_q<R>(Fm + 3 * plane, wzi, ozi, wrh, rrh, gh, odd, false, rs, vx[3], vy[3]);
+      gather_q<R>(Fm + 4 * plane, wzh, ozh, wri, rri, gi, odd, true, rs, vx[4], vy[4]);
+      gather_q<R>(Fm + 5 * plane, wzh, ozh, wrh, rrh, gh, odd, true, rs, vx[5], vy[5]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Ec[c] += vx[c] * Pr + vy[c] * Pi;  // Re(v e^{i m th}) with P = e^{-i m th}
+      Bc[c] += vx[c + 3] * Pr + vy[c + 3] * Pi;
+    }
   }
   if constexpr (STAGE) {
     // the region becomes the wave's current box
@@ -528,67 +591,7 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
     }
   }
   if (ok) {
-    // ---- deposit (FP64): 4-node windows along z and r holding both stencils
-    using D = double;
-    D S0z[4], S1z[4], S0r[4], S1r[4];
-    int bz, br;
-    {
-      D sa[3], sb[3];
-      const int na = zshape<D>(cz, (D)fz, sa);
-      const int nb = zshape<D>(cz + dz, (D)gz, sb);
-      bz = min(na, nb) - 1;
-      place4<D>(sa, na - 1 - bz, S0z);
-      place4<D>(sb, nb - 1 - bz, S1z);
-      const int ra = mri, rb = mrb;
-      splineq<D>((D)dri, sa);
-      splineq<D>((D)drb, sb);
-      br = min(ra, rb) - 1;
-      place4<D>(sa, ra - 1 - br, S0r);
-      place4<D>(sb, rb - 1 - br, S1r);
-    }
-    D Cz[4], Tz[4], Cr[4], Tr[4];
-    {
-      D az = 0, ar = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        az = az + (S1z[k] - S0z[k]);
-        ar = ar + (S1r[k] - S0r[k]);
-        Cz[k] = az;
-        Cr[k] = ar;
-        Tz[k] = 0.5 * (S0z[k] + S1z[k]);
-        Tr[k] = 0.5 * (S0r[k] + S1r[k]);
-      }
-    }
-    const int bzrel = bz - cz + relz - zlo;  // window column 0 in the box
-    int col[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) col[a] = wrap_pow2(bz + a, n1);
-    // azimuthal velocity at the mid point times dt: the move (mx, my) dr
-    // projected on the azimuthal direction of the mid point
-    const D xmid = D(ix) + (D)fx + 0.5 * (D)mx, ymid = D(iy) + (D)fy + 0.5 * (D)my;
-    const D rmid = sqrt(xmid * xmid + ymid * ymid);
-    const D vthdt = rmid > 0.0 ? (xmid * (D)my - ymid * (D)mx) / rmid * (D)r.dr : 0.0;
-    const D g = (D)qw * (D)r.wscale;
-    if (use_lds) {
-      SinkLdsQ<A> K{(lptr<A>)smem_raw + (threadIdx.x >> 6) * WAVE_CAP, H, W, rlo, bzrel, 2 * M - 1};
-      deposit_q<D>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, (D)ct, (D)st, (D)ctb, (D)stb, g,
-                   vthdt);
-    } else {
-      SinkGlobQ<A> K;
-      K.J = r.J[parity];
-      K.plane = plane;
-      K.n1 = n1;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) K.col[a] = col[a];
-      // FP32 form inline (a call would put the weight arrays in scratch
-      // memory), FP64 form out of line (inlining it costs occupancy)
-      if constexpr (sizeof(R) == 4)
-        deposit_q<D>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, (D)ct, (D)st, (D)ctb, (D)stb,
-                     g, vthdt);
-      else
-        deposit_q_global<A>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, (D)ct, (D)st, (D)ctb,
-                            (D)stb, g, vthdt);
-    }
+    // the new state first (fewer values live across the deposit)
     G(P.cell)[p] = wrap_pow2(cz + dz, n1);
     G(P.fz)[p] = gz;
     G(P.ix)[p] = ix + dx;
@@ -598,6 +601,22 @@ __global__ void __launch_bounds__(256) k_q_push_deposit(const RunQ<R> *__restric
     G(P.uz)[p] = u[0];
     G(P.ux)[p] = u[1];
     G(P.uy)[p] = u[2];
+    // ---- deposit (FP64)
+    using D = double;
+    // azimuthal velocity at the mid point times dt: the move (mx, my) dr
+    // projected on the azimuthal direction of the mid point
+    const D xmid = D(ix) + (D)fx + 0.5 * (D)mx, ymid = D(iy) + (D)fy + 0.5 * (D)my;
+    const D rmid = sqrt(xmid * xmid + ymid * ymid);
+    const D vthdt = rmid > 0.0 ? (xmid * (D)my - ymid * (D)mx) / rmid * (D)r.dr : 0.0;
+    const D g = (D)qw * (D)r.wscale;
+    if (use_lds) {
+      SinkLdsQ<A> K{box, H, W, rlo, relz - cz - zlo, 2 * M - 1, 0};
+      deposit_move(K, M, cz, (D)fz, dz, (D)gz, mri, (D)dri, mrb, (D)drb, (D)ct, (D)st, (D)ctb,
+                   (D)stb, g, vthdt);
+    } else {
+      deposit_move_global<A>(r.J[parity], plane, n1, M, cz, (D)fz, dz, (D)gz, mri, (D)dri, mrb,
+                             (D)drb, (D)ct, (D)st, (D)ctb, (D)stb, g, vthdt);
+    }
   }
   __syncthreads();
   if (use_lds) {
@@ -690,7 +709,7 @@ template <class R>
 void LaunchQ<R>::push_deposit(const RunQ<R> *runs, const Item *items, int nitems, int parity,
                               unsigned *err, hipStream_t s) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_q_push_deposit<R>, dim3(nitems), dim3(256), (size_t)QLDS_BYTES, s, runs,
+  hipLaunchKernelGGL(k_q_push_deposit<R>, dim3(nitems), dim3(256), (size_t)QPush<R>::LDS, s, runs,
                      items, parity, err);
 }
 template <class R>
