@@ -395,6 +395,13 @@ constexpr int PUSH_THREADS = 256;
 constexpr int PUSH_BATCH = 4;  // particles loaded per thread before pushing
 constexpr int PUSH_LDS_MIN = 16384;
 constexpr int PUSH_LDS_MAX = 64512;  // with the static LDS, under 64 KiB
+// The 3D push of the FP32 form runs 3 waves per SIMD (register budget 168,
+// three workgroups per compute unit), so its LDS budget is a third of the
+// compute unit's 160 KiB less the static LDS; the FP64 form runs 2 (budget
+// 256 registers: left alone the compiler takes 259 and gets 1 wave).
+constexpr int PUSH3_LDS_MAX_FP32 = 53248;
+template <class R> struct Push3Occupancy { static constexpr int WAVES_PER_SIMD = 2; };
+template <> struct Push3Occupancy<float> { static constexpr int WAVES_PER_SIMD = 3; };
 
 // ---------------------------------------------------------------- launches
 // Host-side launch wrappers (kernels.hip), one instantiation per precision.

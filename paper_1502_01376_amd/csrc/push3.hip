@@ -404,7 +404,7 @@ __device__ __forceinline__ int push_one3(const Run<R> &r, const Parts<R> &P, int
 }
 
 template <class R>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, Push3Occupancy<R>::WAVES_PER_SIMD)
 k_push_deposit3(const Run<R> *__restrict__ runs, const Item *__restrict__ items, int parity, int pp,
                 int lds_bytes, unsigned *err, unsigned *stats) {
   using SK = Sinks3<R>;

@@ -1371,7 +1371,8 @@ class Sim : public SimBase {
     // boxes do not fit gathers its fields through the cache; the 3D FP64 form
     // always does, it was measured faster so)
     const int node_bytes = FIXED ? 48 : (dim_ == 3 ? 24 : 72);
-    push_lds_ = std::min(PUSH_LDS_MAX, std::max(PUSH_LDS_MIN, ((maxbox * node_bytes + 1023) / 1024) * 1024));
+    const int lds_max = (FIXED && dim_ == 3) ? PUSH3_LDS_MAX_FP32 : PUSH_LDS_MAX;
+    push_lds_ = std::min(lds_max, std::max(PUSH_LDS_MIN, ((maxbox * node_bytes + 1023) / 1024) * 1024));
     if (d_tiles_) release(d_tiles_);
     d_tiles_ = nullptr;
     n_tiles_ = 0;
