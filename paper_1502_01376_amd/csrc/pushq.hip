@@ -28,10 +28,10 @@
 // One thread per particle; each wave accumulates into an LDS box (global
 // atomics if its particles spread too far), then adds the box to the global
 // accumulators.  The deposit's arithmetic (shapes, phases and fluxes of the
-// stored positions, their radius and direction in R) is FP64 in both forms; the FP32 form rounds each contribution once to
-// a 64-bit integer on a fine scale (2^40 per unit charge), so the sums do not
-// depend on the order and continuity holds to about 2^-41 of a particle's
-// charge per node and step.  (With FP32 weights and a 2^28 scale, long
+// stored positions, their radius and direction in R) is FP64 in both forms;
+// the FP32 form rounds each contribution once to a 64-bit integer on a fine
+// scale (2^40 per unit charge), so the sums do not depend on the order and
+// continuity holds to about 2^-41 of a particle's charge per node and step.  (With FP32 weights and a 2^28 scale, long
 // drifting-beam runs grew a spurious k1 = 0 mode.)
 #include "hpic_q3d.h"
 
@@ -399,13 +399,14 @@ __device__ __noinline__ void deposit_move_global(A *J, long long plane, int n1, 
 // One thread per particle (items: run, first particle of 256).  Each wave
 // bounds the deposit footprint of its 64 particles before the push (a move is
 // less than a cell: columns cz-2 .. cz+3, rows m-2 .. m+2 around the nearest
-// integer-r node m, ghost rows folded onto rows 0 and 1) and, if the box fits,
-// deposits into its LDS box and adds the box to the global accumulators
-// afterwards; otherwise it deposits with global atomics.
+// integer-r node m, ghost rows folded onto rows 0 and 1).  In the FP32 form
+// its LDS region first holds a copy of the fields its particles gather; then,
+// if the box fits, the region is its current box, added to the global
+// accumulators at the end; otherwise the wave deposits with global atomics.
 template <class R>
-__global__ void __launch_bounds__(256, QPush<R>::WAVES_PER_SIMD) k_q_push_deposit(const RunQ<R> *__restrict__ runs,
-                                                        const Item *__restrict__ items, int parity,
-                                                        unsigned *err) {
+__global__ void __launch_bounds__(256, QPush<R>::WAVES_PER_SIMD)
+    k_q_push_deposit(const RunQ<R> *__restrict__ runs, const Item *__restrict__ items, int parity,
+                     unsigned *err) {
   using C = typename Cplx<R>::T;
   using A = typename AccQ<R>::T;
   extern __shared__ unsigned char smem_raw[];
