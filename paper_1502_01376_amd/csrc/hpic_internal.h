@@ -391,6 +391,7 @@ enum { STAT_FALLBACK = 0, STAT_TILES = 1, NSTAT = 2 };
 // 48 B in FP64) and current accumulators (3 x 8 B per node).  The budget is
 // set per handle from the tile shape (push_lds_bytes), between the minimum
 // and maximum here.
+constexpr int KSTRIP = 8;  // rows per thread of the 2D k-space update
 constexpr int PUSH_THREADS = 256;
 constexpr int PUSH_BATCH = 4;  // particles loaded per thread before pushing
 constexpr int PUSH_LDS_MIN = 16384;

@@ -73,7 +73,7 @@ double dk_mod(const hp_config &c, double k1) {
 }
 
 const int SORT_CHUNK = 256;   // particles per sort workgroup
-const int UPD_BLOCK = 256;    // (i2, kappa) elements per update workgroup
+const int UPD_BLOCK = 256;    // (row or row strip, kappa) elements per update workgroup
 const int TILE1 = 32, TILE2 = 8;  // default particle tile (cells along x1, x2)
 const int SLACK1 = 2, SLACK2 = 1;  // drift beyond the tile the LDS budget allows for
 const int TILE1_3D = 8, TILE2_3D = 4;  // default 3D tile: 8 x 4 x 4 cells
@@ -290,7 +290,8 @@ class Sim : public SimBase {
       h.grp0 = (int)grps.size();
       for (int r = 0; r < d.rows; ++r)
         for (int g = 0; g < 6; g += ncomp_) grps.push_back(Item{i, r, ncomp_ == 3 ? g / 3 : g});
-      const int nel = d.rows * d.nk;
+      // 2D: one update thread per (strip of KSTRIP rows, kappa1); 3D: per (row, kappa1)
+      const int nel = (d.dim == 3 ? d.rows : (d.n2 + KSTRIP - 1) / KSTRIP) * d.nk;
       for (int e = 0; e < nel; e += UPD_BLOCK) upd.push_back(Item{i, e, 0});
       perrun.push_back(Item{i, 0, 0});
     }

@@ -138,6 +138,12 @@ __global__ void __launch_bounds__(256) k_fields_to_k(const Run<R> *__restrict__ 
 // with C_E E = (D2+ E3, -D1+ E3, D1+ E2 - D2+ E1), C_B B = (D2- B3, -D1- B3,
 // D1- B2 - D2- B1), D1+- = i k1 xi+- (Eq. (18)), D2+- the forward/backward
 // differences along x2.
+// 2D update, one thread per (strip of KSTRIP rows, kappa1): the thread walks
+// its rows in order, keeping the previous row's half-step B and new E in
+// registers, so each input row is read once per strip (plus the rows just
+// outside it) instead of up to four times.  Row j needs E^n on rows j-1 .. j+1,
+// B^{n+1/2} on rows j-1 .. j+1 and E^{n+1} on rows j and j+1; every value is
+// computed by the same expressions as for a single row.
 template <class R>
 __global__ void __launch_bounds__(256) k_kupdate(const Run<R> *__restrict__ runs,
                                                  const Item *__restrict__ items, int parity) {
@@ -145,56 +151,81 @@ __global__ void __launch_bounds__(256) k_kupdate(const Run<R> *__restrict__ runs
   const Item it = items[blockIdx.x];
   const Run<R> &r = runs[it.run];
   const int nk = r.nk, n2 = r.n2;
+  const int nstrips = (n2 + KSTRIP - 1) / KSTRIP;
   const int e = it.a + threadIdx.x;
-  if (e >= n2 * nk) return;
-  const int i2 = e / nk, k = e - i2 * nk;
+  if (e >= nstrips * nk) return;
+  const int strip = e / nk, k = e - strip * nk;
+  const int q0 = strip * KSTRIP, q1 = min(q0 + KSTRIP, n2);  // output rows q0 .. q1-1
   const long long plane = (long long)n2 * nk;
   const C *Fi = r.Fk[parity];
   C *Fo = r.Fk[parity ^ 1];
-  const int rm = wrap_small(i2 - 1, n2), rp = wrap_small(i2 + 1, n2), rpp = wrap_small(i2 + 2, n2);
-  auto at = [&](int comp, int row) { return Fi[comp * plane + (long long)row * nk + k]; };
-  const C E1m = at(0, rm), E1 = at(0, i2), E1p = at(0, rp), E1pp = at(0, rpp);
-  const C E2m = at(1, rm), E2 = at(1, i2), E2p = at(1, rp);
-  const C E3m = at(2, rm), E3 = at(2, i2), E3p = at(2, rp), E3pp = at(2, rpp);
-  const C B1m = at(3, rm), B1 = at(3, i2), B1p = at(3, rp);
-  const C B2 = at(4, i2), B2p = at(4, rp);
-  const C B3m = at(5, rm), B3 = at(5, i2), B3p = at(5, rp);
+  auto at = [&](int comp, int row) {
+    return Fi[comp * plane + (long long)wrap_small(row, n2) * nk + k];
+  };
   const auto *Jk = r.Jk;
-  const C j1 = to_d2(Jk[(long long)i2 * nk + k]), j1p = to_d2(Jk[(long long)rp * nk + k]);
-  const C j2 = to_d2(Jk[plane + (long long)i2 * nk + k]);
-  const C j3 = to_d2(Jk[2 * plane + (long long)i2 * nk + k]);
-  const C j3p = to_d2(Jk[2 * plane + (long long)rp * nk + k]);
+  auto jat = [&](int comp, int row) { return to_d2(Jk[comp * plane + (long long)row * nk + k]); };
   const C dp = cmk(r.sym[4 * k + 0], r.sym[4 * k + 1]);
   const C dm = cmk(r.sym[4 * k + 2], r.sym[4 * k + 3]);
   const double hdt = r.mhdt, dt = r.mdt, i2x = r.midx2;
-  // B^{n+1/2} on rows rm, i2, rp
   auto b1h = [&](C B, C Ea, C Eb) { return csub(B, cscale(csub(Eb, Ea), hdt * i2x)); };
   auto b2h = [&](C B, C E) { return cadd(B, cscale(cmul(dp, E), hdt)); };
   auto b3h = [&](C B, C E2x, C E1a, C E1b) {
     return csub(B, cscale(csub(cmul(dp, E2x), cscale(csub(E1b, E1a), i2x)), hdt));
   };
-  const C B1h_m = b1h(B1m, E3m, E3), B1h = b1h(B1, E3, E3p), B1h_p = b1h(B1p, E3p, E3pp);
-  const C B2h = b2h(B2, E3), B2h_p = b2h(B2p, E3p);
-  const C B3h_m = b3h(B3m, E2m, E1m, E1), B3h = b3h(B3, E2, E1, E1p), B3h_p = b3h(B3p, E2p, E1p, E1pp);
-  // E^{n+1} on rows i2 (all) and rp (E1, E3)
   auto e1n = [&](C E, C Ba, C Bb, C j) { return cadd(E, cscale(csub(cscale(csub(Bb, Ba), i2x), j), dt)); };
   auto e3n = [&](C E, C B2x, C B1a, C B1b, C j) {
     return cadd(E, cscale(csub(csub(cmul(dm, B2x), cscale(csub(B1b, B1a), i2x)), j), dt));
   };
-  const C E1n = e1n(E1, B3h_m, B3h, j1), E1n_p = e1n(E1p, B3h, B3h_p, j1p);
-  const C E2n = cadd(E2, cscale(csub(cscale(cmul(dm, B3h), -1.0), j2), dt));
-  const C E3n = e3n(E3, B2h, B1h_m, B1h, j3), E3n_p = e3n(E3p, B2h_p, B1h, B1h_p, j3p);
-  // B^{n+1} on row i2
-  const C B1n = b1h(B1h, E3n, E3n_p);
-  const C B2n = b2h(B2h, E3n);
-  const C B3n = b3h(B3h, E2n, E1n, E1n_p);
-  const long long o = (long long)i2 * nk + k;
-  Fo[o] = E1n;
-  Fo[plane + o] = E2n;
-  Fo[2 * plane + o] = E3n;
-  Fo[3 * plane + o] = B1n;
-  Fo[4 * plane + o] = B2n;
-  Fo[5 * plane + o] = B3n;
+  // row q0-1: the half-step B1 and B3 that row q0 needs
+  C E1 = at(0, q0), E2 = at(1, q0), E3 = at(2, q0);  // E^n of the current row
+  C B1h_m, B3h_m;
+  {
+    const C E1m = at(0, q0 - 1), E2m = at(1, q0 - 1), E3m = at(2, q0 - 1);
+    B1h_m = b1h(at(3, q0 - 1), E3m, E3);
+    B3h_m = b3h(at(5, q0 - 1), E2m, E1m, E1);
+  }
+  // previous row's values, for its output once the current row's E^{n+1} exists
+  C pE1n, pE2n, pE3n, pB1h, pB2h, pB3h;
+  // row j: its half-step B and new E1, E3; the output of row j-1; then, below
+  // the strip's last row + 1, the shift to row j+1
+  auto row = [&](int j, bool last) {
+    const int jw = wrap_small(j, n2);
+    const C E1p = at(0, j + 1), E3p = at(2, j + 1);
+    const C B1h = b1h(at(3, j), E3, E3p);
+    const C B2h = b2h(at(4, j), E3);
+    const C B3h = b3h(at(5, j), E2, E1, E1p);
+    const C E1n = e1n(E1, B3h_m, B3h, jat(0, jw));
+    const C E3n = e3n(E3, B2h, B1h_m, B1h, jat(2, jw));
+    if (j > q0) {
+      // B^{n+1} on row j-1 and the stores of that row
+      const long long o = (long long)(j - 1) * nk + k;
+      Fo[o] = pE1n;
+      Fo[plane + o] = pE2n;
+      Fo[2 * plane + o] = pE3n;
+      Fo[3 * plane + o] = b1h(pB1h, pE3n, E3n);
+      Fo[4 * plane + o] = b2h(pB2h, pE3n);
+      Fo[5 * plane + o] = b3h(pB3h, pE2n, pE1n, E1n);
+    }
+    if (last) return;
+    pE2n = cadd(E2, cscale(csub(cscale(cmul(dm, B3h), -1.0), jat(1, jw)), dt));
+    pE1n = E1n;
+    pE3n = E3n;
+    pB1h = B1h;
+    pB2h = B2h;
+    pB3h = B3h;
+    B1h_m = B1h;
+    B3h_m = B3h;
+    E1 = E1p;
+    E3 = E3p;
+    E2 = at(1, j + 1);
+  };
+  if (q1 - q0 == KSTRIP) {
+    // a whole strip: unrolled, so that the rows' loads can be issued early
+#pragma unroll
+    for (int t = 0; t <= KSTRIP; ++t) row(q0 + t, t == KSTRIP);
+  } else {
+    for (int j = q0; j <= q1; ++j) row(j, j == q1);
+  }
 }
 
 // =====================================================================

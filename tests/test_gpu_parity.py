@@ -249,9 +249,12 @@ def test_fp32_laser_vacuum_1000_steps_matches_oracle(hpic):
     sim.close()
 
 
-def test_fd_mode_matches_oracle_yee(hpic):
-    """deriv1 = 1 turns the hybrid kernels into the Yee scheme (end of Sec. 2.1)."""
-    n1, n2 = 32, 16
+@pytest.mark.parametrize("n2", [16, 13, 4])
+def test_fd_mode_matches_oracle_yee(hpic, n2):
+    """deriv1 = 1 turns the hybrid kernels into the Yee scheme (end of Sec. 2.1).
+    Row counts that are not a multiple of the update kernel's row strip (13)
+    or smaller than one strip (4) take its partial-strip path."""
+    n1 = 32
     gen = np.random.default_rng(9)
     E = gen.standard_normal((3, n2, n1))
     B = gen.standard_normal((3, n2, n1))
