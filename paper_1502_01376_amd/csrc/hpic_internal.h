@@ -118,7 +118,7 @@ template <class C> __device__ __forceinline__ C cmuli(C a, bool plus) {
 // tw[m * tws] = exp(-2 pi i m / M); inverse = true uses the conjugate twiddles
 // (no 1/M).  MAXB bounds the radix-4 butterflies per thread per pass.
 template <class C, int MAXB>
-__device__ void lds_fft(C *buf, int M, int log2M, int NF, const C *__restrict__ tw, int tws,
+__device__ __forceinline__ void lds_fft(C *buf, int M, int log2M, int NF, const C *__restrict__ tw, int tws,
                         bool inverse, int s0 = 0) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int Q = M >> 2;
@@ -232,7 +232,7 @@ __device__ __forceinline__ void dft16(C a[16], bool inverse) {
 // while they fit the block, then the radix-4/2 passes of lds_fft.  Same
 // result as lds_fft.
 template <class C, int MAXB>
-__device__ void lds_fft16(C *buf, int M, int log2M, int NF, const C *__restrict__ tw, int tws,
+__device__ __forceinline__ void lds_fft16(C *buf, int M, int log2M, int NF, const C *__restrict__ tw, int tws,
                           bool inverse) {
   int s = 0;
   if (NF * (M >> 4) <= (int)blockDim.x) {
@@ -278,7 +278,7 @@ __device__ void lds_fft16(C *buf, int M, int log2M, int NF, const C *__restrict_
 // per thread (n1 = 8192 rows: three components of M = 4096).  The choice is
 // uniform over the block, so the barriers inside stay uniform.
 template <class C, int MAXB>
-__device__ void lds_fft_rows(C *buf, int M, int log2M, int NF, const C *__restrict__ tw, int tws,
+__device__ __forceinline__ void lds_fft_rows(C *buf, int M, int log2M, int NF, const C *__restrict__ tw, int tws,
                              bool inverse) {
   if (NF * (M >> 2) <= MAXB * (int)blockDim.x) {
     lds_fft16<C, MAXB>(buf, M, log2M, NF, tw, tws, inverse);
