@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) k_fields_to_k(const Run<R> *__restrict__ 
 // 2D update, one thread per (strip of KSTRIP rows, kappa1): the thread walks
 // its rows in order, keeping the previous row's half-step B and new E in
 // registers, so each input row is read once per strip (plus the rows just
-// outside it) instead of up to four times.  Row j needs E^n on rows j-1 .. j+1,
+// outside it) instead of up to four times.  Row j needs E^n on rows j-1 .. j+2,
 // B^{n+1/2} on rows j-1 .. j+1 and E^{n+1} on rows j and j+1; every value is
 // computed by the same expressions as for a single row.
 template <class R>
