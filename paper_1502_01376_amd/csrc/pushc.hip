@@ -306,9 +306,11 @@ __device__ __forceinline__ void place5(const R s[4], int off, R out[5]) {
 // are bounded first (cells relative to the tile origin, periodic), the
 // current box (bounds -2 .. +3) is accumulated in LDS by all of them and added
 // to the global accumulators at the end; a box too large for LDS falls back to
-// global atomics.
+// global atomics.  The FP32 form is built for 5 waves per SIMD (96 VGPRs;
+// it held 103, i.e. 4 waves, and spills three values off the hot path); the
+// FP64 form keeps its registers.
 template <class R, bool UNIT, bool EC>
-__global__ void __launch_bounds__(256) k_push_deposit_cubic(const Run<R> *__restrict__ runs,
+__global__ void __launch_bounds__(256, sizeof(R) == 4 ? 5 : 1) k_push_deposit_cubic(const Run<R> *__restrict__ runs,
                                                             const Item *__restrict__ items,
                                                             int parity, int pp, int lds_bytes,
                                                             unsigned *err) {
