@@ -16,6 +16,7 @@ import pytest
 
 import oracle
 from paper_1502_01376_amd import workloads as W
+from tests.deposit_bound import node_bounds
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +66,12 @@ def test_full_size_one_step(hpic):
     xb = before["cell"] + step + after["off"].astype(np.float64)
     J64 = oracle.deposit2(g, xall[0], xall[1], xb[0], xb[1], v3.astype(np.float64),
                           before["qw"].astype(np.float64))
+    # the GPU current against that FP64 current, node by node, within the
+    # shape quantisation and FP32 rounding of the particles reaching the node
+    bound = node_bounds(n1, n2, d["dx"][0], d["dx"][1], d["dt"], xall, xb, before["qw"], v3,
+                        fp["P"], fp["inv_wunit"], fp["c3"], fp["Q"] == 0)
+    for c in range(3):
+        assert np.all(np.abs(sim.current(0, c) - d["jbg"][c] - J64[c]) <= bound[c])
     Eo, Bo = oracle.field_update2(g, E0, B0, J64)
     scale = max(np.abs(Eo).max(), np.abs(Bo).max())
     assert np.abs(E1 - Eo).max() <= 2e-5 * scale

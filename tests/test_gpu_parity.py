@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from paper_1502_01376_amd import workloads as W
+from tests.deposit_bound import node_bounds
 
 pytestmark = pytest.mark.gpu
 
@@ -117,18 +118,16 @@ def test_fp32_one_step_matches_oracle(hpic):
                                after["cell"][0], after["cell"][1], after["off"][0],
                                after["off"][1], v3, before["qw"])
     assert np.array_equal(Jg, Jo)
-    # and within the shape quantisation of the FP64 Esirkepov current: each
-    # shape factor is within one 2^-P unit, so a particle moves each of its <= 16
-    # node currents by at most ~8 units times |q w| dx/dt; the errors are
-    # unbiased, so they add in quadrature over particles
+    # and, node by node, within the shape quantisation and FP32 rounding of the
+    # plain FP64 Esirkepov current of the same moves (bound per node: the sum
+    # over the particles reaching it, tests/deposit_bound.py)
     J64 = oracle.deposit2(g, xa[0], xa[1], xg[0], xg[1], v3.astype(np.float64),
                           before["qw"].astype(np.float64))
-    npart = before["qw"].size
-    qmax = np.abs(before["qw"]).max()
-    for c, vscale in enumerate((d["dx"][0] / d["dt"], d["dx"][1] / d["dt"], 1.0)):
+    bound = node_bounds(n1, n2, d["dx"][0], d["dx"][1], d["dt"], xa, xg, before["qw"], v3,
+                        fp["P"], fp["inv_wunit"], fp["c3"], fp["Q"] == 0)
+    for c in range(3):
         jc = sim.current(0, c) - d["jbg"][c]
-        bound = 8 * 2.0 ** -fp["P"] * qmax * vscale * np.sqrt(16 * npart)
-        assert np.linalg.norm(jc - J64[c]) <= bound
+        assert np.all(np.abs(jc - J64[c]) <= bound[c])
     # field update: FP64 hybrid update of the GPU's fields with that current
     Eo, Bo = oracle.field_update2(g, E0, B0, J64)
     scale = max(np.abs(Eo).max(), np.abs(Bo).max())

@@ -193,3 +193,71 @@ def test_fixed_shape_factors_round_to_nearest():
     assert np.abs(err[side]).max() <= 1.0 + 1e-9
     assert abs(err[side].mean()) < 0.02
     assert np.array_equal(col.sum(axis=1), np.full(npart, 2.0 ** P_BITS))
+
+
+@pytest.mark.parametrize("seed,maxstep", [(41, 0.45), (42, 0.99)])
+def test_fp64_matches_column_sum_of_3d_deposit(seed, maxstep):
+    """The 2D current of a move with out-of-plane velocity v3 is the 3D
+    Esirkepov current of the same move, with x3 advanced by v3 dt, summed over
+    a periodic x3 column (both are q w v S with w the density weight).  The 3D
+    deposit is pinned independently by 3D continuity, which fixes all three of
+    its weights; summed over x3 its W3 bracket gives the 2D out-of-plane weight
+    1/3 S0 S0 + 1/6 S1 S0 + 1/6 S0 S1 + 1/3 S1 S1 (Sec. 2.3, Esirkepov's
+    decomposition), and its W1, W2 the in-plane weights.  A wrong 2D W3 such
+    as (S0 S0 + S1 S1)/2 or the midpoint product fails this, where the moment
+    and time-reversal pins above do not."""
+    n1, n2, n3 = 16, 12, 8
+    dx1, dx2, dx3, dt = 0.1, 0.2, 0.25, 0.05
+    xa1, xa2, xb1, xb2, v3, qw = _random_moves(n1, n2, 300, maxstep, seed)
+    g2 = oracle.grid2(n1, n2, dx1, dx2, dt)
+    J2 = oracle.deposit2(g2, xa1, xa2, xb1, xb2, v3, qw)
+    gen = np.random.default_rng(seed + 100)
+    xa3 = gen.uniform(0, n3, xa1.size)
+    xb3 = xa3 + v3 * dt / dx3
+    assert np.abs(xb3 - xa3).max() < 1
+    g3 = oracle.grid3(n1, n2, n3, dx1, dx2, dx3, dt)
+    J3 = oracle.deposit3(g3, np.stack([xa1, xa2, xa3]), np.stack([xb1, xb2, xb3]), qw)
+    col = J3.sum(axis=1)
+    scale = np.abs(J2).max()
+    for c in range(3):
+        assert np.abs(col[c] - J2[c]).max() <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("unit_charge", [True, False])
+def test_fixed_matches_fp64_per_node(unit_charge):
+    """The kernel-precision deposit against the FP64 Esirkepov deposit of the
+    same FP32 positions, node by node: every node's difference is within the
+    sum over the particles reaching it of their shape-quantisation and FP32
+    rounding bounds (tests/deposit_bound.py derives them), and the bound is
+    tight enough to matter: a few 1e-6 of the gross current |q w| v reaching
+    the node with equal charges, 1e-4 with charges rounded to 15 bits."""
+    from tests.deposit_bound import covered_sum, node_bounds
+    n1, n2, dx1, dx2, dt = 16, 8, 0.1, 0.2, 0.045
+    ca1, ca2, fa1, fa2, cb1, cb2, fb1, fb2, v3, qw = _fixed_case(n1, n2, 3000, 0.45, 25, True)
+    if unit_charge:
+        qw = np.full_like(qw, -0.75)
+    qmax = np.float32(np.abs(qw).max())
+    qbits = 0 if unit_charge else 15
+    P = 22 if unit_charge else 20
+    inv_wunit = np.float32(2.0 ** qbits / qmax)
+    c3 = np.float32(2.0 ** (30 - qbits - 2 * P) / 6.0)
+    Ji = oracle.deposit2_fixed(n1, n2, P, inv_wunit, c3, ca1, ca2, fa1, fa2, cb1, cb2, fb1,
+                               fb2, v3, qw)
+    wunit = 1.0 / float(inv_wunit)
+    jf = np.stack([-(dx1 / dt) * wunit * Ji[0] / 2.0 ** (2 * P + 1),
+                   -(dx2 / dt) * wunit * Ji[1] / 2.0 ** (2 * P + 1),
+                   Ji[2] / (float(inv_wunit) * float(c3) * 6.0 * 2.0 ** (2 * P))])
+    d1 = np.mod(cb1 - ca1 + n1 // 2, n1) - n1 // 2
+    d2 = np.mod(cb2 - ca2 + n2 // 2, n2) - n2 // 2
+    xa = np.stack([ca1 + fa1.astype(np.float64), ca2 + fa2.astype(np.float64)])
+    xb = np.stack([ca1 + d1 + fb1.astype(np.float64), ca2 + d2 + fb2.astype(np.float64)])
+    g = oracle.grid2(n1, n2, dx1, dx2, dt)
+    J = oracle.deposit2(g, xa[0], xa[1], xb[0], xb[1], v3.astype(np.float64),
+                        qw.astype(np.float64))
+    bound = node_bounds(n1, n2, dx1, dx2, dt, xa, xb, qw, v3, P, inv_wunit, c3, unit_charge)
+    aq = np.abs(qw.astype(np.float64))
+    gross = [covered_sum(n1, n2, xa, xb, aq) * dx1 / dt, covered_sum(n1, n2, xa, xb, aq) * dx2 / dt,
+             covered_sum(n1, n2, xa, xb, aq * np.abs(v3))]
+    for c in range(3):
+        assert np.all(np.abs(jf[c] - J[c]) <= bound[c])
+        assert np.all(bound[c] <= (4e-6 if unit_charge else 1e-4) * gross[c])
