@@ -367,11 +367,141 @@ __device__ __forceinline__ void deposit2_fp64(const Sink &K, double jfx1, double
   }
 }
 
+template <class T> using lptr = T __attribute__((address_space(3))) *;
+
+// The same deposit into a workgroup's LDS box, giving the same integers bit for
+// bit; only the addressing and which zero contributions are left out differ.
+// In the window (first node min(nearest node before, after) - 1 per axis) both
+// shapes cover nodes 0..2 unless the particle changes its nearest node along
+// that axis, so apart from offsets exactly on a stencil edge the zero
+// contributions are: along x1, column 3 of j2 and j3 and the running sum C1[2]
+// of j1 (zero unless the lane switches nodes along x1); along x2, row 3 of j1
+// and j3 and C2[2] of j2; all of j1 (j2) for a particle that does not move
+// along x1 (x2) by a quantisation step; all of j3 when |h| is too small for
+// any value to round away from zero.  The x1 column is skipped per lane; the
+// x2 row for the whole wave when no lane switches along x2 (the common case
+// for plasmas drifting along x1); a component for the lanes that do not move
+// along its axis, and for the whole wave when none does (a cold drift along x1
+// has no j2 and j3 outside the laser).  Every other node is added without a
+// test (adding an exact zero changes nothing).  Each window row is one LDS
+// pointer, so the nodes of a row are immediate offsets of the atomics.
+template <bool UNIT>
+__device__ __forceinline__ void deposit2_fixed_lds(const LdsFixed &K, int P, float inv_wunit,
+                                                   float c3, int i1, int i2, float fa1, float fa2,
+                                                   int d1, int d2, float fb1, float fb2, float v3,
+                                                   float qw) {
+#pragma clang fp contract(off)
+  int sa1[3], sb1[3], sa2[3], sb2[3];
+  const int na1 = fixed_shape<UNIT>(i1, fa1, P, sa1);
+  const int nb1 = fixed_shape<UNIT>(i1 + d1, fb1, P, sb1);
+  const int na2 = fixed_shape<UNIT>(i2, fa2, P, sa2);
+  const int nb2 = fixed_shape<UNIT>(i2 + d2, fb2, P, sb2);
+  const int base1 = min(na1, nb1) - 1, base2 = min(na2, nb2) - 1;
+  int S0x[4], S1x[4], S0y[4], S1y[4];
+  place4(sa1, na1 - 1 - base1, S0x);
+  place4(sb1, nb1 - 1 - base1, S1x);
+  place4(sa2, na2 - 1 - base2, S0y);
+  place4(sb2, nb2 - 1 - base2, S1y);
+  const float qs = qw * inv_wunit;
+  const int Q = (int)rintf(qs);
+  int C1[4], C2[4], A1[4], A2[4];
+  int acc1 = 0, acc2 = 0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    acc1 += S1x[a] - S0x[a];
+    acc2 += S1y[a] - S0y[a];
+    C1[a] = acc1;
+    C2[a] = acc2;
+    A1[a] = S0x[a] + S1x[a];
+    A2[a] = S0y[a] + S1y[a];
+  }
+  const bool sw1 = na1 != nb1;                      // per lane
+  const bool row3 = __ballot(na2 != nb2) != 0;     // wave-uniform
+  // j1 (j2) vanishes when the quantised x1 (x2) shapes are the same before
+  // and after the move (three integers summing to 2^P: two of them decide)
+  const bool mv1 = (na1 != nb1) | (sa1[0] != sb1[0]) | (sa1[2] != sb1[2]);
+  const bool mv2 = (na2 != nb2) | (sa2[0] != sb2[0]) | (sa2[2] != sb2[2]);
+  const int W = K.W;
+  const lptr<unsigned long long> J1 = (lptr<unsigned long long>)K.J + (__mul24(base2, W) + base1);
+  const lptr<unsigned long long> J2 = J1 + K.plane, J3 = J2 + K.plane;
+  auto add = [](lptr<unsigned long long> q, long long v) {
+    __hip_atomic_fetch_add(q, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
+  auto prod = [&](int qc, int c, int f) -> long long {
+    if (UNIT) return mul24_wide(qc, f);
+    return ((long long)Q * (long long)c) * (long long)f;
+  };
+  // j1 = Q C1[a] A2[b], a = 0..2 (C1[3] = 0)
+  if (__ballot(mv1) != 0 && mv1) {
+    int qc1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) qc1[a] = UNIT ? mul24_lo(Q, C1[a]) : 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (b == 3 && !row3) break;
+      const lptr<unsigned long long> row = J1 + __mul24(b, W);
+      add(row, prod(qc1[0], C1[0], A2[b]));
+      add(row + 1, prod(qc1[1], C1[1], A2[b]));
+      if (sw1) add(row + 2, prod(qc1[2], C1[2], A2[b]));
+    }
+  }
+  // j2 = Q C2[b] A1[a], b = 0..2 (C2[3] = 0)
+  if (__ballot(mv2) != 0 && mv2) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (b == 2 && !row3) break;
+      const lptr<unsigned long long> row = J2 + __mul24(b, W);
+      const int qc = UNIT ? mul24_lo(Q, C2[b]) : 0;
+      add(row, prod(qc, C2[b], A1[0]));
+      add(row + 1, prod(qc, C2[b], A1[1]));
+      add(row + 2, prod(qc, C2[b], A1[2]));
+      if (sw1) add(row + 3, prod(qc, C2[b], A1[3]));
+    }
+  }
+  // j3 = rint(x0[a] t0[b] + x1[a] t1[b]) with the operation order of deposit2_fixed
+  const float hv = qs * v3;
+  const float h = hv * c3;
+  // every j3 value rounds to zero when |h| (S0x t0 + S1x t1) stays below 1/2:
+  // the bracket is at most 2 (3/4)(9/4) 2^(2P) = 3.375 2^(2P), and 0.45 leaves
+  // room for the FP32 rounding of the products
+  const bool z3 = fabsf(h) * (3.375f * (float)(1 << P) * (float)(1 << P)) < 0.45f;
+  if (__ballot(!z3) == 0 || z3) return;
+  float x0[4], x1[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    x0[a] = (float)S0x[a] * h;
+    x1[a] = (float)S1x[a] * h;
+  }
+  auto j3v = [&](int a, float t0, float t1) -> long long {
+    const float p1 = x1[a] * t1;
+    const float v = __builtin_fmaf(x0[a], t0, p1);
+    return (long long)(int)rintf(v);
+  };
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    if (b == 3 && !row3) break;
+    const float B0 = (float)S0y[b], B1 = (float)S1y[b];
+    const float t0 = 2.0f * B0 + B1;
+    const float t1 = B0 + 2.0f * B1;
+    const lptr<unsigned long long> row = J3 + __mul24(b, W);
+    add(row, j3v(0, t0, t1));
+    add(row + 1, j3v(1, t0, t1));
+    add(row + 2, j3v(2, t0, t1));
+    if (sw1) add(row + 3, j3v(3, t0, t1));
+  }
+}
+
 template <bool UNIT, class Sink>
 __device__ __forceinline__ void deposit_one(const Run<float> &r, const Sink &K, int i1, int i2,
                                             float fa1, float fa2, int d1, int d2, float fb1,
                                             float fb2, float v3, float qw) {
   deposit2_fixed<UNIT>(K, r.P, r.inv_wunit, r.c3, i1, i2, fa1, fa2, d1, d2, fb1, fb2, v3, qw);
+}
+template <bool UNIT>
+__device__ __forceinline__ void deposit_one(const Run<float> &r, const LdsFixed &K, int i1, int i2,
+                                            float fa1, float fa2, int d1, int d2, float fb1,
+                                            float fb2, float v3, float qw) {
+  deposit2_fixed_lds<UNIT>(K, r.P, r.inv_wunit, r.c3, i1, i2, fa1, fa2, d1, d2, fb1, fb2, v3, qw);
 }
 template <bool UNIT, class Sink>
 __device__ __forceinline__ void deposit_one(const Run<double> &r, const Sink &K, int i1, int i2,
@@ -499,7 +629,10 @@ k_push_deposit(const Run<R> *__restrict__ runs, const Item *__restrict__ items, 
     blo2 = min(blo2, d2); bhi2 = max(bhi2, d2);
   };
   if (need > (size_t)lds_bytes) {
-    // fallback: gather and deposit in global memory
+    // fallback: gather and deposit in global memory.  The barrier orders the
+    // box initialisation above before every wave's min/max at the end (the
+    // LDS branch has its own barrier after the staging).
+    __syncthreads();
     if (threadIdx.x == 0) atomicAdd(&stats[STAT_FALLBACK], 1u);
     const GlobalFields<R> S{G((const R *)r.F), n1, n2, cells};
     const typename SK::G K{(decltype(SK::G::J))G((typename SK::T *)r.J[parity]), n1, n2, cells};

@@ -452,6 +452,9 @@ k_push_deposit3(const Run<R> *__restrict__ runs, const Item *__restrict__ items,
     }
   };
   if (need > (size_t)lds_bytes) {
+    // the barrier orders the box initialisation above before every wave's
+    // min/max at the end (the LDS branch has its own after the staging)
+    __syncthreads();
     if (threadIdx.x == 0) atomicAdd(&stats[STAT_FALLBACK], 1u);
     const typename SK::G K{(decltype(SK::G::J))G((typename SK::T *)r.J[parity]), n1, n2, n3,
                            n1 * n2, r.cells};
