@@ -304,10 +304,19 @@ def nci_leg(steps):
         out[name] = dict(pick, log10_W_E2_end=round(lw[-1], 3),
                          peak_k1_over_kg1=round(r["peak"]["k1_over_kg1"], 4),
                          peak_k2=round(r["peak"]["k2"], 4))
-    # (0, 0) modes against the time step (filter on): growth rate and k1
-    scan = nci.dt_scan(ratios=(0.25, 0.3, 0.35, 0.4, 0.45, 0.5), steps=30000)
-    out["dt_scan"] = [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()
-                       if k in ("ratio", "growth_rate", "k1_over_kg1")} for r in scan]
+    # (0, 0) modes against the time step (filter on): growth rate and k1,
+    # measured and from the Appendix A linear theory of the same scheme
+    from paper_1502_01376_amd import nci_theory
+    ratios = (0.25, 0.3, 0.35, 0.4, 0.45, 0.5)
+    scan = nci.dt_scan(ratios=ratios, steps=30000)
+    theory = nci_theory.dt_scan(ratios=ratios)
+    out["dt_scan"] = []
+    for r, th in zip(scan, theory):
+        e = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()
+             if k in ("ratio", "growth_rate", "k1_over_kg1")}
+        e["theory_growth_rate"] = round(th["growth_rate"], 5)
+        e["theory_k1_over_kg1"] = round(th["k1_over_kg1"], 4)
+        out["dt_scan"].append(e)
     out["wall_s"] = round(time.time() - t0, 2)
     return out
 

@@ -11,10 +11,11 @@
   shape the E2 energy then rises late in the run, with the cubic shape it
   stays at the noise level up to t = 3200 (Fig. 3).
 
-The paper's figures are not reproduced in its text, so the growth rates and
-levels are parity unpinned: the thresholds are wide margins around the
+The paper's figures are not reproduced in its text, so the levels of the four
+histories are parity unpinned: the thresholds are wide margins around the
 measured histories (orders of magnitude apart), checking only the contrast
-the paper describes."""
+the paper describes.  The growth rate and k1 of the (0, 0) modes against the
+time step are compared with the Appendix A linear theory."""
 import math
 
 import numpy as np
@@ -71,15 +72,22 @@ def test_cubic_shape_keeps_the_kmod_run_quiet(fig3):
 
 
 def test_00_modes_against_the_time_step(hpic):
-    """Sec. 3 (Fig. 2 (a)-(b)): reducing the time step lowers the growth rate
-    of the fastest (0, 0) mode and raises its k1.  Measured on the Table 1
-    drift with the filter: amplitude growth rates 0.025, 0.037, 0.046 and
-    k1/kg1 0.25, 0.23, 0.20 at dt/dx1 = 0.25, 0.35, 0.45 (parity unpinned: the
-    figure is not in the text; only the ordering is checked)."""
-    res = nci.dt_scan(ratios=(0.25, 0.35, 0.45), steps=30000)
+    """Sec. 3 (Fig. 2 (a)-(b)): the growth rate and k1 of the fastest (0, 0)
+    mode on the Table 1 drift with the filter, measured on the GPU, against
+    the linear theory of Appendix A for the same scheme
+    (paper_1502_01376_amd/nci_theory.py, pinned on the CPU): reducing the time
+    step lowers the growth rate and raises k1, and each measured rate is
+    within 10% of the predicted Im(omega), each k1 within 0.02 kg1 (the grid's
+    k1 resolution is 1/256 kg1; the fit window adds the rest)."""
+    from paper_1502_01376_amd import nci_theory
+    ratios = (0.25, 0.35, 0.45)
+    res = nci.dt_scan(ratios=ratios, steps=30000)
+    theory = nci_theory.dt_scan(ratios=ratios)
     rates = [r["growth_rate"] for r in res]
     k1 = [r["k1_over_kg1"] for r in res]
-    assert all(0.005 < g < 0.2 for g in rates), res
     assert rates[0] < rates[1] < rates[2], res
     assert k1[0] > k1[2], res
-    assert all(0.12 < k < 0.3 for k in k1), res
+    for m, t in zip(res, theory):
+        assert t["full_relation"]
+        assert abs(m["growth_rate"] - t["growth_rate"]) <= 0.1 * t["growth_rate"], (m, t)
+        assert abs(m["k1_over_kg1"] - t["k1_over_kg1"]) <= 0.02, (m, t)
