@@ -814,13 +814,12 @@ __global__ void __launch_bounds__(1024) k_sort_scan(const Run<R> *runs, const It
 }
 
 // Scatter.  With `scramble`, a particle's rank within its tile (arrival order)
-// is multiplied by a prime larger than any tile count, modulo the count (a
-// bijection), so that consecutive slots of a tile hold particles from scattered
-// cells: the lanes of a push wave then rarely hit the same LDS accumulator.
-// That is needed once, for input in cell order; later sorts keep the arrival
-// order (already mixed), so lanes of one wave with the same tile write
-// consecutive slots.
-constexpr long long SCRAMBLE = 1048573;  // prime, > any particle count per tile
+// is transposed (a bijection, below) so that consecutive slots of a tile hold
+// particles of different cells: the lanes of a push wave then do not hit the
+// same LDS accumulator, and their addresses fall in different banks.  That is
+// needed once, for input in cell order; later sorts keep the arrival order
+// (already spread), so lanes of one wave with the same tile write consecutive
+// slots.
 template <class R>
 __global__ void k_sort_scatter(const Run<R> *runs, const Item *chunks, int pp, int scramble) {
   const Item it = chunks[blockIdx.x];
@@ -835,8 +834,18 @@ __global__ void k_sort_scatter(const Run<R> *runs, const Item *chunks, int pp, i
   if (!active) return;
   const int t0 = r.tile_start[t], cnt = r.tile_start[t + 1] - t0;
   const int rank = q - t0;
-  const int slot =
-      t0 + ((scramble && (cnt % SCRAMBLE)) ? (int)(((long long)rank * SCRAMBLE) % cnt) : rank);
+  int slot = t0 + rank;
+  if (scramble) {
+    // ragged transpose by the tile's mean particles per cell m: arrival rank
+    // r = m j + k (loaded particles arrive in cell order) goes to column k,
+    // row j, so consecutive slots, the lanes of a wave, hold particles of
+    // different cells
+    const int area = (r.dim == 3) ? r.T1 * r.T2 * r.T3 : r.T1 * r.T2;
+    const int m = max(1, cnt / area);
+    const int rows = cnt / m, rem = cnt - rows * m;
+    const int k = rank % m, j = rank / m;
+    slot = t0 + k * rows + min(k, rem) + j;
+  }
   B.cell[slot] = c;
   B.id[slot] = A.id[p];
   B.f1[slot] = A.f1[p];
