@@ -34,7 +34,8 @@
  * deposited per mode by a charge-conserving scheme (Esirkepov in r-z with
  * the mean phase plus an azimuthal flux from the phase change) and must stay
  * at r < (n2 - 3) dr (no particle boundary at the wall).  Not available for
- * this geometry: the tile calls, checkpoints, raw and fixed-point access.
+ * this geometry: the tile calls, raw and fixed-point access, the device-buffer
+ * transfers.
  * Units: c = 1, t in 1/w_p, x in c/w_p, E and B in m c w_p / e, density in
  * n_p, current in e n_p c (the 4 pi of the paper's Gaussian form is 1).
  *
@@ -158,6 +159,20 @@ int hp_set_stream(hp_sim *sim, void *hip_stream);
 int hp_set_particles(hp_sim *sim, int32_t run, int32_t species, int64_t n, const double *x,
                      const double *u, const double *w, double q_over_m, double q);
 
+/* As hp_set_particles (the scheme's particle input of Sec. 2: positions,
+ * momenta, weights), Cartesian runs only, with x[dim][n], u[3][n], w[n] FP64
+ * arrays in device memory (for example torch tensors on the handle's device).
+ * The conversion to cell index + offset runs on the device with the same
+ * operations as the host loader, so the run holds the same bits either way.
+ * A first device pass validates the input and measures the charges and the
+ * particles per cell; on an error nothing of the run changes.  The buffers stay
+ * caller-owned and are read on the handle's stream before return (the call
+ * synchronises).  Errors: HP_EINVAL (a pointer that is not device memory, a
+ * quasi-3D handle, or as hp_set_particles), HP_ERANGE (fixed-point headroom). */
+int hp_set_particles_device(hp_sim *sim, int32_t run, int32_t species, int64_t n,
+                            const double *x, const double *u, const double *w, double q_over_m,
+                            double q);
+
 /* Sets E^0 and B^0 of a run from host arrays E[3][cells], B[3][cells] at
  * their Yee nodes (mode must be 0).  Quasi-3D: mode m, complex interleaved
  * E[3][n2+1][n1][2], B likewise. */
@@ -280,13 +295,38 @@ int hp_get_particles(hp_sim *sim, int32_t run, int64_t n, double *x, double *u, 
 int hp_get_particles_raw(hp_sim *sim, int32_t run, int64_t n, int32_t *cell, float *off,
                          float *u, float *qw, int32_t *id);
 
+/* Device-buffer reads (Cartesian runs), enqueued on the handle's stream and
+ * asynchronous: the outputs are valid once that stream's work up to here has
+ * completed (hp_synchronize or the caller's own stream synchronisation).
+ * Outputs are caller-owned device memory of the form's real type, float for
+ * HP_PREC_FP32_FIXED and double for HP_PREC_FP64 (written "real" below).
+ *
+ * hp_get_field_device: the real-space field component comp (0..2 = E1..E3,
+ * 3..5 = B1..B3) that the next gather reads, at its Yee nodes (Eqs. (1)-(6)),
+ * into out[count] real, count = cells, layout [n3][n2][n1].
+ *
+ * hp_get_particles_device: the particle state in the library's current order:
+ * cell[dim][n] (int32 i1, i2, i3), off[dim][n] real offsets in [0,1),
+ * u[3][n] real, qw[n] real (charge times weight), id[n] (int32 index given at
+ * loading).  Any pointer may be NULL; n must equal the particle count.
+ *
+ * Errors: HP_EINVAL (a pointer that is not device memory, bad comp or count,
+ * a quasi-3D handle). */
+int hp_get_field_device(hp_sim *sim, int32_t run, int32_t comp, void *out, size_t count);
+int hp_get_particles_device(hp_sim *sim, int32_t run, int64_t n, int32_t *cell, void *off,
+                            void *u, void *qw, int32_t *id);
+
 /* FP64 diagnostics of a run (energies, Gauss residual, continuity residual of
  * the last step when the previous hp_diagnostics call was one step earlier). */
 int hp_diagnostics(hp_sim *sim, int32_t run, hp_diag *out);
 
-/* Checkpoint: with blob == NULL writes the needed size to *size; otherwise
- * fills blob (size bytes).  hp_set_state restores a handle created with the
- * same configs; resuming is bit-exact. */
+/* Checkpoint of every run of the handle (particles, real-space fields, the
+ * FP64 k-space master, the last deposit, the background): with blob == NULL
+ * writes the needed size to *size; otherwise fills blob (size bytes,
+ * caller-owned; synchronous).  hp_set_state restores a handle created with the
+ * same configs (Cartesian or quasi-3D); resuming is bit-exact.  Errors:
+ * HP_EINVAL (buffer too small, a blob of another geometry, precision or run
+ * count, a truncated blob). */
 int hp_get_state(hp_sim *sim, void *blob, size_t *size);
 int hp_set_state(hp_sim *sim, const void *blob, size_t size);
 

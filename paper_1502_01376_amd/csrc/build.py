@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libhpic.so")
 SOURCES = ["push.hip", "push3.hip", "pushc.hip", "pushq.hip", "solve.hip", "solveq.hip",
-           "antenna.hip", "runtime.cpp"]
+           "antenna.hip", "io.hip", "runtime.cpp"]
 ARCH = os.environ.get("HPIC_ARCH", "gfx950")
 
 

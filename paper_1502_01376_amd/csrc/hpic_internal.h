@@ -501,4 +501,28 @@ template <class R>
 void launch_inverse_rows(const typename Cplx<R>::T *Xk, int nk, int n1, int nrows,
                          const typename Cplx<R>::T *tw, R scale, R *out, hipStream_t s);
 
+// ---------------------------------------------------------------- device I/O
+// (io.hip) Geometry of a Cartesian run for loading particles from FP64 device
+// arrays: box lengths L = n dx, cell sizes, packing of the cell index.
+struct LoadGeom {
+  int dim, n1, n2, n3, log2n1, sh3;
+  double L[3], dx[3];
+};
+// Validation pass over n particles (x[dim][n], u[3][n], w[n] in device memory):
+// *bad |= 1 for a non-finite input, count[cells] += particles per cell,
+// qbits[0] = max and qbits[1] = min of |(R)(q w)| as FP64 bit patterns.
+template <class R>
+void launch_scan_particles(const LoadGeom &g, long long n, const double *x, const double *u,
+                           const double *w, double q, int *count, unsigned long long *qbits,
+                           unsigned *bad, hipStream_t s);
+void launch_max_int(const int *a, long long n, int *out, hipStream_t s);
+// Conversion pass: the run's structure of arrays A in input order.
+template <class R>
+void launch_load_particles(const LoadGeom &g, long long n, const double *x, const double *u,
+                           const double *w, double q, Parts<R> A, hipStream_t s);
+// The run's particle state (buffer pp, current order) into device buffers.
+template <class R>
+void launch_unload_particles(const Run<R> *run_dev, int pp, int np, int *cell, R *off, R *u, R *qw,
+                             int *id, hipStream_t s);
+
 }  // namespace hp

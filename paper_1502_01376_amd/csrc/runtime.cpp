@@ -135,7 +135,31 @@ struct SimBase {
   virtual int set_antenna(int, const hp_antenna *) {
     return fail(HP_EINVAL, "the antenna is built for 2D runs only");
   }
+  // transfers with caller-owned device buffers (Cartesian runs)
+  virtual int set_particles_device(int, int64_t, const double *, const double *, const double *,
+                                   double, double) {
+    return fail(HP_EINVAL, "device-buffer particle loading exists for Cartesian runs only");
+  }
+  virtual int get_field_device(int, int, void *, size_t) {
+    return fail(HP_EINVAL, "device-buffer field reads exist for Cartesian runs only");
+  }
+  virtual int get_particles_device(int, int64_t, int32_t *, void *, void *, void *, int32_t *) {
+    return fail(HP_EINVAL, "device-buffer particle reads exist for Cartesian runs only");
+  }
 };
+
+// A pointer the device can dereference: device or managed memory of this
+// process (a host pointer passed to a _device entry point is rejected instead
+// of faulting in a kernel).
+static bool device_pointer(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
 
 struct hp_sim {
   SimBase *impl;
@@ -355,11 +379,128 @@ class Sim : public SimBase {
       id[p] = (int)p;
       count[((size_t)c3 * d.n2 + c2) * d.n1 + c1]++;
     }
-    if (FIXED && n > 0 && three) {
+    {
+      const int cmax = n > 0 ? *std::max_element(count.begin(), count.end()) : 0;
+      int rc;
+      if ((rc = fixed_params_for(h, n, qmax, qmin, cmax))) return rc;
+    }
+    h.qm = qm;
+    h.q = q;
+    d.qmhdt = (R)(0.5 * qm * h.cfg.dt);
+    d.np = (int)n;
+    h.np = n;
+    int rc;
+    if ((rc = alloc_particles(run, n))) return rc;
+    Parts<R> &A = d.pt[pp_];
+    if ((rc = h2d(A.cell, cell.data(), n)) || (rc = h2d(A.id, id.data(), n)) ||
+        (rc = h2d(A.f1, f1.data(), n)) || (rc = h2d(A.f2, f2.data(), n)) ||
+        (rc = h2d(A.u1, u1.data(), n)) || (rc = h2d(A.u2, u2.data(), n)) ||
+        (rc = h2d(A.u3, u3.data(), n)) || (rc = h2d(A.qw, qw.data(), n)) ||
+        (three && (rc = h2d(A.f3, f3.data(), n))))
+      return rc;
+    if ((rc = upload_jfac(run))) return rc;
+    if ((rc = rebuild_sort_items())) return rc;
+    if ((rc = upload_runs())) return rc;
+    return sort_now();
+  }
+
+  // Particles from FP64 arrays in device memory: the conversion of
+  // set_particles done on the device (same operations, same bits).  A first
+  // pass only validates and measures (non-finite input, charges, particles per
+  // cell for the headroom) and changes nothing; then the run's arrays are
+  // replaced and sorted as by set_particles.
+  int set_particles_device(int run, int64_t n, const double *x, const double *u, const double *w,
+                           double qm, double q) override {
+    RunHost &h = runs_[run];
+    Run<R> &d = h.d;
+    if (n < 0 || n > 1000000000) return fail(HP_EINVAL, "particle count %lld out of range", (long long)n);
+    if (n > 0 && (!device_pointer(x) || !device_pointer(u) || !device_pointer(w)))
+      return fail(HP_EINVAL, "particle arrays must be device memory");
+    if (!std::isfinite(qm) || !std::isfinite(q) || qm == 0.0) return fail(HP_EINVAL, "bad q/m or q");
+    const LoadGeom g{d.dim, d.n1, d.n2, d.n3, d.log2n1, d.sh3,
+                     {h.cfg.dx[0] * d.n1, h.cfg.dx[1] * d.n2, h.cfg.dx[2] * d.n3},
+                     {h.cfg.dx[0], h.cfg.dx[1], h.cfg.dx[2]}};
+    double qmax = 0.0, qmin = INFINITY;
+    int cmax = 0;
+    if (n > 0) {
+      int *count, *dmax;
+      unsigned long long *qbits;
+      unsigned *bad;
+      int rc;
+      if ((rc = alloc(&count, (size_t)d.cells)) || (rc = alloc(&dmax, 1)) ||
+          (rc = alloc(&qbits, 2)) || (rc = alloc(&bad, 1)))
+        return rc;
+      const unsigned long long init[2] = {0ull, 0x7ff0000000000000ull};  // 0, +inf
+      auto done = [&](int code) {
+        release(count); release(dmax); release(qbits); release(bad);
+        return code;
+      };
+      if ((rc = h2d(qbits, init, 2))) return done(rc);
+      launch_scan_particles<R>(g, n, x, u, w, q, count, qbits, bad, stream_);
+      launch_max_int(count, d.cells, dmax, stream_);
+      if (hipGetLastError() != hipSuccess) return done(fail(HP_EDEVICE, "particle scan launch failed"));
+      unsigned long long qb[2];
+      unsigned flag = 0;
+      if ((rc = d2h(qb, qbits, 2)) || (rc = d2h(&flag, bad, 1)) || (rc = d2h(&cmax, dmax, 1)))
+        return done(rc);
+      done(HP_OK);
+      if (flag) return fail(HP_EINVAL, "non-finite particle input");
+      std::memcpy(&qmax, &qb[0], sizeof qmax);
+      std::memcpy(&qmin, &qb[1], sizeof qmin);
+    }
+    int rc;
+    if ((rc = fixed_params_for(h, n, qmax, qmin, cmax))) return rc;
+    h.qm = qm;
+    h.q = q;
+    d.qmhdt = (R)(0.5 * qm * h.cfg.dt);
+    d.np = (int)n;
+    h.np = n;
+    if ((rc = alloc_particles(run, n))) return rc;
+    launch_load_particles<R>(g, n, x, u, w, q, d.pt[pp_], stream_);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream_));
+    if ((rc = upload_jfac(run))) return rc;
+    if ((rc = rebuild_sort_items())) return rc;
+    if ((rc = upload_runs())) return rc;
+    return sort_now();
+  }
+
+  // The real-space field of one component (the copy the next gather reads) into
+  // a device buffer of the form's real type; asynchronous on the stream.
+  int get_field_device(int run, int comp, void *out, size_t count) override {
+    const Run<R> &d = runs_[run].d;
+    const size_t cells = (size_t)d.cells;
+    if (comp < 0 || comp > 5 || count != cells) return fail(HP_EINVAL, "bad field request");
+    if (!device_pointer(out)) return fail(HP_EINVAL, "output must be device memory");
+    HIPCHK(hipMemcpyAsync(out, d.F + comp * cells, cells * sizeof(R), hipMemcpyDeviceToDevice,
+                          stream_));
+    return HP_OK;
+  }
+
+  // The particle state in the library's current order into device buffers;
+  // asynchronous on the stream.
+  int get_particles_device(int run, int64_t n, int32_t *cell, void *off, void *u, void *qw,
+                           int32_t *id) override {
+    const RunHost &h = runs_[run];
+    if (n != h.np) return fail(HP_EINVAL, "particle count mismatch");
+    const void *ptrs[5] = {cell, off, u, qw, id};
+    for (const void *p : ptrs)
+      if (p && !device_pointer(p)) return fail(HP_EINVAL, "outputs must be device memory");
+    launch_unload_particles<R>(d_runs_ + run, pp_, (int)n, cell, (R *)off, (R *)u, (R *)qw, id,
+                               stream_);
+    HIPCHK(hipGetLastError());
+    return HP_OK;
+  }
+
+  // Fixed-point parameters of a run (FP32 form) from its charges |q w| (largest
+  // and smallest) and the largest number of particles in one cell: the
+  // accumulators' headroom decides the shape and charge bits.
+  int fixed_params_for(RunHost &h, int64_t n, double qmax, double qmin, int cmax) {
+    Run<R> &d = h.d;
+    if (FIXED && n > 0 && d.dim == 3) {
       // 3D: each node's contribution is at most 3.4 cj in integers, a node
       // collects from the particles of 4 x 4 x 4 cells
       if (!(qmax > 0.0)) return fail(HP_EINVAL, "all particle charges are zero");
-      const int cmax = *std::max_element(count.begin(), count.end());
       if (64.0 * std::max(cmax, 1) * 4.0 * CJ3 >= std::ldexp(1.0, 62))
         return fail(HP_ERANGE, "fixed-point headroom: %d particles in one cell", cmax);
       h.Qbits = 0;
@@ -368,7 +509,6 @@ class Sim : public SimBase {
       d.cj = (float)CJ3;
     } else if (FIXED && n > 0) {
       if (!(qmax > 0.0)) return fail(HP_EINVAL, "all particle charges are zero");
-      const int cmax = *std::max_element(count.begin(), count.end());
       // per node |J| <= K * (particles per cell) * 2^(2P+Q): keep below 2^62.
       // Quadratic: 3 x 3 cells reach a node, |C| <= 2^P, A <= 1.5 2^P (K = 24);
       // cubic: 5 x 5 cells, A <= (4/3) 2^P (K = 34)
@@ -398,24 +538,7 @@ class Sim : public SimBase {
       d.inv_wunit = (float)(std::ldexp(1.0, Q) / qmax);
       d.c3 = (float)(std::ldexp(1.0, 30 - Q - 2 * P) / 6.0);
     }
-    h.qm = qm;
-    h.q = q;
-    d.qmhdt = (R)(0.5 * qm * h.cfg.dt);
-    d.np = (int)n;
-    h.np = n;
-    int rc;
-    if ((rc = alloc_particles(run, n))) return rc;
-    Parts<R> &A = d.pt[pp_];
-    if ((rc = h2d(A.cell, cell.data(), n)) || (rc = h2d(A.id, id.data(), n)) ||
-        (rc = h2d(A.f1, f1.data(), n)) || (rc = h2d(A.f2, f2.data(), n)) ||
-        (rc = h2d(A.u1, u1.data(), n)) || (rc = h2d(A.u2, u2.data(), n)) ||
-        (rc = h2d(A.u3, u3.data(), n)) || (rc = h2d(A.qw, qw.data(), n)) ||
-        (three && (rc = h2d(A.f3, f3.data(), n))))
-      return rc;
-    if ((rc = upload_jfac(run))) return rc;
-    if ((rc = rebuild_sort_items())) return rc;
-    if ((rc = upload_runs())) return rc;
-    return sort_now();
+    return HP_OK;
   }
 
   int set_fields(int run, const double *E, const double *B) override {
@@ -2136,8 +2259,154 @@ class SimQ : public SimBase {
   int get_particles_raw(int, int64_t, int32_t *, float *, float *, float *, int32_t *) override {
     return na();
   }
-  int get_state(void *, size_t *) override { return na(); }
-  int set_state(const void *, size_t) override { return na(); }
+  // Checkpoint of every run: step and parity, per run its particles (11
+  // arrays), the real-space fields, the FP64 k-space master of the current
+  // parity, the last deposit (for the current reads), the background charge
+  // and current.  Resuming from it repeats the same steps bit for bit.
+  size_t state_size() const {
+    size_t s = 7 * sizeof(int64_t);
+    for (const RunHostQ &h : runs_) {
+      const RunQ<R> &d = h.d;
+      const size_t fn = (size_t)d.M * 6 * d.plane, jn = (size_t)d.M * 3 * d.plane;
+      s += 8 * sizeof(double) + (size_t)d.np * (4 * sizeof(int) + 7 * sizeof(R)) +
+           fn * (sizeof(C) + sizeof(double2)) + 2 * jn * sizeof(A) + d.nr * sizeof(double) +
+           (h.rho_bg ? (size_t)d.M * d.plane * sizeof(double2) : 0);
+    }
+    return s;
+  }
+
+  int get_state(void *blob, size_t *size) override {
+    int rc;
+    if ((rc = sync())) return rc;
+    const size_t need = state_size();
+    if (!blob) {
+      *size = need;
+      return HP_OK;
+    }
+    if (*size < need) return fail(HP_EINVAL, "state buffer too small (%zu < %zu)", *size, need);
+    char *o = (char *)blob;
+    auto get = [&](const void *src, size_t bytes) {
+      if (bytes) HIPCHK(hipMemcpy(o, src, bytes, hipMemcpyDeviceToHost));
+      o += bytes;
+      return HP_OK;
+    };
+    const int64_t hdr[7] = {0x48504951, 1, (int64_t)runs_.size(), sizeof(R) == 4 ? 0 : 1, step_,
+                            parity_, deposited_ ? 1 : 0};
+    std::memcpy(o, hdr, sizeof hdr);
+    o += sizeof hdr;
+    for (const RunHostQ &h : runs_) {
+      const RunQ<R> &d = h.d;
+      const size_t n = (size_t)d.np, fn = (size_t)d.M * 6 * d.plane, jn = (size_t)d.M * 3 * d.plane;
+      const double meta[8] = {(double)d.np, h.qm, h.q, (double)d.wscale, h.rho_bg ? 1.0 : 0.0,
+                              0, 0, 0};
+      std::memcpy(o, meta, sizeof meta);
+      o += sizeof meta;
+      const PartsQ<R> &P = d.pt;
+      const int *ia[4] = {P.cell, P.ix, P.iy, P.id};
+      const R *ra[7] = {P.fz, P.fx, P.fy, P.uz, P.ux, P.uy, P.qw};
+      for (const int *a : ia)
+        if ((rc = get(a, sizeof(int) * n))) return rc;
+      for (const R *a : ra)
+        if ((rc = get(a, sizeof(R) * n))) return rc;
+      if ((rc = get(d.F, sizeof(C) * fn)) || (rc = get(d.Fk[parity_], sizeof(double2) * fn)) ||
+          (rc = get(d.J[parity_ ^ 1], 2 * sizeof(A) * jn)) ||
+          (rc = get(d.jbgk, sizeof(double) * d.nr)))
+        return rc;
+      if (h.rho_bg && (rc = get(h.rho_bg, sizeof(double2) * (size_t)d.M * d.plane))) return rc;
+    }
+    *size = need;
+    return HP_OK;
+  }
+
+  int set_state(const void *blob, size_t size) override {
+    const char *o = (const char *)blob;
+    const char *end = o + size;
+    int64_t hdr[7];
+    if (size < sizeof hdr) return fail(HP_EINVAL, "truncated state");
+    std::memcpy(hdr, o, sizeof hdr);
+    o += sizeof hdr;
+    if (hdr[0] != 0x48504951 || hdr[1] != 1 || hdr[2] != (int64_t)runs_.size() ||
+        hdr[3] != (sizeof(R) == 4 ? 0 : 1) || (hdr[5] != 0 && hdr[5] != 1))
+      return fail(HP_EINVAL, "state blob does not match this handle");
+    int rc;
+    if ((rc = sync())) return rc;
+    // check the whole blob before changing anything
+    {
+      const char *q = o;
+      for (const RunHostQ &h : runs_) {
+        const RunQ<R> &d = h.d;
+        double meta[8];
+        if (q + sizeof meta > end) return fail(HP_EINVAL, "truncated state");
+        std::memcpy(meta, q, sizeof meta);
+        q += sizeof meta;
+        const double np = meta[0];
+        if (!(np >= 0 && np <= (double)((int64_t)1 << 30) && np == std::floor(np)))
+          return fail(HP_EINVAL, "bad particle count in state");
+        const size_t n = (size_t)np, fn = (size_t)d.M * 6 * d.plane, jn = (size_t)d.M * 3 * d.plane;
+        const size_t bytes = n * (4 * sizeof(int) + 7 * sizeof(R)) + fn * (sizeof(C) + sizeof(double2)) +
+                             2 * jn * sizeof(A) + d.nr * sizeof(double) +
+                             (meta[4] != 0 ? (size_t)d.M * d.plane * sizeof(double2) : 0);
+        if ((size_t)(end - q) < bytes) return fail(HP_EINVAL, "truncated state");
+        q += bytes;
+      }
+    }
+    step_ = hdr[4];
+    parity_ = (int)hdr[5];
+    deposited_ = hdr[6] != 0;
+    auto put = [&](void *dst, size_t bytes) {
+      if (bytes) HIPCHK(hipMemcpy(dst, o, bytes, hipMemcpyHostToDevice));
+      o += bytes;
+      return HP_OK;
+    };
+    for (int i = 0; i < (int)runs_.size(); ++i) {
+      RunHostQ &h = runs_[i];
+      RunQ<R> &d = h.d;
+      double meta[8];
+      std::memcpy(meta, o, sizeof meta);
+      o += sizeof meta;
+      const int64_t n = (int64_t)meta[0];
+      const size_t fn = (size_t)d.M * 6 * d.plane, jn = (size_t)d.M * 3 * d.plane;
+      for (void *&b : h.pbuf) {
+        if (b) release(b);
+        b = nullptr;
+      }
+      PartsQ<R> &P = d.pt;
+      if ((rc = alloc(&P.cell, n)) || (rc = alloc(&P.fz, n)) || (rc = alloc(&P.ix, n)) ||
+          (rc = alloc(&P.fx, n)) || (rc = alloc(&P.iy, n)) || (rc = alloc(&P.fy, n)) ||
+          (rc = alloc(&P.uz, n)) || (rc = alloc(&P.ux, n)) || (rc = alloc(&P.uy, n)) ||
+          (rc = alloc(&P.qw, n)) || (rc = alloc(&P.id, n)))
+        return rc;
+      void *bufs[11] = {P.cell, P.fz, P.ix, P.fx, P.iy, P.fy, P.uz, P.ux, P.uy, P.qw, P.id};
+      for (int k = 0; k < 11; ++k) h.pbuf[k] = bufs[k];
+      int *ia[4] = {P.cell, P.ix, P.iy, P.id};
+      R *ra[7] = {P.fz, P.fx, P.fy, P.uz, P.ux, P.uy, P.qw};
+      for (int *a : ia)
+        if ((rc = put(a, sizeof(int) * n))) return rc;
+      for (R *a : ra)
+        if ((rc = put(a, sizeof(R) * n))) return rc;
+      d.np = (int)n;
+      h.qm = meta[1];
+      h.q = meta[2];
+      d.wscale = (R)meta[3];
+      d.qmhdt = (R)(h.qm * 0.5 * d.dt);
+      if ((rc = put(d.F, sizeof(C) * fn)) || (rc = put(d.Fk[parity_], sizeof(double2) * fn)) ||
+          (rc = put(d.J[parity_ ^ 1], 2 * sizeof(A) * jn)) ||
+          (rc = put((void *)d.jbgk, sizeof(double) * d.nr)))
+        return rc;
+      HIPCHK(hipMemset(d.J[parity_], 0, 2 * sizeof(A) * jn));
+      if (meta[4] != 0) {
+        if (!h.rho_bg && (rc = alloc(&h.rho_bg, (size_t)d.M * d.plane))) return rc;
+        if ((rc = put(h.rho_bg, sizeof(double2) * (size_t)d.M * d.plane))) return rc;
+      } else if (h.rho_bg) {
+        release(h.rho_bg);
+        h.rho_bg = nullptr;
+      }
+      set_jconv(i);
+    }
+    if ((rc = rebuild_push_items())) return rc;
+    return upload_runs();
+  }
+
   int debug_deposit(int, int64_t, const int32_t *, const float *, const int32_t *, const float *,
                     const float *, const float *, int64_t *) override { return na(); }
   int fixed_params(int, double *) override { return na(); }
@@ -2380,6 +2649,25 @@ int hp_set_particles(hp_sim *sim, int32_t run, int32_t species, int64_t n, const
     if (species != 0) return fail(HP_EINVAL, "only species 0 is supported");
     return sim->impl->set_particles(run, n, x, u, w, q_over_m, q);
   });
+}
+
+int hp_set_particles_device(hp_sim *sim, int32_t run, int32_t species, int64_t n,
+                            const double *x, const double *u, const double *w, double q_over_m,
+                            double q) {
+  return with_run(sim, run, [&] {
+    if (species != 0) return fail(HP_EINVAL, "only species 0 is supported");
+    return sim->impl->set_particles_device(run, n, x, u, w, q_over_m, q);
+  });
+}
+
+int hp_get_field_device(hp_sim *sim, int32_t run, int32_t comp, void *out, size_t count) {
+  return with_run(sim, run, [&] { return sim->impl->get_field_device(run, comp, out, count); });
+}
+
+int hp_get_particles_device(hp_sim *sim, int32_t run, int64_t n, int32_t *cell, void *off,
+                            void *u, void *qw, int32_t *id) {
+  return with_run(sim, run,
+                  [&] { return sim->impl->get_particles_device(run, n, cell, off, u, qw, id); });
 }
 
 int hp_set_fields(hp_sim *sim, int32_t run, int32_t mode, const double *E, const double *B) {

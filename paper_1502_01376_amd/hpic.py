@@ -28,7 +28,8 @@ ABI = (
     "hp_get_particles_raw", "hp_diagnostics", "hp_get_state", "hp_set_state",
     "hp_debug_deposit", "hp_get_fixed_params", "hp_profile", "hp_get_kernel_times",
     "hp_get_push_stats", "hp_use_graphs", "hp_set_tiling", "hp_get_tiling", "hp_autotune",
-    "hp_get_current_mode",
+    "hp_get_current_mode", "hp_set_particles_device", "hp_get_field_device",
+    "hp_get_particles_device",
 )
 
 
@@ -119,6 +120,10 @@ def lib():
             "hp_get_tiling": [_P, _P],
             "hp_autotune": [_P, i32, _P],
             "hp_get_current_mode": [_P, i32, i32, i32, _P, sz],
+            "hp_set_particles_device": [_P, i32, i32, i64, _P, _P, _P, ctypes.c_double,
+                                        ctypes.c_double],
+            "hp_get_field_device": [_P, i32, i32, _P, sz],
+            "hp_get_particles_device": [_P, i32, i64, _P, _P, _P, _P, _P],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -136,6 +141,20 @@ def _check(code):
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(_P)
+
+
+def _dptr(t, dtype, shape):
+    """Device address of a contiguous device tensor (anything with data_ptr(),
+    dtype, shape, is_contiguous()), checked against the expected dtype name
+    and shape; None for None."""
+    if t is None:
+        return None
+    if str(t.dtype).split(".")[-1] != dtype or tuple(t.shape) != tuple(shape):
+        raise ValueError("expected a %s tensor of shape %s, got %s %s" % (dtype, shape, t.dtype,
+                                                                         tuple(t.shape)))
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    return _P(t.data_ptr())
 
 
 def config(n1, n2, dx1, dx2, dt, alpha=0.5, deriv1=0, correct=1, precision="fp32",
@@ -210,6 +229,33 @@ class Sim:
         assert x.shape == (self.dim(run), n) and u.shape == (3, n)
         _check(lib().hp_set_particles(self.h, run, 0, n, _ptr(x), _ptr(u), _ptr(w),
                                       float(q_over_m), float(q)))
+
+    def set_particles_device(self, run, x, u, w, q_over_m=-1.0, q=-1.0):
+        """Particles from float64 device tensors x[dim][n], u[3][n], w[n]."""
+        n = int(w.shape[0])
+        _check(lib().hp_set_particles_device(
+            self.h, run, 0, n, _dptr(x, "float64", (self.dim(run), n)),
+            _dptr(u, "float64", (3, n)), _dptr(w, "float64", (n,)), float(q_over_m), float(q)))
+
+    def _real(self, run):
+        return "float32" if self.cfgs[run].precision == HP_PREC_FP32_FIXED else "float64"
+
+    def field_device(self, run, comp, out):
+        """Real-space field component comp into the device tensor out (shape
+        of the run's grid, float32 in the FP32 form, float64 in the FP64 form);
+        asynchronous on the handle's stream."""
+        _check(lib().hp_get_field_device(self.h, run, int(comp),
+                                         _dptr(out, self._real(run), self.shape(run)),
+                                         int(np.prod(self.shape(run)))))
+
+    def particles_device(self, run, cell=None, off=None, u=None, qw=None, pid=None):
+        """Particle state into device tensors (any may be None): cell int32
+        [dim][n], off [dim][n], u [3][n], qw [n] in the form's real type, pid
+        int32 [n]; asynchronous on the handle's stream."""
+        n, d, r = self.count(run), self.dim(run), self._real(run)
+        _check(lib().hp_get_particles_device(
+            self.h, run, n, _dptr(cell, "int32", (d, n)), _dptr(off, r, (d, n)),
+            _dptr(u, r, (3, n)), _dptr(qw, r, (n,)), _dptr(pid, "int32", (n,))))
 
     def set_fields_mode(self, run, mode, E, B):
         """Quasi-3D: complex E, B [3][n2+1][n1] of azimuthal mode `mode`."""

@@ -266,3 +266,47 @@ def test_fp32_drift_stays_near_fp64_level(hpic):
         sim.close()
         top[prec] = max(logw)
     assert top["fp32"] < top["fp64"] + 1.5, top
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_state_resume_bitexact(hpic, prec):
+    """Checkpoint of a quasi-3D handle (particles, fields of every mode, the
+    FP64 master, the last deposit, the background): the current read right
+    after the restore is the checkpointed handle's, and a fresh handle restored
+    from it and advanced takes the same steps, bit for bit in the FP32 form
+    (64-bit integer deposit).  The FP64 form accumulates its deposit with FP64
+    atomics, whose order varies from run to run, so there the resumed run
+    agrees to rounding."""
+    a, _, g = _setup(hpic, prec, seed=21)
+    a.set_background(0, 2)
+    a.step(3)
+    blob = a.get_state()
+    j_before = [a.current_mode(0, c, m) for m in range(g.nmodes) for c in range(3)]
+    a.step(4)
+    b, _, _ = _setup(hpic, prec, seed=22)
+    b.set_state(blob)
+    for want, m_c in zip(j_before, [(m, c) for m in range(g.nmodes) for c in range(3)]):
+        assert np.array_equal(b.current_mode(0, m_c[1], m_c[0]), want)
+    b.step(4)
+    Ea, Ba = _read_fields(a, g.nmodes)
+    Eb, Bb = _read_fields(b, g.nmodes)
+    pa, pb = a.particles(0), b.particles(0)
+    if prec == "fp32":
+        assert np.array_equal(Ea, Eb) and np.array_equal(Ba, Bb)
+        for k in pa:
+            assert np.array_equal(pa[k], pb[k]), k
+        assert a.diagnostics(0)["gauss_l2"] == b.diagnostics(0)["gauss_l2"]
+    else:
+        scale = max(np.abs(Ea).max(), np.abs(Ba).max())
+        assert max(np.abs(Ea - Eb).max(), np.abs(Ba - Bb).max()) <= 1e-12 * scale
+        assert np.array_equal(pa["id"], pb["id"])
+        for k in ("x", "u"):
+            assert np.abs(pa[k] - pb[k]).max() <= 1e-12 * (1 + np.abs(pa[k]).max())
+    # a blob of the other precision or a truncated one is refused
+    with pytest.raises(hpic.HpError):
+        b.set_state(blob[: len(blob) // 2])
+    other, _, _ = _setup(hpic, "fp32" if prec == "fp64" else "fp64", seed=23)
+    with pytest.raises(hpic.HpError):
+        other.set_state(blob)
+    for s in (a, b, other):
+        s.close()
