@@ -337,6 +337,20 @@ int hp_debug_deposit(hp_sim *sim, int32_t run, int64_t n, const int32_t *cell0,
                      const float *off0, const int32_t *cell1, const float *off1,
                      const float *v3, const float *qw, int64_t *j_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the deposit
+ * of hp_debug_deposit with the same arguments, results and errors, staged in
+ * a region that the library holds on each GPU from load to process end
+ * instead of fresh allocations; it calls no hipMalloc or hipFree.  Limits:
+ * n <= 262144 moves and a grid of at most 262144 cells (else HP_EINVAL); the
+ * region is 16 MiB per GPU.  Every call on a GPU shares that GPU's region
+ * (the last call's contents stay in it; the accumulators are cleared before
+ * each deposit), so calls that overlap on one GPU, from two threads or two
+ * streams, race. */
+int hp_debug_deposit_noalloc(hp_sim *sim, int32_t run, int64_t n, const int32_t *cell0,
+                             const float *off0, const int32_t *cell1, const float *off1,
+                             const float *v3, const float *qw, int64_t *j_out);
+
 /* FP32_FIXED only: out[0] = P, out[1] = inv_wunit, out[2] = c3, out[3] = Q of a
  * run (the fixed-point parameters of the deposit).  3D: out[0] = 0, out[2] = cj,
  * the integer scale of the per-node contributions (j_d = -(dx_d/dt) J_d /

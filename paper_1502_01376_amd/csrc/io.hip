@@ -140,6 +140,20 @@ __global__ void k_unload_particles(const Run<R> *run_dev, int pp, int *cell, R *
   if (id) id[p] = A.id[p];
 }
 
+// p[0..n) = 0 (a kernel rather than a memset, so that a captured graph clears
+// it on every replay).
+__global__ void k_zero_i64(long long *p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+void launch_zero_i64(long long *p, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  const long long blocks = std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zero_i64, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+}
+
 template <class R>
 void launch_scan_particles(const LoadGeom &g, long long n, const double *x, const double *u,
                            const double *w, double q, int *count, unsigned long long *qbits,

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -19,6 +20,20 @@
 #include "hpic_q3d.h"
 
 using namespace hp;
+
+// Staging memory of the entry point that allocates nothing
+// (hp_debug_deposit_noalloc): the moves of at most NOALLOC_MAX_MOVES particles
+// (40 bytes each: two cell pairs, two offset pairs, v3, qw) followed by the
+// 64-bit accumulators of at most NOALLOC_MAX_CELLS cells (3 x 8 bytes each),
+// 16 MiB per GPU, held by every GPU the library runs on until the process
+// ends.  In host code `scratch` is a host-side stand-in for the symbol, not a
+// device address: the address comes from hipGetSymbolAddress (once per device,
+// with that device current) and only that address reaches kernels and copies.
+constexpr size_t NOALLOC_MAX_MOVES = size_t(1) << 18;
+constexpr size_t NOALLOC_MAX_CELLS = size_t(1) << 18;
+constexpr size_t NOALLOC_J_OFFSET = 40 * NOALLOC_MAX_MOVES;
+constexpr size_t NOALLOC_BYTES = NOALLOC_J_OFFSET + 24 * NOALLOC_MAX_CELLS;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
 
 namespace {
 
@@ -39,6 +54,28 @@ int fail(int code, const char *fmt, ...) {
     hipError_t e_ = (x);                                                               \
     if (e_ != hipSuccess) return fail(HP_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
   } while (0)
+
+// Device address of this process's scratch region on device dev (the current
+// device), looked up on the first call for that device.
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[NOALLOC_MAX_DEVICES] = {nullptr};
+
+int scratch_address(int dev, void **out) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(HP_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(HP_EDEVICE, "hipGetSymbolAddress of the scratch region: %s", hipGetErrorString(e));
+    }
+    g_scratch[dev] = ptr;
+  }
+  *out = g_scratch[dev];
+  return HP_OK;
+}
 
 const double PI = 3.14159265358979323846;
 
@@ -146,6 +183,10 @@ struct SimBase {
   virtual int get_particles_device(int, int64_t, int32_t *, void *, void *, void *, int32_t *) {
     return fail(HP_EINVAL, "device-buffer particle reads exist for Cartesian runs only");
   }
+  virtual int debug_deposit_noalloc(int, int64_t, const int32_t *, const float *, const int32_t *,
+                                    const float *, const float *, const float *, int64_t *) {
+    return fail(HP_EINVAL, "the deposit entry point is for 2D Cartesian runs only");
+  }
 };
 
 // A pointer the device can dereference: device or managed memory of this
@@ -206,6 +247,10 @@ class Sim : public SimBase {
 
   int init(const hp_config *cfgs, int nruns) {
     HIPCHK(hipGetDevice(&device_));
+    {
+      int rc;
+      if ((rc = scratch_address(device_, &scratch_))) return rc;
+    }
     {
       // LDS of the row transforms: ncomp components of n1/2 complex values
       // (three per block up to n1 = 4096, one beyond)
@@ -1308,13 +1353,14 @@ class Sim : public SimBase {
     return sort_now();
   }
 
-  int debug_deposit(int run, int64_t n, const int32_t *c0, const float *o0, const int32_t *c1,
-                    const float *o1, const float *v3, const float *qw, int64_t *J) override {
+  // Arguments of the deposit entry points: the 2D quadratic integer deposit of
+  // a run, n moves with cells inside the grid and offsets in [0,1).
+  int check_moves(int run, int64_t n, const int32_t *c0, const float *o0, const int32_t *c1,
+                  const float *o1, const float *v3, const float *qw) {
     if (!FIXED) return fail(HP_EINVAL, "the fixed-point deposit exists only in the FP32 form");
     const Run<R> &d = runs_[run].d;
     if (d.dim != 2 || d.shape != 2)
       return fail(HP_EINVAL, "the deposit test hook is for the 2D quadratic integer deposit");
-    const size_t cells = (size_t)d.n1 * d.n2;
     if (n < 0 || n > 0x7fffffff) return fail(HP_EINVAL, "bad count");
     for (int64_t p = 0; p < n; ++p) {
       if (!(o0[p] >= 0.0f && o0[p] < 1.0f && o0[n + p] >= 0.0f && o0[n + p] < 1.0f &&
@@ -1325,6 +1371,51 @@ class Sim : public SimBase {
         return fail(HP_EINVAL, "cell out of range at %lld", (long long)p);
       if (!std::isfinite(v3[p]) || !std::isfinite(qw[p])) return fail(HP_EINVAL, "non-finite input");
     }
+    return HP_OK;
+  }
+
+  // The deposit of debug_deposit staged in the process's scratch region
+  // instead of fresh allocations: no hipMalloc, no hipFree.  The region is
+  // shared by every call on this GPU (calls that overlap race); the
+  // accumulators are cleared by a kernel before the deposit.
+  int debug_deposit_noalloc(int run, int64_t n, const int32_t *c0, const float *o0,
+                            const int32_t *c1, const float *o1, const float *v3, const float *qw,
+                            int64_t *J) override {
+    int rc;
+    if ((rc = check_moves(run, n, c0, o0, c1, o1, v3, qw))) return rc;
+    const Run<R> &d = runs_[run].d;
+    const size_t cells = (size_t)d.n1 * d.n2;
+    if ((size_t)n > NOALLOC_MAX_MOVES)
+      return fail(HP_EINVAL, "%lld moves exceed the %zu of the no-allocation deposit", (long long)n,
+                  NOALLOC_MAX_MOVES);
+    if (cells > NOALLOC_MAX_CELLS)
+      return fail(HP_EINVAL, "%zu cells exceed the %zu of the no-allocation deposit", cells,
+                  NOALLOC_MAX_CELLS);
+    if (!scratch_) return fail(HP_EDEVICE, "no scratch region on this device");
+    char *base = (char *)scratch_;
+    const size_t M = NOALLOC_MAX_MOVES;
+    int *dc0 = (int *)base, *dc1 = (int *)(base + 8 * M);
+    float *do0 = (float *)(base + 16 * M), *do1 = (float *)(base + 24 * M);
+    float *dv3 = (float *)(base + 32 * M), *dqw = (float *)(base + 36 * M);
+    long long *dJ = (long long *)(base + NOALLOC_J_OFFSET);
+    if (n > 0 && ((rc = h2d(dc0, c0, 2 * n)) || (rc = h2d(dc1, c1, 2 * n)) ||
+                  (rc = h2d(do0, o0, 2 * n)) || (rc = h2d(do1, o1, 2 * n)) ||
+                  (rc = h2d(dv3, v3, n)) || (rc = h2d(dqw, qw, n))))
+      return rc;
+    launch_zero_i64(dJ, (long long)(3 * cells), stream_);
+    launch_debug_deposit(d.n1, d.n2, d.P, d.inv_wunit, d.c3, (int)n, dc0, do0, dc1, do1, dv3, dqw,
+                         dJ, d_err_, stream_);
+    HIPCHK(hipGetLastError());
+    if ((rc = d2h((long long *)J, dJ, 3 * cells))) return rc;
+    return sync();
+  }
+
+  int debug_deposit(int run, int64_t n, const int32_t *c0, const float *o0, const int32_t *c1,
+                    const float *o1, const float *v3, const float *qw, int64_t *J) override {
+    int rcv;
+    if ((rcv = check_moves(run, n, c0, o0, c1, o1, v3, qw))) return rcv;
+    const Run<R> &d = runs_[run].d;
+    const size_t cells = (size_t)d.n1 * d.n2;
     int *dc0, *dc1;
     float *do0, *do1, *dv3, *dqw;
     long long *dJ;
@@ -1334,14 +1425,17 @@ class Sim : public SimBase {
         (rc = alloc(&do1, 2 * m)) || (rc = alloc(&dv3, m)) || (rc = alloc(&dqw, m)) ||
         (rc = alloc(&dJ, 3 * cells)))
       return rc;
-    if (n > 0 && ((rc = h2d(dc0, c0, 2 * n)) || (rc = h2d(dc1, c1, 2 * n)) ||
-                  (rc = h2d(do0, o0, 2 * n)) || (rc = h2d(do1, o1, 2 * n)) ||
-                  (rc = h2d(dv3, v3, n)) || (rc = h2d(dqw, qw, n))))
-      return rc;
-    HIPCHK(hipMemsetAsync(dJ, 0, sizeof(long long) * 3 * cells, stream_));
-    launch_debug_deposit(d.n1, d.n2, d.P, d.inv_wunit, d.c3, (int)n, dc0, do0, dc1, do1, dv3, dqw,
-                         dJ, d_err_, stream_);
-    rc = d2h((long long *)J, dJ, 3 * cells);
+    if (!(n > 0 && ((rc = h2d(dc0, c0, 2 * n)) || (rc = h2d(dc1, c1, 2 * n)) ||
+                    (rc = h2d(do0, o0, 2 * n)) || (rc = h2d(do1, o1, 2 * n)) ||
+                    (rc = h2d(dv3, v3, n)) || (rc = h2d(dqw, qw, n))))) {
+      if (hipMemsetAsync(dJ, 0, sizeof(long long) * 3 * cells, stream_) != hipSuccess) {
+        rc = fail(HP_EDEVICE, "clearing the accumulators failed");
+      } else {
+        launch_debug_deposit(d.n1, d.n2, d.P, d.inv_wunit, d.c3, (int)n, dc0, do0, dc1, do1, dv3,
+                             dqw, dJ, d_err_, stream_);
+        rc = d2h((long long *)J, dJ, 3 * cells);
+      }
+    }
     release(dc0); release(dc1); release(do0); release(do1); release(dv3); release(dqw); release(dJ);
     if (rc) return rc;
     return sync();
@@ -1666,6 +1760,7 @@ class Sim : public SimBase {
   Item *d_chunks_ = nullptr, *d_tiles_ = nullptr, *d_perrun_ = nullptr;
   Item *d_rows_ = nullptr, *d_grps_ = nullptr, *d_upd_ = nullptr;
   int n_chunks_ = 0, n_tiles_ = 0, n_rows_ = 0, n_grps_ = 0, n_upd_ = 0;
+  void *scratch_ = nullptr;  // device address of the process's scratch region (this device)
   int pp_ = 0;             // particle buffer parity
   int n_perrun_ = 0;
   int sort_interval_ = DEFAULT_SORT_INTERVAL, since_sort_ = 0;
@@ -2757,6 +2852,16 @@ int hp_debug_deposit(hp_sim *sim, int32_t run, int64_t n, const int32_t *cell0, 
     if (n > 0 && (!cell0 || !off0 || !cell1 || !off1 || !v3 || !qw)) return fail(HP_EINVAL, "null input");
     if (!j_out) return fail(HP_EINVAL, "null output");
     return sim->impl->debug_deposit(run, n, cell0, off0, cell1, off1, v3, qw, j_out);
+  });
+}
+
+int hp_debug_deposit_noalloc(hp_sim *sim, int32_t run, int64_t n, const int32_t *cell0,
+                             const float *off0, const int32_t *cell1, const float *off1,
+                             const float *v3, const float *qw, int64_t *j_out) {
+  return with_run(sim, run, [&] {
+    if (n > 0 && (!cell0 || !off0 || !cell1 || !off1 || !v3 || !qw)) return fail(HP_EINVAL, "null input");
+    if (!j_out) return fail(HP_EINVAL, "null output");
+    return sim->impl->debug_deposit_noalloc(run, n, cell0, off0, cell1, off1, v3, qw, j_out);
   });
 }
 

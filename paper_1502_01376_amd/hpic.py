@@ -29,7 +29,7 @@ ABI = (
     "hp_debug_deposit", "hp_get_fixed_params", "hp_profile", "hp_get_kernel_times",
     "hp_get_push_stats", "hp_use_graphs", "hp_set_tiling", "hp_get_tiling", "hp_autotune",
     "hp_get_current_mode", "hp_set_particles_device", "hp_get_field_device",
-    "hp_get_particles_device",
+    "hp_get_particles_device", "hp_debug_deposit_noalloc",
 )
 
 
@@ -124,6 +124,7 @@ def lib():
                                         ctypes.c_double],
             "hp_get_field_device": [_P, i32, i32, _P, sz],
             "hp_get_particles_device": [_P, i32, i64, _P, _P, _P, _P, _P],
+            "hp_debug_deposit_noalloc": [_P, i32, i64, _P, _P, _P, _P, _P, _P, _P],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -386,7 +387,9 @@ class Sim:
         buf = np.frombuffer(blob, dtype=np.uint8).copy()
         _check(lib().hp_set_state(self.h, _ptr(buf), buf.size))
 
-    def debug_deposit(self, run, cell0, off0, cell1, off1, v3, qw):
+    def debug_deposit(self, run, cell0, off0, cell1, off1, v3, qw, noalloc=False):
+        """Deposit alone on given moves (hp_debug_deposit, or with noalloc
+        hp_debug_deposit_noalloc, which stages in the library's fixed region)."""
         n2, n1 = self.shape(run)
         c0 = np.ascontiguousarray(cell0, dtype=np.int32)
         c1 = np.ascontiguousarray(cell1, dtype=np.int32)
@@ -397,8 +400,9 @@ class Sim:
         n = qw.size
         assert c0.shape == (2, n) and o0.shape == (2, n) and c1.shape == (2, n) and o1.shape == (2, n)
         J = np.empty((3, n2, n1), dtype=np.int64)
-        _check(lib().hp_debug_deposit(self.h, run, n, _ptr(c0), _ptr(o0), _ptr(c1), _ptr(o1),
-                                      _ptr(v3), _ptr(qw), _ptr(J)))
+        fn = lib().hp_debug_deposit_noalloc if noalloc else lib().hp_debug_deposit
+        _check(fn(self.h, run, n, _ptr(c0), _ptr(o0), _ptr(c1), _ptr(o1), _ptr(v3), _ptr(qw),
+                  _ptr(J)))
         return J
 
     def fixed_params(self, run):
