@@ -66,10 +66,32 @@ def parse():
     return ap.parse_args()
 
 
-def timed_steps(torch, sim, warmup, steps):
-    """Wall time of `steps` steps after `warmup` untimed ones, synchronised on
-    both sides."""
+def align_to_sort(sim):
+    """Untimed steps after which the next step starts with a tile sort: a
+    timed window of n steps then holds ceil(n / K) sorts for the sort interval
+    K, however n compares with K (the sort's cost is counted, never skipped).
+    Returns K (0 for handles without a tile sort)."""
+    try:
+        t = sim.tiling()
+    except Exception:
+        return 0
+    K = int(t["sort_interval"])
+    if K <= 0:
+        return 0
+    sim.set_tiling(t["tile"][0], t["tile"][1], K)  # sorts now
+    # K steps reach the next sort; two more blocks of a sort and K steps
+    # capture the step graphs of both particle buffers outside the window
+    sim.step(3 * K)
+    return K
+
+
+def timed_steps(torch, sim, warmup, steps, align=True):
+    """Wall time of `steps` steps after `warmup` untimed ones (and, with
+    align, the steps that bring the next tile sort to the window's first
+    step), synchronised on both sides."""
     sim.step(warmup)
+    if align:
+        align_to_sort(sim)
     sim.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -92,6 +114,9 @@ def run_form(hpic, torch, ds, precision, warmup, steps, profile=False, tune_step
         sim.set_tiling(*tiling)
     elif tune_steps > 0:
         sim.autotune(tune_steps)
+    # the autotuner's record (candidates, steps, its timing) before the
+    # re-sort that aligns the window resets it
+    sim.tuning = sim.tiling()
     t = timed_steps(torch, sim, warmup, steps)
     kt = None
     if profile:
@@ -138,24 +163,50 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def cpu_baseline(d, min_seconds=10.0, max_steps=10):
-    """FP64 oracle on the host: whole steps of the same workload until about
-    min_seconds of CPU work (at most max_steps)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(d, all_core_seconds=8.0, one_thread_steps=1):
+    """FP64 oracle on the host, whole steps of the same workload: with every
+    host core (OpenMP; its loops give the same bits for any thread count) for
+    about all_core_seconds, then one thread for one_thread_steps."""
     import oracle
     g = oracle.grid2(d["n"][0], d["n"][1], d["dx"][0], d["dx"][1], d["dt"], alpha=d["alpha"],
                      jbg=d["jbg"])
-    st = oracle.State2(g, d["qm"], d["xi"][0], d["xi"][1], d["u"], d["q"] * d["w"],
-                       E=d["E"], B=d["B"])
     npart = d["w"].size
-    steps = 0
-    t0 = time.perf_counter()
-    while steps < max_steps and (time.perf_counter() - t0) < min_seconds:
-        st.step(1)
-        steps += 1
-    dt = time.perf_counter() - t0
-    return {"value": npart * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "%d full steps of the same workload (%d particles, %dx%d grid), "
-                      "single-threaded FP64 C, %.1f s" % (steps, npart, d["n"][0], d["n"][1], dt)}
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    threads = min(ncores, omp) if omp > 0 else ncores
+
+    def run(nthreads, min_s, max_steps):
+        oracle.set_threads(nthreads)
+        st = oracle.State2(g, d["qm"], d["xi"][0], d["xi"][1], d["u"], d["q"] * d["w"],
+                           E=d["E"], B=d["B"])
+        steps, t0 = 0, time.perf_counter()
+        while steps < max_steps and (steps == 0 or time.perf_counter() - t0 < min_s):
+            st.step(1)
+            steps += 1
+        return steps, time.perf_counter() - t0
+
+    s_all, t_all = run(threads, all_core_seconds, 10)
+    s_one, t_one = run(1, 0.0, one_thread_steps)
+    oracle.set_threads(threads)
+    return {"value": npart * s_all / t_all, "unit": "particle-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d full steps of the same workload (%d particles, %dx%d grid), FP64 C "
+                      "with OpenMP on %d threads, %.1f s" % (s_all, npart, d["n"][0], d["n"][1],
+                                                               threads, t_all),
+            "single_thread": {"value": npart * s_one / t_one, "cores": 1,
+                              "sample": "%d full step(s), one thread, %.1f s" % (s_one, t_one)},
+            "host_cpus": ncores, "cpu_model": cpu_model()}
 
 
 def scan_leg(hpic, torch, W, steps, tune_steps):
@@ -169,7 +220,7 @@ def scan_leg(hpic, torch, W, steps, tune_steps):
     warm = 16
     a, t32, _ = run_form(hpic, torch, ds, "fp32", warm, steps, tune_steps=tune_steps)
     b, t64, _ = run_form(hpic, torch, ds, "fp64", warm, steps, tune_steps=tune_steps)
-    tiling = a.tiling()
+    tiling = a.tuning
     errs = {"E": [], "B": [], "J": [], "gauss": []}
     for r in range(len(ds)):
         Ea, Ba = a.fields(r)
@@ -208,7 +259,7 @@ def d3_leg(hpic, torch, W, steps, tune_steps):
     a, t32, kt = run_form(hpic, torch, [d], "fp32", warm, steps, profile=True, tune_steps=tune)
     kt.pop("profiled_wall_s")
     push_stats = kt.pop("push_stats")
-    tiling = a.tiling()
+    tiling = a.tuning
     # the FP64 form takes the same steps, profiled pass included, so the two
     # are compared at the same time
     b, t64, _ = run_form(hpic, torch, [d], "fp64", warm, steps, profile=True, tune_steps=tune)
@@ -401,7 +452,7 @@ def main():
     tiling = [int(v) for v in args.tiling.split(",")] if args.tiling else None
     sim32, t32, kt = run_form(hpic, torch, [d], "fp32", args.warmup, args.steps, profile=True,
                               tune_steps=args.tune_steps, tiling=tiling)
-    chosen = sim32.tiling()
+    chosen = sim32.tuning
     profiled_wall = kt.pop("profiled_wall_s")
     value = npart * args.steps / t32
     ms_step = 1e3 * t32 / args.steps
@@ -432,6 +483,10 @@ def main():
                    "dx": list(d["dx"][:2]), "dt": d["dt"], "particles": npart,
                    "particles_per_cell": 8, "gamma": 20.0, "laser_a0": 2.0,
                    "filter_frac": d["alpha"], "deposit_accumulator": "int64 fixed point",
+                   "field_state": "FP64 k-space master of E and B, updated in FP64 (both "
+                                  "forms); FP32 real-space fields, push and deposit weights",
+                   "sort_interval": chosen["sort_interval"],
+                   "sorts_in_timed_region": -(-args.steps // max(chosen["sort_interval"], 1)),
                    "parallelism": "single GPU"},
         "kernels": kernels,
         "tiling": chosen,

@@ -70,6 +70,8 @@ def lib():
         G3 = ctypes.POINTER(Grid3)
         GQ = ctypes.POINTER(GridQ)
         sig = {
+            "or_set_threads": (None, [ctypes.c_int32]),
+            "or_get_threads": (ctypes.c_int32, []),
             "or_fft": (ctypes.c_int, [ctypes.c_int32, _D, _D, ctypes.c_int32]),
             "or_rfft_rows": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _D, _D, _D]),
             "or_irfft_rows": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _D, _D, _D]),
@@ -116,6 +118,15 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops (results do not depend on it)."""
+    lib().or_set_threads(int(n))
+
+
+def threads():
+    return int(lib().or_get_threads())
 
 
 def _p(a, kind=_D):

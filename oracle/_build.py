@@ -2,7 +2,9 @@
 
 The oracle is test infrastructure: building it is part of the build check, but
 nothing on the product path loads it.  Compiled with floating-point contraction
-off so that every FP32/FP64 operation rounds once, in source order.
+off so that every FP32/FP64 operation rounds once, in source order, and with
+OpenMP: its parallel loops give the same bits for any number of threads
+(OMP_NUM_THREADS).
 """
 import os
 import subprocess
@@ -15,7 +17,7 @@ LIB = os.path.join(HERE, "libhpic_oracle.so")
 def build(verbose=False):
     cmd = [
         "gcc", "-O2", "-std=c11", "-fPIC", "-shared",
-        "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-function",
+        "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-Wall", "-Wno-unused-function",
         SRC, "-o", LIB + ".tmp", "-lm",
     ]
     if verbose:

@@ -41,6 +41,9 @@
 
 #include <complex.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -88,39 +91,64 @@ int or_fft(int32_t n, double *re, double *im, int32_t sign) {
   return 0;
 }
 
+/* Threads of the OpenMP loops (1 without OpenMP); results do not depend on it. */
+void or_set_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+int32_t or_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 int or_rfft_rows(int32_t n1, int32_t nrows, const double *f, double *Fre, double *Fim) {
   if (!is_pow2(n1) || n1 < 2) return -1;
   int32_t nk = n1 / 2 + 1;
-  double *re = malloc(sizeof(double) * n1), *im = malloc(sizeof(double) * n1);
-  for (int32_t r = 0; r < nrows; ++r) {
-    for (int32_t i = 0; i < n1; ++i) { re[i] = f[(int64_t)r * n1 + i]; im[i] = 0.0; }
-    or_fft(n1, re, im, -1);
-    for (int32_t k = 0; k < nk; ++k) {
-      Fre[(int64_t)r * nk + k] = re[k];
-      Fim[(int64_t)r * nk + k] = im[k];
+  /* rows are independent: with OpenMP each thread transforms its own rows */
+#pragma omp parallel
+  {
+    double *re = malloc(sizeof(double) * n1), *im = malloc(sizeof(double) * n1);
+#pragma omp for schedule(static)
+    for (int32_t r = 0; r < nrows; ++r) {
+      for (int32_t i = 0; i < n1; ++i) { re[i] = f[(int64_t)r * n1 + i]; im[i] = 0.0; }
+      or_fft(n1, re, im, -1);
+      for (int32_t k = 0; k < nk; ++k) {
+        Fre[(int64_t)r * nk + k] = re[k];
+        Fim[(int64_t)r * nk + k] = im[k];
+      }
     }
+    free(re); free(im);
   }
-  free(re); free(im);
   return 0;
 }
 
 int or_irfft_rows(int32_t n1, int32_t nrows, const double *Fre, const double *Fim, double *f) {
   if (!is_pow2(n1) || n1 < 2) return -1;
   int32_t nk = n1 / 2 + 1;
-  double *re = malloc(sizeof(double) * n1), *im = malloc(sizeof(double) * n1);
-  for (int32_t r = 0; r < nrows; ++r) {
-    for (int32_t k = 0; k < nk; ++k) {
-      re[k] = Fre[(int64_t)r * nk + k];
-      im[k] = Fim[(int64_t)r * nk + k];
+#pragma omp parallel
+  {
+    double *re = malloc(sizeof(double) * n1), *im = malloc(sizeof(double) * n1);
+#pragma omp for schedule(static)
+    for (int32_t r = 0; r < nrows; ++r) {
+      for (int32_t k = 0; k < nk; ++k) {
+        re[k] = Fre[(int64_t)r * nk + k];
+        im[k] = Fim[(int64_t)r * nk + k];
+      }
+      /* the self-conjugate bins of a real row have no imaginary part */
+      im[0] = 0.0;
+      im[n1 / 2] = 0.0;
+      for (int32_t k = nk; k < n1; ++k) { re[k] = re[n1 - k]; im[k] = -im[n1 - k]; }
+      or_fft(n1, re, im, +1);
+      for (int32_t i = 0; i < n1; ++i) f[(int64_t)r * n1 + i] = re[i] / (double)n1;
     }
-    /* the self-conjugate bins of a real row have no imaginary part */
-    im[0] = 0.0;
-    im[n1 / 2] = 0.0;
-    for (int32_t k = nk; k < n1; ++k) { re[k] = re[n1 - k]; im[k] = -im[n1 - k]; }
-    or_fft(n1, re, im, +1);
-    for (int32_t i = 0; i < n1; ++i) f[(int64_t)r * n1 + i] = re[i] / (double)n1;
+    free(re); free(im);
   }
-  free(re); free(im);
   return 0;
 }
 
@@ -197,6 +225,8 @@ static double interp2(const or_grid2 *g, const double *F, double s1, double s2, 
 void or_gather2(const or_grid2 *g, const double *E, const double *B, int64_t np,
                 const double *xi1, const double *xi2, double *Ep, double *Bp) {
   int64_t cells = (int64_t)g->n1 * g->n2;
+  /* particles are independent: with OpenMP the loop is split over threads */
+#pragma omp parallel for schedule(static)
   for (int64_t p = 0; p < np; ++p) {
     for (int c = 0; c < 3; ++c) {
       Ep[c * np + p] = interp2(g, E + c * cells, STAG_E[c][0], STAG_E[c][1], xi1[p], xi2[p]);
@@ -212,6 +242,7 @@ void or_gather2(const or_grid2 *g, const double *E, const double *B, int64_t np,
 void or_boris(int64_t np, double qm, double dt, const double *Ep, const double *Bp,
               double *u1, double *u2, double *u3) {
   double h = 0.5 * qm * dt;
+#pragma omp parallel for schedule(static)
   for (int64_t p = 0; p < np; ++p) {
     double e[3] = {h * Ep[p], h * Ep[np + p], h * Ep[2 * np + p]};
     double um[3] = {u1[p] + e[0], u2[p] + e[1], u3[p] + e[2]};
@@ -241,45 +272,69 @@ int or_deposit2(const or_grid2 *g, int64_t np, const double *xa1, const double *
   int64_t cells = (int64_t)g->n1 * g->n2;
   double *J1 = J, *J2 = J + cells, *J3 = J + 2 * cells;
   int status = 0, l = shape2(g);
-  for (int64_t p = 0; p < np; ++p) {
-    if (fabs(xb1[p] - xa1[p]) >= 1.0 || fabs(xb2[p] - xa2[p]) >= 1.0) { status = -1; continue; }
-    /* a common window per coordinate holds the old and new stencils: the
-     * nodes within two cells of either position (W = 6 covers the quadratic
-     * and the cubic shape; the spline is zero beyond its support) */
-    int64_t b1 = (int64_t)floor(fmin(xa1[p], xb1[p])) - 2;
-    int64_t b2 = (int64_t)floor(fmin(xa2[p], xb2[p])) - 2;
-    double S0x[6], S1x[6], S0y[6], S1y[6];
-    for (int a = 0; a < 6; ++a) {
-      S0x[a] = spline_n(l, xa1[p] - (double)(b1 + a));
-      S1x[a] = spline_n(l, xb1[p] - (double)(b1 + a));
-      S0y[a] = spline_n(l, xa2[p] - (double)(b2 + a));
-      S1y[a] = spline_n(l, xb2[p] - (double)(b2 + a));
+  /* With OpenMP each thread owns a band of rows [r0, r1) of J and walks all
+   * particles in order, adding only into its rows: every node receives its
+   * contributions in particle order, as in one thread, so the result does not
+   * depend on the number of threads. */
+#pragma omp parallel reduction(min : status)
+  {
+    int32_t r0 = 0, r1 = g->n2;
+#ifdef _OPENMP
+    {
+      int nt = omp_get_num_threads(), t = omp_get_thread_num();
+      r0 = (int32_t)((int64_t)g->n2 * t / nt);
+      r1 = (int32_t)((int64_t)g->n2 * (t + 1) / nt);
     }
-    double f1 = -qw[p] * g->dx1 / g->dt, f2 = -qw[p] * g->dx2 / g->dt;
-    /* j1: running sum along x1 of the W1 weights (continuity, Eq. (23)) */
-    for (int b = 0; b < 6; ++b) {
-      double acc = 0.0;
-      for (int a = 0; a < 6; ++a) {
-        double W1 = (S1x[a] - S0x[a]) * 0.5 * (S0y[b] + S1y[b]);
-        acc += f1 * W1;
-        J1[(int64_t)wrapi(b2 + b, g->n2) * g->n1 + wrapi(b1 + a, g->n1)] += acc;
-      }
-    }
-    /* j2: running sum along x2 of the W2 weights */
-    for (int a = 0; a < 6; ++a) {
-      double acc = 0.0;
+#endif
+    for (int64_t p = 0; p < np; ++p) {
+      if (fabs(xb1[p] - xa1[p]) >= 1.0 || fabs(xb2[p] - xa2[p]) >= 1.0) { status = -1; continue; }
+      /* a common window per coordinate holds the old and new stencils: the
+       * nodes within two cells of either position (W = 6 covers the quadratic
+       * and the cubic shape; the spline is zero beyond its support) */
+      int64_t b1 = (int64_t)floor(fmin(xa1[p], xb1[p])) - 2;
+      int64_t b2 = (int64_t)floor(fmin(xa2[p], xb2[p])) - 2;
+      int row[6], mine = 0;
       for (int b = 0; b < 6; ++b) {
-        double W2 = (S1y[b] - S0y[b]) * 0.5 * (S0x[a] + S1x[a]);
-        acc += f2 * W2;
-        J2[(int64_t)wrapi(b2 + b, g->n2) * g->n1 + wrapi(b1 + a, g->n1)] += acc;
+        row[b] = wrapi(b2 + b, g->n2);
+        mine |= (row[b] >= r0 && row[b] < r1);
       }
-    }
-    /* j3: out-of-plane current with the time-averaged shape W3 */
-    for (int b = 0; b < 6; ++b) {
+      if (!mine) continue;
+      double S0x[6], S1x[6], S0y[6], S1y[6];
       for (int a = 0; a < 6; ++a) {
-        double W3 = S0x[a] * S0y[b] / 3.0 + S1x[a] * S0y[b] / 6.0 + S0x[a] * S1y[b] / 6.0 +
-                    S1x[a] * S1y[b] / 3.0;
-        J3[(int64_t)wrapi(b2 + b, g->n2) * g->n1 + wrapi(b1 + a, g->n1)] += qw[p] * v3[p] * W3;
+        S0x[a] = spline_n(l, xa1[p] - (double)(b1 + a));
+        S1x[a] = spline_n(l, xb1[p] - (double)(b1 + a));
+        S0y[a] = spline_n(l, xa2[p] - (double)(b2 + a));
+        S1y[a] = spline_n(l, xb2[p] - (double)(b2 + a));
+      }
+      double f1 = -qw[p] * g->dx1 / g->dt, f2 = -qw[p] * g->dx2 / g->dt;
+      /* j1: running sum along x1 of the W1 weights (continuity, Eq. (23)) */
+      for (int b = 0; b < 6; ++b) {
+        if (row[b] < r0 || row[b] >= r1) continue;
+        double acc = 0.0;
+        for (int a = 0; a < 6; ++a) {
+          double W1 = (S1x[a] - S0x[a]) * 0.5 * (S0y[b] + S1y[b]);
+          acc += f1 * W1;
+          J1[(int64_t)row[b] * g->n1 + wrapi(b1 + a, g->n1)] += acc;
+        }
+      }
+      /* j2: running sum along x2 of the W2 weights */
+      for (int a = 0; a < 6; ++a) {
+        double acc = 0.0;
+        for (int b = 0; b < 6; ++b) {
+          double W2 = (S1y[b] - S0y[b]) * 0.5 * (S0x[a] + S1x[a]);
+          acc += f2 * W2;
+          if (row[b] >= r0 && row[b] < r1)
+            J2[(int64_t)row[b] * g->n1 + wrapi(b1 + a, g->n1)] += acc;
+        }
+      }
+      /* j3: out-of-plane current with the time-averaged shape W3 */
+      for (int b = 0; b < 6; ++b) {
+        if (row[b] < r0 || row[b] >= r1) continue;
+        for (int a = 0; a < 6; ++a) {
+          double W3 = S0x[a] * S0y[b] / 3.0 + S1x[a] * S0y[b] / 6.0 + S0x[a] * S1y[b] / 6.0 +
+                      S1x[a] * S1y[b] / 3.0;
+          J3[(int64_t)row[b] * g->n1 + wrapi(b1 + a, g->n1)] += qw[p] * v3[p] * W3;
+        }
       }
     }
   }
@@ -506,6 +561,7 @@ int or_step2(const or_grid2 *g, double qm, int64_t np, double *xi1, double *xi2,
   double *v3 = malloc(sizeof(double) * (np > 0 ? np : 1));
   or_gather2(g, E, B, np, xi1, xi2, Ep, Bp);
   or_boris(np, qm, g->dt, Ep, Bp, u1, u2, u3);
+#pragma omp parallel for schedule(static)
   for (int64_t p = 0; p < np; ++p) {
     double gam = sqrt(1.0 + u1[p] * u1[p] + u2[p] * u2[p] + u3[p] * u3[p]);
     xn1[p] = xi1[p] + g->dt * (u1[p] / gam) / g->dx1;
@@ -516,6 +572,7 @@ int or_step2(const or_grid2 *g, double qm, int64_t np, double *xi1, double *xi2,
   int status = or_deposit2(g, np, xi1, xi2, xn1, xn2, v3, qw, J);
   if (ant) or_antenna2(g, ant, t + 0.5 * g->dt, J);
   if (or_field_update2(g, E, B, J) != 0) status = -1;
+#pragma omp parallel for schedule(static)
   for (int64_t p = 0; p < np; ++p) {
     xi1[p] = fmod(xn1[p], (double)g->n1);
     if (xi1[p] < 0.0) xi1[p] += (double)g->n1;
@@ -914,6 +971,7 @@ int or_step3(const or_grid3 *g, double qm, int64_t np, double *xi1, double *xi2,
          *xn3 = malloc(sizeof(double) * m);
   or_gather3(g, E, B, np, xi1, xi2, xi3, Ep, Bp);
   or_boris(np, qm, g->dt, Ep, Bp, u1, u2, u3);
+#pragma omp parallel for schedule(static)
   for (int64_t p = 0; p < np; ++p) {
     double gam = sqrt(1.0 + u1[p] * u1[p] + u2[p] * u2[p] + u3[p] * u3[p]);
     xn1[p] = xi1[p] + g->dt * (u1[p] / gam) / g->dx1;

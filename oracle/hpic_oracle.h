@@ -62,6 +62,11 @@ int or_fft(int32_t n, double *re, double *im, int32_t sign);
 /* Forward transform of nrows real rows of length n1 along x1: F[row][kappa]
  * for kappa = 0..n1/2 (the Nyquist bin is kept).  Inverse: rebuilds the full
  * spectrum by Hermitian symmetry and returns the real rows including 1/n1. */
+/* Threads of the oracle's OpenMP loops (particles, rows, row bands of the
+ * deposit): results are the same bits for any count. */
+void or_set_threads(int32_t n);
+int32_t or_get_threads(void);
+
 int or_rfft_rows(int32_t n1, int32_t nrows, const double *f, double *Fre, double *Fim);
 int or_irfft_rows(int32_t n1, int32_t nrows, const double *Fre, const double *Fim, double *f);
 

@@ -446,7 +446,7 @@ class Sim : public SimBase {
     if ((rc = upload_jfac(run))) return rc;
     if ((rc = rebuild_sort_items())) return rc;
     if ((rc = upload_runs())) return rc;
-    return sort_now();
+    return sort_now(true);
   }
 
   // Particles from FP64 arrays in device memory: the conversion of
@@ -507,7 +507,7 @@ class Sim : public SimBase {
     if ((rc = upload_jfac(run))) return rc;
     if ((rc = rebuild_sort_items())) return rc;
     if ((rc = upload_runs())) return rc;
-    return sort_now();
+    return sort_now(true);
   }
 
   // The real-space field of one component (the copy the next gather reads) into
@@ -801,7 +801,7 @@ class Sim : public SimBase {
     if ((rc = sync())) return rc;
     if ((rc = make_tiles(t1, t2)) || (rc = upload_runs())) return rc;
     sort_interval_ = K;
-    return sort_now();
+    return sort_now(false);
   }
 
   int get_tiling(hp_tune *out) override {
@@ -1350,7 +1350,7 @@ class Sim : public SimBase {
     }
     if ((rc = rebuild_sort_items())) return rc;
     if ((rc = upload_runs())) return rc;
-    return sort_now();
+    return sort_now(false);
   }
 
   // Arguments of the deposit entry points: the 2D quadratic integer deposit of
@@ -1636,8 +1636,11 @@ class Sim : public SimBase {
     return HP_OK;
   }
   // Sort the particles of every run by tile now (into the other buffer).
-  int sort_now() {
-    Launch<R>::sort(d_runs_, d_chunks_, n_chunks_, d_perrun_, (int)runs_.size(), pp_, true,
+  // scramble: the particles arrive in cell order (just loaded), so spread each
+  // tile's slots over its cells (see k_sort_scatter); otherwise keep the
+  // arrival order, already spread.
+  int sort_now(bool scramble) {
+    Launch<R>::sort(d_runs_, d_chunks_, n_chunks_, d_perrun_, (int)runs_.size(), pp_, scramble,
                     stream_);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream_));
