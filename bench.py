@@ -28,6 +28,11 @@ import numpy as np  # noqa: E402
 # three 64-bit current accumulators read and written once (48 B).
 BYTES_PER_PARTICLE = 52
 BYTES_PER_CELL = 72
+# Quasi-3D push+deposit: 76 B per particle (read 40: cell, offsets, momenta,
+# charge; write 36) and 144 B per node of each mode (48 B of complex FP32
+# fields read, 96 B of complex int64 current read-modify-write).
+Q3D_BYTES_PER_PARTICLE = 76
+Q3D_BYTES_PER_MODE_NODE = 144
 HBM_PEAK_GBS = 8000.0
 
 
@@ -39,7 +44,11 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=-1,
                     help="steps of the FP64 form timed beside the FP32 form (-1: as --steps, 0: skip)")
     ap.add_argument("--err-steps", type=int, default=1000,
-                    help="steps over which the FP32 form is compared with the FP64 form")
+                    help="steps over which the FP32 form of the benchmark workload is compared "
+                         "with the FP64 form and its controls (0: skip)")
+    ap.add_argument("--precision", type=int, default=1,
+                    help="compare the FP32 form with the FP64 form and the FP64 controls on the "
+                         "3D, quasi-3D and scan legs too, at their own step counts")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -54,7 +63,7 @@ def parse():
     ap.add_argument("--shape-steps", type=int, default=200,
                     help="steps of the benchmark workload with the energy-conserving gather "
                          "and with the cubic shape (0: skip)")
-    ap.add_argument("--q3d-steps", type=int, default=200,
+    ap.add_argument("--q3d-steps", type=int, default=500,
                     help="steps of the quasi-3D 4096x256 three-mode PIC leg (0: skip)")
     ap.add_argument("--lwfa-steps", type=int, default=6400,
                     help="steps of the Table 2 boosted-frame laser wakefield run (8192x512, "
@@ -112,11 +121,8 @@ def run_form(hpic, torch, ds, precision, warmup, steps, profile=False, tune_step
     sim = hpic.from_workloads(ds, precision, stream=torch.cuda.current_stream(), **cfg_kw)
     if tiling:
         sim.set_tiling(*tiling)
-    elif tune_steps > 0:
-        sim.autotune(tune_steps)
-    # the autotuner's record (candidates, steps, its timing) before the
-    # re-sort that aligns the window resets it
-    sim.tuning = sim.tiling()
+    # the autotuner's record: candidates tried, steps, the choice's timing
+    sim.tuning = sim.autotune(tune_steps) if not tiling and tune_steps > 0 else sim.tiling()
     t = timed_steps(torch, sim, warmup, steps)
     kt = None
     if profile:
@@ -161,6 +167,106 @@ def measured_traffic():
 
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# Error of the FP32 form at the configurations' own lengths, beside two
+# controls that separate round-off amplified by the dynamics from a defect:
+# the FP64 form started from positions one FP64 ulp away (ulp64), and the
+# FP64 form started from the FP32 form's initial state, i.e. the inputs
+# rounded to FP32 offsets, momenta and charges (fp32_init).  All against the
+# FP64 form from the exact inputs, at checkpoints along the run.
+CONTROLS = ("fp32", "fp64_ulp", "fp64_fp32_init")
+
+
+def _ulp_positions(d):
+    return dict(d, xi=np.nextafter(d["xi"], np.inf))
+
+
+def _fp32_init(sim, ds):
+    out = []
+    for r, d in enumerate(ds):
+        p = sim.particles(r)
+        xi = np.stack([p["x"][k] / d["dx"][k] for k in range(p["x"].shape[0])])
+        out.append(dict(d, xi=xi, u=p["u"], w=p["w"]))
+    return out
+
+
+def _cart_state(sim, runs):
+    out = []
+    for r in range(runs):
+        E, B = sim.fields(r)
+        out.append((E, B, np.stack([sim.current(r, c) for c in range(3)])))
+    return out
+
+
+def _errs(st, ref):
+    return [{k: rel_l2(a[i], b[i]) for i, k in enumerate("EBJ")} for a, b in zip(st, ref)]
+
+
+def _checkpoint_loop(sims, read, steps, checkpoints):
+    """Advance every handle of `sims` (fp64 is the reference) to each
+    checkpoint and record the per-run errors of the others against it."""
+    cps = sorted({c for c in checkpoints if 0 < c < steps} | {steps})
+    hist = {k: [] for k in CONTROLS}
+    done = 0
+    for cp in cps:
+        for sim in sims.values():
+            sim.step(cp - done)
+        done = cp
+        ref = read(sims["fp64"])
+        for k in CONTROLS:
+            hist[k].append(_errs(read(sims[k]), ref))
+    diag = [sims["fp32"].diagnostics(r) for r in range(len(hist["fp32"][-1]))]
+    for sim in sims.values():
+        sim.close()
+    return cps, hist, diag
+
+
+def _single_run_table(cps, hist, diag):
+    """Error histories of a one-run handle: per control and component, the
+    relative L2 error at each checkpoint; the FP32 form's Gauss residual."""
+    out = {"checkpoints": cps}
+    for k in CONTROLS:
+        out[k] = {c: [float("%.4g" % h[0][c]) for h in hist[k]] for c in "EBJ"}
+    out["gauss_rel_l2_fp32"] = diag[0]["gauss_l2"] / max(diag[0]["gauss_ref_l2"], 1e-300)
+    return out
+
+
+def precision_cartesian(hpic, ds, steps, checkpoints):
+    """FP32 form and the two FP64 controls against the FP64 form on the
+    Cartesian workloads `ds` (one handle each, all runs together)."""
+    sims = {"fp32": hpic.from_workloads(ds, "fp32"), "fp64": hpic.from_workloads(ds, "fp64"),
+            "fp64_ulp": hpic.from_workloads([_ulp_positions(d) for d in ds], "fp64")}
+    sims["fp64_fp32_init"] = hpic.from_workloads(_fp32_init(sims["fp32"], ds), "fp64")
+    return _checkpoint_loop(sims, lambda s: _cart_state(s, len(ds)), steps, checkpoints)
+
+
+def _q3d_sim(hpic, d, prec, x, u, w):
+    n1, n2 = d["n"]
+    sim = hpic.Sim([hpic.config(n1, n2, d["dx"][0], d["dx"][1], d["dt"], alpha=d["alpha"],
+                                precision=prec, modes=d["modes"])])
+    for m in range(d["modes"]):
+        sim.set_fields_mode(0, m, d["E"][m], d["B"][m])
+    sim.set_particles(0, x, u, w, q_over_m=d["qm"], q=d["q"])
+    sim.set_background(0, 2)
+    return sim
+
+
+def _q3d_state(sim, M):
+    F = np.stack([np.stack([sim.field_mode(0, c, m) for c in range(6)]) for m in range(M)])
+    J = np.stack([np.stack([sim.current_mode(0, c, m) for c in range(3)]) for m in range(M)])
+    return [(F[:, :3], F[:, 3:], J)]
+
+
+def precision_q3d(hpic, d, steps, checkpoints):
+    """The same comparison for a quasi-3D handle (every mode's E, B and J)."""
+    sims = {"fp32": _q3d_sim(hpic, d, "fp32", d["x"], d["u"], d["w"]),
+            "fp64": _q3d_sim(hpic, d, "fp64", d["x"], d["u"], d["w"]),
+            "fp64_ulp": _q3d_sim(hpic, d, "fp64", np.nextafter(d["x"], np.copysign(np.inf, d["x"])),
+                                 d["u"], d["w"])}
+    p = sims["fp32"].particles(0)
+    sims["fp64_fp32_init"] = _q3d_sim(hpic, d, "fp64", p["x"], p["u"], p["w"])
+    return _checkpoint_loop(sims, lambda s: _q3d_state(s, d["modes"]), steps, checkpoints)
 
 
 def cpu_model():
@@ -209,49 +315,67 @@ def cpu_baseline(d, all_core_seconds=8.0, one_thread_steps=1):
             "host_cpus": ncores, "cpu_model": cpu_model()}
 
 
-def scan_leg(hpic, torch, W, steps, tune_steps):
+def scan_leg(hpic, torch, W, steps, tune_steps, precision=True):
     """The 64-run parameter scan in one handle: aggregate particle-steps/s of
-    the FP32 form (graph-replayed) and of the FP64 form, and each run's
-    FP32-vs-FP64 relative L2 error of E, B and J after `steps` steps."""
+    the FP32 form (graph-replayed) and of the FP64 form over `steps` steps;
+    with `precision`, fresh handles over the same `steps` give each run's
+    FP32-vs-FP64 relative L2 error of E, B and J beside the FP64 controls,
+    with the run's gamma, particles per cell and grid."""
     t0 = time.perf_counter()
     ds = W.scan2d()
+    params = W.scan2d_params()
     gen_s = time.perf_counter() - t0
     npart = sum(x["w"].size for x in ds)
     warm = 16
     a, t32, _ = run_form(hpic, torch, ds, "fp32", warm, steps, tune_steps=tune_steps)
-    b, t64, _ = run_form(hpic, torch, ds, "fp64", warm, steps, tune_steps=tune_steps)
     tiling = a.tuning
-    errs = {"E": [], "B": [], "J": [], "gauss": []}
-    for r in range(len(ds)):
-        Ea, Ba = a.fields(r)
-        Eb, Bb = b.fields(r)
-        ja = np.stack([a.current(r, c) for c in range(3)])
-        jb = np.stack([b.current(r, c) for c in range(3)])
-        errs["E"].append(rel_l2(Ea, Eb))
-        errs["B"].append(rel_l2(Ba, Bb))
-        errs["J"].append(rel_l2(ja, jb))
-        dg = a.diagnostics(r)
-        errs["gauss"].append(dg["gauss_l2"] / max(dg["gauss_ref_l2"], 1e-300))
     a.close()
+    b, t64, _ = run_form(hpic, torch, ds, "fp64", warm, steps, tune_steps=tune_steps)
     b.close()
     v32 = npart * steps / t32
     v64 = npart * steps / t64
-    summ = {k: {"max": float(np.max(v)), "median": float(np.median(v))} for k, v in errs.items()}
-    return {"workload": "scan2d_64runs", "runs": len(ds), "particles": npart,
-            "cells": int(sum(x["n"][0] * x["n"][1] for x in ds)), "steps": steps,
-            "value": v32, "unit": "particle-steps/s", "ms_per_step": 1e3 * t32 / steps,
-            "fp64_form": {"value": v64, "ms_per_step": 1e3 * t64 / steps,
-                          "fp32_speedup": v32 / v64},
-            "err_vs_fp64_per_run": summ, "generate_s": gen_s, "tiling": tiling,
-            "note": "autotuner (%d steps) and warm-up (%d steps) before the timed region; "
-                    "errors after all %d steps" % (tune_steps, warm, tune_steps + warm + steps)}
+    out = {"workload": "scan2d_64runs", "runs": len(ds), "particles": npart,
+           "cells": int(sum(x["n"][0] * x["n"][1] for x in ds)), "steps": steps,
+           "value": v32, "unit": "particle-steps/s", "ms_per_step": 1e3 * t32 / steps,
+           "fp64_form": {"value": v64, "ms_per_step": 1e3 * t64 / steps,
+                         "fp32_speedup": v32 / v64},
+           "generate_s": gen_s, "tiling": tiling,
+           "note": "autotuner (%d steps) and warm-up (%d steps) before the timed region"
+                   % (tune_steps, warm)}
+    if precision:
+        cps, hist, diag = precision_cartesian(hpic, ds, steps, (10, 30, 100))
+        fin = {k: hist[k][-1] for k in CONTROLS}
+        runs = []
+        for r, p in enumerate(params):
+            runs.append([p["n1"], p["n2"], p["ppc"], round(p["gamma"], 2), round(p["density"], 3)] +
+                        [float("%.3g" % fin["fp32"][r][c]) for c in "EBJ"] +
+                        [float("%.3g" % fin["fp64_ulp"][r]["E"]),
+                         float("%.3g" % fin["fp64_fp32_init"][r]["E"]),
+                         float("%.3g" % (diag[r]["gauss_l2"] / max(diag[r]["gauss_ref_l2"], 1e-300)))])
+        e32 = np.array([fin["fp32"][r]["E"] for r in range(len(ds))])
+        einit = np.array([fin["fp64_fp32_init"][r]["E"] for r in range(len(ds))])
+        eulp = np.array([fin["fp64_ulp"][r]["E"] for r in range(len(ds))])
+        med = {k: {c: [float("%.3g" % np.median([h[r][c] for r in range(len(ds))]))
+                       for h in hist[k]] for c in "EBJ"} for k in CONTROLS}
+        out["precision"] = {
+            "steps": steps, "checkpoints": cps,
+            "median_over_runs": med,
+            "fp32_E": {"max": float(e32.max()), "median": float(np.median(e32))},
+            "fp32_E_over_fp32_init_E": {"max": float((e32 / einit).max()),
+                                        "median": float(np.median(e32 / einit))},
+            "ulp64_E": {"max": float(eulp.max()), "median": float(np.median(eulp))},
+            "per_run_columns": ["n1", "n2", "ppc", "gamma", "density", "E", "B", "J",
+                                "E_fp64_ulp", "E_fp64_fp32_init", "gauss_rel_fp32"],
+            "per_run": runs}
+    return out
 
 
-def d3_leg(hpic, torch, W, steps, tune_steps):
+def d3_leg(hpic, torch, W, steps, tune_steps, precision=True):
     """3D Cartesian leg: 512 x 128 x 128 cells, 16.8M particles, gamma = 50,
     density +-5%.  Particle-steps/s of the FP32 form (graph-replayed) and the
-    FP64 form over `steps` steps, then the FP32-vs-FP64 relative L2 error of E,
-    B and J and the Gauss and continuity residuals of the FP32 form."""
+    FP64 form over `steps` steps, the Gauss and continuity residuals of the
+    FP32 form, and with `precision`, fresh handles over the same `steps` for
+    the FP32-vs-FP64 errors of E, B and J beside the FP64 controls."""
     d = W.drift3d()
     npart = d["w"].size
     warm = 10
@@ -260,51 +384,47 @@ def d3_leg(hpic, torch, W, steps, tune_steps):
     kt.pop("profiled_wall_s")
     push_stats = kt.pop("push_stats")
     tiling = a.tuning
-    # the FP64 form takes the same steps, profiled pass included, so the two
-    # are compared at the same time
-    b, t64, _ = run_form(hpic, torch, [d], "fp64", warm, steps, profile=True, tune_steps=tune)
     a.diagnostics(0)
-    b.diagnostics(0)
     a.step(1)
-    b.step(1)
     da = a.diagnostics(0)
-    Ea, Ba = a.fields(0)
-    Eb, Bb = b.fields(0)
-    ja = np.stack([a.current(0, c) for c in range(3)])
-    jb = np.stack([b.current(0, c) for c in range(3)])
     a.close()
+    b, t64, _ = run_form(hpic, torch, [d], "fp64", warm, steps, tune_steps=tune)
     b.close()
     v32 = npart * steps / t32
     pd_ms, pd_n = kt["push_deposit"]
     cells = int(np.prod(d["n"]))
     rho_scale = abs(da["charge_total"]) / (cells * float(np.prod(d["dx"])))
-    return {"workload": d["name"], "n": list(d["n"]), "particles": npart, "steps": steps,
-            "value": v32, "unit": "particle-steps/s", "ms_per_step": 1e3 * t32 / steps,
-            "fp64_form": {"value": npart * steps / t64, "ms_per_step": 1e3 * t64 / steps,
-                          "fp32_speedup": t64 / t32},
-            "kernels": {k: {"avg_us": 1e3 * ms / max(n, 1), "launches": n} for k, (ms, n) in kt.items()},
-            "lds_fallback_tiles": push_stats["fallback_tiles"], "tiling": tiling,
-            "err_vs_fp64": {"after_steps": tune + warm + 2 * steps + 1, "E_rel_l2": rel_l2(Ea, Eb),
-                            "B_rel_l2": rel_l2(Ba, Bb), "J_rel_l2": rel_l2(ja, jb),
-                            "gauss_rel_l2_fp32": da["gauss_l2"] / max(da["gauss_ref_l2"], 1e-300),
-                            "continuity_linf_rel_fp32": da["cont_linf"] * d["dt"] / max(rho_scale, 1e-300)},
-            "push_deposit_alg_GBps": (60 * npart + 72 * cells) / (pd_ms / max(pd_n, 1) * 1e-3) / 1e9}
+    out = {"workload": d["name"], "n": list(d["n"]), "particles": npart, "steps": steps,
+           "value": v32, "unit": "particle-steps/s", "ms_per_step": 1e3 * t32 / steps,
+           "fp64_form": {"value": npart * steps / t64, "ms_per_step": 1e3 * t64 / steps,
+                         "fp32_speedup": t64 / t32},
+           "kernels": {k: {"avg_us": 1e3 * ms / max(n, 1), "launches": n} for k, (ms, n) in kt.items()},
+           "lds_fallback_tiles": push_stats["fallback_tiles"], "tiling": tiling,
+           "residuals_fp32": {"after_steps": da["step"],
+                              "gauss_rel_l2": da["gauss_l2"] / max(da["gauss_ref_l2"], 1e-300),
+                              "continuity_linf_rel": da["cont_linf"] * d["dt"] / max(rho_scale, 1e-300)},
+           "push_deposit_alg_GBps": (60 * npart + 72 * cells) / (pd_ms / max(pd_n, 1) * 1e-3) / 1e9}
+    out["push_deposit_frac"] = out["push_deposit_alg_GBps"] / HBM_PEAK_GBS
+    if precision:
+        out["err_vs_fp64"] = _single_run_table(*precision_cartesian(hpic, [d], steps, (10, 30, 100, 300)))
+    return out
 
 
-def q3d_leg(hpic, torch, W, steps):
+def q3d_leg(hpic, torch, W, steps, precision=True):
     """Quasi-3D PIC step: 4096 (z) x 256 (r) cells, dz = 0.1, dr = 0.2, dt =
     0.04, azimuthal modes 0, 1, 2 advanced together (one launch per stage), a
     plasma column of 8 192 000 particles drifting at gamma = 20 over a
     co-drifting background, and an m = 1 seed pulse (synthetic, seeded).  Both
     forms over the same steps: particle-steps/s, per-kernel times, the
-    FP32-vs-FP64 relative L2 error of every mode's E and B, and the change of
-    the Gauss residual norm (constant in exact arithmetic)."""
+    push+deposit kernel's algorithmic GB/s, the change of the Gauss residual
+    norm (constant in exact arithmetic); with `precision`, fresh handles over
+    `steps` steps for the FP32-vs-FP64 errors of every mode's E, B and J beside
+    the FP64 controls."""
     d = W.drift_q3d()
     n1, n2 = d["n"]
     M = d["modes"]
     npart = d["w"].size
     out = {"workload": d["name"], "n": [n1, n2], "modes": M, "particles": npart, "steps": steps}
-    fields = {}
     for prec in ("fp32", "fp64"):
         sim = hpic.Sim([hpic.config(n1, n2, d["dx"][0], d["dx"][1], d["dt"], alpha=d["alpha"],
                                     precision=prec, modes=M)], stream=torch.cuda.current_stream())
@@ -319,8 +439,6 @@ def q3d_leg(hpic, torch, W, steps):
         kt = sim.kernel_times()
         sim.profile(False)
         dg = sim.diagnostics(0)
-        fields[prec] = np.stack([np.stack([sim.field_mode(0, c, m) for c in range(6)])
-                                 for m in range(M)])
         sim.close()
         out[prec] = {"ms_per_step": 1e3 * t / steps,
                      "particle_steps_per_s": npart * steps / t,
@@ -329,11 +447,15 @@ def q3d_leg(hpic, torch, W, steps):
                      "gauss_l2_change": abs(dg["gauss_l2"] - g0) / max(g0, 1e-300),
                      "kinetic": dg["kinetic"],
                      "field_energy": sum(dg["W_E"]) + sum(dg["W_B"])}
-    a, b = fields["fp32"], fields["fp64"]
-    out["err_vs_fp64"] = {"after_steps": 10 + 2 * steps,
-                          "E_rel_l2": rel_l2(a[:, :3], b[:, :3]),
-                          "B_rel_l2": rel_l2(a[:, 3:], b[:, 3:])}
+        if prec == "fp32":
+            pd_ms, pd_n = kt["push_deposit"]
+            alg = Q3D_BYTES_PER_PARTICLE * npart + Q3D_BYTES_PER_MODE_NODE * M * (n2 + 1) * n1
+            out["push_deposit_alg_GBps"] = alg / (pd_ms / max(pd_n, 1) * 1e-3) / 1e9
+            out["push_deposit_alg_bytes"] = alg
+            out["push_deposit_frac"] = out["push_deposit_alg_GBps"] / HBM_PEAK_GBS
     out["fp32_over_fp64"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
+    if precision:
+        out["err_vs_fp64"] = _single_run_table(*precision_q3d(hpic, d, steps, (10, 30, 100, 300)))
     return out
 
 
@@ -510,26 +632,17 @@ def main():
                             "steps": args.fp64_steps,
                             "fp32_speedup": value / (npart * args.fp64_steps / t64)}
     if args.err_steps > 0:
-        a = hpic.from_workload(d, "fp32")
-        b = hpic.from_workload(d, "fp64")
-        a.step(args.err_steps)
-        b.step(args.err_steps)
-        Ea, Ba = a.fields(0)
-        Eb, Bb = b.fields(0)
-        ja = np.stack([a.current(0, c) for c in range(3)])
-        jb = np.stack([b.current(0, c) for c in range(3)])
-        da = a.diagnostics(0)
-        out["err_vs_fp64"] = {"steps": args.err_steps, "E_rel_l2": rel_l2(Ea, Eb),
-                              "B_rel_l2": rel_l2(Ba, Bb), "J_rel_l2": rel_l2(ja, jb),
-                              "gauss_rel_l2_fp32": da["gauss_l2"] / max(da["gauss_ref_l2"], 1e-300)}
-        a.close()
-        b.close()
+        cps, hist, diag = precision_cartesian(hpic, [d], args.err_steps, (10, 30, 100, 300))
+        tab = _single_run_table(cps, hist, diag)
+        out["err_vs_fp64"] = {"steps": args.err_steps, "E_rel_l2": tab["fp32"]["E"][-1],
+                              "B_rel_l2": tab["fp32"]["B"][-1], "J_rel_l2": tab["fp32"]["J"][-1],
+                              "gauss_rel_l2_fp32": tab["gauss_rel_l2_fp32"], "history": tab}
     if args.scan_steps > 0:
-        out["scan2d"] = scan_leg(hpic, torch, W, args.scan_steps, args.tune_steps)
+        out["scan2d"] = scan_leg(hpic, torch, W, args.scan_steps, args.tune_steps, args.precision)
     if args.d3_steps > 0:
-        out["drift3d"] = d3_leg(hpic, torch, W, args.d3_steps, args.tune_steps)
+        out["drift3d"] = d3_leg(hpic, torch, W, args.d3_steps, args.tune_steps, args.precision)
     if args.q3d_steps > 0:
-        out["quasi3d"] = q3d_leg(hpic, torch, W, args.q3d_steps)
+        out["quasi3d"] = q3d_leg(hpic, torch, W, args.q3d_steps, args.precision)
     if args.shape_steps > 0:
         out["shapes2d"] = shape_leg(hpic, torch, d, args.shape_steps, args.tune_steps, tiling)
     if args.nci_steps > 0:

@@ -73,7 +73,8 @@ struct Run {
   R idx3, dtdx3, jfx3;  // 3D: 1/dx3, dt/dx3, -dx3/dt
   float cj;          // 3D FP32 form: integer scale of the per-node contributions
   R inv_m;           // 1/M, M = n1/2 (inverse real FFT normalisation)
-  R jbg0[3];         // n1 * j_bg: added to the kappa = 0 bin of every row
+  double jbgu[3];    // j_bg in accumulator units, added to every node before the
+                     // row transform (so the transform sees the drift-free current)
   Parts<R> pt[2];
   int T1, T2, T3, nt1, nt2, nt3, ntiles;
   int *tile_start, *tile_cnt;

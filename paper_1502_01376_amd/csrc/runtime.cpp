@@ -608,10 +608,7 @@ class Sim : public SimBase {
   int set_background(int run, int rho_from_particles, const double *jbg) override {
     RunHost &h = runs_[run];
     Run<R> &d = h.d;
-    for (int c = 0; c < 3; ++c) {
-      h.jbg[c] = jbg ? jbg[c] : 0.0;
-      d.jbg0[c] = (R)(d.n1 * h.jbg[c]);
-    }
+    for (int c = 0; c < 3; ++c) h.jbg[c] = jbg ? jbg[c] : 0.0;
     if (rho_from_particles) {
       int rc;
       if (d.dim == 3) {
@@ -1311,10 +1308,7 @@ class Sim : public SimBase {
       d.c3 = (float)meta[5];
       d.P = (int)meta[10];
       d.unit_charge = (d.dim == 2 && h.Qbits + d.P <= 22) ? 1 : 0;
-      for (int c = 0; c < 3; ++c) {
-        h.jbg[c] = meta[6 + c];
-        d.jbg0[c] = (R)(d.n1 * h.jbg[c]);
-      }
+      for (int c = 0; c < 3; ++c) h.jbg[c] = meta[6 + c];
       d.qmhdt = (R)(0.5 * h.qm * h.cfg.dt);
       h.np = n;
       d.np = (int)n;
@@ -1545,7 +1539,12 @@ class Sim : public SimBase {
   }
   int upload_runs() {
     std::vector<Run<R>> v(runs_.size());
-    for (size_t i = 0; i < runs_.size(); ++i) v[i] = runs_[i].d;
+    for (size_t i = 0; i < runs_.size(); ++i) {
+      v[i] = runs_[i].d;
+      // the background in the units of the accumulators, which change with
+      // the particles' fixed-point scale
+      for (int c = 0; c < 3; ++c) v[i].jbgu[c] = runs_[i].jbg[c] / acc_factor(runs_[i], c);
+    }
     const int rc = h2d(d_runs_, v.data(), v.size());
     return rc ? rc : upload_antennas();
   }

@@ -14,9 +14,6 @@ namespace hp {
 // FFT of the current along x1, correction and filter
 // =====================================================================
 
-template <class R> __device__ __forceinline__ R to_real(long long v) { return (R)v; }
-template <class R> __device__ __forceinline__ R to_real(double v) { return (R)v; }
-
 // X[k] for k = 0..M of a length-2M real row from Z = FFT_M(z), z[n] = x[2n] + i x[2n+1]:
 // X[k] = (Z[k] + conj Z[M-k])/2 - i W^k (Z[k] - conj Z[M-k])/2, W = exp(-i pi / M).
 template <class C>
@@ -59,9 +56,13 @@ __global__ void __launch_bounds__(256) k_fft_j(const Run<R> *__restrict__ runs,
   const int cb = ncomp == 3 ? 0 : it.b;
   for (int cc = 0; cc < ncomp; ++cc) {
     const long long base = (long long)(cb + cc) * cells + (long long)row * n1;
+    // the uniform background is added per node in FP64 before the conversion:
+    // for a drifting plasma it cancels the bulk current, so that the FP32
+    // transform (FP32 form) rounds relative to the current's fluctuation
+    const double bg = r.jbgu[cb + cc];
     for (int n = threadIdx.x; n < M; n += blockDim.x) {
-      const R x0 = to_real<R>(Jin[base + 2 * n]);
-      const R x1 = to_real<R>(Jin[base + 2 * n + 1]);
+      const R x0 = (R)((double)Jin[base + 2 * n] + bg);
+      const R x1 = (R)((double)Jin[base + 2 * n + 1] + bg);
       lds[cc * M + n] = cmk(x0, x1);
       Jz[base + 2 * n] = 0;
       Jz[base + 2 * n + 1] = 0;
@@ -80,7 +81,6 @@ __global__ void __launch_bounds__(256) k_fft_j(const Run<R> *__restrict__ runs,
       C Xk = r2c_post(Zk, Zmk, Wk);
       const R fk = r.jfac[k * 3 + c];
       Xk = cscale(Xk, fk);
-      if (k == 0) Xk.x += r.jbg0[c];
       C *out = r.Jk + (long long)c * r.rows * nk + (long long)row * nk;
       out[k] = Xk;
       if (mk != k) {

@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(256) k_q_ifft(const RunQ<R> *__restrict__ runs
 // row -> current density (jconv: face area or node volume, dt and the
 // fixed-point scale), the other parity's accumulators cleared, forward complex
 // transform along z, the correction of Eq. (11) on jz and the low-pass filter
-// (kfac), and the co-drifting background at kappa = 0 (m = 0, z).
+// (kfac); the co-drifting background (m = 0, z) is added before the transform.
 template <class R>
 __global__ void __launch_bounds__(256) k_q_fft_j(const RunQ<R> *__restrict__ runs,
                                                  const Item *__restrict__ items, int parity) {
@@ -68,9 +68,13 @@ __global__ void __launch_bounds__(256) k_q_fft_j(const RunQ<R> *__restrict__ run
   const long long base = (long long)mc * r.plane + (long long)row * r.n1;
   const A *Jin = r.J[parity] + 2 * base;
   A *Jclr = r.J[parity ^ 1] + 2 * base;
-  const R conv = (R)r.jconv[mc * r.nr + row];
+  // conversion and the co-drifting background (mode 0, z) per node in FP64
+  // before the transform: the background cancels the column's bulk current,
+  // so that the FP32 transform (FP32 form) rounds relative to its fluctuation
+  const double conv = r.jconv[mc * r.nr + row];
+  const double bg = (m == 0 && c == 0) ? r.jbgk[row] / (double)r.n1 : 0.0;
   for (int n = threadIdx.x; n < r.n1; n += blockDim.x) {
-    lds[n] = cmk((R)Jin[2 * n] * conv, (R)Jin[2 * n + 1] * conv);
+    lds[n] = cmk((R)((double)Jin[2 * n] * conv + bg), (R)((double)Jin[2 * n + 1] * conv));
     Jclr[2 * n] = 0;
     Jclr[2 * n + 1] = 0;
   }
@@ -80,7 +84,6 @@ __global__ void __launch_bounds__(256) k_q_fft_j(const RunQ<R> *__restrict__ run
   const int sel = c == 0 ? 0 : 1;
   for (int k = threadIdx.x; k < r.n1; k += blockDim.x) {
     C v = cscale(lds[k], r.kfac[2 * k + sel]);
-    if (k == 0 && m == 0 && c == 0) v.x += (R)r.jbgk[row];
     out[k] = v;
   }
 }

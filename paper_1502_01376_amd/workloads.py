@@ -275,7 +275,8 @@ def nci_table1(seed=SEED0 + 10, ppc=(2, 2), n=(256, 256)):
     return d
 
 
-def lwfa_boosted(n1=8192, n2=512, gamma_b=14.0, ppc=(2, 2), seed=SEED0 + 13, name=None):
+def lwfa_boosted(n1=8192, n2=512, gamma_b=14.0, ppc=(2, 2), sigma_u=1e-4, seed=SEED0 + 13,
+                 name=None):
     """Lorentz-boosted 2D laser wakefield set-up of Table 2 (Sec. 6), in the
     boosted frame with lab-frame laser units (k0 = omega0 = 1, c = 1, density
     in units of the lab critical density):
@@ -284,9 +285,12 @@ def lwfa_boosted(n1=8192, n2=512, gamma_b=14.0, ppc=(2, 2), seed=SEED0 + 13, nam
       dt = 0.225 dx1, 8192 x 512 cells, filter at half the x1 Nyquist
       wavenumber;
     * plasma of density 1.148e-3 gamma_b streaming along -x1 with
-      u1 = -gamma_b beta_b, cold, on a quiet ppc sub-lattice (2 x 2, 16 777 216
-      particles), filling the periodic box, with co-streaming ions as a fixed
-      neutralising background (charge and uniform current);
+      u1 = -gamma_b beta_b plus a Gaussian spread sigma_u per component (1e-4,
+      as in the Table 1 runs: the seed of the numerical Cherenkov instability,
+      which a cold quiet plasma would take from round-off alone), on a quiet
+      ppc sub-lattice (2 x 2, 16 777 216 particles), filling the periodic box,
+      with co-streaming ions as a fixed neutralising background (charge and
+      uniform current);
     * the laser (a0 = 4, waist 117.81, polarised along x3, field FWHM
       70.64 gamma_b (1 + beta_b) in the boosted frame) launched by a moving
       antenna at rest in the lab frame (v = -beta_b): surface current
@@ -306,6 +310,8 @@ def lwfa_boosted(n1=8192, n2=512, gamma_b=14.0, ppc=(2, 2), seed=SEED0 + 13, nam
     npart = x1.size
     u = np.zeros((3, npart))
     u[0] = -gamma_b * beta_b
+    if sigma_u > 0:
+        u += sigma_u * gen.standard_normal((3, npart))
     w = np.full(npart, density / (ppc[0] * ppc[1]))
     q, qm = -1.0, -1.0
     a0, waist = 4.0, 117.81

@@ -7,7 +7,8 @@ the moving antenna), FP32 form, and the n1 = 8192 row transforms it needs:
   laser has the boosted-frame amplitude a0 omega' on axis, a wake of the
   expected order forms behind it, and the plasma ahead of the laser stays
   quiet (no numerical Cherenkov noise, Sec. 6 reports none);
-* the same run without the filter fills that region with NCI noise.
+* the same run without the filter fills that region with NCI noise (seeded
+  by the plasma's 1e-4 momentum spread, not by round-off).
 
 The paper's comparisons (UPIC-EMMA, OSIRIS lab frame) are not available, so
 the levels are parity unpinned: the thresholds are wide margins around the
