@@ -24,6 +24,14 @@ __device__ __forceinline__ int wrap_delta_3(int d, int n) {
   d -= (d >= n - (n >> 1)) ? n : 0;
   return d;
 }
+// i mod n for any i (a loop of corrections: boxes that fit the LDS reach at
+// most a few periods of a small grid)
+__device__ __forceinline__ int wrap_any3(int i, int n) {
+  while (i >= n) i -= n;
+  while (i < 0) i += n;
+  return i;
+}
+
 __device__ __forceinline__ int wave_min3(int v) {
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
   return v;
@@ -183,6 +191,12 @@ struct Sink3GlobalF64 {
 // holds to about 2^-41 of a particle's charge per node and step (with FP32
 // weights and a 2^28 scale, long drifting-beam runs grew a spurious k1 = 0
 // mode).  FP64 form: g = qw (-dx_d/dt) / 6, physical current.
+// FP64 form: where no particle of the wave changes its nearest node along an
+// axis, the stencil is three nodes wide there (the fourth row of S0 and S1 is
+// zero, the last running sum C[2] along that axis only the rounding of 1 - 1)
+// and both blocks of terms are skipped for the whole wave.  (The same skip in
+// the FP32 form, exact there since C[2] stays below half a unit after the
+// 2^40 scale, cost more in register spills than it saved.)
 template <class Sink>
 __device__ __forceinline__ void deposit3_fixed(const Sink &K, float inv_wunit, float cj,
                                                const int l[3], const float fa[3], const int dd[3],
@@ -238,12 +252,14 @@ __device__ __forceinline__ void deposit3_fp64(const Sink &K, const double jf[3],
                                               const double fb[3], double qw) {
   double S0[3][4], S1[3][4], C[3][4];
   int o[3][4];
+  bool w4[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     double sa[3], sb[3];
     const int na = dshape3(l[d], fa[d], sa);
     const int nb = dshape3(l[d] + dd[d], fb[d], sb);
     const int base = min(na, nb) - 1;
+    w4[d] = __ballot(na != nb) != 0;
     place4_3(sa, na - 1 - base, S0[d]);
     place4_3(sb, nb - 1 - base, S1[d]);
     double acc = 0.0;
@@ -266,12 +282,17 @@ __device__ __forceinline__ void deposit3_fp64(const Sink &K, const double jf[3],
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
+      if (k == 2 && !w4[d]) continue;  // three-node stencil along d
       const double cg = C[d][k] * g;
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i) {
+        if (i == 3 && !w4[e]) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j) {
+          if (j == 3 && !w4[f]) continue;
           K.add(d, o[d][k] + o[e][i] + o[f][j], cg * (S0[e][i] * u0[j] + S1[e][i] * u1[j]));
+        }
+      }
     }
   }
 }
@@ -480,15 +501,19 @@ k_push_deposit3(const Run<R> *__restrict__ runs, const Item *__restrict__ items,
       const gptr<const R> F = G((const R *)r.F);
       const long long cells = r.cells;
       const int o1 = ref[0] + lo[0] - 1, o2 = ref[1] + lo[1] - 1, o3 = ref[2] + lo[2] - 1;
-      for (int q = threadIdx.x; q < 6 * fplane; q += 256) {
-        const int comp = q / fplane, e = q - comp * fplane;
+      // one node's six components per pass, all six loads in flight before
+      // their LDS stores (a tile stages about 13 values per thread, which one
+      // at a time would wait out the memory latency in turn)
+      for (int e = threadIdx.x; e < fplane; e += 256) {
         const int k = e / (FW * FH), rem = e - k * FW * FH;
         const int b = rem / FW, a = rem - b * FW;
-        int g3 = (o3 + k) % n3;
-        g3 += g3 < 0 ? n3 : 0;
-        int g2 = (o2 + b) % n2;
-        g2 += g2 < 0 ? n2 : 0;
-        fl[q] = F[comp * cells + ((long long)g3 * n2 + g2) * n1 + wrap_pow2(o1 + a, n1)];
+        const int g3 = wrap_any3(o3 + k, n3), g2 = wrap_any3(o2 + b, n2);
+        const long long g = ((long long)g3 * n2 + g2) * n1 + wrap_pow2(o1 + a, n1);
+        R v[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = F[c * cells + g];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) fl[c * fplane + e] = v[c];
       }
     }
     __syncthreads();
@@ -509,20 +534,38 @@ k_push_deposit3(const Run<R> *__restrict__ runs, const Item *__restrict__ items,
     __syncthreads();
     const auto J = G((typename SK::T *)r.J[parity]);
     const int c1 = ref[0] + lo[0] - 2, c2 = ref[1] + lo[1] - 2, c3 = ref[2] + lo[2] - 2;
-    for (int q = threadIdx.x; q < vol; q += 256) {
-      const int k = q / (W * H), rem = q - k * W * H;
-      const int b = rem / W, a = rem - b * W;
-      int g3 = (c3 + k) % n3;
-      g3 += g3 < 0 ? n3 : 0;
-      int g2 = (c2 + b) % n2;
-      g2 += g2 < 0 ? n2 : 0;
-      const long long g = ((long long)g3 * n2 + g2) * n1 + wrap_pow2(c1 + a, n1);
+    auto flush = [&](int q, long long g) {
 #pragma unroll
       for (int comp = 0; comp < 3; ++comp) {
         const typename SK::T v = lj[comp * vol + q];
         if (v != 0)
           __scoped_atomic_fetch_add(J + comp * (long long)r.cells + g, v, __ATOMIC_RELAXED,
                                     __MEMORY_SCOPE_DEVICE);
+      }
+    };
+    if (W <= 256) {
+      // each thread keeps one column a of the box and walks the rows
+      // (k, b) = rr, rr + rpp, ... with rpp = 256 / W rows per pass
+      const int rpp = 256 / W, rr = (int)threadIdx.x / W, a = (int)threadIdx.x - rr * W;
+      if (rr < rpp) {
+        const int col = wrap_pow2(c1 + a, n1);
+        int k = rr / H, b = rr - k * H;
+        for (int row = rr; row < H * D; row += rpp) {
+          const int g3 = wrap_any3(c3 + k, n3), g2 = wrap_any3(c2 + b, n2);
+          flush(row * W + a, ((long long)g3 * n2 + g2) * n1 + col);
+          b += rpp;
+          while (b >= H) {
+            b -= H;
+            ++k;
+          }
+        }
+      }
+    } else {
+      for (int q = threadIdx.x; q < vol; q += 256) {
+        const int k = q / (W * H), rem = q - k * W * H;
+        const int b = rem / W, a = rem - b * W;
+        const int g3 = wrap_any3(c3 + k, n3), g2 = wrap_any3(c2 + b, n2);
+        flush(q, ((long long)g3 * n2 + g2) * n1 + wrap_pow2(c1 + a, n1));
       }
     }
   }
