@@ -463,12 +463,19 @@ __global__ void __launch_bounds__(256, QPush<R>::WAVES_PER_SIMD)
       // lane -> (row in a group of rpi rows, column)
       const int rpi = 64 / Wf, sub = lane / Wf, cc = lane - sub * Wf;
       const int col = wrap_pow2(cz0 + fzlo + cc, n1);
+      // a mode's six components per pass, all six loads in flight before
+      // their LDS stores
       if (sub < rpi)
-        for (int cm = 0; cm < 6 * M; ++cm)  // cm = 6 m + component
-          for (int r0 = sub; r0 < Hf; r0 += rpi) {
-            const C v = F[(long long)cm * plane + (long long)(rlo + r0) * n1 + col];
-            fbox[(cm * Hf + r0) * Wf + cc] = V2{v.x, v.y};
+        for (int r0 = sub; r0 < Hf; r0 += rpi) {
+          const long long ro = (long long)(rlo + r0) * n1 + col;
+          for (int m = 0; m < M; ++m) {
+            C v[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) v[c] = F[(long long)(6 * m + c) * plane + ro];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) fbox[((6 * m + c) * Hf + r0) * Wf + cc] = V2{v[c].x, v[c].y};
           }
+        }
     }
   } else {
     if (use_lds)
@@ -623,15 +630,33 @@ __global__ void __launch_bounds__(256, QPush<R>::WAVES_PER_SIMD)
   if (use_lds) {
     A *J = r.J[parity];
     const int per = 2 * M - 1;
-    for (int e = lane; e < W * H * NS; e += 64) {
-      const A v = box[e];
-      if (v == A(0)) continue;
-      const int cc = e % W, rest = e / W;
-      const int row = rlo + rest % H, slot = rest / H;
-      const int c = slot / per, s2 = slot - c * per;
-      const int m = (s2 + 1) >> 1, part = s2 == 0 ? 0 : (s2 - 1) & 1;
-      const int col = wrap_pow2(cz0 + zlo + cc, n1);
-      glob_add(G(J) + ((long long)(m * 3 + c) * plane + (long long)row * n1 + col) * 2 + part, v);
+    if (W <= 64) {
+      // each lane keeps one column of the box and walks its rows, slot by
+      // slot (box layout [slot][row][column])
+      const int rpi = 64 / W, sub = lane / W, cc = lane - sub * W;
+      if (sub < rpi) {
+        const int col = wrap_pow2(cz0 + zlo + cc, n1);
+        for (int slot = 0; slot < NS; ++slot) {
+          const int c = slot / per, s2 = slot - c * per;
+          const int m = (s2 + 1) >> 1, part = s2 == 0 ? 0 : (s2 - 1) & 1;
+          const auto Jb = G(J) + (long long)(m * 3 + c) * plane * 2 + part;
+          for (int r0 = sub; r0 < H; r0 += rpi) {
+            const A v = box[(slot * H + r0) * W + cc];
+            if (v != A(0)) glob_add(Jb + ((long long)(rlo + r0) * n1 + col) * 2, v);
+          }
+        }
+      }
+    } else {
+      for (int e = lane; e < W * H * NS; e += 64) {
+        const A v = box[e];
+        if (v == A(0)) continue;
+        const int cc = e % W, rest = e / W;
+        const int row = rlo + rest % H, slot = rest / H;
+        const int c = slot / per, s2 = slot - c * per;
+        const int m = (s2 + 1) >> 1, part = s2 == 0 ? 0 : (s2 - 1) & 1;
+        const int col = wrap_pow2(cz0 + zlo + cc, n1);
+        glob_add(G(J) + ((long long)(m * 3 + c) * plane + (long long)row * n1 + col) * 2 + part, v);
+      }
     }
   }
 }
