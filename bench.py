@@ -60,6 +60,9 @@ def parse():
                     help="steps of the 64-run parameter scan (0: skip)")
     ap.add_argument("--d3-steps", type=int, default=500,
                     help="steps of the 3D 512x128x128 drifting-plasma leg (0: skip)")
+    ap.add_argument("--d3-tiling", type=str, default="",
+                    help="T1,T2,K: fixed 3D tiling (T1 x T2 x T2 cells, sort interval K) instead "
+                         "of the autotuner")
     ap.add_argument("--shape-steps", type=int, default=200,
                     help="steps of the benchmark workload with the energy-conserving gather "
                          "and with the cubic shape (0: skip)")
@@ -140,29 +143,37 @@ PUSH_SOURCES = [os.path.join(ROOT, "paper_1502_01376_amd", "csrc", f)
                 for f in ("push.hip", "hpic_internal.h")]
 
 
-def source_hash():
+CSRC = os.path.join(ROOT, "paper_1502_01376_amd", "csrc")
+D3_COUNTERS = os.path.join(ROOT, "profiles", "drift3d_512x128x128_counters.txt")
+D3_SOURCES = [os.path.join(CSRC, f) for f in ("push3.hip", "hpic_internal.h")]
+Q3D_COUNTERS = os.path.join(ROOT, "profiles", "drift_q3d_4096x256_counters.txt")
+Q3D_SOURCES = [os.path.join(CSRC, f) for f in ("pushq.hip", "hpic_q3d.h", "hpic_internal.h")]
+
+
+def source_hash(files=None):
     import hashlib
     h = hashlib.sha256()
-    for f in PUSH_SOURCES:
+    for f in files or PUSH_SOURCES:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per push+deposit launch from the committed rocprofv3 counter
+def measured_traffic(path=TRAFFIC_FILE, sources=None, prefix=""):
+    """HBM bytes per push+deposit launch from a committed rocprofv3 counter
     summary, or None if the kernel source changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             parts = line.split()
             if len(parts) == 2 and not line.startswith("#"):
                 vals[parts[0]] = parts[1]
-    if vals.get("source_hash") != source_hash() or "hbm_bytes_per_launch" not in vals:
+    key = prefix + "hbm_bytes_per_launch"
+    if vals.get(prefix + "source_hash") != source_hash(sources) or key not in vals:
         return None
-    return float(vals["hbm_bytes_per_launch"])
+    return float(vals[key])
 
 
 def rel_l2(a, b):
@@ -370,7 +381,7 @@ def scan_leg(hpic, torch, W, steps, tune_steps, precision=True):
     return out
 
 
-def d3_leg(hpic, torch, W, steps, tune_steps, precision=True):
+def d3_leg(hpic, torch, W, steps, tune_steps, precision=True, tiling=None):
     """3D Cartesian leg: 512 x 128 x 128 cells, 16.8M particles, gamma = 50,
     density +-5%.  Particle-steps/s of the FP32 form (graph-replayed) and the
     FP64 form over `steps` steps, the Gauss and continuity residuals of the
@@ -380,7 +391,8 @@ def d3_leg(hpic, torch, W, steps, tune_steps, precision=True):
     npart = d["w"].size
     warm = 10
     tune = min(tune_steps, 400)
-    a, t32, kt = run_form(hpic, torch, [d], "fp32", warm, steps, profile=True, tune_steps=tune)
+    a, t32, kt = run_form(hpic, torch, [d], "fp32", warm, steps, profile=True, tune_steps=tune,
+                          tiling=tiling)
     kt.pop("profiled_wall_s")
     push_stats = kt.pop("push_stats")
     tiling = a.tuning
@@ -388,7 +400,7 @@ def d3_leg(hpic, torch, W, steps, tune_steps, precision=True):
     a.step(1)
     da = a.diagnostics(0)
     a.close()
-    b, t64, _ = run_form(hpic, torch, [d], "fp64", warm, steps, tune_steps=tune)
+    b, t64, _ = run_form(hpic, torch, [d], "fp64", warm, steps, tune_steps=tune, tiling=tiling)
     b.close()
     v32 = npart * steps / t32
     pd_ms, pd_n = kt["push_deposit"]
@@ -405,6 +417,7 @@ def d3_leg(hpic, torch, W, steps, tune_steps, precision=True):
                               "continuity_linf_rel": da["cont_linf"] * d["dt"] / max(rho_scale, 1e-300)},
            "push_deposit_alg_GBps": (60 * npart + 72 * cells) / (pd_ms / max(pd_n, 1) * 1e-3) / 1e9}
     out["push_deposit_frac"] = out["push_deposit_alg_GBps"] / HBM_PEAK_GBS
+    out["push_deposit_traffic"] = measured_traffic(D3_COUNTERS, D3_SOURCES, "push_deposit.")
     if precision:
         out["err_vs_fp64"] = _single_run_table(*precision_cartesian(hpic, [d], steps, (10, 30, 100, 300)))
     return out
@@ -453,6 +466,8 @@ def q3d_leg(hpic, torch, W, steps, precision=True):
             out["push_deposit_alg_GBps"] = alg / (pd_ms / max(pd_n, 1) * 1e-3) / 1e9
             out["push_deposit_alg_bytes"] = alg
             out["push_deposit_frac"] = out["push_deposit_alg_GBps"] / HBM_PEAK_GBS
+            out["push_deposit_traffic"] = measured_traffic(Q3D_COUNTERS, Q3D_SOURCES,
+                                                           "push_deposit.")
     out["fp32_over_fp64"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
     if precision:
         out["err_vs_fp64"] = _single_run_table(*precision_q3d(hpic, d, steps, (10, 30, 100, 300)))
@@ -640,7 +655,8 @@ def main():
     if args.scan_steps > 0:
         out["scan2d"] = scan_leg(hpic, torch, W, args.scan_steps, args.tune_steps, args.precision)
     if args.d3_steps > 0:
-        out["drift3d"] = d3_leg(hpic, torch, W, args.d3_steps, args.tune_steps, args.precision)
+        d3t = [int(v) for v in args.d3_tiling.split(",")] if args.d3_tiling else None
+        out["drift3d"] = d3_leg(hpic, torch, W, args.d3_steps, args.tune_steps, args.precision, d3t)
     if args.q3d_steps > 0:
         out["quasi3d"] = q3d_leg(hpic, torch, W, args.q3d_steps, args.precision)
     if args.shape_steps > 0:
