@@ -381,7 +381,7 @@ def scan_leg(hpic, torch, W, steps, tune_steps, precision=True):
     return out
 
 
-def d3_leg(hpic, torch, W, steps, tune_steps, precision=True, tiling=None):
+def d3_leg(hpic, torch, W, steps, tune_steps, precision=True, fixed_tiling=None):
     """3D Cartesian leg: 512 x 128 x 128 cells, 16.8M particles, gamma = 50,
     density +-5%.  Particle-steps/s of the FP32 form (graph-replayed) and the
     FP64 form over `steps` steps, the Gauss and continuity residuals of the
@@ -392,7 +392,7 @@ def d3_leg(hpic, torch, W, steps, tune_steps, precision=True, tiling=None):
     warm = 10
     tune = min(tune_steps, 400)
     a, t32, kt = run_form(hpic, torch, [d], "fp32", warm, steps, profile=True, tune_steps=tune,
-                          tiling=tiling)
+                          tiling=fixed_tiling)
     kt.pop("profiled_wall_s")
     push_stats = kt.pop("push_stats")
     tiling = a.tuning
@@ -400,7 +400,8 @@ def d3_leg(hpic, torch, W, steps, tune_steps, precision=True, tiling=None):
     a.step(1)
     da = a.diagnostics(0)
     a.close()
-    b, t64, _ = run_form(hpic, torch, [d], "fp64", warm, steps, tune_steps=tune, tiling=tiling)
+    b, t64, _ = run_form(hpic, torch, [d], "fp64", warm, steps, tune_steps=tune,
+                         tiling=fixed_tiling)
     b.close()
     v32 = npart * steps / t32
     pd_ms, pd_n = kt["push_deposit"]
