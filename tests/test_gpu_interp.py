@@ -50,6 +50,26 @@ def test_2d_interp_changes_the_result(hpic):
     assert np.abs(out[0] - out[1]).max() > 1e-6 * np.abs(out[0]).max()
 
 
+def test_3d_energy_conserving_fp32_tracks_oracle(hpic):
+    """FP32 form with the energy-conserving gather, 10 steps, against the
+    oracle started from the FP32 particle state: the FP32 fields and push
+    (measured 1.7e-7 and 2.2e-7 of the field scale)."""
+    d = W.drift3d(16, 8, 8, spread=0.05, sigma_u=0.3, gamma=3.0, jitter=True, seed=14, sub=(2, 1, 1))
+    sim = hpic.from_workload(d, "fp32", interp=1)
+    raw = sim.particles_raw(0)
+    o = np.argsort(raw["id"])
+    g = oracle.grid3(*d["n"], *d["dx"], d["dt"], alpha=d["alpha"], jbg=d["jbg"], interp=1)
+    st = oracle.State3(g, d["qm"], raw["cell"][:, o] + raw["off"][:, o].astype(np.float64),
+                       raw["u"][:, o], raw["qw"][o])
+    sim.step(10)
+    st.step(10)
+    E1, B1 = sim.fields(0)
+    scale = max(np.abs(st.E).max(), np.abs(st.B).max())
+    assert np.abs(E1 - st.E).max() <= 1e-6 * scale
+    assert np.abs(B1 - st.B).max() <= 1e-6 * scale
+    sim.close()
+
+
 def test_3d_energy_conserving_matches_oracle(hpic):
     d = W.drift3d(16, 8, 8, spread=0.05, sigma_u=0.3, gamma=3.0, jitter=True, seed=14, sub=(2, 1, 1))
     sim = hpic.from_workload(d, "fp64", interp=1)
@@ -102,7 +122,9 @@ def _q3d_setup(hpic, prec, interp, seed=2):
     return sim, st, M
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 2e-3)])
+# FP32: rounding of the FP32 state over 20 steps (measured 1.2e-7 of the
+# field scale, 2.2e-7 in the momenta)
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-6)])
 def test_q3d_energy_conserving_matches_oracle(hpic, prec, tol):
     sim, st, M = _q3d_setup(hpic, prec, 1)
     sim.step(20)

@@ -153,10 +153,13 @@ def test_fp32_ten_steps_track_oracle(hpic):
     sim.step(10)
     st.step(10)
     E1, B1 = sim.fields(0)
+    # the oracle starts from the FP32 state: what remains is the FP32 push,
+    # gather and fields over 10 steps (measured relative L2 1.4e-7 (E) and
+    # 1.5e-7 (B), momenta 7.5e-7)
     for a, b in ((E1, st.E), (B1, st.B)):
-        assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(b)
+        assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(b)
     p = _by_id(sim.particles(0))
-    assert np.abs(p["u"] - st.u).max() <= 1e-4 * (1 + np.abs(st.u).max())
+    assert np.abs(p["u"] - st.u).max() <= 3e-6 * (1 + np.abs(st.u).max())
     sim.close()
 
 

@@ -103,9 +103,13 @@ def test_one_step_matches_oracle(hpic, prec, tol):
     sim.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 2e-3)])
+# FP32: the oracle starts from the exact inputs, so the error is the FP32
+# rounding of the particle state and the fields (a few units of 6e-8)
+# carried over 20 steps; measured 1.1e-7 and 1.2e-7 of the field scale, and
+# 2.2e-6 in the momenta (the FP32 mode gather with its FP32 phase factors)
+@pytest.mark.parametrize("prec,tol,tol_u", [("fp64", 1e-9, 1e-9), ("fp32", 1e-6, 1e-5)])
 @pytest.mark.parametrize("kmod", [0, 1])
-def test_many_steps_match_oracle(hpic, prec, tol, kmod):
+def test_many_steps_match_oracle(hpic, prec, tol, tol_u, kmod):
     sim, st, g = _setup(hpic, prec, seed=1, kmod=kmod)
     M = g.nmodes
     sim.step(20)
@@ -115,7 +119,7 @@ def test_many_steps_match_oracle(hpic, prec, tol, kmod):
     assert np.abs(E - st.E).max() <= tol * scale
     assert np.abs(B - st.B).max() <= tol * scale
     x, u = _particles(sim)
-    assert np.abs(u - st.u).max() <= tol * max(1.0, np.abs(st.u).max())
+    assert np.abs(u - st.u).max() <= tol_u * max(1.0, np.abs(st.u).max())
     sim.close()
 
 
