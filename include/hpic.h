@@ -237,7 +237,14 @@ typedef struct hp_tune {
 /* Sets the tile shape (1..4096 cells per direction; 3D tiles are
  * tile1 x tile2 x tile2) and sort interval
  * (1..1024 steps) and re-sorts the particles.  Results of the FP32_FIXED form
- * are bit-identical for every setting.  HP_EINVAL out of range. */
+ * are bit-identical for every setting.  HP_EINVAL out of range.
+ * Quasi-3D handles: the bins of the periodic particle sort, tile1 z columns x
+ * tile2 radial rows (default 4 x 2), and its interval (default 64 steps; a
+ * load sorts before the first step); the push works on waves of 64
+ * consecutive particles, so the bins set how compact a wave is.  The sort
+ * only permutes storage: FP32_FIXED results are bit-identical for every
+ * setting (FP64: equal to rounding, the deposit's atomics add in another
+ * order).  lds_bytes reads 0 for these handles. */
 int hp_set_tiling(hp_sim *sim, int32_t tile1, int32_t tile2, int32_t sort_interval);
 int hp_get_tiling(hp_sim *sim, hp_tune *out);
 

@@ -42,6 +42,10 @@ struct RunQ {
   const double *sym; // [n1][4]: i [k]1 xi+ (re, im), i [k]1 xi- (re, im), signed k1
   // particle side (np = 0: field solve only)
   PartsQ<R> pt;
+  PartsQ<R> pt2;     // the other particle buffer: target of the periodic sort
+  int *skey, *srank; // [np]: sort bin of each particle and its rank in the bin
+  int *sbin;         // [nbins + 1]: bin counts, then their exclusive prefix sums
+  int sbz, sbr, nbr, nbins;  // bins of sbz z columns x sbr radial rows, nbr bins along r
   int np;
   R qmhdt, dtdz, dtdr, rmax;  // q/m dt/2, dt/dz, dt/dr, limit of r/dr
   R wscale;                       // contribution scale: inv_wunit cj (FP32), 1 (FP64)
@@ -69,6 +73,10 @@ struct LaunchQ {
   // by its transform along z; NULL for the vacuum law)
   static void gauss(const RunQ<R> *runs, const Item *items, int nitems, int parity,
                     const double2 *rho, double *rows_out, int maxn1, hipStream_t s);
+  // counting sort of a run's particles by (z column, radial row) bin into
+  // pt2, then pt and pt2 swap places (in the device copy of the run; the
+  // caller swaps its host copy)
+  static void sort(RunQ<R> *run_dev, int np, int nbins, hipStream_t s);
   // gather, Boris, move and per-mode deposit into J[parity]; items (run,
   // first particle) of 256 particles
   static void push_deposit(const RunQ<R> *runs, const Item *items, int nitems, int parity,

@@ -731,6 +731,104 @@ __global__ void __launch_bounds__(256) k_q_jbg(const RunQ<R> *__restrict__ run, 
   }
 }
 
+// ---------------------------------------------------------------- sort
+// The particles of a wave come from consecutive storage slots; the loader
+// stores them by (z column, radial row), and a periodic counting sort by bins
+// of sbz columns x sbr rows keeps a wave's particles, and so its field copy
+// and its current box, compact as they move.  Order within a bin is the
+// order of the atomics: the FP32 form's integer deposit does not depend on it.
+template <class R>
+__device__ __forceinline__ int q_sort_bin(const RunQ<R> &r, const PartsQ<R> &P, int p) {
+  const float x = (float)G(P.ix)[p] + (float)G(P.fx)[p];
+  const float y = (float)G(P.iy)[p] + (float)G(P.fy)[p];
+  const int j = min(max((int)sqrtf(x * x + y * y), 0), r.n2 - 1);
+  return (G(P.cell)[p] / r.sbz) * r.nbr + j / r.sbr;
+}
+
+template <class R>
+__global__ void k_q_sort_clear(const RunQ<R> *__restrict__ run) {
+  const RunQ<R> &r = *run;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= r.nbins; i += gridDim.x * blockDim.x)
+    r.sbin[i] = 0;
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_q_sort_count(const RunQ<R> *__restrict__ run) {
+  const RunQ<R> &r = *run;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= r.np) return;
+  const int b = q_sort_bin<R>(r, r.pt, p);
+  r.skey[p] = b;
+  r.srank[p] = atomicAdd(r.sbin + b, 1);
+}
+
+// Exclusive prefix sum of the bin counts, one block of 1024 threads: each
+// thread sums a contiguous chunk, the block scans the chunk sums in LDS, and
+// each thread rewrites its chunk.
+template <class R>
+__global__ void __launch_bounds__(1024) k_q_sort_scan(const RunQ<R> *__restrict__ run) {
+  __shared__ int part[1024];
+  const RunQ<R> &r = *run;
+  const int n = r.nbins, t = threadIdx.x;
+  const int chunk = (n + 1023) / 1024, lo = min(n, t * chunk), hi = min(n, lo + chunk);
+  int sum = 0;
+  for (int i = lo; i < hi; ++i) sum += r.sbin[i];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run_sum = part[t] - sum;  // exclusive prefix of this chunk
+  for (int i = lo; i < hi; ++i) {
+    const int c = r.sbin[i];
+    r.sbin[i] = run_sum;
+    run_sum += c;
+  }
+  if (t == 1023) r.sbin[n] = part[1023];
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_q_sort_scatter(const RunQ<R> *__restrict__ run) {
+  const RunQ<R> &r = *run;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= r.np) return;
+  const int d = r.sbin[r.skey[p]] + r.srank[p];
+  const PartsQ<R> &A = r.pt, &B = r.pt2;
+  G(B.cell)[d] = G(A.cell)[p];
+  G(B.ix)[d] = G(A.ix)[p];
+  G(B.iy)[d] = G(A.iy)[p];
+  G(B.id)[d] = G(A.id)[p];
+  G(B.fz)[d] = G(A.fz)[p];
+  G(B.fx)[d] = G(A.fx)[p];
+  G(B.fy)[d] = G(A.fy)[p];
+  G(B.uz)[d] = G(A.uz)[p];
+  G(B.ux)[d] = G(A.ux)[p];
+  G(B.uy)[d] = G(A.uy)[p];
+  G(B.qw)[d] = G(A.qw)[p];
+}
+
+template <class R>
+__global__ void k_q_sort_swap(RunQ<R> *run) {
+  const PartsQ<R> t = run->pt;
+  run->pt = run->pt2;
+  run->pt2 = t;
+}
+
+template <class R>
+void LaunchQ<R>::sort(RunQ<R> *run_dev, int np, int nbins, hipStream_t s) {
+  if (np <= 0 || nbins <= 0) return;
+  const int pb = (np + 255) / 256;
+  hipLaunchKernelGGL(k_q_sort_clear<R>, dim3(std::min((nbins + 256) / 256, 1024)), dim3(256), 0, s,
+                     run_dev);
+  hipLaunchKernelGGL(k_q_sort_count<R>, dim3(pb), dim3(256), 0, s, run_dev);
+  hipLaunchKernelGGL(k_q_sort_scan<R>, dim3(1), dim3(1024), 0, s, run_dev);
+  hipLaunchKernelGGL(k_q_sort_scatter<R>, dim3(pb), dim3(256), 0, s, run_dev);
+  hipLaunchKernelGGL(k_q_sort_swap<R>, dim3(1), dim3(1), 0, s, run_dev);
+}
+
 template <class R>
 void LaunchQ<R>::push_deposit(const RunQ<R> *runs, const Item *items, int nitems, int parity,
                               unsigned *err, hipStream_t s) {
@@ -753,6 +851,8 @@ template void LaunchQ<float>::push_deposit(const RunQ<float> *, const Item *, in
                                            hipStream_t);
 template void LaunchQ<double>::push_deposit(const RunQ<double> *, const Item *, int, int,
                                             unsigned *, hipStream_t);
+template void LaunchQ<float>::sort(RunQ<float> *, int, int, hipStream_t);
+template void LaunchQ<double>::sort(RunQ<double> *, int, int, hipStream_t);
 template void LaunchQ<float>::rho(const RunQ<float> *, int, int, double2 *, hipStream_t);
 template void LaunchQ<double>::rho(const RunQ<double> *, int, int, double2 *, hipStream_t);
 template void LaunchQ<float>::jbg(const RunQ<float> *, int, double *, hipStream_t);

@@ -1803,7 +1803,7 @@ class SimQ : public SimBase {
     int jitem0 = 0;  // first (3 m + c, row) item of the run
     double qm = -1.0, q = -1.0;
     double2 *rho_bg = nullptr;  // [M][nr][n1] background charge density, or NULL
-    void *pbuf[11] = {nullptr};  // particle arrays
+    void *pbuf[24] = {nullptr};  // particle arrays (both buffers) and sort keys, ranks
   };
 
  public:
@@ -1917,7 +1917,8 @@ class SimQ : public SimBase {
     if ((rc = upload(rows, &d_rows_, &n_rows_)) || (rc = upload(upd, &d_upd_, &n_upd_)) ||
         (rc = upload(gitems, &d_gauss_, &n_gauss_)) || (rc = upload(jitems, &d_jitems_, &n_jitems_)))
       return rc;
-    if ((rc = alloc(&d_runs_, nruns)) || (rc = alloc(&d_err_, 1))) return rc;
+    if ((rc = alloc(&d_runs_, nruns)) || (rc = alloc(&d_err_, 1)) || (rc = set_bins(sbz_, sbr_)))
+      return rc;
     for (int i = 0; i < nruns; ++i) set_jconv(i);
     return upload_runs();
   }
@@ -1957,7 +1958,19 @@ class SimQ : public SimBase {
   int step(int nsteps) override {
     if (nsteps < 0) return fail(HP_EINVAL, "negative step count");
     for (int k = 0; k < nsteps; ++k) {
+      if (n_push_ > 0 && sort_interval_ > 0 && since_sort_ >= sort_interval_) {
+        mark(HP_K_SORT, true);
+        for (size_t i = 0; i < runs_.size(); ++i) {
+          RunQ<R> &d = runs_[i].d;
+          if (d.np <= 0) continue;
+          LaunchQ<R>::sort(d_runs_ + i, d.np, d.nbins, stream_);
+          std::swap(d.pt, d.pt2);  // the host copy follows the device's swap
+        }
+        mark(HP_K_SORT, false);
+        since_sort_ = 0;
+      }
       if (n_push_ > 0) {
+        ++since_sort_;
         mark(HP_K_PUSH_DEPOSIT, true);
         LaunchQ<R>::push_deposit(d_runs_, d_push_, n_push_, parity_, d_err_, stream_);
         mark(HP_K_PUSH_DEPOSIT, false);
@@ -2037,18 +2050,8 @@ class SimQ : public SimBase {
       wmax = std::max(wmax, std::fabs(q * w[p]));
       id[p] = (int)p;
     }
-    for (void *&b : h.pbuf) {
-      if (b) release(b);
-      b = nullptr;
-    }
+    if ((rc = alloc_parts(h, n))) return rc;
     PartsQ<R> &P = d.pt;
-    if ((rc = alloc(&P.cell, n)) || (rc = alloc(&P.fz, n)) || (rc = alloc(&P.ix, n)) ||
-        (rc = alloc(&P.fx, n)) || (rc = alloc(&P.iy, n)) || (rc = alloc(&P.fy, n)) ||
-        (rc = alloc(&P.uz, n)) || (rc = alloc(&P.ux, n)) || (rc = alloc(&P.uy, n)) ||
-        (rc = alloc(&P.qw, n)) || (rc = alloc(&P.id, n)))
-      return rc;
-    void *bufs[11] = {P.cell, P.fz, P.ix, P.fx, P.iy, P.fy, P.uz, P.ux, P.uy, P.qw, P.id};
-    for (int k = 0; k < 11; ++k) h.pbuf[k] = bufs[k];
     if (n > 0) {
       HIPCHK(hipMemcpy(P.cell, cell.data(), sizeof(int) * n, hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(P.fz, fz.data(), sizeof(R) * n, hipMemcpyHostToDevice));
@@ -2463,18 +2466,8 @@ class SimQ : public SimBase {
       o += sizeof meta;
       const int64_t n = (int64_t)meta[0];
       const size_t fn = (size_t)d.M * 6 * d.plane, jn = (size_t)d.M * 3 * d.plane;
-      for (void *&b : h.pbuf) {
-        if (b) release(b);
-        b = nullptr;
-      }
+      if ((rc = alloc_parts(h, n))) return rc;
       PartsQ<R> &P = d.pt;
-      if ((rc = alloc(&P.cell, n)) || (rc = alloc(&P.fz, n)) || (rc = alloc(&P.ix, n)) ||
-          (rc = alloc(&P.fx, n)) || (rc = alloc(&P.iy, n)) || (rc = alloc(&P.fy, n)) ||
-          (rc = alloc(&P.uz, n)) || (rc = alloc(&P.ux, n)) || (rc = alloc(&P.uy, n)) ||
-          (rc = alloc(&P.qw, n)) || (rc = alloc(&P.id, n)))
-        return rc;
-      void *bufs[11] = {P.cell, P.fz, P.ix, P.fx, P.iy, P.fy, P.uz, P.ux, P.uy, P.qw, P.id};
-      for (int k = 0; k < 11; ++k) h.pbuf[k] = bufs[k];
       int *ia[4] = {P.cell, P.ix, P.iy, P.id};
       R *ra[7] = {P.fz, P.fx, P.fy, P.uz, P.ux, P.uy, P.qw};
       for (int *a : ia)
@@ -2508,8 +2501,24 @@ class SimQ : public SimBase {
                     const float *, const float *, int64_t *) override { return na(); }
   int fixed_params(int, double *) override { return na(); }
   int push_stats(int64_t *) override { return na(); }
-  int set_tiling(int, int, int) override { return na(); }
-  int get_tiling(hp_tune *) override { return na(); }
+  // Quasi-3D: sort bins of tile1 z columns x tile2 radial rows, particles
+  // re-sorted every sort_interval steps.
+  int set_tiling(int t1, int t2, int k) override {
+    if (t1 < 1 || t1 > 4096 || t2 < 1 || t2 > 4096 || k < 1 || k > 1024)
+      return fail(HP_EINVAL, "tile sizes must be 1..4096 and the sort interval 1..1024");
+    int rc;
+    if ((rc = sync()) || (rc = set_bins(t1, t2))) return rc;
+    sort_interval_ = k;
+    return upload_runs();
+  }
+  int get_tiling(hp_tune *out) override {
+    if (!out) return fail(HP_EINVAL, "null output");
+    std::memset(out, 0, sizeof *out);
+    out->tile[0] = sbz_;
+    out->tile[1] = sbr_;
+    out->sort_interval = sort_interval_;
+    return HP_OK;
+  }
   int autotune(int, hp_tune *) override { return na(); }
 
  private:
@@ -2527,6 +2536,46 @@ class SimQ : public SimBase {
     }
     allocs_.push_back(q);
     *p = (T *)q;
+    return HP_OK;
+  }
+  // Both particle buffers and the sort's per-particle arrays of a run, for n
+  // particles (the previous ones released).
+  int alloc_parts(RunHostQ &h, int64_t n) {
+    for (void *&b : h.pbuf) {
+      if (b) release(b);
+      b = nullptr;
+    }
+    int k = 0, rc;
+    for (PartsQ<R> *P : {&h.d.pt, &h.d.pt2}) {
+      if ((rc = alloc(&P->cell, n)) || (rc = alloc(&P->fz, n)) || (rc = alloc(&P->ix, n)) ||
+          (rc = alloc(&P->fx, n)) || (rc = alloc(&P->iy, n)) || (rc = alloc(&P->fy, n)) ||
+          (rc = alloc(&P->uz, n)) || (rc = alloc(&P->ux, n)) || (rc = alloc(&P->uy, n)) ||
+          (rc = alloc(&P->qw, n)) || (rc = alloc(&P->id, n)))
+        return rc;
+      void *bufs[11] = {P->cell, P->fz, P->ix, P->fx, P->iy, P->fy, P->uz, P->ux, P->uy, P->qw, P->id};
+      for (void *b : bufs) h.pbuf[k++] = b;
+    }
+    if ((rc = alloc(&h.d.skey, n)) || (rc = alloc(&h.d.srank, n))) return rc;
+    h.pbuf[k++] = h.d.skey;
+    h.pbuf[k++] = h.d.srank;
+    since_sort_ = sort_interval_;  // sort before the first step
+    return HP_OK;
+  }
+  // Sort bins of sbz z columns x sbr radial rows for every run.
+  int set_bins(int sbz, int sbr) {
+    for (RunHostQ &h : runs_) {
+      RunQ<R> &d = h.d;
+      d.sbz = std::min(sbz, d.n1);
+      d.sbr = std::min(sbr, d.n2);
+      d.nbr = (d.n2 + d.sbr - 1) / d.sbr;
+      d.nbins = ((d.n1 + d.sbz - 1) / d.sbz) * d.nbr;
+      if (d.sbin) release(d.sbin);
+      d.sbin = nullptr;
+      int rc;
+      if ((rc = alloc(&d.sbin, (size_t)d.nbins + 1))) return rc;
+    }
+    sbz_ = sbz;
+    sbr_ = sbr;
     return HP_OK;
   }
   void release(void *p) {
@@ -2612,6 +2661,12 @@ class SimQ : public SimBase {
   std::vector<Event2> events_;
   double kms_[HP_NK] = {0};
   int64_t kn_[HP_NK] = {0};
+  // particle sort: bins of sbz_ z columns x sbr_ radial rows, every
+  // sort_interval_ steps, and before the first step after a load (4 x 2
+  // cells: a wave's 64 particles of an 8-per-cell column then span few rows;
+  // on the 4096 x 256 drift 1.27 ms per push against 1.47 ms for 2 x 4 and
+  // 1.93 ms unsorted)
+  int sbz_ = 4, sbr_ = 2, sort_interval_ = 64, since_sort_ = 0;
 };
 
 int check_sim(hp_sim *s) {

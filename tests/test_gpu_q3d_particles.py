@@ -75,6 +75,11 @@ def _particles(sim):
     return p["x"][:, order], p["u"][:, order]
 
 
+def _by_id(p):
+    o = np.argsort(p["id"])
+    return {k: v[..., o] for k, v in p.items()}
+
+
 def _zdiff(a, b, L):
     return (a - b + 0.5 * L) % L - 0.5 * L
 
@@ -295,7 +300,7 @@ def test_state_resume_bitexact(hpic, prec):
     b.step(4)
     Ea, Ba = _read_fields(a, g.nmodes)
     Eb, Bb = _read_fields(b, g.nmodes)
-    pa, pb = a.particles(0), b.particles(0)
+    pa, pb = _by_id(a.particles(0)), _by_id(b.particles(0))
     if prec == "fp32":
         assert np.array_equal(Ea, Eb) and np.array_equal(Ba, Bb)
         for k in pa:
@@ -317,3 +322,35 @@ def test_state_resume_bitexact(hpic, prec):
         other.set_state(blob)
     for s in (a, b, other):
         s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_sort_leaves_the_steps_unchanged(hpic, prec):
+    """The periodic counting sort of the particles by (z column, radial row)
+    bin only permutes their storage: sorting every step and never sorting give
+    the same fields and particles, bit for bit in the FP32 form (integer
+    deposit), to rounding in the FP64 form (FP64 atomics)."""
+    a, _, g = _setup(hpic, prec, seed=31, uth=0.2)
+    b, _, _ = _setup(hpic, prec, seed=31, uth=0.2)
+    a.set_tiling(2, 4, 1)
+    b.set_tiling(2, 4, 1024)
+    assert tuple(a.tiling()["tile"]) == (2, 4) and a.tiling()["sort_interval"] == 1
+    a.step(30)
+    b.step(30)
+    Ea, Ba = _read_fields(a, g.nmodes)
+    Eb, Bb = _read_fields(b, g.nmodes)
+    ra, rb = a.particles(0), b.particles(0)
+    assert not np.array_equal(ra["id"], rb["id"])  # the sort did reorder
+    pa, pb = _by_id(ra), _by_id(rb)
+    if prec == "fp32":
+        assert np.array_equal(Ea, Eb) and np.array_equal(Ba, Bb)
+        for k in pa:
+            assert np.array_equal(pa[k], pb[k]), k
+    else:
+        scale = max(np.abs(Ea).max(), np.abs(Ba).max())
+        assert max(np.abs(Ea - Eb).max(), np.abs(Ba - Bb).max()) <= 1e-12 * scale
+        assert np.abs(pa["u"] - pb["u"]).max() <= 1e-12 * (1 + np.abs(pa["u"]).max())
+    for sim in (a, b):
+        with pytest.raises(hpic.HpError):
+            sim.set_tiling(0, 4, 8)
+        sim.close()
