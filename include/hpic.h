@@ -317,9 +317,18 @@ int hp_get_particles_raw(hp_sim *sim, int32_t run, int64_t n, int32_t *cell, flo
  * u[3][n] real, qw[n] real (charge times weight), id[n] (int32 index given at
  * loading).  Any pointer may be NULL; n must equal the particle count.
  *
+ * hp_get_current_device: the current j^{n-1/2} of the last step, component comp
+ * (0..2), as hp_get_current returns it (corrected = 0: as deposited, plus the
+ * background, in physical units on the j nodes; 1: after the correction of
+ * Eq. (11) and the filter, transformed back to x1), into out[count] double,
+ * count = cells, layout [n3][n2][n1].  The same values as the host read, bit
+ * for bit.
+ *
  * Errors: HP_EINVAL (a pointer that is not device memory, bad comp or count,
  * a quasi-3D handle). */
 int hp_get_field_device(hp_sim *sim, int32_t run, int32_t comp, void *out, size_t count);
+int hp_get_current_device(hp_sim *sim, int32_t run, int32_t comp, int32_t corrected, double *out,
+                          size_t count);
 int hp_get_particles_device(hp_sim *sim, int32_t run, int64_t n, int32_t *cell, void *off,
                             void *u, void *qw, int32_t *id);
 

@@ -517,6 +517,10 @@ void launch_scan_particles(const LoadGeom &g, long long n, const double *x, cons
                            const double *w, double q, int *count, unsigned long long *qbits,
                            unsigned *bad, hipStream_t s);
 void launch_max_int(const int *a, long long n, int *out, hipStream_t s);
+template <class A>
+void launch_current_out(const A *raw, long long n, double f, double bg, double *out, hipStream_t s);
+template <class R>
+void launch_real_to_double(const R *in, long long n, double *out, hipStream_t s);
 void launch_zero_i64(long long *p, long long n, hipStream_t s);
 // Conversion pass: the run's structure of arrays A in input order.
 template <class R>

@@ -140,6 +140,42 @@ __global__ void k_unload_particles(const Run<R> *run_dev, int pp, int *cell, R *
   if (id) id[p] = A.id[p];
 }
 
+// out[i] = raw[i] f + bg in FP64, one rounding per operation as on the host
+// (the deposited current in physical units from the accumulators).
+template <class A>
+__global__ void k_current_out(const A *raw, long long n, double f, double bg, double *out) {
+#pragma clang fp contract(off)
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = (double)raw[i] * f + bg;
+}
+
+template <class R>
+__global__ void k_real_to_double(const R *in, long long n, double *out) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = (double)in[i];
+}
+
+template <class A>
+void launch_current_out(const A *raw, long long n, double f, double bg, double *out, hipStream_t s) {
+  if (n <= 0) return;
+  const long long blocks = std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_current_out<A>, dim3((unsigned)blocks), dim3(256), 0, s, raw, n, f, bg, out);
+}
+template <class R>
+void launch_real_to_double(const R *in, long long n, double *out, hipStream_t s) {
+  if (n <= 0) return;
+  const long long blocks = std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_real_to_double<R>, dim3((unsigned)blocks), dim3(256), 0, s, in, n, out);
+}
+template void launch_current_out<long long>(const long long *, long long, double, double, double *,
+                                            hipStream_t);
+template void launch_current_out<double>(const double *, long long, double, double, double *,
+                                         hipStream_t);
+template void launch_real_to_double<float>(const float *, long long, double *, hipStream_t);
+template void launch_real_to_double<double>(const double *, long long, double *, hipStream_t);
+
 // p[0..n) = 0 (a kernel rather than a memset, so that a captured graph clears
 // it on every replay).
 __global__ void k_zero_i64(long long *p, long long n) {

@@ -183,6 +183,9 @@ struct SimBase {
   virtual int get_particles_device(int, int64_t, int32_t *, void *, void *, void *, int32_t *) {
     return fail(HP_EINVAL, "device-buffer particle reads exist for Cartesian runs only");
   }
+  virtual int get_current_device(int, int, int, double *, size_t) {
+    return fail(HP_EINVAL, "device-buffer current reads exist for Cartesian runs only");
+  }
   virtual int debug_deposit_noalloc(int, int64_t, const int32_t *, const float *, const int32_t *,
                                     const float *, const float *, const float *, int64_t *) {
     return fail(HP_EINVAL, "the deposit entry point is for 2D Cartesian runs only");
@@ -533,6 +536,34 @@ class Sim : public SimBase {
       if (p && !device_pointer(p)) return fail(HP_EINVAL, "outputs must be device memory");
     launch_unload_particles<R>(d_runs_ + run, pp_, (int)n, cell, (R *)off, (R *)u, (R *)qw, id,
                                stream_);
+    HIPCHK(hipGetLastError());
+    return HP_OK;
+  }
+
+  // The current of the last step into a device buffer (FP64, as get_current);
+  // asynchronous on the stream.
+  int get_current_device(int run, int comp, int corrected, double *out, size_t count) override {
+    const RunHost &h = runs_[run];
+    const Run<R> &d = h.d;
+    const size_t cells = (size_t)d.cells;
+    if (comp < 0 || comp > 2 || count != cells) return fail(HP_EINVAL, "bad current request");
+    if (!device_pointer(out)) return fail(HP_EINVAL, "output must be device memory");
+    if (corrected) {
+      if (cur_tmp_n_ < cells) {
+        int rc;
+        if (cur_tmp_) release(cur_tmp_);
+        cur_tmp_ = nullptr;
+        cur_tmp_n_ = 0;
+        if ((rc = alloc(&cur_tmp_, cells))) return rc;
+        cur_tmp_n_ = cells;
+      }
+      launch_inverse_rows<R>(d.Jk + (size_t)comp * d.rows * d.nk, d.nk, d.n1, d.rows, d.tw,
+                             d.inv_m, cur_tmp_, stream_);
+      launch_real_to_double<R>(cur_tmp_, (long long)cells, out, stream_);
+    } else {
+      launch_current_out<Acc>(d.J[parity_ ^ 1] + comp * cells, (long long)cells,
+                              acc_factor(h, comp), h.jbg[comp], out, stream_);
+    }
     HIPCHK(hipGetLastError());
     return HP_OK;
   }
@@ -1768,6 +1799,8 @@ class Sim : public SimBase {
   int sort_interval_ = DEFAULT_SORT_INTERVAL, since_sort_ = 0;
   unsigned *d_stats_ = nullptr;
   int tile1_ = TILE1, tile2_ = TILE2, push_lds_ = PUSH_LDS_MIN;
+  R *cur_tmp_ = nullptr;  // staging of hp_get_current_device (corrected current)
+  size_t cur_tmp_n_ = 0;
   int dim_ = 2;
   double tuned_ms_ = 0.0;
   bool use_graphs_ = true;
@@ -2820,6 +2853,12 @@ int hp_get_particles_device(hp_sim *sim, int32_t run, int64_t n, int32_t *cell, 
                             void *u, void *qw, int32_t *id) {
   return with_run(sim, run,
                   [&] { return sim->impl->get_particles_device(run, n, cell, off, u, qw, id); });
+}
+
+int hp_get_current_device(hp_sim *sim, int32_t run, int32_t comp, int32_t corrected, double *out,
+                          size_t count) {
+  return with_run(sim, run,
+                  [&] { return sim->impl->get_current_device(run, comp, corrected, out, count); });
 }
 
 int hp_set_fields(hp_sim *sim, int32_t run, int32_t mode, const double *E, const double *B) {

@@ -29,7 +29,7 @@ ABI = (
     "hp_debug_deposit", "hp_get_fixed_params", "hp_profile", "hp_get_kernel_times",
     "hp_get_push_stats", "hp_use_graphs", "hp_set_tiling", "hp_get_tiling", "hp_autotune",
     "hp_get_current_mode", "hp_set_particles_device", "hp_get_field_device",
-    "hp_get_particles_device", "hp_debug_deposit_noalloc",
+    "hp_get_particles_device", "hp_get_current_device", "hp_debug_deposit_noalloc",
 )
 
 
@@ -124,6 +124,7 @@ def lib():
                                         ctypes.c_double],
             "hp_get_field_device": [_P, i32, i32, _P, sz],
             "hp_get_particles_device": [_P, i32, i64, _P, _P, _P, _P, _P],
+            "hp_get_current_device": [_P, i32, i32, i32, _P, sz],
             "hp_debug_deposit_noalloc": [_P, i32, i64, _P, _P, _P, _P, _P, _P, _P],
         }
         for name, args in sigs.items():
@@ -248,6 +249,14 @@ class Sim:
         _check(lib().hp_get_field_device(self.h, run, int(comp),
                                          _dptr(out, self._real(run), self.shape(run)),
                                          int(np.prod(self.shape(run)))))
+
+    def current_device(self, run, comp, out, corrected=False):
+        """Current component comp of the last step into the float64 device
+        tensor out (shape of the run's grid), as current() returns it;
+        asynchronous on the handle's stream."""
+        _check(lib().hp_get_current_device(self.h, run, int(comp), int(bool(corrected)),
+                                           _dptr(out, "float64", self.shape(run)),
+                                           int(np.prod(self.shape(run)))))
 
     def particles_device(self, run, cell=None, off=None, u=None, qw=None, pid=None):
         """Particle state into device tensors (any may be None): cell int32

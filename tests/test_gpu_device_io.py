@@ -3,9 +3,10 @@ field/particle output, Sec. 2, with caller-owned device memory):
 hp_set_particles_device loads from FP64 device tensors with the same
 conversion as the host loader, so the run's state is the same bit for bit and
 so are the fields after steps (the FP32 form; the FP64 form's atomics make
-them equal to rounding); hp_get_field_device and hp_get_particles_device
-return what the host reads return; host pointers, quasi-3D handles and
-non-finite input are rejected without changing the run."""
+them equal to rounding); hp_get_field_device, hp_get_particles_device and
+hp_get_current_device return what the host reads return; host pointers,
+quasi-3D handles and non-finite input are rejected without changing the
+run."""
 import ctypes
 
 import numpy as np
@@ -80,6 +81,13 @@ def test_device_reads_equal_host_reads(hpic, precision):
     sim.synchronize()
     E, B = sim.fields(0)
     assert np.array_equal(F.cpu().numpy().astype(np.float64), np.concatenate([E, B]))
+    for corrected in (False, True):
+        J = torch.empty((3,) + sim.shape(0), dtype=torch.float64, device=dev)
+        for c in range(3):
+            sim.current_device(0, c, J[c], corrected=corrected)
+        sim.synchronize()
+        want = np.stack([sim.current(0, c, corrected=corrected) for c in range(3)])
+        assert np.array_equal(J.cpu().numpy(), want), corrected
     if precision == "fp32":
         raw = sim.particles_raw(0)
         for k, t in (("cell", cell), ("off", off), ("u", u), ("qw", qw), ("id", pid)):
@@ -111,6 +119,9 @@ def test_device_entry_points_reject_bad_input(hpic):
     out = np.empty(sim.shape(0), dtype=np.float32)
     assert hpic.lib().hp_get_field_device(sim.h, 0, 0, out.ctypes.data_as(ctypes.c_void_p),
                                           out.size) == hpic.HP_EINVAL
+    out64 = np.empty(sim.shape(0))
+    assert hpic.lib().hp_get_current_device(sim.h, 0, 0, 0, out64.ctypes.data_as(ctypes.c_void_p),
+                                            out64.size) == hpic.HP_EINVAL
     # a non-finite input leaves the run as it was
     u_bad = u.clone()
     u_bad[1, n // 2] = float("nan")
