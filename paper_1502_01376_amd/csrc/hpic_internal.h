@@ -381,6 +381,27 @@ __device__ __forceinline__ int wrap_small(int i, int n) {
   return i;
 }
 
+// Wave-aggregated atomic add of 1 per lane to cnt[key]: lanes with equal keys
+// share one atomic; returns the lane's rank among the previous value and its
+// peers (so the result equals a per-lane atomicAdd(cnt + key, 1) up to the
+// order among peers).
+__device__ __forceinline__ int wave_atomic_inc(int *cnt, int key, bool active) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(active);
+  int result = 0;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lk = __shfl(key, leader);
+    const unsigned long long same = __ballot(active && key == lk) & todo;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(cnt + lk, __popcll(same));
+    base = __shfl(base, leader);
+    if (active && key == lk) result = base + __popcll(same & ((1ull << lane) - 1));
+    todo &= ~same;
+  }
+  return result;
+}
+
 // Error bits of the device error word.
 enum : unsigned { ERR_RANGE = 1u, ERR_NUMERIC = 2u };
 

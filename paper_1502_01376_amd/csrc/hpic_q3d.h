@@ -45,6 +45,7 @@ struct RunQ {
   PartsQ<R> pt2;     // the other particle buffer: target of the periodic sort
   int *skey, *srank; // [np]: sort bin of each particle and its rank in the bin
   int *sbin;         // [nbins + 1]: bin counts, then their exclusive prefix sums
+  int *ssum;         // [ceil(nbins / 1024) + 1]: per-block sums of the scan
   int sbz, sbr, nbr, nbins;  // bins of sbz z columns x sbr radial rows, nbr bins along r
   int np;
   R qmhdt, dtdz, dtdr, rmax;  // q/m dt/2, dt/dz, dt/dr, limit of r/dr

@@ -756,38 +756,65 @@ template <class R>
 __global__ void __launch_bounds__(256) k_q_sort_count(const RunQ<R> *__restrict__ run) {
   const RunQ<R> &r = *run;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= r.np) return;
-  const int b = q_sort_bin<R>(r, r.pt, p);
+  const bool active = p < r.np;
+  // neighbours in storage share bins: one atomic per distinct bin of a wave
+  const int b = active ? q_sort_bin<R>(r, r.pt, p) : 0;
+  const int rank = wave_atomic_inc(r.sbin, b, active);
+  if (!active) return;
   r.skey[p] = b;
-  r.srank[p] = atomicAdd(r.sbin + b, 1);
+  r.srank[p] = rank;
 }
 
-// Exclusive prefix sum of the bin counts, one block of 1024 threads: each
-// thread sums a contiguous chunk, the block scans the chunk sums in LDS, and
-// each thread rewrites its chunk.
-template <class R>
-__global__ void __launch_bounds__(1024) k_q_sort_scan(const RunQ<R> *__restrict__ run) {
-  __shared__ int part[1024];
-  const RunQ<R> &r = *run;
-  const int n = r.nbins, t = threadIdx.x;
-  const int chunk = (n + 1023) / 1024, lo = min(n, t * chunk), hi = min(n, lo + chunk);
-  int sum = 0;
-  for (int i = lo; i < hi; ++i) sum += r.sbin[i];
-  part[t] = sum;
+// Exclusive prefix sum of the bin counts in three launches: each block of
+// 1024 threads scans its 1024 bins in LDS and records their sum; one block
+// scans the block sums (a contiguous chunk per thread, then across threads);
+// every block adds its offset.
+__device__ __forceinline__ int block_scan_incl(int v, int *part) {
+  const int t = threadIdx.x;
+  part[t] = v;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
-    const int v = t >= off ? part[t - off] : 0;
+    const int w = t >= off ? part[t - off] : 0;
     __syncthreads();
-    part[t] += v;
+    part[t] += w;
     __syncthreads();
   }
-  int run_sum = part[t] - sum;  // exclusive prefix of this chunk
+  return part[t];
+}
+
+template <class R>
+__global__ void __launch_bounds__(1024) k_q_scan_local(const RunQ<R> *__restrict__ run) {
+  __shared__ int part[1024];
+  const RunQ<R> &r = *run;
+  const int i = blockIdx.x * 1024 + threadIdx.x;
+  const int v = i < r.nbins ? r.sbin[i] : 0;
+  const int inc = block_scan_incl(v, part);
+  if (i < r.nbins) r.sbin[i] = inc - v;
+  if (threadIdx.x == 1023) r.ssum[blockIdx.x] = inc;
+}
+
+template <class R>
+__global__ void __launch_bounds__(1024) k_q_scan_sums(const RunQ<R> *__restrict__ run) {
+  __shared__ int part[1024];
+  const RunQ<R> &r = *run;
+  const int n = (r.nbins + 1023) / 1024, t = threadIdx.x;
+  const int chunk = (n + 1023) / 1024, lo = min(n, t * chunk), hi = min(n, lo + chunk);
+  int sum = 0;
+  for (int i = lo; i < hi; ++i) sum += r.ssum[i];
+  int run_sum = block_scan_incl(sum, part) - sum;  // exclusive prefix of this chunk
   for (int i = lo; i < hi; ++i) {
-    const int c = r.sbin[i];
-    r.sbin[i] = run_sum;
+    const int c = r.ssum[i];
+    r.ssum[i] = run_sum;
     run_sum += c;
   }
-  if (t == 1023) r.sbin[n] = part[1023];
+  if (t == 1023) r.sbin[r.nbins] = part[1023];
+}
+
+template <class R>
+__global__ void __launch_bounds__(1024) k_q_scan_add(const RunQ<R> *__restrict__ run) {
+  const RunQ<R> &r = *run;
+  const int i = blockIdx.x * 1024 + threadIdx.x;
+  if (i < r.nbins) r.sbin[i] += r.ssum[blockIdx.x];
 }
 
 template <class R>
@@ -824,7 +851,10 @@ void LaunchQ<R>::sort(RunQ<R> *run_dev, int np, int nbins, hipStream_t s) {
   hipLaunchKernelGGL(k_q_sort_clear<R>, dim3(std::min((nbins + 256) / 256, 1024)), dim3(256), 0, s,
                      run_dev);
   hipLaunchKernelGGL(k_q_sort_count<R>, dim3(pb), dim3(256), 0, s, run_dev);
-  hipLaunchKernelGGL(k_q_sort_scan<R>, dim3(1), dim3(1024), 0, s, run_dev);
+  const int sb = (nbins + 1023) / 1024;
+  hipLaunchKernelGGL(k_q_scan_local<R>, dim3(sb), dim3(1024), 0, s, run_dev);
+  hipLaunchKernelGGL(k_q_scan_sums<R>, dim3(1), dim3(1024), 0, s, run_dev);
+  hipLaunchKernelGGL(k_q_scan_add<R>, dim3(sb), dim3(1024), 0, s, run_dev);
   hipLaunchKernelGGL(k_q_sort_scatter<R>, dim3(pb), dim3(256), 0, s, run_dev);
   hipLaunchKernelGGL(k_q_sort_swap<R>, dim3(1), dim3(1), 0, s, run_dev);
 }

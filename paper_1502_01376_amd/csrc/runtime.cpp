@@ -2603,9 +2603,12 @@ class SimQ : public SimBase {
       d.nbr = (d.n2 + d.sbr - 1) / d.sbr;
       d.nbins = ((d.n1 + d.sbz - 1) / d.sbz) * d.nbr;
       if (d.sbin) release(d.sbin);
-      d.sbin = nullptr;
+      if (d.ssum) release(d.ssum);
+      d.sbin = d.ssum = nullptr;
       int rc;
-      if ((rc = alloc(&d.sbin, (size_t)d.nbins + 1))) return rc;
+      if ((rc = alloc(&d.sbin, (size_t)d.nbins + 1)) ||
+          (rc = alloc(&d.ssum, (size_t)(d.nbins + 1023) / 1024 + 1)))
+        return rc;
     }
     sbz_ = sbz;
     sbr_ = sbr;
