@@ -114,6 +114,13 @@ def timed_steps(torch, sim, warmup, steps, align=True):
     return t1 - t0
 
 
+def _as_tiling(t):
+    """[T1, T2, K] of a tiling record (the FP64 form runs at the FP32 form's
+    tiling: its own short autotuning picked tiles whose boxes outgrow the LDS
+    budget later in a run)."""
+    return [t["tile"][0], t["tile"][1], t["sort_interval"]]
+
+
 def run_form(hpic, torch, ds, precision, warmup, steps, profile=False, tune_steps=0, tiling=None,
              **cfg_kw):
     """Untimed: the autotuner (tune_steps steps, picking tile shape and sort
@@ -341,7 +348,7 @@ def scan_leg(hpic, torch, W, steps, tune_steps, precision=True):
     a, t32, _ = run_form(hpic, torch, ds, "fp32", warm, steps, tune_steps=tune_steps)
     tiling = a.tuning
     a.close()
-    b, t64, _ = run_form(hpic, torch, ds, "fp64", warm, steps, tune_steps=tune_steps)
+    b, t64, _ = run_form(hpic, torch, ds, "fp64", warm, steps, tiling=_as_tiling(tiling))
     b.close()
     v32 = npart * steps / t32
     v64 = npart * steps / t64
@@ -400,8 +407,9 @@ def d3_leg(hpic, torch, W, steps, tune_steps, precision=True, fixed_tiling=None)
     a.step(1)
     da = a.diagnostics(0)
     a.close()
-    b, t64, _ = run_form(hpic, torch, [d], "fp64", warm, steps, tune_steps=tune,
-                         tiling=fixed_tiling)
+    b, t64, _ = run_form(hpic, torch, [d], "fp64", warm, steps,
+                         tiling=fixed_tiling or _as_tiling(tiling))
+    tiling64 = b.tuning
     b.close()
     v32 = npart * steps / t32
     pd_ms, pd_n = kt["push_deposit"]
@@ -410,7 +418,7 @@ def d3_leg(hpic, torch, W, steps, tune_steps, precision=True, fixed_tiling=None)
     out = {"workload": d["name"], "n": list(d["n"]), "particles": npart, "steps": steps,
            "value": v32, "unit": "particle-steps/s", "ms_per_step": 1e3 * t32 / steps,
            "fp64_form": {"value": npart * steps / t64, "ms_per_step": 1e3 * t64 / steps,
-                         "fp32_speedup": t64 / t32},
+                         "fp32_speedup": t64 / t32, "tiling": tiling64},
            "kernels": {k: {"avg_us": 1e3 * ms / max(n, 1), "launches": n} for k, (ms, n) in kt.items()},
            "lds_fallback_tiles": push_stats["fallback_tiles"], "tiling": tiling,
            "residuals_fp32": {"after_steps": da["step"],
@@ -641,7 +649,7 @@ def main():
         args.fp64_steps = args.steps
     if args.fp64_steps > 0:
         sim64, t64, _ = run_form(hpic, torch, [d], "fp64", args.warmup, args.fp64_steps,
-                                 tune_steps=args.tune_steps, tiling=tiling)
+                                 tiling=tiling or _as_tiling(chosen))
         sim64.close()
         out["fp64_form"] = {"value": npart * args.fp64_steps / t64,
                             "ms_per_step": 1e3 * t64 / args.fp64_steps,
