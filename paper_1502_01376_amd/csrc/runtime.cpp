@@ -880,6 +880,18 @@ class Sim : public SimBase {
                                                     {128, 4}, {16, 8}, {128, 2}};
     std::vector<std::vector<int>> seen;
     const int K0 = bestK;
+    // a shape whose current box, grown by one cell of particle spread per
+    // axis, no longer fits the LDS budget would send its tiles to global
+    // atomics later in a run (a short trial does not see that): skipped
+    const int lds_max = (FIXED && dim_ == 3) ? PUSH3_LDS_MAX_FP32 : PUSH_LDS_MAX;
+    auto fits = [&](int t1, int t2) {
+      for (const RunHost &h : runs_) {
+        const long long w = std::min(t1, h.d.n1) + 6, hh = std::min(t2, h.d.n2) + 6;
+        const long long dd = h.d.dim == 3 ? std::min(t2, h.d.n3) + 6 : 1;
+        if (w * hh * dd * 3 * (long long)sizeof(Acc) > lds_max) return false;
+      }
+      return true;
+    };
     for (const auto &sh : shapes) {
       std::vector<int> key;
       for (const RunHost &h : runs_) {
@@ -889,6 +901,7 @@ class Sim : public SimBase {
       }
       if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
       seen.push_back(key);
+      if (!fits(sh[0], sh[1])) continue;
       if (left < 2 * K0) break;
       double ms;
       if ((rc = trial(sh[0], sh[1], K0, &ms))) break;
