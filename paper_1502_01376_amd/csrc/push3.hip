@@ -3,17 +3,18 @@
 // and the 3D charge density of the diagnostics.
 //
 // One workgroup per particle tile (T1 x T2 x T3 cells).  The tile's particles
-// gather the 27-node quadratic stencil of each field component through the
-// cache (the 3D field box of a tile does not fit LDS next to the current box),
-// and deposit into an LDS copy of the current box that is added to the global
-// accumulators with one atomic per touched node.  Too large a box falls back
-// to depositing with global atomics.
+// gather the 27-node quadratic stencil of each field component, in the FP32
+// form from a copy of the tile's field box staged in LDS when it fits next to
+// the current box (else, and in the FP64 form, through the cache), and deposit
+// into an LDS copy of the current box that is added to the global accumulators
+// with one atomic per touched node.  Too large a box falls back to depositing
+// with global atomics.
 //
-// FP32 form: the Esirkepov weights are computed in FP32 and each node's
-// contribution is rounded once to an integer, accumulated in 64 bits: the
-// result does not depend on the order of the atomics.  (An exact integer
-// scheme as in 2D would need products of three shape factors plus the charge,
-// more than 64 bits for general charges.)
+// FP32 form: the Esirkepov weights of the FP32 offsets are computed in FP64
+// and each node's contribution is rounded once to an integer, accumulated in
+// 64 bits: the result does not depend on the order of the atomics.  (An exact
+// integer scheme as in 2D would need products of three shape factors plus the
+// charge, more than 64 bits for general charges.)
 #include "hpic_internal.h"
 
 namespace hp {
@@ -191,12 +192,15 @@ struct Sink3GlobalF64 {
 // holds to about 2^-41 of a particle's charge per node and step (with FP32
 // weights and a 2^28 scale, long drifting-beam runs grew a spurious k1 = 0
 // mode).  FP64 form: g = qw (-dx_d/dt) / 6, physical current.
-// FP64 form: where no particle of the wave changes its nearest node along an
-// axis, the stencil is three nodes wide there (the fourth row of S0 and S1 is
-// zero, the last running sum C[2] along that axis only the rounding of 1 - 1)
-// and both blocks of terms are skipped for the whole wave.  (The same skip in
-// the FP32 form, exact there since C[2] stays below half a unit after the
-// 2^40 scale, cost more in register spills than it saved.)
+// Where no particle of the wave changes its nearest node along an axis, the
+// stencil is three nodes wide there (the fourth row of S0 and S1 is zero, the
+// last running sum C[2] along that axis only the rounding of 1 - 1) and both
+// blocks of terms are skipped for the whole wave.  In the FP32 form the skip
+// is exact: the skipped rows add exact zeros, and |C[2]| is a few units of
+// 2^-53, so |C[2] g T| < 2^-53 x 8 x 2^40 x 3.4 stays far below the half
+// unit that would round away from zero.  The FP32 form walks the nodes (i, j)
+// of the two other axes outside the three running sums, so only one bracket
+// T is live at a time (the whole 4 x 4 block of brackets spilled registers).
 template <class Sink>
 __device__ __forceinline__ void deposit3_fixed(const Sink &K, float inv_wunit, float cj,
                                                const int l[3], const float fa[3], const int dd[3],
@@ -204,12 +208,14 @@ __device__ __forceinline__ void deposit3_fixed(const Sink &K, float inv_wunit, f
 #pragma clang fp contract(off)
   double S0[3][4], S1[3][4], C[3][4];
   int o[3][4];
+  bool w4[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     double sa[3], sb[3];
     const int na = dshape3(l[d], (double)fa[d], sa);
     const int nb = dshape3(l[d] + dd[d], (double)fb[d], sb);
     const int base = min(na, nb) - 1;
+    w4[d] = __ballot(na != nb) != 0;
     place4_3(sa, na - 1 - base, S0[d]);
     place4_3(sb, nb - 1 - base, S1[d]);
     double acc = 0.0;
@@ -224,24 +230,28 @@ __device__ __forceinline__ void deposit3_fixed(const Sink &K, float inv_wunit, f
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int e = (d + 1) % 3, f = (d + 2) % 3;
-    double u0[4], u1[4], T[4][4];
+    double u0[4], u1[4], cg[3];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       u0[j] = 2.0 * S0[f][j] + S1[f][j];
       u1[j] = S0[f][j] + 2.0 * S1[f][j];
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 3; ++k) cg[k] = C[d][k] * gq;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) T[i][j] = S0[e][i] * u0[j] + S1[e][i] * u1[j];
+    for (int i = 0; i < 4; ++i) {
+      if (i == 3 && !w4[e]) continue;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double cg = C[d][k] * gq;
+      for (int j = 0; j < 4; ++j) {
+        if (j == 3 && !w4[f]) continue;
+        const double T = S0[e][i] * u0[j] + S1[e][i] * u1[j];
+        const int oij = o[e][i] + o[f][j];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          K.add(d, o[d][k] + o[e][i] + o[f][j], rint_i64(cg * T[i][j]));
+        for (int k = 0; k < 3; ++k) {
+          if (k == 2 && !w4[d]) continue;
+          K.add(d, o[d][k] + oij, rint_i64(cg[k] * T));
+        }
+      }
     }
   }
 }
