@@ -140,12 +140,20 @@ __device__ __forceinline__ void place4_3(const T s[3], int off, T out[4]) {
 }
 
 // Current sinks: node offset = o1[a] + o2[b] + o3[c] (from offs()), add().
+// (FP32 form: node offsets in bytes, so that an address is one add)
 struct Sink3Lds {
-  unsigned long long *J;
-  int W, WH, vol;
-  __device__ int offs(int axis, int i) const { return axis == 0 ? i : (axis == 1 ? i * W : i * WH); }
-  __device__ void add(int c, int off, long long v) const {
-    if (v != 0) atomicAdd(J + c * vol + off, (unsigned long long)v);
+  unsigned char __attribute__((address_space(3))) *J;
+  int W8, WH8, vol8;
+  static __device__ Sink3Lds make(void *lj, int W, int WH, int vol) {
+    return Sink3Lds{(unsigned char __attribute__((address_space(3))) *)lj, 8 * W, 8 * WH, 8 * vol};
+  }
+  __device__ int offs(int axis, int i) const { return axis == 0 ? 8 * i : (axis == 1 ? i * W8 : i * WH8); }
+  using Base = unsigned char __attribute__((address_space(3))) *;
+  __device__ Base base(int c, int off) const { return J + c * vol8 + off; }
+  __device__ void put(Base b, int off, long long v) const {
+    if (v != 0)
+      __hip_atomic_fetch_add((unsigned long long __attribute__((address_space(3))) *)(b + off),
+                             (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 };
 struct Sink3Global {
@@ -154,15 +162,20 @@ struct Sink3Global {
   __device__ int offs(int axis, int i) const {
     return axis == 0 ? wrap_pow2(i, n1) : (axis == 1 ? wrap_small(i, n2) * n1 : wrap_small(i, n3) * n12);
   }
-  __device__ void add(int c, int off, long long v) const {
+  using Base = gptr<unsigned long long>;
+  __device__ Base base(int c, int off) const { return J + c * cells + off; }
+  __device__ void put(Base b, int off, long long v) const {
     if (v != 0)
-      __scoped_atomic_fetch_add(J + c * cells + off, (unsigned long long)v, __ATOMIC_RELAXED,
+      __scoped_atomic_fetch_add(b + off, (unsigned long long)v, __ATOMIC_RELAXED,
                                 __MEMORY_SCOPE_DEVICE);
   }
 };
 struct Sink3LdsF64 {
   double *J;
   int W, WH, vol;
+  static __device__ Sink3LdsF64 make(void *lj, int W, int WH, int vol) {
+    return Sink3LdsF64{(double *)lj, W, WH, vol};
+  }
   __device__ int offs(int axis, int i) const { return axis == 0 ? i : (axis == 1 ? i * W : i * WH); }
   __device__ void add(int c, int off, double v) const {
     if (v != 0.0) unsafeAtomicAdd(J + c * vol + off, v);
@@ -236,8 +249,12 @@ __device__ __forceinline__ void deposit3_fixed(const Sink &K, float inv_wunit, f
       u0[j] = 2.0 * S0[f][j] + S1[f][j];
       u1[j] = S0[f][j] + 2.0 * S1[f][j];
     }
+    typename Sink::Base bk[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) cg[k] = C[d][k] * gq;
+    for (int k = 0; k < 3; ++k) {
+      cg[k] = C[d][k] * gq;
+      bk[k] = K.base(d, o[d][k]);
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (i == 3 && !w4[e]) continue;
@@ -249,7 +266,7 @@ __device__ __forceinline__ void deposit3_fixed(const Sink &K, float inv_wunit, f
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           if (k == 2 && !w4[d]) continue;
-          K.add(d, o[d][k] + oij, rint_i64(cg[k] * T));
+          K.put(bk[k], oij, rint_i64(cg[k] * T));
         }
       }
     }
@@ -350,13 +367,30 @@ template <class R> struct LdsF3 {
 // when S is local), Boris, move, deposit into K in the sink's frame (cell
 // l[]), store.  Returns the new packed cell (the old one if the particle was
 // rejected).
+template <class R> struct PState3 {
+  R f[3], u[3], qw;
+};
+template <class R>
+__device__ __forceinline__ PState3<R> load_state3(const Parts<R> &P, int p) {
+  PState3<R> s;
+  s.f[0] = G(P.f1)[p];
+  s.f[1] = G(P.f2)[p];
+  s.f[2] = G(P.f3)[p];
+  s.u[0] = G(P.u1)[p];
+  s.u[1] = G(P.u2)[p];
+  s.u[2] = G(P.u3)[p];
+  s.qw = G(P.qw)[p];
+  return s;
+}
+
 template <class R, class Src, class Sink>
 __device__ __forceinline__ int push_one3(const Run<R> &r, const Parts<R> &P, int p, int cell,
-                                         int g1, int g2, int g3, const int l[3], const Src &S,
-                                         const Sink &K, unsigned *err) {
-  const R f[3] = {G(P.f1)[p], G(P.f2)[p], G(P.f3)[p]};
-  R u[3] = {G(P.u1)[p], G(P.u2)[p], G(P.u3)[p]};
-  const R qw = G(P.qw)[p];
+                                         const PState3<R> &st, int g1, int g2, int g3,
+                                         const int l[3], const Src &S, const Sink &K,
+                                         unsigned *err) {
+  const R f[3] = {st.f[0], st.f[1], st.f[2]};
+  R u[3] = {st.u[0], st.u[1], st.u[2]};
+  const R qw = st.qw;
   const int n1 = r.n1, n2 = r.n2, n3 = r.n3, n12 = n1 * n2, cells = r.cells;
   // stencil weights and offsets, integer (i) and half (h) nodes per axis
   R wi[3][3], wh[3][3];
@@ -494,7 +528,7 @@ k_push_deposit3(const Run<R> *__restrict__ runs, const Item *__restrict__ items,
       int i1, i2, i3;
       unpack3(cell, r.log2n1, r.sh3, n1, i1, i2, i3);
       const int l[3] = {i1, i2, i3};
-      track(push_one3<R>(r, P, p, cell, i1, i2, i3, l, GlobalF3<R>{}, K, err));
+      track(push_one3<R>(r, P, p, cell, load_state3(P, p), i1, i2, i3, l, GlobalF3<R>{}, K, err));
     }
   } else {
     typename SK::T *lj = (typename SK::T *)smem_raw;
@@ -506,6 +540,16 @@ k_push_deposit3(const Run<R> *__restrict__ runs, const Item *__restrict__ items,
     const bool use_fl =
         sizeof(R) == 4 && jbytes + (size_t)6 * fplane * sizeof(R) <= (size_t)lds_bytes;
     const lptr3<R> fl = (lptr3<R>)(smem_raw + jbytes);
+    // FP32 form: the thread's first particle is loaded before the staging, so
+    // that its loads wait out the memory latency together with the staging's
+    const int p0 = start + (int)threadIdx.x;
+    constexpr bool pre = sizeof(R) == 4;
+    int cell0 = 0;
+    PState3<R> st0{};
+    if (pre && p0 < end) {
+      cell0 = G(P.cell)[p0];
+      st0 = load_state3(P, p0);
+    }
     for (int q = threadIdx.x; q < 3 * vol; q += 256) lj[q] = 0;
     if (use_fl) {
       const gptr<const R> F = G((const R *)r.F);
@@ -527,19 +571,27 @@ k_push_deposit3(const Run<R> *__restrict__ runs, const Item *__restrict__ items,
       }
     }
     __syncthreads();
-    const typename SK::L K{lj, W, W * H, vol};
+    const typename SK::L K = SK::L::make(lj, W, W * H, vol);
     const LdsF3<R> SL{fl, FW, FW * FH, fplane};
-    for (int p = start + threadIdx.x; p < end; p += 256) {
-      const int cell = G(P.cell)[p];
+    for (int p = p0; p < end; p += 256) {
+      int cell;
+      PState3<R> st;
+      if (pre && p == p0) {
+        cell = cell0;
+        st = st0;
+      } else {
+        cell = G(P.cell)[p];
+        st = load_state3(P, p);
+      }
       int i1, i2, i3;
       unpack3(cell, r.log2n1, r.sh3, n1, i1, i2, i3);
       const int l[3] = {wrap_delta_pow2_3(i1 - ref[0], n1) - lo[0] + 2,
                         wrap_delta_3(i2 - ref[1], n2) - lo[1] + 2,
                         wrap_delta_3(i3 - ref[2], n3) - lo[2] + 2};
       if (use_fl)
-        track(push_one3<R>(r, P, p, cell, i1, i2, i3, l, SL, K, err));
+        track(push_one3<R>(r, P, p, cell, st, i1, i2, i3, l, SL, K, err));
       else
-        track(push_one3<R>(r, P, p, cell, i1, i2, i3, l, GlobalF3<R>{}, K, err));
+        track(push_one3<R>(r, P, p, cell, st, i1, i2, i3, l, GlobalF3<R>{}, K, err));
     }
     __syncthreads();
     const auto J = G((typename SK::T *)r.J[parity]);

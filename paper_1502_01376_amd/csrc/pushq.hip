@@ -209,12 +209,16 @@ struct SinkLdsQ {
   int H, W, rlo, z0, per;  // z0: box column of global column 0 of the window frame
   int bzrel;               // box column of the window's first column
   __device__ __forceinline__ void window(int bz) { bzrel = bz + z0; }
-  __device__ __forceinline__ void operator()(int c, int m, int part, int row, int a, double v) const {
+  // the window's first node in row `row` of accumulator (c, m, part); the
+  // nodes of the row are then immediate offsets
+  using Row = lptr<A>;
+  __device__ __forceinline__ Row row(int c, int m, int part, int row) const {
     const int slot = c * per + (m == 0 ? 0 : 2 * m - 1 + part);
+    return box + (__mul24(__mul24(slot, H) + (row - rlo), W) + bzrel);
+  }
+  __device__ __forceinline__ void put(Row r, int a, double v) const {
     const A q = to_acc<A>(v);
-    if (q != A(0))
-      __hip_atomic_fetch_add(box + (slot * H + (row - rlo)) * W + (bzrel + a), q, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (q != A(0)) __hip_atomic_fetch_add(r + a, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 };
 template <class A>
@@ -226,12 +230,14 @@ struct SinkGlobQ {
 #pragma unroll
     for (int a = 0; a < 4; ++a) col[a] = wrap_pow2(bz + a, n1);
   }
-  __device__ __forceinline__ void operator()(int c, int m, int part, int row, int a, double v) const {
+  using Row = gptr<A>;
+  __device__ __forceinline__ Row row(int c, int m, int part, int row) const {
+    return G(J) + ((long long)(m * 3 + c) * plane + (long long)row * n1) * 2 + part;
+  }
+  __device__ __forceinline__ void put(Row r, int a, double v) const {
     const A q = to_acc<A>(v);
     if (q != A(0))
-      __hip_atomic_fetch_add(
-          G(J) + ((long long)(m * 3 + c) * plane + (long long)row * n1 + col[a]) * 2 + part, q,
-          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(r + 2 * col[a], q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 };
 __device__ __forceinline__ void glob_add(gptr<long long> p, long long v) {
@@ -277,11 +283,12 @@ __device__ __forceinline__ void deposit_q(const Sink &put, int M, const R S0z[4]
         if (odd) f = -f;
       }
       if (f == R(0)) continue;
+      const auto r0 = put.row(0, m, 0, row), r1 = put.row(0, m, 1, row);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const R w = Cz[a] * f;
-        put(0, m, 0, row, a, qr * w);
-        if (m > 0) put(0, m, 1, row, a, qi * w);
+        put.put(r0, a, qr * w);
+        if (m > 0) put.put(r1, a, qi * w);
       }
     }
     // r faces (face j at (j + 1/2) dr; face -1 lands on face 0)
@@ -294,12 +301,13 @@ __device__ __forceinline__ void deposit_q(const Sink &put, int M, const R S0z[4]
         if (!odd) f = -f;
       }
       if (f == R(0)) continue;
+      const auto r0 = put.row(1, m, 0, face), r1 = put.row(1, m, 1, face);
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const R w = Tz[a] * f;
         if (w == R(0)) continue;
-        put(1, m, 0, face, a, qr * w);
-        if (m > 0) put(1, m, 1, face, a, qi * w);
+        put.put(r0, a, qr * w);
+        if (m > 0) put.put(r1, a, qi * w);
       }
     }
     // azimuthal current
@@ -312,6 +320,7 @@ __device__ __forceinline__ void deposit_q(const Sink &put, int M, const R S0z[4]
       if (ghost) row = -row;
       const bool direct = m == 0 || (m == 1 && row == 0);
       if (!direct && row == 0) continue;
+      const auto r0 = put.row(2, m, 0, row), r1 = put.row(2, m, 1, row);
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         if (direct) {
@@ -320,16 +329,16 @@ __device__ __forceinline__ void deposit_q(const Sink &put, int M, const R S0z[4]
           if (W3 == R(0)) continue;
           R sv = cm * g * W3 * vthdt;
           if (ghost && !odd) sv = -sv;  // -(-1)^m
-          put(2, m, 0, row, a, sv * Pmr);
-          if (m > 0) put(2, m, 1, row, a, sv * Pmi);
+          put.put(r0, a, sv * Pmr);
+          if (m > 0) put.put(r1, a, sv * Pmi);
         } else {
           const R Wb = R(0.5) * (S0z[a] * S0r[b] + S1z[a] * S1r[b]);
           if (Wb == R(0)) continue;
           R sv = cm * g * Wb * inv_m;
           if (ghost && odd) sv = -sv;  // (-1)^m
           // i sv dP
-          put(2, m, 0, row, a, -sv * dPi);
-          put(2, m, 1, row, a, sv * dPr);
+          put.put(r0, a, -sv * dPi);
+          put.put(r1, a, sv * dPr);
         }
       }
     }
