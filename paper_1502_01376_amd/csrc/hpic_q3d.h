@@ -79,9 +79,10 @@ struct LaunchQ {
   // caller swaps its host copy)
   static void sort(RunQ<R> *run_dev, int np, int nbins, hipStream_t s);
   // gather, Boris, move and per-mode deposit into J[parity]; items (run,
-  // first particle) of 256 particles
+  // first particle) of 256 particles; modes: the mode count of every run in
+  // the launch, or 0 when they differ
   static void push_deposit(const RunQ<R> *runs, const Item *items, int nitems, int parity,
-                           unsigned *err, hipStream_t s);
+                           int modes, unsigned *err, hipStream_t s);
   // per (run, 3 m + c, row): accumulator J[parity] -> complex current, forward
   // transform, correction and filter, background; clears J[parity ^ 1]
   static void fft_j(const RunQ<R> *runs, const Item *items, int nitems, int parity, int maxn1,

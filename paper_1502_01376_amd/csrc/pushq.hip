@@ -167,8 +167,7 @@ __device__ __forceinline__ void gather_q(PC F, const R wz[3], const int oz[3], c
 // LDS of one push workgroup: a private region per wave of WAVE_CAP 64-bit
 // accumulators (the wave's particles are consecutive, hence close together).
 // FP32 form: three workgroups per compute unit (3 waves per SIMD, the register
-// budget 168; the compiler spills a little, which costs less than the lost
-// occupancy); FP64 form: two.
+// budget 168); FP64 form: two.
 template <class R> struct QPush;
 template <> struct QPush<float> {
   static constexpr int LDS = 53248;
@@ -252,7 +251,7 @@ __device__ __forceinline__ void glob_add(gptr<double> p, double v) {
 // old and new directions (cta, sta), (ctb, stb) (phases P_m = (c - i s)^m by
 // the same recurrence for both, so the new phase of one step is bit for bit
 // the old phase of the next), scaled charge g and v_th dt.
-template <class R, class Sink>
+template <int MC, class R, class Sink>
 __device__ __forceinline__ void deposit_q(const Sink &put, int M, const R S0z[4], const R S1z[4],
                                           const R S0r[4], const R S1r[4], const R Cz[4],
                                           const R Tz[4], const R Cr[4], const R Tr[4], int br,
@@ -260,6 +259,7 @@ __device__ __forceinline__ void deposit_q(const Sink &put, int M, const R S0z[4]
 #pragma clang fp contract(off)
   R P0r = 1, P0i = 0;  // phase at the old position
   R P1r = 1, P1i = 0;  // phase at the new position
+  if (MC > 0) M = MC;
   for (int m = 0; m < M; ++m) {
     if (m > 0) {
       const R t0 = P0r * cta + P0i * sta;
@@ -350,7 +350,7 @@ __device__ __forceinline__ void deposit_q(const Sink &put, int M, const R S0z[4]
 // offsets dri, drb; old and new directions; scaled charge g; v_th dt.  Builds
 // the 4-node windows along z and r holding both stencils, their running sums
 // and means, and deposits through K (whose column origin follows the window).
-template <class Sink>
+template <int MC, class Sink>
 __device__ __forceinline__ void deposit_move(Sink K, int M, int cz, double fz, int dz, double gz,
                                              int mri, double dri, int mrb, double drb, double ct,
                                              double st, double ctb, double stb, double g,
@@ -385,7 +385,7 @@ __device__ __forceinline__ void deposit_move(Sink K, int M, int cz, double fz, i
     }
   }
   K.window(bz);
-  deposit_q<D>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, ct, st, ctb, stb, g, vthdt);
+  deposit_q<MC, D>(K, M, S0z, S1z, S0r, S1r, Cz, Tz, Cr, Tr, br, ct, st, ctb, stb, g, vthdt);
 }
 
 // The rare global-atomic path out of line, with plain arguments (no array
@@ -400,7 +400,7 @@ __device__ __noinline__ void deposit_move_global(A *J, long long plane, int n1, 
   K.J = J;
   K.plane = plane;
   K.n1 = n1;
-  deposit_move(K, M, cz, fz, dz, gz, mri, dri, mrb, drb, ct, st, ctb, stb, g, vthdt);
+  deposit_move<0>(K, M, cz, fz, dz, gz, mri, dri, mrb, drb, ct, st, ctb, stb, g, vthdt);
 }
 
 }  // namespace
@@ -412,7 +412,9 @@ __device__ __noinline__ void deposit_move_global(A *J, long long plane, int n1, 
 // its LDS region first holds a copy of the fields its particles gather; then,
 // if the box fits, the region is its current box, added to the global
 // accumulators at the end; otherwise the wave deposits with global atomics.
-template <class R>
+// MC: the mode count when every run of the launch has it (the gather's mode
+// loop is then unrolled and the deposit's has a constant trip count), or 0.
+template <class R, int MC>
 __global__ void __launch_bounds__(256, QPush<R>::WAVES_PER_SIMD)
     k_q_push_deposit(const RunQ<R> *__restrict__ runs, const Item *__restrict__ items, int parity,
                      unsigned *err) {
@@ -428,7 +430,7 @@ __global__ void __launch_bounds__(256, QPush<R>::WAVES_PER_SIMD)
   // box whenever the wave has an active lane
   const int p = active ? p0 : r.np - 1;
   const PartsQ<R> P = r.pt;
-  const int n1 = r.n1, M = r.M;
+  const int n1 = r.n1, M = MC > 0 ? MC : r.M;
   const long long plane = r.plane;
   const int cz = G(P.cell)[p], ix = G(P.ix)[p], iy = G(P.iy)[p];
   const R fz = G(P.fz)[p], fx = G(P.fx)[p], fy = G(P.fy)[p];
@@ -515,6 +517,8 @@ __global__ void __launch_bounds__(256, QPush<R>::WAVES_PER_SIMD)
   // recurrence
   R Ec[3] = {0, 0, 0}, Bc[3] = {0, 0, 0};
   R Pr = 1, Pi = 0;
+  constexpr int MU = MC > 0 ? MC : 1;
+#pragma unroll MU
   for (int m = 0; m < M; ++m) {
     if (m > 0) {
       const R t = Pr * ct + Pi * st;
@@ -628,7 +632,7 @@ __global__ void __launch_bounds__(256, QPush<R>::WAVES_PER_SIMD)
     const D g = (D)qw * (D)r.wscale;
     if (use_lds) {
       SinkLdsQ<A> K{box, H, W, rlo, relz - cz - zlo, 2 * M - 1, 0};
-      deposit_move(K, M, cz, (D)fz, dz, (D)gz, mri, (D)dri, mrb, (D)drb, (D)ct, (D)st, (D)ctb,
+      deposit_move<MC>(K, M, cz, (D)fz, dz, (D)gz, mri, (D)dri, mrb, (D)drb, (D)ct, (D)st, (D)ctb,
                    (D)stb, g, vthdt);
     } else {
       deposit_move_global<A>(r.J[parity], plane, n1, M, cz, (D)fz, dz, (D)gz, mri, (D)dri, mrb,
@@ -870,10 +874,12 @@ void LaunchQ<R>::sort(RunQ<R> *run_dev, int np, int nbins, hipStream_t s) {
 
 template <class R>
 void LaunchQ<R>::push_deposit(const RunQ<R> *runs, const Item *items, int nitems, int parity,
-                              unsigned *err, hipStream_t s) {
+                              int modes, unsigned *err, hipStream_t s) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_q_push_deposit<R>, dim3(nitems), dim3(256), (size_t)QPush<R>::LDS, s, runs,
-                     items, parity, err);
+  // kernels with the mode loops unrolled for the common mode counts
+  auto k = modes == 2 ? k_q_push_deposit<R, 2> : modes == 3 ? k_q_push_deposit<R, 3>
+                                                            : k_q_push_deposit<R, 0>;
+  hipLaunchKernelGGL(k, dim3(nitems), dim3(256), (size_t)QPush<R>::LDS, s, runs, items, parity, err);
 }
 template <class R>
 void LaunchQ<R>::rho(const RunQ<R> *run_dev, int np, int M, double2 *rho, hipStream_t s) {
@@ -886,9 +892,9 @@ void LaunchQ<R>::jbg(const RunQ<R> *run_dev, int np, double *jbg, hipStream_t s)
   hipLaunchKernelGGL(k_q_jbg<R>, dim3((np + 255) / 256), dim3(256), 0, s, run_dev, jbg);
 }
 
-template void LaunchQ<float>::push_deposit(const RunQ<float> *, const Item *, int, int, unsigned *,
-                                           hipStream_t);
-template void LaunchQ<double>::push_deposit(const RunQ<double> *, const Item *, int, int,
+template void LaunchQ<float>::push_deposit(const RunQ<float> *, const Item *, int, int, int,
+                                           unsigned *, hipStream_t);
+template void LaunchQ<double>::push_deposit(const RunQ<double> *, const Item *, int, int, int,
                                             unsigned *, hipStream_t);
 template void LaunchQ<float>::sort(RunQ<float> *, int, int, hipStream_t);
 template void LaunchQ<double>::sort(RunQ<double> *, int, int, hipStream_t);

@@ -2001,6 +2001,15 @@ class SimQ : public SimBase {
     return HP_OK;
   }
 
+  // the mode count shared by every run (the push kernel then has its mode
+  // loops unrolled), or 0 when runs differ
+  int common_modes() const {
+    int m = runs_.empty() ? 0 : runs_[0].d.M;
+    for (const auto &h : runs_)
+      if (h.d.M != m) return 0;
+    return m;
+  }
+
   int step(int nsteps) override {
     if (nsteps < 0) return fail(HP_EINVAL, "negative step count");
     for (int k = 0; k < nsteps; ++k) {
@@ -2018,7 +2027,8 @@ class SimQ : public SimBase {
       if (n_push_ > 0) {
         ++since_sort_;
         mark(HP_K_PUSH_DEPOSIT, true);
-        LaunchQ<R>::push_deposit(d_runs_, d_push_, n_push_, parity_, d_err_, stream_);
+        LaunchQ<R>::push_deposit(d_runs_, d_push_, n_push_, parity_, common_modes(), d_err_,
+                                 stream_);
         mark(HP_K_PUSH_DEPOSIT, false);
         mark(HP_K_FFT_J, true);
         LaunchQ<R>::fft_j(d_runs_, d_jitems_, n_jitems_, parity_, maxn1_, stream_);
