@@ -259,8 +259,17 @@ class Sim : public SimBase {
       // (three per block up to n1 = 4096, one beyond)
       int lim = 0, n1max = 0;
       HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device_));
-      for (int i = 0; i < nruns; ++i) n1max = std::max(n1max, cfgs[i].n[0]);
+      long long nrows = 0;
+      for (int i = 0; i < nruns; ++i) {
+        n1max = std::max(n1max, cfgs[i].n[0]);
+        nrows += (long long)cfgs[i].n[1] * (cfgs[i].geom == HP_GEOM_3D ? cfgs[i].n[2] : 1);
+      }
       ncomp_ = n1max > 4096 ? 1 : 3;
+      // the current's forward transform: one component per block when three
+      // per block would leave fewer than about eight blocks per compute unit
+      // (2048 x 512: 21.5 instead of 25.7 us; with 16384 rows of 512 one per
+      // block is slower, 157 against 109 us)
+      ncompj_ = (ncomp_ == 1 || nrows < 2048) ? 1 : 3;
       const size_t need = (size_t)ncomp_ * (n1max / 2) * sizeof(C);
       if (need > (size_t)lim)
         return fail(HP_EINVAL, "n1 = %d needs %zu bytes of LDS per row transform, the device allows %d",
@@ -355,10 +364,11 @@ class Sim : public SimBase {
       d.midx3 = d.dim == 3 ? 1.0 / c.dx[2] : 0.0;
       d.jfac = djfac;
       if ((rc = upload_jfac(i))) return rc;
-      // rows longer than 4096 are transformed one component per block
+      // row-transform items: (run, row, 0) for three components per block,
+      // (run, row, component) for one
       h.row0 = (int)rows.size();
       for (int r = 0; r < d.rows; ++r)
-        for (int c = 0; c < 3; c += ncomp_) rows.push_back(Item{i, r, ncomp_ == 3 ? 0 : c});
+        for (int c = 0; c < 3; c += ncompj_) rows.push_back(Item{i, r, ncompj_ == 3 ? 0 : c});
       h.grp0 = (int)grps.size();
       for (int r = 0; r < d.rows; ++r)
         for (int g = 0; g < 6; g += ncomp_) grps.push_back(Item{i, r, ncomp_ == 3 ? g / 3 : g});
@@ -679,7 +689,7 @@ class Sim : public SimBase {
     ++since_sort_;
     if (n_ant_ > 0) launch_antenna<R>(d_runs_, d_ant_, n_ant_, ant_maxn2_, p, d_step_, stream_);
     mark(HP_K_FFT_J, true);
-    Launch<R>::fft_j(d_runs_, d_rows_, n_rows_, p, maxM_, ncomp_, stream_);
+    Launch<R>::fft_j(d_runs_, d_rows_, n_rows_, p, maxM_, ncompj_, stream_);
     mark(HP_K_FFT_J, false);
     mark(HP_K_KUPDATE, true);
     if (dim_ == 3)
@@ -1821,6 +1831,7 @@ class Sim : public SimBase {
   hipStream_t capture_stream_ = nullptr;
   int maxM_ = 0;
   int ncomp_ = 3;                  // components per row-transform block (1 for n1 > 4096)
+  int ncompj_ = 3;                 // the same for the current's forward transform
   int parity_ = 0;
   int64_t step_ = 0;
   unsigned *d_err_ = nullptr;
