@@ -372,8 +372,10 @@ class Sim : public SimBase {
       h.grp0 = (int)grps.size();
       for (int r = 0; r < d.rows; ++r)
         for (int g = 0; g < 6; g += ncomp_) grps.push_back(Item{i, r, ncomp_ == 3 ? g / 3 : g});
-      // 2D: one update thread per (strip of KSTRIP rows, kappa1); 3D: per (row, kappa1)
-      const int nel = (d.dim == 3 ? d.rows : (d.n2 + KSTRIP - 1) / KSTRIP) * d.nk;
+      // 2D: one update thread per (strip of KSTRIP rows, kappa1); 3D: per
+      // (strip of KSTRIP3 planes, i2, kappa1)
+      const int nel =
+          (d.dim == 3 ? ((d.n3 + KSTRIP3 - 1) / KSTRIP3) * d.n2 : (d.n2 + KSTRIP - 1) / KSTRIP) * d.nk;
       for (int e = 0; e < nel; e += UPD_BLOCK) upd.push_back(Item{i, e, 0});
       perrun.push_back(Item{i, 0, 0});
     }

@@ -240,6 +240,12 @@ __global__ void __launch_bounds__(256) k_kupdate(const Run<R> *__restrict__ runs
 // C_E E = (D2+ E3 - D3+ E2, D3+ E1 - D1+ E3, D1+ E2 - D2+ E1) and
 // C_B B = (D2- B3 - D3- B2, D3- B1 - D1- B3, D1- B2 - D2- B1) (the Yee curl of
 // Sec. 2.2 with the x1 derivative replaced by i k1 xi+-).
+// One thread per (strip of KSTRIP3 planes i3, i2, kappa1): the thread walks
+// its planes in order and carries what the next plane shares with this one
+// (E1 and E2 of plane i3 + 1, E2 of row i2 - 1 there, and the half-step B1,
+// B2 of plane i3 that plane i3 + 1 needs as its i3 - 1 values), so a plane
+// reads 13 complex values of the master copy instead of 21.  Every value is
+// computed by the same expression as for a single plane.
 template <class R>
 __global__ void __launch_bounds__(256) k_kupdate3a(const Run<R> *__restrict__ runs,
                                                    const Item *__restrict__ items, int parity) {
@@ -247,58 +253,80 @@ __global__ void __launch_bounds__(256) k_kupdate3a(const Run<R> *__restrict__ ru
   const Item it = items[blockIdx.x];
   const Run<R> &r = runs[it.run];
   const int nk = r.nk, n2 = r.n2, n3 = r.n3;
+  const int nstrips = (n3 + KSTRIP3 - 1) / KSTRIP3;
   const int e = it.a + threadIdx.x;
-  if (e >= r.rows * nk) return;
-  const int row = e / nk, k = e - row * nk;
-  const int i3 = row / n2, i2 = row - i3 * n2;
+  if (e >= nstrips * n2 * nk) return;
+  const int strip = e / (n2 * nk), rem = e - strip * (n2 * nk);
+  const int i2 = rem / nk, k = rem - i2 * nk;
+  const int q0 = strip * KSTRIP3, q1 = min(q0 + KSTRIP3, n3);  // planes q0 .. q1-1
   const long long vol = (long long)r.rows * nk;
   const C *Fi = r.Fk[parity];
   C *Fo = r.Fk[parity ^ 1];
   const int a2p = wrap_small(i2 + 1, n2), a2m = wrap_small(i2 - 1, n2);
-  const int a3p = wrap_small(i3 + 1, n3), a3m = wrap_small(i3 - 1, n3);
-  auto at = [&](int comp, int j2, int j3) { return Fi[comp * vol + ((long long)j3 * n2 + j2) * nk + k]; };
+  auto at = [&](int comp, int j2, int j3) {
+    return Fi[comp * vol + ((long long)wrap_small(j3, n3) * n2 + j2) * nk + k];
+  };
   const C dp = cmk(r.sym[4 * k + 0], r.sym[4 * k + 1]);
   const C dm = cmk(r.sym[4 * k + 2], r.sym[4 * k + 3]);
   const double hdt = r.mhdt, dt = r.mdt, i2x = r.midx2, i3x = r.midx3;
-  // E^n on the rows the half-step B needs
-  const C E1 = at(0, i2, i3), E2 = at(1, i2, i3), E3 = at(2, i2, i3);
-  const C E1_2p = at(0, a2p, i3), E3_2p = at(2, a2p, i3);            // (i2+1, i3)
-  const C E1_3p = at(0, i2, a3p), E2_3p = at(1, i2, a3p);            // (i2, i3+1)
-  const C E1_2m = at(0, a2m, i3), E2_2m = at(1, a2m, i3), E3_2m = at(2, a2m, i3);  // (i2-1, i3)
-  const C E2_2m3p = at(1, a2m, a3p);                                  // (i2-1, i3+1)
-  const C E1_3m = at(0, i2, a3m), E2_3m = at(1, i2, a3m), E3_3m = at(2, i2, a3m);  // (i2, i3-1)
-  const C E3_2p3m = at(2, a2p, a3m);                                  // (i2+1, i3-1)
   // curl E components, forward differences
   auto cE1 = [&](C e3, C e3n2, C e2, C e2n3) {
     return csub(cscale(csub(e3n2, e3), i2x), cscale(csub(e2n3, e2), i3x));
   };
   auto cE2 = [&](C e1, C e1n3, C e3) { return csub(cscale(csub(e1n3, e1), i3x), cmul(dp, e3)); };
   auto cE3 = [&](C e2, C e1, C e1n2) { return csub(cmul(dp, e2), cscale(csub(e1n2, e1), i2x)); };
-  // B^{n+1/2} on (i2, i3)
-  const C B1h = csub(at(3, i2, i3), cscale(cE1(E3, E3_2p, E2, E2_3p), hdt));
-  const C B2h = csub(at(4, i2, i3), cscale(cE2(E1, E1_3p, E3), hdt));
-  const C B3h = csub(at(5, i2, i3), cscale(cE3(E2, E1, E1_2p), hdt));
-  // on (i2-1, i3): B1 and B3
-  const C B1h_2m = csub(at(3, a2m, i3), cscale(cE1(E3_2m, E3, E2_2m, E2_2m3p), hdt));
-  const C B3h_2m = csub(at(5, a2m, i3), cscale(cE3(E2_2m, E1_2m, E1), hdt));
-  // on (i2, i3-1): B1 and B2
-  const C B1h_3m = csub(at(3, i2, a3m), cscale(cE1(E3_3m, E3_2p3m, E2_3m, E2), hdt));
-  const C B2h_3m = csub(at(4, i2, a3m), cscale(cE2(E1_3m, E1, E3_3m), hdt));
-  // curl B, backward differences
-  const C cB1 = csub(cscale(csub(B3h, B3h_2m), i2x), cscale(csub(B2h, B2h_3m), i3x));
-  const C cB2 = csub(cscale(csub(B1h, B1h_3m), i3x), cmul(dm, B3h));
-  const C cB3 = csub(cmul(dm, B2h), cscale(csub(B1h, B1h_2m), i2x));
   const auto *Jk = r.Jk;
-  const long long o = (long long)row * nk + k;
-  const C j1 = to_d2(Jk[o]), j2 = to_d2(Jk[vol + o]), j3 = to_d2(Jk[2 * vol + o]);
-  Fo[o] = cadd(E1, cscale(csub(cB1, j1), dt));
-  Fo[vol + o] = cadd(E2, cscale(csub(cB2, j2), dt));
-  Fo[2 * vol + o] = cadd(E3, cscale(csub(cB3, j3), dt));
-  Fo[3 * vol + o] = B1h;
-  Fo[4 * vol + o] = B2h;
-  Fo[5 * vol + o] = B3h;
+  // carried values: E1, E2 on (i2, i3), E2 on (i2-1, i3), and B1, B2 at the
+  // half step on (i2, i3-1)
+  C E1 = at(0, i2, q0), E2 = at(1, i2, q0), E2_2m = at(1, a2m, q0);
+  C B1h_3m, B2h_3m;
+  {
+    const C E1_3m = at(0, i2, q0 - 1), E2_3m = at(1, i2, q0 - 1), E3_3m = at(2, i2, q0 - 1);
+    const C E3_2p3m = at(2, a2p, q0 - 1);
+    B1h_3m = csub(at(3, i2, q0 - 1), cscale(cE1(E3_3m, E3_2p3m, E2_3m, E2), hdt));
+    B2h_3m = csub(at(4, i2, q0 - 1), cscale(cE2(E1_3m, E1, E3_3m), hdt));
+  }
+  auto plane = [&](int i3) {
+    const C E3 = at(2, i2, i3);
+    const C E1_2p = at(0, a2p, i3), E3_2p = at(2, a2p, i3);     // (i2+1, i3)
+    const C E1_2m = at(0, a2m, i3), E3_2m = at(2, a2m, i3);     // (i2-1, i3)
+    const C E1_3p = at(0, i2, i3 + 1), E2_3p = at(1, i2, i3 + 1);  // (i2, i3+1)
+    const C E2_2m3p = at(1, a2m, i3 + 1);                       // (i2-1, i3+1)
+    // B^{n+1/2} on (i2, i3)
+    const C B1h = csub(at(3, i2, i3), cscale(cE1(E3, E3_2p, E2, E2_3p), hdt));
+    const C B2h = csub(at(4, i2, i3), cscale(cE2(E1, E1_3p, E3), hdt));
+    const C B3h = csub(at(5, i2, i3), cscale(cE3(E2, E1, E1_2p), hdt));
+    // on (i2-1, i3): B1 and B3
+    const C B1h_2m = csub(at(3, a2m, i3), cscale(cE1(E3_2m, E3, E2_2m, E2_2m3p), hdt));
+    const C B3h_2m = csub(at(5, a2m, i3), cscale(cE3(E2_2m, E1_2m, E1), hdt));
+    // curl B, backward differences
+    const C cB1 = csub(cscale(csub(B3h, B3h_2m), i2x), cscale(csub(B2h, B2h_3m), i3x));
+    const C cB2 = csub(cscale(csub(B1h, B1h_3m), i3x), cmul(dm, B3h));
+    const C cB3 = csub(cmul(dm, B2h), cscale(csub(B1h, B1h_2m), i2x));
+    const long long o = ((long long)i3 * n2 + i2) * nk + k;
+    const C j1 = to_d2(Jk[o]), j2 = to_d2(Jk[vol + o]), j3 = to_d2(Jk[2 * vol + o]);
+    Fo[o] = cadd(E1, cscale(csub(cB1, j1), dt));
+    Fo[vol + o] = cadd(E2, cscale(csub(cB2, j2), dt));
+    Fo[2 * vol + o] = cadd(E3, cscale(csub(cB3, j3), dt));
+    Fo[3 * vol + o] = B1h;
+    Fo[4 * vol + o] = B2h;
+    Fo[5 * vol + o] = B3h;
+    B1h_3m = B1h;
+    B2h_3m = B2h;
+    E1 = E1_3p;
+    E2 = E2_3p;
+    E2_2m = E2_2m3p;
+  };
+  if (q1 - q0 == KSTRIP3) {
+#pragma unroll
+    for (int t = 0; t < KSTRIP3; ++t) plane(q0 + t);
+  } else {
+    for (int i3 = q0; i3 < q1; ++i3) plane(i3);
+  }
 }
 
+// Pass B over the same (strip, i2, kappa1) threads: E1, E2 of plane i3 + 1
+// are carried to the next plane.
 template <class R>
 __global__ void __launch_bounds__(256) k_kupdate3b(const Run<R> *__restrict__ runs,
                                                    const Item *__restrict__ items, int parity) {
@@ -306,26 +334,41 @@ __global__ void __launch_bounds__(256) k_kupdate3b(const Run<R> *__restrict__ ru
   const Item it = items[blockIdx.x];
   const Run<R> &r = runs[it.run];
   const int nk = r.nk, n2 = r.n2, n3 = r.n3;
+  const int nstrips = (n3 + KSTRIP3 - 1) / KSTRIP3;
   const int e = it.a + threadIdx.x;
-  if (e >= r.rows * nk) return;
-  const int row = e / nk, k = e - row * nk;
-  const int i3 = row / n2, i2 = row - i3 * n2;
+  if (e >= nstrips * n2 * nk) return;
+  const int strip = e / (n2 * nk), rem = e - strip * (n2 * nk);
+  const int i2 = rem / nk, k = rem - i2 * nk;
+  const int q0 = strip * KSTRIP3, q1 = min(q0 + KSTRIP3, n3);
   const long long vol = (long long)r.rows * nk;
   C *F = r.Fk[parity ^ 1];
-  const int a2p = wrap_small(i2 + 1, n2), a3p = wrap_small(i3 + 1, n3);
-  auto at = [&](int comp, int j2, int j3) { return F[comp * vol + ((long long)j3 * n2 + j2) * nk + k]; };
+  const int a2p = wrap_small(i2 + 1, n2);
+  auto at = [&](int comp, int j2, int j3) {
+    return F[comp * vol + ((long long)wrap_small(j3, n3) * n2 + j2) * nk + k];
+  };
   const C dp = cmk(r.sym[4 * k + 0], r.sym[4 * k + 1]);
   const double hdt = r.mhdt, i2x = r.midx2, i3x = r.midx3;
-  const C E1 = at(0, i2, i3), E2 = at(1, i2, i3), E3 = at(2, i2, i3);
-  const C E1_2p = at(0, a2p, i3), E3_2p = at(2, a2p, i3);
-  const C E1_3p = at(0, i2, a3p), E2_3p = at(1, i2, a3p);
-  const C c1 = csub(cscale(csub(E3_2p, E3), i2x), cscale(csub(E2_3p, E2), i3x));
-  const C c2 = csub(cscale(csub(E1_3p, E1), i3x), cmul(dp, E3));
-  const C c3 = csub(cmul(dp, E2), cscale(csub(E1_2p, E1), i2x));
-  const long long o = (long long)row * nk + k;
-  F[3 * vol + o] = csub(F[3 * vol + o], cscale(c1, hdt));
-  F[4 * vol + o] = csub(F[4 * vol + o], cscale(c2, hdt));
-  F[5 * vol + o] = csub(F[5 * vol + o], cscale(c3, hdt));
+  C E1 = at(0, i2, q0), E2 = at(1, i2, q0);
+  auto plane = [&](int i3) {
+    const C E3 = at(2, i2, i3);
+    const C E1_2p = at(0, a2p, i3), E3_2p = at(2, a2p, i3);
+    const C E1_3p = at(0, i2, i3 + 1), E2_3p = at(1, i2, i3 + 1);
+    const C c1 = csub(cscale(csub(E3_2p, E3), i2x), cscale(csub(E2_3p, E2), i3x));
+    const C c2 = csub(cscale(csub(E1_3p, E1), i3x), cmul(dp, E3));
+    const C c3 = csub(cmul(dp, E2), cscale(csub(E1_2p, E1), i2x));
+    const long long o = ((long long)i3 * n2 + i2) * nk + k;
+    F[3 * vol + o] = csub(F[3 * vol + o], cscale(c1, hdt));
+    F[4 * vol + o] = csub(F[4 * vol + o], cscale(c2, hdt));
+    F[5 * vol + o] = csub(F[5 * vol + o], cscale(c3, hdt));
+    E1 = E1_3p;
+    E2 = E2_3p;
+  };
+  if (q1 - q0 == KSTRIP3) {
+#pragma unroll
+    for (int t = 0; t < KSTRIP3; ++t) plane(q0 + t);
+  } else {
+    for (int i3 = q0; i3 < q1; ++i3) plane(i3);
+  }
 }
 
 // =====================================================================
