@@ -414,7 +414,6 @@ enum { STAT_FALLBACK = 0, STAT_TILES = 1, NSTAT = 2 };
 // set per handle from the tile shape (push_lds_bytes), between the minimum
 // and maximum here.
 constexpr int KSTRIP = 8;  // rows per thread of the 2D k-space update
-constexpr int KSTRIP3 = 8;  // planes i3 per thread of the 3D k-space update
 constexpr int PUSH_THREADS = 256;
 constexpr int PUSH_BATCH = 4;  // particles loaded per thread before pushing
 constexpr int PUSH_LDS_MIN = 16384;

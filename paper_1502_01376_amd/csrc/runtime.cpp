@@ -18,6 +18,7 @@
 
 #include "hpic.h"
 #include "hpic_q3d.h"
+#include "hpic_update3.h"
 
 using namespace hp;
 

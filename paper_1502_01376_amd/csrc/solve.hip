@@ -7,6 +7,7 @@
 // batched over all runs of a handle through a work-item list.  FP64
 // diagnostics (energies, Gauss and continuity residuals) live here too.
 #include "hpic_internal.h"
+#include "hpic_update3.h"
 
 namespace hp {
 
