@@ -134,8 +134,11 @@ def test_3d_vacuum_dispersion(hpic, prec, tol):
     sim.close()
 
 
-def test_3d_fd_mode_matches_oracle_yee(hpic):
-    n, dx, dt = (16, 8, 4), (0.2, 0.3, 0.25), 0.05
+# n3 = 4: one partial strip of planes in the update; 12: a whole strip of 8
+# and a partial one; 9 with n2 = 5: a strip of 8 and a single plane
+@pytest.mark.parametrize("n", [(16, 8, 4), (8, 6, 12), (16, 5, 9)])
+def test_3d_fd_mode_matches_oracle_yee(hpic, n):
+    dx, dt = (0.2, 0.3, 0.25), 0.05
     gen = np.random.default_rng(8)
     E0 = gen.standard_normal((3, n[2], n[1], n[0]))
     B0 = gen.standard_normal((3, n[2], n[1], n[0]))
