@@ -140,7 +140,9 @@ __device__ __forceinline__ void place4_3(const T s[3], int off, T out[4]) {
 }
 
 // Current sinks: node offset = o1[a] + o2[b] + o3[c] (from offs()), add().
-// (FP32 form: node offsets in bytes, so that an address is one add)
+// (FP32 form: node offsets in bytes, so that an address is one add; the LDS
+// atomic is issued for zero contributions too: adding an exact zero changes
+// nothing, and it costs less than the test)
 struct Sink3Lds {
   unsigned char __attribute__((address_space(3))) *J;
   int W8, WH8, vol8;
@@ -151,9 +153,8 @@ struct Sink3Lds {
   using Base = unsigned char __attribute__((address_space(3))) *;
   __device__ Base base(int c, int off) const { return J + c * vol8 + off; }
   __device__ void put(Base b, int off, long long v) const {
-    if (v != 0)
-      __hip_atomic_fetch_add((unsigned long long __attribute__((address_space(3))) *)(b + off),
-                             (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add((unsigned long long __attribute__((address_space(3))) *)(b + off),
+                           (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 };
 struct Sink3Global {
@@ -363,10 +364,7 @@ template <class R> struct LdsF3 {
   int FW, FWH, plane;
 };
 
-// Push one particle p: gather at global cell (g1, g2, g3) (from the field box
-// when S is local), Boris, move, deposit into K in the sink's frame (cell
-// l[]), store.  Returns the new packed cell (the old one if the particle was
-// rejected).
+// State of one particle as loaded: offsets, momenta, charge.
 template <class R> struct PState3 {
   R f[3], u[3], qw;
 };
@@ -383,6 +381,10 @@ __device__ __forceinline__ PState3<R> load_state3(const Parts<R> &P, int p) {
   return s;
 }
 
+// Push particle p (loaded state st, packed cell `cell`): gather at global
+// cell (g1, g2, g3) (from the field box when S is local), Boris, move, deposit
+// into K in the sink's frame (cell l[]), store.  Returns the new packed cell
+// (the old one if the particle was rejected).
 template <class R, class Src, class Sink>
 __device__ __forceinline__ int push_one3(const Run<R> &r, const Parts<R> &P, int p, int cell,
                                          const PState3<R> &st, int g1, int g2, int g3,
